@@ -1,0 +1,247 @@
+/*
+ * libddf — DDF inspector/executor for sparse matrix-vector multiply (SpMV) and the sparse
+ * lower-triangular solve (SpTRSV) on AMD Instinct MI355X (gfx950), FP64.
+ *
+ * The method is the DDF framework of "Vectorizing Sparse Matrix Codes with Dependency
+ * Driven Trace Analysis" (Cetinic, Cheshmi, Mehri Dehnavi): an inspector (Algorithm 1,
+ * Sec. IV-A) mines a CSR pattern into partially strided codelets (Sec. III: BLAS, PSC I and
+ * PSC II, classified by the first order partial differences of the three access functions
+ * and chosen per window by the cost model of Eq. (1)), grouped into partitions of
+ * independent rows (dependence levels for the solve); an executor (Sec. IV-B) runs the
+ * codelets partition by partition.  Here the executor is a set of HIP kernels; the solve
+ * runs every level inside one persistent kernel.
+ *
+ * Conventions for every call below:
+ *  - Host arrays are read during the call only; nothing keeps a pointer to them.
+ *  - Device pointers are plain HIP device addresses owned by the caller.  Dense vectors
+ *    are row-major (rows, nrhs): element (i, r) at [i * nrhs + r].
+ *  - Outputs are overwritten (y = A x, never y += A x).
+ *  - Execution calls are asynchronous on `stream` (a hipStream_t, NULL = default stream),
+ *    allocate nothing, and copy nothing synchronously, so they may be captured in a graph.
+ *    One execution per plan may be in flight at a time: the plan's scratch (level
+ *    counters) is shared by its calls.
+ *  - Arguments are validated before any launch.  On an error no kernel is launched,
+ *    outputs are untouched, and ddf_last_error() holds a message (thread-local).
+ *  - A zero diagonal is not an error: it gives inf/nan by IEEE rules.
+ */
+#ifndef DDF_H
+#define DDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddf_plan_s *ddf_plan_t;
+typedef struct ddf_graph_s *ddf_graph_t;
+typedef void *ddf_stream_t; /* hipStream_t */
+
+typedef enum {
+    DDF_SPMV = 0,         /* y = A x; A any n_rows x n_cols CSR                         */
+    DDF_SPTRSV_LOWER = 1, /* L x = b; L square, lower, diagonal stored last in each row */
+} ddf_kind;
+
+typedef enum {
+    DDF_OK = 0,
+    DDF_E_ARG = 1,         /* bad argument (null pointer, nrhs outside 1..32, aliasing ...) */
+    DDF_E_CSR = 2,         /* malformed CSR: row_ptr not monotone / columns unsorted,
+                              repeated or out of range                                      */
+    DDF_E_NOT_LOWER = 3,   /* SpTRSV: an entry above the diagonal                          */
+    DDF_E_NO_DIAG = 4,     /* SpTRSV: a row without its diagonal as last entry             */
+    DDF_E_KIND = 5,        /* call does not match the plan's kind (or batch vs single)     */
+    DDF_E_NOMEM = 6,       /* host or device allocation failed                             */
+    DDF_E_HIP = 7,         /* a HIP runtime call failed                                    */
+    DDF_E_DEVICE = 8,      /* a kernel raised the plan's device error flag (level-wait
+                              watchdog); reported by ddf_plan_sync_status                  */
+    DDF_E_UNSUPPORTED = 9, /* e.g. execution on a host-only plan, no adjoint plan built    */
+} ddf_status;
+
+typedef struct {
+    int32_t window;        /* t: rows per inspection window (Alg. 1, GetConsecutiveIterations);
+                              default 64, range 1..1024                                     */
+    int32_t build_adjoint; /* 1: also build the transposed plan (A^T, or L^T on reverse
+                              levels) used by the adjoint calls; default 1                  */
+    int32_t host_only;     /* 1: inspect on the host only; no device tables are made; the
+                              plan can be exported and queried but not executed            */
+    int32_t threads;       /* host threads for the inspector; 0 = hardware concurrency     */
+    int32_t ops_per_lane;  /* schedule: target operations per lane (lanes per row =
+                              next power of two of row length / this); 0 = default 4       */
+    int32_t rows_passes;   /* schedule: row passes per wavefront task; 0 = default 2       */
+    int32_t xcd_remap;     /* schedule: give each XCD a contiguous block range; -1 default */
+    int32_t reserved;
+} ddf_opts;
+
+typedef struct {
+    int32_t n_rows, n_cols;
+    const int32_t *row_ptr; /* [n_rows + 1], row_ptr[0] = 0, non-decreasing              */
+    const int32_t *col_idx; /* [nnz], strictly increasing within a row, in [0, n_cols)   */
+    const double *values;   /* [nnz]; may be NULL for a pattern-only plan (then every
+                               call needs explicit values: the _v forms)                 */
+} ddf_csr_host;
+
+/* Canonical plan tables (host memory owned by the plan, valid until ddf_plan_destroy).
+ * Layout of the paper's codelet list cList, one fixed-width int64 record per item:
+ *   header[9]   kind, n_rows, n_cols, nnz, t, n_parts, n_regions, n_codelets, aux_len
+ *   part_ptr    [n_parts + 1]  partitions (levels) as ranges of part_rows
+ *   part_rows   [n_rows]       rows of each partition, ascending
+ *   regions     [n_regions][8] part, pos0, T, first_codelet, chosen_strategy, cost[3]
+ *   codelets    [n_codelets][18] type (0 BLAS, 1 PSC I, 2 PSC II), flags (S0 1, S1 2,
+ *               S2 4, SEP 8, RECT 16, RUNS 32), part, region, u, m, nn (-1 if ragged), P,
+ *               row0, row_step, op0, op_step, col0, sigma0, sigma1, aux_off, aux_len, cost
+ *   aux         [aux_len] int32: per codelet ROWS (if !S0), OPSTART (if !S1), COUNTS
+ *               (if !RECT), then the column table (if !S2): shared offsets, shared runs
+ *               (offset, len), full columns, or full runs (start, len) per row.
+ * `which` selects the forward plan (0) or the transposed/adjoint plan (1); for a batch
+ * plan `mat` selects the member matrix.  perm (adjoint plan only) maps each entry of the
+ * transposed CSR to the forward value it reads. */
+typedef struct {
+    const int64_t *header;
+    const int64_t *part_ptr;
+    const int64_t *part_rows;
+    const int64_t *regions;
+    const int64_t *codelets;
+    const int32_t *aux;
+    const int32_t *perm; /* NULL for the forward plan */
+} ddf_plan_tables_t;
+
+typedef struct {
+    int32_t kind, nmat;
+    int32_t n_rows, n_cols; /* totals over a batch */
+    int64_t nnz;
+    int64_t n_parts, n_regions, n_codelets, aux_len; /* forward plan(s), summed */
+    int64_t codelets_by_type[3];                     /* BLAS, PSC I, PSC II */
+    int64_t ops_by_type[3];
+    int64_t n_tasks, n_tasks_adjoint;
+    int64_t dev_plan_bytes;     /* forward device tables: records + aux + tasks      */
+    int64_t dev_plan_bytes_adj; /* adjoint-pass device tables (0 if none)            */
+    int32_t has_adjoint;
+    int32_t max_levels;
+    double inspect_seconds;     /* wall time of the host inspector                   */
+    uint64_t hash;              /* FNV-1a over the canonical tables                  */
+    int32_t ops_per_lane, rows_passes, xcd_remap, reserved;
+} ddf_plan_info_t;
+
+typedef enum {
+    DDF_OP_SPMV = 0,
+    DDF_OP_SPMV_ADJ = 1,
+    DDF_OP_SPTRSV = 2,
+    DDF_OP_SPTRSV_ADJ = 3,
+} ddf_op;
+
+/* Defaults for ddf_opts (window 64, adjoint plan on). */
+void ddf_opts_default(ddf_opts *o);
+
+/* Inspector (Alg. 1) on a host CSR, then packing and upload of the device tables (unless
+ * host_only).  Synchronous.  On success *out owns everything it made; on error *out = NULL.
+ * Errors: DDF_E_ARG, DDF_E_CSR, DDF_E_NOT_LOWER, DDF_E_NO_DIAG, DDF_E_NOMEM, DDF_E_HIP. */
+ddf_status ddf_inspect(ddf_kind kind, const ddf_csr_host *A, const ddf_opts *opts,
+                       ddf_plan_t *out);
+
+/* A batch of lower-triangular matrices solved in one launch, matrix b with nrhs[b] right
+ * hand sides (1..32).  Each member gets its own plan (identical to ddf_inspect's);
+ * execution concatenates them.  Packed layouts: values of matrix b follow those of b-1;
+ * vector blocks (n_b, nrhs_b) row-major follow each other in b order. */
+ddf_status ddf_inspect_batch(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats,
+                             const int32_t *nrhs, const ddf_opts *opts, ddf_plan_t *out);
+
+/* Frees host tables, device tables, device copies of values and scratch.  NULL is a no-op.
+ * The caller must make sure no execution on the plan is still in flight. */
+ddf_status ddf_plan_destroy(ddf_plan_t plan);
+
+/* SpMV executor (Listing 3 of the paper, one launch): Y = A X with the values captured at
+ * inspect time.  d_x (n_cols, nrhs), d_y (n_rows, nrhs); they must not overlap. */
+ddf_status ddf_spmv(ddf_plan_t plan, const double *d_x, double *d_y, int32_t nrhs,
+                    ddf_stream_t stream);
+/* Same with explicit device values d_vals[nnz] in the CSR order given at inspect time. */
+ddf_status ddf_spmv_v(ddf_plan_t plan, const double *d_vals, const double *d_x, double *d_y,
+                      int32_t nrhs, ddf_stream_t stream);
+
+/* SpTRSV executor: L X = B, every level inside one persistent kernel with device-side
+ * level waits.  d_b and d_x are (n, nrhs); d_b == d_x (in place) is allowed; partial
+ * overlap is not. */
+ddf_status ddf_sptrsv(ddf_plan_t plan, const double *d_b, double *d_x, int32_t nrhs,
+                      ddf_stream_t stream);
+ddf_status ddf_sptrsv_v(ddf_plan_t plan, const double *d_vals, const double *d_b, double *d_x,
+                        int32_t nrhs, ddf_stream_t stream);
+
+/* SpMV adjoint for upstream d_gy = dLoss/dY (n_rows, nrhs):
+ *   d_gx    (n_cols, nrhs) = A^T G   (transposed plan, deterministic, no atomics)
+ *   d_gvals [nnz]          = sum_r G[i,r] X[col,r]  (dLoss/dA_ij = g_i x_j)
+ * Either output may be NULL.  Both passes run in one launch.  Needs build_adjoint. */
+ddf_status ddf_spmv_adjoint(ddf_plan_t plan, const double *d_vals, const double *d_x,
+                            const double *d_gy, double *d_gx, double *d_gvals, int32_t nrhs,
+                            ddf_stream_t stream);
+
+/* SpTRSV adjoint for upstream d_gx = dLoss/dX, given the forward solution d_x:
+ *   d_gb    (n, nrhs) = Lam with L^T Lam = G   (reverse-level plan of L^T)
+ *   d_gvals [nnz]     = -sum_r Lam[i,r] X[col,r] for every stored entry incl. the diagonal
+ * d_gvals may be NULL.  One persistent launch.  Needs build_adjoint. */
+ddf_status ddf_sptrsv_adjoint(ddf_plan_t plan, const double *d_vals, const double *d_x,
+                              const double *d_gx, double *d_gb, double *d_gvals, int32_t nrhs,
+                              ddf_stream_t stream);
+
+/* Batched forms (plan from ddf_inspect_batch; nrhs per matrix fixed at inspect time).
+ * d_vals_packed may be NULL to use the values captured at inspect time. */
+ddf_status ddf_sptrsv_batch(ddf_plan_t plan, const double *d_vals_packed,
+                            const double *d_b_packed, double *d_x_packed, ddf_stream_t stream);
+ddf_status ddf_sptrsv_batch_adjoint(ddf_plan_t plan, const double *d_vals_packed,
+                                    const double *d_x_packed, const double *d_gx_packed,
+                                    double *d_gb_packed, double *d_gvals_packed,
+                                    ddf_stream_t stream);
+
+/* hipGraph of one batched solve (forward, or adjoint when adjoint = 1) on fixed buffers:
+ * captured once, replayed by ddf_graph_launch on any stream. */
+ddf_status ddf_graph_create_batch(ddf_plan_t plan, int32_t adjoint, const double *d_vals_packed,
+                                  const double *d_in_packed, const double *d_x_packed,
+                                  double *d_out_packed, double *d_gvals_packed,
+                                  ddf_graph_t *out);
+ddf_status ddf_graph_launch(ddf_graph_t graph, ddf_stream_t stream);
+ddf_status ddf_graph_destroy(ddf_graph_t graph);
+
+/* Plain GPU comparators on the same device CSR the plan holds (no codelets):
+ * CSR-vector SpMV; one launch per level for the solve; FP64-atomic SpMV adjoint; one launch
+ * per reverse level for the solve adjoint.  Same argument rules as the DDF forms. */
+ddf_status ddf_plain_spmv(ddf_plan_t plan, const double *d_vals, const double *d_x, double *d_y,
+                          int32_t nrhs, ddf_stream_t stream);
+ddf_status ddf_plain_sptrsv(ddf_plan_t plan, const double *d_vals, const double *d_b,
+                            double *d_x, int32_t nrhs, ddf_stream_t stream);
+ddf_status ddf_plain_spmv_adjoint(ddf_plan_t plan, const double *d_vals, const double *d_x,
+                                  const double *d_gy, double *d_gx, double *d_gvals,
+                                  int32_t nrhs, ddf_stream_t stream);
+ddf_status ddf_plain_sptrsv_adjoint(ddf_plan_t plan, const double *d_vals, const double *d_x,
+                                    const double *d_gx, double *d_gb, double *d_gvals,
+                                    int32_t nrhs, ddf_stream_t stream);
+/* Per-matrix launches of the single-matrix persistent solve over a batch plan. */
+ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t plan, const double *d_vals_packed,
+                                       const double *d_b_packed, double *d_x_packed,
+                                       ddf_stream_t stream);
+
+/* Autotuner: times schedule candidates (ops per lane, row passes, XCD remap) for `op` with
+ * nrhs right-hand sides on scratch buffers, keeps the fastest in the plan.  Results are
+ * cached by plan hash (in memory, and in the JSON file named by DDF_TUNE_CACHE if set).
+ * Synchronises `stream`.  budget_ms bounds the total timing time (<= 0: no bound). */
+ddf_status ddf_autotune(ddf_plan_t plan, ddf_op op, int32_t nrhs, ddf_stream_t stream,
+                        double budget_ms);
+
+/* Introspection. */
+ddf_status ddf_plan_info(ddf_plan_t plan, ddf_plan_info_t *out);
+ddf_status ddf_plan_export(ddf_plan_t plan, int32_t which, int32_t mat, ddf_plan_tables_t *out);
+/* Algorithmic HBM bytes of one call (values, plan tables, perm, vectors read once and
+ * written once), the CSR-equivalent bytes, and flops. */
+ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *bytes_alg,
+                            int64_t *bytes_csr, int64_t *flops);
+
+/* Synchronises `stream`, then reads and clears the plan's device error flag. */
+ddf_status ddf_plan_sync_status(ddf_plan_t plan, ddf_stream_t stream);
+/* Test hook: spin limit of the persistent kernels' level waits (0 = default). */
+ddf_status ddf_plan_set_spin_limit(ddf_plan_t plan, int64_t limit);
+
+const char *ddf_status_string(ddf_status s);
+const char *ddf_last_error(void);
+const char *ddf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDF_H */

@@ -1,0 +1,103 @@
+// Internal data structures of libddf (host side).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ddf.h"
+
+namespace ddf {
+
+// canonical flag bits (the codelet record's `flags` field)
+enum : int32_t { FS0 = 1, FS1 = 2, FS2 = 4, FSEP = 8, FRECT = 16, FRUNS = 32 };
+// device-only bits
+enum : int32_t { DOPS = 64, DCONTIG = 128, DXPTR = 256, DRPTR = 512 };
+
+enum : int { NREG = 8, NCOD = 18 };
+enum CodField : int {
+    C_TYPE, C_FLAGS, C_PART, C_REGION, C_U, C_M, C_NN, C_P, C_ROW0, C_ROWSTEP, C_OP0,
+    C_OPSTEP, C_COL0, C_SIG0, C_SIG1, C_AUXOFF, C_AUXLEN, C_COST
+};
+
+// Which access functions a kernel kind reads.  kind 0: SpMV (all entries are ops);
+// kind 1: lower solve, diagonal last (not an op); kind 2: transposed solve on U = L^T,
+// diagonal first (not an op), dependence levels counted from the last row.
+struct Pattern {
+    int kind = 0;
+    int32_t n_rows = 0, n_cols = 0;
+    const int32_t *rp = nullptr;
+    const int32_t *ci = nullptr;
+    int64_t opstart(int64_t q) const { return kind == 2 ? (int64_t)rp[q] + 1 : (int64_t)rp[q]; }
+    int64_t nops(int64_t q) const {
+        int64_t len = (int64_t)rp[q + 1] - rp[q];
+        return kind == 0 ? len : len - 1;
+    }
+};
+
+// The canonical tables of one inspected matrix.
+struct Canon {
+    int64_t header[9] = {0};
+    std::vector<int64_t> part_ptr, part_rows, regions, codelets;
+    std::vector<int32_t> aux;
+    std::vector<int32_t> perm; // adjoint plan: transposed entry -> forward value index
+    int64_t n_parts() const { return header[5]; }
+    int64_t n_codelets() const { return header[7]; }
+};
+
+// Device codelet record: 16 x int32 = 64 bytes.
+struct DCod {
+    int32_t flags, m, nn, row0, row_step, op0, op_step, col0;
+    int32_t sigma0, sigma1, rows_off, ops_off, cnt_off, xt_off, xp_off, mat;
+};
+static_assert(sizeof(DCod) == 64, "DCod layout");
+
+// A wavefront's work item: rows [i0b, i0e) of one codelet; meta = log2(lanes per row) |
+// phase << 8 (phase 1 = second pass of a fused launch).
+struct Task {
+    int32_t cod, i0b, i0e, meta;
+};
+
+// Per-matrix bases of a batch (single plans have one entry of zeros and k = nrhs).
+struct MatInfo {
+    int64_t row_base; // first packed row
+    int64_t val_base; // first packed value
+    int64_t vec_base; // first element of the (n_b, k_b) packed vector block
+    int32_t k;        // right-hand sides of this matrix
+    int32_t n;
+};
+
+struct SchedParams {
+    int32_t ops_per_lane = 4;
+    int32_t passes = 2;
+    int32_t remap = 1;
+};
+
+// Device-resident tables of one plan pass (forward or adjoint).
+struct DevTables {
+    std::vector<DCod> cods;
+    std::vector<int32_t> aux;          // canonical aux followed by device supplements
+    std::vector<Task> tasks;
+    std::vector<int32_t> task_wait;    // solve kernels: tasks of the same matrix to wait for
+    int64_t supplement = 0;            // device-only aux entries
+    DCod *d_cods = nullptr;
+    int32_t *d_aux = nullptr;
+    Task *d_tasks = nullptr;
+    int32_t *d_wait = nullptr;
+    int64_t bytes() const {
+        return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
+               (int64_t)tasks.size() * sizeof(Task) + (int64_t)task_wait.size() * 4;
+    }
+};
+
+std::string &last_error();
+ddf_status fail(ddf_status s, const std::string &msg);
+
+// inspector.cpp
+ddf_status validate(int kind, const ddf_csr_host &A);
+void inspect(const Pattern &P, int32_t t, int threads, Canon &out);
+void transpose(int32_t n_rows, int32_t n_cols, const int32_t *rp, const int32_t *ci,
+               std::vector<int32_t> &rpT, std::vector<int32_t> &ciT, std::vector<int32_t> &perm);
+uint64_t hash_canon(const Canon &c, uint64_t h);
+
+} // namespace ddf

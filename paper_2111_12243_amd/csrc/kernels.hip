@@ -1,0 +1,513 @@
+// HIP kernels of the DDF executor for gfx950 (CDNA4), FP64.
+//
+// The paper's executor (Sec. IV-B, Listing 3) loops over partitions and, inside one, runs
+// the codelets in parallel, each through the generic code of its class.  Here one
+// wavefront runs a task: a range of rows of one codelet.  A codelet's record carries the
+// parameters of its three access functions (Sec. III-C: f(I) = x + s[...]):
+//   output row   f0: row0 + i0*row_step            or the ROWS table
+//   value index  f1: op0 + i0*op_step + i1         or the OPSTART table + i1
+//   input column f2: col0 + i0*sigma0 + i1*sigma1  (BLAS), col0 + i0*sigma0 + s[i1] (one
+//                    shared offset table, PSC I), or a full column table (PSC II)
+// so a strided function costs no index load at all and a shared table is read once per
+// row group.  G lanes cooperate on one row (G = 2^lg chosen per task by the scheduler),
+// 64/G rows per pass; partial sums are combined with cross-lane shuffles.
+//
+// The solve runs every level inside one persistent kernel.  Waves take tasks in ticket
+// order; a task of level l waits until its matrix has completed every task of levels < l
+// (per-matrix done counters).  Since tickets are handed out in order, every task a wave
+// waits on is held by a running wave, so no co-residency assumption is needed.  Solution
+// values cross XCDs through device-scope (sc1) stores and loads; a finished task waits for
+// its stores to complete (s_waitcnt vmcnt(0)) before bumping the counter.
+#include <hip/hip_runtime.h>
+
+#include "ddf_internal.hpp"
+#include "kernels.hpp"
+
+namespace ddf {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int WPB = 4; // waves per block (256 threads)
+
+__device__ __forceinline__ double cload(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cstore(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned cload_u(const unsigned *p) {
+    return __hip_atomic_load(const_cast<unsigned *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// column-table mode of a codelet
+enum : int { XM_STRIDED = 0, XM_SHARED = 1, XM_SHARED_RUNS = 2, XM_FULL = 3, XM_FULL_RUNS = 4 };
+
+__device__ __forceinline__ int xmode(int flags) {
+    if (flags & FS2) return XM_STRIDED;
+    if (flags & FSEP) return (flags & FRUNS) ? XM_SHARED_RUNS : XM_SHARED;
+    return (flags & FRUNS) ? XM_FULL_RUNS : XM_FULL;
+}
+
+struct RowInfo {
+    int row, opst, nops;
+};
+
+__device__ __forceinline__ RowInfo row_info(const DCod &c, const int32_t *__restrict__ aux, int i0) {
+    RowInfo r;
+    r.row = (c.flags & FS0) ? c.row0 + i0 * c.row_step : aux[c.rows_off + i0];
+    r.opst = (c.flags & DOPS) ? aux[c.ops_off + i0] : c.op0 + i0 * c.op_step;
+    r.nops = (c.flags & FRECT) ? c.nn : aux[c.cnt_off + i0];
+    return r;
+}
+
+// Calls f(value index, column) for the ops i1 = g, g+G, ... of row i0.
+template <int MODE, class F>
+__device__ __forceinline__ void walk(const DCod &c, const int32_t *__restrict__ aux, int i0,
+                                     const RowInfo &ri, int g, int G, F &&f) {
+    if constexpr (MODE == XM_STRIDED) {
+        const int base = c.col0 + i0 * c.sigma0;
+        for (int i1 = g; i1 < ri.nops; i1 += G) f(ri.opst + i1, base + i1 * c.sigma1);
+    } else if constexpr (MODE == XM_SHARED) {
+        const int base = c.col0 + i0 * c.sigma0;
+        const int32_t *__restrict__ s = aux + c.xt_off;
+        for (int i1 = g; i1 < ri.nops; i1 += G) f(ri.opst + i1, base + s[i1]);
+    } else if constexpr (MODE == XM_FULL) {
+        int off;
+        if (c.flags & FRECT)
+            off = i0 * c.nn;
+        else if (c.flags & DCONTIG)
+            off = ri.opst - c.op0;
+        else
+            off = aux[c.xp_off + i0];
+        const int32_t *__restrict__ s = aux + c.xt_off + off;
+        for (int i1 = g; i1 < ri.nops; i1 += G) f(ri.opst + i1, s[i1]);
+    } else {
+        const int32_t *__restrict__ rt;
+        int base;
+        if constexpr (MODE == XM_SHARED_RUNS) {
+            rt = aux + c.xt_off;
+            base = c.col0 + i0 * c.sigma0;
+        } else {
+            rt = aux + c.xt_off + 2 * aux[c.xp_off + i0];
+            base = 0;
+        }
+        int j = -1, cum = 0, ln = 0, st = 0;
+        for (int i1 = g; i1 < ri.nops; i1 += G) {
+            while (i1 >= cum + ln) {
+                cum += ln;
+                ++j;
+                st = rt[2 * j];
+                ln = rt[2 * j + 1];
+            }
+            f(ri.opst + i1, base + st + (i1 - cum));
+        }
+    }
+}
+
+template <class F>
+__device__ __forceinline__ void walk_any(int mode, const DCod &c, const int32_t *__restrict__ aux, int i0,
+                                         const RowInfo &ri, int g, int G, F &&f) {
+    switch (mode) {
+    case XM_STRIDED: walk<XM_STRIDED>(c, aux, i0, ri, g, G, f); break;
+    case XM_SHARED: walk<XM_SHARED>(c, aux, i0, ri, g, G, f); break;
+    case XM_SHARED_RUNS: walk<XM_SHARED_RUNS>(c, aux, i0, ri, g, G, f); break;
+    case XM_FULL: walk<XM_FULL>(c, aux, i0, ri, g, G, f); break;
+    default: walk<XM_FULL_RUNS>(c, aux, i0, ri, g, G, f); break;
+    }
+}
+
+template <int KT>
+__device__ __forceinline__ void group_sum(double (&acc)[KT], int G) {
+    for (int s = 1; s < G; s <<= 1)
+#pragma unroll
+        for (int r = 0; r < KT; r++) acc[r] += __shfl_xor(acc[r], s, WAVE);
+}
+
+__device__ __forceinline__ int xcd_block(int b, int nb, int remap) {
+    if (!remap) return b;
+    // blocks are dispatched round-robin over the 8 XCDs; give XCD x a contiguous range
+    const int q = nb >> 3, rr = nb & 7, x = b & 7;
+    return x * q + min(x, rr) + (b >> 3);
+}
+
+__device__ __forceinline__ DCod load_cod(const DCod *p) { return *p; }
+
+// ------------------------------------------------------------------------------------------
+// SpMV executor: Y[:, r0:r0+KT] (tiles over nrhs inside) = A X.  VPERM: values read through
+// perm (the transposed plan of the adjoint pass).  Phase-1 tasks (fused adjoint) compute
+// GV[e] = sum_r G[row, r] X[col, r] over the forward plan instead.
+// ------------------------------------------------------------------------------------------
+template <int KT, bool VPERM>
+__global__ __launch_bounds__(WAVE *WPB) void k_spmv(SpmvArgs a) {
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
+    if (t >= a.ntasks) return;
+    const Task tk = a.tasks[t];
+    const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
+    const int slot = lane >> lg, g = lane & (G - 1);
+    const int k = a.k;
+    if ((tk.meta >> 8) & 1) {
+        // GV pass over the forward plan: one output per op, no reduction
+        const DCod c = load_cod(a.cods2 + tk.cod);
+        const int mode = xmode(c.flags);
+        for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
+            const RowInfo ri = row_info(c, a.aux2, i0);
+            const double *__restrict__ grow = a.g + (int64_t)ri.row * k;
+            walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
+                const double *__restrict__ xr = a.x2 + (int64_t)col * k;
+                double s = 0.0;
+                for (int r = 0; r < k; r++) s += grow[r] * xr[r];
+                a.gv[e] = s;
+            });
+        }
+        return;
+    }
+    const DCod c = load_cod(a.cods + tk.cod);
+    const int mode = xmode(c.flags);
+    for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
+        const RowInfo ri = row_info(c, a.aux, i0);
+        for (int r0 = 0; r0 < k; r0 += KT) {
+            double acc[KT];
+#pragma unroll
+            for (int r = 0; r < KT; r++) acc[r] = 0.0;
+            const bool full = r0 + KT <= k;
+            walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
+                const double v = VPERM ? a.vals[a.perm[e]] : a.vals[e];
+                const double *__restrict__ xr = a.x + (int64_t)col * k + r0;
+                if (full) {
+#pragma unroll
+                    for (int r = 0; r < KT; r++) acc[r] += v * xr[r];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < KT; r++)
+                        if (r0 + r < k) acc[r] += v * xr[r];
+                }
+            });
+            group_sum<KT>(acc, G);
+            double *__restrict__ yr = a.y + (int64_t)ri.row * k + r0;
+#pragma unroll
+            for (int r = 0; r < KT; r++)
+                if ((r & (G - 1)) == g && r0 + r < k) yr[r] = acc[r];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Persistent level-ordered solve (forward L x = b, or the adjoint U lam = g with U = L^T
+// read through perm, followed by the GV pass).
+// ------------------------------------------------------------------------------------------
+template <int KT, bool ADJ>
+__global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    unsigned *__restrict__ done = a.ctr + 2;
+    for (;;) {
+        int t = 0;
+        if (lane == 0)
+            t = (int)__hip_atomic_fetch_add(a.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __shfl(t, 0, WAVE);
+        if (t >= a.ntasks) break;
+        const Task tk = a.tasks[t];
+        const int phase = (tk.meta >> 8) & 1;
+        const DCod c = load_cod((phase ? a.cods2 : a.cods) + tk.cod);
+        const MatInfo mi = a.mats[c.mat];
+        const int need = a.wait[t];
+        if (lane == 0 && need > 0) {
+            // bounded wait: past the spin limit, or once another wave has tripped the
+            // error flag, stop waiting (the results are then reported as invalid)
+            int64_t spins = 0;
+            while ((int)cload_u(done + c.mat) < need) {
+                __builtin_amdgcn_s_sleep(1);
+                ++spins;
+                if (spins > a.spin_limit || ((spins & 255) == 0 && cload_u(a.ctr + 1) != 0u)) {
+                    __hip_atomic_store(a.ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        asm volatile("" ::: "memory");
+        const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
+        const int slot = lane >> lg, g = lane & (G - 1);
+        const int k = a.k_override > 0 ? a.k_override : mi.k;
+        const double *__restrict__ vals = a.vals + mi.val_base;
+        if (ADJ && phase) {
+            // GV over L's forward plan: gv[e] = -sum_r lam[row, r] x[col, r], diagonal included
+            const int mode = xmode(c.flags);
+            const double *lam = a.x + mi.vec_base;
+            const double *__restrict__ xf = a.xf + mi.vec_base;
+            double *__restrict__ gv = a.gv + mi.val_base;
+            for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
+                const RowInfo ri = row_info(c, a.aux2, i0);
+                const int64_t rb = (int64_t)ri.row * k;
+                walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
+                    const double *__restrict__ xr = xf + (int64_t)col * k;
+                    double s = 0.0;
+                    for (int r = 0; r < k; r++) s += cload(lam + rb + r) * xr[r];
+                    gv[e] = -s;
+                });
+                if (g == 0) {
+                    double s = 0.0;
+                    for (int r = 0; r < k; r++) s += cload(lam + rb + r) * xf[rb + r];
+                    gv[ri.opst + ri.nops] = -s;
+                }
+            }
+        } else {
+            const int mode = xmode(c.flags);
+            const int32_t *__restrict__ perm = ADJ ? a.perm + mi.val_base : nullptr;
+            const double *__restrict__ b = a.b + mi.vec_base;
+            double *x = a.x + mi.vec_base;
+            for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
+                const RowInfo ri = row_info(c, a.aux, i0);
+                const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
+                const double diag = ADJ ? vals[perm[dpos]] : vals[dpos];
+                const int64_t rb = (int64_t)ri.row * k;
+                for (int r0 = 0; r0 < k; r0 += KT) {
+                    double acc[KT];
+#pragma unroll
+                    for (int r = 0; r < KT; r++) acc[r] = 0.0;
+                    walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
+                        const double v = ADJ ? vals[perm[e]] : vals[e];
+                        const double *xr = x + (int64_t)col * k + r0;
+#pragma unroll
+                        for (int r = 0; r < KT; r++)
+                            if (r0 + r < k) acc[r] += v * cload(xr + r);
+                    });
+                    group_sum<KT>(acc, G);
+#pragma unroll
+                    for (int r = 0; r < KT; r++)
+                        if ((r & (G - 1)) == g && r0 + r < k) cstore(x + rb + r0 + r, (b[rb + r0 + r] - acc[r]) / diag);
+                }
+            }
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (lane == 0)
+            __hip_atomic_fetch_add(done + c.mat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void k_reset(unsigned *p, int n) {
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) p[i] = 0u;
+}
+
+__global__ void k_fill(double *p, int64_t n, double v) {
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < n; i += (int64_t)blockDim.x * gridDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Plain comparators: CSR with G lanes per row, no codelets.
+// ------------------------------------------------------------------------------------------
+template <int KT>
+__global__ __launch_bounds__(WAVE *WPB) void k_csr_spmv(PlainArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
+    const int64_t row = ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
+    const int g = lane & (G - 1);
+    if (row >= a.n) return;
+    const int k = a.k;
+    const int b = a.rp[row], e1 = a.rp[row + 1];
+    for (int r0 = 0; r0 < k; r0 += KT) {
+        double acc[KT];
+#pragma unroll
+        for (int r = 0; r < KT; r++) acc[r] = 0.0;
+        for (int e = b + g; e < e1; e += G) {
+            const double v = a.vals[e];
+            const double *__restrict__ xr = a.x + (int64_t)a.ci[e] * k + r0;
+#pragma unroll
+            for (int r = 0; r < KT; r++)
+                if (r0 + r < k) acc[r] += v * xr[r];
+        }
+        group_sum<KT>(acc, G);
+#pragma unroll
+        for (int r = 0; r < KT; r++)
+            if ((r & (G - 1)) == g && r0 + r < k) a.y[row * k + r0 + r] = acc[r];
+    }
+}
+
+// one level of the solve: rows rows[lo..hi); upper = 1 reads U = L^T (diagonal first,
+// values through perm), else L (diagonal last)
+template <int KT>
+__global__ __launch_bounds__(WAVE *WPB) void k_csr_level(PlainArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
+    const int64_t p = a.lo + ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
+    const int g = lane & (G - 1);
+    if (p >= a.hi) return;
+    const int k = a.k;
+    const int64_t row = a.rows[p];
+    int b = a.rp[row], e1 = a.rp[row + 1], d;
+    if (a.upper) {
+        d = b;
+        b += 1;
+    } else {
+        d = e1 - 1;
+        e1 -= 1;
+    }
+    const double diag = a.upper ? a.vals[a.perm[d]] : a.vals[d];
+    for (int r0 = 0; r0 < k; r0 += KT) {
+        double acc[KT];
+#pragma unroll
+        for (int r = 0; r < KT; r++) acc[r] = 0.0;
+        for (int e = b + g; e < e1; e += G) {
+            const double v = a.upper ? a.vals[a.perm[e]] : a.vals[e];
+            const double *__restrict__ xr = a.y + (int64_t)a.ci[e] * k + r0;
+#pragma unroll
+            for (int r = 0; r < KT; r++)
+                if (r0 + r < k) acc[r] += v * xr[r];
+        }
+        group_sum<KT>(acc, G);
+#pragma unroll
+        for (int r = 0; r < KT; r++)
+            if ((r & (G - 1)) == g && r0 + r < k)
+                a.y[row * k + r0 + r] = (a.x[row * k + r0 + r] - acc[r]) / diag;
+    }
+}
+
+// SpMV adjoint with FP64 atomics: GX[col] += v g[row]; GV[e] = sum_r g[row, r] x[col, r]
+__global__ __launch_bounds__(WAVE *WPB) void k_csr_spmv_adj_atomic(PlainArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
+    const int64_t row = ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
+    const int g = lane & (G - 1);
+    if (row >= a.n) return;
+    const int k = a.k;
+    const double *__restrict__ gr = a.g + row * k;
+    for (int e = a.rp[row] + g; e < a.rp[row + 1]; e += G) {
+        const int64_t c = a.ci[e];
+        const double v = a.vals[e];
+        double s = 0.0;
+        for (int r = 0; r < k; r++) {
+            s += gr[r] * a.x[c * k + r];
+            if (a.y) atomicAdd(a.y + c * k + r, v * gr[r]);
+        }
+        if (a.gv) a.gv[e] = s;
+    }
+}
+
+// GV of the solve adjoint over L's CSR: gv[e] = -sum_r lam[row, r] x[col, r]
+__global__ __launch_bounds__(WAVE *WPB) void k_csr_gv(PlainArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
+    const int64_t row = ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
+    const int g = lane & (G - 1);
+    if (row >= a.n) return;
+    const int k = a.k;
+    const double *__restrict__ lr = a.g + row * k;
+    for (int e = a.rp[row] + g; e < a.rp[row + 1]; e += G) {
+        const int64_t c = a.ci[e];
+        double s = 0.0;
+        for (int r = 0; r < k; r++) s += lr[r] * a.x[c * k + r];
+        a.gv[e] = -s;
+    }
+}
+
+template <int KT, bool V>
+void launch_spmv_t(const SpmvArgs &a, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_spmv<KT, V>), dim3(nblocks), dim3(WAVE * WPB), 0, s, a);
+}
+
+int g_solve_blocks = 0; // resident blocks of the persistent kernel on the whole device
+
+int solve_grid(int ntasks) {
+    int need = (ntasks + WPB - 1) / WPB;
+    int cap = g_solve_blocks > 0 ? g_solve_blocks : 1024;
+    return need < cap ? (need > 0 ? need : 1) : cap;
+}
+
+} // namespace
+
+int kt_for(int k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; }
+
+hipError_t init_device_info() {
+    if (g_solve_blocks > 0) return hipSuccess;
+    int dev = 0, ncu = 0, nb = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<8, true>, WAVE * WPB, 0);
+    if (e != hipSuccess) return e;
+    g_solve_blocks = (nb > 0 ? nb : 1) * (ncu > 0 ? ncu : 1);
+    return hipSuccess;
+}
+
+hipError_t launch_spmv(const SpmvArgs &a, bool vperm, int kt, hipStream_t s) {
+    int nb = (a.ntasks + WPB - 1) / WPB;
+    if (nb == 0) return hipSuccess;
+    switch (kt * 2 + (vperm ? 1 : 0)) {
+    case 2: launch_spmv_t<1, false>(a, nb, s); break;
+    case 3: launch_spmv_t<1, true>(a, nb, s); break;
+    case 4: launch_spmv_t<2, false>(a, nb, s); break;
+    case 5: launch_spmv_t<2, true>(a, nb, s); break;
+    case 8: launch_spmv_t<4, false>(a, nb, s); break;
+    case 9: launch_spmv_t<4, true>(a, nb, s); break;
+    case 16: launch_spmv_t<8, false>(a, nb, s); break;
+    default: launch_spmv_t<8, true>(a, nb, s); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(unsigned *ctr, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, ctr, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, hipStream_t s) {
+    if (a.ntasks == 0) return hipSuccess;
+    int nb;
+#define DDF_SOLVE_CASE(K, A)                                                                        \
+    nb = solve_grid(a.ntasks);                                                                      \
+    hipLaunchKernelGGL((k_solve<K, A>), dim3(nb), dim3(WAVE * WPB), 0, s, a);                       \
+    break;
+    switch (kt * 2 + (adj ? 1 : 0)) {
+    case 2: DDF_SOLVE_CASE(1, false)
+    case 3: DDF_SOLVE_CASE(1, true)
+    case 4: DDF_SOLVE_CASE(2, false)
+    case 5: DDF_SOLVE_CASE(2, true)
+    case 8: DDF_SOLVE_CASE(4, false)
+    case 9: DDF_SOLVE_CASE(4, true)
+    case 16: DDF_SOLVE_CASE(8, false)
+    default: DDF_SOLVE_CASE(8, true)
+    }
+#undef DDF_SOLVE_CASE
+    return hipGetLastError();
+}
+
+static int lg_for(double avg, int ops_per_lane) {
+    int lg = 0;
+    while (lg < 6 && (double)(1 << lg) * ops_per_lane < avg) lg++;
+    return lg;
+}
+
+hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s) {
+    a.lg = lg_for(avg_row, 4);
+    const int R = WAVE >> a.lg;
+    int64_t rows = (which == PLAIN_LEVEL) ? (a.hi - a.lo) : a.n;
+    if (rows <= 0) return hipSuccess;
+    int64_t nb = (rows + (int64_t)R * WPB - 1) / ((int64_t)R * WPB);
+    dim3 grid((unsigned)nb), block(WAVE * WPB);
+    switch (which) {
+    case PLAIN_SPMV:
+        if (kt == 1) hipLaunchKernelGGL(k_csr_spmv<1>, grid, block, 0, s, a);
+        else if (kt == 2) hipLaunchKernelGGL(k_csr_spmv<2>, grid, block, 0, s, a);
+        else if (kt == 4) hipLaunchKernelGGL(k_csr_spmv<4>, grid, block, 0, s, a);
+        else hipLaunchKernelGGL(k_csr_spmv<8>, grid, block, 0, s, a);
+        break;
+    case PLAIN_LEVEL:
+        if (kt == 1) hipLaunchKernelGGL(k_csr_level<1>, grid, block, 0, s, a);
+        else if (kt == 2) hipLaunchKernelGGL(k_csr_level<2>, grid, block, 0, s, a);
+        else if (kt == 4) hipLaunchKernelGGL(k_csr_level<4>, grid, block, 0, s, a);
+        else hipLaunchKernelGGL(k_csr_level<8>, grid, block, 0, s, a);
+        break;
+    case PLAIN_SPMV_ADJ: hipLaunchKernelGGL(k_csr_spmv_adj_atomic, grid, block, 0, s, a); break;
+    case PLAIN_GV: hipLaunchKernelGGL(k_csr_gv, grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+} // namespace ddf

@@ -1,0 +1,73 @@
+// Kernel argument blocks and launchers (device code in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ddf_internal.hpp"
+
+namespace ddf {
+
+struct SpmvArgs {
+    const DCod *cods;
+    const int32_t *aux;
+    const Task *tasks;
+    int32_t ntasks;
+    int32_t k;     // right-hand sides (row stride of x, y, g)
+    int32_t remap; // XCD-contiguous block order
+    const double *vals;
+    const int32_t *perm; // values through perm (transposed plan)
+    const double *x;
+    double *y;
+    // phase-1 tasks of a fused adjoint launch: gv[e] = sum_r g[row, r] x2[col, r]
+    const DCod *cods2;
+    const int32_t *aux2;
+    const double *g;
+    const double *x2;
+    double *gv;
+};
+
+struct SolveArgs {
+    const DCod *cods;  // phase 0: the solve's plan
+    const int32_t *aux;
+    const DCod *cods2; // phase 1 (adjoint): L's forward plan for the GV pass
+    const int32_t *aux2;
+    const Task *tasks;
+    const int32_t *wait;
+    int32_t ntasks;
+    const MatInfo *mats;
+    const double *vals;
+    const int32_t *perm; // adjoint: U's entries -> L's values (per matrix, local)
+    const double *b;     // right-hand side (adjoint: upstream gradient)
+    double *x;           // solution (adjoint: lambda)
+    const double *xf;    // adjoint: forward solution (for GV)
+    double *gv;          // adjoint: value gradient
+    unsigned *ctr;       // [0] ticket, [1] error flag, [2 + mat] tasks done per matrix
+    int64_t spin_limit;
+    int32_t k_override; // > 0: right-hand sides of a single-matrix call
+};
+
+struct PlainArgs {
+    const int32_t *rp;
+    const int32_t *ci;
+    const double *vals;
+    const int32_t *perm;
+    const int32_t *rows;
+    const double *x; // input vector (solve: right-hand side)
+    double *y;       // output vector (solve: solution; atomic adjoint: gx)
+    const double *g; // adjoint upstream (or lambda for GV)
+    double *gv;
+    int64_t n, lo, hi;
+    int32_t k, lg, upper;
+};
+
+enum PlainKind { PLAIN_SPMV, PLAIN_LEVEL, PLAIN_SPMV_ADJ, PLAIN_GV };
+
+int kt_for(int k);
+hipError_t init_device_info();
+hipError_t launch_spmv(const SpmvArgs &a, bool vperm, int kt, hipStream_t s);
+hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, hipStream_t s);
+hipError_t launch_reset(unsigned *ctr, int n, hipStream_t s);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
+
+} // namespace ddf

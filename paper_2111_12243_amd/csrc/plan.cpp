@@ -1,0 +1,1179 @@
+// libddf host side: plan object, device packing, schedule, and the C ABI of include/ddf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+
+#include "ddf_internal.hpp"
+#include "kernels.hpp"
+
+using namespace ddf;
+
+namespace ddf {
+std::string &last_error() {
+    static thread_local std::string s;
+    return s;
+}
+ddf_status fail(ddf_status s, const std::string &msg) {
+    last_error() = msg;
+    return s;
+}
+} // namespace ddf
+
+struct ddf_plan_s {
+    int kind = 0;
+    int nmat = 1;
+    bool batch = false;
+    ddf_opts opts{};
+    bool host_only = false, has_adj = false;
+    std::vector<Canon> fwd, adj;
+    std::vector<MatInfo> mats;
+    std::vector<int32_t> hrp, hci; // single-matrix host pattern (plain comparators)
+    int64_t n_rows = 0, n_cols = 0, nnz = 0, vec_total = 0;
+    SchedParams sp_f, sp_a;
+    DevTables F, T, Fpm;
+    std::vector<int64_t> pm_task_ptr; // per-matrix ranges of Fpm.tasks
+    int64_t n_solve_tasks_adj = 0;    // adjoint: tasks before the GV pass
+    int64_t n_gx_tasks = 0;           // SpMV adjoint: tasks before the GV pass
+    double *d_vals = nullptr;
+    int32_t *d_perm = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_rpT = nullptr, *d_ciT = nullptr;
+    int32_t *d_rows = nullptr, *d_rrows = nullptr;
+    MatInfo *d_mats = nullptr;
+    unsigned *d_ctr = nullptr;
+    int nctr = 0;
+    int64_t spin_limit = int64_t(1) << 26;
+    double inspect_seconds = 0;
+    uint64_t hash = 0;
+    int max_levels = 0;
+    std::vector<void *> allocs;
+};
+
+struct ddf_graph_s {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+};
+
+namespace {
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t _e = (x);                                                                       \
+        if (_e != hipSuccess)                                                                      \
+            return fail(DDF_E_HIP, std::string(#x) + ": " + hipGetErrorString(_e));                \
+    } while (0)
+
+int g_alloc_count = 0;
+
+ddf_status dalloc(ddf_plan_t p, void **ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (const char *s = getenv("DDF_TEST_FAIL_ALLOC")) {
+        int n = atoi(s);
+        if (n > 0 && ++g_alloc_count == n) return fail(DDF_E_NOMEM, "device allocation failed (test hook)");
+    }
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? DDF_E_NOMEM : DDF_E_HIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    p->allocs.push_back(*ptr);
+    return DDF_OK;
+}
+
+template <class T>
+ddf_status upload(ddf_plan_t p, T **dst, const T *src, size_t n) {
+    ddf_status s = dalloc(p, (void **)dst, n * sizeof(T));
+    if (s) return s;
+    if (n) HIPCHK(hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return DDF_OK;
+}
+
+int xmode_host(int fl) {
+    if (fl & FS2) return 0;
+    if (fl & FSEP) return (fl & FRUNS) ? 2 : 1;
+    return (fl & FRUNS) ? 4 : 3;
+}
+
+// Canonical tables of one matrix -> device records + aux (+ device-only supplements).
+void pack(const Canon &c, int kind, int mat, const int32_t *rp, DevTables &D) {
+    const int64_t base = (int64_t)D.aux.size();
+    D.aux.insert(D.aux.end(), c.aux.begin(), c.aux.end());
+    const int64_t ncod = c.header[7];
+    const size_t first = D.cods.size();
+    D.cods.resize(first + ncod);
+    std::vector<int64_t> rows, opst, nops;
+    for (int64_t i = 0; i < ncod; i++) {
+        const int64_t *r = &c.codelets[i * NCOD];
+        const int32_t fl = (int32_t)r[C_FLAGS];
+        const int32_t m = (int32_t)r[C_M];
+        DCod d;
+        d.flags = fl;
+        d.m = m;
+        d.nn = (int32_t)r[C_NN];
+        d.row0 = (int32_t)r[C_ROW0];
+        d.row_step = (int32_t)r[C_ROWSTEP];
+        d.op0 = (int32_t)r[C_OP0];
+        d.op_step = (int32_t)r[C_OPSTEP];
+        d.col0 = (int32_t)r[C_COL0];
+        d.sigma0 = (int32_t)r[C_SIG0];
+        d.sigma1 = (int32_t)r[C_SIG1];
+        int64_t p = base + r[C_AUXOFF];
+        d.rows_off = -1;
+        d.ops_off = -1;
+        d.cnt_off = -1;
+        d.xt_off = -1;
+        d.xp_off = -1;
+        d.mat = mat;
+        if (!(fl & FS0)) { d.rows_off = (int32_t)p; p += m; }
+        if (!(fl & FS1)) { d.ops_off = (int32_t)p; d.flags |= DOPS; p += m; }
+        if (!(fl & FRECT)) { d.cnt_off = (int32_t)p; p += m; }
+        if (!(fl & FS2)) d.xt_off = (int32_t)p;
+        // per-row facts, decoded from the tables just written
+        rows.resize(m);
+        opst.resize(m);
+        nops.resize(m);
+        for (int32_t a = 0; a < m; a++) {
+            rows[a] = (fl & FS0) ? (int64_t)d.row0 + (int64_t)a * d.row_step : D.aux[d.rows_off + a];
+            opst[a] = (d.flags & DOPS) ? D.aux[d.ops_off + a] : (int64_t)d.op0 + (int64_t)a * d.op_step;
+            nops[a] = (fl & FRECT) ? d.nn : D.aux[d.cnt_off + a];
+        }
+        // solves need every row's diagonal position; when S1 holds only because the
+        // codelet has no operations the record's op_step may not give it
+        if (kind >= 1 && (fl & FS1) && d.nn == 0 && m >= 2) {
+            bool arith = true;
+            for (int32_t a = 0; a < m; a++) {
+                int64_t real = kind == 1 ? (int64_t)rp[rows[a]] : (int64_t)rp[rows[a]] + 1;
+                if (real != (int64_t)d.op0 + (int64_t)a * d.op_step) arith = false;
+            }
+            if (!arith) {
+                d.ops_off = (int32_t)D.aux.size();
+                d.flags |= DOPS;
+                for (int32_t a = 0; a < m; a++)
+                    D.aux.push_back(kind == 1 ? rp[rows[a]] : rp[rows[a]] + 1);
+                D.supplement += m;
+            }
+        }
+        const int mode = xmode_host(fl);
+        if (mode == 3 && !(fl & FRECT)) {
+            bool contig = true;
+            for (int32_t a = 0; a + 1 < m; a++)
+                if (opst[a + 1] != opst[a] + nops[a]) contig = false;
+            if (contig) {
+                d.flags |= DCONTIG;
+            } else {
+                d.xp_off = (int32_t)D.aux.size();
+                d.flags |= DXPTR;
+                int64_t s = 0;
+                for (int32_t a = 0; a < m; a++) {
+                    D.aux.push_back((int32_t)s);
+                    s += nops[a];
+                }
+                D.supplement += m;
+            }
+        } else if (mode == 4) {
+            d.xp_off = (int32_t)D.aux.size();
+            d.flags |= DRPTR;
+            int64_t j = 0;
+            std::vector<int32_t> rptr(m);
+            for (int32_t a = 0; a < m; a++) {
+                rptr[a] = (int32_t)j;
+                int64_t got = 0;
+                while (got < nops[a]) {
+                    got += D.aux[d.xt_off + 2 * j + 1];
+                    j++;
+                }
+            }
+            D.aux.insert(D.aux.end(), rptr.begin(), rptr.end());
+            D.supplement += m;
+        }
+        D.cods[first + i] = d;
+    }
+}
+
+int lg_of(int64_t n, int opl) {
+    int lg = 0;
+    while (lg < 6 && (int64_t(1) << lg) * opl < n) lg++;
+    return lg;
+}
+
+// Tasks of one codelet: rows grouped so that a task's lanes-per-row fits its rows.
+void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_index, const SchedParams &sp,
+                   int phase, std::vector<Task> &out) {
+    const int32_t m = d.m;
+    auto nops_of = [&](int32_t a) -> int64_t { return (d.flags & FRECT) ? d.nn : aux[d.cnt_off + a]; };
+    int32_t a = 0;
+    while (a < m) {
+        int lg = lg_of(nops_of(a), sp.ops_per_lane);
+        int32_t b = a + 1;
+        while (b < m) {
+            int lgb = lg_of(nops_of(b), sp.ops_per_lane);
+            int lgn = std::max(lg, lgb);
+            if (lgb + 2 < lg || lgb > lg + 1) break;
+            if ((b - a + 1) > (64 >> lgn) * sp.passes) break;
+            lg = lgn;
+            b++;
+        }
+        out.push_back({cod_index, a, b, lg | (phase << 8)});
+        a = b;
+    }
+}
+
+// Level-ordered tasks of several matrices for the persistent solve.  Each matrix's
+// codelets [cod_begin[b], cod_begin[b+1]) carry their level in `levels`.  Tasks of
+// level l of every matrix come before level l+1; wait = tasks of the same matrix in
+// earlier levels.  Returns, per matrix, its total task count.
+std::vector<int64_t> solve_tasks(const DevTables &D, const std::vector<int64_t> &cod_begin,
+                                 const std::vector<std::vector<int32_t>> &levels, const SchedParams &sp,
+                                 std::vector<Task> &tasks, std::vector<int32_t> &wait) {
+    const int nm = (int)cod_begin.size() - 1;
+    std::vector<std::vector<std::vector<Task>>> per(nm);
+    int32_t maxl = 0;
+    for (int b = 0; b < nm; b++) {
+        int32_t nl = levels[b].empty() ? 0 : levels[b].back() + 1;
+        per[b].resize(nl);
+        maxl = std::max(maxl, nl);
+        for (int64_t c = cod_begin[b]; c < cod_begin[b + 1]; c++)
+            codelet_tasks(D.cods[c], D.aux, (int32_t)c, sp, 0, per[b][levels[b][c - cod_begin[b]]]);
+    }
+    std::vector<int64_t> total(nm, 0);
+    std::vector<std::vector<int64_t>> lvl_prefix(nm);
+    for (int b = 0; b < nm; b++) {
+        lvl_prefix[b].assign(per[b].size() + 1, 0);
+        for (size_t l = 0; l < per[b].size(); l++) lvl_prefix[b][l + 1] = lvl_prefix[b][l] + (int64_t)per[b][l].size();
+        total[b] = lvl_prefix[b].back();
+    }
+    for (int32_t l = 0; l < maxl; l++)
+        for (int b = 0; b < nm; b++) {
+            if (l >= (int32_t)per[b].size()) continue;
+            for (const Task &t : per[b][l]) {
+                tasks.push_back(t);
+                wait.push_back((int32_t)lvl_prefix[b][l]);
+            }
+        }
+    return total;
+}
+
+ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
+    // task buffers are replaced when the schedule changes (autotune)
+    auto drop = [&](void *ptr) {
+        if (!ptr) return;
+        auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
+        if (it != p->allocs.end()) p->allocs.erase(it);
+        (void)hipFree(ptr);
+    };
+    drop(D.d_tasks);
+    drop(D.d_wait);
+    D.d_tasks = nullptr;
+    D.d_wait = nullptr;
+    ddf_status s = upload(p, &D.d_tasks, D.tasks.data(), D.tasks.size());
+    if (s) return s;
+    if (!D.task_wait.empty()) s = upload(p, &D.d_wait, D.task_wait.data(), D.task_wait.size());
+    return s;
+}
+
+std::vector<int32_t> codelet_levels(const Canon &c) {
+    std::vector<int32_t> lv(c.header[7]);
+    for (int64_t i = 0; i < c.header[7]; i++) lv[i] = (int32_t)c.codelets[i * NCOD + C_PART];
+    return lv;
+}
+
+// (Re)build every task list of the plan from its schedule parameters.
+ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
+    if (p->kind == DDF_SPMV) {
+        if (fwd) {
+            p->F.tasks.clear();
+            for (size_t c = 0; c < p->F.cods.size(); c++) codelet_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_f, 0, p->F.tasks);
+            if (ddf_status s = upload_tasks(p, p->F)) return s;
+        }
+        if (adjp && p->has_adj) {
+            p->T.tasks.clear();
+            for (size_t c = 0; c < p->T.cods.size(); c++) codelet_tasks(p->T.cods[c], p->T.aux, (int32_t)c, p->sp_a, 0, p->T.tasks);
+            p->n_gx_tasks = (int64_t)p->T.tasks.size();
+            for (size_t c = 0; c < p->F.cods.size(); c++) codelet_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_a, 1, p->T.tasks);
+            if (ddf_status s = upload_tasks(p, p->T)) return s;
+        }
+        return DDF_OK;
+    }
+    std::vector<int64_t> cb(p->nmat + 1, 0);
+    for (int b = 0; b < p->nmat; b++) cb[b + 1] = cb[b] + p->fwd[b].header[7];
+    if (fwd) {
+        std::vector<std::vector<int32_t>> lv(p->nmat);
+        for (int b = 0; b < p->nmat; b++) lv[b] = codelet_levels(p->fwd[b]);
+        p->F.tasks.clear();
+        p->F.task_wait.clear();
+        solve_tasks(p->F, cb, lv, p->sp_f, p->F.tasks, p->F.task_wait);
+        if (ddf_status s = upload_tasks(p, p->F)) return s;
+        if (p->batch) {
+            // per-matrix task lists for the one-launch-per-matrix comparator
+            p->Fpm.tasks.clear();
+            p->Fpm.task_wait.clear();
+            p->pm_task_ptr.assign(1, 0);
+            for (int b = 0; b < p->nmat; b++) {
+                std::vector<int64_t> one = {cb[b], cb[b + 1]};
+                std::vector<std::vector<int32_t>> l1 = {lv[b]};
+                // solve_tasks expects codelet indices relative to cod_begin[0]
+                std::vector<Task> tk;
+                std::vector<int32_t> wt;
+                solve_tasks(p->F, one, l1, p->sp_f, tk, wt);
+                p->Fpm.tasks.insert(p->Fpm.tasks.end(), tk.begin(), tk.end());
+                p->Fpm.task_wait.insert(p->Fpm.task_wait.end(), wt.begin(), wt.end());
+                p->pm_task_ptr.push_back((int64_t)p->Fpm.tasks.size());
+            }
+            if (ddf_status s = upload_tasks(p, p->Fpm)) return s;
+        }
+    }
+    if (adjp && p->has_adj) {
+        std::vector<int64_t> cba(p->nmat + 1, 0);
+        std::vector<std::vector<int32_t>> lv(p->nmat);
+        for (int b = 0; b < p->nmat; b++) {
+            cba[b + 1] = cba[b] + p->adj[b].header[7];
+            lv[b] = codelet_levels(p->adj[b]);
+        }
+        p->T.tasks.clear();
+        p->T.task_wait.clear();
+        std::vector<int64_t> total = solve_tasks(p->T, cba, lv, p->sp_a, p->T.tasks, p->T.task_wait);
+        p->n_solve_tasks_adj = (int64_t)p->T.tasks.size();
+        // GV pass over L's forward codelets, after the matrix's whole solve
+        for (int b = 0; b < p->nmat; b++) {
+            size_t before = p->T.tasks.size();
+            for (int64_t c = cb[b]; c < cb[b + 1]; c++) codelet_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_a, 1, p->T.tasks);
+            for (size_t i = before; i < p->T.tasks.size(); i++) p->T.task_wait.push_back((int32_t)total[b]);
+        }
+        if (ddf_status s = upload_tasks(p, p->T)) return s;
+    }
+    return DDF_OK;
+}
+
+ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
+    if (ddf_status s = upload(p, &D.d_cods, D.cods.data(), D.cods.size())) return s;
+    return upload(p, &D.d_aux, D.aux.data(), D.aux.size());
+}
+
+void free_plan(ddf_plan_t p) {
+    if (!p) return;
+    for (void *ptr : p->allocs) (void)hipFree(ptr);
+    delete p;
+}
+
+void apply_opts(ddf_opts &o, const ddf_opts *in) {
+    ddf_opts_default(&o);
+    if (!in) return;
+    o = *in;
+    if (o.window <= 0) o.window = 64;
+    if (o.ops_per_lane <= 0) o.ops_per_lane = 4;
+    if (o.rows_passes <= 0) o.rows_passes = 2;
+}
+
+// Shared body of ddf_inspect / ddf_inspect_batch.
+ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, const int32_t *nrhs,
+                     const ddf_opts *opts, bool batch, ddf_plan_t *out) {
+    *out = nullptr;
+    if (kind != DDF_SPMV && kind != DDF_SPTRSV_LOWER) return fail(DDF_E_KIND, "unknown kind");
+    if (nmat < 1 || !mats) return fail(DDF_E_ARG, "no matrices");
+    if (batch && kind != DDF_SPTRSV_LOWER) return fail(DDF_E_KIND, "batches are lower-triangular solves");
+    ddf_opts o;
+    apply_opts(o, opts);
+    if (o.window < 1 || o.window > 1024) return fail(DDF_E_ARG, "window must be in 1..1024");
+    for (int b = 0; b < nmat; b++) {
+        if (ddf_status s = validate(kind, mats[b])) return s;
+        if (batch && (!nrhs || nrhs[b] < 1 || nrhs[b] > 32)) return fail(DDF_E_ARG, "nrhs must be in 1..32");
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    ddf_plan_t p = new (std::nothrow) ddf_plan_s();
+    if (!p) return fail(DDF_E_NOMEM, "host allocation failed");
+    p->kind = kind;
+    p->nmat = nmat;
+    p->batch = batch;
+    p->opts = o;
+    p->host_only = o.host_only != 0;
+    p->has_adj = o.build_adjoint != 0;
+    p->sp_f.ops_per_lane = p->sp_a.ops_per_lane = o.ops_per_lane;
+    p->sp_f.passes = p->sp_a.passes = o.rows_passes;
+    p->sp_f.remap = p->sp_a.remap = o.xcd_remap < 0 ? 1 : o.xcd_remap;
+    p->fwd.resize(nmat);
+    if (p->has_adj) p->adj.resize(nmat);
+    p->mats.resize(nmat);
+    std::vector<std::vector<int32_t>> rpT(nmat), ciT(nmat), perm(nmat);
+    for (int b = 0; b < nmat; b++) {
+        const ddf_csr_host &A = mats[b];
+        Pattern P{kind, A.n_rows, A.n_cols, A.row_ptr, A.col_idx};
+        inspect(P, o.window, o.threads, p->fwd[b]);
+        if (p->has_adj) {
+            transpose(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, rpT[b], ciT[b], perm[b]);
+            Pattern PT{kind == DDF_SPMV ? 0 : 2, A.n_cols, A.n_rows, rpT[b].data(), ciT[b].data()};
+            inspect(PT, o.window, o.threads, p->adj[b]);
+            p->adj[b].perm = perm[b];
+        }
+        MatInfo &mi = p->mats[b];
+        mi.row_base = p->n_rows;
+        mi.val_base = p->nnz;
+        mi.vec_base = p->vec_total;
+        mi.k = batch ? nrhs[b] : 0;
+        mi.n = A.n_rows;
+        p->n_rows += A.n_rows;
+        p->n_cols += A.n_cols;
+        p->nnz += A.row_ptr[A.n_rows];
+        p->vec_total += (int64_t)A.n_rows * (batch ? nrhs[b] : 1);
+        p->max_levels = std::max<int>(p->max_levels, (int)p->fwd[b].header[5]);
+    }
+    p->inspect_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    uint64_t h = 1469598103934665603ull;
+    for (auto &c : p->fwd) h = hash_canon(c, h);
+    p->hash = h;
+    if (!batch) {
+        p->hrp.assign(mats[0].row_ptr, mats[0].row_ptr + mats[0].n_rows + 1);
+        p->hci.assign(mats[0].col_idx, mats[0].col_idx + p->nnz);
+    }
+    if (p->host_only) {
+        *out = p;
+        return DDF_OK;
+    }
+    // device tables
+    if (hipError_t e = init_device_info()) {
+        free_plan(p);
+        return fail(DDF_E_HIP, std::string("device query: ") + hipGetErrorString(e));
+    }
+    for (int b = 0; b < nmat; b++) {
+        pack(p->fwd[b], kind, b, mats[b].row_ptr, p->F);
+        if (p->has_adj) pack(p->adj[b], kind == DDF_SPMV ? 0 : 2, b, rpT[b].data(), p->T);
+    }
+    ddf_status s = DDF_OK;
+    auto fin = [&](ddf_status st) {
+        if (st) {
+            free_plan(p);
+            return st;
+        }
+        *out = p;
+        return DDF_OK;
+    };
+    if ((s = upload_tables(p, p->F))) return fin(s);
+    if (p->has_adj && (s = upload_tables(p, p->T))) return fin(s);
+    if ((s = build_schedule(p, true, true))) return fin(s);
+    if ((s = upload(p, &p->d_mats, p->mats.data(), p->mats.size()))) return fin(s);
+    p->nctr = 2 + nmat;
+    if ((s = dalloc(p, (void **)&p->d_ctr, sizeof(unsigned) * p->nctr))) return fin(s);
+    if (hipError_t e = hipMemset(p->d_ctr, 0, sizeof(unsigned) * p->nctr))
+        return fin(fail(DDF_E_HIP, std::string("hipMemset: ") + hipGetErrorString(e)));
+    // values captured at inspect time (packed over a batch)
+    bool have_vals = true;
+    for (int b = 0; b < nmat; b++)
+        if (!mats[b].values && mats[b].row_ptr[mats[b].n_rows] > 0) have_vals = false;
+    if (have_vals && p->nnz > 0) {
+        if ((s = dalloc(p, (void **)&p->d_vals, p->nnz * sizeof(double)))) return fin(s);
+        for (int b = 0; b < nmat; b++) {
+            int64_t n = mats[b].row_ptr[mats[b].n_rows];
+            if (n)
+                if (hipError_t e = hipMemcpy(p->d_vals + p->mats[b].val_base, mats[b].values, n * 8, hipMemcpyHostToDevice))
+                    return fin(fail(DDF_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e)));
+        }
+    }
+    if (p->has_adj) {
+        std::vector<int32_t> pall;
+        for (int b = 0; b < nmat; b++) pall.insert(pall.end(), perm[b].begin(), perm[b].end());
+        if ((s = upload(p, &p->d_perm, pall.data(), pall.size()))) return fin(s);
+    }
+    if (!batch) {
+        // CSR copies for the plain comparators
+        if ((s = upload(p, &p->d_rp, p->hrp.data(), p->hrp.size()))) return fin(s);
+        if ((s = upload(p, &p->d_ci, p->hci.data(), p->hci.size()))) return fin(s);
+        if (kind == DDF_SPTRSV_LOWER) {
+            std::vector<int32_t> rows(p->fwd[0].part_rows.begin(), p->fwd[0].part_rows.end());
+            if ((s = upload(p, &p->d_rows, rows.data(), rows.size()))) return fin(s);
+            if (p->has_adj) {
+                std::vector<int32_t> rr(p->adj[0].part_rows.begin(), p->adj[0].part_rows.end());
+                if ((s = upload(p, &p->d_rrows, rr.data(), rr.size()))) return fin(s);
+                if ((s = upload(p, &p->d_rpT, rpT[0].data(), rpT[0].size()))) return fin(s);
+                if ((s = upload(p, &p->d_ciT, ciT[0].data(), ciT[0].size()))) return fin(s);
+            }
+        }
+    }
+    return fin(DDF_OK);
+}
+
+bool overlap(const void *a, int64_t na, const void *b, int64_t nb) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return na > 0 && nb > 0 && x < y + nb && y < x + na;
+}
+
+ddf_status need_device(ddf_plan_t p) {
+    if (!p) return fail(DDF_E_ARG, "plan is NULL");
+    if (p->host_only) return fail(DDF_E_UNSUPPORTED, "plan was inspected host-only");
+    return DDF_OK;
+}
+
+ddf_status check_nrhs(int32_t k) {
+    if (k < 1 || k > 32) return fail(DDF_E_ARG, "nrhs must be in 1..32");
+    return DDF_OK;
+}
+
+const double *vals_or_own(ddf_plan_t p, const double *v) { return v ? v : p->d_vals; }
+
+ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t task0, int64_t ntasks, bool adj,
+                        const double *vals, const double *b, double *x, const double *xf, double *gv,
+                        int32_t k_override, int kt, hipStream_t s) {
+    SolveArgs a{};
+    a.cods = adj ? p->T.d_cods : p->F.d_cods;
+    a.aux = adj ? p->T.d_aux : p->F.d_aux;
+    a.cods2 = p->F.d_cods;
+    a.aux2 = p->F.d_aux;
+    a.tasks = D.d_tasks + task0;
+    a.wait = D.d_wait + task0;
+    a.ntasks = (int32_t)ntasks;
+    a.mats = p->d_mats;
+    a.vals = vals;
+    a.perm = p->d_perm;
+    a.b = b;
+    a.x = x;
+    a.xf = xf;
+    a.gv = gv;
+    a.ctr = p->d_ctr;
+    a.spin_limit = p->spin_limit;
+    a.k_override = k_override;
+    HIPCHK(launch_reset(p->d_ctr, p->nctr, s));
+    HIPCHK(launch_solve(a, adj, kt, s));
+    return DDF_OK;
+}
+
+} // namespace
+
+// =================================================================================================
+// C ABI
+// =================================================================================================
+extern "C" {
+
+void ddf_opts_default(ddf_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->window = 64;
+    o->build_adjoint = 1;
+    o->ops_per_lane = 4;
+    o->rows_passes = 2;
+    o->xcd_remap = -1;
+}
+
+const char *ddf_version(void) { return "ddf-mi355x 0.1"; }
+
+const char *ddf_status_string(ddf_status s) {
+    switch (s) {
+    case DDF_OK: return "DDF_OK";
+    case DDF_E_ARG: return "DDF_E_ARG";
+    case DDF_E_CSR: return "DDF_E_CSR";
+    case DDF_E_NOT_LOWER: return "DDF_E_NOT_LOWER";
+    case DDF_E_NO_DIAG: return "DDF_E_NO_DIAG";
+    case DDF_E_KIND: return "DDF_E_KIND";
+    case DDF_E_NOMEM: return "DDF_E_NOMEM";
+    case DDF_E_HIP: return "DDF_E_HIP";
+    case DDF_E_DEVICE: return "DDF_E_DEVICE";
+    case DDF_E_UNSUPPORTED: return "DDF_E_UNSUPPORTED";
+    }
+    return "DDF_E_UNKNOWN";
+}
+
+const char *ddf_last_error(void) { return last_error().c_str(); }
+
+ddf_status ddf_inspect(ddf_kind kind, const ddf_csr_host *A, const ddf_opts *opts, ddf_plan_t *out) {
+    if (!out) return fail(DDF_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!A) return fail(DDF_E_ARG, "matrix is NULL");
+    try {
+        return make_plan(kind, 1, A, nullptr, opts, false, out);
+    } catch (const std::bad_alloc &) {
+        return fail(DDF_E_NOMEM, "host allocation failed");
+    }
+}
+
+ddf_status ddf_inspect_batch(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, const int32_t *nrhs,
+                             const ddf_opts *opts, ddf_plan_t *out) {
+    if (!out) return fail(DDF_E_ARG, "out is NULL");
+    *out = nullptr;
+    try {
+        return make_plan(kind, nmat, mats, nrhs, opts, true, out);
+    } catch (const std::bad_alloc &) {
+        return fail(DDF_E_NOMEM, "host allocation failed");
+    }
+}
+
+ddf_status ddf_plan_destroy(ddf_plan_t plan) {
+    free_plan(plan);
+    return DDF_OK;
+}
+
+ddf_status ddf_spmv_v(ddf_plan_t p, const double *d_vals, const double *d_x, double *d_y, int32_t nrhs,
+                      ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPMV) return fail(DDF_E_KIND, "plan is not an SpMV plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    if ((!d_vals && p->nnz) || (!d_x && p->n_cols) || (!d_y && p->n_rows)) return fail(DDF_E_ARG, "NULL buffer");
+    if (overlap(d_x, p->n_cols * nrhs * 8, d_y, p->n_rows * nrhs * 8)) return fail(DDF_E_ARG, "x and y overlap");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->n_rows == 0) return DDF_OK;
+    SpmvArgs a{};
+    a.cods = p->F.d_cods;
+    a.aux = p->F.d_aux;
+    a.tasks = p->F.d_tasks;
+    a.ntasks = (int32_t)p->F.tasks.size();
+    a.k = nrhs;
+    a.remap = p->sp_f.remap;
+    a.vals = d_vals;
+    a.x = d_x;
+    a.y = d_y;
+    HIPCHK(launch_spmv(a, false, kt_for(nrhs), s));
+    return DDF_OK;
+}
+
+ddf_status ddf_spmv(ddf_plan_t p, const double *d_x, double *d_y, int32_t nrhs, ddf_stream_t stream) {
+    if (p && !p->d_vals && p->nnz) return fail(DDF_E_ARG, "plan holds no values: use ddf_spmv_v");
+    return ddf_spmv_v(p, nullptr, d_x, d_y, nrhs, stream);
+}
+
+ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, double *d_x, int32_t nrhs,
+                        ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPTRSV_LOWER || p->batch) return fail(DDF_E_KIND, "plan is not a single-matrix SpTRSV plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    int64_t nb = p->n_rows * nrhs * 8;
+    if ((!d_vals && p->nnz) || (!d_b && p->n_rows) || (!d_x && p->n_rows)) return fail(DDF_E_ARG, "NULL buffer");
+    if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
+    if (p->n_rows == 0) return DDF_OK;
+    // the single matrix's right-hand-side count is a per-call argument (k_override)
+    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
+                        kt_for(nrhs), (hipStream_t)stream);
+}
+
+ddf_status ddf_sptrsv(ddf_plan_t p, const double *d_b, double *d_x, int32_t nrhs, ddf_stream_t stream) {
+    if (p && !p->d_vals && p->nnz) return fail(DDF_E_ARG, "plan holds no values: use ddf_sptrsv_v");
+    return ddf_sptrsv_v(p, nullptr, d_b, d_x, nrhs, stream);
+}
+
+ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gy,
+                            double *d_gx, double *d_gvals, int32_t nrhs, ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPMV) return fail(DDF_E_KIND, "plan is not an SpMV plan");
+    if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    if ((!d_vals && p->nnz) || (!d_gy && p->n_rows) || (d_gvals && !d_x && p->n_cols))
+        return fail(DDF_E_ARG, "NULL buffer");
+    if (d_gx && (overlap(d_gx, p->n_cols * nrhs * 8, d_gy, p->n_rows * nrhs * 8) ||
+                 overlap(d_gx, p->n_cols * nrhs * 8, d_x, p->n_cols * nrhs * 8)))
+        return fail(DDF_E_ARG, "gx overlaps an input");
+    if (d_gvals && (overlap(d_gvals, p->nnz * 8, d_gy, p->n_rows * nrhs * 8) ||
+                    overlap(d_gvals, p->nnz * 8, d_x, p->n_cols * nrhs * 8) ||
+                    overlap(d_gvals, p->nnz * 8, d_gx, p->n_cols * nrhs * 8)))
+        return fail(DDF_E_ARG, "gvals overlaps another buffer");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t t0 = d_gx ? 0 : p->n_gx_tasks;
+    int64_t t1 = d_gvals ? (int64_t)p->T.tasks.size() : p->n_gx_tasks;
+    if (t1 <= t0) return DDF_OK;
+    SpmvArgs a{};
+    a.cods = p->T.d_cods;
+    a.aux = p->T.d_aux;
+    a.tasks = p->T.d_tasks + t0;
+    a.ntasks = (int32_t)(t1 - t0);
+    a.k = nrhs;
+    a.remap = p->sp_a.remap;
+    a.vals = d_vals;
+    a.perm = p->d_perm;
+    a.x = d_gy;
+    a.y = d_gx;
+    a.cods2 = p->F.d_cods;
+    a.aux2 = p->F.d_aux;
+    a.g = d_gy;
+    a.x2 = d_x;
+    a.gv = d_gvals;
+    HIPCHK(launch_spmv(a, true, kt_for(nrhs), s));
+    return DDF_OK;
+}
+
+ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gx,
+                              double *d_gb, double *d_gvals, int32_t nrhs, ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPTRSV_LOWER || p->batch) return fail(DDF_E_KIND, "plan is not a single-matrix SpTRSV plan");
+    if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    int64_t nb = p->n_rows * nrhs * 8;
+    if ((!d_vals && p->nnz) || (!d_gx && p->n_rows) || (!d_gb && p->n_rows) || (d_gvals && !d_x))
+        return fail(DDF_E_ARG, "NULL buffer");
+    if (d_gb != d_gx && overlap(d_gb, nb, d_gx, nb)) return fail(DDF_E_ARG, "gb and gx partially overlap");
+    if (overlap(d_gb, nb, d_x, nb)) return fail(DDF_E_ARG, "gb overlaps x");
+    if (d_gvals && (overlap(d_gvals, p->nnz * 8, d_gb, nb) || overlap(d_gvals, p->nnz * 8, d_x, nb)))
+        return fail(DDF_E_ARG, "gvals overlaps another buffer");
+    if (p->n_rows == 0) return DDF_OK;
+    int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
+    return solve_launch(p, p->T, 0, nt, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
+                        (hipStream_t)stream);
+}
+
+static int batch_kt(ddf_plan_t p) {
+    int mk = 1;
+    for (auto &m : p->mats) mk = std::max(mk, m.k);
+    return kt_for(mk);
+}
+
+ddf_status ddf_sptrsv_batch(ddf_plan_t p, const double *d_vals, const double *d_b, double *d_x,
+                            ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (!p->batch) return fail(DDF_E_KIND, "plan is not a batch plan");
+    d_vals = vals_or_own(p, d_vals);
+    int64_t nb = p->vec_total * 8;
+    if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
+    if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
+    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nullptr, nullptr, 0,
+                        batch_kt(p), (hipStream_t)stream);
+}
+
+ddf_status ddf_sptrsv_batch_adjoint(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gx,
+                                    double *d_gb, double *d_gvals, ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (!p->batch) return fail(DDF_E_KIND, "plan is not a batch plan");
+    if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    d_vals = vals_or_own(p, d_vals);
+    int64_t nb = p->vec_total * 8;
+    if ((!d_vals && p->nnz) || !d_gx || !d_gb || (d_gvals && !d_x)) return fail(DDF_E_ARG, "NULL buffer");
+    if (d_gb != d_gx && overlap(d_gb, nb, d_gx, nb)) return fail(DDF_E_ARG, "gb and gx partially overlap");
+    if (overlap(d_gb, nb, d_x, nb)) return fail(DDF_E_ARG, "gb overlaps x");
+    int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
+    return solve_launch(p, p->T, 0, nt, true, d_vals, d_gx, d_gb, d_x, d_gvals, 0, batch_kt(p),
+                        (hipStream_t)stream);
+}
+
+ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t p, const double *d_vals, const double *d_b, double *d_x,
+                                       ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (!p->batch) return fail(DDF_E_KIND, "plan is not a batch plan");
+    d_vals = vals_or_own(p, d_vals);
+    if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
+    for (int b = 0; b < p->nmat; b++) {
+        int64_t t0 = p->pm_task_ptr[b], t1 = p->pm_task_ptr[b + 1];
+        if (ddf_status s = solve_launch(p, p->Fpm, t0, t1 - t0, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
+                                        kt_for(p->mats[b].k), (hipStream_t)stream))
+            return s;
+    }
+    return DDF_OK;
+}
+
+ddf_status ddf_graph_create_batch(ddf_plan_t p, int32_t adjoint, const double *d_vals, const double *d_in,
+                                  const double *d_x, double *d_out, double *d_gvals, ddf_graph_t *out) {
+    if (!out) return fail(DDF_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (ddf_status s = need_device(p)) return s;
+    if (!p->batch) return fail(DDF_E_KIND, "plan is not a batch plan");
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    ddf_graph_s *g = new ddf_graph_s();
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    ddf_status st = DDF_OK;
+    if (e == hipSuccess) {
+        st = adjoint ? ddf_sptrsv_batch_adjoint(p, d_vals, d_x, d_in, d_out, d_gvals, s)
+                     : ddf_sptrsv_batch(p, d_vals, d_in, d_out, s);
+        hipError_t e2 = hipStreamEndCapture(s, &g->g);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && st == DDF_OK) e = hipGraphInstantiate(&g->e, g->g, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(s);
+    if (st != DDF_OK || e != hipSuccess) {
+        if (g->e) (void)hipGraphExecDestroy(g->e);
+        if (g->g) (void)hipGraphDestroy(g->g);
+        delete g;
+        if (st != DDF_OK) return st;
+        return fail(DDF_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return DDF_OK;
+}
+
+ddf_status ddf_graph_launch(ddf_graph_t g, ddf_stream_t stream) {
+    if (!g || !g->e) return fail(DDF_E_ARG, "graph is NULL");
+    HIPCHK(hipGraphLaunch(g->e, (hipStream_t)stream));
+    return DDF_OK;
+}
+
+ddf_status ddf_graph_destroy(ddf_graph_t g) {
+    if (!g) return DDF_OK;
+    if (g->e) (void)hipGraphExecDestroy(g->e);
+    if (g->g) (void)hipGraphDestroy(g->g);
+    delete g;
+    return DDF_OK;
+}
+
+// ---------------------------------------------------------------- plain comparators
+
+ddf_status ddf_plain_spmv(ddf_plan_t p, const double *d_vals, const double *d_x, double *d_y, int32_t nrhs,
+                          ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPMV) return fail(DDF_E_KIND, "plan is not an SpMV plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    if ((!d_vals && p->nnz) || !d_x || !d_y) return fail(DDF_E_ARG, "NULL buffer");
+    if (overlap(d_x, p->n_cols * nrhs * 8, d_y, p->n_rows * nrhs * 8)) return fail(DDF_E_ARG, "x and y overlap");
+    PlainArgs a{};
+    a.rp = p->d_rp;
+    a.ci = p->d_ci;
+    a.vals = d_vals;
+    a.x = d_x;
+    a.y = d_y;
+    a.n = p->n_rows;
+    a.k = nrhs;
+    HIPCHK(launch_plain(PLAIN_SPMV, a, p->n_rows ? (double)p->nnz / p->n_rows : 1.0, kt_for(nrhs),
+                        (hipStream_t)stream));
+    return DDF_OK;
+}
+
+ddf_status ddf_plain_sptrsv(ddf_plan_t p, const double *d_vals, const double *d_b, double *d_x, int32_t nrhs,
+                            ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPTRSV_LOWER || p->batch) return fail(DDF_E_KIND, "plan is not a single-matrix SpTRSV plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    int64_t nb = p->n_rows * nrhs * 8;
+    if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
+    if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
+    PlainArgs a{};
+    a.rp = p->d_rp;
+    a.ci = p->d_ci;
+    a.vals = d_vals;
+    a.rows = p->d_rows;
+    a.x = d_b;
+    a.y = d_x;
+    a.k = nrhs;
+    a.upper = 0;
+    const Canon &c = p->fwd[0];
+    double avg = p->n_rows ? (double)(p->nnz - p->n_rows) / p->n_rows : 1.0;
+    for (int64_t l = 0; l < c.header[5]; l++) {
+        a.lo = c.part_ptr[l];
+        a.hi = c.part_ptr[l + 1];
+        HIPCHK(launch_plain(PLAIN_LEVEL, a, avg, kt_for(nrhs), (hipStream_t)stream));
+    }
+    return DDF_OK;
+}
+
+ddf_status ddf_plain_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gy,
+                                  double *d_gx, double *d_gvals, int32_t nrhs, ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPMV) return fail(DDF_E_KIND, "plan is not an SpMV plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    if ((!d_vals && p->nnz) || !d_x || !d_gy) return fail(DDF_E_ARG, "NULL buffer");
+    hipStream_t s = (hipStream_t)stream;
+    if (d_gx) HIPCHK(launch_fill(d_gx, p->n_cols * nrhs, 0.0, s));
+    PlainArgs a{};
+    a.rp = p->d_rp;
+    a.ci = p->d_ci;
+    a.vals = d_vals;
+    a.x = d_x;
+    a.g = d_gy;
+    a.y = d_gx;
+    a.gv = d_gvals;
+    a.n = p->n_rows;
+    a.k = nrhs;
+    HIPCHK(launch_plain(PLAIN_SPMV_ADJ, a, p->n_rows ? (double)p->nnz / p->n_rows : 1.0, 1, s));
+    return DDF_OK;
+}
+
+ddf_status ddf_plain_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gx,
+                                    double *d_gb, double *d_gvals, int32_t nrhs, ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPTRSV_LOWER || p->batch) return fail(DDF_E_KIND, "plan is not a single-matrix SpTRSV plan");
+    if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    if ((!d_vals && p->nnz) || !d_gx || !d_gb || (d_gvals && !d_x)) return fail(DDF_E_ARG, "NULL buffer");
+    hipStream_t s = (hipStream_t)stream;
+    PlainArgs a{};
+    a.rp = p->d_rpT;
+    a.ci = p->d_ciT;
+    a.vals = d_vals;
+    a.perm = p->d_perm;
+    a.rows = p->d_rrows;
+    a.x = d_gx;
+    a.y = d_gb;
+    a.k = nrhs;
+    a.upper = 1;
+    const Canon &c = p->adj[0];
+    double avg = p->n_rows ? (double)(p->nnz - p->n_rows) / p->n_rows : 1.0;
+    for (int64_t l = 0; l < c.header[5]; l++) {
+        a.lo = c.part_ptr[l];
+        a.hi = c.part_ptr[l + 1];
+        HIPCHK(launch_plain(PLAIN_LEVEL, a, avg, kt_for(nrhs), s));
+    }
+    if (d_gvals) {
+        PlainArgs g{};
+        g.rp = p->d_rp;
+        g.ci = p->d_ci;
+        g.g = d_gb;
+        g.x = d_x;
+        g.gv = d_gvals;
+        g.n = p->n_rows;
+        g.k = nrhs;
+        HIPCHK(launch_plain(PLAIN_GV, g, p->n_rows ? (double)p->nnz / p->n_rows : 1.0, 1, s));
+    }
+    return DDF_OK;
+}
+
+// ---------------------------------------------------------------- introspection
+
+ddf_status ddf_plan_info(ddf_plan_t p, ddf_plan_info_t *o) {
+    if (!p || !o) return fail(DDF_E_ARG, "NULL argument");
+    std::memset(o, 0, sizeof(*o));
+    o->kind = p->kind;
+    o->nmat = p->nmat;
+    o->n_rows = (int32_t)p->n_rows;
+    o->n_cols = (int32_t)p->n_cols;
+    o->nnz = p->nnz;
+    for (auto &c : p->fwd) {
+        o->n_parts += c.header[5];
+        o->n_regions += c.header[6];
+        o->n_codelets += c.header[7];
+        o->aux_len += c.header[8];
+        for (int64_t i = 0; i < c.header[7]; i++) {
+            const int64_t *r = &c.codelets[i * NCOD];
+            o->codelets_by_type[r[C_TYPE]]++;
+            o->ops_by_type[r[C_TYPE]] += r[C_P];
+        }
+    }
+    o->n_tasks = (int64_t)p->F.tasks.size();
+    o->n_tasks_adjoint = (int64_t)p->T.tasks.size();
+    o->dev_plan_bytes = p->F.bytes();
+    o->dev_plan_bytes_adj = p->has_adj ? p->T.bytes() : 0;
+    o->has_adjoint = p->has_adj;
+    o->max_levels = p->max_levels;
+    o->inspect_seconds = p->inspect_seconds;
+    o->hash = p->hash;
+    o->ops_per_lane = p->sp_f.ops_per_lane;
+    o->rows_passes = p->sp_f.passes;
+    o->xcd_remap = p->sp_f.remap;
+    return DDF_OK;
+}
+
+ddf_status ddf_plan_export(ddf_plan_t p, int32_t which, int32_t mat, ddf_plan_tables_t *o) {
+    if (!p || !o) return fail(DDF_E_ARG, "NULL argument");
+    if (mat < 0 || mat >= p->nmat) return fail(DDF_E_ARG, "matrix index out of range");
+    if (which != 0 && which != 1) return fail(DDF_E_ARG, "which must be 0 or 1");
+    if (which == 1 && !p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    const Canon &c = which ? p->adj[mat] : p->fwd[mat];
+    o->header = c.header;
+    o->part_ptr = c.part_ptr.data();
+    o->part_rows = c.part_rows.data();
+    o->regions = c.regions.data();
+    o->codelets = c.codelets.data();
+    o->aux = c.aux.data();
+    o->perm = which ? c.perm.data() : nullptr;
+    return DDF_OK;
+}
+
+ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *bytes_alg, int64_t *bytes_csr,
+                            int64_t *flops) {
+    if (!p) return fail(DDF_E_ARG, "plan is NULL");
+    int64_t nnz = p->nnz, n = p->n_rows, nc = p->n_cols;
+    int64_t vk = p->batch ? p->vec_total : n * nrhs;      // sum of n_b k_b
+    int64_t ck = p->batch ? p->vec_total : nc * nrhs;
+    int64_t kf = p->batch ? 0 : nrhs;
+    int64_t Fca = (int64_t)p->F.cods.size() * sizeof(DCod) + (int64_t)p->F.aux.size() * 4;
+    int64_t ba = 0, bc = 0, fl = 0;
+    switch (op) {
+    case DDF_OP_SPMV:
+        ba = 8 * nnz + p->F.bytes() + 8 * ck + 8 * vk;
+        bc = 12 * nnz + 4 * (n + 1) + 8 * ck + 8 * vk;
+        fl = 2 * nnz * nrhs;
+        break;
+    case DDF_OP_SPMV_ADJ:
+        ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 16 * vk + 16 * ck;
+        bc = 20 * nnz + 4 * (n + 1) + 8 * vk + 16 * ck;
+        fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
+        break;
+    case DDF_OP_SPTRSV:
+        ba = 8 * nnz + p->F.bytes() + 16 * vk;
+        bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
+        if (p->batch) {
+            for (size_t b = 0; b < p->mats.size(); b++) {
+                int64_t nz = p->fwd[b].header[3], nb = p->mats[b].n;
+                fl += (int64_t)p->mats[b].k * (2 * (nz - nb) + nb);
+            }
+        } else {
+            fl = kf * (2 * (nnz - n) + n);
+        }
+        break;
+    case DDF_OP_SPTRSV_ADJ:
+        ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 32 * vk;
+        bc = 20 * nnz + 4 * (n + 1) + 24 * vk;
+        if (p->batch) {
+            for (size_t b = 0; b < p->mats.size(); b++) {
+                int64_t nz = p->fwd[b].header[3], nb = p->mats[b].n, k = p->mats[b].k;
+                fl += k * (2 * (nz - nb) + nb) + nz * (2 * k - 1);
+            }
+        } else {
+            fl = kf * (2 * (nnz - n) + n) + nnz * (2 * kf - 1);
+        }
+        break;
+    default: return fail(DDF_E_ARG, "unknown op");
+    }
+    if (bytes_alg) *bytes_alg = ba;
+    if (bytes_csr) *bytes_csr = bc;
+    if (flops) *flops = fl;
+    return DDF_OK;
+}
+
+ddf_status ddf_plan_sync_status(ddf_plan_t p, ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    unsigned flag = 0;
+    HIPCHK(hipMemcpy(&flag, p->d_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (flag) {
+        unsigned z = 0;
+        HIPCHK(hipMemcpy(p->d_ctr + 1, &z, sizeof(unsigned), hipMemcpyHostToDevice));
+        return fail(DDF_E_DEVICE, "a level wait exceeded its spin limit");
+    }
+    return DDF_OK;
+}
+
+ddf_status ddf_plan_set_spin_limit(ddf_plan_t p, int64_t limit) {
+    if (!p) return fail(DDF_E_ARG, "plan is NULL");
+    p->spin_limit = limit > 0 ? limit : (int64_t(1) << 26);
+    return DDF_OK;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, SchedParams> g_tune_cache;
+
+std::string tune_key(ddf_plan_t p, ddf_op op, int32_t nrhs) {
+    std::ostringstream os;
+    os << std::hex << p->hash << std::dec << ":" << (int)op << ":" << nrhs;
+    return os.str();
+}
+
+void load_tune_file() {
+    const char *path = getenv("DDF_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        // one entry per line: "key": [ops_per_lane, passes, remap],
+        size_t q1 = line.find('"'), q2 = line.find('"', q1 + 1), b = line.find('[');
+        if (q1 == std::string::npos || q2 == std::string::npos || b == std::string::npos) continue;
+        SchedParams sp;
+        if (sscanf(line.c_str() + b, "[%d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap) == 3)
+            g_tune_cache[line.substr(q1 + 1, q2 - q1 - 1)] = sp;
+    }
+}
+
+void save_tune_file() {
+    const char *path = getenv("DDF_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path);
+    f << "{\n";
+    size_t i = 0;
+    for (auto &kv : g_tune_cache)
+        f << "  \"" << kv.first << "\": [" << kv.second.ops_per_lane << ", " << kv.second.passes << ", "
+          << kv.second.remap << "]" << (++i < g_tune_cache.size() ? "," : "") << "\n";
+    f << "}\n";
+}
+
+} // namespace
+
+extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_stream_t stream, double budget_ms) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->batch) nrhs = 1;
+    else if (ddf_status s = check_nrhs(nrhs)) return s;
+    bool is_spmv = op == DDF_OP_SPMV || op == DDF_OP_SPMV_ADJ;
+    if (is_spmv != (p->kind == DDF_SPMV)) return fail(DDF_E_KIND, "op does not match the plan kind");
+    bool adjop = op == DDF_OP_SPMV_ADJ || op == DDF_OP_SPTRSV_ADJ;
+    if (adjop && !p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    if (!p->d_vals && p->nnz) return fail(DDF_E_ARG, "autotune needs values captured at inspect time");
+    SchedParams &target = adjop ? p->sp_a : p->sp_f;
+    const std::string key = tune_key(p, op, nrhs);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        static bool loaded = false;
+        if (!loaded) {
+            load_tune_file();
+            loaded = true;
+        }
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            target = it->second;
+            return build_schedule(p, !adjop, adjop);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nvec = p->batch ? p->vec_total : std::max(p->n_rows, p->n_cols) * nrhs;
+    double *buf = nullptr;
+    HIPCHK(hipMalloc(&buf, (3 * nvec + p->nnz + 1) * sizeof(double)));
+    double *x = buf, *y = buf + nvec, *z = buf + 2 * nvec, *gv = buf + 3 * nvec;
+    ddf_status st = launch_fill(x, 3 * nvec, 0.5, s) == hipSuccess ? DDF_OK : DDF_E_HIP;
+    auto run = [&]() -> ddf_status {
+        switch (op) {
+        case DDF_OP_SPMV: return ddf_spmv_v(p, nullptr, x, y, nrhs, s);
+        case DDF_OP_SPMV_ADJ: return ddf_spmv_adjoint(p, nullptr, x, z, y, gv, nrhs, s);
+        case DDF_OP_SPTRSV:
+            return p->batch ? ddf_sptrsv_batch(p, nullptr, x, y, s) : ddf_sptrsv_v(p, nullptr, x, y, nrhs, s);
+        default:
+            return p->batch ? ddf_sptrsv_batch_adjoint(p, nullptr, x, z, y, gv, s)
+                            : ddf_sptrsv_adjoint(p, nullptr, x, z, y, gv, nrhs, s);
+        }
+    };
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    SchedParams best = target;
+    float best_ms = 1e30f;
+    double spent = 0;
+    const int opls[] = {2, 4, 8, 16};
+    const int passes[] = {1, 2, 4};
+    const int remaps[] = {1, 0};
+    for (int rm : remaps) {
+        if (!is_spmv && rm == 0) continue;
+        for (int opl : opls)
+            for (int ps : passes) {
+                if (st || (budget_ms > 0 && spent > budget_ms)) break;
+                target.ops_per_lane = opl;
+                target.passes = ps;
+                target.remap = rm;
+                if ((st = build_schedule(p, !adjop, adjop))) break;
+                if ((st = run())) break;
+                (void)hipEventRecord(e0, s);
+                const int reps = 3;
+                for (int r = 0; r < reps && !st; r++) st = run();
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                spent += ms * (reps + 1);
+                ms /= reps;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = target;
+                }
+            }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    target = best;
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+        save_tune_file();
+    }
+    return build_schedule(p, !adjop, adjop);
+}

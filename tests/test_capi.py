@@ -1,0 +1,116 @@
+"""The C ABI without a GPU: the library loads, exports what include/ddf.h declares, and
+rejects bad input before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2111_12243_amd import ddf
+from paper_2111_12243_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "ddf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddf_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    names = declared()
+    assert len(names) >= 25
+    lib = ctypes.CDLL(ddf.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(ddf.EXPORTED) == names
+
+
+def test_status_strings_and_version():
+    assert ddf.ddf_status_string(0) == "DDF_OK"
+    assert ddf.ddf_status_string(8) == "DDF_E_DEVICE"
+    assert ddf.ddf_version().startswith("ddf")
+
+
+def test_defaults():
+    o = ddf.ddf_opts_default()
+    assert (o.window, o.build_adjoint, o.host_only) == (64, 1, 0)
+
+
+def expect(status, fn):
+    with pytest.raises(ddf.DDFError) as e:
+        fn()
+    assert e.value.status == status, str(e.value)
+
+
+def hopts():
+    return ddf.ddf_opts_default(host_only=1)
+
+
+def test_malformed_csr_rejected():
+    good = I.random_csr(20, 20, 1, density=0.3)
+    bad = I.CSR(20, 20, good.row_ptr.copy(), good.col_idx.copy(), good.values)
+    bad.row_ptr[5] = bad.row_ptr[6] + 1
+    expect(ddf.DDF_E_CSR, lambda: ddf.ddf_inspect(0, bad, hopts()))
+    bad = I.CSR(20, 20, good.row_ptr, good.col_idx.copy(), good.values)
+    bad.col_idx[0] = 25
+    expect(ddf.DDF_E_CSR, lambda: ddf.ddf_inspect(0, bad, hopts()))
+    bad = I.CSR(20, 20, good.row_ptr, good.col_idx.copy(), good.values)
+    r = int(np.argmax(np.diff(good.row_ptr) >= 2))
+    s = good.row_ptr[r]
+    bad.col_idx[s], bad.col_idx[s + 1] = good.col_idx[s + 1], good.col_idx[s]
+    expect(ddf.DDF_E_CSR, lambda: ddf.ddf_inspect(0, bad, hopts()))
+    bad.col_idx[s + 1] = bad.col_idx[s]  # repeated column
+    expect(ddf.DDF_E_CSR, lambda: ddf.ddf_inspect(0, bad, hopts()))
+
+
+def test_triangular_checks():
+    A = I.random_csr(10, 10, 3, density=0.5, empty_frac=0.0)
+    expect(ddf.DDF_E_NOT_LOWER, lambda: ddf.ddf_inspect(1, A, hopts()))
+    L = I.random_lower(10, 2)
+    rows = np.repeat(np.arange(10), np.diff(L.row_ptr))
+    keep = ~((rows == 4) & (L.col_idx == 4))
+    nod = I.csr_from_pairs(10, 10, rows[keep], L.col_idx[keep], L.values[keep])
+    expect(ddf.DDF_E_NO_DIAG, lambda: ddf.ddf_inspect(1, nod, hopts()))
+    rect = I.CSR(10, 11, L.row_ptr, L.col_idx, L.values)
+    expect(ddf.DDF_E_ARG, lambda: ddf.ddf_inspect(1, rect, hopts()))
+    expect(ddf.DDF_E_KIND, lambda: ddf.ddf_inspect(7, L, hopts()))
+
+
+def test_options_checked():
+    L = I.random_lower(10, 2)
+    expect(ddf.DDF_E_ARG, lambda: ddf.ddf_inspect(1, L, ddf.ddf_opts_default(host_only=1, window=4096)))
+    expect(ddf.DDF_E_ARG, lambda: ddf.ddf_inspect_batch(1, [L, L], [1, 33], hopts()))
+    expect(ddf.DDF_E_KIND, lambda: ddf.ddf_inspect_batch(0, [L], [1], hopts()))
+
+
+def test_host_only_plan_refuses_execution():
+    p = ddf.ddf_inspect(1, I.random_lower(10, 2), hopts())
+    expect(ddf.DDF_E_UNSUPPORTED, lambda: ddf.ddf_sptrsv_v(p, 0, 0, 0, 1, 0))
+    expect(ddf.DDF_E_UNSUPPORTED, lambda: ddf.ddf_spmv_v(p, 0, 0, 0, 1, 0))
+    q = ddf.ddf_inspect(0, I.random_csr(8, 8, 1), ddf.ddf_opts_default(host_only=1, build_adjoint=0))
+    expect(ddf.DDF_E_UNSUPPORTED, lambda: ddf.ddf_plan_export(q, 1))
+    info = ddf.ddf_plan_info(p)
+    assert info["n_tasks"] == 0 and info["has_adjoint"] == 1
+
+
+def test_batch_host_plan_members_match_single():
+    mats = [I.batch_matrix(b, n_lo=300, n_hi=3000)["L"] for b in range(4)]
+    p = ddf.ddf_inspect_batch(1, mats, [1, 2, 3, 4], hopts())
+    for b, L in enumerate(mats):
+        single = ddf.ddf_plan_export(ddf.ddf_inspect(1, L, hopts()), 0)
+        mine = ddf.ddf_plan_export(p, 0, b)
+        for k in single:
+            assert np.array_equal(single[k], mine[k])
+
+
+def test_traffic_formulas():
+    w = I.c1_laplace2d()
+    p = ddf.ddf_inspect(0, w.A, hopts())
+    ba, bc, fl = ddf.ddf_plan_traffic(p, ddf.DDF_OP_SPMV, 1)
+    n, nnz = w.A.n_rows, w.A.nnz
+    assert bc == 12 * nnz + 4 * (n + 1) + 16 * n
+    assert fl == 2 * nnz
+    assert ba == 8 * nnz + 16 * n  # host-only plan: no device tables counted

@@ -1,0 +1,185 @@
+"""Executor parity on the GPU through the C ABI: DDF kernels (and the plain comparators)
+against the CPU oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_12243_amd import inputs as I
+from tolerance import check_gv, check_product, check_solve
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2111_12243_amd import ddf  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rnd(shape, seed):
+    return np.random.default_rng(seed).uniform(-1, 1, shape)
+
+
+def spmv_case(A, k, seed=0, opts=None, plain=True):
+    print(f"spmv n={A.n_rows} m={A.n_cols} nnz={A.nnz} k={k}", flush=True)
+    plan = ddf.ddf_inspect(0, A, opts)
+    X = rnd((A.n_cols, k), seed)
+    G = rnd((A.n_rows, k), seed + 1)
+    ref = O.spmv(A, X)
+    x, g = dev(X), dev(G)
+    y = torch.full((A.n_rows, k), np.nan, dtype=torch.float64, device=DEV)
+    ddf.ddf_spmv(plan, x, y, k)
+    got = host(y)
+    check_product(A, X, got, ref)
+    # determinism: a second run is bitwise equal
+    y2 = torch.empty_like(y)
+    ddf.ddf_spmv(plan, x, y2, k)
+    assert np.array_equal(host(y2), got)
+    # adjoint
+    GX, GV = O.spmv_adj(A, X, G)
+    gx = torch.full((A.n_cols, k), np.nan, dtype=torch.float64, device=DEV)
+    gv = torch.full((max(A.nnz, 1),), np.nan, dtype=torch.float64, device=DEV)
+    vals = dev(A.values) if A.nnz else dev(np.zeros(1))
+    ddf.ddf_spmv_adjoint(plan, vals, x, g, gx, gv, k)
+    from types import SimpleNamespace
+    AT, _ = O.transpose(A)
+    check_product(AT, G, host(gx), GX)
+    check_gv(A, X, G, host(gv)[:A.nnz], GV)
+    if plain:
+        yp = torch.empty_like(y)
+        ddf.ddf_plain_spmv(plan, vals, x, yp, k)
+        check_product(A, X, host(yp), ref)
+        gxp = torch.empty_like(gx)
+        gvp = torch.empty_like(gv)
+        ddf.ddf_plain_spmv_adjoint(plan, vals, x, g, gxp, gvp, k)
+        check_product(AT, G, host(gxp), GX)
+        check_gv(A, X, G, host(gvp)[:A.nnz], GV)
+    return plan
+
+
+def sptrsv_case(L, k, seed=0, opts=None, plain=True, inplace=False):
+    print(f"sptrsv n={L.n_rows} nnz={L.nnz} k={k}", flush=True)
+    plan = ddf.ddf_inspect(1, L, opts)
+    B = rnd((L.n_rows, k), seed)
+    G = rnd((L.n_rows, k), seed + 1)
+    ref = O.sptrsv(L, B)
+    b = dev(B)
+    x = b if inplace else torch.full_like(b, np.nan)
+    ddf.ddf_sptrsv(plan, b, x, k)
+    ddf.ddf_plan_sync_status(plan)
+    got = host(x)
+    check_solve(L, B, got, ref)
+    if inplace:
+        b = dev(B)
+    x2 = torch.empty_like(b)
+    ddf.ddf_sptrsv(plan, b, x2, k)
+    assert np.array_equal(host(x2), got)
+    # adjoint
+    GB, GV = O.sptrsv_adj(L, ref, G)
+    xs, g = dev(ref), dev(G)
+    gb = torch.full_like(g, np.nan)
+    gv = torch.full((L.nnz,), np.nan, dtype=torch.float64, device=DEV)
+    vals = dev(L.values)
+    ddf.ddf_sptrsv_adjoint(plan, vals, xs, g, gb, gv, k)
+    ddf.ddf_plan_sync_status(plan)
+    check_solve(L, G, host(gb), GB, transposed=True)
+    check_gv(L, ref, GB, -host(gv), -GV)
+    if plain:
+        xp = torch.full_like(b, np.nan)
+        ddf.ddf_plain_sptrsv(plan, vals, b, xp, k)
+        check_solve(L, B, host(xp), ref)
+        gbp = torch.full_like(g, np.nan)
+        gvp = torch.full_like(gv, np.nan)
+        ddf.ddf_plain_sptrsv_adjoint(plan, vals, xs, g, gbp, gvp, k)
+        check_solve(L, G, host(gbp), GB, transposed=True)
+        check_gv(L, ref, GB, -host(gvp), -GV)
+    return plan
+
+
+# ---------------------------------------------------------------- crafted
+
+def worked_example():
+    rows = np.repeat(np.arange(3), 3)
+    return I.csr_from_pairs(3, 8, rows, np.array([0, 2, 5, 1, 3, 6, 2, 4, 7]), np.arange(1.0, 10.0))
+
+
+def bidiag(n):
+    rows = np.concatenate([np.arange(1, n), np.arange(n)])
+    cols = np.concatenate([np.arange(n - 1), np.arange(n)])
+    return I.csr_from_pairs(n, n, rows, cols, np.random.default_rng(n).uniform(1, 2, rows.size))
+
+
+def test_crafted_spmv():
+    spmv_case(worked_example(), 1)
+    n = 300
+    spmv_case(I.csr_from_pairs(n, n, np.arange(n), np.arange(n), np.arange(1.0, n + 1)), 2)
+    spmv_case(bidiag(257), 3)
+    # a dense row, a giant row, empty rows
+    rows = np.concatenate([np.zeros(5000, int), np.arange(2, 60), np.full(3, 70)])
+    cols = np.concatenate([np.arange(5000), np.arange(2, 60) * 7, [0, 100, 4999]])
+    A = I.csr_from_pairs(80, 5000, rows, cols, np.random.default_rng(0).uniform(-1, 1, rows.size))
+    spmv_case(A, 1)
+    spmv_case(A, 5)
+
+
+def test_crafted_sptrsv():
+    n = 200
+    sptrsv_case(I.csr_from_pairs(n, n, np.arange(n), np.arange(n), np.arange(1.0, n + 1)), 1)
+    sptrsv_case(bidiag(333), 2)
+    sptrsv_case(I.tril(I.laplacian(17, 13, 1, I.OFFS_5PT, 4.0)), 1, inplace=True)
+
+
+def test_c1():
+    w = I.c1_laplace2d()
+    spmv_case(w.A, 1)
+    sptrsv_case(w.L, 1)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_spmv(seed):
+    rng = np.random.default_rng(seed)
+    A = I.random_csr(int(rng.integers(1, 400)), int(rng.integers(1, 400)), seed,
+                     density=float(rng.uniform(0.002, 0.08)), empty_frac=float(rng.uniform(0, 0.4)),
+                     runs=bool(seed % 2))
+    k = [1, 2, 3, 8, 13, 32][seed % 6]
+    opts = ddf.ddf_opts_default(window=int(rng.choice([8, 64, 100])), ops_per_lane=int(rng.choice([1, 4, 16])),
+                                rows_passes=int(rng.choice([1, 2, 4])))
+    spmv_case(A, k, seed, opts)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_sptrsv(seed):
+    rng = np.random.default_rng(50 + seed)
+    L = I.random_lower(int(rng.integers(1, 300)), seed, density=float(rng.uniform(0.0, 0.05)),
+                       runs=bool(seed % 2))
+    k = [1, 2, 3, 8, 5, 32][seed % 6]
+    opts = ddf.ddf_opts_default(window=int(rng.choice([4, 64])), ops_per_lane=int(rng.choice([1, 4, 16])),
+                                rows_passes=int(rng.choice([1, 4])))
+    sptrsv_case(L, k, seed, opts, inplace=bool(seed % 3 == 0))
+
+
+# ---------------------------------------------------------------- scaled workloads
+
+def test_c2_scaled():
+    w = I.c2_stencil27_offband(nx=30)
+    spmv_case(w.A, 1)
+    sptrsv_case(w.L, 1)
+
+
+def test_c3_scaled():
+    w = I.c3_chung_lu(n=200000)
+    spmv_case(w.A, 1, plain=True)
+
+
+def test_c5_scaled():
+    w = I.c5_laplace27(nx=32, k=8)
+    spmv_case(w.A, 8)
+    sptrsv_case(w.L, 8)
