@@ -1,0 +1,248 @@
+"""Benchmark of the DDF hot path on one MI355X.
+
+One step = SpMV forward, SpMV adjoint (A^T g and dA), SpTRSV forward and SpTRSV adjoint
+(L^T lambda = g and dL) on one synthetic workload, FP64, inputs resident in HBM.  The value is
+whole-step effective HBM bandwidth: the algorithmic bytes of the four calls (values, plan
+tables, vectors read once and written once; see ddf_plan_traffic) divided by the step time.
+The plain GPU comparators (CSR-vector SpMV, FP64-atomic adjoint, one launch per level) are
+timed the same way, and the CPU oracle on a bounded sample of the same step.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2|c5|c1|c3]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--op-reps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-op", default="", help="run only this op K times (for rocprofv3)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernels_sha():
+    p = os.path.join(ROOT, "paper_2111_12243_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:12]
+
+
+def traffic_from_profiles(kernel, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, when it was taken on the
+    current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_sha = re.search(r"kernels_hip_sha:\s*(\w+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b or m_sha.group(1) != kernels_sha():
+        return None
+    return float(m_b.group(1))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
+              "of this path is a design note, not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2111_12243_amd import ddf
+    from paper_2111_12243_amd import inputs as I
+
+    if not os.path.exists(ddf.LIB_PATH):
+        from paper_2111_12243_amd import build as B
+        B.build()
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = I.workload(args.workload)
+    log(f"[bench] workload {w.name} generated in {time.time() - t0:.1f}s")
+    k = w.k
+    A, L = w.A, w.L
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    t0 = time.time()
+    pA = ddf.ddf_inspect(ddf.DDF_SPMV, A)
+    tA = time.time() - t0
+    t0 = time.time()
+    pL = ddf.ddf_inspect(ddf.DDF_SPTRSV_LOWER, L) if L is not None else None
+    tL = time.time() - t0
+    log(f"[bench] inspect: A {tA:.2f}s, L {tL:.2f}s")
+    vA, X, Gy = d(A.values), d(w.X), d(w.Gy)
+    Y = torch.empty((A.n_rows, k), dtype=torch.float64, device=dev)
+    GX = torch.empty((A.n_cols, k), dtype=torch.float64, device=dev)
+    GVA = torch.empty(A.nnz, dtype=torch.float64, device=dev)
+    if pL is not None:
+        vL, Bv, Gx = d(L.values), d(w.B), d(w.Gx)
+        Xs = torch.empty_like(Bv)
+        GB = torch.empty_like(Bv)
+        GVL = torch.empty(L.nnz, dtype=torch.float64, device=dev)
+
+    ops = {
+        "spmv": lambda: ddf.ddf_spmv_v(pA, vA, X, Y, k),
+        "spmv_adj": lambda: ddf.ddf_spmv_adjoint(pA, vA, X, Gy, GX, GVA, k),
+    }
+    plain = {
+        "spmv": lambda: ddf.ddf_plain_spmv(pA, vA, X, Y, k),
+        "spmv_adj": lambda: ddf.ddf_plain_spmv_adjoint(pA, vA, X, Gy, GX, GVA, k),
+    }
+    traffic = {"spmv": ddf.ddf_plan_traffic(pA, ddf.DDF_OP_SPMV, k),
+               "spmv_adj": ddf.ddf_plan_traffic(pA, ddf.DDF_OP_SPMV_ADJ, k)}
+    if pL is not None:
+        ops["sptrsv"] = lambda: ddf.ddf_sptrsv_v(pL, vL, Bv, Xs, k)
+        ops["sptrsv_adj"] = lambda: ddf.ddf_sptrsv_adjoint(pL, vL, Xs, Gx, GB, GVL, k)
+        plain["sptrsv"] = lambda: ddf.ddf_plain_sptrsv(pL, vL, Bv, Xs, k)
+        plain["sptrsv_adj"] = lambda: ddf.ddf_plain_sptrsv_adjoint(pL, vL, Xs, Gx, GB, GVL, k)
+        traffic["sptrsv"] = ddf.ddf_plan_traffic(pL, ddf.DDF_OP_SPTRSV, k)
+        traffic["sptrsv_adj"] = ddf.ddf_plan_traffic(pL, ddf.DDF_OP_SPTRSV_ADJ, k)
+
+    if not args.no_tune:
+        t0 = time.time()
+        ddf.ddf_autotune(pA, ddf.DDF_OP_SPMV, k, budget_ms=1500)
+        ddf.ddf_autotune(pA, ddf.DDF_OP_SPMV_ADJ, k, budget_ms=1500)
+        if pL is not None:
+            ddf.ddf_autotune(pL, ddf.DDF_OP_SPTRSV, k, budget_ms=3000)
+            ddf.ddf_autotune(pL, ddf.DDF_OP_SPTRSV_ADJ, k, budget_ms=3000)
+        torch.cuda.synchronize()
+        log(f"[bench] autotune {time.time() - t0:.1f}s")
+
+    if args.profile_op:
+        fn = ops[args.profile_op]
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        log(f"[bench] ran {args.profile_op} x{args.steps}")
+        return
+
+    def step(table):
+        for f in table.values():
+            f()
+
+    def time_steps(table, n, warm):
+        for _ in range(warm):
+            step(table)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            step(table)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    def time_op(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # timed region: K whole steps
+    ms = time_steps(ops, args.steps, args.warmup)
+    if pL is not None:
+        ddf.ddf_plan_sync_status(pL)
+    log(f"[bench] DDF step {ms:.3f} ms")
+    ms_plain = time_steps(plain, max(3, args.steps // 4), 1)
+    log(f"[bench] plain step {ms_plain:.3f} ms")
+    per_op = {}
+    for name, fn in ops.items():
+        t = time_op(fn, args.op_reps)
+        tp = time_op(plain[name], max(2, args.op_reps // 2))
+        ba, bc, fl = traffic[name]
+        per_op[name] = {"ms": round(t, 4), "gbps_alg": round(ba / t / 1e6, 1), "pct_peak": round(100 * ba / t / 1e6 / PEAK_GBPS, 2),
+                        "gbps_csr_equiv": round(bc / t / 1e6, 1), "gflops": round(fl / t / 1e6, 2),
+                        "plain_ms": round(tp, 4), "speedup_vs_plain": round(tp / t, 3)}
+        log(f"[bench] {name}: {per_op[name]}")
+
+    # parity spot check against the oracle (outside the timed region)
+    import oracle as O
+    parity = {}
+    step(ops)
+    torch.cuda.synchronize()
+    yref = O.spmv(A, w.X)
+    parity["spmv_max_abs_err"] = float(np.max(np.abs(Y.cpu().numpy() - yref)))
+    if pL is not None:
+        xref = O.sptrsv(L, w.B)
+        parity["sptrsv_rel_err"] = float(np.max(np.abs(Xs.cpu().numpy() - xref)) / np.max(np.abs(xref)))
+
+    bytes_step = sum(t[0] for t in traffic.values())
+    value = bytes_step / (ms / 1e3) / 1e9
+    value_plain = bytes_step / (ms_plain / 1e3) / 1e9
+    dom = max(per_op, key=lambda n: per_op[n]["ms"])
+    kname = {"spmv": "k_spmv", "spmv_adj": "k_spmv", "sptrsv": "k_solve", "sptrsv_adj": "k_solve"}[dom]
+    ach = traffic[dom][0] / (per_op[dom]["ms"] / 1e3) / 1e9
+    hbm = traffic_from_profiles(f"{kname}_{dom}", args.workload)
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBPS, "unit": "GB/s",
+                "frac": round(ach / PEAK_GBPS, 4), "traffic": hbm, "kernel": f"{kname} ({dom})"}
+
+    cpu = None
+    if not args.no_cpu:
+        # the oracle as it stands, single-threaded, on whole steps until ~cpu_seconds elapse
+        t0 = time.time()
+        nsteps = 0
+        while True:
+            O.spmv(A, w.X)
+            O.spmv_adj(A, w.X, w.Gy)
+            if L is not None:
+                xr = O.sptrsv(L, w.B)
+                O.sptrsv_adj(L, xr, w.Gx)
+            nsteps += 1
+            if time.time() - t0 > args.cpu_seconds:
+                break
+        cpu_s = (time.time() - t0) / nsteps
+        cpu = {"value": round(bytes_step / cpu_s / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{nsteps} whole steps of {w.name} (SpMV fwd+adj, SpTRSV fwd+adj), "
+                         f"{cpu_s * 1e3:.1f} ms/step, single-threaded plain C loops"}
+        log(f"[bench] cpu oracle {cpu_s * 1e3:.1f} ms/step")
+
+    info_L = ddf.ddf_plan_info(pL) if pL is not None else {}
+    info_A = ddf.ddf_plan_info(pA)
+    out = {
+        "metric": "SpMV/SpTRSV fwd+adjoint effective HBM GB/s and % of peak vs plain, FP64",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": A.n_rows, "nnz_A": A.nnz, "nnz_L": L.nnz if L is not None else 0,
+                   "levels": info_L.get("n_parts", 0), "nrhs": k,
+                   "codelets_A_by_type": info_A["codelets_by_type"], "ops_A_by_type": info_A["ops_by_type"],
+                   "codelets_L_by_type": info_L.get("codelets_by_type"),
+                   "inspect_s": {"A": round(tA, 3), "L": round(tL, 3)}},
+        "pct_of_peak": round(100 * value / PEAK_GBPS, 2),
+        "plain": {"ms_per_step": round(ms_plain, 4), "value": round(value_plain, 2),
+                  "speedup_vs_plain": round(ms_plain / ms, 3)},
+        "per_op": per_op, "bytes_alg_per_step": bytes_step, "parity": parity,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

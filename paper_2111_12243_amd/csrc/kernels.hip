@@ -164,30 +164,38 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmv(SpmvArgs a) {
     }
     const DCod c = load_cod(a.cods + tk.cod);
     const int mode = xmode(c.flags);
-    for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
-        const RowInfo ri = row_info(c, a.aux, i0);
+    // passes are wave-uniform; lanes whose row is past the task's end stay converged for the
+    // shuffles and contribute zeros
+    for (int base = tk.i0b; base < tk.i0e; base += R) {
+        const int i0 = base + slot;
+        const bool active = i0 < tk.i0e;
+        RowInfo ri{0, 0, 0};
+        if (active) ri = row_info(c, a.aux, i0);
         for (int r0 = 0; r0 < k; r0 += KT) {
             double acc[KT];
 #pragma unroll
             for (int r = 0; r < KT; r++) acc[r] = 0.0;
             const bool full = r0 + KT <= k;
-            walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
-                const double v = VPERM ? a.vals[a.perm[e]] : a.vals[e];
-                const double *__restrict__ xr = a.x + (int64_t)col * k + r0;
-                if (full) {
+            if (active)
+                walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
+                    const double v = VPERM ? a.vals[a.perm[e]] : a.vals[e];
+                    const double *__restrict__ xr = a.x + (int64_t)col * k + r0;
+                    if (full) {
 #pragma unroll
-                    for (int r = 0; r < KT; r++) acc[r] += v * xr[r];
-                } else {
+                        for (int r = 0; r < KT; r++) acc[r] += v * xr[r];
+                    } else {
 #pragma unroll
-                    for (int r = 0; r < KT; r++)
-                        if (r0 + r < k) acc[r] += v * xr[r];
-                }
-            });
+                        for (int r = 0; r < KT; r++)
+                            if (r0 + r < k) acc[r] += v * xr[r];
+                    }
+                });
             group_sum<KT>(acc, G);
-            double *__restrict__ yr = a.y + (int64_t)ri.row * k + r0;
+            if (active) {
+                double *__restrict__ yr = a.y + (int64_t)ri.row * k + r0;
 #pragma unroll
-            for (int r = 0; r < KT; r++)
-                if ((r & (G - 1)) == g && r0 + r < k) yr[r] = acc[r];
+                for (int r = 0; r < KT; r++)
+                    if ((r & (G - 1)) == g && r0 + r < k) yr[r] = acc[r];
+            }
         }
     }
 }
@@ -200,25 +208,31 @@ template <int KT, bool ADJ>
 __global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
     const int lane = threadIdx.x % WAVE;
     unsigned *__restrict__ done = a.ctr + 2;
+    // Every step below is executed by all 64 lanes with wave-uniform results (no branch on
+    // the lane id around the ticket, the waits or the counters): lane 0 contributes the
+    // increments, readfirstlane broadcasts lane 0's result.
+    const unsigned one = lane == 0 ? 1u : 0u;
     for (;;) {
-        int t = 0;
-        if (lane == 0)
-            t = (int)__hip_atomic_fetch_add(a.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __shfl(t, 0, WAVE);
+        const unsigned tv = __hip_atomic_fetch_add(a.ctr, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int t = __builtin_amdgcn_readfirstlane((int)tv);
         if (t >= a.ntasks) break;
         const Task tk = a.tasks[t];
         const int phase = (tk.meta >> 8) & 1;
         const DCod c = load_cod((phase ? a.cods2 : a.cods) + tk.cod);
         const MatInfo mi = a.mats[c.mat];
         const int need = a.wait[t];
-        if (lane == 0 && need > 0) {
+        if (need > 0) {
             // bounded wait: past the spin limit, or once another wave has tripped the
             // error flag, stop waiting (the results are then reported as invalid)
             int64_t spins = 0;
-            while ((int)cload_u(done + c.mat) < need) {
+            for (;;) {
+                const int d = __builtin_amdgcn_readfirstlane((int)cload_u(done + c.mat));
+                if (d >= need) break;
                 __builtin_amdgcn_s_sleep(1);
                 ++spins;
-                if (spins > a.spin_limit || ((spins & 255) == 0 && cload_u(a.ctr + 1) != 0u)) {
+                bool trip = spins > a.spin_limit;
+                if ((spins & 255) == 0) trip = trip || __builtin_amdgcn_readfirstlane((int)cload_u(a.ctr + 1)) != 0;
+                if (trip) {
                     __hip_atomic_store(a.ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
@@ -255,32 +269,42 @@ __global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
             const int32_t *__restrict__ perm = ADJ ? a.perm + mi.val_base : nullptr;
             const double *__restrict__ b = a.b + mi.vec_base;
             double *x = a.x + mi.vec_base;
-            for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
-                const RowInfo ri = row_info(c, a.aux, i0);
-                const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
-                const double diag = ADJ ? vals[perm[dpos]] : vals[dpos];
+            for (int base = tk.i0b; base < tk.i0e; base += R) {
+                const int i0 = base + slot;
+                const bool active = i0 < tk.i0e;
+                RowInfo ri{0, 0, 0};
+                double diag = 1.0;
+                if (active) {
+                    ri = row_info(c, a.aux, i0);
+                    const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
+                    diag = ADJ ? vals[perm[dpos]] : vals[dpos];
+                }
                 const int64_t rb = (int64_t)ri.row * k;
                 for (int r0 = 0; r0 < k; r0 += KT) {
                     double acc[KT];
 #pragma unroll
                     for (int r = 0; r < KT; r++) acc[r] = 0.0;
-                    walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
-                        const double v = ADJ ? vals[perm[e]] : vals[e];
-                        const double *xr = x + (int64_t)col * k + r0;
+                    if (active)
+                        walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
+                            const double v = ADJ ? vals[perm[e]] : vals[e];
+                            const double *xr = x + (int64_t)col * k + r0;
+#pragma unroll
+                            for (int r = 0; r < KT; r++)
+                                if (r0 + r < k) acc[r] += v * cload(xr + r);
+                        });
+                    group_sum<KT>(acc, G);
+                    if (active) {
 #pragma unroll
                         for (int r = 0; r < KT; r++)
-                            if (r0 + r < k) acc[r] += v * cload(xr + r);
-                    });
-                    group_sum<KT>(acc, G);
-#pragma unroll
-                    for (int r = 0; r < KT; r++)
-                        if ((r & (G - 1)) == g && r0 + r < k) cstore(x + rb + r0 + r, (b[rb + r0 + r] - acc[r]) / diag);
+                            if ((r & (G - 1)) == g && r0 + r < k)
+                                cstore(x + rb + r0 + r, (b[rb + r0 + r] - acc[r]) / diag);
+                    }
                 }
             }
         }
+        // this wave's solution stores are complete (device-scope) before the counter moves
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        if (lane == 0)
-            __hip_atomic_fetch_add(done + c.mat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(done + c.mat, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -302,9 +326,9 @@ __global__ __launch_bounds__(WAVE *WPB) void k_csr_spmv(PlainArgs a) {
     const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
     const int64_t row = ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
     const int g = lane & (G - 1);
-    if (row >= a.n) return;
+    const bool active = row < a.n;
     const int k = a.k;
-    const int b = a.rp[row], e1 = a.rp[row + 1];
+    const int b = active ? a.rp[row] : 0, e1 = active ? a.rp[row + 1] : 0;
     for (int r0 = 0; r0 < k; r0 += KT) {
         double acc[KT];
 #pragma unroll
@@ -317,9 +341,11 @@ __global__ __launch_bounds__(WAVE *WPB) void k_csr_spmv(PlainArgs a) {
                 if (r0 + r < k) acc[r] += v * xr[r];
         }
         group_sum<KT>(acc, G);
+        if (active) {
 #pragma unroll
-        for (int r = 0; r < KT; r++)
-            if ((r & (G - 1)) == g && r0 + r < k) a.y[row * k + r0 + r] = acc[r];
+            for (int r = 0; r < KT; r++)
+                if ((r & (G - 1)) == g && r0 + r < k) a.y[row * k + r0 + r] = acc[r];
+        }
     }
 }
 
@@ -331,18 +357,23 @@ __global__ __launch_bounds__(WAVE *WPB) void k_csr_level(PlainArgs a) {
     const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
     const int64_t p = a.lo + ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
     const int g = lane & (G - 1);
-    if (p >= a.hi) return;
+    const bool active = p < a.hi;
     const int k = a.k;
-    const int64_t row = a.rows[p];
-    int b = a.rp[row], e1 = a.rp[row + 1], d;
-    if (a.upper) {
-        d = b;
-        b += 1;
-    } else {
-        d = e1 - 1;
-        e1 -= 1;
+    const int64_t row = active ? a.rows[p] : 0;
+    int b = 0, e1 = 0, d = 0;
+    double diag = 1.0;
+    if (active) {
+        b = a.rp[row];
+        e1 = a.rp[row + 1];
+        if (a.upper) {
+            d = b;
+            b += 1;
+        } else {
+            d = e1 - 1;
+            e1 -= 1;
+        }
+        diag = a.upper ? a.vals[a.perm[d]] : a.vals[d];
     }
-    const double diag = a.upper ? a.vals[a.perm[d]] : a.vals[d];
     for (int r0 = 0; r0 < k; r0 += KT) {
         double acc[KT];
 #pragma unroll
@@ -355,10 +386,12 @@ __global__ __launch_bounds__(WAVE *WPB) void k_csr_level(PlainArgs a) {
                 if (r0 + r < k) acc[r] += v * xr[r];
         }
         group_sum<KT>(acc, G);
+        if (active) {
 #pragma unroll
-        for (int r = 0; r < KT; r++)
-            if ((r & (G - 1)) == g && r0 + r < k)
-                a.y[row * k + r0 + r] = (a.x[row * k + r0 + r] - acc[r]) / diag;
+            for (int r = 0; r < KT; r++)
+                if ((r & (G - 1)) == g && r0 + r < k)
+                    a.y[row * k + r0 + r] = (a.x[row * k + r0 + r] - acc[r]) / diag;
+        }
     }
 }
 
