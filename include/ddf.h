@@ -232,6 +232,22 @@ ddf_status ddf_plan_export(ddf_plan_t plan, int32_t which, int32_t mat, ddf_plan
 ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *bytes_alg,
                             int64_t *bytes_csr, int64_t *flops);
 
+/* Host copies of the tables the kernels read (also built for host-only plans), for
+ * inspection and testing.  which: 0 forward pass, 1 adjoint pass, 2 per-matrix batch
+ * schedule.  Valid until the next ddf_autotune or ddf_plan_destroy.
+ *   cods   [n_cods][16]  flags, m, nn, row0, row_step, op0, op_step, col0, sigma0, sigma1,
+ *                        rows_off, ops_off, cnt_off, xt_off, xp_off, mat
+ *   tasks  [n_tasks][4]  codelet, first row, end row, meta (log2 lanes per row | phase << 8 |
+ *                        look-ahead eligible << 9)
+ *   groups [n_groups][8] type (0 wide, 1 thin), first task, end task, tasks to wait for,
+ *                        matrix, level-table offset, levels, 0
+ *   lvl    [lvl_len]     task boundaries of the levels of thin groups */
+typedef struct {
+    const int32_t *cods, *aux, *tasks, *groups, *lvl;
+    int64_t n_cods, aux_len, n_tasks, n_groups, lvl_len;
+} ddf_device_tables_t;
+ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
+
 /* Synchronises `stream`, then reads and clears the plan's device error flag. */
 ddf_status ddf_plan_sync_status(ddf_plan_t plan, ddf_stream_t stream);
 /* Test hook: spin limit of the persistent kernels' level waits (0 = default). */

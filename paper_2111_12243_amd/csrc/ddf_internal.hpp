@@ -71,6 +71,9 @@ struct SchedParams {
     int32_t ops_per_lane = 4;
     int32_t passes = 2;
     int32_t remap = 1;
+    int32_t blocks = 0;      // solve: persistent grid (0 = one per CU)
+    int32_t thin_tasks = 16; // solve: levels with at most this many tasks run in THIN groups
+    int32_t backoff = 16;    // solve: longest sleep between polls (units of 64 cycles)
 };
 
 // Device-resident tables of one plan pass (forward or adjoint).
@@ -78,15 +81,16 @@ struct DevTables {
     std::vector<DCod> cods;
     std::vector<int32_t> aux;          // canonical aux followed by device supplements
     std::vector<Task> tasks;
-    std::vector<int32_t> task_wait;    // solve kernels: tasks of the same matrix to wait for
-    int64_t supplement = 0;            // device-only aux entries
+    std::vector<int32_t> groups;       // solve: 8 int32 per group (see kernels.hpp Group)
+    std::vector<int32_t> lvl;          // solve: level boundaries of THIN groups
     DCod *d_cods = nullptr;
     int32_t *d_aux = nullptr;
     Task *d_tasks = nullptr;
-    int32_t *d_wait = nullptr;
+    int32_t *d_groups = nullptr;
+    int32_t *d_lvl = nullptr;
     int64_t bytes() const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
-               (int64_t)tasks.size() * sizeof(Task) + (int64_t)task_wait.size() * 4;
+               (int64_t)tasks.size() * sizeof(Task) + (int64_t)groups.size() * 4 + (int64_t)lvl.size() * 4;
     }
 };
 

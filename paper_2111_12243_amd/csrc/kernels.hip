@@ -203,108 +203,264 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmv(SpmvArgs a) {
 // ------------------------------------------------------------------------------------------
 // Persistent level-ordered solve (forward L x = b, or the adjoint U lam = g with U = L^T
 // read through perm, followed by the GV pass).
+//
+// Blocks take groups in ticket order.  A WIDE group is a slice of one level's tasks: its
+// waves exchange solution values with the rest of the device through device-scope (sc1)
+// loads and stores.  A THIN group is a run of consecutive small levels of one matrix, all
+// run by this block: levels are separated by block barriers, solution values stay in the
+// XCD's caches (one agent-scope acquire on entry, one release on exit), and each wave
+// loads the next level's rows, values and columns (none of which depend on the solution)
+// while it computes the current level.
 // ------------------------------------------------------------------------------------------
+constexpr int PE = LOOKAHEAD;
+
+template <bool COH>
+__device__ __forceinline__ double xload(const double *p) {
+    if constexpr (COH) return cload(p);
+    else return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void xstore(double *p, double v) {
+    if constexpr (COH) cstore(p, v);
+    else *p = v;
+}
+
+// every row of one task, all passes, all right-hand-side tiles
+template <int KT, bool ADJ, bool COH>
+__device__ void solve_task(const SolveArgs &a, int t, int lane) {
+    const Task tk = a.tasks[t];
+    const int phase = (tk.meta >> 8) & 1;
+    const DCod c = load_cod((phase ? a.cods2 : a.cods) + tk.cod);
+    const MatInfo mi = a.mats[c.mat];
+    const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
+    const int slot = lane >> lg, g = lane & (G - 1);
+    const int k = a.k_override > 0 ? a.k_override : mi.k;
+    const double *__restrict__ vals = a.vals + mi.val_base;
+    const int mode = xmode(c.flags);
+    if (ADJ && phase) {
+        // GV over L's forward plan: gv[e] = -sum_r lam[row, r] x[col, r], diagonal included
+        const double *lam = a.x + mi.vec_base;
+        const double *__restrict__ xf = a.xf + mi.vec_base;
+        double *__restrict__ gv = a.gv + mi.val_base;
+        for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
+            const RowInfo ri = row_info(c, a.aux2, i0);
+            const int64_t rb = (int64_t)ri.row * k;
+            walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
+                const double *__restrict__ xr = xf + (int64_t)col * k;
+                double s = 0.0;
+                for (int r = 0; r < k; r++) s += xload<COH>(lam + rb + r) * xr[r];
+                gv[e] = -s;
+            });
+            if (g == 0) {
+                double s = 0.0;
+                for (int r = 0; r < k; r++) s += xload<COH>(lam + rb + r) * xf[rb + r];
+                gv[ri.opst + ri.nops] = -s;
+            }
+        }
+        return;
+    }
+    const int32_t *__restrict__ perm = ADJ ? a.perm + mi.val_base : nullptr;
+    const double *__restrict__ b = a.b + mi.vec_base;
+    double *x = a.x + mi.vec_base;
+    for (int base = tk.i0b; base < tk.i0e; base += R) {
+        const int i0 = base + slot;
+        const bool active = i0 < tk.i0e;
+        RowInfo ri{0, 0, 0};
+        double diag = 1.0;
+        if (active) {
+            ri = row_info(c, a.aux, i0);
+            const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
+            diag = ADJ ? vals[perm[dpos]] : vals[dpos];
+        }
+        const int64_t rb = (int64_t)ri.row * k;
+        for (int r0 = 0; r0 < k; r0 += KT) {
+            double acc[KT];
+#pragma unroll
+            for (int r = 0; r < KT; r++) acc[r] = 0.0;
+            if (active)
+                walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
+                    const double v = ADJ ? vals[perm[e]] : vals[e];
+                    const double *xr = x + (int64_t)col * k + r0;
+#pragma unroll
+                    for (int r = 0; r < KT; r++)
+                        if (r0 + r < k) acc[r] += v * xload<COH>(xr + r);
+                });
+            group_sum<KT>(acc, G);
+            if (active) {
+#pragma unroll
+                for (int r = 0; r < KT; r++)
+                    if ((r & (G - 1)) == g && r0 + r < k) xstore<COH>(x + rb + r0 + r, (b[rb + r0 + r] - acc[r]) / diag);
+            }
+        }
+    }
+}
+
+// What a wave loaded ahead for its task of the next thin level.
+struct Pre {
+    double v[PE];
+    int col[PE];
+    double diag;
+    int64_t vec_base;
+    int task, row, nops, lg, k;
+    bool active, fast;
+};
+
+__device__ __forceinline__ int col_at(int mode, const DCod &c, const int32_t *__restrict__ aux, int i0,
+                                      const RowInfo &ri, int i1) {
+    if (mode == XM_STRIDED) return c.col0 + i0 * c.sigma0 + i1 * c.sigma1;
+    if (mode == XM_SHARED) return c.col0 + i0 * c.sigma0 + aux[c.xt_off + i1];
+    int off;
+    if (c.flags & FRECT)
+        off = i0 * c.nn;
+    else if (c.flags & DCONTIG)
+        off = ri.opst - c.op0;
+    else
+        off = aux[c.xp_off + i0];
+    return aux[c.xt_off + off + i1];
+}
+
+template <bool ADJ>
+__device__ __forceinline__ void pre_load(const SolveArgs &a, int t, int lane, Pre &p) {
+    p.task = t;
+    p.active = false;
+    p.fast = false;
+    if (t < 0) return;
+    const Task tk = a.tasks[t];
+    p.fast = (tk.meta >> 9) & 1;
+    if (!p.fast) return;
+    const DCod c = load_cod(a.cods + tk.cod);
+    const MatInfo mi = a.mats[c.mat];
+    p.lg = tk.meta & 7;
+    p.k = a.k_override > 0 ? a.k_override : mi.k;
+    p.vec_base = mi.vec_base;
+    const int G = 1 << p.lg, g = lane & (G - 1);
+    const int i0 = tk.i0b + (lane >> p.lg);
+    p.active = i0 < tk.i0e;
+    if (!p.active) return;
+    const double *__restrict__ vals = a.vals + mi.val_base;
+    const int32_t *__restrict__ perm = ADJ ? a.perm + mi.val_base : nullptr;
+    const RowInfo ri = row_info(c, a.aux, i0);
+    const int mode = xmode(c.flags);
+    p.row = ri.row;
+    p.nops = ri.nops;
+    const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
+    p.diag = ADJ ? vals[perm[dpos]] : vals[dpos];
+#pragma unroll
+    for (int j = 0; j < PE; j++) {
+        const int i1 = g + j * G;
+        p.v[j] = 0.0;
+        p.col[j] = 0;
+        if (i1 < ri.nops) {
+            const int e = ri.opst + i1;
+            p.v[j] = ADJ ? vals[perm[e]] : vals[e];
+            p.col[j] = col_at(mode, c, a.aux, i0, ri, i1);
+        }
+    }
+}
+
 template <int KT, bool ADJ>
-__global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
+__device__ __forceinline__ void pre_compute(const SolveArgs &a, const Pre &p, int lane) {
+    if (p.task < 0) return;
+    if (!p.fast) {
+        solve_task<KT, ADJ, false>(a, p.task, lane);
+        return;
+    }
+    const int G = 1 << p.lg, g = lane & (G - 1);
+    const int k = p.k;
+    const double *__restrict__ b = a.b + p.vec_base;
+    double *x = a.x + p.vec_base;
+    const int64_t rb = (int64_t)p.row * k;
+    for (int r0 = 0; r0 < k; r0 += KT) {
+        double acc[KT];
+#pragma unroll
+        for (int r = 0; r < KT; r++) acc[r] = 0.0;
+        if (p.active) {
+#pragma unroll
+            for (int j = 0; j < PE; j++) {
+                if (g + j * G < p.nops) {
+                    const double *xr = x + (int64_t)p.col[j] * k + r0;
+#pragma unroll
+                    for (int r = 0; r < KT; r++)
+                        if (r0 + r < k) acc[r] += p.v[j] * xr[r];
+                }
+            }
+        }
+        group_sum<KT>(acc, G);
+        if (p.active) {
+#pragma unroll
+            for (int r = 0; r < KT; r++)
+                if ((r & (G - 1)) == g && r0 + r < k) x[rb + r0 + r] = (b[rb + r0 + r] - acc[r]) / p.diag;
+        }
+    }
+}
+
+template <int KT, bool ADJ>
+__global__ __launch_bounds__(WAVE *SWPB) void k_solve(SolveArgs a) {
+    __shared__ int s_gi;
     const int lane = threadIdx.x % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     unsigned *__restrict__ done = a.ctr + 2;
-    // Every step below is executed by all 64 lanes with wave-uniform results (no branch on
-    // the lane id around the ticket, the waits or the counters): lane 0 contributes the
-    // increments, readfirstlane broadcasts lane 0's result.
+    // lane 0 carries the increments; every lane issues the atomics so that no branch
+    // depends on the lane id (results are broadcast with readfirstlane)
     const unsigned one = lane == 0 ? 1u : 0u;
     for (;;) {
-        const unsigned tv = __hip_atomic_fetch_add(a.ctr, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int t = __builtin_amdgcn_readfirstlane((int)tv);
-        if (t >= a.ntasks) break;
-        const Task tk = a.tasks[t];
-        const int phase = (tk.meta >> 8) & 1;
-        const DCod c = load_cod((phase ? a.cods2 : a.cods) + tk.cod);
-        const MatInfo mi = a.mats[c.mat];
-        const int need = a.wait[t];
-        if (need > 0) {
-            // bounded wait: past the spin limit, or once another wave has tripped the
-            // error flag, stop waiting (the results are then reported as invalid)
+        if (wave == 0) s_gi = __builtin_amdgcn_readfirstlane(
+                           (int)__hip_atomic_fetch_add(a.ctr, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        __syncthreads();
+        const int gi = __builtin_amdgcn_readfirstlane(s_gi);
+        __syncthreads();
+        if (gi >= a.ngroups) break;
+        const Group gr = a.groups[gi];
+        if (wave == 0 && gr.need > 0) {
+            // bounded wait with backoff; past the spin limit, or once another block has
+            // tripped the error flag, stop waiting (the results are then reported invalid)
             int64_t spins = 0;
+            int back = 1;
             for (;;) {
-                const int d = __builtin_amdgcn_readfirstlane((int)cload_u(done + c.mat));
-                if (d >= need) break;
-                __builtin_amdgcn_s_sleep(1);
-                ++spins;
+                const int d = __builtin_amdgcn_readfirstlane((int)cload_u(done + gr.mat));
+                if (d >= gr.need) break;
+                for (int z = 0; z < back; z++) __builtin_amdgcn_s_sleep(1);
+                if (back < a.backoff_max) back <<= 1;
+                spins += back;
                 bool trip = spins > a.spin_limit;
-                if ((spins & 255) == 0) trip = trip || __builtin_amdgcn_readfirstlane((int)cload_u(a.ctr + 1)) != 0;
+                if ((spins & 1023) < back)
+                    trip = trip || __builtin_amdgcn_readfirstlane((int)cload_u(a.ctr + 1)) != 0;
                 if (trip) {
                     __hip_atomic_store(a.ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
         }
-        asm volatile("" ::: "memory");
-        const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
-        const int slot = lane >> lg, g = lane & (G - 1);
-        const int k = a.k_override > 0 ? a.k_override : mi.k;
-        const double *__restrict__ vals = a.vals + mi.val_base;
-        if (ADJ && phase) {
-            // GV over L's forward plan: gv[e] = -sum_r lam[row, r] x[col, r], diagonal included
-            const int mode = xmode(c.flags);
-            const double *lam = a.x + mi.vec_base;
-            const double *__restrict__ xf = a.xf + mi.vec_base;
-            double *__restrict__ gv = a.gv + mi.val_base;
-            for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
-                const RowInfo ri = row_info(c, a.aux2, i0);
-                const int64_t rb = (int64_t)ri.row * k;
-                walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
-                    const double *__restrict__ xr = xf + (int64_t)col * k;
-                    double s = 0.0;
-                    for (int r = 0; r < k; r++) s += cload(lam + rb + r) * xr[r];
-                    gv[e] = -s;
-                });
-                if (g == 0) {
-                    double s = 0.0;
-                    for (int r = 0; r < k; r++) s += cload(lam + rb + r) * xf[rb + r];
-                    gv[ri.opst + ri.nops] = -s;
+        __syncthreads();
+        if (gr.type == GROUP_THIN) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            Pre cur, nxt;
+            int lb = a.lvl[gr.lv_off], le = a.lvl[gr.lv_off + 1];
+            pre_load<ADJ>(a, lb + wave < le ? lb + wave : -1, lane, cur);
+            for (int l = 0; l < gr.nlv; l++) {
+                int nb = 0, ne = 0;
+                if (l + 1 < gr.nlv) {
+                    nb = a.lvl[gr.lv_off + l + 1];
+                    ne = a.lvl[gr.lv_off + l + 2];
                 }
+                pre_load<ADJ>(a, nb + wave < ne ? nb + wave : -1, lane, nxt);
+                pre_compute<KT, ADJ>(a, cur, lane);
+                for (int t = lb + wave + SWPB; t < le; t += SWPB) solve_task<KT, ADJ, false>(a, t, lane);
+                __syncthreads();
+                cur = nxt;
+                lb = nb;
+                le = ne;
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         } else {
-            const int mode = xmode(c.flags);
-            const int32_t *__restrict__ perm = ADJ ? a.perm + mi.val_base : nullptr;
-            const double *__restrict__ b = a.b + mi.vec_base;
-            double *x = a.x + mi.vec_base;
-            for (int base = tk.i0b; base < tk.i0e; base += R) {
-                const int i0 = base + slot;
-                const bool active = i0 < tk.i0e;
-                RowInfo ri{0, 0, 0};
-                double diag = 1.0;
-                if (active) {
-                    ri = row_info(c, a.aux, i0);
-                    const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
-                    diag = ADJ ? vals[perm[dpos]] : vals[dpos];
-                }
-                const int64_t rb = (int64_t)ri.row * k;
-                for (int r0 = 0; r0 < k; r0 += KT) {
-                    double acc[KT];
-#pragma unroll
-                    for (int r = 0; r < KT; r++) acc[r] = 0.0;
-                    if (active)
-                        walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
-                            const double v = ADJ ? vals[perm[e]] : vals[e];
-                            const double *xr = x + (int64_t)col * k + r0;
-#pragma unroll
-                            for (int r = 0; r < KT; r++)
-                                if (r0 + r < k) acc[r] += v * cload(xr + r);
-                        });
-                    group_sum<KT>(acc, G);
-                    if (active) {
-#pragma unroll
-                        for (int r = 0; r < KT; r++)
-                            if ((r & (G - 1)) == g && r0 + r < k)
-                                cstore(x + rb + r0 + r, (b[rb + r0 + r] - acc[r]) / diag);
-                    }
-                }
-            }
+            for (int t = gr.t0 + wave; t < gr.t1; t += SWPB) solve_task<KT, ADJ, true>(a, t, lane);
+            // this wave's device-scope stores are complete before the block signals
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         }
-        // this wave's solution stores are complete (device-scope) before the counter moves
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __hip_atomic_fetch_add(done + c.mat, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (wave == 0)
+            __hip_atomic_fetch_add(done + gr.mat, lane == 0 ? (unsigned)(gr.t1 - gr.t0) : 0u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -439,11 +595,12 @@ void launch_spmv_t(const SpmvArgs &a, int nblocks, hipStream_t s) {
 }
 
 int g_solve_blocks = 0; // resident blocks of the persistent kernel on the whole device
+int g_num_cu = 0;
 
-int solve_grid(int ntasks) {
-    int need = (ntasks + WPB - 1) / WPB;
-    int cap = g_solve_blocks > 0 ? g_solve_blocks : 1024;
-    return need < cap ? (need > 0 ? need : 1) : cap;
+int solve_grid(int ngroups, int want) {
+    int cap = g_solve_blocks > 0 ? g_solve_blocks : 256;
+    if (want > 0 && want < cap) cap = want;
+    return ngroups < cap ? (ngroups > 0 ? ngroups : 1) : cap;
 }
 
 } // namespace
@@ -455,9 +612,10 @@ hipError_t init_device_info() {
     int dev = 0, ncu = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<8, true>, WAVE * WPB, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<8, true>, WAVE * SWPB, 0);
     if (e != hipSuccess) return e;
-    g_solve_blocks = (nb > 0 ? nb : 1) * (ncu > 0 ? ncu : 1);
+    g_num_cu = ncu > 0 ? ncu : 1;
+    g_solve_blocks = (nb > 0 ? nb : 1) * g_num_cu;
     return hipSuccess;
 }
 
@@ -490,12 +648,14 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, hipStream_t s) {
-    if (a.ntasks == 0) return hipSuccess;
+int num_cu() { return g_num_cu > 0 ? g_num_cu : 256; }
+
+hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s) {
+    if (a.ngroups == 0) return hipSuccess;
     int nb;
 #define DDF_SOLVE_CASE(K, A)                                                                        \
-    nb = solve_grid(a.ntasks);                                                                      \
-    hipLaunchKernelGGL((k_solve<K, A>), dim3(nb), dim3(WAVE * WPB), 0, s, a);                       \
+    nb = solve_grid(a.ngroups, blocks);                                                             \
+    hipLaunchKernelGGL((k_solve<K, A>), dim3(nb), dim3(WAVE * SWPB), 0, s, a);                      \
     break;
     switch (kt * 2 + (adj ? 1 : 0)) {
     case 2: DDF_SOLVE_CASE(1, false)

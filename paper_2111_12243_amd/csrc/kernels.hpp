@@ -26,14 +26,28 @@ struct SpmvArgs {
     double *gv;
 };
 
+constexpr int SWPB = 16;     // waves per block of the persistent solve (1024 threads)
+constexpr int LOOKAHEAD = 4; // elements per lane a thin-range wave loads ahead
+enum : int32_t { GROUP_WIDE = 0, GROUP_THIN = 1 };
+enum : int32_t { TASK_FAST = 1 << 9 }; // thin-range task whose rows fit the look-ahead registers
+
+// A block's unit of work in the persistent solve: tasks [t0, t1) of matrix `mat`, started
+// once `need` tasks of that matrix are done.  THIN groups span nlv levels whose task
+// boundaries are lvl[lv_off .. lv_off + nlv].
+struct Group {
+    int32_t type, t0, t1, need, mat, lv_off, nlv, pad;
+};
+
 struct SolveArgs {
     const DCod *cods;  // phase 0: the solve's plan
     const int32_t *aux;
     const DCod *cods2; // phase 1 (adjoint): L's forward plan for the GV pass
     const int32_t *aux2;
     const Task *tasks;
-    const int32_t *wait;
-    int32_t ntasks;
+    const Group *groups;
+    int32_t ngroups;
+    const int32_t *lvl;
+    int32_t backoff_max;
     const MatInfo *mats;
     const double *vals;
     const int32_t *perm; // adjoint: U's entries -> L's values (per matrix, local)
@@ -65,7 +79,8 @@ enum PlainKind { PLAIN_SPMV, PLAIN_LEVEL, PLAIN_SPMV_ADJ, PLAIN_GV };
 int kt_for(int k);
 hipError_t init_device_info();
 hipError_t launch_spmv(const SpmvArgs &a, bool vperm, int kt, hipStream_t s);
-hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, hipStream_t s);
+hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s);
+int num_cu();
 hipError_t launch_reset(unsigned *ctr, int n, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);

@@ -40,8 +40,8 @@ struct ddf_plan_s {
     int64_t n_rows = 0, n_cols = 0, nnz = 0, vec_total = 0;
     SchedParams sp_f, sp_a;
     DevTables F, T, Fpm;
-    std::vector<int64_t> pm_task_ptr; // per-matrix ranges of Fpm.tasks
-    int64_t n_solve_tasks_adj = 0;    // adjoint: tasks before the GV pass
+    std::vector<int64_t> pm_group_ptr; // per-matrix ranges of Fpm.groups
+    int64_t n_solve_groups_adj = 0;    // adjoint: groups before the GV pass
     int64_t n_gx_tasks = 0;           // SpMV adjoint: tasks before the GV pass
     double *d_vals = nullptr;
     int32_t *d_perm = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_rpT = nullptr, *d_ciT = nullptr;
@@ -104,10 +104,17 @@ int xmode_host(int fl) {
     return (fl & FRUNS) ? 4 : 3;
 }
 
-// Canonical tables of one matrix -> device records + aux (+ device-only supplements).
-void pack(const Canon &c, int kind, int mat, const int32_t *rp, DevTables &D) {
-    const int64_t base = (int64_t)D.aux.size();
-    D.aux.insert(D.aux.end(), c.aux.begin(), c.aux.end());
+// Full column tables stored as runs stay runs on the device only when runs are long on
+// average; shorter ones are decoded faster from a plain column list.
+constexpr double RUNS_MIN_AVG = 3.0;
+
+// Device tables of one matrix's codelets: per codelet, exactly the tables its kernel path
+// reads (the canonical tables' information, re-encoded for the GPU):
+//   ROWS (!S0), OPSTART (!S1, or when S1 holds only because rows have no operations and a
+//   solve still needs each row's diagonal position), COUNTS (!RECT), and the column table:
+//   shared offsets (SEP; runs expanded), full runs with a per-row run index, or full
+//   columns with a per-row offset when rows are neither rectangular nor contiguous.
+void pack(const Canon &c, const Pattern &P, int mat, DevTables &D) {
     const int64_t ncod = c.header[7];
     const size_t first = D.cods.size();
     D.cods.resize(first + ncod);
@@ -117,7 +124,6 @@ void pack(const Canon &c, int kind, int mat, const int32_t *rp, DevTables &D) {
         const int32_t fl = (int32_t)r[C_FLAGS];
         const int32_t m = (int32_t)r[C_M];
         DCod d;
-        d.flags = fl;
         d.m = m;
         d.nn = (int32_t)r[C_NN];
         d.row0 = (int32_t)r[C_ROW0];
@@ -127,75 +133,92 @@ void pack(const Canon &c, int kind, int mat, const int32_t *rp, DevTables &D) {
         d.col0 = (int32_t)r[C_COL0];
         d.sigma0 = (int32_t)r[C_SIG0];
         d.sigma1 = (int32_t)r[C_SIG1];
-        int64_t p = base + r[C_AUXOFF];
-        d.rows_off = -1;
-        d.ops_off = -1;
-        d.cnt_off = -1;
-        d.xt_off = -1;
-        d.xp_off = -1;
+        d.rows_off = d.ops_off = d.cnt_off = d.xt_off = d.xp_off = -1;
         d.mat = mat;
-        if (!(fl & FS0)) { d.rows_off = (int32_t)p; p += m; }
-        if (!(fl & FS1)) { d.ops_off = (int32_t)p; d.flags |= DOPS; p += m; }
-        if (!(fl & FRECT)) { d.cnt_off = (int32_t)p; p += m; }
-        if (!(fl & FS2)) d.xt_off = (int32_t)p;
-        // per-row facts, decoded from the tables just written
+        int32_t dfl = fl & ~FRUNS;
+        // rows of the codelet: canonical ROWS table or the strided formula
         rows.resize(m);
         opst.resize(m);
         nops.resize(m);
+        int64_t ap = r[C_AUXOFF];
+        for (int32_t a = 0; a < m; a++)
+            rows[a] = (fl & FS0) ? (int64_t)d.row0 + (int64_t)a * d.row_step : c.aux[ap + a];
         for (int32_t a = 0; a < m; a++) {
-            rows[a] = (fl & FS0) ? (int64_t)d.row0 + (int64_t)a * d.row_step : D.aux[d.rows_off + a];
-            opst[a] = (d.flags & DOPS) ? D.aux[d.ops_off + a] : (int64_t)d.op0 + (int64_t)a * d.op_step;
-            nops[a] = (fl & FRECT) ? d.nn : D.aux[d.cnt_off + a];
+            opst[a] = P.opstart(rows[a]);
+            nops[a] = P.nops(rows[a]);
         }
-        // solves need every row's diagonal position; when S1 holds only because the
-        // codelet has no operations the record's op_step may not give it
-        if (kind >= 1 && (fl & FS1) && d.nn == 0 && m >= 2) {
-            bool arith = true;
-            for (int32_t a = 0; a < m; a++) {
-                int64_t real = kind == 1 ? (int64_t)rp[rows[a]] : (int64_t)rp[rows[a]] + 1;
-                if (real != (int64_t)d.op0 + (int64_t)a * d.op_step) arith = false;
-            }
-            if (!arith) {
-                d.ops_off = (int32_t)D.aux.size();
-                d.flags |= DOPS;
-                for (int32_t a = 0; a < m; a++)
-                    D.aux.push_back(kind == 1 ? rp[rows[a]] : rp[rows[a]] + 1);
-                D.supplement += m;
-            }
+        if (!(fl & FS0)) {
+            d.rows_off = (int32_t)D.aux.size();
+            for (int32_t a = 0; a < m; a++) D.aux.push_back((int32_t)rows[a]);
         }
-        const int mode = xmode_host(fl);
-        if (mode == 3 && !(fl & FRECT)) {
-            bool contig = true;
-            for (int32_t a = 0; a + 1 < m; a++)
-                if (opst[a + 1] != opst[a] + nops[a]) contig = false;
-            if (contig) {
-                d.flags |= DCONTIG;
+        bool need_ops = !(fl & FS1);
+        if (!need_ops && P.kind >= 1 && m >= 2)
+            for (int32_t a = 0; a < m; a++)
+                if (opst[a] != (int64_t)d.op0 + (int64_t)a * d.op_step) need_ops = true;
+        if (need_ops) {
+            d.ops_off = (int32_t)D.aux.size();
+            dfl |= DOPS;
+            for (int32_t a = 0; a < m; a++) D.aux.push_back((int32_t)opst[a]);
+        }
+        if (!(fl & FRECT)) {
+            d.cnt_off = (int32_t)D.aux.size();
+            for (int32_t a = 0; a < m; a++) D.aux.push_back((int32_t)nops[a]);
+        }
+        if (!(fl & FS2)) {
+            if (fl & FSEP) {
+                d.xt_off = (int32_t)D.aux.size();
+                for (int64_t b = 0; b < nops[0]; b++) D.aux.push_back(P.ci[opst[0] + b] - d.col0);
             } else {
-                d.xp_off = (int32_t)D.aux.size();
-                d.flags |= DXPTR;
-                int64_t s = 0;
+                int64_t Ptot = 0, R = 0;
                 for (int32_t a = 0; a < m; a++) {
-                    D.aux.push_back((int32_t)s);
-                    s += nops[a];
+                    Ptot += nops[a];
+                    for (int64_t b = 0; b < nops[a]; b++)
+                        if (b == 0 || P.ci[opst[a] + b] != P.ci[opst[a] + b - 1] + 1) R++;
                 }
-                D.supplement += m;
-            }
-        } else if (mode == 4) {
-            d.xp_off = (int32_t)D.aux.size();
-            d.flags |= DRPTR;
-            int64_t j = 0;
-            std::vector<int32_t> rptr(m);
-            for (int32_t a = 0; a < m; a++) {
-                rptr[a] = (int32_t)j;
-                int64_t got = 0;
-                while (got < nops[a]) {
-                    got += D.aux[d.xt_off + 2 * j + 1];
-                    j++;
+                const bool keep_runs = (fl & FRUNS) && (double)Ptot >= RUNS_MIN_AVG * (double)R;
+                if (keep_runs) {
+                    dfl |= FRUNS | DRPTR;
+                    d.xt_off = (int32_t)D.aux.size();
+                    std::vector<int32_t> rptr(m);
+                    int64_t j = 0;
+                    for (int32_t a = 0; a < m; a++) {
+                        rptr[a] = (int32_t)j;
+                        int64_t b = 0;
+                        while (b < nops[a]) {
+                            int64_t e = b + 1;
+                            while (e < nops[a] && P.ci[opst[a] + e] == P.ci[opst[a] + e - 1] + 1) e++;
+                            D.aux.push_back(P.ci[opst[a] + b]);
+                            D.aux.push_back((int32_t)(e - b));
+                            j++;
+                            b = e;
+                        }
+                    }
+                    d.xp_off = (int32_t)D.aux.size();
+                    D.aux.insert(D.aux.end(), rptr.begin(), rptr.end());
+                } else {
+                    d.xt_off = (int32_t)D.aux.size();
+                    for (int32_t a = 0; a < m; a++)
+                        for (int64_t b = 0; b < nops[a]; b++) D.aux.push_back(P.ci[opst[a] + b]);
+                    if (!(fl & FRECT)) {
+                        bool contig = true;
+                        for (int32_t a = 0; a + 1 < m; a++)
+                            if (opst[a + 1] != opst[a] + nops[a]) contig = false;
+                        if (contig) {
+                            dfl |= DCONTIG;
+                        } else {
+                            dfl |= DXPTR;
+                            d.xp_off = (int32_t)D.aux.size();
+                            int64_t s = 0;
+                            for (int32_t a = 0; a < m; a++) {
+                                D.aux.push_back((int32_t)s);
+                                s += nops[a];
+                            }
+                        }
+                    }
                 }
             }
-            D.aux.insert(D.aux.end(), rptr.begin(), rptr.end());
-            D.supplement += m;
         }
+        d.flags = dfl;
         D.cods[first + i] = d;
     }
 }
@@ -206,14 +229,18 @@ int lg_of(int64_t n, int opl) {
     return lg;
 }
 
-// Tasks of one codelet: rows grouped so that a task's lanes-per-row fits its rows.
+// Tasks of one codelet: rows grouped so that a task's lanes-per-row fits its rows.  A task
+// that a single pass covers, on a plain column table, with every row within the look-ahead
+// registers is marked TASK_FAST.
 void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_index, const SchedParams &sp,
                    int phase, std::vector<Task> &out) {
     const int32_t m = d.m;
     auto nops_of = [&](int32_t a) -> int64_t { return (d.flags & FRECT) ? d.nn : aux[d.cnt_off + a]; };
+    const int mode = xmode_host(d.flags);
     int32_t a = 0;
     while (a < m) {
         int lg = lg_of(nops_of(a), sp.ops_per_lane);
+        int64_t mx = nops_of(a);
         int32_t b = a + 1;
         while (b < m) {
             int lgb = lg_of(nops_of(b), sp.ops_per_lane);
@@ -221,63 +248,117 @@ void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_i
             if (lgb + 2 < lg || lgb > lg + 1) break;
             if ((b - a + 1) > (64 >> lgn) * sp.passes) break;
             lg = lgn;
+            mx = std::max(mx, nops_of(b));
             b++;
         }
-        out.push_back({cod_index, a, b, lg | (phase << 8)});
+        int meta = lg | (phase << 8);
+        if (phase == 0 && (b - a) <= (64 >> lg) && (mode == 0 || mode == 1 || mode == 3) &&
+            mx <= ((int64_t)LOOKAHEAD << lg))
+            meta |= TASK_FAST;
+        out.push_back({cod_index, a, b, meta});
         a = b;
     }
 }
 
-// Level-ordered tasks of several matrices for the persistent solve.  Each matrix's
-// codelets [cod_begin[b], cod_begin[b+1]) carry their level in `levels`.  Tasks of
-// level l of every matrix come before level l+1; wait = tasks of the same matrix in
-// earlier levels.  Returns, per matrix, its total task count.
-std::vector<int64_t> solve_tasks(const DevTables &D, const std::vector<int64_t> &cod_begin,
+// Persistent-solve schedule of several matrices: per matrix and level, the level's tasks;
+// runs of consecutive levels with at most thin_tasks tasks become THIN groups, other levels
+// are cut into WIDE groups of at most SWPB tasks.  Groups are ordered by (first level,
+// matrix), so a group only ever waits on earlier groups.  Returns each matrix's task count.
+std::vector<int64_t> build_solve(const DevTables &D, const std::vector<int64_t> &cod_begin,
                                  const std::vector<std::vector<int32_t>> &levels, const SchedParams &sp,
-                                 std::vector<Task> &tasks, std::vector<int32_t> &wait) {
+                                 std::vector<Task> &tasks, std::vector<int32_t> &groups, std::vector<int32_t> &lvl,
+                                 int32_t mat_base = 0) {
     const int nm = (int)cod_begin.size() - 1;
     std::vector<std::vector<std::vector<Task>>> per(nm);
-    int32_t maxl = 0;
     for (int b = 0; b < nm; b++) {
-        int32_t nl = levels[b].empty() ? 0 : levels[b].back() + 1;
+        int32_t nl = 0;
+        for (int32_t l : levels[b]) nl = std::max(nl, l + 1);
         per[b].resize(nl);
-        maxl = std::max(maxl, nl);
         for (int64_t c = cod_begin[b]; c < cod_begin[b + 1]; c++)
             codelet_tasks(D.cods[c], D.aux, (int32_t)c, sp, 0, per[b][levels[b][c - cod_begin[b]]]);
     }
+    struct Item {
+        int32_t l0, mat, type, l1; // levels [l0, l1) for THIN; one level and a slice for WIDE
+        int32_t s0, s1;
+    };
+    std::vector<Item> items;
+    std::vector<std::vector<int64_t>> pre(nm);
     std::vector<int64_t> total(nm, 0);
-    std::vector<std::vector<int64_t>> lvl_prefix(nm);
     for (int b = 0; b < nm; b++) {
-        lvl_prefix[b].assign(per[b].size() + 1, 0);
-        for (size_t l = 0; l < per[b].size(); l++) lvl_prefix[b][l + 1] = lvl_prefix[b][l] + (int64_t)per[b][l].size();
-        total[b] = lvl_prefix[b].back();
-    }
-    for (int32_t l = 0; l < maxl; l++)
-        for (int b = 0; b < nm; b++) {
-            if (l >= (int32_t)per[b].size()) continue;
-            for (const Task &t : per[b][l]) {
-                tasks.push_back(t);
-                wait.push_back((int32_t)lvl_prefix[b][l]);
+        const int32_t nl = (int32_t)per[b].size();
+        pre[b].assign(nl + 1, 0);
+        for (int32_t l = 0; l < nl; l++) pre[b][l + 1] = pre[b][l] + (int64_t)per[b][l].size();
+        total[b] = pre[b][nl];
+        int32_t l = 0;
+        while (l < nl) {
+            if ((int64_t)per[b][l].size() <= sp.thin_tasks) {
+                int32_t l2 = l;
+                while (l2 < nl && (int64_t)per[b][l2].size() <= sp.thin_tasks) l2++;
+                items.push_back({l, b, GROUP_THIN, l2, 0, 0});
+                l = l2;
+            } else {
+                const int32_t n = (int32_t)per[b][l].size();
+                for (int32_t s = 0; s < n; s += SWPB) items.push_back({l, b, GROUP_WIDE, l + 1, s, std::min(n, s + SWPB)});
+                l++;
             }
         }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) {
+        return x.l0 != y.l0 ? x.l0 < y.l0 : x.mat < y.mat;
+    });
+    for (const Item &it : items) {
+        const int32_t t0 = (int32_t)tasks.size();
+        int32_t lv_off = 0, nlv = 0;
+        if (it.type == GROUP_THIN) {
+            lv_off = (int32_t)lvl.size();
+            nlv = it.l1 - it.l0;
+            for (int32_t l = it.l0; l < it.l1; l++) {
+                lvl.push_back((int32_t)tasks.size());
+                tasks.insert(tasks.end(), per[it.mat][l].begin(), per[it.mat][l].end());
+            }
+            lvl.push_back((int32_t)tasks.size());
+        } else {
+            tasks.insert(tasks.end(), per[it.mat][it.l0].begin() + it.s0, per[it.mat][it.l0].begin() + it.s1);
+        }
+        const int32_t g[8] = {it.type, t0, (int32_t)tasks.size(), (int32_t)pre[it.mat][it.l0], mat_base + it.mat, lv_off,
+                              nlv, 0};
+        groups.insert(groups.end(), g, g + 8);
+    }
     return total;
 }
 
+// WIDE groups (after everything else) over phase-1 tasks of matrix b, waiting for `need`.
+void append_gv_groups(const DevTables &F, int64_t c0, int64_t c1, int32_t mat, int64_t need, const SchedParams &sp,
+                      std::vector<Task> &tasks, std::vector<int32_t> &groups) {
+    std::vector<Task> tk;
+    for (int64_t c = c0; c < c1; c++) codelet_tasks(F.cods[c], F.aux, (int32_t)c, sp, 1, tk);
+    for (size_t s = 0; s < tk.size(); s += SWPB) {
+        const int32_t t0 = (int32_t)tasks.size();
+        tasks.insert(tasks.end(), tk.begin() + s, tk.begin() + std::min(tk.size(), s + SWPB));
+        const int32_t g[8] = {GROUP_WIDE, t0, (int32_t)tasks.size(), (int32_t)need, mat, 0, 0, 0};
+        groups.insert(groups.end(), g, g + 8);
+    }
+}
+
+void drop_alloc(ddf_plan_t p, void *ptr) {
+    if (!ptr) return;
+    auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
+    if (it != p->allocs.end()) p->allocs.erase(it);
+    (void)hipFree(ptr);
+}
+
 ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
-    // task buffers are replaced when the schedule changes (autotune)
-    auto drop = [&](void *ptr) {
-        if (!ptr) return;
-        auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
-        if (it != p->allocs.end()) p->allocs.erase(it);
-        (void)hipFree(ptr);
-    };
-    drop(D.d_tasks);
-    drop(D.d_wait);
+    if (p->host_only) return DDF_OK;
+    // schedule buffers are replaced when the schedule changes (autotune)
+    drop_alloc(p, D.d_tasks);
+    drop_alloc(p, D.d_groups);
+    drop_alloc(p, D.d_lvl);
     D.d_tasks = nullptr;
-    D.d_wait = nullptr;
+    D.d_groups = nullptr;
+    D.d_lvl = nullptr;
     ddf_status s = upload(p, &D.d_tasks, D.tasks.data(), D.tasks.size());
-    if (s) return s;
-    if (!D.task_wait.empty()) s = upload(p, &D.d_wait, D.task_wait.data(), D.task_wait.size());
+    if (!s && !D.groups.empty()) s = upload(p, &D.d_groups, D.groups.data(), D.groups.size());
+    if (!s && !D.lvl.empty()) s = upload(p, &D.d_lvl, D.lvl.data(), D.lvl.size());
     return s;
 }
 
@@ -306,49 +387,42 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
     }
     std::vector<int64_t> cb(p->nmat + 1, 0);
     for (int b = 0; b < p->nmat; b++) cb[b + 1] = cb[b] + p->fwd[b].header[7];
+    std::vector<std::vector<int32_t>> lv(p->nmat);
+    for (int b = 0; b < p->nmat; b++) lv[b] = codelet_levels(p->fwd[b]);
     if (fwd) {
-        std::vector<std::vector<int32_t>> lv(p->nmat);
-        for (int b = 0; b < p->nmat; b++) lv[b] = codelet_levels(p->fwd[b]);
         p->F.tasks.clear();
-        p->F.task_wait.clear();
-        solve_tasks(p->F, cb, lv, p->sp_f, p->F.tasks, p->F.task_wait);
+        p->F.groups.clear();
+        p->F.lvl.clear();
+        build_solve(p->F, cb, lv, p->sp_f, p->F.tasks, p->F.groups, p->F.lvl);
         if (ddf_status s = upload_tasks(p, p->F)) return s;
         if (p->batch) {
-            // per-matrix task lists for the one-launch-per-matrix comparator
+            // per-matrix schedules for the one-launch-per-matrix comparator
             p->Fpm.tasks.clear();
-            p->Fpm.task_wait.clear();
-            p->pm_task_ptr.assign(1, 0);
+            p->Fpm.groups.clear();
+            p->Fpm.lvl.clear();
+            p->pm_group_ptr.assign(1, 0);
             for (int b = 0; b < p->nmat; b++) {
                 std::vector<int64_t> one = {cb[b], cb[b + 1]};
                 std::vector<std::vector<int32_t>> l1 = {lv[b]};
-                // solve_tasks expects codelet indices relative to cod_begin[0]
-                std::vector<Task> tk;
-                std::vector<int32_t> wt;
-                solve_tasks(p->F, one, l1, p->sp_f, tk, wt);
-                p->Fpm.tasks.insert(p->Fpm.tasks.end(), tk.begin(), tk.end());
-                p->Fpm.task_wait.insert(p->Fpm.task_wait.end(), wt.begin(), wt.end());
-                p->pm_task_ptr.push_back((int64_t)p->Fpm.tasks.size());
+                build_solve(p->F, one, l1, p->sp_f, p->Fpm.tasks, p->Fpm.groups, p->Fpm.lvl, b);
+                p->pm_group_ptr.push_back((int64_t)p->Fpm.groups.size() / 8);
             }
             if (ddf_status s = upload_tasks(p, p->Fpm)) return s;
         }
     }
     if (adjp && p->has_adj) {
         std::vector<int64_t> cba(p->nmat + 1, 0);
-        std::vector<std::vector<int32_t>> lv(p->nmat);
+        std::vector<std::vector<int32_t>> lva(p->nmat);
         for (int b = 0; b < p->nmat; b++) {
             cba[b + 1] = cba[b] + p->adj[b].header[7];
-            lv[b] = codelet_levels(p->adj[b]);
+            lva[b] = codelet_levels(p->adj[b]);
         }
         p->T.tasks.clear();
-        p->T.task_wait.clear();
-        std::vector<int64_t> total = solve_tasks(p->T, cba, lv, p->sp_a, p->T.tasks, p->T.task_wait);
-        p->n_solve_tasks_adj = (int64_t)p->T.tasks.size();
-        // GV pass over L's forward codelets, after the matrix's whole solve
-        for (int b = 0; b < p->nmat; b++) {
-            size_t before = p->T.tasks.size();
-            for (int64_t c = cb[b]; c < cb[b + 1]; c++) codelet_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_a, 1, p->T.tasks);
-            for (size_t i = before; i < p->T.tasks.size(); i++) p->T.task_wait.push_back((int32_t)total[b]);
-        }
+        p->T.groups.clear();
+        p->T.lvl.clear();
+        std::vector<int64_t> total = build_solve(p->T, cba, lva, p->sp_a, p->T.tasks, p->T.groups, p->T.lvl);
+        p->n_solve_groups_adj = (int64_t)p->T.groups.size() / 8;
+        for (int b = 0; b < p->nmat; b++) append_gv_groups(p->F, cb[b], cb[b + 1], b, total[b], p->sp_a, p->T.tasks, p->T.groups);
         if (ddf_status s = upload_tasks(p, p->T)) return s;
     }
     return DDF_OK;
@@ -434,18 +508,29 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         p->hrp.assign(mats[0].row_ptr, mats[0].row_ptr + mats[0].n_rows + 1);
         p->hci.assign(mats[0].col_idx, mats[0].col_idx + p->nnz);
     }
-    if (p->host_only) {
-        *out = p;
-        return DDF_OK;
-    }
-    // device tables
-    if (hipError_t e = init_device_info()) {
-        free_plan(p);
-        return fail(DDF_E_HIP, std::string("device query: ") + hipGetErrorString(e));
+    // device tables (built on the host for every plan; uploaded unless host_only)
+    if (!p->host_only) {
+        if (hipError_t e = init_device_info()) {
+            free_plan(p);
+            return fail(DDF_E_HIP, std::string("device query: ") + hipGetErrorString(e));
+        }
     }
     for (int b = 0; b < nmat; b++) {
-        pack(p->fwd[b], kind, b, mats[b].row_ptr, p->F);
-        if (p->has_adj) pack(p->adj[b], kind == DDF_SPMV ? 0 : 2, b, rpT[b].data(), p->T);
+        Pattern P{kind, mats[b].n_rows, mats[b].n_cols, mats[b].row_ptr, mats[b].col_idx};
+        pack(p->fwd[b], P, b, p->F);
+        if (p->has_adj) {
+            Pattern PT{kind == DDF_SPMV ? 0 : 2, mats[b].n_cols, mats[b].n_rows, rpT[b].data(), ciT[b].data()};
+            pack(p->adj[b], PT, b, p->T);
+        }
+    }
+    if (p->host_only) {
+        ddf_status st = build_schedule(p, true, true);
+        if (st) {
+            free_plan(p);
+            return st;
+        }
+        *out = p;
+        return DDF_OK;
     }
     ddf_status s = DDF_OK;
     auto fin = [&](ddf_status st) {
@@ -518,17 +603,20 @@ ddf_status check_nrhs(int32_t k) {
 
 const double *vals_or_own(ddf_plan_t p, const double *v) { return v ? v : p->d_vals; }
 
-ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t task0, int64_t ntasks, bool adj,
+ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t g0, int64_t ngroups, bool adj,
                         const double *vals, const double *b, double *x, const double *xf, double *gv,
                         int32_t k_override, int kt, hipStream_t s) {
+    const SchedParams &sp = adj ? p->sp_a : p->sp_f;
     SolveArgs a{};
     a.cods = adj ? p->T.d_cods : p->F.d_cods;
     a.aux = adj ? p->T.d_aux : p->F.d_aux;
     a.cods2 = p->F.d_cods;
     a.aux2 = p->F.d_aux;
-    a.tasks = D.d_tasks + task0;
-    a.wait = D.d_wait + task0;
-    a.ntasks = (int32_t)ntasks;
+    a.tasks = D.d_tasks;
+    a.groups = reinterpret_cast<const Group *>(D.d_groups) + g0;
+    a.ngroups = (int32_t)ngroups;
+    a.lvl = D.d_lvl;
+    a.backoff_max = sp.backoff > 0 ? sp.backoff : 16;
     a.mats = p->d_mats;
     a.vals = vals;
     a.perm = p->d_perm;
@@ -540,7 +628,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t task0, int64_t
     a.spin_limit = p->spin_limit;
     a.k_override = k_override;
     HIPCHK(launch_reset(p->d_ctr, p->nctr, s));
-    HIPCHK(launch_solve(a, adj, kt, s));
+    HIPCHK(launch_solve(a, adj, kt, sp.blocks > 0 ? sp.blocks : num_cu(), s));
     return DDF_OK;
 }
 
@@ -648,7 +736,7 @@ ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, d
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
     if (p->n_rows == 0) return DDF_OK;
     // the single matrix's right-hand-side count is a per-call argument (k_override)
-    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
+    return solve_launch(p, p->F, 0, (int64_t)p->F.groups.size() / 8, false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
                         kt_for(nrhs), (hipStream_t)stream);
 }
 
@@ -712,8 +800,8 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
     if (d_gvals && (overlap(d_gvals, p->nnz * 8, d_gb, nb) || overlap(d_gvals, p->nnz * 8, d_x, nb)))
         return fail(DDF_E_ARG, "gvals overlaps another buffer");
     if (p->n_rows == 0) return DDF_OK;
-    int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
-    return solve_launch(p, p->T, 0, nt, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
+    int64_t ng = d_gvals ? (int64_t)p->T.groups.size() / 8 : p->n_solve_groups_adj;
+    return solve_launch(p, p->T, 0, ng, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
                         (hipStream_t)stream);
 }
 
@@ -731,7 +819,7 @@ ddf_status ddf_sptrsv_batch(ddf_plan_t p, const double *d_vals, const double *d_
     int64_t nb = p->vec_total * 8;
     if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
-    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nullptr, nullptr, 0,
+    return solve_launch(p, p->F, 0, (int64_t)p->F.groups.size() / 8, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
                         batch_kt(p), (hipStream_t)stream);
 }
 
@@ -745,8 +833,8 @@ ddf_status ddf_sptrsv_batch_adjoint(ddf_plan_t p, const double *d_vals, const do
     if ((!d_vals && p->nnz) || !d_gx || !d_gb || (d_gvals && !d_x)) return fail(DDF_E_ARG, "NULL buffer");
     if (d_gb != d_gx && overlap(d_gb, nb, d_gx, nb)) return fail(DDF_E_ARG, "gb and gx partially overlap");
     if (overlap(d_gb, nb, d_x, nb)) return fail(DDF_E_ARG, "gb overlaps x");
-    int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
-    return solve_launch(p, p->T, 0, nt, true, d_vals, d_gx, d_gb, d_x, d_gvals, 0, batch_kt(p),
+    int64_t ng = d_gvals ? (int64_t)p->T.groups.size() / 8 : p->n_solve_groups_adj;
+    return solve_launch(p, p->T, 0, ng, true, d_vals, d_gx, d_gb, d_x, d_gvals, 0, batch_kt(p),
                         (hipStream_t)stream);
 }
 
@@ -757,8 +845,8 @@ ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t p, const double *d_vals, const
     d_vals = vals_or_own(p, d_vals);
     if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
     for (int b = 0; b < p->nmat; b++) {
-        int64_t t0 = p->pm_task_ptr[b], t1 = p->pm_task_ptr[b + 1];
-        if (ddf_status s = solve_launch(p, p->Fpm, t0, t1 - t0, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
+        int64_t g0 = p->pm_group_ptr[b], g1 = p->pm_group_ptr[b + 1];
+        if (ddf_status s = solve_launch(p, p->Fpm, g0, g1 - g0, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
                                         kt_for(p->mats[b].k), (hipStream_t)stream))
             return s;
     }
@@ -971,6 +1059,25 @@ ddf_status ddf_plan_export(ddf_plan_t p, int32_t which, int32_t mat, ddf_plan_ta
     o->codelets = c.codelets.data();
     o->aux = c.aux.data();
     o->perm = which ? c.perm.data() : nullptr;
+    return DDF_OK;
+}
+
+ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables_t *o) {
+    if (!p || !o) return fail(DDF_E_ARG, "NULL argument");
+    const DevTables *D = which == 0 ? &p->F : which == 1 ? &p->T : which == 2 ? &p->Fpm : nullptr;
+    if (!D) return fail(DDF_E_ARG, "which must be 0, 1 or 2");
+    if (which == 1 && !p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    const DevTables &S = which == 2 ? p->F : *D; // per-matrix schedules share F's records
+    o->cods = reinterpret_cast<const int32_t *>(S.cods.data());
+    o->aux = S.aux.data();
+    o->tasks = reinterpret_cast<const int32_t *>(D->tasks.data());
+    o->groups = D->groups.data();
+    o->lvl = D->lvl.data();
+    o->n_cods = (int64_t)S.cods.size();
+    o->aux_len = (int64_t)S.aux.size();
+    o->n_tasks = (int64_t)D->tasks.size();
+    o->n_groups = (int64_t)D->groups.size() / 8;
+    o->lvl_len = (int64_t)D->lvl.size();
     return DDF_OK;
 }
 

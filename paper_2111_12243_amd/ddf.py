@@ -29,7 +29,7 @@ EXPORTED = [
     "ddf_sptrsv_batch", "ddf_sptrsv_batch_adjoint", "ddf_graph_create_batch", "ddf_graph_launch",
     "ddf_graph_destroy", "ddf_plain_spmv", "ddf_plain_sptrsv", "ddf_plain_spmv_adjoint",
     "ddf_plain_sptrsv_adjoint", "ddf_sptrsv_batch_per_matrix", "ddf_autotune", "ddf_plan_info",
-    "ddf_plan_export", "ddf_plan_traffic", "ddf_plan_sync_status", "ddf_plan_set_spin_limit",
+    "ddf_plan_export", "ddf_plan_device_tables", "ddf_plan_traffic", "ddf_plan_sync_status", "ddf_plan_set_spin_limit",
     "ddf_status_string", "ddf_last_error", "ddf_version",
 ]
 
@@ -56,6 +56,12 @@ class ddf_plan_tables_t(C.Structure):
                 ("part_rows", C.POINTER(C.c_int64)), ("regions", C.POINTER(C.c_int64)),
                 ("codelets", C.POINTER(C.c_int64)), ("aux", C.POINTER(C.c_int32)),
                 ("perm", C.POINTER(C.c_int32))]
+
+
+class ddf_device_tables_t(C.Structure):
+    _fields_ = [("cods", C.POINTER(C.c_int32)), ("aux", C.POINTER(C.c_int32)), ("tasks", C.POINTER(C.c_int32)),
+                ("groups", C.POINTER(C.c_int32)), ("lvl", C.POINTER(C.c_int32)), ("n_cods", C.c_int64),
+                ("aux_len", C.c_int64), ("n_tasks", C.c_int64), ("n_groups", C.c_int64), ("lvl_len", C.c_int64)]
 
 
 class ddf_plan_info_t(C.Structure):
@@ -104,6 +110,7 @@ def lib():
             "ddf_autotune": (I32, [P, I32, I32, P, D]),
             "ddf_plan_info": (I32, [P, C.POINTER(ddf_plan_info_t)]),
             "ddf_plan_export": (I32, [P, I32, I32, C.POINTER(ddf_plan_tables_t)]),
+            "ddf_plan_device_tables": (I32, [P, I32, C.POINTER(ddf_device_tables_t)]),
             "ddf_plan_traffic": (I32, [P, I32, I32, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
             "ddf_plan_sync_status": (I32, [P, P]),
             "ddf_plan_set_spin_limit": (I32, [P, I64]),
@@ -336,6 +343,22 @@ def ddf_plan_export(plan, which=0, mat=0) -> dict:
     if which == 1:
         out["perm"] = grab(t.perm, int(h[3]), np.int64)
     return out
+
+
+def ddf_plan_device_tables(plan, which=0) -> dict:
+    """Copies of the tables the kernels read (records, aux, tasks, groups, level bounds)."""
+    t = ddf_device_tables_t()
+    _check(lib().ddf_plan_device_tables(plan.handle, which, C.byref(t)))
+
+    def grab(p, n, cols=None):
+        if n == 0 or not p:
+            a = np.zeros(0, dtype=np.int32)
+        else:
+            a = np.ctypeslib.as_array(p, shape=(n * (cols or 1),)).copy()
+        return a.reshape(-1, cols) if cols else a
+
+    return {"cods": grab(t.cods, t.n_cods, 16), "aux": grab(t.aux, t.aux_len), "tasks": grab(t.tasks, t.n_tasks, 4),
+            "groups": grab(t.groups, t.n_groups, 8), "lvl": grab(t.lvl, t.lvl_len)}
 
 
 def ddf_plan_traffic(plan, op, nrhs) -> tuple:

@@ -1,0 +1,196 @@
+"""Test helper: replays the kernels' indexing over the device tables on the CPU.
+
+It reads the tables exactly as the HIP kernels do (record fields, flag bits, aux offsets,
+tasks, groups, thin-level bounds), asserts that every table, value and column index stays
+in bounds, that groups only read solution entries written by earlier groups, and returns the
+results so they can be compared with the oracle.  It shares nothing with the library but
+the published table layout.
+"""
+import numpy as np
+
+FS0, FS1, FS2, FSEP, FRECT, FRUNS = 1, 2, 4, 8, 16, 32
+DOPS, DCONTIG, DXPTR, DRPTR = 64, 128, 256, 512
+TASK_FAST = 1 << 9
+LOOKAHEAD = 4
+F = {n: i for i, n in enumerate(["flags", "m", "nn", "row0", "row_step", "op0", "op_step", "col0", "sigma0",
+                                 "sigma1", "rows_off", "ops_off", "cnt_off", "xt_off", "xp_off", "mat"])}
+
+
+def xmode(fl):
+    if fl & FS2:
+        return 0
+    if fl & FSEP:
+        return 2 if fl & FRUNS else 1
+    return 4 if fl & FRUNS else 3
+
+
+class Tables:
+    def __init__(self, t):
+        self.cods, self.aux, self.tasks, self.groups, self.lvl = t["cods"], t["aux"], t["tasks"], t["groups"], t["lvl"]
+
+    def a(self, i):
+        assert 0 <= i < self.aux.size, f"aux index {i} out of [0, {self.aux.size})"
+        return int(self.aux[i])
+
+    def row_info(self, c, i0):
+        fl = int(c[F["flags"]])
+        assert 0 <= i0 < c[F["m"]]
+        row = int(c[F["row0"]] + i0 * c[F["row_step"]]) if fl & FS0 else self.a(c[F["rows_off"]] + i0)
+        opst = self.a(c[F["ops_off"]] + i0) if fl & DOPS else int(c[F["op0"]] + i0 * c[F["op_step"]])
+        nops = int(c[F["nn"]]) if fl & FRECT else self.a(c[F["cnt_off"]] + i0)
+        return row, opst, nops
+
+    def cols(self, c, i0, opst, nops):
+        fl = int(c[F["flags"]])
+        mode = xmode(fl)
+        out = []
+        if mode == 0:
+            base = int(c[F["col0"]] + i0 * c[F["sigma0"]])
+            out = [base + i1 * int(c[F["sigma1"]]) for i1 in range(nops)]
+        elif mode == 1:
+            base = int(c[F["col0"]] + i0 * c[F["sigma0"]])
+            out = [base + self.a(c[F["xt_off"]] + i1) for i1 in range(nops)]
+        elif mode == 3:
+            if fl & FRECT:
+                off = i0 * int(c[F["nn"]])
+            elif fl & DCONTIG:
+                off = opst - int(c[F["op0"]])
+            else:
+                off = self.a(c[F["xp_off"]] + i0)
+            out = [self.a(c[F["xt_off"]] + off + i1) for i1 in range(nops)]
+        else:
+            if mode == 2:
+                rt, base = int(c[F["xt_off"]]), int(c[F["col0"]] + i0 * c[F["sigma0"]])
+            else:
+                rt, base = int(c[F["xt_off"]]) + 2 * self.a(c[F["xp_off"]] + i0), 0
+            j, cum, ln, st = -1, 0, 0, 0
+            for i1 in range(nops):
+                while i1 >= cum + ln:
+                    cum += ln
+                    j += 1
+                    st, ln = self.a(rt + 2 * j), self.a(rt + 2 * j + 1)
+                out.append(base + st + (i1 - cum))
+        return out
+
+    def task_rows(self, t):
+        """[(row, value indices, columns)] of task t, with the codelet record."""
+        cod, i0b, i0e, meta = (int(v) for v in self.tasks[t])
+        c = self.cods[cod]
+        lg = meta & 7
+        assert 0 <= i0b < i0e <= c[F["m"]]
+        if meta & TASK_FAST:
+            assert i0e - i0b <= (64 >> lg)
+            assert xmode(int(c[F["flags"]])) in (0, 1, 3)
+        out = []
+        for i0 in range(i0b, i0e):
+            row, opst, nops = self.row_info(c, i0)
+            if meta & TASK_FAST:
+                assert nops <= (LOOKAHEAD << lg)
+            out.append((row, opst, nops, self.cols(c, i0, opst, nops)))
+        return c, meta, out
+
+
+def spmv(tabs, A, X, vals=None, perm=None, tasks=None):
+    """Y = A X replayed over SpMV tasks (values through perm for the transposed plan)."""
+    T = Tables(tabs)
+    v = A.values if vals is None else vals
+    k = X.shape[1]
+    Y = np.full((A.n_rows, k), np.nan)
+    seen = np.zeros(A.n_rows, int)
+    for t in (range(T.tasks.shape[0]) if tasks is None else tasks):
+        c, meta, rows = T.task_rows(t)
+        if (meta >> 8) & 1:
+            continue
+        for row, opst, nops, cols in rows:
+            assert 0 <= row < A.n_rows
+            seen[row] += 1
+            acc = np.zeros(k)
+            for i1, col in enumerate(cols):
+                e = opst + i1
+                assert 0 <= e < int(A.row_ptr[-1]) and 0 <= col < X.shape[0]
+                acc += (v[perm[e]] if perm is not None else v[e]) * X[col]
+            Y[row] = acc
+    assert np.all(seen == 1), "rows not covered exactly once"
+    return Y
+
+
+def gv(tabs, fwd_tabs, A, G, X, t0):
+    """GV[e] = sum_r G[row, r] X[col, r] over phase-1 tasks (tasks of `tabs`, records and
+    aux of the forward tables) from t0 on."""
+    T, TF = Tables(tabs), Tables(fwd_tabs)
+    out = np.full(int(A.row_ptr[-1]), np.nan)
+    for t in range(t0, T.tasks.shape[0]):
+        c, meta, rows = _rows_from(TF, T.tasks[t])
+        assert (meta >> 8) & 1
+        for row, opst, nops, cols in rows:
+            for i1, col in enumerate(cols):
+                e = opst + i1
+                assert np.isnan(out[e])
+                out[e] = G[row] @ X[col]
+    return out
+
+
+def solve(tabs, L, B, kind=1, vals=None, perm=None, fwd_tabs=None, Xf=None, with_gv=False, only_mat=None):
+    """Replays the persistent solve group by group in ticket order.  kind 1: L X = B on L's
+    plan; kind 2: U Lam = B with U = L^T, values through perm.  Checks that every solution
+    entry read was written by an earlier task and that every group's wait count equals the
+    tasks of earlier levels."""
+    T = Tables(tabs)
+    v = L.values if vals is None else vals
+    n, k = B.shape
+    X = np.full((n, k), np.nan)
+    written = np.zeros(n, bool)
+    done = 0
+    gvout = np.full(int(L.row_ptr[-1]), np.nan) if with_gv else None
+    TF = Tables(fwd_tabs) if fwd_tabs is not None else None
+    for g in T.groups:
+        typ, t0, t1, need, mat, lv_off, nlv, _ = (int(x) for x in g)
+        if only_mat is not None and mat != only_mat:
+            continue
+        assert need <= done, "group waits on tasks that come later"
+        if typ == 1:
+            bounds = [int(T.lvl[lv_off + i]) for i in range(nlv + 1)]
+            assert bounds[0] == t0 and bounds[-1] == t1
+            levels = [range(bounds[i], bounds[i + 1]) for i in range(nlv)]
+        else:
+            levels = [range(t0, t1)]
+        for lv in levels:
+            pending = []
+            for t in lv:
+                meta = int(T.tasks[t][3])
+                if (meta >> 8) & 1:
+                    assert with_gv and TF is not None
+                    assert written.all(), "GV pass before the solve finished"
+                    c, _, rows = _rows_from(TF, T.tasks[t])
+                    for row, opst, nops, cols in rows:
+                        for i1, col in enumerate(cols):
+                            gvout[opst + i1] = -(X[row] @ Xf[col])
+                        gvout[opst + nops] = -(X[row] @ Xf[row])
+                    continue
+                c, _, rows = T.task_rows(t)
+                for row, opst, nops, cols in rows:
+                    acc = np.zeros(k)
+                    for i1, col in enumerate(cols):
+                        e = opst + i1
+                        assert written[col], f"row {row} reads x[{col}] before it is solved"
+                        acc += (v[perm[e]] if kind == 2 else v[e]) * X[col]
+                    d = opst - 1 if kind == 2 else opst + nops
+                    diag = v[perm[d]] if kind == 2 else v[d]
+                    pending.append((row, (B[row] - acc) / diag))
+            for row, val in pending:  # a level's rows are independent
+                assert not written[row]
+                X[row] = val
+                written[row] = True
+        done += t1 - t0
+    assert written.all()
+    return X, gvout
+
+
+def _rows_from(TF, task):
+    cod, i0b, i0e, meta = (int(v) for v in task)
+    c = TF.cods[cod]
+    out = []
+    for i0 in range(i0b, i0e):
+        row, opst, nops = TF.row_info(c, i0)
+        out.append((row, opst, nops, TF.cols(c, i0, opst, nops)))
+    return c, meta, out

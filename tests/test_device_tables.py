@@ -1,0 +1,113 @@
+"""Device tables and schedules of host-only plans, replayed on the CPU with the kernels'
+indexing (tests/device_emulator.py): bounds, exact cover, dependency order, and values
+against the oracle."""
+import numpy as np
+import pytest
+
+import device_emulator as E
+import oracle as O
+from paper_2111_12243_amd import ddf
+from paper_2111_12243_amd import inputs as I
+from tolerance import check_gv, check_product, check_solve
+
+
+def hplan(kind, A, **kw):
+    return ddf.ddf_inspect(kind, A, ddf.ddf_opts_default(host_only=1, **kw))
+
+
+def replay_spmv(A, k=2, seed=0, **kw):
+    p = hplan(0, A, **kw)
+    rng = np.random.default_rng(seed)
+    X, G = rng.uniform(-1, 1, (A.n_cols, k)), rng.uniform(-1, 1, (A.n_rows, k))
+    F = ddf.ddf_plan_device_tables(p, 0)
+    check_product(A, X, E.spmv(F, A, X), O.spmv(A, X))
+    T = ddf.ddf_plan_device_tables(p, 1)
+    AT, perm = O.transpose(A)
+    n_gx = int(np.sum(((T["tasks"][:, 3] >> 8) & 1) == 0))
+    GXr, GVr = O.spmv_adj(A, X, G)
+    gx = E.spmv(T, AT, G, vals=A.values, perm=perm, tasks=range(n_gx))
+    check_product(AT, G, gx, GXr)
+    check_gv(A, X, G, E.gv(T, F, A, G, X, n_gx), GVr)
+
+
+def replay_solve(L, k=2, seed=0, **kw):
+    p = hplan(1, L, **kw)
+    rng = np.random.default_rng(seed)
+    B, G = rng.uniform(-1, 1, (L.n_rows, k)), rng.uniform(-1, 1, (L.n_rows, k))
+    F = ddf.ddf_plan_device_tables(p, 0)
+    X, _ = E.solve(F, L, B)
+    ref = O.sptrsv(L, B)
+    check_solve(L, B, X, ref)
+    T = ddf.ddf_plan_device_tables(p, 1)
+    U, perm = O.transpose(L)
+    lam, gv = E.solve(T, U, G, kind=2, vals=L.values, perm=perm, fwd_tabs=F, Xf=ref, with_gv=True)
+    GBr, GVr = O.sptrsv_adj(L, ref, G)
+    check_solve(L, G, lam, GBr, transposed=True)
+    check_gv(L, ref, GBr, -gv, -GVr)
+    return F
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_spmv_tables(seed):
+    rng = np.random.default_rng(seed)
+    A = I.random_csr(int(rng.integers(1, 200)), int(rng.integers(1, 200)), seed,
+                     density=float(rng.uniform(0.005, 0.1)), empty_frac=float(rng.uniform(0, 0.4)),
+                     runs=bool(seed % 2))
+    replay_spmv(A, k=1 + seed % 3, seed=seed, ops_per_lane=int(rng.choice([1, 4, 16])),
+                rows_passes=int(rng.choice([1, 2, 4])), window=int(rng.choice([8, 64])))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_solve_tables(seed):
+    rng = np.random.default_rng(70 + seed)
+    L = I.random_lower(int(rng.integers(1, 160)), seed, density=float(rng.uniform(0, 0.06)), runs=bool(seed % 2))
+    replay_solve(L, k=1 + seed % 3, seed=seed, ops_per_lane=int(rng.choice([1, 4, 16])),
+                 rows_passes=int(rng.choice([1, 2])), window=int(rng.choice([4, 64])))
+
+
+def test_workload_tables():
+    w = I.c1_laplace2d()
+    replay_spmv(w.A, k=1)
+    F = replay_solve(w.L, k=1)
+    assert F["groups"].shape[0] == 1 and F["groups"][0, 0] == 1  # one thin range of 127 levels
+    w = I.c2_stencil27_offband(nx=12)
+    replay_spmv(w.A, k=1)
+    replay_solve(w.L, k=1)
+    w = I.c5_laplace27(nx=10, k=2)
+    replay_spmv(w.A, k=2)
+    replay_solve(w.L, k=2)
+
+
+def test_thin_and_wide_groups():
+    # a 2D Laplacian whose middle levels exceed 16 tasks: wide groups between two thin ranges
+    L = I.tril(I.laplacian(700, 700, 1, I.OFFS_5PT, 4.0))
+    F = ddf.ddf_plan_device_tables(hplan(1, L, ops_per_lane=1, rows_passes=1), 0)
+    types = F["groups"][:, 0]
+    assert types[0] == 1 and types[-1] == 1 and (types == 0).any()
+    # groups are ordered by first level and their waits never decrease
+    assert np.all(np.diff(F["groups"][:, 3]) >= 0)
+
+
+def test_batch_schedule_per_matrix():
+    mats = [I.batch_matrix(b, n_lo=200, n_hi=3000) for b in range(5)]
+    Ls = [m["L"] for m in mats]
+    p = ddf.ddf_inspect_batch(1, Ls, [m["k"] for m in mats], ddf.ddf_opts_default(host_only=1))
+    F = ddf.ddf_plan_device_tables(p, 0)
+    T = ddf.ddf_plan_device_tables(p, 1)
+    PM = ddf.ddf_plan_device_tables(p, 2)
+    for g in F["groups"]:
+        for t in range(g[1], g[2]):
+            assert F["cods"][F["tasks"][t][0]][15] == g[4]
+    for b, m in enumerate(mats):
+        L, k = m["L"], m["k"]
+        B = m["B"]
+        X, _ = E.solve(F, L, B, only_mat=b)
+        ref = O.sptrsv(L, B)
+        check_solve(L, B, X, ref)
+        X2, _ = E.solve(PM, L, B, only_mat=b)
+        assert np.array_equal(X, X2)
+        U, perm = O.transpose(L)
+        lam, gv = E.solve(T, U, m["G"], kind=2, vals=L.values, perm=perm, fwd_tabs=F, Xf=ref, with_gv=True,
+                          only_mat=b)
+        GBr, GVr = O.sptrsv_adj(L, ref, m["G"])
+        check_solve(L, m["G"], lam, GBr, transposed=True)
