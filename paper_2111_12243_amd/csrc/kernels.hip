@@ -358,11 +358,11 @@ __device__ __forceinline__ void pre_load(const SolveArgs &a, int t, int lane, Pr
     }
 }
 
-template <int KT, bool ADJ>
+template <int KT, bool ADJ, bool COH>
 __device__ __forceinline__ void pre_compute(const SolveArgs &a, const Pre &p, int lane) {
     if (p.task < 0) return;
     if (!p.fast) {
-        solve_task<KT, ADJ, false>(a, p.task, lane);
+        solve_task<KT, ADJ, COH>(a, p.task, lane);
         return;
     }
     const int G = 1 << p.lg, g = lane & (G - 1);
@@ -381,7 +381,7 @@ __device__ __forceinline__ void pre_compute(const SolveArgs &a, const Pre &p, in
                     const double *xr = x + (int64_t)p.col[j] * k + r0;
 #pragma unroll
                     for (int r = 0; r < KT; r++)
-                        if (r0 + r < k) acc[r] += p.v[j] * xr[r];
+                        if (r0 + r < k) acc[r] += p.v[j] * xload<COH>(xr + r);
                 }
             }
         }
@@ -389,7 +389,7 @@ __device__ __forceinline__ void pre_compute(const SolveArgs &a, const Pre &p, in
         if (p.active) {
 #pragma unroll
             for (int r = 0; r < KT; r++)
-                if ((r & (G - 1)) == g && r0 + r < k) x[rb + r0 + r] = (b[rb + r0 + r] - acc[r]) / p.diag;
+                if ((r & (G - 1)) == g && r0 + r < k) xstore<COH>(x + rb + r0 + r, (b[rb + r0 + r] - acc[r]) / p.diag);
         }
     }
 }
@@ -411,6 +411,15 @@ __global__ __launch_bounds__(WAVE *SWPB) void k_solve(SolveArgs a) {
         __syncthreads();
         if (gi >= a.ngroups) break;
         const Group gr = a.groups[gi];
+        // a WIDE group loads everything its first task needs that does not depend on the
+        // solution before it waits, so the loads overlap the levels still running
+        Pre wide;
+        wide.task = -1;
+        const bool is_wide = gr.type != GROUP_THIN;
+        if (is_wide) {
+            const int t = gr.t0 + wave;
+            if (t < gr.t1 && ((a.tasks[t].meta >> 8) & 1) == 0) pre_load<ADJ>(a, t, lane, wide);
+        }
         if (wave == 0 && gr.need > 0) {
             // bounded wait with backoff; past the spin limit, or once another block has
             // tripped the error flag, stop waiting (the results are then reported invalid)
@@ -444,7 +453,7 @@ __global__ __launch_bounds__(WAVE *SWPB) void k_solve(SolveArgs a) {
                     ne = a.lvl[gr.lv_off + l + 2];
                 }
                 pre_load<ADJ>(a, nb + wave < ne ? nb + wave : -1, lane, nxt);
-                pre_compute<KT, ADJ>(a, cur, lane);
+                pre_compute<KT, ADJ, false>(a, cur, lane);
                 for (int t = lb + wave + SWPB; t < le; t += SWPB) solve_task<KT, ADJ, false>(a, t, lane);
                 __syncthreads();
                 cur = nxt;
@@ -453,7 +462,12 @@ __global__ __launch_bounds__(WAVE *SWPB) void k_solve(SolveArgs a) {
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         } else {
-            for (int t = gr.t0 + wave; t < gr.t1; t += SWPB) solve_task<KT, ADJ, true>(a, t, lane);
+            int t = gr.t0 + wave;
+            if (wide.task >= 0) {
+                pre_compute<KT, ADJ, true>(a, wide, lane);
+                t += SWPB;
+            }
+            for (; t < gr.t1; t += SWPB) solve_task<KT, ADJ, true>(a, t, lane);
             // this wave's device-scope stores are complete before the block signals
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         }

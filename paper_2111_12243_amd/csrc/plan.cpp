@@ -1173,11 +1173,11 @@ void load_tune_file() {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // one entry per line: "key": [ops_per_lane, passes, remap],
+        // one entry per line: "key": [ops_per_lane, passes, remap, thin_tasks],
         size_t q1 = line.find('"'), q2 = line.find('"', q1 + 1), b = line.find('[');
         if (q1 == std::string::npos || q2 == std::string::npos || b == std::string::npos) continue;
         SchedParams sp;
-        if (sscanf(line.c_str() + b, "[%d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap) == 3)
+        if (sscanf(line.c_str() + b, "[%d, %d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap, &sp.thin_tasks) == 4)
             g_tune_cache[line.substr(q1 + 1, q2 - q1 - 1)] = sp;
     }
 }
@@ -1190,7 +1190,7 @@ void save_tune_file() {
     size_t i = 0;
     for (auto &kv : g_tune_cache)
         f << "  \"" << kv.first << "\": [" << kv.second.ops_per_lane << ", " << kv.second.passes << ", "
-          << kv.second.remap << "]" << (++i < g_tune_cache.size() ? "," : "") << "\n";
+          << kv.second.remap << ", " << kv.second.thin_tasks << "]" << (++i < g_tune_cache.size() ? "," : "") << "\n";
     f << "}\n";
 }
 
@@ -1243,33 +1243,42 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
     SchedParams best = target;
     float best_ms = 1e30f;
     double spent = 0;
-    const int opls[] = {2, 4, 8, 16};
-    const int passes[] = {1, 2, 4};
-    const int remaps[] = {1, 0};
-    for (int rm : remaps) {
-        if (!is_spmv && rm == 0) continue;
-        for (int opl : opls)
-            for (int ps : passes) {
-                if (st || (budget_ms > 0 && spent > budget_ms)) break;
-                target.ops_per_lane = opl;
-                target.passes = ps;
-                target.remap = rm;
-                if ((st = build_schedule(p, !adjop, adjop))) break;
-                if ((st = run())) break;
-                (void)hipEventRecord(e0, s);
-                const int reps = 3;
-                for (int r = 0; r < reps && !st; r++) st = run();
-                (void)hipEventRecord(e1, s);
-                (void)hipEventSynchronize(e1);
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                spent += ms * (reps + 1);
-                ms /= reps;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = target;
-                }
-            }
+    // candidates: SpMV varies lanes per row, row passes and XCD block order; the solve
+    // varies lanes per row, row passes and whether small levels run as THIN ranges
+    struct Cand {
+        int opl, ps, rm, thin;
+    };
+    std::vector<Cand> cands;
+    if (is_spmv) {
+        for (int rm : {1, 0})
+            for (int opl : {1, 2, 4, 8, 16})
+                for (int ps : {1, 2, 4}) cands.push_back({opl, ps, rm, target.thin_tasks});
+    } else {
+        for (int thin : {SWPB, 0})
+            for (int opl : {2, 4, 8})
+                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, thin});
+    }
+    for (const Cand &cd : cands) {
+        if (st || (budget_ms > 0 && spent > budget_ms)) break;
+        target.ops_per_lane = cd.opl;
+        target.passes = cd.ps;
+        target.remap = cd.rm;
+        target.thin_tasks = cd.thin;
+        if ((st = build_schedule(p, !adjop, adjop))) break;
+        if ((st = run())) break;
+        (void)hipEventRecord(e0, s);
+        const int reps = 3;
+        for (int r = 0; r < reps && !st; r++) st = run();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        spent += ms * (reps + 1);
+        ms /= reps;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = target;
+        }
     }
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);
