@@ -69,7 +69,8 @@ typedef struct {
                               next power of two of row length / this); 0 = default 4       */
     int32_t rows_passes;   /* schedule: row passes per wavefront task; 0 = default 2       */
     int32_t xcd_remap;     /* schedule: give each XCD a contiguous block range; -1 default */
-    int32_t reserved;
+    int32_t thin_tasks;    /* schedule (solve): runs of levels with at most this many tasks
+                              are solved inside one block; 0 = never; -1 = default 16      */
 } ddf_opts;
 
 typedef struct {
@@ -238,13 +239,15 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
  *   cods   [n_cods][16]  flags, m, nn, row0, row_step, op0, op_step, col0, sigma0, sigma1,
  *                        rows_off, ops_off, cnt_off, xt_off, xp_off, mat
  *   tasks  [n_tasks][4]  codelet, first row, end row, meta (log2 lanes per row | phase << 8 |
- *                        look-ahead eligible << 9)
+ *                        look-ahead eligible << 9 | streamed << 10); for SpMV the list used
+ *                        with one right-hand side
+ *   tasksN [n_tasksN][4] SpMV: the list used with several right-hand sides
  *   groups [n_groups][8] type (0 wide, 1 thin), first task, end task, tasks to wait for,
  *                        matrix, level-table offset, levels, 0
  *   lvl    [lvl_len]     task boundaries of the levels of thin groups */
 typedef struct {
-    const int32_t *cods, *aux, *tasks, *groups, *lvl;
-    int64_t n_cods, aux_len, n_tasks, n_groups, lvl_len;
+    const int32_t *cods, *aux, *tasks, *groups, *lvl, *tasksN;
+    int64_t n_cods, aux_len, n_tasks, n_groups, lvl_len, n_tasksN;
 } ddf_device_tables_t;
 ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
 

@@ -80,17 +80,25 @@ struct SchedParams {
 struct DevTables {
     std::vector<DCod> cods;
     std::vector<int32_t> aux;          // canonical aux followed by device supplements
-    std::vector<Task> tasks;
+    std::vector<Task> tasks;           // solve; SpMV with one right-hand side
+    std::vector<Task> tasksN;          // SpMV with several right-hand sides
     std::vector<int32_t> groups;       // solve: 8 int32 per group (see kernels.hpp Group)
     std::vector<int32_t> lvl;          // solve: level boundaries of THIN groups
     DCod *d_cods = nullptr;
     int32_t *d_aux = nullptr;
     Task *d_tasks = nullptr;
+    Task *d_tasksN = nullptr;
     int32_t *d_groups = nullptr;
     int32_t *d_lvl = nullptr;
     int64_t bytes() const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
                (int64_t)tasks.size() * sizeof(Task) + (int64_t)groups.size() * 4 + (int64_t)lvl.size() * 4;
+    }
+    // bytes a launch reads: records and aux (upper bound) plus its own task list
+    int64_t launch_bytes(bool many_rhs) const {
+        return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
+               (int64_t)(many_rhs ? tasksN.size() : tasks.size()) * sizeof(Task) + (int64_t)groups.size() * 4 +
+               (int64_t)lvl.size() * 4;
     }
 };
 

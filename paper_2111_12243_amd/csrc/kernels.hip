@@ -133,69 +133,154 @@ __device__ __forceinline__ int xcd_block(int b, int nb, int remap) {
 __device__ __forceinline__ DCod load_cod(const DCod *p) { return *p; }
 
 // ------------------------------------------------------------------------------------------
-// SpMV executor: Y[:, r0:r0+KT] (tiles over nrhs inside) = A X.  VPERM: values read through
-// perm (the transposed plan of the adjoint pass).  Phase-1 tasks (fused adjoint) compute
-// GV[e] = sum_r G[row, r] X[col, r] over the forward plan instead.
+// SpMV executor.  Three task shapes, chosen per task by the scheduler:
+//  - stream (one right-hand side, rectangular codelet with contiguous values): the task's
+//    values (and a full column table) are one contiguous range; lane l takes elements
+//    l + 64 j, keeps SJ independent loads in flight, and row sums go through LDS;
+//  - lanes-per-row (one right-hand side, any codelet): G lanes share a row, shuffles
+//    combine their partial sums;
+//  - rhs-lanes (several right-hand sides): KR lanes per row, lane r owns right-hand side r,
+//    so each x row is read as one contiguous 8*k-byte segment and no reduction is needed.
+// VPERM reads values through perm (the transposed plan of the adjoint pass).  Phase-1
+// tasks of a fused adjoint launch compute GV[e] = sum_r G[row, r] X[col, r] instead.
 // ------------------------------------------------------------------------------------------
-template <int KT, bool VPERM>
-__global__ __launch_bounds__(WAVE *WPB) void k_spmv(SpmvArgs a) {
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
-    if (t >= a.ntasks) return;
-    const Task tk = a.tasks[t];
+constexpr int SJ = 8; // elements per lane of a stream task (64 * SJ per task)
+
+template <bool VPERM>
+__device__ __forceinline__ double val_at(const SpmvArgs &a, int e) {
+    return VPERM ? a.vals[a.perm[e]] : a.vals[e];
+}
+
+__device__ __forceinline__ int row_of(const DCod &c, const int32_t *__restrict__ aux, int i0) {
+    return (c.flags & FS0) ? c.row0 + i0 * c.row_step : aux[c.rows_off + i0];
+}
+
+// GV over the forward plan for phase-1 tasks: one output per op (lanes split the ops)
+__device__ void spmv_gv_task(const SpmvArgs &a, const Task &tk, int lane) {
     const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
     const int slot = lane >> lg, g = lane & (G - 1);
     const int k = a.k;
-    if ((tk.meta >> 8) & 1) {
-        // GV pass over the forward plan: one output per op, no reduction
-        const DCod c = load_cod(a.cods2 + tk.cod);
-        const int mode = xmode(c.flags);
-        for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
-            const RowInfo ri = row_info(c, a.aux2, i0);
-            const double *__restrict__ grow = a.g + (int64_t)ri.row * k;
-            walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
-                const double *__restrict__ xr = a.x2 + (int64_t)col * k;
-                double s = 0.0;
-                for (int r = 0; r < k; r++) s += grow[r] * xr[r];
-                a.gv[e] = s;
-            });
-        }
-        return;
-    }
-    const DCod c = load_cod(a.cods + tk.cod);
+    const DCod c = load_cod(a.cods2 + tk.cod);
     const int mode = xmode(c.flags);
-    // passes are wave-uniform; lanes whose row is past the task's end stay converged for the
-    // shuffles and contribute zeros
+    for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
+        const RowInfo ri = row_info(c, a.aux2, i0);
+        const double *__restrict__ grow = a.g + (int64_t)ri.row * k;
+        walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
+            const double *__restrict__ xr = a.x2 + (int64_t)col * k;
+            double s = 0.0;
+            for (int r = 0; r < k; r++) s += grow[r] * xr[r];
+            a.gv[e] = s;
+        });
+    }
+}
+
+template <bool VPERM>
+__device__ void spmv_stream_task(const SpmvArgs &a, const Task &tk, int lane, double *__restrict__ lds) {
+    const DCod c = load_cod(a.cods + tk.cod);
+    const int a0 = tk.i0b, nrow = tk.i0e - tk.i0b, nn = c.nn;
+    const int E = nrow * nn;
+    const int ebase = c.op0 + a0 * nn;
+    const int mode = xmode(c.flags);
+    // q = e / nn by multiply-high: exact for e, nn < 2^16
+    const unsigned magic = 0xFFFFFFFFu / (unsigned)nn + 1u;
+    double prod[SJ];
+#pragma unroll
+    for (int j = 0; j < SJ; j++) {
+        const int e = lane + WAVE * j;
+        prod[j] = 0.0;
+        if (e < E) {
+            const int q = (int)__umulhi((unsigned)e, magic);
+            const int i1 = e - q * nn;
+            const int i0 = a0 + q;
+            int col;
+            if (mode == XM_STRIDED)
+                col = c.col0 + i0 * c.sigma0 + i1 * c.sigma1;
+            else if (mode == XM_SHARED)
+                col = c.col0 + i0 * c.sigma0 + a.aux[c.xt_off + i1];
+            else
+                col = a.aux[c.xt_off + a0 * nn + e];
+            prod[j] = val_at<VPERM>(a, ebase + e) * a.x[col];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < SJ; j++) {
+        const int e = lane + WAVE * j;
+        if (e < E) lds[e] = prod[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < nrow) {
+        double s = 0.0;
+        for (int i1 = 0; i1 < nn; i1++) s += lds[lane * nn + i1];
+        a.y[row_of(c, a.aux, a0 + lane)] = s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool VPERM>
+__device__ void spmv_group_task(const SpmvArgs &a, const Task &tk, int lane) {
+    const DCod c = load_cod(a.cods + tk.cod);
+    const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
+    const int slot = lane >> lg, g = lane & (G - 1);
+    const int mode = xmode(c.flags);
     for (int base = tk.i0b; base < tk.i0e; base += R) {
         const int i0 = base + slot;
         const bool active = i0 < tk.i0e;
         RowInfo ri{0, 0, 0};
         if (active) ri = row_info(c, a.aux, i0);
-        for (int r0 = 0; r0 < k; r0 += KT) {
-            double acc[KT];
-#pragma unroll
-            for (int r = 0; r < KT; r++) acc[r] = 0.0;
-            const bool full = r0 + KT <= k;
-            if (active)
-                walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
-                    const double v = VPERM ? a.vals[a.perm[e]] : a.vals[e];
-                    const double *__restrict__ xr = a.x + (int64_t)col * k + r0;
-                    if (full) {
-#pragma unroll
-                        for (int r = 0; r < KT; r++) acc[r] += v * xr[r];
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < KT; r++)
-                            if (r0 + r < k) acc[r] += v * xr[r];
-                    }
-                });
-            group_sum<KT>(acc, G);
-            if (active) {
-                double *__restrict__ yr = a.y + (int64_t)ri.row * k + r0;
-#pragma unroll
-                for (int r = 0; r < KT; r++)
-                    if ((r & (G - 1)) == g && r0 + r < k) yr[r] = acc[r];
-            }
+        double acc[1] = {0.0};
+        if (active) walk_any(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) { acc[0] += val_at<VPERM>(a, e) * a.x[col]; });
+        group_sum<1>(acc, G);
+        if (active && g == 0) a.y[ri.row] = acc[0];
+    }
+}
+
+// one right-hand side: stream and lanes-per-row tasks (and phase-1 GV tasks)
+template <bool VPERM>
+__global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
+    __shared__ double lds_all[WPB][WAVE * SJ];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
+    if (t >= a.ntasks) return;
+    const Task tk = a.tasks[t];
+    if ((tk.meta >> 8) & 1)
+        spmv_gv_task(a, tk, lane);
+    else if (tk.meta & TASK_STREAM)
+        spmv_stream_task<VPERM>(a, tk, lane, lds_all[wave]);
+    else
+        spmv_group_task<VPERM>(a, tk, lane);
+}
+
+// several right-hand sides: KR lanes per row, lane r owns right-hand sides r, r + KR, ...
+template <int KR, bool VPERM>
+__global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
+    if (t >= a.ntasks) return;
+    const Task tk = a.tasks[t];
+    if ((tk.meta >> 8) & 1) {
+        spmv_gv_task(a, tk, lane);
+        return;
+    }
+    const DCod c = load_cod(a.cods + tk.cod);
+    const int mode = xmode(c.flags);
+    constexpr int P = WAVE / KR;
+    const int slot = lane / KR, r = lane % KR;
+    const int k = a.k;
+    for (int base = tk.i0b; base < tk.i0e; base += P) {
+        const int i0 = base + slot;
+        if (i0 >= tk.i0e) break;
+        const RowInfo ri = row_info(c, a.aux, i0);
+        for (int r0 = 0; r0 < k; r0 += KR) {
+            const int rr = r0 + r;
+            if (rr >= k) break;
+            double acc = 0.0;
+            walk_any(mode, c, a.aux, i0, ri, 0, 1,
+                     [&](int e, int col) { acc += val_at<VPERM>(a, e) * a.x[(int64_t)col * k + rr]; });
+            a.y[(int64_t)ri.row * k + rr] = acc;
         }
     }
 }
@@ -462,14 +547,16 @@ __global__ __launch_bounds__(WAVE *SWPB) void k_solve(SolveArgs a) {
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         } else {
+            // one agent-scope acquire after the wait, cached loads and stores, one release
+            // before the block signals
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             int t = gr.t0 + wave;
             if (wide.task >= 0) {
-                pre_compute<KT, ADJ, true>(a, wide, lane);
+                pre_compute<KT, ADJ, false>(a, wide, lane);
                 t += SWPB;
             }
-            for (; t < gr.t1; t += SWPB) solve_task<KT, ADJ, true>(a, t, lane);
-            // this wave's device-scope stores are complete before the block signals
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            for (; t < gr.t1; t += SWPB) solve_task<KT, ADJ, false>(a, t, lane);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         }
         __syncthreads();
         if (wave == 0)
@@ -603,11 +690,6 @@ __global__ __launch_bounds__(WAVE *WPB) void k_csr_gv(PlainArgs a) {
     }
 }
 
-template <int KT, bool V>
-void launch_spmv_t(const SpmvArgs &a, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv<KT, V>), dim3(nblocks), dim3(WAVE * WPB), 0, s, a);
-}
-
 int g_solve_blocks = 0; // resident blocks of the persistent kernel on the whole device
 int g_num_cu = 0;
 
@@ -633,19 +715,29 @@ hipError_t init_device_info() {
     return hipSuccess;
 }
 
-hipError_t launch_spmv(const SpmvArgs &a, bool vperm, int kt, hipStream_t s) {
-    int nb = (a.ntasks + WPB - 1) / WPB;
+int kr_for(int k) { return k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32; }
+
+hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s) {
+    const int nb = (a.ntasks + WPB - 1) / WPB;
     if (nb == 0) return hipSuccess;
-    switch (kt * 2 + (vperm ? 1 : 0)) {
-    case 2: launch_spmv_t<1, false>(a, nb, s); break;
-    case 3: launch_spmv_t<1, true>(a, nb, s); break;
-    case 4: launch_spmv_t<2, false>(a, nb, s); break;
-    case 5: launch_spmv_t<2, true>(a, nb, s); break;
-    case 8: launch_spmv_t<4, false>(a, nb, s); break;
-    case 9: launch_spmv_t<4, true>(a, nb, s); break;
-    case 16: launch_spmv_t<8, false>(a, nb, s); break;
-    default: launch_spmv_t<8, true>(a, nb, s); break;
+    const dim3 grid(nb), block(WAVE * WPB);
+    if (a.k == 1) {
+        if (vperm) hipLaunchKernelGGL(k_spmv1<true>, grid, block, 0, s, a);
+        else hipLaunchKernelGGL(k_spmv1<false>, grid, block, 0, s, a);
+        return hipGetLastError();
     }
+#define DDF_SPMVN(KR)                                                                               \
+    if (vperm) hipLaunchKernelGGL((k_spmvN<KR, true>), grid, block, 0, s, a);                      \
+    else hipLaunchKernelGGL((k_spmvN<KR, false>), grid, block, 0, s, a);                            \
+    break;
+    switch (kr_for(a.k)) {
+    case 2: DDF_SPMVN(2)
+    case 4: DDF_SPMVN(4)
+    case 8: DDF_SPMVN(8)
+    case 16: DDF_SPMVN(16)
+    default: DDF_SPMVN(32)
+    }
+#undef DDF_SPMVN
     return hipGetLastError();
 }
 

@@ -29,7 +29,9 @@ struct SpmvArgs {
 constexpr int SWPB = 16;     // waves per block of the persistent solve (1024 threads)
 constexpr int LOOKAHEAD = 4; // elements per lane a thin-range wave loads ahead
 enum : int32_t { GROUP_WIDE = 0, GROUP_THIN = 1 };
-enum : int32_t { TASK_FAST = 1 << 9 }; // thin-range task whose rows fit the look-ahead registers
+enum : int32_t { TASK_FAST = 1 << 9,     // solve: thin-range task whose rows fit the look-ahead registers
+                 TASK_STREAM = 1 << 10 }; // SpMV: one-RHS task streamed element by element
+constexpr int STREAM_ELEMS = 64 * 8;     // elements of a stream task (64 lanes x 8)
 
 // A block's unit of work in the persistent solve: tasks [t0, t1) of matrix `mat`, started
 // once `need` tasks of that matrix are done.  THIN groups span nlv levels whose task
@@ -78,7 +80,8 @@ enum PlainKind { PLAIN_SPMV, PLAIN_LEVEL, PLAIN_SPMV_ADJ, PLAIN_GV };
 
 int kt_for(int k);
 hipError_t init_device_info();
-hipError_t launch_spmv(const SpmvArgs &a, bool vperm, int kt, hipStream_t s);
+hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s);
+int kr_for(int k);
 hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s);
 int num_cu();
 hipError_t launch_reset(unsigned *ctr, int n, hipStream_t s);

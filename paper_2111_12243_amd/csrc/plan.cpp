@@ -42,7 +42,8 @@ struct ddf_plan_s {
     DevTables F, T, Fpm;
     std::vector<int64_t> pm_group_ptr; // per-matrix ranges of Fpm.groups
     int64_t n_solve_groups_adj = 0;    // adjoint: groups before the GV pass
-    int64_t n_gx_tasks = 0;           // SpMV adjoint: tasks before the GV pass
+    int64_t n_gx_tasks = 0;           // SpMV adjoint: tasks before the GV pass (one RHS)
+    int64_t n_gx_tasksN = 0;          // same, several right-hand sides
     double *d_vals = nullptr;
     int32_t *d_perm = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_rpT = nullptr, *d_ciT = nullptr;
     int32_t *d_rows = nullptr, *d_rrows = nullptr;
@@ -260,6 +261,28 @@ void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_i
     }
 }
 
+// SpMV tasks of one codelet for one right-hand side: rectangular codelets whose values
+// (and full column table) are contiguous are streamed element by element, STREAM_ELEMS per
+// task; others get lanes-per-row tasks.
+void spmv1_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_index, const SchedParams &sp,
+                 std::vector<Task> &out) {
+    const int mode = xmode_host(d.flags);
+    const bool stream = (d.flags & FRECT) && d.nn >= 1 && d.nn <= STREAM_ELEMS && (mode == 0 || mode == 1 || mode == 3) &&
+                        !(d.flags & DOPS) && (d.m == 1 || d.op_step == d.nn);
+    if (!stream) {
+        codelet_tasks(d, aux, cod_index, sp, 0, out);
+        return;
+    }
+    const int32_t rows = STREAM_ELEMS / d.nn;
+    for (int32_t a = 0; a < d.m; a += rows) out.push_back({cod_index, a, std::min(d.m, a + rows), TASK_STREAM});
+}
+
+// SpMV tasks for several right-hand sides: fixed row blocks (right-hand sides across lanes).
+void spmvN_tasks(const DCod &d, int32_t cod_index, const SchedParams &sp, std::vector<Task> &out) {
+    const int32_t rows = 16 * std::max(1, sp.passes);
+    for (int32_t a = 0; a < d.m; a += rows) out.push_back({cod_index, a, std::min(d.m, a + rows), 0});
+}
+
 // Persistent-solve schedule of several matrices: per matrix and level, the level's tasks;
 // runs of consecutive levels with at most thin_tasks tasks become THIN groups, other levels
 // are cut into WIDE groups of at most SWPB tasks.  Groups are ordered by (first level,
@@ -351,12 +374,15 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     if (p->host_only) return DDF_OK;
     // schedule buffers are replaced when the schedule changes (autotune)
     drop_alloc(p, D.d_tasks);
+    drop_alloc(p, D.d_tasksN);
     drop_alloc(p, D.d_groups);
     drop_alloc(p, D.d_lvl);
     D.d_tasks = nullptr;
+    D.d_tasksN = nullptr;
     D.d_groups = nullptr;
     D.d_lvl = nullptr;
     ddf_status s = upload(p, &D.d_tasks, D.tasks.data(), D.tasks.size());
+    if (!s && !D.tasksN.empty()) s = upload(p, &D.d_tasksN, D.tasksN.data(), D.tasksN.size());
     if (!s && !D.groups.empty()) s = upload(p, &D.d_groups, D.groups.data(), D.groups.size());
     if (!s && !D.lvl.empty()) s = upload(p, &D.d_lvl, D.lvl.data(), D.lvl.size());
     return s;
@@ -373,14 +399,26 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
     if (p->kind == DDF_SPMV) {
         if (fwd) {
             p->F.tasks.clear();
-            for (size_t c = 0; c < p->F.cods.size(); c++) codelet_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_f, 0, p->F.tasks);
+            p->F.tasksN.clear();
+            for (size_t c = 0; c < p->F.cods.size(); c++) {
+                spmv1_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_f, p->F.tasks);
+                spmvN_tasks(p->F.cods[c], (int32_t)c, p->sp_f, p->F.tasksN);
+            }
             if (ddf_status s = upload_tasks(p, p->F)) return s;
         }
         if (adjp && p->has_adj) {
             p->T.tasks.clear();
-            for (size_t c = 0; c < p->T.cods.size(); c++) codelet_tasks(p->T.cods[c], p->T.aux, (int32_t)c, p->sp_a, 0, p->T.tasks);
+            p->T.tasksN.clear();
+            for (size_t c = 0; c < p->T.cods.size(); c++) {
+                spmv1_tasks(p->T.cods[c], p->T.aux, (int32_t)c, p->sp_a, p->T.tasks);
+                spmvN_tasks(p->T.cods[c], (int32_t)c, p->sp_a, p->T.tasksN);
+            }
             p->n_gx_tasks = (int64_t)p->T.tasks.size();
-            for (size_t c = 0; c < p->F.cods.size(); c++) codelet_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_a, 1, p->T.tasks);
+            p->n_gx_tasksN = (int64_t)p->T.tasksN.size();
+            std::vector<Task> gvt;
+            for (size_t c = 0; c < p->F.cods.size(); c++) codelet_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_a, 1, gvt);
+            p->T.tasks.insert(p->T.tasks.end(), gvt.begin(), gvt.end());
+            p->T.tasksN.insert(p->T.tasksN.end(), gvt.begin(), gvt.end());
             if (ddf_status s = upload_tasks(p, p->T)) return s;
         }
         return DDF_OK;
@@ -474,6 +512,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     p->sp_f.ops_per_lane = p->sp_a.ops_per_lane = o.ops_per_lane;
     p->sp_f.passes = p->sp_a.passes = o.rows_passes;
     p->sp_f.remap = p->sp_a.remap = o.xcd_remap < 0 ? 1 : o.xcd_remap;
+    p->sp_f.thin_tasks = p->sp_a.thin_tasks = o.thin_tasks < 0 ? SWPB : o.thin_tasks;
     p->fwd.resize(nmat);
     if (p->has_adj) p->adj.resize(nmat);
     p->mats.resize(nmat);
@@ -647,6 +686,7 @@ void ddf_opts_default(ddf_opts *o) {
     o->ops_per_lane = 4;
     o->rows_passes = 2;
     o->xcd_remap = -1;
+    o->thin_tasks = -1;
 }
 
 const char *ddf_version(void) { return "ddf-mi355x 0.1"; }
@@ -709,14 +749,15 @@ ddf_status ddf_spmv_v(ddf_plan_t p, const double *d_vals, const double *d_x, dou
     SpmvArgs a{};
     a.cods = p->F.d_cods;
     a.aux = p->F.d_aux;
-    a.tasks = p->F.d_tasks;
-    a.ntasks = (int32_t)p->F.tasks.size();
+    const bool many = nrhs > 1;
+    a.tasks = many ? p->F.d_tasksN : p->F.d_tasks;
+    a.ntasks = (int32_t)(many ? p->F.tasksN.size() : p->F.tasks.size());
     a.k = nrhs;
     a.remap = p->sp_f.remap;
     a.vals = d_vals;
     a.x = d_x;
     a.y = d_y;
-    HIPCHK(launch_spmv(a, false, kt_for(nrhs), s));
+    HIPCHK(launch_spmv(a, false, s));
     return DDF_OK;
 }
 
@@ -762,13 +803,16 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
                     overlap(d_gvals, p->nnz * 8, d_gx, p->n_cols * nrhs * 8)))
         return fail(DDF_E_ARG, "gvals overlaps another buffer");
     hipStream_t s = (hipStream_t)stream;
-    int64_t t0 = d_gx ? 0 : p->n_gx_tasks;
-    int64_t t1 = d_gvals ? (int64_t)p->T.tasks.size() : p->n_gx_tasks;
+    const bool many = nrhs > 1;
+    const int64_t ngx = many ? p->n_gx_tasksN : p->n_gx_tasks;
+    const int64_t nall = (int64_t)(many ? p->T.tasksN.size() : p->T.tasks.size());
+    int64_t t0 = d_gx ? 0 : ngx;
+    int64_t t1 = d_gvals ? nall : ngx;
     if (t1 <= t0) return DDF_OK;
     SpmvArgs a{};
     a.cods = p->T.d_cods;
     a.aux = p->T.d_aux;
-    a.tasks = p->T.d_tasks + t0;
+    a.tasks = (many ? p->T.d_tasksN : p->T.d_tasks) + t0;
     a.ntasks = (int32_t)(t1 - t0);
     a.k = nrhs;
     a.remap = p->sp_a.remap;
@@ -781,7 +825,7 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
     a.g = d_gy;
     a.x2 = d_x;
     a.gv = d_gvals;
-    HIPCHK(launch_spmv(a, true, kt_for(nrhs), s));
+    HIPCHK(launch_spmv(a, true, s));
     return DDF_OK;
 }
 
@@ -1078,6 +1122,8 @@ ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables
     o->n_tasks = (int64_t)D->tasks.size();
     o->n_groups = (int64_t)D->groups.size() / 8;
     o->lvl_len = (int64_t)D->lvl.size();
+    o->tasksN = reinterpret_cast<const int32_t *>(D->tasksN.data());
+    o->n_tasksN = (int64_t)D->tasksN.size();
     return DDF_OK;
 }
 
@@ -1089,15 +1135,16 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
     int64_t ck = p->batch ? p->vec_total : nc * nrhs;
     int64_t kf = p->batch ? 0 : nrhs;
     int64_t Fca = (int64_t)p->F.cods.size() * sizeof(DCod) + (int64_t)p->F.aux.size() * 4;
+    const bool many = !p->batch && nrhs > 1;
     int64_t ba = 0, bc = 0, fl = 0;
     switch (op) {
     case DDF_OP_SPMV:
-        ba = 8 * nnz + p->F.bytes() + 8 * ck + 8 * vk;
+        ba = 8 * nnz + p->F.launch_bytes(many) + 8 * ck + 8 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 8 * ck + 8 * vk;
         fl = 2 * nnz * nrhs;
         break;
     case DDF_OP_SPMV_ADJ:
-        ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 16 * vk + 16 * ck;
+        ba = 20 * nnz + (p->has_adj ? p->T.launch_bytes(many) : 0) + Fca + 16 * vk + 16 * ck;
         bc = 20 * nnz + 4 * (n + 1) + 8 * vk + 16 * ck;
         fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
         break;
@@ -1249,6 +1296,7 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
         int opl, ps, rm, thin;
     };
     std::vector<Cand> cands;
+    cands.push_back({target.ops_per_lane, target.passes, target.remap, target.thin_tasks}); // current first
     if (is_spmv) {
         for (int rm : {1, 0})
             for (int opl : {1, 2, 4, 8, 16})

@@ -11,6 +11,8 @@ import numpy as np
 FS0, FS1, FS2, FSEP, FRECT, FRUNS = 1, 2, 4, 8, 16, 32
 DOPS, DCONTIG, DXPTR, DRPTR = 64, 128, 256, 512
 TASK_FAST = 1 << 9
+TASK_STREAM = 1 << 10
+STREAM_ELEMS = 512
 LOOKAHEAD = 4
 F = {n: i for i, n in enumerate(["flags", "m", "nn", "row0", "row_step", "op0", "op_step", "col0", "sigma0",
                                  "sigma1", "rows_off", "ops_off", "cnt_off", "xt_off", "xp_off", "mat"])}
@@ -87,12 +89,34 @@ class Tables:
             if meta & TASK_FAST:
                 assert nops <= (LOOKAHEAD << lg)
             out.append((row, opst, nops, self.cols(c, i0, opst, nops)))
+        if meta & TASK_STREAM:
+            # the stream kernel's own indexing: contiguous values from op0 + i0b*nn, and for a
+            # full table contiguous columns from xt_off + i0b*nn
+            fl, nn = int(c[F["flags"]]), int(c[F["nn"]])
+            assert fl & FRECT and 1 <= nn and (i0e - i0b) * nn <= STREAM_ELEMS and not fl & DOPS
+            assert c[F["m"]] == 1 or c[F["op_step"]] == nn
+            mode = xmode(fl)
+            assert mode in (0, 1, 3)
+            ebase = int(c[F["op0"]]) + i0b * nn
+            for q, (row, opst, nops, cols) in enumerate(out):
+                i0 = i0b + q
+                assert opst == ebase + q * nn and row == (int(c[F["row0"]] + i0 * c[F["row_step"]]) if fl & FS0
+                                                          else self.a(c[F["rows_off"]] + i0))
+                for i1 in range(nn):
+                    if mode == 0:
+                        col = int(c[F["col0"]] + i0 * c[F["sigma0"]] + i1 * c[F["sigma1"]])
+                    elif mode == 1:
+                        col = int(c[F["col0"]] + i0 * c[F["sigma0"]]) + self.a(c[F["xt_off"]] + i1)
+                    else:
+                        col = self.a(c[F["xt_off"]] + i0b * nn + q * nn + i1)
+                    assert col == cols[i1]
         return c, meta, out
 
 
-def spmv(tabs, A, X, vals=None, perm=None, tasks=None):
-    """Y = A X replayed over SpMV tasks (values through perm for the transposed plan)."""
-    T = Tables(tabs)
+def spmv(tabs, A, X, vals=None, perm=None, tasks=None, many=False):
+    """Y = A X replayed over SpMV tasks (values through perm for the transposed plan); many
+    selects the task list of several right-hand sides."""
+    T = Tables(dict(tabs, tasks=tabs["tasksN"]) if many else tabs)
     v = A.values if vals is None else vals
     k = X.shape[1]
     Y = np.full((A.n_rows, k), np.nan)
@@ -114,10 +138,10 @@ def spmv(tabs, A, X, vals=None, perm=None, tasks=None):
     return Y
 
 
-def gv(tabs, fwd_tabs, A, G, X, t0):
+def gv(tabs, fwd_tabs, A, G, X, t0, many=False):
     """GV[e] = sum_r G[row, r] X[col, r] over phase-1 tasks (tasks of `tabs`, records and
     aux of the forward tables) from t0 on."""
-    T, TF = Tables(tabs), Tables(fwd_tabs)
+    T, TF = Tables(dict(tabs, tasks=tabs["tasksN"]) if many else tabs), Tables(fwd_tabs)
     out = np.full(int(A.row_ptr[-1]), np.nan)
     for t in range(t0, T.tasks.shape[0]):
         c, meta, rows = _rows_from(TF, T.tasks[t])

