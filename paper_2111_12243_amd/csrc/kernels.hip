@@ -181,15 +181,15 @@ __device__ void spmv_stream_task(const SpmvArgs &a, const Task &tk, int lane, do
     const int E = nrow * nn;
     const int ebase = c.op0 + a0 * nn;
     const int mode = xmode(c.flags);
-    // q = e / nn by multiply-high: exact for e, nn < 2^16
-    const unsigned magic = 0xFFFFFFFFu / (unsigned)nn + 1u;
+    // q = e / nn as (e * ceil(2^32 / nn)) >> 32: exact for e, nn < 2^16
+    const uint64_t magic = 0xFFFFFFFFull / (uint64_t)nn + 1ull;
     double prod[SJ];
 #pragma unroll
     for (int j = 0; j < SJ; j++) {
         const int e = lane + WAVE * j;
         prod[j] = 0.0;
         if (e < E) {
-            const int q = (int)__umulhi((unsigned)e, magic);
+            const int q = (int)(((uint64_t)e * magic) >> 32);
             const int i1 = e - q * nn;
             const int i0 = a0 + q;
             int col;

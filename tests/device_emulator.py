@@ -98,6 +98,9 @@ class Tables:
             mode = xmode(fl)
             assert mode in (0, 1, 3)
             ebase = int(c[F["op0"]]) + i0b * nn
+            magic = (0xFFFFFFFF // nn + 1) & 0xFFFFFFFFFFFFFFFF  # the kernel's 64-bit divisor
+            for e in range((i0e - i0b) * nn):
+                assert (e * magic) >> 32 == e // nn
             for q, (row, opst, nops, cols) in enumerate(out):
                 i0 = i0b + q
                 assert opst == ebase + q * nn and row == (int(c[F["row0"]] + i0 * c[F["row_step"]]) if fl & FS0

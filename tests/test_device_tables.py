@@ -114,3 +114,13 @@ def test_batch_schedule_per_matrix():
                           only_mat=b)
         GBr, GVr = O.sptrsv_adj(L, ref, m["G"])
         check_solve(L, m["G"], lam, GBr, transposed=True)
+
+
+def test_stream_tasks_single_entry_rows():
+    # rows of one entry (nn = 1) and the paper's worked example, transposed
+    rows = np.repeat(np.arange(3), 3)
+    A = I.csr_from_pairs(3, 8, rows, np.array([0, 2, 5, 1, 3, 6, 2, 4, 7]), np.arange(1.0, 10.0))
+    replay_spmv(A, k=1)
+    n = 100
+    eye = I.csr_from_pairs(n, n, np.arange(n), np.arange(n), np.arange(1.0, n + 1))
+    replay_spmv(eye, k=1)
