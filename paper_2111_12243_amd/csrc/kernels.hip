@@ -174,38 +174,38 @@ __device__ void spmv_gv_task(const SpmvArgs &a, const Task &tk, int lane) {
     }
 }
 
-template <bool VPERM>
-__device__ void spmv_stream_task(const SpmvArgs &a, const Task &tk, int lane, double *__restrict__ lds) {
-    const DCod c = load_cod(a.cods + tk.cod);
-    const int a0 = tk.i0b, nrow = tk.i0e - tk.i0b, nn = c.nn;
-    const int E = nrow * nn;
+template <int MODE, bool VPERM>
+__device__ __forceinline__ void spmv_stream_body(const SpmvArgs &a, const DCod &c, int a0, int nrow, int lane,
+                                                 double *__restrict__ lds) {
+    const int nn = c.nn, E = nrow * nn;
     const int ebase = c.op0 + a0 * nn;
-    const int mode = xmode(c.flags);
     // q = e / nn as (e * ceil(2^32 / nn)) >> 32: exact for e, nn < 2^16
     const uint64_t magic = 0xFFFFFFFFull / (uint64_t)nn + 1ull;
-    double prod[SJ];
+    // every load is unconditional (indices clamped into the task) so that a lane issues all
+    // of its value, column and then x loads back to back
+    int col[SJ];
+    double v[SJ];
 #pragma unroll
     for (int j = 0; j < SJ; j++) {
-        const int e = lane + WAVE * j;
-        prod[j] = 0.0;
-        if (e < E) {
-            const int q = (int)(((uint64_t)e * magic) >> 32);
-            const int i1 = e - q * nn;
-            const int i0 = a0 + q;
-            int col;
-            if (mode == XM_STRIDED)
-                col = c.col0 + i0 * c.sigma0 + i1 * c.sigma1;
-            else if (mode == XM_SHARED)
-                col = c.col0 + i0 * c.sigma0 + a.aux[c.xt_off + i1];
-            else
-                col = a.aux[c.xt_off + a0 * nn + e];
-            prod[j] = val_at<VPERM>(a, ebase + e) * a.x[col];
-        }
+        const int e = min(lane + WAVE * j, E - 1);
+        const int q = (int)(((uint64_t)e * magic) >> 32);
+        const int i1 = e - q * nn;
+        const int i0 = a0 + q;
+        if constexpr (MODE == XM_STRIDED)
+            col[j] = c.col0 + i0 * c.sigma0 + i1 * c.sigma1;
+        else if constexpr (MODE == XM_SHARED)
+            col[j] = c.col0 + i0 * c.sigma0 + a.aux[c.xt_off + i1];
+        else
+            col[j] = a.aux[c.xt_off + a0 * nn + e];
+        v[j] = val_at<VPERM>(a, ebase + e);
     }
+    double xv[SJ];
+#pragma unroll
+    for (int j = 0; j < SJ; j++) xv[j] = a.x[col[j]];
 #pragma unroll
     for (int j = 0; j < SJ; j++) {
         const int e = lane + WAVE * j;
-        if (e < E) lds[e] = prod[j];
+        if (e < E) lds[e] = v[j] * xv[j];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -218,6 +218,18 @@ __device__ void spmv_stream_task(const SpmvArgs &a, const Task &tk, int lane, do
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool VPERM>
+__device__ void spmv_stream_task(const SpmvArgs &a, const Task &tk, int lane, double *__restrict__ lds) {
+    const DCod c = load_cod(a.cods + tk.cod);
+    const int mode = xmode(c.flags);
+    if (mode == XM_STRIDED)
+        spmv_stream_body<XM_STRIDED, VPERM>(a, c, tk.i0b, tk.i0e - tk.i0b, lane, lds);
+    else if (mode == XM_SHARED)
+        spmv_stream_body<XM_SHARED, VPERM>(a, c, tk.i0b, tk.i0e - tk.i0b, lane, lds);
+    else
+        spmv_stream_body<XM_FULL, VPERM>(a, c, tk.i0b, tk.i0e - tk.i0b, lane, lds);
 }
 
 template <bool VPERM>
@@ -255,21 +267,53 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
 }
 
 // several right-hand sides: KR lanes per row, lane r owns right-hand sides r, r + KR, ...
-template <int KR, bool VPERM>
-__global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
-    if (t >= a.ntasks) return;
-    const Task tk = a.tasks[t];
-    if ((tk.meta >> 8) & 1) {
-        spmv_gv_task(a, tk, lane);
-        return;
+constexpr int RU = 4; // ops per unrolled chunk of a rectangular row
+
+template <int KR, int MODE, bool VPERM>
+__device__ __forceinline__ void spmvN_rect(const SpmvArgs &a, const DCod &c, const Task &tk, int lane) {
+    constexpr int P = WAVE / KR;
+    const int slot = lane / KR, r = lane % KR;
+    const int k = a.k, nn = c.nn;
+    for (int base = tk.i0b; base < tk.i0e; base += P) {
+        const int i0 = min(base + slot, tk.i0e - 1);
+        const bool active = base + slot < tk.i0e;
+        const int row = row_of(c, a.aux, i0);
+        const int opst = c.op0 + i0 * c.op_step;
+        const int cbase = (MODE == XM_FULL) ? c.xt_off + i0 * nn : c.col0 + i0 * c.sigma0;
+        for (int r0 = 0; r0 < k; r0 += KR) {
+            const int rr = min(r0 + r, k - 1);
+            double acc = 0.0;
+            for (int i1 = 0; i1 < nn; i1 += RU) {
+                int col[RU];
+                double v[RU], xv[RU];
+#pragma unroll
+                for (int u = 0; u < RU; u++) {
+                    const int j = min(i1 + u, nn - 1);
+                    if constexpr (MODE == XM_STRIDED)
+                        col[u] = cbase + j * c.sigma1;
+                    else if constexpr (MODE == XM_SHARED)
+                        col[u] = cbase + a.aux[c.xt_off + j];
+                    else
+                        col[u] = a.aux[cbase + j];
+                    v[u] = val_at<VPERM>(a, opst + j);
+                }
+#pragma unroll
+                for (int u = 0; u < RU; u++) xv[u] = a.x[(int64_t)col[u] * k + rr];
+#pragma unroll
+                for (int u = 0; u < RU; u++)
+                    if (i1 + u < nn) acc += v[u] * xv[u];
+            }
+            if (active && r0 + r < k) a.y[(int64_t)row * k + r0 + r] = acc;
+        }
     }
-    const DCod c = load_cod(a.cods + tk.cod);
-    const int mode = xmode(c.flags);
+}
+
+template <int KR, bool VPERM>
+__device__ __forceinline__ void spmvN_walk(const SpmvArgs &a, const DCod &c, const Task &tk, int lane) {
     constexpr int P = WAVE / KR;
     const int slot = lane / KR, r = lane % KR;
     const int k = a.k;
+    const int mode = xmode(c.flags);
     for (int base = tk.i0b; base < tk.i0e; base += P) {
         const int i0 = base + slot;
         if (i0 >= tk.i0e) break;
@@ -283,6 +327,29 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
             a.y[(int64_t)ri.row * k + rr] = acc;
         }
     }
+}
+
+template <int KR, bool VPERM>
+__global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
+    if (t >= a.ntasks) return;
+    const Task tk = a.tasks[t];
+    if ((tk.meta >> 8) & 1) {
+        spmv_gv_task(a, tk, lane);
+        return;
+    }
+    const DCod c = load_cod(a.cods + tk.cod);
+    const int mode = xmode(c.flags);
+    const bool rect = (c.flags & FRECT) && !(c.flags & DOPS) && c.nn > 0;
+    if (rect && mode == XM_STRIDED)
+        spmvN_rect<KR, XM_STRIDED, VPERM>(a, c, tk, lane);
+    else if (rect && mode == XM_SHARED)
+        spmvN_rect<KR, XM_SHARED, VPERM>(a, c, tk, lane);
+    else if (rect && mode == XM_FULL)
+        spmvN_rect<KR, XM_FULL, VPERM>(a, c, tk, lane);
+    else
+        spmvN_walk<KR, VPERM>(a, c, tk, lane);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -330,12 +397,26 @@ __device__ void solve_task(const SolveArgs &a, int t, int lane) {
         for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
             const RowInfo ri = row_info(c, a.aux2, i0);
             const int64_t rb = (int64_t)ri.row * k;
-            walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
-                const double *__restrict__ xr = xf + (int64_t)col * k;
-                double s = 0.0;
-                for (int r = 0; r < k; r++) s += xload<COH>(lam + rb + r) * xr[r];
-                gv[e] = -s;
-            });
+            if (k <= KT) {
+                double lr[KT];
+#pragma unroll
+                for (int r = 0; r < KT; r++) lr[r] = r < k ? xload<COH>(lam + rb + r) : 0.0;
+                walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
+                    const double *__restrict__ xr = xf + (int64_t)col * k;
+                    double s = 0.0;
+#pragma unroll
+                    for (int r = 0; r < KT; r++)
+                        if (r < k) s += lr[r] * xr[r];
+                    gv[e] = -s;
+                });
+            } else {
+                walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
+                    const double *__restrict__ xr = xf + (int64_t)col * k;
+                    double s = 0.0;
+                    for (int r = 0; r < k; r++) s += xload<COH>(lam + rb + r) * xr[r];
+                    gv[e] = -s;
+                });
+            }
             if (g == 0) {
                 double s = 0.0;
                 for (int r = 0; r < k; r++) s += xload<COH>(lam + rb + r) * xf[rb + r];
@@ -547,16 +628,14 @@ __global__ __launch_bounds__(WAVE *SWPB) void k_solve(SolveArgs a) {
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         } else {
-            // one agent-scope acquire after the wait, cached loads and stores, one release
-            // before the block signals
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             int t = gr.t0 + wave;
             if (wide.task >= 0) {
-                pre_compute<KT, ADJ, false>(a, wide, lane);
+                pre_compute<KT, ADJ, true>(a, wide, lane);
                 t += SWPB;
             }
-            for (; t < gr.t1; t += SWPB) solve_task<KT, ADJ, false>(a, t, lane);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (; t < gr.t1; t += SWPB) solve_task<KT, ADJ, true>(a, t, lane);
+            // this wave's device-scope stores are complete before the block signals
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         }
         __syncthreads();
         if (wave == 0)
