@@ -69,8 +69,8 @@ typedef struct {
                               next power of two of row length / this); 0 = default 4       */
     int32_t rows_passes;   /* schedule: row passes per wavefront task; 0 = default 2       */
     int32_t xcd_remap;     /* schedule: give each XCD a contiguous block range; -1 default */
-    int32_t thin_tasks;    /* schedule (solve): runs of levels with at most this many tasks
-                              are solved inside one block; 0 = never; -1 = default 16      */
+    int32_t solve_blocks;  /* schedule (solve): 256-thread blocks of the persistent kernel;
+                              0 = every block the device keeps resident                     */
 } ddf_opts;
 
 typedef struct {
@@ -240,14 +240,13 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
  *                        rows_off, ops_off, cnt_off, xt_off, xp_off, mat
  *   tasks  [n_tasks][4]  codelet, first row, end row, meta (log2 lanes per row | phase << 8 |
  *                        look-ahead eligible << 9 | streamed << 10); for SpMV the list used
- *                        with one right-hand side
- *   tasksN [n_tasksN][4] SpMV: the list used with several right-hand sides
- *   groups [n_groups][8] type (0 wide, 1 thin), first task, end task, tasks to wait for,
- *                        matrix, level-table offset, levels, 0
- *   lvl    [lvl_len]     task boundaries of the levels of thin groups */
+ *                        with one right-hand side; for the solve in ticket order
+ *   sync   [n_tasks][4]  solve: level counter to wait on (-1: none), task count it must
+ *                        reach, level counter to signal (-1: none), 0
+ *   tasksN [n_tasksN][4] SpMV: the list used with several right-hand sides */
 typedef struct {
-    const int32_t *cods, *aux, *tasks, *groups, *lvl, *tasksN;
-    int64_t n_cods, aux_len, n_tasks, n_groups, lvl_len, n_tasksN;
+    const int32_t *cods, *aux, *tasks, *sync, *tasksN;
+    int64_t n_cods, aux_len, n_tasks, n_counters, n_tasksN;
 } ddf_device_tables_t;
 ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
 

@@ -71,9 +71,8 @@ struct SchedParams {
     int32_t ops_per_lane = 4;
     int32_t passes = 2;
     int32_t remap = 1;
-    int32_t blocks = 0;      // solve: persistent grid (0 = one per CU)
-    int32_t thin_tasks = 16; // solve: levels with at most this many tasks run in THIN groups
-    int32_t backoff = 16;    // solve: longest sleep between polls (units of 64 cycles)
+    int32_t blocks = 0;   // solve: persistent grid in 256-thread blocks (0 = all resident)
+    int32_t backoff = 16; // solve: longest sleep between polls (units of 64 cycles)
 };
 
 // Device-resident tables of one plan pass (forward or adjoint).
@@ -82,23 +81,21 @@ struct DevTables {
     std::vector<int32_t> aux;          // canonical aux followed by device supplements
     std::vector<Task> tasks;           // solve; SpMV with one right-hand side
     std::vector<Task> tasksN;          // SpMV with several right-hand sides
-    std::vector<int32_t> groups;       // solve: 8 int32 per group (see kernels.hpp Group)
-    std::vector<int32_t> lvl;          // solve: level boundaries of THIN groups
+    std::vector<int32_t> sync;         // solve: 4 int32 per task (wait counter, count, signal counter)
+    int64_t n_counters = 0;            // solve: level counters the schedule uses
     DCod *d_cods = nullptr;
     int32_t *d_aux = nullptr;
     Task *d_tasks = nullptr;
     Task *d_tasksN = nullptr;
-    int32_t *d_groups = nullptr;
-    int32_t *d_lvl = nullptr;
+    int32_t *d_sync = nullptr;
     int64_t bytes() const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
-               (int64_t)tasks.size() * sizeof(Task) + (int64_t)groups.size() * 4 + (int64_t)lvl.size() * 4;
+               (int64_t)tasks.size() * sizeof(Task) + (int64_t)sync.size() * 4;
     }
     // bytes a launch reads: records and aux (upper bound) plus its own task list
     int64_t launch_bytes(bool many_rhs) const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
-               (int64_t)(many_rhs ? tasksN.size() : tasks.size()) * sizeof(Task) + (int64_t)groups.size() * 4 +
-               (int64_t)lvl.size() * 4;
+               (int64_t)(many_rhs ? tasksN.size() : tasks.size()) * sizeof(Task) + (int64_t)sync.size() * 4;
     }
 };
 

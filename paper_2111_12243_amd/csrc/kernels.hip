@@ -560,92 +560,63 @@ __device__ __forceinline__ void pre_compute(const SolveArgs &a, const Pre &p, in
     }
 }
 
+// Each wave takes tasks in ticket order.  A task of level l signals its level's counter
+// when done and waits, before computing, until level l-1's counter holds all of that
+// level's tasks; since a level only starts once the previous one is complete, that implies
+// every earlier level is complete.  Tickets follow the level order, so every task a wave
+// waits on is held by a running wave.  Counters live on separate 128-byte lines so the
+// waits on different levels do not contend; what a task reads that does not depend on the
+// solution is loaded before it waits.
 template <int KT, bool ADJ>
-__global__ __launch_bounds__(WAVE *SWPB) void k_solve(SolveArgs a) {
-    __shared__ int s_gi;
+__global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
     const int lane = threadIdx.x % WAVE;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    unsigned *__restrict__ done = a.ctr + 2;
     // lane 0 carries the increments; every lane issues the atomics so that no branch
     // depends on the lane id (results are broadcast with readfirstlane)
     const unsigned one = lane == 0 ? 1u : 0u;
+    unsigned *__restrict__ cnt = a.ctr + 2 * CTR_STRIDE;
     for (;;) {
-        if (wave == 0) s_gi = __builtin_amdgcn_readfirstlane(
-                           (int)__hip_atomic_fetch_add(a.ctr, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        __syncthreads();
-        const int gi = __builtin_amdgcn_readfirstlane(s_gi);
-        __syncthreads();
-        if (gi >= a.ngroups) break;
-        const Group gr = a.groups[gi];
-        // a WIDE group loads everything its first task needs that does not depend on the
-        // solution before it waits, so the loads overlap the levels still running
-        Pre wide;
-        wide.task = -1;
-        const bool is_wide = gr.type != GROUP_THIN;
-        if (is_wide) {
-            const int t = gr.t0 + wave;
-            if (t < gr.t1 && ((a.tasks[t].meta >> 8) & 1) == 0) pre_load<ADJ>(a, t, lane, wide);
-        }
-        if (wave == 0 && gr.need > 0) {
-            // bounded wait with backoff; past the spin limit, or once another block has
+        const int t = __builtin_amdgcn_readfirstlane(
+            (int)__hip_atomic_fetch_add(a.ctr, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (t >= a.ntasks) break;
+        const int4 sy = a.sync[t];
+        Pre pre;
+        pre.task = -1;
+        if (((a.tasks[t].meta >> 8) & 1) == 0) pre_load<ADJ>(a, t, lane, pre);
+        if (sy.x >= 0) {
+            // bounded wait with backoff; past the spin limit, or once another wave has
             // tripped the error flag, stop waiting (the results are then reported invalid)
             int64_t spins = 0;
             int back = 1;
             for (;;) {
-                const int d = __builtin_amdgcn_readfirstlane((int)cload_u(done + gr.mat));
-                if (d >= gr.need) break;
+                const int d = __builtin_amdgcn_readfirstlane((int)cload_u(cnt + (int64_t)sy.x * CTR_STRIDE));
+                if (d >= sy.y) break;
                 for (int z = 0; z < back; z++) __builtin_amdgcn_s_sleep(1);
                 if (back < a.backoff_max) back <<= 1;
                 spins += back;
                 bool trip = spins > a.spin_limit;
                 if ((spins & 1023) < back)
-                    trip = trip || __builtin_amdgcn_readfirstlane((int)cload_u(a.ctr + 1)) != 0;
+                    trip = trip || __builtin_amdgcn_readfirstlane((int)cload_u(a.ctr + CTR_STRIDE)) != 0;
                 if (trip) {
-                    __hip_atomic_store(a.ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(a.ctr + CTR_STRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
         }
-        __syncthreads();
-        if (gr.type == GROUP_THIN) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            Pre cur, nxt;
-            int lb = a.lvl[gr.lv_off], le = a.lvl[gr.lv_off + 1];
-            pre_load<ADJ>(a, lb + wave < le ? lb + wave : -1, lane, cur);
-            for (int l = 0; l < gr.nlv; l++) {
-                int nb = 0, ne = 0;
-                if (l + 1 < gr.nlv) {
-                    nb = a.lvl[gr.lv_off + l + 1];
-                    ne = a.lvl[gr.lv_off + l + 2];
-                }
-                pre_load<ADJ>(a, nb + wave < ne ? nb + wave : -1, lane, nxt);
-                pre_compute<KT, ADJ, false>(a, cur, lane);
-                for (int t = lb + wave + SWPB; t < le; t += SWPB) solve_task<KT, ADJ, false>(a, t, lane);
-                __syncthreads();
-                cur = nxt;
-                lb = nb;
-                le = ne;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        } else {
-            int t = gr.t0 + wave;
-            if (wide.task >= 0) {
-                pre_compute<KT, ADJ, true>(a, wide, lane);
-                t += SWPB;
-            }
-            for (; t < gr.t1; t += SWPB) solve_task<KT, ADJ, true>(a, t, lane);
-            // this wave's device-scope stores are complete before the block signals
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        }
-        __syncthreads();
-        if (wave == 0)
-            __hip_atomic_fetch_add(done + gr.mat, lane == 0 ? (unsigned)(gr.t1 - gr.t0) : 0u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        asm volatile("" ::: "memory");
+        if (pre.task >= 0)
+            pre_compute<KT, ADJ, true>(a, pre, lane);
+        else
+            solve_task<KT, ADJ, true>(a, t, lane);
+        // this wave's device-scope stores are complete before its level's counter moves
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (sy.z >= 0)
+            __hip_atomic_fetch_add(cnt + (int64_t)sy.z * CTR_STRIDE, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-__global__ void k_reset(unsigned *p, int n) {
-    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) p[i] = 0u;
+__global__ void k_reset(unsigned *p, int64_t n) {
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < n; i += (int64_t)blockDim.x * gridDim.x)
+        p[i] = 0u;
 }
 
 __global__ void k_fill(double *p, int64_t n, double v) {
@@ -772,10 +743,11 @@ __global__ __launch_bounds__(WAVE *WPB) void k_csr_gv(PlainArgs a) {
 int g_solve_blocks = 0; // resident blocks of the persistent kernel on the whole device
 int g_num_cu = 0;
 
-int solve_grid(int ngroups, int want) {
-    int cap = g_solve_blocks > 0 ? g_solve_blocks : 256;
+int solve_grid(int ntasks, int want) {
+    int cap = g_solve_blocks > 0 ? g_solve_blocks : 1024;
     if (want > 0 && want < cap) cap = want;
-    return ngroups < cap ? (ngroups > 0 ? ngroups : 1) : cap;
+    const int need = (ntasks + WPB - 1) / WPB;
+    return need < cap ? (need > 0 ? need : 1) : cap;
 }
 
 } // namespace
@@ -787,7 +759,7 @@ hipError_t init_device_info() {
     int dev = 0, ncu = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<8, true>, WAVE * SWPB, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<8, true>, WAVE * WPB, 0);
     if (e != hipSuccess) return e;
     g_num_cu = ncu > 0 ? ncu : 1;
     g_solve_blocks = (nb > 0 ? nb : 1) * g_num_cu;
@@ -820,8 +792,11 @@ hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_reset(unsigned *ctr, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, ctr, n);
+hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s) {
+    int64_t nb = (n + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_reset, dim3((unsigned)nb), dim3(256), 0, s, ctr, n);
     return hipGetLastError();
 }
 
@@ -836,11 +811,11 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
 int num_cu() { return g_num_cu > 0 ? g_num_cu : 256; }
 
 hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s) {
-    if (a.ngroups == 0) return hipSuccess;
+    if (a.ntasks == 0) return hipSuccess;
     int nb;
 #define DDF_SOLVE_CASE(K, A)                                                                        \
-    nb = solve_grid(a.ngroups, blocks);                                                             \
-    hipLaunchKernelGGL((k_solve<K, A>), dim3(nb), dim3(WAVE * SWPB), 0, s, a);                      \
+    nb = solve_grid(a.ntasks, blocks);                                                              \
+    hipLaunchKernelGGL((k_solve<K, A>), dim3(nb), dim3(WAVE * WPB), 0, s, a);                       \
     break;
     switch (kt * 2 + (adj ? 1 : 0)) {
     case 2: DDF_SOLVE_CASE(1, false)

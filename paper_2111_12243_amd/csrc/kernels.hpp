@@ -26,19 +26,11 @@ struct SpmvArgs {
     double *gv;
 };
 
-constexpr int SWPB = 16;     // waves per block of the persistent solve (1024 threads)
-constexpr int LOOKAHEAD = 4; // elements per lane a thin-range wave loads ahead
-enum : int32_t { GROUP_WIDE = 0, GROUP_THIN = 1 };
+constexpr int LOOKAHEAD = 4;   // elements per lane a solve task loads before its wait
+constexpr int CTR_STRIDE = 32; // uint32 per counter line (128 bytes)
 enum : int32_t { TASK_FAST = 1 << 9,     // solve: thin-range task whose rows fit the look-ahead registers
                  TASK_STREAM = 1 << 10 }; // SpMV: one-RHS task streamed element by element
 constexpr int STREAM_ELEMS = 64 * 8;     // elements of a stream task (64 lanes x 8)
-
-// A block's unit of work in the persistent solve: tasks [t0, t1) of matrix `mat`, started
-// once `need` tasks of that matrix are done.  THIN groups span nlv levels whose task
-// boundaries are lvl[lv_off .. lv_off + nlv].
-struct Group {
-    int32_t type, t0, t1, need, mat, lv_off, nlv, pad;
-};
 
 struct SolveArgs {
     const DCod *cods;  // phase 0: the solve's plan
@@ -46,9 +38,8 @@ struct SolveArgs {
     const DCod *cods2; // phase 1 (adjoint): L's forward plan for the GV pass
     const int32_t *aux2;
     const Task *tasks;
-    const Group *groups;
-    int32_t ngroups;
-    const int32_t *lvl;
+    const int4 *sync; // per task: counter to wait on (-1 none), count to wait for, counter to signal
+    int32_t ntasks;
     int32_t backoff_max;
     const MatInfo *mats;
     const double *vals;
@@ -57,7 +48,7 @@ struct SolveArgs {
     double *x;           // solution (adjoint: lambda)
     const double *xf;    // adjoint: forward solution (for GV)
     double *gv;          // adjoint: value gradient
-    unsigned *ctr;       // [0] ticket, [1] error flag, [2 + mat] tasks done per matrix
+    unsigned *ctr;       // lines of CTR_STRIDE: ticket, error flag, then one counter per level
     int64_t spin_limit;
     int32_t k_override; // > 0: right-hand sides of a single-matrix call
 };
@@ -84,7 +75,7 @@ hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s);
 int kr_for(int k);
 hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s);
 int num_cu();
-hipError_t launch_reset(unsigned *ctr, int n, hipStream_t s);
+hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
 

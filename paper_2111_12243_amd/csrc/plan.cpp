@@ -40,8 +40,9 @@ struct ddf_plan_s {
     int64_t n_rows = 0, n_cols = 0, nnz = 0, vec_total = 0;
     SchedParams sp_f, sp_a;
     DevTables F, T, Fpm;
-    std::vector<int64_t> pm_group_ptr; // per-matrix ranges of Fpm.groups
-    int64_t n_solve_groups_adj = 0;    // adjoint: groups before the GV pass
+    std::vector<int64_t> pm_task_ptr; // per-matrix ranges of Fpm.tasks
+    int64_t n_solve_tasks_adj = 0;    // adjoint: tasks before the GV pass
+    int64_t ctr_words = 0;            // allocated counter words
     int64_t n_gx_tasks = 0;           // SpMV adjoint: tasks before the GV pass (one RHS)
     int64_t n_gx_tasksN = 0;          // same, several right-hand sides
     double *d_vals = nullptr;
@@ -49,7 +50,6 @@ struct ddf_plan_s {
     int32_t *d_rows = nullptr, *d_rrows = nullptr;
     MatInfo *d_mats = nullptr;
     unsigned *d_ctr = nullptr;
-    int nctr = 0;
     int64_t spin_limit = int64_t(1) << 26;
     double inspect_seconds = 0;
     uint64_t hash = 0;
@@ -283,83 +283,53 @@ void spmvN_tasks(const DCod &d, int32_t cod_index, const SchedParams &sp, std::v
     for (int32_t a = 0; a < d.m; a += rows) out.push_back({cod_index, a, std::min(d.m, a + rows), 0});
 }
 
-// Persistent-solve schedule of several matrices: per matrix and level, the level's tasks;
-// runs of consecutive levels with at most thin_tasks tasks become THIN groups, other levels
-// are cut into WIDE groups of at most SWPB tasks.  Groups are ordered by (first level,
-// matrix), so a group only ever waits on earlier groups.  Returns each matrix's task count.
-std::vector<int64_t> build_solve(const DevTables &D, const std::vector<int64_t> &cod_begin,
-                                 const std::vector<std::vector<int32_t>> &levels, const SchedParams &sp,
-                                 std::vector<Task> &tasks, std::vector<int32_t> &groups, std::vector<int32_t> &lvl,
-                                 int32_t mat_base = 0) {
+// Persistent-solve schedule of several matrices.  Tasks are ordered by (level, matrix);
+// every level of every matrix gets a completion counter (ids from counter_base on).  A task
+// of level l > 0 waits until counter (b, l-1) reaches that level's task count and signals
+// counter (b, l).  Returns per matrix the (counter id, task count) of its last level.
+std::vector<std::pair<int64_t, int64_t>> build_solve(const DevTables &D, const std::vector<int64_t> &cod_begin,
+                                                     const std::vector<std::vector<int32_t>> &levels,
+                                                     const SchedParams &sp, std::vector<Task> &tasks,
+                                                     std::vector<int32_t> &sync, int64_t &counter_base) {
     const int nm = (int)cod_begin.size() - 1;
     std::vector<std::vector<std::vector<Task>>> per(nm);
+    std::vector<int64_t> base(nm);
+    int32_t maxl = 0;
     for (int b = 0; b < nm; b++) {
         int32_t nl = 0;
         for (int32_t l : levels[b]) nl = std::max(nl, l + 1);
         per[b].resize(nl);
+        maxl = std::max(maxl, nl);
         for (int64_t c = cod_begin[b]; c < cod_begin[b + 1]; c++)
             codelet_tasks(D.cods[c], D.aux, (int32_t)c, sp, 0, per[b][levels[b][c - cod_begin[b]]]);
+        base[b] = counter_base;
+        counter_base += nl;
     }
-    struct Item {
-        int32_t l0, mat, type, l1; // levels [l0, l1) for THIN; one level and a slice for WIDE
-        int32_t s0, s1;
-    };
-    std::vector<Item> items;
-    std::vector<std::vector<int64_t>> pre(nm);
-    std::vector<int64_t> total(nm, 0);
-    for (int b = 0; b < nm; b++) {
-        const int32_t nl = (int32_t)per[b].size();
-        pre[b].assign(nl + 1, 0);
-        for (int32_t l = 0; l < nl; l++) pre[b][l + 1] = pre[b][l] + (int64_t)per[b][l].size();
-        total[b] = pre[b][nl];
-        int32_t l = 0;
-        while (l < nl) {
-            if ((int64_t)per[b][l].size() <= sp.thin_tasks) {
-                int32_t l2 = l;
-                while (l2 < nl && (int64_t)per[b][l2].size() <= sp.thin_tasks) l2++;
-                items.push_back({l, b, GROUP_THIN, l2, 0, 0});
-                l = l2;
-            } else {
-                const int32_t n = (int32_t)per[b][l].size();
-                for (int32_t s = 0; s < n; s += SWPB) items.push_back({l, b, GROUP_WIDE, l + 1, s, std::min(n, s + SWPB)});
-                l++;
+    for (int32_t l = 0; l < maxl; l++)
+        for (int b = 0; b < nm; b++) {
+            if (l >= (int32_t)per[b].size()) continue;
+            for (const Task &t : per[b][l]) {
+                tasks.push_back(t);
+                const int32_t sy[4] = {l > 0 ? (int32_t)(base[b] + l - 1) : -1,
+                                       l > 0 ? (int32_t)per[b][l - 1].size() : 0, (int32_t)(base[b] + l), 0};
+                sync.insert(sync.end(), sy, sy + 4);
             }
         }
-    }
-    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) {
-        return x.l0 != y.l0 ? x.l0 < y.l0 : x.mat < y.mat;
-    });
-    for (const Item &it : items) {
-        const int32_t t0 = (int32_t)tasks.size();
-        int32_t lv_off = 0, nlv = 0;
-        if (it.type == GROUP_THIN) {
-            lv_off = (int32_t)lvl.size();
-            nlv = it.l1 - it.l0;
-            for (int32_t l = it.l0; l < it.l1; l++) {
-                lvl.push_back((int32_t)tasks.size());
-                tasks.insert(tasks.end(), per[it.mat][l].begin(), per[it.mat][l].end());
-            }
-            lvl.push_back((int32_t)tasks.size());
-        } else {
-            tasks.insert(tasks.end(), per[it.mat][it.l0].begin() + it.s0, per[it.mat][it.l0].begin() + it.s1);
-        }
-        const int32_t g[8] = {it.type, t0, (int32_t)tasks.size(), (int32_t)pre[it.mat][it.l0], mat_base + it.mat, lv_off,
-                              nlv, 0};
-        groups.insert(groups.end(), g, g + 8);
-    }
-    return total;
+    std::vector<std::pair<int64_t, int64_t>> last(nm, {-1, 0});
+    for (int b = 0; b < nm; b++)
+        if (!per[b].empty()) last[b] = {base[b] + (int64_t)per[b].size() - 1, (int64_t)per[b].back().size()};
+    return last;
 }
 
-// WIDE groups (after everything else) over phase-1 tasks of matrix b, waiting for `need`.
-void append_gv_groups(const DevTables &F, int64_t c0, int64_t c1, int32_t mat, int64_t need, const SchedParams &sp,
-                      std::vector<Task> &tasks, std::vector<int32_t> &groups) {
+// GV tasks (phase 1) of matrix b's forward codelets, run once its last level is complete.
+void append_gv(const DevTables &F, int64_t c0, int64_t c1, std::pair<int64_t, int64_t> last, const SchedParams &sp,
+               std::vector<Task> &tasks, std::vector<int32_t> &sync) {
     std::vector<Task> tk;
     for (int64_t c = c0; c < c1; c++) codelet_tasks(F.cods[c], F.aux, (int32_t)c, sp, 1, tk);
-    for (size_t s = 0; s < tk.size(); s += SWPB) {
-        const int32_t t0 = (int32_t)tasks.size();
-        tasks.insert(tasks.end(), tk.begin() + s, tk.begin() + std::min(tk.size(), s + SWPB));
-        const int32_t g[8] = {GROUP_WIDE, t0, (int32_t)tasks.size(), (int32_t)need, mat, 0, 0, 0};
-        groups.insert(groups.end(), g, g + 8);
+    for (const Task &t : tk) {
+        tasks.push_back(t);
+        const int32_t sy[4] = {(int32_t)last.first, (int32_t)last.second, -1, 0};
+        sync.insert(sync.end(), sy, sy + 4);
     }
 }
 
@@ -375,17 +345,29 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     // schedule buffers are replaced when the schedule changes (autotune)
     drop_alloc(p, D.d_tasks);
     drop_alloc(p, D.d_tasksN);
-    drop_alloc(p, D.d_groups);
-    drop_alloc(p, D.d_lvl);
+    drop_alloc(p, D.d_sync);
     D.d_tasks = nullptr;
     D.d_tasksN = nullptr;
-    D.d_groups = nullptr;
-    D.d_lvl = nullptr;
+    D.d_sync = nullptr;
     ddf_status s = upload(p, &D.d_tasks, D.tasks.data(), D.tasks.size());
     if (!s && !D.tasksN.empty()) s = upload(p, &D.d_tasksN, D.tasksN.data(), D.tasksN.size());
-    if (!s && !D.groups.empty()) s = upload(p, &D.d_groups, D.groups.data(), D.groups.size());
-    if (!s && !D.lvl.empty()) s = upload(p, &D.d_lvl, D.lvl.data(), D.lvl.size());
+    if (!s && !D.sync.empty()) s = upload(p, &D.d_sync, D.sync.data(), D.sync.size());
     return s;
+}
+
+// Counter lines of the persistent solve: ticket, error flag, one per level of the largest
+// schedule.  Grown (never shrunk) when a schedule needs more.
+ddf_status ensure_counters(ddf_plan_t p) {
+    if (p->host_only || p->kind == DDF_SPMV) return DDF_OK;
+    const int64_t need = (2 + std::max({p->F.n_counters, p->T.n_counters, p->Fpm.n_counters})) * CTR_STRIDE;
+    if (need <= p->ctr_words) return DDF_OK;
+    drop_alloc(p, p->d_ctr);
+    p->d_ctr = nullptr;
+    if (ddf_status s = dalloc(p, (void **)&p->d_ctr, need * sizeof(unsigned))) return s;
+    if (hipError_t e = hipMemset(p->d_ctr, 0, need * sizeof(unsigned)))
+        return fail(DDF_E_HIP, std::string("hipMemset: ") + hipGetErrorString(e));
+    p->ctr_words = need;
+    return DDF_OK;
 }
 
 std::vector<int32_t> codelet_levels(const Canon &c) {
@@ -429,21 +411,23 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
     for (int b = 0; b < p->nmat; b++) lv[b] = codelet_levels(p->fwd[b]);
     if (fwd) {
         p->F.tasks.clear();
-        p->F.groups.clear();
-        p->F.lvl.clear();
-        build_solve(p->F, cb, lv, p->sp_f, p->F.tasks, p->F.groups, p->F.lvl);
+        p->F.sync.clear();
+        p->F.n_counters = 0;
+        build_solve(p->F, cb, lv, p->sp_f, p->F.tasks, p->F.sync, p->F.n_counters);
         if (ddf_status s = upload_tasks(p, p->F)) return s;
         if (p->batch) {
             // per-matrix schedules for the one-launch-per-matrix comparator
             p->Fpm.tasks.clear();
-            p->Fpm.groups.clear();
-            p->Fpm.lvl.clear();
-            p->pm_group_ptr.assign(1, 0);
+            p->Fpm.sync.clear();
+            p->Fpm.n_counters = 0;
+            p->pm_task_ptr.assign(1, 0);
             for (int b = 0; b < p->nmat; b++) {
                 std::vector<int64_t> one = {cb[b], cb[b + 1]};
                 std::vector<std::vector<int32_t>> l1 = {lv[b]};
-                build_solve(p->F, one, l1, p->sp_f, p->Fpm.tasks, p->Fpm.groups, p->Fpm.lvl, b);
-                p->pm_group_ptr.push_back((int64_t)p->Fpm.groups.size() / 8);
+                int64_t nc = 0; // every per-matrix launch resets and reuses counters from 0
+                build_solve(p->F, one, l1, p->sp_f, p->Fpm.tasks, p->Fpm.sync, nc);
+                p->Fpm.n_counters = std::max(p->Fpm.n_counters, nc);
+                p->pm_task_ptr.push_back((int64_t)p->Fpm.tasks.size());
             }
             if (ddf_status s = upload_tasks(p, p->Fpm)) return s;
         }
@@ -456,14 +440,14 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
             lva[b] = codelet_levels(p->adj[b]);
         }
         p->T.tasks.clear();
-        p->T.groups.clear();
-        p->T.lvl.clear();
-        std::vector<int64_t> total = build_solve(p->T, cba, lva, p->sp_a, p->T.tasks, p->T.groups, p->T.lvl);
-        p->n_solve_groups_adj = (int64_t)p->T.groups.size() / 8;
-        for (int b = 0; b < p->nmat; b++) append_gv_groups(p->F, cb[b], cb[b + 1], b, total[b], p->sp_a, p->T.tasks, p->T.groups);
+        p->T.sync.clear();
+        p->T.n_counters = 0;
+        auto last = build_solve(p->T, cba, lva, p->sp_a, p->T.tasks, p->T.sync, p->T.n_counters);
+        p->n_solve_tasks_adj = (int64_t)p->T.tasks.size();
+        for (int b = 0; b < p->nmat; b++) append_gv(p->F, cb[b], cb[b + 1], last[b], p->sp_a, p->T.tasks, p->T.sync);
         if (ddf_status s = upload_tasks(p, p->T)) return s;
     }
-    return DDF_OK;
+    return ensure_counters(p);
 }
 
 ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
@@ -512,7 +496,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     p->sp_f.ops_per_lane = p->sp_a.ops_per_lane = o.ops_per_lane;
     p->sp_f.passes = p->sp_a.passes = o.rows_passes;
     p->sp_f.remap = p->sp_a.remap = o.xcd_remap < 0 ? 1 : o.xcd_remap;
-    p->sp_f.thin_tasks = p->sp_a.thin_tasks = o.thin_tasks < 0 ? SWPB : o.thin_tasks;
+    p->sp_f.blocks = p->sp_a.blocks = o.solve_blocks > 0 ? o.solve_blocks : 0;
     p->fwd.resize(nmat);
     if (p->has_adj) p->adj.resize(nmat);
     p->mats.resize(nmat);
@@ -584,10 +568,6 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     if (p->has_adj && (s = upload_tables(p, p->T))) return fin(s);
     if ((s = build_schedule(p, true, true))) return fin(s);
     if ((s = upload(p, &p->d_mats, p->mats.data(), p->mats.size()))) return fin(s);
-    p->nctr = 2 + nmat;
-    if ((s = dalloc(p, (void **)&p->d_ctr, sizeof(unsigned) * p->nctr))) return fin(s);
-    if (hipError_t e = hipMemset(p->d_ctr, 0, sizeof(unsigned) * p->nctr))
-        return fin(fail(DDF_E_HIP, std::string("hipMemset: ") + hipGetErrorString(e)));
     // values captured at inspect time (packed over a batch)
     bool have_vals = true;
     for (int b = 0; b < nmat; b++)
@@ -642,7 +622,7 @@ ddf_status check_nrhs(int32_t k) {
 
 const double *vals_or_own(ddf_plan_t p, const double *v) { return v ? v : p->d_vals; }
 
-ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t g0, int64_t ngroups, bool adj,
+ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t ntasks, int64_t ncounters, bool adj,
                         const double *vals, const double *b, double *x, const double *xf, double *gv,
                         int32_t k_override, int kt, hipStream_t s) {
     const SchedParams &sp = adj ? p->sp_a : p->sp_f;
@@ -651,10 +631,9 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t g0, int64_t ng
     a.aux = adj ? p->T.d_aux : p->F.d_aux;
     a.cods2 = p->F.d_cods;
     a.aux2 = p->F.d_aux;
-    a.tasks = D.d_tasks;
-    a.groups = reinterpret_cast<const Group *>(D.d_groups) + g0;
-    a.ngroups = (int32_t)ngroups;
-    a.lvl = D.d_lvl;
+    a.tasks = D.d_tasks + t0;
+    a.sync = reinterpret_cast<const int4 *>(D.d_sync) + t0;
+    a.ntasks = (int32_t)ntasks;
     a.backoff_max = sp.backoff > 0 ? sp.backoff : 16;
     a.mats = p->d_mats;
     a.vals = vals;
@@ -666,8 +645,8 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t g0, int64_t ng
     a.ctr = p->d_ctr;
     a.spin_limit = p->spin_limit;
     a.k_override = k_override;
-    HIPCHK(launch_reset(p->d_ctr, p->nctr, s));
-    HIPCHK(launch_solve(a, adj, kt, sp.blocks > 0 ? sp.blocks : num_cu(), s));
+    HIPCHK(launch_reset(p->d_ctr, (2 + ncounters) * CTR_STRIDE, s));
+    HIPCHK(launch_solve(a, adj, kt, sp.blocks, s));
     return DDF_OK;
 }
 
@@ -686,7 +665,7 @@ void ddf_opts_default(ddf_opts *o) {
     o->ops_per_lane = 4;
     o->rows_passes = 2;
     o->xcd_remap = -1;
-    o->thin_tasks = -1;
+    o->solve_blocks = 0;
 }
 
 const char *ddf_version(void) { return "ddf-mi355x 0.1"; }
@@ -777,7 +756,7 @@ ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, d
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
     if (p->n_rows == 0) return DDF_OK;
     // the single matrix's right-hand-side count is a per-call argument (k_override)
-    return solve_launch(p, p->F, 0, (int64_t)p->F.groups.size() / 8, false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
+    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), p->F.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
                         kt_for(nrhs), (hipStream_t)stream);
 }
 
@@ -844,8 +823,8 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
     if (d_gvals && (overlap(d_gvals, p->nnz * 8, d_gb, nb) || overlap(d_gvals, p->nnz * 8, d_x, nb)))
         return fail(DDF_E_ARG, "gvals overlaps another buffer");
     if (p->n_rows == 0) return DDF_OK;
-    int64_t ng = d_gvals ? (int64_t)p->T.groups.size() / 8 : p->n_solve_groups_adj;
-    return solve_launch(p, p->T, 0, ng, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
+    int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
+    return solve_launch(p, p->T, 0, nt, p->T.n_counters, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
                         (hipStream_t)stream);
 }
 
@@ -863,7 +842,7 @@ ddf_status ddf_sptrsv_batch(ddf_plan_t p, const double *d_vals, const double *d_
     int64_t nb = p->vec_total * 8;
     if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
-    return solve_launch(p, p->F, 0, (int64_t)p->F.groups.size() / 8, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
+    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), p->F.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
                         batch_kt(p), (hipStream_t)stream);
 }
 
@@ -877,8 +856,8 @@ ddf_status ddf_sptrsv_batch_adjoint(ddf_plan_t p, const double *d_vals, const do
     if ((!d_vals && p->nnz) || !d_gx || !d_gb || (d_gvals && !d_x)) return fail(DDF_E_ARG, "NULL buffer");
     if (d_gb != d_gx && overlap(d_gb, nb, d_gx, nb)) return fail(DDF_E_ARG, "gb and gx partially overlap");
     if (overlap(d_gb, nb, d_x, nb)) return fail(DDF_E_ARG, "gb overlaps x");
-    int64_t ng = d_gvals ? (int64_t)p->T.groups.size() / 8 : p->n_solve_groups_adj;
-    return solve_launch(p, p->T, 0, ng, true, d_vals, d_gx, d_gb, d_x, d_gvals, 0, batch_kt(p),
+    int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
+    return solve_launch(p, p->T, 0, nt, p->T.n_counters, true, d_vals, d_gx, d_gb, d_x, d_gvals, 0, batch_kt(p),
                         (hipStream_t)stream);
 }
 
@@ -889,8 +868,8 @@ ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t p, const double *d_vals, const
     d_vals = vals_or_own(p, d_vals);
     if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
     for (int b = 0; b < p->nmat; b++) {
-        int64_t g0 = p->pm_group_ptr[b], g1 = p->pm_group_ptr[b + 1];
-        if (ddf_status s = solve_launch(p, p->Fpm, g0, g1 - g0, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
+        int64_t t0 = p->pm_task_ptr[b], t1 = p->pm_task_ptr[b + 1];
+        if (ddf_status s = solve_launch(p, p->Fpm, t0, t1 - t0, p->Fpm.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
                                         kt_for(p->mats[b].k), (hipStream_t)stream))
             return s;
     }
@@ -1115,13 +1094,11 @@ ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables
     o->cods = reinterpret_cast<const int32_t *>(S.cods.data());
     o->aux = S.aux.data();
     o->tasks = reinterpret_cast<const int32_t *>(D->tasks.data());
-    o->groups = D->groups.data();
-    o->lvl = D->lvl.data();
+    o->sync = D->sync.data();
     o->n_cods = (int64_t)S.cods.size();
     o->aux_len = (int64_t)S.aux.size();
     o->n_tasks = (int64_t)D->tasks.size();
-    o->n_groups = (int64_t)D->groups.size() / 8;
-    o->lvl_len = (int64_t)D->lvl.size();
+    o->n_counters = D->n_counters;
     o->tasksN = reinterpret_cast<const int32_t *>(D->tasksN.data());
     o->n_tasksN = (int64_t)D->tasksN.size();
     return DDF_OK;
@@ -1184,10 +1161,11 @@ ddf_status ddf_plan_sync_status(ddf_plan_t p, ddf_stream_t stream) {
     if (ddf_status s = need_device(p)) return s;
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     unsigned flag = 0;
-    HIPCHK(hipMemcpy(&flag, p->d_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (!p->d_ctr) return DDF_OK;
+    HIPCHK(hipMemcpy(&flag, p->d_ctr + CTR_STRIDE, sizeof(unsigned), hipMemcpyDeviceToHost));
     if (flag) {
         unsigned z = 0;
-        HIPCHK(hipMemcpy(p->d_ctr + 1, &z, sizeof(unsigned), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(p->d_ctr + CTR_STRIDE, &z, sizeof(unsigned), hipMemcpyHostToDevice));
         return fail(DDF_E_DEVICE, "a level wait exceeded its spin limit");
     }
     return DDF_OK;
@@ -1220,11 +1198,11 @@ void load_tune_file() {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // one entry per line: "key": [ops_per_lane, passes, remap, thin_tasks],
+        // one entry per line: "key": [ops_per_lane, passes, remap, blocks],
         size_t q1 = line.find('"'), q2 = line.find('"', q1 + 1), b = line.find('[');
         if (q1 == std::string::npos || q2 == std::string::npos || b == std::string::npos) continue;
         SchedParams sp;
-        if (sscanf(line.c_str() + b, "[%d, %d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap, &sp.thin_tasks) == 4)
+        if (sscanf(line.c_str() + b, "[%d, %d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap, &sp.blocks) == 4)
             g_tune_cache[line.substr(q1 + 1, q2 - q1 - 1)] = sp;
     }
 }
@@ -1237,7 +1215,7 @@ void save_tune_file() {
     size_t i = 0;
     for (auto &kv : g_tune_cache)
         f << "  \"" << kv.first << "\": [" << kv.second.ops_per_lane << ", " << kv.second.passes << ", "
-          << kv.second.remap << ", " << kv.second.thin_tasks << "]" << (++i < g_tune_cache.size() ? "," : "") << "\n";
+          << kv.second.remap << ", " << kv.second.blocks << "]" << (++i < g_tune_cache.size() ? "," : "") << "\n";
     f << "}\n";
 }
 
@@ -1293,25 +1271,26 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
     // candidates: SpMV varies lanes per row, row passes and XCD block order; the solve
     // varies lanes per row, row passes and whether small levels run as THIN ranges
     struct Cand {
-        int opl, ps, rm, thin;
+        int opl, ps, rm, blocks;
     };
     std::vector<Cand> cands;
-    cands.push_back({target.ops_per_lane, target.passes, target.remap, target.thin_tasks}); // current first
+    cands.push_back({target.ops_per_lane, target.passes, target.remap, target.blocks}); // current first
     if (is_spmv) {
         for (int rm : {1, 0})
             for (int opl : {1, 2, 4, 8, 16})
-                for (int ps : {1, 2, 4}) cands.push_back({opl, ps, rm, target.thin_tasks});
+                for (int ps : {1, 2, 4}) cands.push_back({opl, ps, rm, 0});
     } else {
-        for (int thin : {SWPB, 0})
-            for (int opl : {2, 4, 8})
-                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, thin});
+        const int full = 4 * num_cu(); // up to four 256-thread blocks per CU
+        for (int blocks : {full, full / 4, full / 16})
+            for (int opl : {4, 2, 8})
+                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, blocks});
     }
     for (const Cand &cd : cands) {
         if (st || (budget_ms > 0 && spent > budget_ms)) break;
         target.ops_per_lane = cd.opl;
         target.passes = cd.ps;
         target.remap = cd.rm;
-        target.thin_tasks = cd.thin;
+        target.blocks = cd.blocks;
         if ((st = build_schedule(p, !adjop, adjop))) break;
         if ((st = run())) break;
         (void)hipEventRecord(e0, s);

@@ -28,7 +28,7 @@ def xmode(fl):
 
 class Tables:
     def __init__(self, t):
-        self.cods, self.aux, self.tasks, self.groups, self.lvl = t["cods"], t["aux"], t["tasks"], t["groups"], t["lvl"]
+        self.cods, self.aux, self.tasks = t["cods"], t["aux"], t["tasks"]
 
     def a(self, i):
         assert 0 <= i < self.aux.size, f"aux index {i} out of [0, {self.aux.size})"
@@ -158,58 +158,62 @@ def gv(tabs, fwd_tabs, A, G, X, t0, many=False):
 
 
 def solve(tabs, L, B, kind=1, vals=None, perm=None, fwd_tabs=None, Xf=None, with_gv=False, only_mat=None):
-    """Replays the persistent solve group by group in ticket order.  kind 1: L X = B on L's
-    plan; kind 2: U Lam = B with U = L^T, values through perm.  Checks that every solution
-    entry read was written by an earlier task and that every group's wait count equals the
-    tasks of earlier levels."""
+    """Replays the persistent solve task by task in ticket order.  kind 1: L X = B on L's
+    plan; kind 2: U Lam = B with U = L^T, values through perm.  Checks the counter protocol:
+    each task's wait is already satisfied by earlier tickets, every count waited for equals
+    the number of tasks signalling that counter, and every solution entry a task reads was
+    written by a task whose counter the wait covers."""
     T = Tables(tabs)
+    sync = tabs["sync"]
     v = L.values if vals is None else vals
     n, k = B.shape
     X = np.full((n, k), np.nan)
-    written = np.zeros(n, bool)
-    done = 0
+    writer = np.full(n, -2)  # signal counter of the task that wrote each row
     gvout = np.full(int(L.row_ptr[-1]), np.nan) if with_gv else None
     TF = Tables(fwd_tabs) if fwd_tabs is not None else None
-    for g in T.groups:
-        typ, t0, t1, need, mat, lv_off, nlv, _ = (int(x) for x in g)
-        if only_mat is not None and mat != only_mat:
-            continue
-        assert need <= done, "group waits on tasks that come later"
-        if typ == 1:
-            bounds = [int(T.lvl[lv_off + i]) for i in range(nlv + 1)]
-            assert bounds[0] == t0 and bounds[-1] == t1
-            levels = [range(bounds[i], bounds[i + 1]) for i in range(nlv)]
+    def mat_of(t):
+        cod = int(T.tasks[t][0])
+        return int((TF.cods if (int(T.tasks[t][3]) >> 8) & 1 else T.cods)[cod][F["mat"]])
+
+    # one launch covers the tasks of `only_mat` (per-matrix schedules reuse counter ids)
+    mine = [t for t in range(T.tasks.shape[0]) if only_mat is None or mat_of(t) == only_mat]
+    sigs = np.array([int(sync[t][2]) for t in mine], dtype=np.int64)
+    nsig = np.bincount(sigs[sigs >= 0], minlength=max(1, int(tabs["n_counters"])))
+    done = np.zeros_like(nsig)
+    for t in mine:
+        w, cnt, sig, _ = (int(x) for x in sync[t])
+        if w >= 0:
+            assert nsig[w] == cnt, "count waited for differs from the tasks signalling the counter"
+            assert done[w] >= cnt, "wait not satisfied by earlier tickets"
+        meta = int(T.tasks[t][3])
+        if (meta >> 8) & 1:
+            assert with_gv and TF is not None
+            assert (writer >= 0).all() and (writer <= w).all(), "GV pass before the solve finished"
+            c, _, rows = _rows_from(TF, T.tasks[t])
+            for row, opst, nops, cols in rows:
+                for i1, col in enumerate(cols):
+                    gvout[opst + i1] = -(X[row] @ Xf[col])
+                gvout[opst + nops] = -(X[row] @ Xf[row])
         else:
-            levels = [range(t0, t1)]
-        for lv in levels:
+            assert sig >= 0 and (w == -1 or w == sig - 1)
+            c, _, rows = T.task_rows(t)
             pending = []
-            for t in lv:
-                meta = int(T.tasks[t][3])
-                if (meta >> 8) & 1:
-                    assert with_gv and TF is not None
-                    assert written.all(), "GV pass before the solve finished"
-                    c, _, rows = _rows_from(TF, T.tasks[t])
-                    for row, opst, nops, cols in rows:
-                        for i1, col in enumerate(cols):
-                            gvout[opst + i1] = -(X[row] @ Xf[col])
-                        gvout[opst + nops] = -(X[row] @ Xf[row])
-                    continue
-                c, _, rows = T.task_rows(t)
-                for row, opst, nops, cols in rows:
-                    acc = np.zeros(k)
-                    for i1, col in enumerate(cols):
-                        e = opst + i1
-                        assert written[col], f"row {row} reads x[{col}] before it is solved"
-                        acc += (v[perm[e]] if kind == 2 else v[e]) * X[col]
-                    d = opst - 1 if kind == 2 else opst + nops
-                    diag = v[perm[d]] if kind == 2 else v[d]
-                    pending.append((row, (B[row] - acc) / diag))
-            for row, val in pending:  # a level's rows are independent
-                assert not written[row]
+            for row, opst, nops, cols in rows:
+                acc = np.zeros(k)
+                for i1, col in enumerate(cols):
+                    e = opst + i1
+                    assert writer[col] >= 0 and writer[col] <= w, f"row {row} reads x[{col}] not covered by its wait"
+                    acc += (v[perm[e]] if kind == 2 else v[e]) * X[col]
+                d = opst - 1 if kind == 2 else opst + nops
+                diag = v[perm[d]] if kind == 2 else v[d]
+                pending.append((row, (B[row] - acc) / diag))
+            for row, val in pending:
+                assert writer[row] == -2
                 X[row] = val
-                written[row] = True
-        done += t1 - t0
-    assert written.all()
+                writer[row] = sig
+        if sig >= 0:
+            done[sig] += 1
+    assert (writer >= 0).all()
     return X, gvout
 
 

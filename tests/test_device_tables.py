@@ -72,7 +72,7 @@ def test_workload_tables():
     w = I.c1_laplace2d()
     replay_spmv(w.A, k=1)
     F = replay_solve(w.L, k=1)
-    assert F["groups"].shape[0] == 1 and F["groups"][0, 0] == 1  # one thin range of 127 levels
+    assert F["n_counters"] == 127  # one counter per level
     w = I.c2_stencil27_offband(nx=12)
     replay_spmv(w.A, k=1)
     replay_solve(w.L, k=1)
@@ -81,14 +81,14 @@ def test_workload_tables():
     replay_solve(w.L, k=2)
 
 
-def test_thin_and_wide_groups():
-    # a 2D Laplacian whose middle levels exceed 16 tasks: wide groups between two thin ranges
-    L = I.tril(I.laplacian(700, 700, 1, I.OFFS_5PT, 4.0))
-    F = ddf.ddf_plan_device_tables(hplan(1, L, ops_per_lane=1, rows_passes=1), 0)
-    types = F["groups"][:, 0]
-    assert types[0] == 1 and types[-1] == 1 and (types == 0).any()
-    # groups are ordered by first level and their waits never decrease
-    assert np.all(np.diff(F["groups"][:, 3]) >= 0)
+def test_counter_protocol_2d_laplacian():
+    # wide middle levels: many tasks per level, each waiting on the previous level's counter
+    L = I.tril(I.laplacian(300, 300, 1, I.OFFS_5PT, 4.0))
+    p = hplan(1, L, ops_per_lane=1, rows_passes=1)
+    F = ddf.ddf_plan_device_tables(p, 0)
+    assert F["n_counters"] == 599
+    X, _ = E.solve(F, L, np.ones((L.n_rows, 1)))
+    check_solve(L, np.ones((L.n_rows, 1)), X, O.sptrsv(L, np.ones((L.n_rows, 1))))
 
 
 def test_batch_schedule_per_matrix():
@@ -98,9 +98,6 @@ def test_batch_schedule_per_matrix():
     F = ddf.ddf_plan_device_tables(p, 0)
     T = ddf.ddf_plan_device_tables(p, 1)
     PM = ddf.ddf_plan_device_tables(p, 2)
-    for g in F["groups"]:
-        for t in range(g[1], g[2]):
-            assert F["cods"][F["tasks"][t][0]][15] == g[4]
     for b, m in enumerate(mats):
         L, k = m["L"], m["k"]
         B = m["B"]
