@@ -71,6 +71,10 @@ typedef struct {
     int32_t xcd_remap;     /* schedule: give each XCD a contiguous block range; -1 default */
     int32_t solve_blocks;  /* schedule (solve): 256-thread blocks of the persistent kernel;
                               0 = every block the device keeps resident                     */
+    int32_t solve_path;    /* solve kernel: 0 auto (single-block when every level fits one
+                              1024-lane pass, else multi-block), 1 multi-block, 2 single-block
+                              when possible                                                */
+    int32_t reserved[3];
 } ddf_opts;
 
 typedef struct {
@@ -247,6 +251,11 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
 typedef struct {
     const int32_t *cods, *aux, *tasks, *sync, *tasksN;
     int64_t n_cods, aux_len, n_tasks, n_counters, n_tasksN;
+    const int32_t *thin_rec; /* single-block solve: [n_thin_rec][12] per lane slot: row, value
+                                index of the diagonal, ops, 0, value indices[4], columns[4] */
+    const int32_t *thin_lvl; /* [n_levels][2] first record, lane slots in use (0 if absent)  */
+    int64_t n_thin_rec, n_thin_lvl;
+    int32_t thin_lg, reserved;
 } ddf_device_tables_t;
 ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
 

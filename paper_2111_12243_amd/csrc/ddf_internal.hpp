@@ -73,6 +73,7 @@ struct SchedParams {
     int32_t remap = 1;
     int32_t blocks = 0;   // solve: persistent grid in 256-thread blocks (0 = all resident)
     int32_t backoff = 16; // solve: longest sleep between polls (units of 64 cycles)
+    int32_t path = 0;     // solve: 0 auto, 1 multi-block, 2 single-block
 };
 
 // Device-resident tables of one plan pass (forward or adjoint).
@@ -83,6 +84,11 @@ struct DevTables {
     std::vector<Task> tasksN;          // SpMV with several right-hand sides
     std::vector<int32_t> sync;         // solve: 4 int32 per task (wait counter, count, signal counter)
     int64_t n_counters = 0;            // solve: level counters the schedule uses
+    std::vector<int32_t> thin_rec;     // single-block solve records (empty if not eligible)
+    std::vector<int32_t> thin_lvl;     // per level: first record, lanes
+    int32_t thin_lg = 0;
+    int32_t *d_thin_rec = nullptr;
+    int32_t *d_thin_lvl = nullptr;
     DCod *d_cods = nullptr;
     int32_t *d_aux = nullptr;
     Task *d_tasks = nullptr;
@@ -92,6 +98,7 @@ struct DevTables {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
                (int64_t)tasks.size() * sizeof(Task) + (int64_t)sync.size() * 4;
     }
+    int64_t thin_bytes() const { return (int64_t)(thin_rec.size() + thin_lvl.size()) * 4; }
     // bytes a launch reads: records and aux (upper bound) plus its own task list
     int64_t launch_bytes(bool many_rhs) const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +

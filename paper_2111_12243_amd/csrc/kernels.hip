@@ -169,8 +169,14 @@ __device__ void spmv_gv_task(const SpmvArgs &a, const Task &tk, int lane) {
             const double *__restrict__ xr = a.x2 + (int64_t)col * k;
             double s = 0.0;
             for (int r = 0; r < k; r++) s += grow[r] * xr[r];
-            a.gv[e] = s;
+            a.gv[e] = a.gv_sign * s;
         });
+        if (a.gv_diag && g == 0) {
+            const double *__restrict__ xr = a.x2 + (int64_t)ri.row * k;
+            double s = 0.0;
+            for (int r = 0; r < k; r++) s += grow[r] * xr[r];
+            a.gv[ri.opst + ri.nops] = a.gv_sign * s;
+        }
     }
 }
 
@@ -614,6 +620,86 @@ __global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Single-block solve for matrices whose every level fits one pass of the block.  One lane
+// slot per (row, lane-of-row); levels are separated by block barriers.  Each level issues,
+// together, the records of level l+2, the values of level l+1 and the solution loads of
+// level l, so a level costs about one memory round trip; solution values stay in the CU's
+// caches (the block is the only writer).
+// ------------------------------------------------------------------------------------------
+struct ThinRec {
+    int row, dpos, cnt;
+    int vidx[LOOKAHEAD], col[LOOKAHEAD];
+};
+
+__device__ __forceinline__ void thin_rec_load(const ThinArgs &a, int2 lv, int s, ThinRec &r) {
+    r.row = -1;
+    r.cnt = 0;
+    if (s < lv.y) {
+        const int4 *q = reinterpret_cast<const int4 *>(a.rec + (int64_t)(lv.x + s) * THIN_REC);
+        const int4 h = q[0], v = q[1], c = q[2];
+        r.row = h.x;
+        r.dpos = h.y;
+        r.cnt = h.z;
+        r.vidx[0] = v.x; r.vidx[1] = v.y; r.vidx[2] = v.z; r.vidx[3] = v.w;
+        r.col[0] = c.x; r.col[1] = c.y; r.col[2] = c.z; r.col[3] = c.w;
+    }
+}
+
+template <int KT>
+__global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
+    static_assert(LOOKAHEAD == 4, "record layout");
+    const int s = threadIdx.x;
+    const int G = 1 << a.lg, g = s & (G - 1);
+    const int k = a.k;
+    const int2 zero = make_int2(0, 0);
+    ThinRec r0, r1, r2;
+    double v0[LOOKAHEAD], v1[LOOKAHEAD], d0 = 1.0, d1 = 1.0;
+    int2 lv2 = a.nlev > 2 ? a.lvl[2] : zero;
+    thin_rec_load(a, a.nlev > 0 ? a.lvl[0] : zero, s, r0);
+    thin_rec_load(a, a.nlev > 1 ? a.lvl[1] : zero, s, r1);
+#pragma unroll
+    for (int j = 0; j < LOOKAHEAD; j++) v0[j] = j < r0.cnt ? a.vals[r0.vidx[j]] : 0.0;
+    if (r0.row >= 0) d0 = a.vals[r0.dpos];
+    for (int l = 0; l < a.nlev; l++) {
+        const int2 lv3 = l + 3 < a.nlev ? a.lvl[l + 3] : zero;
+        // records two levels ahead, values one level ahead (neither depends on the solution)
+        thin_rec_load(a, lv2, s, r2);
+#pragma unroll
+        for (int j = 0; j < LOOKAHEAD; j++) v1[j] = j < r1.cnt ? a.vals[r1.vidx[j]] : 0.0;
+        if (r1.row >= 0) d1 = a.vals[r1.dpos];
+        // this level
+        for (int r0k = 0; r0k < k; r0k += KT) {
+            double acc[KT];
+#pragma unroll
+            for (int r = 0; r < KT; r++) acc[r] = 0.0;
+#pragma unroll
+            for (int j = 0; j < LOOKAHEAD; j++) {
+                if (j < r0.cnt) {
+                    const double *xr = a.x + (int64_t)r0.col[j] * k + r0k;
+#pragma unroll
+                    for (int r = 0; r < KT; r++)
+                        if (r0k + r < k) acc[r] += v0[j] * xr[r];
+                }
+            }
+            group_sum<KT>(acc, G);
+            if (r0.row >= 0) {
+                const int64_t rb = (int64_t)r0.row * k + r0k;
+#pragma unroll
+                for (int r = 0; r < KT; r++)
+                    if ((r & (G - 1)) == g && r0k + r < k) a.x[rb + r] = (a.b[rb + r] - acc[r]) / d0;
+            }
+        }
+        __syncthreads();
+        r0 = r1;
+        r1 = r2;
+#pragma unroll
+        for (int j = 0; j < LOOKAHEAD; j++) v0[j] = v1[j];
+        d0 = d1;
+        lv2 = lv3;
+    }
+}
+
 __global__ void k_reset(unsigned *p, int64_t n) {
     for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < n; i += (int64_t)blockDim.x * gridDim.x)
         p[i] = 0u;
@@ -797,6 +883,16 @@ hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s) {
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_reset, dim3((unsigned)nb), dim3(256), 0, s, ctr, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_thin(const ThinArgs &a, int kt, hipStream_t s) {
+    if (a.nlev == 0) return hipSuccess;
+    const dim3 grid(1), block(THIN_THREADS);
+    if (kt == 1) hipLaunchKernelGGL(k_solve_thin<1>, grid, block, 0, s, a);
+    else if (kt == 2) hipLaunchKernelGGL(k_solve_thin<2>, grid, block, 0, s, a);
+    else if (kt == 4) hipLaunchKernelGGL(k_solve_thin<4>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_solve_thin<8>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

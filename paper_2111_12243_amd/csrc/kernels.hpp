@@ -24,6 +24,24 @@ struct SpmvArgs {
     const double *g;
     const double *x2;
     double *gv;
+    double gv_sign;  // GV scale (+1 for SpMV, -1 for the solve adjoint)
+    int32_t gv_diag; // also write the diagonal entry (triangular forward plans)
+};
+
+// Single-block solve of a matrix whose every level fits one 1024-thread pass.  Per lane
+// slot and level one record of THIN_REC int32: row, value index of the diagonal, number of
+// ops (<= LOOKAHEAD), 0, value indices [LOOKAHEAD], columns [LOOKAHEAD]; G lanes per row.
+constexpr int THIN_REC = 12;
+constexpr int THIN_THREADS = 1024;
+struct ThinArgs {
+    const int32_t *rec;
+    const int2 *lvl; // per level: first record, lanes in use
+    int32_t nlev;
+    int32_t lg;      // log2 lanes per row
+    int32_t k;
+    const double *vals;
+    const double *b;
+    double *x;
 };
 
 constexpr int LOOKAHEAD = 4;   // elements per lane a solve task loads before its wait
@@ -76,6 +94,7 @@ int kr_for(int k);
 hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s);
 int num_cu();
 hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
+hipError_t launch_solve_thin(const ThinArgs &a, int kt, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
 

@@ -355,6 +355,60 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     return s;
 }
 
+// Records of the single-block solve, built from a matrix's codelets level by level (rows in
+// plan order).  Eligible when every row has at most 64 * LOOKAHEAD ops and every level fits
+// one 1024-lane pass; value indices go through perm for the transposed solve.
+void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *perm, DevTables &D) {
+    D.thin_rec.clear();
+    D.thin_lvl.clear();
+    const int64_t n = P.n_rows;
+    int64_t maxn = 0;
+    for (int64_t r = 0; r < n; r++) maxn = std::max(maxn, P.nops(r));
+    int lg = 0;
+    while ((int64_t(LOOKAHEAD) << lg) < maxn && lg < 6) lg++;
+    if ((int64_t(LOOKAHEAD) << lg) < maxn) return;
+    const int G = 1 << lg;
+    const int64_t nl = c.header[5];
+    for (int64_t l = 0; l < nl; l++)
+        if ((c.part_ptr[l + 1] - c.part_ptr[l]) * G > THIN_THREADS) return;
+    // codelets of each level, in plan order
+    std::vector<std::vector<int64_t>> by_level(nl);
+    for (int64_t i = 0; i < c.header[7]; i++) by_level[c.codelets[i * NCOD + C_PART]].push_back(i);
+    auto vidx = [&](int64_t e) -> int32_t { return perm ? (*perm)[e] : (int32_t)e; };
+    for (int64_t l = 0; l < nl; l++) {
+        const int64_t first = (int64_t)D.thin_rec.size() / THIN_REC;
+        for (int64_t ci : by_level[l]) {
+            const int64_t *r = &c.codelets[ci * NCOD];
+            const int32_t fl = (int32_t)r[C_FLAGS];
+            for (int64_t a = 0; a < r[C_M]; a++) {
+                const int64_t row = (fl & FS0) ? r[C_ROW0] + a * r[C_ROWSTEP] : c.aux[r[C_AUXOFF] + a];
+                const int64_t op = P.opstart(row), no = P.nops(row);
+                const int64_t dpos = P.kind == 2 ? op - 1 : op + no;
+                for (int g = 0; g < G; g++) {
+                    int32_t rec[THIN_REC] = {(int32_t)row, vidx(dpos), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    int cnt = 0;
+                    for (int j = 0; j < LOOKAHEAD; j++) {
+                        const int64_t i1 = g + (int64_t)j * G;
+                        if (i1 < no) {
+                            rec[4 + j] = vidx(op + i1);
+                            rec[8 + j] = P.ci[op + i1];
+                            cnt = j + 1;
+                        } else {
+                            rec[4 + j] = vidx(dpos); // in-bounds filler, never used
+                            rec[8 + j] = (int32_t)row;
+                        }
+                    }
+                    rec[2] = cnt;
+                    D.thin_rec.insert(D.thin_rec.end(), rec, rec + THIN_REC);
+                }
+            }
+        }
+        D.thin_lvl.push_back((int32_t)first);
+        D.thin_lvl.push_back((int32_t)((int64_t)D.thin_rec.size() / THIN_REC - first));
+    }
+    D.thin_lg = lg;
+}
+
 // Counter lines of the persistent solve: ticket, error flag, one per level of the largest
 // schedule.  Grown (never shrunk) when a schedule needs more.
 ddf_status ensure_counters(ddf_plan_t p) {
@@ -452,7 +506,28 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
 
 ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
     if (ddf_status s = upload(p, &D.d_cods, D.cods.data(), D.cods.size())) return s;
+    if (!D.thin_rec.empty()) {
+        if (ddf_status s = upload(p, &D.d_thin_rec, D.thin_rec.data(), D.thin_rec.size())) return s;
+        if (ddf_status s = upload(p, &D.d_thin_lvl, D.thin_lvl.data(), D.thin_lvl.size())) return s;
+    }
     return upload(p, &D.d_aux, D.aux.data(), D.aux.size());
+}
+
+bool use_thin(const DevTables &D, const SchedParams &sp) { return !D.thin_rec.empty() && sp.path != 1; }
+
+ddf_status thin_launch(const DevTables &D, int nlev, const double *vals, const double *b, double *x, int32_t k,
+                       hipStream_t s) {
+    ThinArgs t{};
+    t.rec = D.d_thin_rec;
+    t.lvl = reinterpret_cast<const int2 *>(D.d_thin_lvl);
+    t.nlev = nlev;
+    t.lg = D.thin_lg;
+    t.k = k;
+    t.vals = vals;
+    t.b = b;
+    t.x = x;
+    HIPCHK(launch_solve_thin(t, kt_for(k), s));
+    return DDF_OK;
 }
 
 void free_plan(ddf_plan_t p) {
@@ -546,6 +621,15 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
             pack(p->adj[b], PT, b, p->T);
         }
     }
+    if (kind == DDF_SPTRSV_LOWER && !batch) {
+        Pattern P{kind, mats[0].n_rows, mats[0].n_cols, mats[0].row_ptr, mats[0].col_idx};
+        build_thin(p->fwd[0], P, nullptr, p->F);
+        if (p->has_adj) {
+            Pattern PT{2, mats[0].n_cols, mats[0].n_rows, rpT[0].data(), ciT[0].data()};
+            build_thin(p->adj[0], PT, &perm[0], p->T);
+        }
+    }
+    p->sp_f.path = p->sp_a.path = o.solve_path;
     if (p->host_only) {
         ddf_status st = build_schedule(p, true, true);
         if (st) {
@@ -755,6 +839,8 @@ ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, d
     if ((!d_vals && p->nnz) || (!d_b && p->n_rows) || (!d_x && p->n_rows)) return fail(DDF_E_ARG, "NULL buffer");
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
     if (p->n_rows == 0) return DDF_OK;
+    if (use_thin(p->F, p->sp_f))
+        return thin_launch(p->F, (int)p->fwd[0].header[5], d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
     // the single matrix's right-hand-side count is a per-call argument (k_override)
     return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), p->F.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
                         kt_for(nrhs), (hipStream_t)stream);
@@ -804,6 +890,7 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
     a.g = d_gy;
     a.x2 = d_x;
     a.gv = d_gvals;
+    a.gv_sign = 1.0;
     HIPCHK(launch_spmv(a, true, s));
     return DDF_OK;
 }
@@ -823,6 +910,26 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
     if (d_gvals && (overlap(d_gvals, p->nnz * 8, d_gb, nb) || overlap(d_gvals, p->nnz * 8, d_x, nb)))
         return fail(DDF_E_ARG, "gvals overlaps another buffer");
     if (p->n_rows == 0) return DDF_OK;
+    if (use_thin(p->T, p->sp_a)) {
+        // single-block transposed solve, then the GV pass as one parallel launch
+        hipStream_t s = (hipStream_t)stream;
+        if (ddf_status st = thin_launch(p->T, (int)p->adj[0].header[5], d_vals, d_gx, d_gb, nrhs, s)) return st;
+        if (!d_gvals) return DDF_OK;
+        SpmvArgs a{};
+        a.tasks = p->T.d_tasks + p->n_solve_tasks_adj;
+        a.ntasks = (int32_t)((int64_t)p->T.tasks.size() - p->n_solve_tasks_adj);
+        a.k = nrhs;
+        a.remap = p->sp_a.remap;
+        a.cods2 = p->F.d_cods;
+        a.aux2 = p->F.d_aux;
+        a.g = d_gb;
+        a.x2 = d_x;
+        a.gv = d_gvals;
+        a.gv_sign = -1.0;
+        a.gv_diag = 1;
+        HIPCHK(launch_spmv(a, false, s));
+        return DDF_OK;
+    }
     int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
     return solve_launch(p, p->T, 0, nt, p->T.n_counters, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
                         (hipStream_t)stream);
@@ -1101,6 +1208,11 @@ ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables
     o->n_counters = D->n_counters;
     o->tasksN = reinterpret_cast<const int32_t *>(D->tasksN.data());
     o->n_tasksN = (int64_t)D->tasksN.size();
+    o->thin_rec = D->thin_rec.data();
+    o->thin_lvl = D->thin_lvl.data();
+    o->n_thin_rec = (int64_t)D->thin_rec.size() / THIN_REC;
+    o->n_thin_lvl = (int64_t)D->thin_lvl.size() / 2;
+    o->thin_lg = D->thin_lg;
     return DDF_OK;
 }
 
@@ -1126,7 +1238,7 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
         break;
     case DDF_OP_SPTRSV:
-        ba = 8 * nnz + p->F.bytes() + 16 * vk;
+        ba = 8 * nnz + (use_thin(p->F, p->sp_f) ? p->F.thin_bytes() : p->F.bytes()) + 16 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
         if (p->batch) {
             for (size_t b = 0; b < p->mats.size(); b++) {
@@ -1138,7 +1250,11 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         }
         break;
     case DDF_OP_SPTRSV_ADJ:
-        ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 32 * vk;
+        if (p->has_adj && use_thin(p->T, p->sp_a))
+            ba = 16 * nnz + p->T.thin_bytes() + Fca + (int64_t)(p->T.tasks.size() - p->n_solve_tasks_adj) * sizeof(Task) +
+                 32 * vk;
+        else
+            ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 32 * vk;
         bc = 20 * nnz + 4 * (n + 1) + 24 * vk;
         if (p->batch) {
             for (size_t b = 0; b < p->mats.size(); b++) {
@@ -1198,11 +1314,12 @@ void load_tune_file() {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // one entry per line: "key": [ops_per_lane, passes, remap, blocks],
+        // one entry per line: "key": [ops_per_lane, passes, remap, blocks, path],
         size_t q1 = line.find('"'), q2 = line.find('"', q1 + 1), b = line.find('[');
         if (q1 == std::string::npos || q2 == std::string::npos || b == std::string::npos) continue;
         SchedParams sp;
-        if (sscanf(line.c_str() + b, "[%d, %d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap, &sp.blocks) == 4)
+        if (sscanf(line.c_str() + b, "[%d, %d, %d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap, &sp.blocks,
+                   &sp.path) == 5)
             g_tune_cache[line.substr(q1 + 1, q2 - q1 - 1)] = sp;
     }
 }
@@ -1215,7 +1332,8 @@ void save_tune_file() {
     size_t i = 0;
     for (auto &kv : g_tune_cache)
         f << "  \"" << kv.first << "\": [" << kv.second.ops_per_lane << ", " << kv.second.passes << ", "
-          << kv.second.remap << ", " << kv.second.blocks << "]" << (++i < g_tune_cache.size() ? "," : "") << "\n";
+          << kv.second.remap << ", " << kv.second.blocks << ", " << kv.second.path << "]"
+          << (++i < g_tune_cache.size() ? "," : "") << "\n";
     f << "}\n";
 }
 
@@ -1271,19 +1389,21 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
     // candidates: SpMV varies lanes per row, row passes and XCD block order; the solve
     // varies lanes per row, row passes and whether small levels run as THIN ranges
     struct Cand {
-        int opl, ps, rm, blocks;
+        int opl, ps, rm, blocks, path;
     };
     std::vector<Cand> cands;
-    cands.push_back({target.ops_per_lane, target.passes, target.remap, target.blocks}); // current first
+    cands.push_back({target.ops_per_lane, target.passes, target.remap, target.blocks, target.path}); // current first
     if (is_spmv) {
         for (int rm : {1, 0})
             for (int opl : {1, 2, 4, 8, 16})
-                for (int ps : {1, 2, 4}) cands.push_back({opl, ps, rm, 0});
+                for (int ps : {1, 2, 4}) cands.push_back({opl, ps, rm, 0, 0});
     } else {
+        const DevTables &D = adjop ? p->T : p->F;
+        if (!D.thin_rec.empty()) cands.push_back({target.ops_per_lane, target.passes, target.remap, 0, 2});
         const int full = 4 * num_cu(); // up to four 256-thread blocks per CU
         for (int blocks : {full, full / 4, full / 16})
             for (int opl : {4, 2, 8})
-                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, blocks});
+                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, blocks, 1});
     }
     for (const Cand &cd : cands) {
         if (st || (budget_ms > 0 && spent > budget_ms)) break;
@@ -1291,6 +1411,7 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
         target.passes = cd.ps;
         target.remap = cd.rm;
         target.blocks = cd.blocks;
+        target.path = cd.path;
         if ((st = build_schedule(p, !adjop, adjop))) break;
         if ((st = run())) break;
         (void)hipEventRecord(e0, s);

@@ -43,7 +43,8 @@ class DDFError(RuntimeError):
 class ddf_opts(C.Structure):
     _fields_ = [("window", C.c_int32), ("build_adjoint", C.c_int32), ("host_only", C.c_int32),
                 ("threads", C.c_int32), ("ops_per_lane", C.c_int32), ("rows_passes", C.c_int32),
-                ("xcd_remap", C.c_int32), ("solve_blocks", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("solve_blocks", C.c_int32),
+                ("solve_path", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class ddf_csr_host(C.Structure):
@@ -61,7 +62,9 @@ class ddf_plan_tables_t(C.Structure):
 class ddf_device_tables_t(C.Structure):
     _fields_ = [("cods", C.POINTER(C.c_int32)), ("aux", C.POINTER(C.c_int32)), ("tasks", C.POINTER(C.c_int32)),
                 ("sync", C.POINTER(C.c_int32)), ("tasksN", C.POINTER(C.c_int32)), ("n_cods", C.c_int64),
-                ("aux_len", C.c_int64), ("n_tasks", C.c_int64), ("n_counters", C.c_int64), ("n_tasksN", C.c_int64)]
+                ("aux_len", C.c_int64), ("n_tasks", C.c_int64), ("n_counters", C.c_int64), ("n_tasksN", C.c_int64),
+                ("thin_rec", C.POINTER(C.c_int32)), ("thin_lvl", C.POINTER(C.c_int32)), ("n_thin_rec", C.c_int64),
+                ("n_thin_lvl", C.c_int64), ("thin_lg", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ddf_plan_info_t(C.Structure):
@@ -359,7 +362,9 @@ def ddf_plan_device_tables(plan, which=0) -> dict:
 
     sync = grab(t.sync, t.n_tasks, 4) if t.sync else np.zeros((0, 4), np.int32)
     return {"cods": grab(t.cods, t.n_cods, 16), "aux": grab(t.aux, t.aux_len), "tasks": grab(t.tasks, t.n_tasks, 4),
-            "sync": sync, "n_counters": int(t.n_counters), "tasksN": grab(t.tasksN, t.n_tasksN, 4)}
+            "sync": sync, "n_counters": int(t.n_counters), "tasksN": grab(t.tasksN, t.n_tasksN, 4),
+            "thin_rec": grab(t.thin_rec, t.n_thin_rec, 12), "thin_lvl": grab(t.thin_lvl, t.n_thin_lvl, 2),
+            "thin_lg": int(t.thin_lg)}
 
 
 def ddf_plan_traffic(plan, op, nrhs) -> tuple:

@@ -225,3 +225,36 @@ def _rows_from(TF, task):
         row, opst, nops = TF.row_info(c, i0)
         out.append((row, opst, nops, TF.cols(c, i0, opst, nops)))
     return c, meta, out
+
+
+def thin_solve(tabs, L, B, vals=None):
+    """Replays the single-block solve: level by level, G lanes per row; checks that every
+    solution entry read was written by an earlier level and every row is solved once."""
+    rec, lvl, lg = tabs["thin_rec"], tabs["thin_lvl"], tabs["thin_lg"]
+    v = L.values if vals is None else vals
+    n, k = B.shape
+    G = 1 << lg
+    X = np.full((n, k), np.nan)
+    level_of = np.full(n, -1)
+    for l, (first, lanes) in enumerate(lvl):
+        assert 0 < lanes <= 1024 and lanes % G == 0
+        acc = {}
+        diag = {}
+        for s in range(lanes):
+            row, dpos, cnt = (int(x) for x in rec[first + s][:3])
+            if s % G == 0:
+                acc[row] = np.zeros(k)
+                diag[row] = v[dpos]
+            else:
+                assert row in acc
+            assert 0 <= cnt <= 4
+            for j in range(cnt):
+                vi, col = int(rec[first + s][4 + j]), int(rec[first + s][8 + j])
+                assert 0 <= level_of[col] < l, f"row {row} reads x[{col}] not solved in an earlier level"
+                acc[row] += v[vi] * X[col]
+        for row, a in acc.items():
+            assert level_of[row] == -1
+            X[row] = (B[row] - a) / diag[row]
+            level_of[row] = l
+    assert (level_of >= 0).all()
+    return X

@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 from paper_2111_12243_amd import inputs as I
-from tolerance import check_gv, check_solve
+from tolerance import check_gv, check_gv_solve, check_solve
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -70,7 +70,7 @@ def test_batch_forward_adjoint(nmat, n_lo, n_hi):
     for m, gb, gv, ref in zip(mats, split(dgb.cpu().numpy(), mats), split_vals(dgv.cpu().numpy(), mats), refs):
         GB, GV = O.sptrsv_adj(m["L"], ref, m["G"])
         check_solve(m["L"], m["G"], gb, GB, transposed=True)
-        check_gv(m["L"], ref, GB, -gv, -GV)
+        check_gv_solve(m["L"], ref, gb, GB, gv, GV)
 
 
 def test_graph_replays():

@@ -8,7 +8,7 @@ import device_emulator as E
 import oracle as O
 from paper_2111_12243_amd import ddf
 from paper_2111_12243_amd import inputs as I
-from tolerance import check_gv, check_product, check_solve
+from tolerance import check_gv, check_gv_solve, check_product, check_solve
 
 
 def hplan(kind, A, **kw):
@@ -43,10 +43,15 @@ def replay_solve(L, k=2, seed=0, **kw):
     check_solve(L, B, X, ref)
     T = ddf.ddf_plan_device_tables(p, 1)
     U, perm = O.transpose(L)
+    if F["thin_rec"].shape[0]:
+        check_solve(L, B, E.thin_solve(F, L, B), ref)
+    if T["thin_rec"].shape[0]:
+        lam_t = E.thin_solve(T, U, G, vals=L.values)
+        check_solve(L, G, lam_t, O.sptrsv_adj(L, ref, G)[0], transposed=True)
     lam, gv = E.solve(T, U, G, kind=2, vals=L.values, perm=perm, fwd_tabs=F, Xf=ref, with_gv=True)
     GBr, GVr = O.sptrsv_adj(L, ref, G)
     check_solve(L, G, lam, GBr, transposed=True)
-    check_gv(L, ref, GBr, -gv, -GVr)
+    check_gv_solve(L, ref, lam, GBr, gv, GVr)
     return F
 
 
@@ -121,3 +126,17 @@ def test_stream_tasks_single_entry_rows():
     n = 100
     eye = I.csr_from_pairs(n, n, np.arange(n), np.arange(n), np.arange(1.0, n + 1))
     replay_spmv(eye, k=1)
+
+
+def test_thin_records_workloads():
+    w = I.c1_laplace2d()
+    F = ddf.ddf_plan_device_tables(hplan(1, w.L), 0)
+    assert F["thin_lvl"].shape[0] == 127
+    w = I.c2_stencil27_offband(nx=16)
+    p = hplan(1, w.L)
+    F, T = ddf.ddf_plan_device_tables(p, 0), ddf.ddf_plan_device_tables(p, 1)
+    assert F["thin_rec"].shape[0] and T["thin_rec"].shape[0]
+    replay_solve(w.L, k=1)
+    # a level wider than one pass is not eligible
+    L = I.tril(I.laplacian(1200, 1200, 1, I.OFFS_5PT, 4.0))
+    assert ddf.ddf_plan_device_tables(hplan(1, L, build_adjoint=0), 0)["thin_rec"].shape[0] == 0

@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 from paper_2111_12243_amd import inputs as I
-from tolerance import check_gv, check_product, check_solve
+from tolerance import check_gv, check_gv_solve, check_product, check_solve
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -66,7 +66,14 @@ def spmv_case(A, k, seed=0, opts=None, plain=True):
 
 
 def sptrsv_case(L, k, seed=0, opts=None, plain=True, inplace=False):
-    print(f"sptrsv n={L.n_rows} nnz={L.nnz} k={k}", flush=True)
+    for path in (1, 2):  # multi-block persistent kernel; single-block kernel where eligible
+        o = opts if opts is not None else ddf.ddf_opts_default()
+        o.solve_path = path
+        sptrsv_case_path(L, k, seed, o, plain and path == 1, inplace)
+
+
+def sptrsv_case_path(L, k, seed, opts, plain, inplace):
+    print(f"sptrsv n={L.n_rows} nnz={L.nnz} k={k} path={opts.solve_path}", flush=True)
     plan = ddf.ddf_inspect(1, L, opts)
     B = rnd((L.n_rows, k), seed)
     G = rnd((L.n_rows, k), seed + 1)
@@ -91,7 +98,7 @@ def sptrsv_case(L, k, seed=0, opts=None, plain=True, inplace=False):
     ddf.ddf_sptrsv_adjoint(plan, vals, xs, g, gb, gv, k)
     ddf.ddf_plan_sync_status(plan)
     check_solve(L, G, host(gb), GB, transposed=True)
-    check_gv(L, ref, GB, -host(gv), -GV)
+    check_gv_solve(L, ref, host(gb), GB, host(gv), GV)
     if plain:
         xp = torch.full_like(b, np.nan)
         ddf.ddf_plain_sptrsv(plan, vals, b, xp, k)
@@ -100,7 +107,7 @@ def sptrsv_case(L, k, seed=0, opts=None, plain=True, inplace=False):
         gvp = torch.full_like(gv, np.nan)
         ddf.ddf_plain_sptrsv_adjoint(plan, vals, xs, g, gbp, gvp, k)
         check_solve(L, G, host(gbp), GB, transposed=True)
-        check_gv(L, ref, GB, -host(gvp), -GV)
+        check_gv_solve(L, ref, host(gbp), GB, host(gvp), GV)
     return plan
 
 

@@ -52,3 +52,17 @@ def check_solve(L, B, got, ref, transposed=False):
     res = np.max(np.abs(r)) / scale if B.size else 0.0
     assert res <= RES_TOL, f"residual {res:.3e}"
     return err / max(nrm, 1e-300), res
+
+
+def check_gv_solve(L, X, lam_dev, lam_ref, got, ref):
+    """GV of the solve adjoint, GV[e] = -sum_r lam[i,r] X[j,r].  (1) The GV pass itself,
+    against the device's own lambda, elementwise within 1e-14 of sum_r |lam_i x_j|; (2) the
+    propagated error of lambda: |got - ref| <= TOL * ||lam||_inf * sum_r |X[j, r]|."""
+    rows = np.repeat(np.arange(L.n_rows), np.diff(L.row_ptr))
+    cols = L.col_idx
+    own = -np.sum(lam_dev[rows] * X[cols], axis=1)
+    scale = np.sum(np.abs(lam_dev[rows]) * np.abs(X[cols]), axis=1)
+    err = np.abs(got - own)
+    assert np.all(err <= 1e-14 * scale + 0.0), f"GV pass error {np.max(err / np.maximum(scale, 1e-300)):.3e}"
+    bound = TOL * np.max(np.abs(lam_ref)) * np.sum(np.abs(X[cols]), axis=1)
+    assert np.all(np.abs(got - ref) <= bound), "GV propagated error above bound"
