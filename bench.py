@@ -110,15 +110,11 @@ def main():
         "spmv": lambda: ddf.ddf_plain_spmv(pA, vA, X, Y, k),
         "spmv_adj": lambda: ddf.ddf_plain_spmv_adjoint(pA, vA, X, Gy, GX, GVA, k),
     }
-    traffic = {"spmv": ddf.ddf_plan_traffic(pA, ddf.DDF_OP_SPMV, k),
-               "spmv_adj": ddf.ddf_plan_traffic(pA, ddf.DDF_OP_SPMV_ADJ, k)}
     if pL is not None:
         ops["sptrsv"] = lambda: ddf.ddf_sptrsv_v(pL, vL, Bv, Xs, k)
         ops["sptrsv_adj"] = lambda: ddf.ddf_sptrsv_adjoint(pL, vL, Xs, Gx, GB, GVL, k)
         plain["sptrsv"] = lambda: ddf.ddf_plain_sptrsv(pL, vL, Bv, Xs, k)
         plain["sptrsv_adj"] = lambda: ddf.ddf_plain_sptrsv_adjoint(pL, vL, Xs, Gx, GB, GVL, k)
-        traffic["sptrsv"] = ddf.ddf_plan_traffic(pL, ddf.DDF_OP_SPTRSV, k)
-        traffic["sptrsv_adj"] = ddf.ddf_plan_traffic(pL, ddf.DDF_OP_SPTRSV_ADJ, k)
 
     if not args.no_tune:
         t0 = time.time()
@@ -130,28 +126,58 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] autotune {time.time() - t0:.1f}s")
 
+    # algorithmic bytes per call, for the schedules the tuner settled on
+    traffic = {"spmv": ddf.ddf_plan_traffic(pA, ddf.DDF_OP_SPMV, k),
+               "spmv_adj": ddf.ddf_plan_traffic(pA, ddf.DDF_OP_SPMV_ADJ, k)}
+    if pL is not None:
+        traffic["sptrsv"] = ddf.ddf_plan_traffic(pL, ddf.DDF_OP_SPTRSV, k)
+        traffic["sptrsv_adj"] = ddf.ddf_plan_traffic(pL, ddf.DDF_OP_SPTRSV_ADJ, k)
+
     if args.profile_op:
-        fn = ops[args.profile_op]
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
-        log(f"[bench] ran {args.profile_op} x{args.steps}")
+        # a leg per name, each run --steps times (rocprofv3 counter and trace runs); "copy" is
+        # an elementwise copy of 64 Mi doubles (512 MiB read, 512 MiB written) to scale counters
+        for name in args.profile_op.split(","):
+            if name == "copy":
+                src = torch.rand(1 << 26, dtype=torch.float64, device=dev)
+                dst = torch.empty_like(src)
+                fn = lambda: torch.mul(src, 1.0, out=dst)  # noqa: E731
+            else:
+                fn = ops[name]
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            log(f"[bench] ran {name} x{args.steps}")
         return
 
     def step(table):
         for f in table.values():
             f()
 
-    def time_steps(table, n, warm):
+    def time_steps(table, n, warm, per_op=None):
+        """Average ms per step over n steps; with per_op, also each call's average from HIP
+        events recorded around it on the stream the calls launch on."""
         for _ in range(warm):
             step(table)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+        e0, e1 = ev(), ev()
+        marks = {name: [] for name in table} if per_op is not None else None
         e0.record()
         for _ in range(n):
-            step(table)
+            for name, f in table.items():
+                if marks is None:
+                    f()
+                else:
+                    a, b = ev(), ev()
+                    a.record()
+                    f()
+                    b.record()
+                    marks[name].append((a, b))
         e1.record()
         torch.cuda.synchronize()
+        if marks is not None:
+            for name, m in marks.items():
+                per_op[name] = sum(a.elapsed_time(b) for a, b in m) / len(m)
         return e0.elapsed_time(e1) / n
 
     def time_op(fn, reps):
@@ -165,16 +191,17 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    # timed region: K whole steps
-    ms = time_steps(ops, args.steps, args.warmup)
+    # timed region: K whole steps, each call bracketed by events
+    op_ms = {}
+    ms = time_steps(ops, args.steps, args.warmup, op_ms)
     if pL is not None:
         ddf.ddf_plan_sync_status(pL)
     log(f"[bench] DDF step {ms:.3f} ms")
     ms_plain = time_steps(plain, max(3, args.steps // 4), 1)
     log(f"[bench] plain step {ms_plain:.3f} ms")
     per_op = {}
-    for name, fn in ops.items():
-        t = time_op(fn, args.op_reps)
+    for name in ops:
+        t = op_ms[name]
         tp = time_op(plain[name], max(2, args.op_reps // 2))
         ba, bc, fl = traffic[name]
         per_op[name] = {"ms": round(t, 4), "gbps_alg": round(ba / t / 1e6, 1), "pct_peak": round(100 * ba / t / 1e6 / PEAK_GBPS, 2),
@@ -196,12 +223,21 @@ def main():
     bytes_step = sum(t[0] for t in traffic.values())
     value = bytes_step / (ms / 1e3) / 1e9
     value_plain = bytes_step / (ms_plain / 1e3) / 1e9
+    # the dominant kernel: each call of the step is one main launch (the solves add a small
+    # counter reset on the multi-block path)
+    info_L = ddf.ddf_plan_info(pL) if pL is not None else {}
+    info_A = ddf.ddf_plan_info(pA)
+    kernel_of = {"spmv": "k_spmv1" if k == 1 else "k_spmvN", "spmv_adj": "k_spmv1" if k == 1 else "k_spmvN"}
+    if pL is not None:
+        kernel_of["sptrsv"] = "k_solve_thin" if info_L["solve_path"] == 2 else "k_solve"
+        kernel_of["sptrsv_adj"] = "k_solve_thin" if info_L["solve_path_adj"] == 2 else "k_solve"
     dom = max(per_op, key=lambda n: per_op[n]["ms"])
-    kname = {"spmv": "k_spmv", "spmv_adj": "k_spmv", "sptrsv": "k_solve", "sptrsv_adj": "k_solve"}[dom]
+    kname = kernel_of[dom]
     ach = traffic[dom][0] / (per_op[dom]["ms"] / 1e3) / 1e9
     hbm = traffic_from_profiles(f"{kname}_{dom}", args.workload)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBPS, "unit": "GB/s",
-                "frac": round(ach / PEAK_GBPS, 4), "traffic": hbm, "kernel": f"{kname} ({dom})"}
+                "frac": round(ach / PEAK_GBPS, 4),
+                "traffic": hbm, "kernel": f"{kname} ({dom})", "bytes_alg_per_launch": traffic[dom][0]}
 
     cpu = None
     if not args.no_cpu:
@@ -223,8 +259,6 @@ def main():
                          f"{cpu_s * 1e3:.1f} ms/step, single-threaded plain C loops"}
         log(f"[bench] cpu oracle {cpu_s * 1e3:.1f} ms/step")
 
-    info_L = ddf.ddf_plan_info(pL) if pL is not None else {}
-    info_A = ddf.ddf_plan_info(pA)
     out = {
         "metric": "SpMV/SpTRSV fwd+adjoint effective HBM GB/s and % of peak vs plain, FP64",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -232,6 +266,7 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "n": A.n_rows, "nnz_A": A.nnz, "nnz_L": L.nnz if L is not None else 0,
                    "levels": info_L.get("n_parts", 0), "nrhs": k,
+                   "solve_kernel": {"fwd": kernel_of.get("sptrsv"), "adj": kernel_of.get("sptrsv_adj")},
                    "codelets_A_by_type": info_A["codelets_by_type"], "ops_A_by_type": info_A["ops_by_type"],
                    "codelets_L_by_type": info_L.get("codelets_by_type"),
                    "inspect_s": {"A": round(tA, 3), "L": round(tL, 3)}},

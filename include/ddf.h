@@ -74,7 +74,11 @@ typedef struct {
     int32_t solve_path;    /* solve kernel: 0 auto (single-block when every level fits one
                               1024-lane pass, else multi-block), 1 multi-block, 2 single-block
                               when possible                                                */
-    int32_t reserved[3];
+    int32_t thin_helpers;  /* single-block solve: helper blocks that pull the next levels'
+                              tables into the solver's L2; -1 default (2), 0 none, max 8  */
+    int32_t thin_ahead;    /* single-block solve: levels the helpers run ahead; 0 default
+                              (32), at least 8                                              */
+    int32_t reserved[1];
 } ddf_opts;
 
 typedef struct {
@@ -124,7 +128,10 @@ typedef struct {
     int32_t max_levels;
     double inspect_seconds;     /* wall time of the host inspector                   */
     uint64_t hash;              /* FNV-1a over the canonical tables                  */
-    int32_t ops_per_lane, rows_passes, xcd_remap, reserved;
+    int32_t ops_per_lane, rows_passes, xcd_remap;
+    int32_t solve_path;         /* kernel the solve uses: 1 multi-block, 2 single-block  */
+    int32_t solve_path_adj;     /* same for the adjoint solve (0 for SpMV plans)          */
+    int32_t reserved;
 } ddf_plan_info_t;
 
 typedef enum {
@@ -132,6 +139,7 @@ typedef enum {
     DDF_OP_SPMV_ADJ = 1,
     DDF_OP_SPTRSV = 2,
     DDF_OP_SPTRSV_ADJ = 3,
+    DDF_OP_SPTRSV_T = 4, /* the transposed solve alone (ddf_sptrsv_adjoint with d_gvals = NULL) */
 } ddf_op;
 
 /* Defaults for ddf_opts (window 64, adjoint plan on). */

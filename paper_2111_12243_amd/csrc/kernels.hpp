@@ -32,16 +32,25 @@ struct SpmvArgs {
 // slot and level one record of THIN_REC int32: row, value index of the diagonal, number of
 // ops (<= LOOKAHEAD), 0, value indices [LOOKAHEAD], columns [LOOKAHEAD]; G lanes per row.
 constexpr int THIN_REC = 12;
+constexpr int THIN_SW = 8; // per record: values of its 4 ops, diagonal, b and xf of its row, pad
 constexpr int THIN_THREADS = 1024;
 struct ThinArgs {
     const int32_t *rec;
     const int2 *lvl; // per level: first record, lanes in use
     int32_t nlev;
     int32_t lg;      // log2 lanes per row
-    int32_t k;
+    int32_t k;       // right-hand sides (at most the kernel's KT)
+    int32_t helpers; // blocks that pull upcoming levels into the solver's L2
+    int32_t ahead;   // levels the helpers may run ahead of the solver
+    int64_t n_rec;
     const double *vals;
     const double *b;
     double *x;
+    const double *xf;  // adjoint with value gradient: the forward solution
+    double *gv;        // adjoint: gradient of the values (NULL: not wanted)
+    double *stream;    // THIN_SW doubles per record, gathered before the solve
+    unsigned *progress; // levels the solver has finished (read by the helpers)
+    unsigned *sink;     // helpers' discard word (never read)
 };
 
 constexpr int LOOKAHEAD = 4;   // elements per lane a solve task loads before its wait

@@ -509,23 +509,37 @@ ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
     if (!D.thin_rec.empty()) {
         if (ddf_status s = upload(p, &D.d_thin_rec, D.thin_rec.data(), D.thin_rec.size())) return s;
         if (ddf_status s = upload(p, &D.d_thin_lvl, D.thin_lvl.data(), D.thin_lvl.size())) return s;
+        if (ddf_status s = dalloc(p, (void **)&D.d_thin_stream, D.thin_rec.size() / THIN_REC * THIN_SW * sizeof(double)))
+            return s;
     }
     return upload(p, &D.d_aux, D.aux.data(), D.aux.size());
 }
 
-bool use_thin(const DevTables &D, const SchedParams &sp) { return !D.thin_rec.empty() && sp.path != 1; }
+// the single-block kernel takes up to 8 right-hand sides in one pass
+bool use_thin(const DevTables &D, const SchedParams &sp, int32_t k) {
+    return !D.thin_rec.empty() && sp.path != 1 && k <= 8;
+}
 
-ddf_status thin_launch(const DevTables &D, int nlev, const double *vals, const double *b, double *x, int32_t k,
-                       hipStream_t s) {
+ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, int nlev, const double *vals,
+                       const double *b, double *x, int32_t k, hipStream_t s, const double *xf = nullptr,
+                       double *gv = nullptr) {
     ThinArgs t{};
     t.rec = D.d_thin_rec;
     t.lvl = reinterpret_cast<const int2 *>(D.d_thin_lvl);
     t.nlev = nlev;
     t.lg = D.thin_lg;
     t.k = k;
+    t.helpers = std::max(0, std::min(sp.helpers, 8));
+    t.ahead = std::max(8, sp.ahead);
+    t.n_rec = (int64_t)D.thin_rec.size() / THIN_REC;
     t.vals = vals;
     t.b = b;
     t.x = x;
+    t.xf = xf;
+    t.gv = gv;
+    t.stream = D.d_thin_stream;
+    t.progress = p->d_ctr + CTR_STRIDE + 16; // second counter line: error flag, then these
+    t.sink = p->d_ctr + CTR_STRIDE + 17;
     HIPCHK(launch_solve_thin(t, kt_for(k), s));
     return DDF_OK;
 }
@@ -630,6 +644,8 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         }
     }
     p->sp_f.path = p->sp_a.path = o.solve_path;
+    p->sp_f.helpers = p->sp_a.helpers = o.thin_helpers < 0 ? 2 : std::min(o.thin_helpers, 8);
+    p->sp_f.ahead = p->sp_a.ahead = o.thin_ahead <= 0 ? 32 : std::max(o.thin_ahead, 8);
     if (p->host_only) {
         ddf_status st = build_schedule(p, true, true);
         if (st) {
@@ -750,6 +766,8 @@ void ddf_opts_default(ddf_opts *o) {
     o->rows_passes = 2;
     o->xcd_remap = -1;
     o->solve_blocks = 0;
+    o->thin_helpers = -1;
+    o->thin_ahead = 0;
 }
 
 const char *ddf_version(void) { return "ddf-mi355x 0.1"; }
@@ -839,8 +857,8 @@ ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, d
     if ((!d_vals && p->nnz) || (!d_b && p->n_rows) || (!d_x && p->n_rows)) return fail(DDF_E_ARG, "NULL buffer");
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
     if (p->n_rows == 0) return DDF_OK;
-    if (use_thin(p->F, p->sp_f))
-        return thin_launch(p->F, (int)p->fwd[0].header[5], d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
+    if (use_thin(p->F, p->sp_f, nrhs))
+        return thin_launch(p, p->F, p->sp_f, (int)p->fwd[0].header[5], d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
     // the single matrix's right-hand-side count is a per-call argument (k_override)
     return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), p->F.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
                         kt_for(nrhs), (hipStream_t)stream);
@@ -910,25 +928,10 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
     if (d_gvals && (overlap(d_gvals, p->nnz * 8, d_gb, nb) || overlap(d_gvals, p->nnz * 8, d_x, nb)))
         return fail(DDF_E_ARG, "gvals overlaps another buffer");
     if (p->n_rows == 0) return DDF_OK;
-    if (use_thin(p->T, p->sp_a)) {
-        // single-block transposed solve, then the GV pass as one parallel launch
-        hipStream_t s = (hipStream_t)stream;
-        if (ddf_status st = thin_launch(p->T, (int)p->adj[0].header[5], d_vals, d_gx, d_gb, nrhs, s)) return st;
-        if (!d_gvals) return DDF_OK;
-        SpmvArgs a{};
-        a.tasks = p->T.d_tasks + p->n_solve_tasks_adj;
-        a.ntasks = (int32_t)((int64_t)p->T.tasks.size() - p->n_solve_tasks_adj);
-        a.k = nrhs;
-        a.remap = p->sp_a.remap;
-        a.cods2 = p->F.d_cods;
-        a.aux2 = p->F.d_aux;
-        a.g = d_gb;
-        a.x2 = d_x;
-        a.gv = d_gvals;
-        a.gv_sign = -1.0;
-        a.gv_diag = 1;
-        HIPCHK(launch_spmv(a, false, s));
-        return DDF_OK;
+    if (use_thin(p->T, p->sp_a, nrhs)) {
+        // single-block transposed solve with the value gradient fused
+        return thin_launch(p, p->T, p->sp_a, (int)p->adj[0].header[5], d_vals, d_gx, d_gb, nrhs, (hipStream_t)stream,
+                           d_x, d_gvals);
     }
     int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
     return solve_launch(p, p->T, 0, nt, p->T.n_counters, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
@@ -1173,6 +1176,10 @@ ddf_status ddf_plan_info(ddf_plan_t p, ddf_plan_info_t *o) {
     o->ops_per_lane = p->sp_f.ops_per_lane;
     o->rows_passes = p->sp_f.passes;
     o->xcd_remap = p->sp_f.remap;
+    if (p->kind != 0) {
+        o->solve_path = use_thin(p->F, p->sp_f, 1) ? 2 : 1;
+        o->solve_path_adj = p->has_adj ? (use_thin(p->T, p->sp_a, 1) ? 2 : 1) : 0;
+    }
     return DDF_OK;
 }
 
@@ -1238,7 +1245,7 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
         break;
     case DDF_OP_SPTRSV:
-        ba = 8 * nnz + (use_thin(p->F, p->sp_f) ? p->F.thin_bytes() : p->F.bytes()) + 16 * vk;
+        ba = 8 * nnz + (!p->batch && use_thin(p->F, p->sp_f, nrhs) ? p->F.thin_bytes() : p->F.bytes()) + 16 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
         if (p->batch) {
             for (size_t b = 0; b < p->mats.size(); b++) {
@@ -1250,9 +1257,8 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         }
         break;
     case DDF_OP_SPTRSV_ADJ:
-        if (p->has_adj && use_thin(p->T, p->sp_a))
-            ba = 16 * nnz + p->T.thin_bytes() + Fca + (int64_t)(p->T.tasks.size() - p->n_solve_tasks_adj) * sizeof(Task) +
-                 32 * vk;
+        if (p->has_adj && !p->batch && use_thin(p->T, p->sp_a, nrhs))
+            ba = 16 * nnz + p->T.thin_bytes() + 24 * vk;
         else
             ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 32 * vk;
         bc = 20 * nnz + 4 * (n + 1) + 24 * vk;
@@ -1264,6 +1270,16 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         } else {
             fl = kf * (2 * (nnz - n) + n) + nnz * (2 * kf - 1);
         }
+        break;
+    case DDF_OP_SPTRSV_T:
+        if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+        if (!p->batch && use_thin(p->T, p->sp_a, nrhs))
+            ba = 8 * nnz + p->T.thin_bytes() + 16 * vk;
+        else
+            ba = 8 * nnz + (int64_t)p->T.cods.size() * sizeof(DCod) + (int64_t)p->T.aux.size() * 4 +
+                 p->n_solve_tasks_adj * (int64_t)(sizeof(Task) + 16) + 16 * vk;
+        bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
+        fl = p->batch ? 0 : kf * (2 * (nnz - n) + n);
         break;
     default: return fail(DDF_E_ARG, "unknown op");
     }
@@ -1314,12 +1330,12 @@ void load_tune_file() {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // one entry per line: "key": [ops_per_lane, passes, remap, blocks, path],
+        // one entry per line: "key": [ops_per_lane, passes, remap, blocks, path, helpers, ahead],
         size_t q1 = line.find('"'), q2 = line.find('"', q1 + 1), b = line.find('[');
         if (q1 == std::string::npos || q2 == std::string::npos || b == std::string::npos) continue;
         SchedParams sp;
-        if (sscanf(line.c_str() + b, "[%d, %d, %d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap, &sp.blocks,
-                   &sp.path) == 5)
+        if (sscanf(line.c_str() + b, "[%d, %d, %d, %d, %d, %d, %d]", &sp.ops_per_lane, &sp.passes, &sp.remap,
+                   &sp.blocks, &sp.path, &sp.helpers, &sp.ahead) == 7)
             g_tune_cache[line.substr(q1 + 1, q2 - q1 - 1)] = sp;
     }
 }
@@ -1332,7 +1348,8 @@ void save_tune_file() {
     size_t i = 0;
     for (auto &kv : g_tune_cache)
         f << "  \"" << kv.first << "\": [" << kv.second.ops_per_lane << ", " << kv.second.passes << ", "
-          << kv.second.remap << ", " << kv.second.blocks << ", " << kv.second.path << "]"
+          << kv.second.remap << ", " << kv.second.blocks << ", " << kv.second.path << ", " << kv.second.helpers
+          << ", " << kv.second.ahead << "]"
           << (++i < g_tune_cache.size() ? "," : "") << "\n";
     f << "}\n";
 }
@@ -1343,6 +1360,7 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
     if (ddf_status s = need_device(p)) return s;
     if (p->batch) nrhs = 1;
     else if (ddf_status s = check_nrhs(nrhs)) return s;
+    if (op < DDF_OP_SPMV || op > DDF_OP_SPTRSV_ADJ) return fail(DDF_E_ARG, "autotune takes the four executor ops");
     bool is_spmv = op == DDF_OP_SPMV || op == DDF_OP_SPMV_ADJ;
     if (is_spmv != (p->kind == DDF_SPMV)) return fail(DDF_E_KIND, "op does not match the plan kind");
     bool adjop = op == DDF_OP_SPMV_ADJ || op == DDF_OP_SPTRSV_ADJ;
@@ -1389,21 +1407,24 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
     // candidates: SpMV varies lanes per row, row passes and XCD block order; the solve
     // varies lanes per row, row passes and whether small levels run as THIN ranges
     struct Cand {
-        int opl, ps, rm, blocks, path;
+        int opl, ps, rm, blocks, path, helpers, ahead;
     };
     std::vector<Cand> cands;
-    cands.push_back({target.ops_per_lane, target.passes, target.remap, target.blocks, target.path}); // current first
+    cands.push_back({target.ops_per_lane, target.passes, target.remap, target.blocks, target.path, target.helpers,
+                     target.ahead}); // current first
     if (is_spmv) {
         for (int rm : {1, 0})
             for (int opl : {1, 2, 4, 8, 16})
-                for (int ps : {1, 2, 4}) cands.push_back({opl, ps, rm, 0, 0});
+                for (int ps : {1, 2, 4}) cands.push_back({opl, ps, rm, 0, 0, target.helpers, target.ahead});
     } else {
         const DevTables &D = adjop ? p->T : p->F;
-        if (!D.thin_rec.empty()) cands.push_back({target.ops_per_lane, target.passes, target.remap, 0, 2});
+        if (!D.thin_rec.empty() && nrhs <= 8)
+            for (int hp : {2, 0, 4, 1})
+                for (int ah : {32, 96}) cands.push_back({target.ops_per_lane, target.passes, target.remap, 0, 2, hp, ah});
         const int full = 4 * num_cu(); // up to four 256-thread blocks per CU
         for (int blocks : {full, full / 4, full / 16})
             for (int opl : {4, 2, 8})
-                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, blocks, 1});
+                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, blocks, 1, target.helpers, target.ahead});
     }
     for (const Cand &cd : cands) {
         if (st || (budget_ms > 0 && spent > budget_ms)) break;
@@ -1412,6 +1433,8 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
         target.remap = cd.rm;
         target.blocks = cd.blocks;
         target.path = cd.path;
+        target.helpers = cd.helpers;
+        target.ahead = cd.ahead;
         if ((st = build_schedule(p, !adjop, adjop))) break;
         if ((st = run())) break;
         (void)hipEventRecord(e0, s);

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libddf.so")
 
 DDF_SPMV, DDF_SPTRSV_LOWER = 0, 1
-DDF_OP_SPMV, DDF_OP_SPMV_ADJ, DDF_OP_SPTRSV, DDF_OP_SPTRSV_ADJ = 0, 1, 2, 3
+DDF_OP_SPMV, DDF_OP_SPMV_ADJ, DDF_OP_SPTRSV, DDF_OP_SPTRSV_ADJ, DDF_OP_SPTRSV_T = 0, 1, 2, 3, 4
 STATUS = ["DDF_OK", "DDF_E_ARG", "DDF_E_CSR", "DDF_E_NOT_LOWER", "DDF_E_NO_DIAG", "DDF_E_KIND",
           "DDF_E_NOMEM", "DDF_E_HIP", "DDF_E_DEVICE", "DDF_E_UNSUPPORTED"]
 (DDF_OK, DDF_E_ARG, DDF_E_CSR, DDF_E_NOT_LOWER, DDF_E_NO_DIAG, DDF_E_KIND, DDF_E_NOMEM, DDF_E_HIP,
@@ -44,7 +44,8 @@ class ddf_opts(C.Structure):
     _fields_ = [("window", C.c_int32), ("build_adjoint", C.c_int32), ("host_only", C.c_int32),
                 ("threads", C.c_int32), ("ops_per_lane", C.c_int32), ("rows_passes", C.c_int32),
                 ("xcd_remap", C.c_int32), ("solve_blocks", C.c_int32),
-                ("solve_path", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("solve_path", C.c_int32), ("thin_helpers", C.c_int32), ("thin_ahead", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class ddf_csr_host(C.Structure):
@@ -75,7 +76,8 @@ class ddf_plan_info_t(C.Structure):
                 ("dev_plan_bytes", C.c_int64), ("dev_plan_bytes_adj", C.c_int64),
                 ("has_adjoint", C.c_int32), ("max_levels", C.c_int32), ("inspect_seconds", C.c_double),
                 ("hash", C.c_uint64), ("ops_per_lane", C.c_int32), ("rows_passes", C.c_int32),
-                ("xcd_remap", C.c_int32), ("reserved", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("solve_path", C.c_int32), ("solve_path_adj", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _LIB = None

@@ -227,24 +227,28 @@ def _rows_from(TF, task):
     return c, meta, out
 
 
-def thin_solve(tabs, L, B, vals=None):
+def thin_solve(tabs, L, B, vals=None, Xf=None):
     """Replays the single-block solve: level by level, G lanes per row; checks that every
-    solution entry read was written by an earlier level and every row is solved once."""
+    solution entry read was written by an earlier level and every row is solved once.  With
+    Xf (transposed solve), also returns the fused value gradient: -<x[col], Xf[row]> at each
+    op's value index and -<x[row], Xf[row]> at the diagonal."""
     rec, lvl, lg = tabs["thin_rec"], tabs["thin_lvl"], tabs["thin_lg"]
     v = L.values if vals is None else vals
     n, k = B.shape
     G = 1 << lg
     X = np.full((n, k), np.nan)
+    gv = np.full(v.shape[0], np.nan) if Xf is not None else None
     level_of = np.full(n, -1)
     for l, (first, lanes) in enumerate(lvl):
         assert 0 < lanes <= 1024 and lanes % G == 0
         acc = {}
         diag = {}
+        dpos = {}
         for s in range(lanes):
-            row, dpos, cnt = (int(x) for x in rec[first + s][:3])
+            row, dp, cnt = (int(x) for x in rec[first + s][:3])
             if s % G == 0:
                 acc[row] = np.zeros(k)
-                diag[row] = v[dpos]
+                diag[row] = v[dp]
             else:
                 assert row in acc
             assert 0 <= cnt <= 4
@@ -252,9 +256,16 @@ def thin_solve(tabs, L, B, vals=None):
                 vi, col = int(rec[first + s][4 + j]), int(rec[first + s][8 + j])
                 assert 0 <= level_of[col] < l, f"row {row} reads x[{col}] not solved in an earlier level"
                 acc[row] += v[vi] * X[col]
+                if gv is not None:
+                    assert np.isnan(gv[vi])
+                    gv[vi] = -np.dot(X[col], Xf[row])
+            if gv is not None and s % G == 0:
+                dpos[row] = int(rec[first + s][1])
         for row, a in acc.items():
             assert level_of[row] == -1
             X[row] = (B[row] - a) / diag[row]
             level_of[row] = l
+            if gv is not None:
+                gv[dpos[row]] = -np.dot(X[row], Xf[row])
     assert (level_of >= 0).all()
-    return X
+    return X if gv is None else (X, gv)

@@ -46,8 +46,10 @@ def replay_solve(L, k=2, seed=0, **kw):
     if F["thin_rec"].shape[0]:
         check_solve(L, B, E.thin_solve(F, L, B), ref)
     if T["thin_rec"].shape[0]:
-        lam_t = E.thin_solve(T, U, G, vals=L.values)
-        check_solve(L, G, lam_t, O.sptrsv_adj(L, ref, G)[0], transposed=True)
+        lam_t, gv_t = E.thin_solve(T, U, G, vals=L.values, Xf=ref)
+        GBt, GVt = O.sptrsv_adj(L, ref, G)
+        check_solve(L, G, lam_t, GBt, transposed=True)
+        check_gv_solve(L, ref, lam_t, GBt, gv_t, GVt)
     lam, gv = E.solve(T, U, G, kind=2, vals=L.values, perm=perm, fwd_tabs=F, Xf=ref, with_gv=True)
     GBr, GVr = O.sptrsv_adj(L, ref, G)
     check_solve(L, G, lam, GBr, transposed=True)
