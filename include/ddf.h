@@ -259,11 +259,22 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
 typedef struct {
     const int32_t *cods, *aux, *tasks, *sync, *tasksN;
     int64_t n_cods, aux_len, n_tasks, n_counters, n_tasksN;
-    const int32_t *thin_rec; /* single-block solve: [n_thin_rec][12] per lane slot: row, value
-                                index of the diagonal, ops, 0, value indices[4], columns[4] */
-    const int32_t *thin_lvl; /* [n_levels][2] first record, lane slots in use (0 if absent)  */
+    const int32_t *thin_rec; /* single-block solve: [n_thin_rec][16] per lane slot: row, value
+                                index of the diagonal, ops, placeholder flag (levels start on
+                                64-record boundaries), value indices[4], columns[4],
+                                operand codes[4]: INT32_MIN empty; >= 0 plan position (first
+                                record / lane slots per row) of a row read from global
+                                memory; else -(1 + ring slot)                               */
+    const int32_t *thin_lvl; /* [n][2] first record, lane slots in use, per level, then empty
+                                levels up to a multiple of 4 plus 4 (absent: n = 0)        */
     int64_t n_thin_rec, n_thin_lvl;
-    int32_t thin_lg, reserved;
+    int32_t thin_lg;          /* log2 lane slots per row                                       */
+    int32_t thin_ring_rows;   /* operand codes < 0: slot = -(code + 1) = (level mod ring_levels)
+                                 * ring_rows + position of the row in its level               */
+    int32_t thin_ring_levels;
+    int32_t thin_ngs;         /* op slots per lane (the lowest) that may read global memory   */
+    int32_t thin_block;       /* threads of the solving block                                  */
+    int32_t reserved;
 } ddf_device_tables_t;
 ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
 

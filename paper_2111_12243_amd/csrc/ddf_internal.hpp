@@ -89,9 +89,15 @@ struct DevTables {
     std::vector<int32_t> thin_rec;     // single-block solve records (empty if not eligible)
     std::vector<int32_t> thin_lvl;     // per level: first record, lanes
     int32_t thin_lg = 0;
+    int32_t thin_R = 0;                // ring rows (widest level)
+    int32_t thin_RW = 0;               // ring levels
+    int32_t thin_nlev_pad = 0;         // levels rounded up to a multiple of 3
+    int32_t thin_ngs = 0;              // op slots per lane that may hold a global operand
+    int32_t thin_block = 64;           // threads of the solving block (widest level, rounded to 64)
+    double *d_thin_xs = nullptr;       // solutions in plan order
     int32_t *d_thin_rec = nullptr;
     int32_t *d_thin_lvl = nullptr;
-    double *d_thin_stream = nullptr;   // per-call gathered values, 8 doubles per record
+    double *d_thin_stream = nullptr;   // per-call stream, THIN_SW doubles per record
     DCod *d_cods = nullptr;
     int32_t *d_aux = nullptr;
     Task *d_tasks = nullptr;

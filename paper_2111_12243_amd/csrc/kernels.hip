@@ -621,24 +621,19 @@ __global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Single-block solve for matrices whose every level fits one pass of the block.  One lane
-// slot per (row, lane-of-row); levels are separated by block barriers and solution values stay
-// in the CU's caches (the block is the only writer).
+// Single-block solve for matrices whose every level fits one pass of the block: one lane slot
+// per (row, lane-of-row), levels separated by block barriers.
 //
-// Vector memory operations of a wave complete in issue order, so a wait for this level's
-// operands also waits for every load issued before them.  The level therefore issues its
-// operand loads first and only then fetches the next level's records (whose latency then
-// overlaps the arithmetic), and the per-call values come from a stream gathered in record
-// order beforehand, so a fetch is one set of contiguous loads with no dependent gather.
-// Helper blocks dispatched to the solver's XCD pull the records and stream of the levels
-// just ahead into the shared L2, so that fetch hits there rather than in HBM.
+// One CU runs the whole solve, so its vector memory pipeline is the limit: a level costs
+// roughly the vector memory instructions its waves issue.  Only waves with lanes in use at a
+// level fetch or compute for it, and a lane fetches one stream entry (operand codes, values,
+// diagonal, b) plus only the operands that must come from global memory.  Operands solved in
+// the last ring_levels levels come from an LDS ring.  A wave's vector memory operations
+// complete in issue order, so nothing on a level's critical path reads global memory: the
+// stream entry is fetched four levels ahead and the global operands (rows final by then) two
+// levels ahead.  Helper blocks dispatched to the solver's XCD pull the stream of the levels
+// just ahead into the shared L2.
 // ------------------------------------------------------------------------------------------
-struct ThinLane {
-    int row, cnt, dpos;
-    int col[LOOKAHEAD], vidx[LOOKAHEAD]; // vidx, dpos: value gradient only
-    double v[LOOKAHEAD], d, b, xf;
-    bool act;
-};
 
 // level table entry through the constant address space: a scalar load, counted apart from the
 // vector memory operations
@@ -648,108 +643,112 @@ __device__ __forceinline__ int2 thin_lvl(const ThinArgs &a, int l) {
     return make_int2((int)(unsigned)(e & 0xffffffffll), (int)(e >> 32));
 }
 
-template <bool GV>
-__device__ __forceinline__ void thin_fetch(const ThinArgs &a, int l, int s, ThinLane &t) {
+// whether the wave holding lane s has a lane in use at a level (uniform over the wave)
+__device__ __forceinline__ bool thin_wave_on(int2 lv, int s) { return (s & ~(WAVE - 1)) < lv.y; }
+
+template <int KT> struct ThinA {
+    int code[LOOKAHEAD];
+    double v[LOOKAHEAD], d, b[KT];
+};
+template <int KT, int NGS> struct ThinB {
+    double gx[NGS > 0 ? NGS : 1][KT]; // operands gathered from global memory
+};
+
+// Fetches are issued by every wave, also one with no lane in use at the level (it reads the
+// level's first 64 entries): a fetch on one path only would make the compiler's wait counts
+// cover it on both.
+template <int KT>
+__device__ __forceinline__ void thin_fetch_a(const ThinArgs &a, int l, int s, ThinA<KT> &t) {
     const int2 lv = thin_lvl(a, l);
-    t.act = s < lv.y;
-    // idle lanes read the level's first record (in bounds) and stay idle
-    const int64_t p = lv.x + (t.act ? s : 0);
-    const int4 *q = reinterpret_cast<const int4 *>(a.rec + p * THIN_REC);
-    const int4 h = q[0], c = q[2];
-    const double2 *w = reinterpret_cast<const double2 *>(a.stream + p * THIN_SW);
-    const double2 w0 = w[0], w1 = w[1], w2 = w[2];
-    t.row = h.x;
-    t.cnt = h.z;
-    t.col[0] = c.x; t.col[1] = c.y; t.col[2] = c.z; t.col[3] = c.w;
-    t.v[0] = w0.x; t.v[1] = w0.y; t.v[2] = w1.x; t.v[3] = w1.y;
-    t.d = w2.x;
-    t.b = w2.y;
-    if (GV) {
-        const int4 v = q[1];
-        t.dpos = h.y;
-        t.vidx[0] = v.x; t.vidx[1] = v.y; t.vidx[2] = v.z; t.vidx[3] = v.w;
-        t.xf = w[3].x;
+    const int64_t p = (int64_t)lv.x + (thin_wave_on(lv, s) ? s : (s & (WAVE - 1)));
+    const double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
+    const int4 c = *reinterpret_cast<const int4 *>(w);
+    const double2 v01 = *reinterpret_cast<const double2 *>(w + 128);
+    const double2 v23 = *reinterpret_cast<const double2 *>(w + 256);
+    const double2 db = *reinterpret_cast<const double2 *>(w + 384);
+    t.code[0] = c.x; t.code[1] = c.y; t.code[2] = c.z; t.code[3] = c.w;
+    t.v[0] = v01.x; t.v[1] = v01.y; t.v[2] = v23.x; t.v[3] = v23.y;
+    t.d = db.x;
+    t.b[0] = db.y;
+    if (KT > 1) t.b[1] = reinterpret_cast<const double2 *>(w + 512)->x;
+}
+
+template <int KT, int NGS>
+__device__ __forceinline__ void thin_fetch_b(const ThinArgs &a, const ThinA<KT> &t, ThinB<KT, NGS> &u) {
+#pragma unroll
+    for (int j = 0; j < NGS; j++) {
+        // ring codes and empty slots read position 0 (in bounds; not used)
+        const int64_t c = max(t.code[j], 0);
+        if (KT == 1) {
+            u.gx[j][0] = a.xs[c];
+        } else {
+            const double2 q = *reinterpret_cast<const double2 *>(a.xs + c * KT);
+            u.gx[j][0] = q.x;
+            u.gx[j][KT - 1] = q.y;
+        }
     }
 }
 
-template <int KT, bool GV>
-__device__ __forceinline__ void thin_level(const ThinArgs &a, int l, int s, int g, int G, ThinLane &t, ThinLane &nx) {
-    const int k = a.k;
-    // this level's operands (column fillers of unused op slots are valid rows)
-    double xv[LOOKAHEAD][KT];
+template <int KT, int NGS>
+__device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, int g, int G, const ThinA<KT> &t,
+                                             const ThinB<KT, NGS> &u, double *ring) {
+    const int2 lv = thin_lvl(a, l);
+    double acc[KT];
 #pragma unroll
-    for (int j = 0; j < LOOKAHEAD; j++)
-#pragma unroll
-        for (int r = 0; r < KT; r++) xv[j][r] = a.x[(int64_t)t.col[j] * k + min(r, k - 1)];
-    double bv[KT], xf[KT];
-    if (KT > 1) {
-#pragma unroll
-        for (int r = 0; r < KT; r++) {
-            bv[r] = a.b[(int64_t)t.row * k + min(r, k - 1)];
-            xf[r] = GV ? a.xf[(int64_t)t.row * k + min(r, k - 1)] : 0.0;
-        }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    // unconditional (the last level fetches itself again): a fetch on one path only would
-    // make the compiler's wait counts cover it on both
-    thin_fetch<GV>(a, min(l + 1, a.nlev - 1), s, nx);
-    __builtin_amdgcn_sched_barrier(0);
-    if (KT == 1) {
-        bv[0] = t.b;
-        xf[0] = GV ? t.xf : 0.0;
-    }
-    double acc[KT], gacc[LOOKAHEAD];
-#pragma unroll
-    for (int r = 0; r < KT; r++) acc[r] = 0.0;
+    for (int rr = 0; rr < KT; rr++) acc[rr] = 0.0;
 #pragma unroll
     for (int j = 0; j < LOOKAHEAD; j++) {
-        gacc[j] = 0.0;
-        const bool on = j < t.cnt;
+        const int c = t.code[j];
+        const bool used = c != THIN_UNUSED;
+        const int idx = (c < 0 && used) ? -(c + 1) : 0;
 #pragma unroll
-        for (int r = 0; r < KT; r++) {
-            const double xr = on ? xv[j][r] : 0.0;
-            acc[r] = fma(t.v[j], xr, acc[r]);
-            if (GV && r < k) gacc[j] = fma(xr, xf[r], gacc[j]);
+        for (int rr = 0; rr < KT; rr++) {
+            double xo = ring[idx * KT + rr];
+            if (j < NGS) xo = c >= 0 ? u.gx[j < NGS ? j : 0][rr] : xo;
+            acc[rr] = fma(t.v[j], used ? xo : 0.0, acc[rr]);
         }
     }
     group_sum<KT>(acc, G);
-    double gd[1] = {0.0};
-    if (t.act) {
-        const int64_t rb = (int64_t)t.row * k;
+    if (s < lv.y) {
+        const int pos = s >> a.lg;
+        const int64_t rp = ((int64_t)lv.x >> a.lg) + pos; // plan position of the row
+        const int slot = (l & (a.ring_levels - 1)) * a.ring_rows + pos;
 #pragma unroll
-        for (int r = 0; r < KT; r++)
-            if ((r & (G - 1)) == g && r < k) {
-                const double xn = (bv[r] - acc[r]) / t.d;
-                a.x[rb + r] = xn;
-                if (GV) gd[0] = fma(xn, xf[r], gd[0]);
+        for (int rr = 0; rr < KT; rr++)
+            if ((rr & (G - 1)) == g && rr < a.k) {
+                const double xn = (t.b[rr] - acc[rr]) / t.d;
+                a.xs[rp * KT + rr] = xn;
+                ring[slot * KT + rr] = xn;
             }
     }
-    if (GV) {
-        // value gradient of the transposed solve: entry (c, row) of L gets -<lambda_c, xf_row>,
-        // the diagonal -<lambda_row, xf_row>
-        group_sum<1>(gd, G);
-        if (t.act) {
-#pragma unroll
-            for (int j = 0; j < LOOKAHEAD; j++)
-                if (j < t.cnt) a.gv[t.vidx[j]] = -gacc[j];
-            if (g == 0) a.gv[t.dpos] = -gd[0];
-        }
-    }
-    if (s == 0 && (l & 7) == 7)
+}
+
+// One level: solve it, then gather the global operands of the level two ahead and fetch the
+// stream entry of the level four ahead (into the slot this level used).
+template <int KT, int NGS>
+__device__ __forceinline__ void thin_step(const ThinArgs &a, int l, int s, int g, int G, ThinA<KT> &a0,
+                                          ThinB<KT, NGS> &b0, const ThinA<KT> &a2, double *ring) {
+    thin_compute<KT, NGS>(a, l, s, g, G, a0, b0, ring);
+    __builtin_amdgcn_sched_barrier(0);
+    thin_fetch_b<KT, NGS>(a, a2, b0);
+    thin_fetch_a<KT>(a, l + 4, s, a0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (s == 0 && (l & 3) == 3)
         __hip_atomic_store(a.progress, (unsigned)(l + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
 }
+
 // Helper blocks: each wave takes every nw-th level and touches each 128-byte line of its
-// records and stream entries, staying at most `ahead` levels in front of the solver.  A helper
-// that waits past its poll limit just stops (the solver never waits for it).
+// stream entries, staying at most `ahead` levels in front of the solver.  A helper that waits
+// past its poll limit just stops (the solver never waits for it).
 __device__ void thin_helper(const ThinArgs &a) {
     const int h = (int)blockIdx.x / 8 - 1;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int wpb = THIN_THREADS / WAVE, nw = a.helpers * wpb;
+    const int wpb = (int)blockDim.x / WAVE, nw = a.helpers * wpb;
     unsigned sink = 0;
     int seen = 0;
     int64_t polls = 0;
-    for (int l = 1 + h * wpb + wave; l < a.nlev; l += nw) {
+    for (int l = 3 + h * wpb + wave; l < a.nlev; l += nw) {
         while (seen + a.ahead < l) {
             seen = __builtin_amdgcn_readfirstlane((int)cload_u(a.progress));
             if (seen + a.ahead >= l) break;
@@ -757,13 +756,8 @@ __device__ void thin_helper(const ThinArgs &a) {
             __builtin_amdgcn_s_sleep(4);
         }
         const int2 lv = thin_lvl(a, l);
-        const uintptr_t r0 = reinterpret_cast<uintptr_t>(a.rec + (int64_t)lv.x * THIN_REC);
-        const uintptr_t r1 = r0 + (uintptr_t)lv.y * THIN_REC * 4;
         const uintptr_t s0 = reinterpret_cast<uintptr_t>(a.stream + (int64_t)lv.x * THIN_SW);
-        const uintptr_t s1 = s0 + (uintptr_t)lv.y * THIN_SW * 8;
-#pragma unroll 4
-        for (uintptr_t o = (r0 & ~uintptr_t(127)) + lane * 128; o < r1; o += WAVE * 128)
-            sink ^= *reinterpret_cast<const unsigned *>(o);
+        const uintptr_t s1 = s0 + (uintptr_t)((lv.y + 63) & ~63) * THIN_SW * 8;
 #pragma unroll 4
         for (uintptr_t o = (s0 & ~uintptr_t(127)) + lane * 128; o < s1; o += WAVE * 128)
             sink ^= *reinterpret_cast<const unsigned *>(o);
@@ -771,7 +765,7 @@ __device__ void thin_helper(const ThinArgs &a) {
     if (sink == 0x9e3779b9u) *a.sink = sink; // keeps the loads
 }
 
-template <int KT, bool GV>
+template <int KT, int NGS>
 __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
     static_assert(LOOKAHEAD == 4, "record layout");
     if (blockIdx.x != 0) {
@@ -779,31 +773,82 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
         if (blockIdx.x % 8 == 0) thin_helper(a);
         return;
     }
+    extern __shared__ double ring[];
     const int s = threadIdx.x;
     const int G = 1 << a.lg, g = s & (G - 1);
-    ThinLane A, B;
-    thin_fetch<GV>(a, 0, s, A);
-    for (int l = 0; l < a.nlev; l += 2) {
-        thin_level<KT, GV>(a, l, s, g, G, A, B);
-        if (l + 1 < a.nlev) thin_level<KT, GV>(a, l + 1, s, g, G, B, A);
+    ThinA<KT> A0, A1, A2, A3;
+    ThinB<KT, NGS> B0, B1;
+    // same issue order as the loop's steady state (gathers for l + 1, then stream l + 3), so
+    // the compiler's wait counts at the loop head agree on both entries
+    thin_fetch_a<KT>(a, 0, s, A0);
+    thin_fetch_a<KT>(a, 1, s, A1);
+    __builtin_amdgcn_sched_barrier(0);
+    thin_fetch_b<KT, NGS>(a, A0, B0);
+    thin_fetch_a<KT>(a, 2, s, A2);
+    __builtin_amdgcn_sched_barrier(0);
+    thin_fetch_b<KT, NGS>(a, A1, B1);
+    thin_fetch_a<KT>(a, 3, s, A3);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int l = 0; l < a.nlev_pad; l += 4) {
+        thin_step<KT, NGS>(a, l, s, g, G, A0, B0, A2, ring);
+        thin_step<KT, NGS>(a, l + 1, s, g, G, A1, B1, A3, ring);
+        thin_step<KT, NGS>(a, l + 2, s, g, G, A2, B0, A0, ring);
+        thin_step<KT, NGS>(a, l + 3, s, g, G, A3, B1, A1, ring);
     }
 }
 
-// Per-call gather of the values (and b, xf of the first right-hand side) into record order.
-// Also clears the solver's progress word before the solve starts.
-template <bool GV>
+// Per-call gather, in record order, of each slot's operand codes, values (0 for empty slots),
+// diagonal and b.  Also clears the solver's progress word before the solve starts.
 __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p == 0) *a.progress = 0u;
     if (p >= a.n_rec) return;
     const int4 *q = reinterpret_cast<const int4 *>(a.rec + p * THIN_REC);
-    const int4 h = q[0], v = q[1];
+    const int4 h = q[0], v = q[1], c = q[3];
     const int64_t rb = (int64_t)h.x * a.k;
-    double2 *w = reinterpret_cast<double2 *>(a.stream + p * THIN_SW);
-    w[0] = make_double2(a.vals[v.x], a.vals[v.y]);
-    w[1] = make_double2(a.vals[v.z], a.vals[v.w]);
-    w[2] = make_double2(a.vals[h.y], a.b[rb]);
-    if (GV) w[3] = make_double2(a.xf[rb], 0.0);
+    double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
+    *reinterpret_cast<int4 *>(w) = c;
+    *reinterpret_cast<double2 *>(w + 128) =
+        make_double2(c.x != THIN_UNUSED ? a.vals[v.x] : 0.0, c.y != THIN_UNUSED ? a.vals[v.y] : 0.0);
+    *reinterpret_cast<double2 *>(w + 256) =
+        make_double2(c.z != THIN_UNUSED ? a.vals[v.z] : 0.0, c.w != THIN_UNUSED ? a.vals[v.w] : 0.0);
+    *reinterpret_cast<double2 *>(w + 384) = make_double2(a.vals[h.y], a.b[rb]);
+    if (a.kt > 1) *reinterpret_cast<double2 *>(w + 512) = make_double2(a.k > 1 ? a.b[rb + 1] : 0.0, 0.0);
+}
+
+// Solutions from plan order into row order.
+__global__ __launch_bounds__(256) void k_thin_scatter(ThinArgs a) {
+    const int64_t rp = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (rp >= a.n) return;
+    const int32_t *q = a.rec + (rp << a.lg) * THIN_REC;
+    if (q[3]) return; // placeholder
+    const int64_t row = q[0];
+    for (int r = 0; r < a.k; r++) a.x[row * a.k + r] = a.xs[rp * a.kt + r];
+}
+
+// Value gradient of the transposed solve, after the scatter: entry (c, row) of L (an op of
+// record row `row`, column c) gets -<lambda_c, xf_row>; the diagonal -<lambda_row, xf_row>
+// (first lane of the row).
+__global__ __launch_bounds__(256) void k_thin_gv(ThinArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.n_rec) return;
+    const int4 *q = reinterpret_cast<const int4 *>(a.rec + p * THIN_REC);
+    const int4 h = q[0], vi = q[1], c = q[2], cd = q[3];
+    const int k = a.k;
+    const int64_t rb = (int64_t)h.x * k;
+    const int vv[4] = {vi.x, vi.y, vi.z, vi.w}, cc[4] = {c.x, c.y, c.z, c.w}, co[4] = {cd.x, cd.y, cd.z, cd.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        if (co[j] != THIN_UNUSED) {
+            double t = 0.0;
+            for (int r = 0; r < k; r++) t = fma(a.x[(int64_t)cc[j] * k + r], a.xf[rb + r], t);
+            a.gv[vv[j]] = -t;
+        }
+    if ((p & ((1 << a.lg) - 1)) == 0 && h.w == 0) {
+        double t = 0.0;
+        for (int r = 0; r < k; r++) t = fma(a.x[rb + r], a.xf[rb + r], t);
+        a.gv[h.y] = -t;
+    }
 }
 
 __global__ void k_reset(unsigned *p, int64_t n) {
@@ -992,23 +1037,24 @@ hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_solve_thin(const ThinArgs &a, int kt, hipStream_t s) {
+template <int KT>
+static void launch_thin_kt(const ThinArgs &a, int ngs, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    if (ngs == 0) hipLaunchKernelGGL((k_solve_thin<KT, 0>), grid, block, lds, s, a);
+    else if (ngs == 1) hipLaunchKernelGGL((k_solve_thin<KT, 1>), grid, block, lds, s, a);
+    else if (ngs == 2) hipLaunchKernelGGL((k_solve_thin<KT, 2>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_solve_thin<KT, 4>), grid, block, lds, s, a);
+}
+
+hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     if (a.nlev == 0) return hipSuccess;
-    const dim3 sgrid((unsigned)((a.n_rec + 255) / 256)), sblock(256);
-    if (a.gv) hipLaunchKernelGGL((k_thin_stream<true>), sgrid, sblock, 0, s, a);
-    else hipLaunchKernelGGL((k_thin_stream<false>), sgrid, sblock, 0, s, a);
-    const dim3 grid(1 + 8 * (unsigned)a.helpers), block(THIN_THREADS);
-    if (a.gv) {
-        if (kt == 1) hipLaunchKernelGGL((k_solve_thin<1, true>), grid, block, 0, s, a);
-        else if (kt == 2) hipLaunchKernelGGL((k_solve_thin<2, true>), grid, block, 0, s, a);
-        else if (kt == 4) hipLaunchKernelGGL((k_solve_thin<4, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_solve_thin<8, true>), grid, block, 0, s, a);
-    } else {
-        if (kt == 1) hipLaunchKernelGGL((k_solve_thin<1, false>), grid, block, 0, s, a);
-        else if (kt == 2) hipLaunchKernelGGL((k_solve_thin<2, false>), grid, block, 0, s, a);
-        else if (kt == 4) hipLaunchKernelGGL((k_solve_thin<4, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_solve_thin<8, false>), grid, block, 0, s, a);
-    }
+    const dim3 pgrid((unsigned)((a.n_rec + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
+    hipLaunchKernelGGL(k_thin_stream, pgrid, pblock, 0, s, a);
+    const dim3 grid(1 + 8 * (unsigned)a.helpers), block((unsigned)a.block);
+    const size_t lds = (size_t)a.ring_levels * a.ring_rows * a.kt * sizeof(double);
+    if (a.kt == 1) launch_thin_kt<1>(a, ngs, grid, block, lds, s);
+    else launch_thin_kt<2>(a, ngs, grid, block, lds, s);
+    hipLaunchKernelGGL(k_thin_scatter, rgrid, pblock, 0, s, a);
+    if (a.gv) hipLaunchKernelGGL(k_thin_gv, pgrid, pblock, 0, s, a);
     return hipGetLastError();
 }
 

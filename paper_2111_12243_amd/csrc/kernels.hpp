@@ -28,27 +28,48 @@ struct SpmvArgs {
     int32_t gv_diag; // also write the diagonal entry (triangular forward plans)
 };
 
-// Single-block solve of a matrix whose every level fits one 1024-thread pass.  Per lane
-// slot and level one record of THIN_REC int32: row, value index of the diagonal, number of
-// ops (<= LOOKAHEAD), 0, value indices [LOOKAHEAD], columns [LOOKAHEAD]; G lanes per row.
-constexpr int THIN_REC = 12;
-constexpr int THIN_SW = 8; // per record: values of its 4 ops, diagonal, b and xf of its row, pad
+// Single-block solve of a matrix whose every level fits one 1024-thread pass; G lanes per row.
+// Static record per lane slot and level, THIN_REC int32:
+//   [0] row, [1] value index of the diagonal, [2] ops in the slot, [3] 0,
+//   [4..7] value index of each op slot, [8..11] its column,
+//   [12..15] its operand code: THIN_UNUSED for an empty slot; >= 0 the plan position of a row
+//   solved at least THIN_HORIZON levels before, read from global memory (only in the first
+//   `ngs` slots); otherwise -(1 + ring slot) of the LDS ring that keeps the solutions of the
+//   last ring_levels levels, ring slot = (level mod ring_levels) * ring_rows + position in level.
+// Every level's records start on a 64-record boundary; placeholder records ([3] = 1, no ops)
+// fill the gap.  The plan position of a row is the index of its first record / G.  Per call, a
+// stream is gathered in record order, structure-of-arrays per 64 records: five 16-byte fields
+// (operand codes, v[0..1], v[2..3], diagonal and b[0], b[1] and pad) of 64 records each.  The
+// solve writes solutions in plan order, and a scatter puts them in row order.
+constexpr int THIN_REC = 16;
+constexpr int THIN_SW = 10;               // stream doubles per record
 constexpr int THIN_THREADS = 1024;
+constexpr int THIN_KT_MAX = 2;            // right-hand sides the single-block kernel takes
+constexpr int THIN_RING_BYTES = 64 << 10; // LDS ring, sized for THIN_KT_MAX
+constexpr int THIN_HORIZON = 3;           // a global operand's row was solved this many levels before
+constexpr int32_t THIN_UNUSED = (int32_t)0x80000000;
 struct ThinArgs {
     const int32_t *rec;
-    const int2 *lvl; // per level: first record, lanes in use
-    int32_t nlev;
-    int32_t lg;      // log2 lanes per row
-    int32_t k;       // right-hand sides (at most the kernel's KT)
-    int32_t helpers; // blocks that pull upcoming levels into the solver's L2
-    int32_t ahead;   // levels the helpers may run ahead of the solver
+    const int2 *lvl; // per level: first record, lanes in use (padded with empty levels)
+    int32_t nlev;     // levels
+    int32_t nlev_pad; // levels rounded up to a multiple of 4 (the table holds 4 more)
+    int32_t lg;       // log2 lanes per row
+    int32_t k;        // right-hand sides (at most the kernel's KT)
+    int32_t kt;       // the kernel's KT (stride of xs)
+    int32_t ring_rows;   // rows per ring level (the widest level)
+    int32_t ring_levels; // levels in the ring (a power of two, >= 4)
+    int32_t helpers;  // blocks that pull upcoming levels into the solver's L2
+    int32_t ahead;    // levels the helpers may run ahead of the solver
+    int32_t n;        // plan positions (records / G)
+    int32_t block;    // threads of the solving block
     int64_t n_rec;
     const double *vals;
     const double *b;
     double *x;
-    const double *xf;  // adjoint with value gradient: the forward solution
-    double *gv;        // adjoint: gradient of the values (NULL: not wanted)
-    double *stream;    // THIN_SW doubles per record, gathered before the solve
+    const double *xf;   // adjoint with value gradient: the forward solution
+    double *gv;         // adjoint: gradient of the values (NULL: not wanted)
+    double *stream;     // THIN_SW doubles per record, gathered before the solve
+    double *xs;         // solutions in plan order, kt per row
     unsigned *progress; // levels the solver has finished (read by the helpers)
     unsigned *sink;     // helpers' discard word (never read)
 };
@@ -103,7 +124,7 @@ int kr_for(int k);
 hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s);
 int num_cu();
 hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
-hipError_t launch_solve_thin(const ThinArgs &a, int kt, hipStream_t s);
+hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
 

@@ -361,6 +361,7 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
 void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *perm, DevTables &D) {
     D.thin_rec.clear();
     D.thin_lvl.clear();
+    D.thin_block = 64;
     const int64_t n = P.n_rows;
     int64_t maxn = 0;
     for (int64_t r = 0; r < n; r++) maxn = std::max(maxn, P.nops(r));
@@ -369,44 +370,105 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
     if ((int64_t(LOOKAHEAD) << lg) < maxn) return;
     const int G = 1 << lg;
     const int64_t nl = c.header[5];
-    for (int64_t l = 0; l < nl; l++)
-        if ((c.part_ptr[l + 1] - c.part_ptr[l]) * G > THIN_THREADS) return;
-    // codelets of each level, in plan order
+    int64_t R = 1;
+    for (int64_t l = 0; l < nl; l++) R = std::max(R, c.part_ptr[l + 1] - c.part_ptr[l]);
+    if (R * G > THIN_THREADS) return;
+    int RW = 1;
+    while ((int64_t)RW * 2 * R * THIN_KT_MAX * 8 <= THIN_RING_BYTES && RW < 16) RW *= 2;
+    if (RW < 4) return;
+    // codelets of each level, in plan order; level and position of every row
     std::vector<std::vector<int64_t>> by_level(nl);
     for (int64_t i = 0; i < c.header[7]; i++) by_level[c.codelets[i * NCOD + C_PART]].push_back(i);
-    auto vidx = [&](int64_t e) -> int32_t { return perm ? (*perm)[e] : (int32_t)e; };
-    for (int64_t l = 0; l < nl; l++) {
-        const int64_t first = (int64_t)D.thin_rec.size() / THIN_REC;
+    std::vector<int32_t> lev(n, -1), pos(n, -1);
+    std::vector<std::vector<int64_t>> rows_of(nl);
+    for (int64_t l = 0; l < nl; l++)
         for (int64_t ci : by_level[l]) {
             const int64_t *r = &c.codelets[ci * NCOD];
             const int32_t fl = (int32_t)r[C_FLAGS];
             for (int64_t a = 0; a < r[C_M]; a++) {
                 const int64_t row = (fl & FS0) ? r[C_ROW0] + a * r[C_ROWSTEP] : c.aux[r[C_AUXOFF] + a];
-                const int64_t op = P.opstart(row), no = P.nops(row);
-                const int64_t dpos = P.kind == 2 ? op - 1 : op + no;
-                for (int g = 0; g < G; g++) {
-                    int32_t rec[THIN_REC] = {(int32_t)row, vidx(dpos), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-                    int cnt = 0;
-                    for (int j = 0; j < LOOKAHEAD; j++) {
-                        const int64_t i1 = g + (int64_t)j * G;
-                        if (i1 < no) {
-                            rec[4 + j] = vidx(op + i1);
-                            rec[8 + j] = P.ci[op + i1];
-                            cnt = j + 1;
-                        } else {
-                            rec[4 + j] = vidx(dpos); // in-bounds filler, never used
-                            rec[8 + j] = (int32_t)row;
-                        }
-                    }
-                    rec[2] = cnt;
-                    D.thin_rec.insert(D.thin_rec.end(), rec, rec + THIN_REC);
-                }
+                lev[row] = (int32_t)l;
+                pos[row] = (int32_t)rows_of[l].size();
+                rows_of[l].push_back(row);
             }
         }
-        D.thin_lvl.push_back((int32_t)first);
-        D.thin_lvl.push_back((int32_t)((int64_t)D.thin_rec.size() / THIN_REC - first));
+    // plan position of a row: index of its first record / G (levels start on 64-record
+    // boundaries, padded with placeholder records)
+    std::vector<int64_t> plan_pos(n, -1);
+    {
+        int64_t q = 0;
+        for (int64_t l = 0; l < nl; l++) {
+            for (int64_t row : rows_of[l]) plan_pos[row] = q++;
+            q = (q * G + 63) / 64 * 64 / G;
+        }
     }
+    auto vidx = [&](int64_t e) -> int32_t { return perm ? (*perm)[e] : (int32_t)e; };
+    int ngs = 0;
+    std::vector<int32_t> slot_vi, slot_col, slot_code;
+    for (int64_t l = 0; l < nl; l++) {
+        const int64_t first = (int64_t)D.thin_rec.size() / THIN_REC;
+        for (int64_t row : rows_of[l]) {
+            const int64_t op = P.opstart(row), no = P.nops(row);
+            const int64_t dpos = P.kind == 2 ? op - 1 : op + no;
+            // slot s = j * G + g (op slot j of lane g): operands from global memory first, so
+            // that they sit in the lowest slot indices of every lane
+            const int S = G * LOOKAHEAD;
+            slot_vi.assign(S, vidx(dpos));
+            slot_col.assign(S, (int32_t)row);
+            slot_code.assign(S, THIN_UNUSED);
+            int next = 0;
+            for (int pass = 0; pass < 2; pass++)
+                for (int64_t i = 0; i < no; i++) {
+                    const int32_t col = P.ci[op + i];
+                    const int64_t m = lev[col];
+                    const bool global = m <= l - RW;
+                    if (global != (pass == 0)) continue;
+                    slot_vi[next] = vidx(op + i);
+                    slot_col[next] = col;
+                    slot_code[next] = global ? (int32_t)plan_pos[col]
+                                             : -(1 + (int32_t)((m & (RW - 1)) * R + pos[col]));
+                    if (global) ngs = std::max(ngs, next / G + 1);
+                    next++;
+                }
+            for (int g = 0; g < G; g++) {
+                int32_t rec[THIN_REC] = {(int32_t)row, vidx(dpos), 0, 0};
+                int cnt = 0;
+                for (int j = 0; j < LOOKAHEAD; j++) {
+                    const int sl = j * G + g;
+                    rec[4 + j] = slot_vi[sl];
+                    rec[8 + j] = slot_col[sl];
+                    rec[12 + j] = slot_code[sl];
+                    cnt += slot_code[sl] != THIN_UNUSED;
+                }
+                rec[2] = cnt;
+                D.thin_rec.insert(D.thin_rec.end(), rec, rec + THIN_REC);
+            }
+        }
+        const int64_t lanes = (int64_t)D.thin_rec.size() / THIN_REC - first;
+        // placeholders up to the next 64-record boundary: the level's first row, flag 1, no ops
+        while (((int64_t)D.thin_rec.size() / THIN_REC) % 64) {
+            int32_t rec[THIN_REC];
+            std::copy(&D.thin_rec[first * THIN_REC], &D.thin_rec[first * THIN_REC] + THIN_REC, rec);
+            rec[2] = 0;
+            rec[3] = 1;
+            for (int j = 0; j < LOOKAHEAD; j++) rec[12 + j] = THIN_UNUSED;
+            D.thin_rec.insert(D.thin_rec.end(), rec, rec + THIN_REC);
+        }
+        D.thin_lvl.push_back((int32_t)first);
+        D.thin_lvl.push_back((int32_t)lanes);
+        D.thin_block = std::max<int32_t>(D.thin_block, (int32_t)((lanes + 63) / 64 * 64));
+    }
+    // empty levels up to a multiple of four, and four more for the kernel's fetches ahead
+    const int64_t pad = (nl + 3) / 4 * 4;
+    for (int64_t l = nl; l < pad + 4; l++) {
+        D.thin_lvl.push_back(0);
+        D.thin_lvl.push_back(0);
+    }
+    D.thin_ngs = ngs == 3 ? 4 : ngs;
     D.thin_lg = lg;
+    D.thin_R = (int32_t)R;
+    D.thin_RW = RW;
+    D.thin_nlev_pad = (int32_t)pad;
 }
 
 // Counter lines of the persistent solve: ticket, error flag, one per level of the largest
@@ -511,13 +573,15 @@ ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
         if (ddf_status s = upload(p, &D.d_thin_lvl, D.thin_lvl.data(), D.thin_lvl.size())) return s;
         if (ddf_status s = dalloc(p, (void **)&D.d_thin_stream, D.thin_rec.size() / THIN_REC * THIN_SW * sizeof(double)))
             return s;
+        const int64_t slots = (int64_t)D.thin_rec.size() / THIN_REC >> D.thin_lg; // plan positions
+        if (ddf_status s = dalloc(p, (void **)&D.d_thin_xs, slots * THIN_KT_MAX * sizeof(double))) return s;
     }
     return upload(p, &D.d_aux, D.aux.data(), D.aux.size());
 }
 
-// the single-block kernel takes up to 8 right-hand sides in one pass
+// the single-block kernel takes up to THIN_KT_MAX right-hand sides
 bool use_thin(const DevTables &D, const SchedParams &sp, int32_t k) {
-    return !D.thin_rec.empty() && sp.path != 1 && k <= 8;
+    return !D.thin_rec.empty() && sp.path != 1 && k <= THIN_KT_MAX;
 }
 
 ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, int nlev, const double *vals,
@@ -527,8 +591,15 @@ ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, 
     t.rec = D.d_thin_rec;
     t.lvl = reinterpret_cast<const int2 *>(D.d_thin_lvl);
     t.nlev = nlev;
+    t.nlev_pad = D.thin_nlev_pad;
+    t.ring_rows = D.thin_R;
+    t.ring_levels = D.thin_RW;
     t.lg = D.thin_lg;
     t.k = k;
+    t.kt = k <= 1 ? 1 : 2;
+    t.n = (int32_t)((int64_t)D.thin_rec.size() / THIN_REC >> D.thin_lg); // plan positions
+    t.block = D.thin_block;
+    t.xs = D.d_thin_xs;
     t.helpers = std::max(0, std::min(sp.helpers, 8));
     t.ahead = std::max(8, sp.ahead);
     t.n_rec = (int64_t)D.thin_rec.size() / THIN_REC;
@@ -540,7 +611,7 @@ ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, 
     t.stream = D.d_thin_stream;
     t.progress = p->d_ctr + CTR_STRIDE + 16; // second counter line: error flag, then these
     t.sink = p->d_ctr + CTR_STRIDE + 17;
-    HIPCHK(launch_solve_thin(t, kt_for(k), s));
+    HIPCHK(launch_solve_thin(t, D.thin_ngs, s));
     return DDF_OK;
 }
 
@@ -1220,6 +1291,10 @@ ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables
     o->n_thin_rec = (int64_t)D->thin_rec.size() / THIN_REC;
     o->n_thin_lvl = (int64_t)D->thin_lvl.size() / 2;
     o->thin_lg = D->thin_lg;
+    o->thin_ring_rows = D->thin_R;
+    o->thin_ring_levels = D->thin_RW;
+    o->thin_ngs = D->thin_ngs;
+    o->thin_block = D->thin_block;
     return DDF_OK;
 }
 
@@ -1418,7 +1493,7 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
                 for (int ps : {1, 2, 4}) cands.push_back({opl, ps, rm, 0, 0, target.helpers, target.ahead});
     } else {
         const DevTables &D = adjop ? p->T : p->F;
-        if (!D.thin_rec.empty() && nrhs <= 8)
+        if (!D.thin_rec.empty() && nrhs <= THIN_KT_MAX)
             for (int hp : {2, 0, 4, 1})
                 for (int ah : {32, 96}) cands.push_back({target.ops_per_lane, target.passes, target.remap, 0, 2, hp, ah});
         const int full = 4 * num_cu(); // up to four 256-thread blocks per CU

@@ -65,7 +65,9 @@ class ddf_device_tables_t(C.Structure):
                 ("sync", C.POINTER(C.c_int32)), ("tasksN", C.POINTER(C.c_int32)), ("n_cods", C.c_int64),
                 ("aux_len", C.c_int64), ("n_tasks", C.c_int64), ("n_counters", C.c_int64), ("n_tasksN", C.c_int64),
                 ("thin_rec", C.POINTER(C.c_int32)), ("thin_lvl", C.POINTER(C.c_int32)), ("n_thin_rec", C.c_int64),
-                ("n_thin_lvl", C.c_int64), ("thin_lg", C.c_int32), ("reserved", C.c_int32)]
+                ("n_thin_lvl", C.c_int64), ("thin_lg", C.c_int32), ("thin_ring_rows", C.c_int32),
+                ("thin_ring_levels", C.c_int32), ("thin_ngs", C.c_int32), ("thin_block", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ddf_plan_info_t(C.Structure):
@@ -365,8 +367,10 @@ def ddf_plan_device_tables(plan, which=0) -> dict:
     sync = grab(t.sync, t.n_tasks, 4) if t.sync else np.zeros((0, 4), np.int32)
     return {"cods": grab(t.cods, t.n_cods, 16), "aux": grab(t.aux, t.aux_len), "tasks": grab(t.tasks, t.n_tasks, 4),
             "sync": sync, "n_counters": int(t.n_counters), "tasksN": grab(t.tasksN, t.n_tasksN, 4),
-            "thin_rec": grab(t.thin_rec, t.n_thin_rec, 12), "thin_lvl": grab(t.thin_lvl, t.n_thin_lvl, 2),
-            "thin_lg": int(t.thin_lg)}
+            "thin_rec": grab(t.thin_rec, t.n_thin_rec, 16), "thin_lvl": grab(t.thin_lvl, t.n_thin_lvl, 2),
+            "thin_lg": int(t.thin_lg), "thin_ring_rows": int(t.thin_ring_rows),
+            "thin_ring_levels": int(t.thin_ring_levels), "thin_ngs": int(t.thin_ngs),
+            "thin_block": int(t.thin_block)}
 
 
 def ddf_plan_traffic(plan, op, nrhs) -> tuple:

@@ -227,44 +227,69 @@ def _rows_from(TF, task):
     return c, meta, out
 
 
+THIN_UNUSED = -(1 << 31)
+
+
 def thin_solve(tabs, L, B, vals=None, Xf=None):
-    """Replays the single-block solve: level by level, G lanes per row; checks that every
-    solution entry read was written by an earlier level and every row is solved once.  With
-    Xf (transposed solve), also returns the fused value gradient: -<x[col], Xf[row]> at each
-    op's value index and -<x[row], Xf[row]> at the diagonal."""
+    """Replays the single-block solve: level by level, G lanes per row, operands by their
+    codes.  Checks that every ring operand finds its row in the LDS ring (written by one of the
+    last ring_levels levels, not overwritten), that every global operand sits in one of the
+    first thin_ngs slots of its lane, names the plan position of its column and was solved at
+    least THIN_HORIZON levels before (so the gather two levels ahead sees it final), that
+    empty slots carry no op, and that every row is solved once.  With Xf (transposed solve),
+    also returns the value gradient of the follow-up pass: -<x[col], Xf[row]> at each op's
+    value index and -<x[row], Xf[row]> at the diagonal."""
     rec, lvl, lg = tabs["thin_rec"], tabs["thin_lvl"], tabs["thin_lg"]
+    R, RW, ngs = tabs["thin_ring_rows"], tabs["thin_ring_levels"], tabs["thin_ngs"]
+    assert RW >= 4 and RW & (RW - 1) == 0 and ngs in (0, 1, 2, 4)
+    assert lvl.shape[0] % 4 == 0 and (lvl[-4:, 1] == 0).all()
+    assert rec.shape[0] % 64 == 0 and tabs["thin_block"] >= lvl[:, 1].max()
     v = L.values if vals is None else vals
     n, k = B.shape
     G = 1 << lg
+    plan_rows = rec[::G, 0]
     X = np.full((n, k), np.nan)
     gv = np.full(v.shape[0], np.nan) if Xf is not None else None
     level_of = np.full(n, -1)
+    ring = {}
     for l, (first, lanes) in enumerate(lvl):
-        assert 0 < lanes <= 1024 and lanes % G == 0
-        acc = {}
-        diag = {}
-        dpos = {}
+        if lanes == 0:
+            continue
+        assert 0 < lanes <= 1024 and lanes % G == 0 and first % 64 == 0 and lanes // G <= R
+        nxt = first + (lanes + 63) // 64 * 64
+        assert (rec[first:first + lanes, 3] == 0).all() and (rec[first + lanes:nxt, 3] == 1).all()
+        assert (rec[first + lanes:nxt, 12:16] == THIN_UNUSED).all()
+        acc, diag, dpos, slot = {}, {}, {}, {}
         for s in range(lanes):
-            row, dp, cnt = (int(x) for x in rec[first + s][:3])
+            r = rec[first + s]
+            row, dp, cnt = int(r[0]), int(r[1]), int(r[2])
             if s % G == 0:
                 acc[row] = np.zeros(k)
-                diag[row] = v[dp]
+                diag[row], dpos[row] = v[dp], dp
+                slot[row] = (l % RW) * R + s // G
+                assert plan_rows[(first + s) // G] == row
             else:
                 assert row in acc
-            assert 0 <= cnt <= 4
-            for j in range(cnt):
-                vi, col = int(rec[first + s][4 + j]), int(rec[first + s][8 + j])
-                assert 0 <= level_of[col] < l, f"row {row} reads x[{col}] not solved in an earlier level"
+            assert cnt == sum(int(c) != THIN_UNUSED for c in r[12:16])
+            for j in range(4):
+                vi, col, code = int(r[4 + j]), int(r[8 + j]), int(r[12 + j])
+                if code == THIN_UNUSED:
+                    continue
+                m = level_of[col]
+                assert 0 <= m < l, f"row {row} reads x[{col}] not solved in an earlier level"
+                if code >= 0:
+                    assert j < ngs and plan_rows[code] == col and m <= l - 3
+                else:
+                    assert ring.get(-code - 1) == (col, m) and m > l - RW
                 acc[row] += v[vi] * X[col]
                 if gv is not None:
                     assert np.isnan(gv[vi])
                     gv[vi] = -np.dot(X[col], Xf[row])
-            if gv is not None and s % G == 0:
-                dpos[row] = int(rec[first + s][1])
         for row, a in acc.items():
             assert level_of[row] == -1
             X[row] = (B[row] - a) / diag[row]
             level_of[row] = l
+            ring[slot[row]] = (row, l)
             if gv is not None:
                 gv[dpos[row]] = -np.dot(X[row], Xf[row])
     assert (level_of >= 0).all()
