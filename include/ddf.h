@@ -259,12 +259,12 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
 typedef struct {
     const int32_t *cods, *aux, *tasks, *sync, *tasksN;
     int64_t n_cods, aux_len, n_tasks, n_counters, n_tasksN;
-    const int32_t *thin_rec; /* single-block solve: [n_thin_rec][16] per lane slot: row, value
+    const int32_t *thin_rec; /* single-block solve: [n_thin_rec][20] per lane slot: row, value
                                 index of the diagonal, ops, placeholder flag (levels start on
-                                64-record boundaries), value indices[4], columns[4],
-                                operand codes[4]: INT32_MIN empty; >= 0 plan position (first
+                                64-record boundaries), value indices[5], columns[5],
+                                operand codes[5]: INT32_MIN empty; >= 0 plan position (first
                                 record / lane slots per row) of a row read from global
-                                memory; else -(1 + ring slot)                               */
+                                memory; else -(1 + ring slot); 0                            */
     const int32_t *thin_lvl; /* [n][2] first record, lane slots in use, per level, then empty
                                 levels up to a multiple of 4 plus 4 (absent: n = 0)        */
     int64_t n_thin_rec, n_thin_lvl;

@@ -647,30 +647,34 @@ __device__ __forceinline__ int2 thin_lvl(const ThinArgs &a, int l) {
 __device__ __forceinline__ bool thin_wave_on(int2 lv, int s) { return (s & ~(WAVE - 1)) < lv.y; }
 
 template <int KT> struct ThinA {
-    int code[LOOKAHEAD];
-    double v[LOOKAHEAD], d, b[KT];
+    int code[THIN_SLOTS];
+    int wide; // 0: row of G lanes; 1, 2: first, second half of a row of 2G lanes
+    double v[THIN_SLOTS], d, b[KT];
 };
 template <int KT, int NGS> struct ThinB {
     double gx[NGS > 0 ? NGS : 1][KT]; // operands gathered from global memory
 };
 
 // Fetches are issued by every wave, also one with no lane in use at the level (it reads the
-// level's first 64 entries): a fetch on one path only would make the compiler's wait counts
-// cover it on both.
+// stream's chunk of empty records): a fetch on one path only would make the compiler's wait
+// counts cover it on both.
 template <int KT>
 __device__ __forceinline__ void thin_fetch_a(const ThinArgs &a, int l, int s, ThinA<KT> &t) {
     const int2 lv = thin_lvl(a, l);
-    const int64_t p = (int64_t)lv.x + (thin_wave_on(lv, s) ? s : (s & (WAVE - 1)));
+    const int64_t p = thin_wave_on(lv, s) ? (int64_t)lv.x + s : a.n_rec + (s & (WAVE - 1));
     const double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
     const int4 c = *reinterpret_cast<const int4 *>(w);
     const double2 v01 = *reinterpret_cast<const double2 *>(w + 128);
     const double2 v23 = *reinterpret_cast<const double2 *>(w + 256);
-    const double2 db = *reinterpret_cast<const double2 *>(w + 384);
+    const double2 v4d = *reinterpret_cast<const double2 *>(w + 384);
+    const int4 bc = *reinterpret_cast<const int4 *>(w + 512);
     t.code[0] = c.x; t.code[1] = c.y; t.code[2] = c.z; t.code[3] = c.w;
-    t.v[0] = v01.x; t.v[1] = v01.y; t.v[2] = v23.x; t.v[3] = v23.y;
-    t.d = db.x;
-    t.b[0] = db.y;
-    if (KT > 1) t.b[1] = reinterpret_cast<const double2 *>(w + 512)->x;
+    t.code[4] = bc.z;
+    t.wide = bc.w;
+    t.v[0] = v01.x; t.v[1] = v01.y; t.v[2] = v23.x; t.v[3] = v23.y; t.v[4] = v4d.x;
+    t.d = v4d.y;
+    t.b[0] = __hiloint2double(bc.y, bc.x);
+    if (KT > 1) t.b[1] = reinterpret_cast<const double2 *>(w + 640)->x;
 }
 
 template <int KT, int NGS>
@@ -697,7 +701,7 @@ __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, in
 #pragma unroll
     for (int rr = 0; rr < KT; rr++) acc[rr] = 0.0;
 #pragma unroll
-    for (int j = 0; j < LOOKAHEAD; j++) {
+    for (int j = 0; j < THIN_SLOTS; j++) {
         const int c = t.code[j];
         const bool used = c != THIN_UNUSED;
         const int idx = (c < 0 && used) ? -(c + 1) : 0;
@@ -709,7 +713,15 @@ __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, in
         }
     }
     group_sum<KT>(acc, G);
-    if (s < lv.y) {
+    if (__any(t.wide != 0)) {
+        // rows of 2G lanes: add the other half
+#pragma unroll
+        for (int rr = 0; rr < KT; rr++) {
+            const double o = __shfl_xor(acc[rr], G, WAVE);
+            if (t.wide) acc[rr] += o;
+        }
+    }
+    if (s < lv.y && t.wide != 2) {
         const int pos = s >> a.lg;
         const int64_t rp = ((int64_t)lv.x >> a.lg) + pos; // plan position of the row
         const int slot = (l & (a.ring_levels - 1)) * a.ring_rows + pos;
@@ -767,7 +779,7 @@ __device__ void thin_helper(const ThinArgs &a) {
 
 template <int KT, int NGS>
 __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
-    static_assert(LOOKAHEAD == 4, "record layout");
+    static_assert(THIN_SLOTS == 5, "stream layout");
     if (blockIdx.x != 0) {
         // blocks are dispatched round robin over the 8 XCDs: multiples of 8 share block 0's L2
         if (blockIdx.x % 8 == 0) thin_helper(a);
@@ -802,18 +814,32 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
 __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p == 0) *a.progress = 0u;
-    if (p >= a.n_rec) return;
-    const int4 *q = reinterpret_cast<const int4 *>(a.rec + p * THIN_REC);
-    const int4 h = q[0], v = q[1], c = q[3];
-    const int64_t rb = (int64_t)h.x * a.k;
+    if (p >= a.n_rec + 64) return;
     double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
-    *reinterpret_cast<int4 *>(w) = c;
-    *reinterpret_cast<double2 *>(w + 128) =
-        make_double2(c.x != THIN_UNUSED ? a.vals[v.x] : 0.0, c.y != THIN_UNUSED ? a.vals[v.y] : 0.0);
-    *reinterpret_cast<double2 *>(w + 256) =
-        make_double2(c.z != THIN_UNUSED ? a.vals[v.z] : 0.0, c.w != THIN_UNUSED ? a.vals[v.w] : 0.0);
-    *reinterpret_cast<double2 *>(w + 384) = make_double2(a.vals[h.y], a.b[rb]);
-    if (a.kt > 1) *reinterpret_cast<double2 *>(w + 512) = make_double2(a.k > 1 ? a.b[rb + 1] : 0.0, 0.0);
+    if (p >= a.n_rec) {
+        // the chunk of empty records
+        *reinterpret_cast<int4 *>(w) = make_int4(THIN_UNUSED, THIN_UNUSED, THIN_UNUSED, THIN_UNUSED);
+        *reinterpret_cast<double2 *>(w + 128) = make_double2(0.0, 0.0);
+        *reinterpret_cast<double2 *>(w + 256) = make_double2(0.0, 0.0);
+        *reinterpret_cast<double2 *>(w + 384) = make_double2(0.0, 1.0);
+        *reinterpret_cast<int4 *>(w + 512) = make_int4(0, 0, THIN_UNUSED, 0);
+        *reinterpret_cast<double2 *>(w + 640) = make_double2(0.0, 0.0);
+        return;
+    }
+    const int32_t *r = a.rec + p * THIN_REC;
+    const int row = r[0], dpos = r[1];
+    const int32_t *vi = r + 4, *co = r + 4 + 2 * THIN_SLOTS;
+    const int64_t rb = (int64_t)row * a.k;
+    double v[THIN_SLOTS];
+#pragma unroll
+    for (int j = 0; j < THIN_SLOTS; j++) v[j] = co[j] != THIN_UNUSED ? a.vals[vi[j]] : 0.0;
+    const double bv = a.b[rb];
+    *reinterpret_cast<int4 *>(w) = make_int4(co[0], co[1], co[2], co[3]);
+    *reinterpret_cast<double2 *>(w + 128) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2 *>(w + 256) = make_double2(v[2], v[3]);
+    *reinterpret_cast<double2 *>(w + 384) = make_double2(v[4], a.vals[dpos]);
+    *reinterpret_cast<int4 *>(w + 512) = make_int4(__double2loint(bv), __double2hiint(bv), co[4], r[THIN_REC - 1]);
+    if (a.kt > 1) *reinterpret_cast<double2 *>(w + 640) = make_double2(a.k > 1 ? a.b[rb + 1] : 0.0, 0.0);
 }
 
 // Solutions from plan order into row order.
@@ -821,7 +847,7 @@ __global__ __launch_bounds__(256) void k_thin_scatter(ThinArgs a) {
     const int64_t rp = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (rp >= a.n) return;
     const int32_t *q = a.rec + (rp << a.lg) * THIN_REC;
-    if (q[3]) return; // placeholder
+    if (q[3] || q[THIN_REC - 1] == 2) return; // placeholder, or second half of a wide row
     const int64_t row = q[0];
     for (int r = 0; r < a.k; r++) a.x[row * a.k + r] = a.xs[rp * a.kt + r];
 }
@@ -832,22 +858,22 @@ __global__ __launch_bounds__(256) void k_thin_scatter(ThinArgs a) {
 __global__ __launch_bounds__(256) void k_thin_gv(ThinArgs a) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= a.n_rec) return;
-    const int4 *q = reinterpret_cast<const int4 *>(a.rec + p * THIN_REC);
-    const int4 h = q[0], vi = q[1], c = q[2], cd = q[3];
+    const int32_t *r = a.rec + p * THIN_REC;
+    if (r[3]) return; // placeholder
+    const int32_t *vi = r + 4, *cc = r + 4 + THIN_SLOTS, *co = r + 4 + 2 * THIN_SLOTS;
     const int k = a.k;
-    const int64_t rb = (int64_t)h.x * k;
-    const int vv[4] = {vi.x, vi.y, vi.z, vi.w}, cc[4] = {c.x, c.y, c.z, c.w}, co[4] = {cd.x, cd.y, cd.z, cd.w};
+    const int64_t rb = (int64_t)r[0] * k;
 #pragma unroll
-    for (int j = 0; j < 4; j++)
+    for (int j = 0; j < THIN_SLOTS; j++)
         if (co[j] != THIN_UNUSED) {
             double t = 0.0;
-            for (int r = 0; r < k; r++) t = fma(a.x[(int64_t)cc[j] * k + r], a.xf[rb + r], t);
-            a.gv[vv[j]] = -t;
+            for (int q = 0; q < k; q++) t = fma(a.x[(int64_t)cc[j] * k + q], a.xf[rb + q], t);
+            a.gv[vi[j]] = -t;
         }
-    if ((p & ((1 << a.lg) - 1)) == 0 && h.w == 0) {
+    if ((p & ((1 << a.lg) - 1)) == 0 && r[THIN_REC - 1] != 2) {
         double t = 0.0;
-        for (int r = 0; r < k; r++) t = fma(a.x[rb + r], a.xf[rb + r], t);
-        a.gv[h.y] = -t;
+        for (int q = 0; q < k; q++) t = fma(a.x[rb + q], a.xf[rb + q], t);
+        a.gv[r[1]] = -t;
     }
 }
 
@@ -1042,13 +1068,15 @@ static void launch_thin_kt(const ThinArgs &a, int ngs, dim3 grid, dim3 block, si
     if (ngs == 0) hipLaunchKernelGGL((k_solve_thin<KT, 0>), grid, block, lds, s, a);
     else if (ngs == 1) hipLaunchKernelGGL((k_solve_thin<KT, 1>), grid, block, lds, s, a);
     else if (ngs == 2) hipLaunchKernelGGL((k_solve_thin<KT, 2>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_solve_thin<KT, 4>), grid, block, lds, s, a);
+    else if (ngs == 3) hipLaunchKernelGGL((k_solve_thin<KT, 3>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_solve_thin<KT, THIN_SLOTS>), grid, block, lds, s, a);
 }
 
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     if (a.nlev == 0) return hipSuccess;
-    const dim3 pgrid((unsigned)((a.n_rec + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
-    hipLaunchKernelGGL(k_thin_stream, pgrid, pblock, 0, s, a);
+    const dim3 pgrid((unsigned)((a.n_rec + 255) / 256)), sgrid((unsigned)((a.n_rec + 64 + 255) / 256)),
+        rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
+    hipLaunchKernelGGL(k_thin_stream, sgrid, pblock, 0, s, a);
     const dim3 grid(1 + 8 * (unsigned)a.helpers), block((unsigned)a.block);
     const size_t lds = (size_t)a.ring_levels * a.ring_rows * a.kt * sizeof(double);
     if (a.kt == 1) launch_thin_kt<1>(a, ngs, grid, block, lds, s);

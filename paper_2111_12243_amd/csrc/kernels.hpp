@@ -28,21 +28,25 @@ struct SpmvArgs {
     int32_t gv_diag; // also write the diagonal entry (triangular forward plans)
 };
 
-// Single-block solve of a matrix whose every level fits one 1024-thread pass; G lanes per row.
-// Static record per lane slot and level, THIN_REC int32:
-//   [0] row, [1] value index of the diagonal, [2] ops in the slot, [3] 0,
-//   [4..7] value index of each op slot, [8..11] its column,
-//   [12..15] its operand code: THIN_UNUSED for an empty slot; >= 0 the plan position of a row
+// Single-block solve of a matrix whose every level fits one 1024-thread pass; G lanes per row,
+// THIN_SLOTS op slots per lane.  Static record per lane slot and level, THIN_REC int32:
+//   [0] row, [1] value index of the diagonal, [2] ops in the lane, [3] placeholder flag,
+//   [4..8] value index of each op slot, [9..13] its column,
+//   [14..18] its operand code: THIN_UNUSED for an empty slot; >= 0 the plan position of a row
 //   solved at least THIN_HORIZON levels before, read from global memory (only in the first
 //   `ngs` slots); otherwise -(1 + ring slot) of the LDS ring that keeps the solutions of the
-//   last ring_levels levels, ring slot = (level mod ring_levels) * ring_rows + position in level.
-// Every level's records start on a 64-record boundary; placeholder records ([3] = 1, no ops)
+//   last ring_levels levels, ring slot = (level mod ring_levels) * ring_rows + position in level;
+//   [19] 0 for a row of G lanes; a "wide" row takes 2G lanes (its first G flagged 1, the
+//   others 2) and comes before the other rows of its level.
+// Every level's records start on a 64-record boundary; placeholder records (flag 1, no ops)
 // fill the gap.  The plan position of a row is the index of its first record / G.  Per call, a
-// stream is gathered in record order, structure-of-arrays per 64 records: five 16-byte fields
-// (operand codes, v[0..1], v[2..3], diagonal and b[0], b[1] and pad) of 64 records each.  The
+// stream is gathered in record order, structure-of-arrays per 64 records: six 16-byte fields
+// (codes 0..3, v0 v1, v2 v3, v4 and diagonal, b[0] code 4 wide flag, b[1] and pad) of 64 records
+// each, then one chunk of empty records that waves with no lane in use at a level read.  The
 // solve writes solutions in plan order, and a scatter puts them in row order.
-constexpr int THIN_REC = 16;
-constexpr int THIN_SW = 10;               // stream doubles per record
+constexpr int THIN_SLOTS = 5;
+constexpr int THIN_REC = 20;
+constexpr int THIN_SW = 12;               // stream doubles per record
 constexpr int THIN_THREADS = 1024;
 constexpr int THIN_KT_MAX = 2;            // right-hand sides the single-block kernel takes
 constexpr int THIN_RING_BYTES = 64 << 10; // LDS ring, sized for THIN_KT_MAX
@@ -62,7 +66,7 @@ struct ThinArgs {
     int32_t ahead;    // levels the helpers may run ahead of the solver
     int32_t n;        // plan positions (records / G)
     int32_t block;    // threads of the solving block
-    int64_t n_rec;
+    int64_t n_rec;    // records (a multiple of 64; the stream holds one more chunk)
     const double *vals;
     const double *b;
     double *x;

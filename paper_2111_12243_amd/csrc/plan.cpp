@@ -356,49 +356,72 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
 }
 
 // Records of the single-block solve, built from a matrix's codelets level by level (rows in
-// plan order).  Eligible when every row has at most 64 * LOOKAHEAD ops and every level fits
+// plan order).  Eligible when every row has at most 64 * THIN_SLOTS ops and every level fits
 // one 1024-lane pass; value indices go through perm for the transposed solve.
 void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *perm, DevTables &D) {
     D.thin_rec.clear();
     D.thin_lvl.clear();
     D.thin_block = 64;
     const int64_t n = P.n_rows;
+    // G lanes per row cover all but about 1% of rows; the rest ("wide" rows) take 2G lanes
+    std::vector<int64_t> hist;
     int64_t maxn = 0;
-    for (int64_t r = 0; r < n; r++) maxn = std::max(maxn, P.nops(r));
+    for (int64_t r = 0; r < n; r++) {
+        const int64_t no = P.nops(r);
+        maxn = std::max(maxn, no);
+        if ((int64_t)hist.size() <= no) hist.resize(no + 1, 0);
+        hist[no]++;
+    }
+    int64_t p99 = 0;
+    for (int64_t acc = 0; p99 < (int64_t)hist.size(); p99++)
+        if ((acc += hist[p99]) * 100 >= n * 99) break;
     int lg = 0;
-    while ((int64_t(LOOKAHEAD) << lg) < maxn && lg < 6) lg++;
-    if ((int64_t(LOOKAHEAD) << lg) < maxn) return;
+    while (((int64_t(THIN_SLOTS) << lg) < p99 || (int64_t(THIN_SLOTS) << (lg + 1)) < maxn) && lg < 5) lg++;
+    if ((int64_t(THIN_SLOTS) << (lg + 1)) < maxn) return;
     const int G = 1 << lg;
+    auto lanes_of = [&](int64_t row) -> int { return P.nops(row) > (int64_t)G * THIN_SLOTS ? 2 * G : G; };
     const int64_t nl = c.header[5];
-    int64_t R = 1;
-    for (int64_t l = 0; l < nl; l++) R = std::max(R, c.part_ptr[l + 1] - c.part_ptr[l]);
-    if (R * G > THIN_THREADS) return;
-    int RW = 1;
-    while ((int64_t)RW * 2 * R * THIN_KT_MAX * 8 <= THIN_RING_BYTES && RW < 16) RW *= 2;
-    if (RW < 4) return;
-    // codelets of each level, in plan order; level and position of every row
+    // codelets of each level, in plan order
     std::vector<std::vector<int64_t>> by_level(nl);
     for (int64_t i = 0; i < c.header[7]; i++) by_level[c.codelets[i * NCOD + C_PART]].push_back(i);
+    // rows of each level in plan order, wide rows first (so they start on 2G-lane boundaries);
+    // a row's position in its level is its first lane / G
     std::vector<int32_t> lev(n, -1), pos(n, -1);
     std::vector<std::vector<int64_t>> rows_of(nl);
-    for (int64_t l = 0; l < nl; l++)
+    int64_t R = 1;
+    for (int64_t l = 0; l < nl; l++) {
+        std::vector<int64_t> narrow;
         for (int64_t ci : by_level[l]) {
             const int64_t *r = &c.codelets[ci * NCOD];
             const int32_t fl = (int32_t)r[C_FLAGS];
             for (int64_t a = 0; a < r[C_M]; a++) {
                 const int64_t row = (fl & FS0) ? r[C_ROW0] + a * r[C_ROWSTEP] : c.aux[r[C_AUXOFF] + a];
-                lev[row] = (int32_t)l;
-                pos[row] = (int32_t)rows_of[l].size();
-                rows_of[l].push_back(row);
+                (lanes_of(row) > G ? rows_of[l] : narrow).push_back(row);
             }
         }
+        rows_of[l].insert(rows_of[l].end(), narrow.begin(), narrow.end());
+        int64_t q = 0;
+        for (int64_t row : rows_of[l]) {
+            lev[row] = (int32_t)l;
+            pos[row] = (int32_t)q;
+            q += lanes_of(row) / G;
+        }
+        R = std::max(R, q);
+    }
+    if (R * G > THIN_THREADS) return;
+    int RW = 1;
+    while ((int64_t)RW * 2 * R * THIN_KT_MAX * 8 <= THIN_RING_BYTES && RW < 16) RW *= 2;
+    if (RW < 4) return;
     // plan position of a row: index of its first record / G (levels start on 64-record
     // boundaries, padded with placeholder records)
     std::vector<int64_t> plan_pos(n, -1);
     {
         int64_t q = 0;
         for (int64_t l = 0; l < nl; l++) {
-            for (int64_t row : rows_of[l]) plan_pos[row] = q++;
+            for (int64_t row : rows_of[l]) {
+                plan_pos[row] = q;
+                q += lanes_of(row) / G;
+            }
             q = (q * G + 63) / 64 * 64 / G;
         }
     }
@@ -410,9 +433,10 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
         for (int64_t row : rows_of[l]) {
             const int64_t op = P.opstart(row), no = P.nops(row);
             const int64_t dpos = P.kind == 2 ? op - 1 : op + no;
-            // slot s = j * G + g (op slot j of lane g): operands from global memory first, so
-            // that they sit in the lowest slot indices of every lane
-            const int S = G * LOOKAHEAD;
+            // slot s = j * NL + g (op slot j of lane g of the row's NL lanes): operands from
+            // global memory first, so that they sit in the lowest slot indices of every lane
+            const int NL = lanes_of(row);
+            const int S = NL * THIN_SLOTS;
             slot_vi.assign(S, vidx(dpos));
             slot_col.assign(S, (int32_t)row);
             slot_code.assign(S, THIN_UNUSED);
@@ -427,17 +451,18 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
                     slot_col[next] = col;
                     slot_code[next] = global ? (int32_t)plan_pos[col]
                                              : -(1 + (int32_t)((m & (RW - 1)) * R + pos[col]));
-                    if (global) ngs = std::max(ngs, next / G + 1);
+                    if (global) ngs = std::max(ngs, next / NL + 1);
                     next++;
                 }
-            for (int g = 0; g < G; g++) {
+            for (int g = 0; g < NL; g++) {
                 int32_t rec[THIN_REC] = {(int32_t)row, vidx(dpos), 0, 0};
+                rec[THIN_REC - 1] = NL == G ? 0 : g < G ? 1 : 2;
                 int cnt = 0;
-                for (int j = 0; j < LOOKAHEAD; j++) {
-                    const int sl = j * G + g;
+                for (int j = 0; j < THIN_SLOTS; j++) {
+                    const int sl = j * NL + g;
                     rec[4 + j] = slot_vi[sl];
-                    rec[8 + j] = slot_col[sl];
-                    rec[12 + j] = slot_code[sl];
+                    rec[4 + THIN_SLOTS + j] = slot_col[sl];
+                    rec[4 + 2 * THIN_SLOTS + j] = slot_code[sl];
                     cnt += slot_code[sl] != THIN_UNUSED;
                 }
                 rec[2] = cnt;
@@ -451,7 +476,8 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
             std::copy(&D.thin_rec[first * THIN_REC], &D.thin_rec[first * THIN_REC] + THIN_REC, rec);
             rec[2] = 0;
             rec[3] = 1;
-            for (int j = 0; j < LOOKAHEAD; j++) rec[12 + j] = THIN_UNUSED;
+            rec[THIN_REC - 1] = 0;
+            for (int j = 0; j < THIN_SLOTS; j++) rec[4 + 2 * THIN_SLOTS + j] = THIN_UNUSED;
             D.thin_rec.insert(D.thin_rec.end(), rec, rec + THIN_REC);
         }
         D.thin_lvl.push_back((int32_t)first);
@@ -464,7 +490,7 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
         D.thin_lvl.push_back(0);
         D.thin_lvl.push_back(0);
     }
-    D.thin_ngs = ngs == 3 ? 4 : ngs;
+    D.thin_ngs = ngs == 4 ? THIN_SLOTS : ngs;
     D.thin_lg = lg;
     D.thin_R = (int32_t)R;
     D.thin_RW = RW;
@@ -571,7 +597,8 @@ ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
     if (!D.thin_rec.empty()) {
         if (ddf_status s = upload(p, &D.d_thin_rec, D.thin_rec.data(), D.thin_rec.size())) return s;
         if (ddf_status s = upload(p, &D.d_thin_lvl, D.thin_lvl.data(), D.thin_lvl.size())) return s;
-        if (ddf_status s = dalloc(p, (void **)&D.d_thin_stream, D.thin_rec.size() / THIN_REC * THIN_SW * sizeof(double)))
+        if (ddf_status s = dalloc(p, (void **)&D.d_thin_stream,
+                                  (D.thin_rec.size() / THIN_REC + 64) * THIN_SW * sizeof(double)))
             return s;
         const int64_t slots = (int64_t)D.thin_rec.size() / THIN_REC >> D.thin_lg; // plan positions
         if (ddf_status s = dalloc(p, (void **)&D.d_thin_xs, slots * THIN_KT_MAX * sizeof(double))) return s;

@@ -241,7 +241,8 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
     value index and -<x[row], Xf[row]> at the diagonal."""
     rec, lvl, lg = tabs["thin_rec"], tabs["thin_lvl"], tabs["thin_lg"]
     R, RW, ngs = tabs["thin_ring_rows"], tabs["thin_ring_levels"], tabs["thin_ngs"]
-    assert RW >= 4 and RW & (RW - 1) == 0 and ngs in (0, 1, 2, 4)
+    S = 5  # op slots per lane
+    assert RW >= 4 and RW & (RW - 1) == 0 and ngs in (0, 1, 2, 3, 5)
     assert lvl.shape[0] % 4 == 0 and (lvl[-4:, 1] == 0).all()
     assert rec.shape[0] % 64 == 0 and tabs["thin_block"] >= lvl[:, 1].max()
     v = L.values if vals is None else vals
@@ -258,21 +259,26 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
         assert 0 < lanes <= 1024 and lanes % G == 0 and first % 64 == 0 and lanes // G <= R
         nxt = first + (lanes + 63) // 64 * 64
         assert (rec[first:first + lanes, 3] == 0).all() and (rec[first + lanes:nxt, 3] == 1).all()
-        assert (rec[first + lanes:nxt, 12:16] == THIN_UNUSED).all()
+        assert (rec[first + lanes:nxt, 4 + 2 * S:4 + 3 * S] == THIN_UNUSED).all()
         acc, diag, dpos, slot = {}, {}, {}, {}
         for s in range(lanes):
             r = rec[first + s]
-            row, dp, cnt = int(r[0]), int(r[1]), int(r[2])
-            if s % G == 0:
+            row, dp, cnt, wide = int(r[0]), int(r[1]), int(r[2]), int(r[19])
+            assert wide in (0, 1, 2)
+            if s % G == 0 and wide != 2:
+                # head of a row of G lanes (wide = 0) or of 2G lanes (wide = 1, 2G-aligned)
+                assert row not in acc and (wide == 0 or s % (2 * G) == 0)
                 acc[row] = np.zeros(k)
                 diag[row], dpos[row] = v[dp], dp
                 slot[row] = (l % RW) * R + s // G
                 assert plan_rows[(first + s) // G] == row
             else:
                 assert row in acc
-            assert cnt == sum(int(c) != THIN_UNUSED for c in r[12:16])
-            for j in range(4):
-                vi, col, code = int(r[4 + j]), int(r[8 + j]), int(r[12 + j])
+                prev = rec[first + s - (s % G if wide != 2 or s % G else G)]
+                assert int(prev[0]) == row and (wide == int(prev[19]) or (wide == 2 and int(prev[19]) == 1))
+            assert cnt == sum(int(c) != THIN_UNUSED for c in r[4 + 2 * S:4 + 3 * S])
+            for j in range(S):
+                vi, col, code = int(r[4 + j]), int(r[4 + S + j]), int(r[4 + 2 * S + j])
                 if code == THIN_UNUSED:
                     continue
                 m = level_of[col]

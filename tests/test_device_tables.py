@@ -139,6 +139,7 @@ def test_thin_records_workloads():
     p = hplan(1, w.L)
     F, T = ddf.ddf_plan_device_tables(p, 0), ddf.ddf_plan_device_tables(p, 1)
     assert F["thin_rec"].shape[0] and T["thin_rec"].shape[0]
+    assert (T["thin_rec"][:, 19] == 1).any()  # the transposed factor has rows of 2G lanes
     replay_solve(w.L, k=1)
     # a level wider than one pass is not eligible
     L = I.tril(I.laplacian(1200, 1200, 1, I.OFFS_5PT, 4.0))
