@@ -1,5 +1,8 @@
 """The oracle inspector (Algorithm 1 with the FOPD classification and Eq. (1)) pinned to the
 paper's worked example, hand-derived plans, definition-level brute force and invariants."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -9,26 +12,29 @@ from plan_decode import (C, F_RECT, F_RUNS, F_S0, F_S1, F_S2, F_SEP, codelet_row
                          expected_triples)
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "psc_worked_example.json")
+
+
 def worked_example():
-    # Sec. III-C/D: three rows, three ops each; values at 0..8; x at i0 + s[i1], s = {0,2,5}
-    rows = np.repeat(np.arange(3), 3)
-    cols = np.array([0, 2, 5, 1, 3, 6, 2, 4, 7])
-    return I.csr_from_pairs(3, 8, rows, cols, np.arange(9.0))
+    g = json.load(open(GOLDEN))
+    vals = np.arange(float(len(g["cols"])))
+    return I.csr_from_pairs(g["n_rows"], g["n_cols"], np.array(g["rows"]), np.array(g["cols"]), vals)
 
 
 def test_paper_worked_example():
+    e = json.load(open(GOLDEN))["expect"]
     p = O.inspect(0, worked_example())
     assert p["codelets"].shape == (1, 18)
     c = dict(zip(O.COD_FIELDS, p["codelets"][0]))
-    assert c["type"] == 1  # PSC I: f0 and f1 strided, h (x) not
+    assert c["type"] == e["type"]  # PSC I: f0 and f1 strided, h (x) not
     assert c["flags"] == F_S0 | F_S1 | F_SEP | F_RECT
-    assert c["op_step"] == 3  # FOPD_i0 of g = 3, FOPD_i1 = 1
-    assert c["sigma0"] == 1
-    assert list(p["aux"]) == [0, 2, 5]  # the shared offset table s
+    assert c["op_step"] == e["op_step"]  # FOPD_i0 of g = 3, FOPD_i1 = 1
+    assert c["sigma0"] == e["sigma0"]
+    assert list(p["aux"]) == e["offsets"]  # the shared offset table s
     # h needs |s| + 1 = 4 loads; Eq. (1): 9 ops + 3 functions + 3 table entries
-    assert c["cost"] == 15
+    assert c["cost"] == e["cost"]
     # a 3-BLAS cover would cost 3 * (3 + 3) = 18 > 15, and needs 9 loads (3 per codelet)
-    assert p["regions"][0, 5:].tolist() == [15, 15, 15]
+    assert p["regions"][0, 5:].tolist() == e["region_costs"]
 
 
 def test_worked_example_fopd():
