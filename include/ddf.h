@@ -78,7 +78,8 @@ typedef struct {
                               tables into the solver's L2; -1 default (2), 0 none, max 8  */
     int32_t thin_ahead;    /* single-block solve: levels the helpers run ahead; 0 default
                               (32), at least 8                                              */
-    int32_t reserved[1];
+    int32_t thin_ring;     /* single-block solve: LDS ring of recent solutions, in rows; a
+                              power of two in 256..16384; 0 default (16384)                */
 } ddf_opts;
 
 typedef struct {
@@ -262,16 +263,18 @@ typedef struct {
     const int32_t *thin_rec; /* single-block solve: [n_thin_rec][20] per lane slot: row, value
                                 index of the diagonal, ops, placeholder flag (levels start on
                                 64-record boundaries), value indices[5], columns[5],
-                                operand codes[5]: INT32_MIN empty; >= 0 plan position (first
-                                record / lane slots per row) of a row read from global
-                                memory; else -(1 + ring slot); 0                            */
-    const int32_t *thin_lvl; /* [n][2] first record, lane slots in use, per level, then empty
-                                levels up to a multiple of 4 plus 4 (absent: n = 0)        */
+                                operand codes[5]: INT32_MIN empty; >= 0 solve-order index of
+                                a row read from global memory; else -(1 + ring slot); then
+                                0, or 1 / 2 for the first / second half of a row of 2G lanes */
+    const int32_t *thin_lvl; /* [n][4] first record, lane slots in use, first solve-order
+                                index, rows of 2G lanes, per level, then empty levels up to a
+                                multiple of 4 plus 4 (absent: n = 0)                        */
+    const int32_t *thin_rows; /* [n_rows] row of each solve-order index (absent: NULL)      */
     int64_t n_thin_rec, n_thin_lvl;
     int32_t thin_lg;          /* log2 lane slots per row                                       */
-    int32_t thin_ring_rows;   /* operand codes < 0: slot = -(code + 1) = (level mod ring_levels)
-                                 * ring_rows + position of the row in its level               */
-    int32_t thin_ring_levels;
+    int32_t thin_ring_size;   /* operand codes < 0: slot = -(code + 1) = solve-order index of
+                                 the row mod thin_ring_size                                    */
+    int32_t thin_reserved;
     int32_t thin_ngs;         /* op slots per lane (the lowest) that may read global memory   */
     int32_t thin_block;       /* threads of the solving block                                  */
     int32_t reserved;

@@ -87,16 +87,17 @@ struct DevTables {
     std::vector<int32_t> sync;         // solve: 4 int32 per task (wait counter, count, signal counter)
     int64_t n_counters = 0;            // solve: level counters the schedule uses
     std::vector<int32_t> thin_rec;     // single-block solve records (empty if not eligible)
-    std::vector<int32_t> thin_lvl;     // per level: first record, lanes
+    std::vector<int32_t> thin_lvl;     // per level: first record, lanes, first solve index, wide rows
+    std::vector<int32_t> thin_rows;    // row of each solve-order index
     int32_t thin_lg = 0;
-    int32_t thin_R = 0;                // ring rows (widest level)
-    int32_t thin_RW = 0;               // ring levels
+    int32_t thin_ring = 0;             // LDS ring size in plan positions
     int32_t thin_nlev_pad = 0;         // levels rounded up to a multiple of 3
     int32_t thin_ngs = 0;              // op slots per lane that may hold a global operand
     int32_t thin_block = 64;           // threads of the solving block (widest level, rounded to 64)
-    double *d_thin_xs = nullptr;       // solutions in plan order
+    double *d_thin_xs = nullptr;       // solutions in solve order
     int32_t *d_thin_rec = nullptr;
     int32_t *d_thin_lvl = nullptr;
+    int32_t *d_thin_rows = nullptr;
     double *d_thin_stream = nullptr;   // per-call stream, THIN_SW doubles per record
     DCod *d_cods = nullptr;
     int32_t *d_aux = nullptr;
@@ -107,7 +108,7 @@ struct DevTables {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
                (int64_t)tasks.size() * sizeof(Task) + (int64_t)sync.size() * 4;
     }
-    int64_t thin_bytes() const { return (int64_t)(thin_rec.size() + thin_lvl.size()) * 4; }
+    int64_t thin_bytes() const { return (int64_t)(thin_rec.size() + thin_lvl.size() + thin_rows.size()) * 4; }
     // bytes a launch reads: records and aux (upper bound) plus its own task list
     int64_t launch_bytes(bool many_rhs) const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +

@@ -635,16 +635,48 @@ __global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
 // just ahead into the shared L2.
 // ------------------------------------------------------------------------------------------
 
+// Lane exchange within 16-lane rows through DPP (no LDS round trip): the value of lane
+// i ^ d for d in {1, 2, 4, 8}; other distances go through the LDS crossbar.
+template <int D> __device__ __forceinline__ int dpp_xor_i(int v) {
+    if constexpr (D == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);      // quad_perm 1,0,3,2
+    else if constexpr (D == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); // quad_perm 2,3,0,1
+    else if constexpr (D == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); // row_ror 8
+    else {
+        const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0xF, false); // row_shl 4: lane i + 4
+        const int dn = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false); // row_shr 4: lane i - 4
+        return (__lane_id() & 4) ? dn : up;
+    }
+}
+template <int D> __device__ __forceinline__ double dpp_xor(double v) {
+    const int lo = dpp_xor_i<D>(__double2loint(v)), hi = dpp_xor_i<D>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+// v of lane i ^ D: DPP within 16-lane rows for D <= 8, the LDS crossbar beyond
+template <int D> __device__ __forceinline__ double lane_xor(double v) {
+    if constexpr (D <= 8) return dpp_xor<D>(v);
+    else return __shfl_xor(v, D, WAVE);
+}
+// sum over aligned groups of G = 2^LG lanes; every lane gets its group's sum
+template <int LG, int KT> __device__ __forceinline__ void group_sum_c(double (&acc)[KT]) {
+    if constexpr (LG > 0) {
+        group_sum_c<LG - 1, KT>(acc);
+#pragma unroll
+        for (int r = 0; r < KT; r++) acc[r] += lane_xor<(1 << (LG - 1))>(acc[r]);
+    }
+}
+
 // level table entry through the constant address space: a scalar load, counted apart from the
 // vector memory operations
 typedef const __attribute__((address_space(4))) long long *const_i64_ptr;
-__device__ __forceinline__ int2 thin_lvl(const ThinArgs &a, int l) {
-    const long long e = ((const_i64_ptr)(a.lvl))[l];
-    return make_int2((int)(unsigned)(e & 0xffffffffll), (int)(e >> 32));
+__device__ __forceinline__ int4 thin_lvl(const ThinArgs &a, int l) {
+    const const_i64_ptr p = (const_i64_ptr)(a.lvl) + 2 * (int64_t)l;
+    const long long e0 = p[0], e1 = p[1];
+    return make_int4((int)(unsigned)(e0 & 0xffffffffll), (int)(e0 >> 32), (int)(unsigned)(e1 & 0xffffffffll),
+                     (int)(e1 >> 32));
 }
 
 // whether the wave holding lane s has a lane in use at a level (uniform over the wave)
-__device__ __forceinline__ bool thin_wave_on(int2 lv, int s) { return (s & ~(WAVE - 1)) < lv.y; }
+__device__ __forceinline__ bool thin_wave_on(int4 lv, int s) { return (s & ~(WAVE - 1)) < lv.y; }
 
 template <int KT> struct ThinA {
     int code[THIN_SLOTS];
@@ -660,7 +692,7 @@ template <int KT, int NGS> struct ThinB {
 // counts cover it on both.
 template <int KT>
 __device__ __forceinline__ void thin_fetch_a(const ThinArgs &a, int l, int s, ThinA<KT> &t) {
-    const int2 lv = thin_lvl(a, l);
+    const int4 lv = thin_lvl(a, l);
     const int64_t p = thin_wave_on(lv, s) ? (int64_t)lv.x + s : a.n_rec + (s & (WAVE - 1));
     const double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
     const int4 c = *reinterpret_cast<const int4 *>(w);
@@ -674,7 +706,7 @@ __device__ __forceinline__ void thin_fetch_a(const ThinArgs &a, int l, int s, Th
     t.v[0] = v01.x; t.v[1] = v01.y; t.v[2] = v23.x; t.v[3] = v23.y; t.v[4] = v4d.x;
     t.d = v4d.y;
     t.b[0] = __hiloint2double(bc.y, bc.x);
-    if (KT > 1) t.b[1] = reinterpret_cast<const double2 *>(w + 640)->x;
+    static_assert(KT == 1, "one right-hand side");
 }
 
 template <int KT, int NGS>
@@ -693,10 +725,12 @@ __device__ __forceinline__ void thin_fetch_b(const ThinArgs &a, const ThinA<KT> 
     }
 }
 
-template <int KT, int NGS>
-__device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, int g, int G, const ThinA<KT> &t,
+template <int KT, int NGS, int LG>
+__device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, const ThinA<KT> &t,
                                              const ThinB<KT, NGS> &u, double *ring) {
-    const int2 lv = thin_lvl(a, l);
+    constexpr int G = 1 << LG;
+    const int g = s & (G - 1);
+    const int4 lv = thin_lvl(a, l);
     double acc[KT];
 #pragma unroll
     for (int rr = 0; rr < KT; rr++) acc[rr] = 0.0;
@@ -712,23 +746,24 @@ __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, in
             acc[rr] = fma(t.v[j], used ? xo : 0.0, acc[rr]);
         }
     }
-    group_sum<KT>(acc, G);
+    group_sum_c<LG, KT>(acc);
     if (__any(t.wide != 0)) {
         // rows of 2G lanes: add the other half
 #pragma unroll
         for (int rr = 0; rr < KT; rr++) {
-            const double o = __shfl_xor(acc[rr], G, WAVE);
+            const double o = lane_xor<G>(acc[rr]);
             if (t.wide) acc[rr] += o;
         }
     }
     if (s < lv.y && t.wide != 2) {
-        const int pos = s >> a.lg;
-        const int64_t rp = ((int64_t)lv.x >> a.lg) + pos; // plan position of the row
-        const int slot = (l & (a.ring_levels - 1)) * a.ring_rows + pos;
+        // solve-order index: the level's first, plus the row's rank (wide rows of 2G lanes first)
+        const int ww = lv.w << (LG + 1);
+        const int64_t rp = lv.z + (s < ww ? s >> (LG + 1) : lv.w + ((s - ww) >> LG));
+        const int slot = (int)(rp & (a.ring - 1));
 #pragma unroll
         for (int rr = 0; rr < KT; rr++)
             if ((rr & (G - 1)) == g && rr < a.k) {
-                const double xn = (t.b[rr] - acc[rr]) / t.d;
+                const double xn = (t.b[rr] - acc[rr]) * t.d; // t.d holds 1 / diagonal
                 a.xs[rp * KT + rr] = xn;
                 ring[slot * KT + rr] = xn;
             }
@@ -737,10 +772,10 @@ __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, in
 
 // One level: solve it, then gather the global operands of the level two ahead and fetch the
 // stream entry of the level four ahead (into the slot this level used).
-template <int KT, int NGS>
-__device__ __forceinline__ void thin_step(const ThinArgs &a, int l, int s, int g, int G, ThinA<KT> &a0,
-                                          ThinB<KT, NGS> &b0, const ThinA<KT> &a2, double *ring) {
-    thin_compute<KT, NGS>(a, l, s, g, G, a0, b0, ring);
+template <int KT, int NGS, int LG>
+__device__ __forceinline__ void thin_step(const ThinArgs &a, int l, int s, ThinA<KT> &a0, ThinB<KT, NGS> &b0,
+                                          const ThinA<KT> &a2, double *ring) {
+    thin_compute<KT, NGS, LG>(a, l, s, a0, b0, ring);
     __builtin_amdgcn_sched_barrier(0);
     thin_fetch_b<KT, NGS>(a, a2, b0);
     thin_fetch_a<KT>(a, l + 4, s, a0);
@@ -767,7 +802,7 @@ __device__ void thin_helper(const ThinArgs &a) {
             if (++polls > (int64_t(1) << 24)) return;
             __builtin_amdgcn_s_sleep(4);
         }
-        const int2 lv = thin_lvl(a, l);
+        const int4 lv = thin_lvl(a, l);
         const uintptr_t s0 = reinterpret_cast<uintptr_t>(a.stream + (int64_t)lv.x * THIN_SW);
         const uintptr_t s1 = s0 + (uintptr_t)((lv.y + 63) & ~63) * THIN_SW * 8;
 #pragma unroll 4
@@ -777,7 +812,7 @@ __device__ void thin_helper(const ThinArgs &a) {
     if (sink == 0x9e3779b9u) *a.sink = sink; // keeps the loads
 }
 
-template <int KT, int NGS>
+template <int KT, int NGS, int LG>
 __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
     static_assert(THIN_SLOTS == 5, "stream layout");
     if (blockIdx.x != 0) {
@@ -787,7 +822,6 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
     }
     extern __shared__ double ring[];
     const int s = threadIdx.x;
-    const int G = 1 << a.lg, g = s & (G - 1);
     ThinA<KT> A0, A1, A2, A3;
     ThinB<KT, NGS> B0, B1;
     // same issue order as the loop's steady state (gathers for l + 1, then stream l + 3), so
@@ -802,15 +836,15 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
     thin_fetch_a<KT>(a, 3, s, A3);
     __builtin_amdgcn_sched_barrier(0);
     for (int l = 0; l < a.nlev_pad; l += 4) {
-        thin_step<KT, NGS>(a, l, s, g, G, A0, B0, A2, ring);
-        thin_step<KT, NGS>(a, l + 1, s, g, G, A1, B1, A3, ring);
-        thin_step<KT, NGS>(a, l + 2, s, g, G, A2, B0, A0, ring);
-        thin_step<KT, NGS>(a, l + 3, s, g, G, A3, B1, A1, ring);
+        thin_step<KT, NGS, LG>(a, l, s, A0, B0, A2, ring);
+        thin_step<KT, NGS, LG>(a, l + 1, s, A1, B1, A3, ring);
+        thin_step<KT, NGS, LG>(a, l + 2, s, A2, B0, A0, ring);
+        thin_step<KT, NGS, LG>(a, l + 3, s, A3, B1, A1, ring);
     }
 }
 
 // Per-call gather, in record order, of each slot's operand codes, values (0 for empty slots),
-// diagonal and b.  Also clears the solver's progress word before the solve starts.
+// the reciprocal of the diagonal and b.  Also clears the solver's progress word before the solve starts.
 __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p == 0) *a.progress = 0u;
@@ -823,7 +857,6 @@ __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
         *reinterpret_cast<double2 *>(w + 256) = make_double2(0.0, 0.0);
         *reinterpret_cast<double2 *>(w + 384) = make_double2(0.0, 1.0);
         *reinterpret_cast<int4 *>(w + 512) = make_int4(0, 0, THIN_UNUSED, 0);
-        *reinterpret_cast<double2 *>(w + 640) = make_double2(0.0, 0.0);
         return;
     }
     const int32_t *r = a.rec + p * THIN_REC;
@@ -837,44 +870,16 @@ __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
     *reinterpret_cast<int4 *>(w) = make_int4(co[0], co[1], co[2], co[3]);
     *reinterpret_cast<double2 *>(w + 128) = make_double2(v[0], v[1]);
     *reinterpret_cast<double2 *>(w + 256) = make_double2(v[2], v[3]);
-    *reinterpret_cast<double2 *>(w + 384) = make_double2(v[4], a.vals[dpos]);
+    *reinterpret_cast<double2 *>(w + 384) = make_double2(v[4], 1.0 / a.vals[dpos]);
     *reinterpret_cast<int4 *>(w + 512) = make_int4(__double2loint(bv), __double2hiint(bv), co[4], r[THIN_REC - 1]);
-    if (a.kt > 1) *reinterpret_cast<double2 *>(w + 640) = make_double2(a.k > 1 ? a.b[rb + 1] : 0.0, 0.0);
 }
 
-// Solutions from plan order into row order.
+// Solutions from solve order into row order.
 __global__ __launch_bounds__(256) void k_thin_scatter(ThinArgs a) {
-    const int64_t rp = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (rp >= a.n) return;
-    const int32_t *q = a.rec + (rp << a.lg) * THIN_REC;
-    if (q[3] || q[THIN_REC - 1] == 2) return; // placeholder, or second half of a wide row
-    const int64_t row = q[0];
-    for (int r = 0; r < a.k; r++) a.x[row * a.k + r] = a.xs[rp * a.kt + r];
-}
-
-// Value gradient of the transposed solve, after the scatter: entry (c, row) of L (an op of
-// record row `row`, column c) gets -<lambda_c, xf_row>; the diagonal -<lambda_row, xf_row>
-// (first lane of the row).
-__global__ __launch_bounds__(256) void k_thin_gv(ThinArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.n_rec) return;
-    const int32_t *r = a.rec + p * THIN_REC;
-    if (r[3]) return; // placeholder
-    const int32_t *vi = r + 4, *cc = r + 4 + THIN_SLOTS, *co = r + 4 + 2 * THIN_SLOTS;
-    const int k = a.k;
-    const int64_t rb = (int64_t)r[0] * k;
-#pragma unroll
-    for (int j = 0; j < THIN_SLOTS; j++)
-        if (co[j] != THIN_UNUSED) {
-            double t = 0.0;
-            for (int q = 0; q < k; q++) t = fma(a.x[(int64_t)cc[j] * k + q], a.xf[rb + q], t);
-            a.gv[vi[j]] = -t;
-        }
-    if ((p & ((1 << a.lg) - 1)) == 0 && r[THIN_REC - 1] != 2) {
-        double t = 0.0;
-        for (int q = 0; q < k; q++) t = fma(a.x[rb + q], a.xf[rb + q], t);
-        a.gv[r[1]] = -t;
-    }
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= a.n) return;
+    const int64_t row = a.rows[q];
+    for (int r = 0; r < a.k; r++) a.x[row * a.k + r] = a.xs[q * a.kt + r];
 }
 
 __global__ void k_reset(unsigned *p, int64_t n) {
@@ -1063,26 +1068,41 @@ hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int KT>
-static void launch_thin_kt(const ThinArgs &a, int ngs, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-    if (ngs == 0) hipLaunchKernelGGL((k_solve_thin<KT, 0>), grid, block, lds, s, a);
-    else if (ngs == 1) hipLaunchKernelGGL((k_solve_thin<KT, 1>), grid, block, lds, s, a);
-    else if (ngs == 2) hipLaunchKernelGGL((k_solve_thin<KT, 2>), grid, block, lds, s, a);
-    else if (ngs == 3) hipLaunchKernelGGL((k_solve_thin<KT, 3>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_solve_thin<KT, THIN_SLOTS>), grid, block, lds, s, a);
+template <int NGS, int LG>
+static void launch_thin(const ThinArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    static bool attr = false; // more dynamic LDS than the default 64 KiB
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_thin<1, NGS, LG>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, THIN_RING_MAX * 8);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_solve_thin<1, NGS, LG>), grid, block, lds, s, a);
+}
+
+template <int NGS>
+static void launch_thin_lg(const ThinArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    switch (a.lg) {
+    case 0: launch_thin<NGS, 0>(a, grid, block, lds, s); break;
+    case 1: launch_thin<NGS, 1>(a, grid, block, lds, s); break;
+    case 2: launch_thin<NGS, 2>(a, grid, block, lds, s); break;
+    case 3: launch_thin<NGS, 3>(a, grid, block, lds, s); break;
+    case 4: launch_thin<NGS, 4>(a, grid, block, lds, s); break;
+    default: launch_thin<NGS, 5>(a, grid, block, lds, s); break;
+    }
 }
 
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     if (a.nlev == 0) return hipSuccess;
-    const dim3 pgrid((unsigned)((a.n_rec + 255) / 256)), sgrid((unsigned)((a.n_rec + 64 + 255) / 256)),
-        rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
+    const dim3 sgrid((unsigned)((a.n_rec + 64 + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
     hipLaunchKernelGGL(k_thin_stream, sgrid, pblock, 0, s, a);
     const dim3 grid(1 + 8 * (unsigned)a.helpers), block((unsigned)a.block);
-    const size_t lds = (size_t)a.ring_levels * a.ring_rows * a.kt * sizeof(double);
-    if (a.kt == 1) launch_thin_kt<1>(a, ngs, grid, block, lds, s);
-    else launch_thin_kt<2>(a, ngs, grid, block, lds, s);
+    const size_t lds = (size_t)a.ring * sizeof(double);
+    if (ngs == 0) launch_thin_lg<0>(a, grid, block, lds, s);
+    else if (ngs == 1) launch_thin_lg<1>(a, grid, block, lds, s);
+    else if (ngs == 2) launch_thin_lg<2>(a, grid, block, lds, s);
+    else if (ngs == 3) launch_thin_lg<3>(a, grid, block, lds, s);
+    else launch_thin_lg<THIN_SLOTS>(a, grid, block, lds, s);
     hipLaunchKernelGGL(k_thin_scatter, rgrid, pblock, 0, s, a);
-    if (a.gv) hipLaunchKernelGGL(k_thin_gv, pgrid, pblock, 0, s, a);
     return hipGetLastError();
 }
 

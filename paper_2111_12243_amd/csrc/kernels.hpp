@@ -32,48 +32,47 @@ struct SpmvArgs {
 // THIN_SLOTS op slots per lane.  Static record per lane slot and level, THIN_REC int32:
 //   [0] row, [1] value index of the diagonal, [2] ops in the lane, [3] placeholder flag,
 //   [4..8] value index of each op slot, [9..13] its column,
-//   [14..18] its operand code: THIN_UNUSED for an empty slot; >= 0 the plan position of a row
-//   solved at least THIN_HORIZON levels before, read from global memory (only in the first
+//   [14..18] its operand code: THIN_UNUSED for an empty slot; >= 0 the solve-order index of a
+//   row solved at least THIN_HORIZON levels before, read from global memory (only in the first
 //   `ngs` slots); otherwise -(1 + ring slot) of the LDS ring that keeps the solutions of the
-//   last ring_levels levels, ring slot = (level mod ring_levels) * ring_rows + position in level;
+//   last `ring` rows solved, ring slot = solve-order index mod ring;
 //   [19] 0 for a row of G lanes; a "wide" row takes 2G lanes (its first G flagged 1, the
 //   others 2) and comes before the other rows of its level.
 // Every level's records start on a 64-record boundary; placeholder records (flag 1, no ops)
-// fill the gap.  The plan position of a row is the index of its first record / G.  Per call, a
-// stream is gathered in record order, structure-of-arrays per 64 records: six 16-byte fields
-// (codes 0..3, v0 v1, v2 v3, v4 and diagonal, b[0] code 4 wide flag, b[1] and pad) of 64 records
-// each, then one chunk of empty records that waves with no lane in use at a level read.  The
-// solve writes solutions in plan order, and a scatter puts them in row order.
+// fill the gap.  The solve order numbers rows level by level, wide rows first.  Per call, a
+// stream is gathered in record order, structure-of-arrays per 64 records: five 16-byte fields
+// (codes 0..3, v0 v1, v2 v3, v4 and 1/diagonal, b code 4 wide flag) of 64 records each, then one
+// chunk of empty records that waves with no lane in use at a level read.  The solve writes
+// solutions in solve order, and a scatter puts them in row order.  One right-hand side.
 constexpr int THIN_SLOTS = 5;
 constexpr int THIN_REC = 20;
-constexpr int THIN_SW = 12;               // stream doubles per record
+constexpr int THIN_SW = 10;                 // stream doubles per record
 constexpr int THIN_THREADS = 1024;
-constexpr int THIN_KT_MAX = 2;            // right-hand sides the single-block kernel takes
-constexpr int THIN_RING_BYTES = 64 << 10; // LDS ring, sized for THIN_KT_MAX
+constexpr int THIN_KT_MAX = 1;              // right-hand sides the single-block kernel takes
+constexpr int THIN_RING_MAX = 16384;       // LDS ring of solutions, plan positions (128 KiB)
 constexpr int THIN_HORIZON = 3;           // a global operand's row was solved this many levels before
 constexpr int32_t THIN_UNUSED = (int32_t)0x80000000;
 struct ThinArgs {
     const int32_t *rec;
-    const int2 *lvl; // per level: first record, lanes in use (padded with empty levels)
+    const int4 *lvl; // per level: first record, lanes in use, first solve index, wide rows
+                     // (padded with empty levels)
+    const int32_t *rows; // row of each solve-order index
     int32_t nlev;     // levels
     int32_t nlev_pad; // levels rounded up to a multiple of 4 (the table holds 4 more)
     int32_t lg;       // log2 lanes per row
     int32_t k;        // right-hand sides (at most the kernel's KT)
     int32_t kt;       // the kernel's KT (stride of xs)
-    int32_t ring_rows;   // rows per ring level (the widest level)
-    int32_t ring_levels; // levels in the ring (a power of two, >= 4)
+    int32_t ring;     // LDS ring size in plan positions (a power of two)
     int32_t helpers;  // blocks that pull upcoming levels into the solver's L2
     int32_t ahead;    // levels the helpers may run ahead of the solver
-    int32_t n;        // plan positions (records / G)
+    int32_t n;        // rows
     int32_t block;    // threads of the solving block
     int64_t n_rec;    // records (a multiple of 64; the stream holds one more chunk)
     const double *vals;
     const double *b;
     double *x;
-    const double *xf;   // adjoint with value gradient: the forward solution
-    double *gv;         // adjoint: gradient of the values (NULL: not wanted)
     double *stream;     // THIN_SW doubles per record, gathered before the solve
-    double *xs;         // solutions in plan order, kt per row
+    double *xs;         // solutions in solve order, kt per row
     unsigned *progress; // levels the solver has finished (read by the helpers)
     unsigned *sink;     // helpers' discard word (never read)
 };

@@ -358,9 +358,10 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
 // Records of the single-block solve, built from a matrix's codelets level by level (rows in
 // plan order).  Eligible when every row has at most 64 * THIN_SLOTS ops and every level fits
 // one 1024-lane pass; value indices go through perm for the transposed solve.
-void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *perm, DevTables &D) {
+void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *perm, int32_t ring, DevTables &D) {
     D.thin_rec.clear();
     D.thin_lvl.clear();
+    D.thin_rows.clear();
     D.thin_block = 64;
     const int64_t n = P.n_rows;
     // G lanes per row cover all but about 1% of rows; the rest ("wide" rows) take 2G lanes
@@ -379,52 +380,67 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
     while (((int64_t(THIN_SLOTS) << lg) < p99 || (int64_t(THIN_SLOTS) << (lg + 1)) < maxn) && lg < 5) lg++;
     if ((int64_t(THIN_SLOTS) << (lg + 1)) < maxn) return;
     const int G = 1 << lg;
-    auto lanes_of = [&](int64_t row) -> int { return P.nops(row) > (int64_t)G * THIN_SLOTS ? 2 * G : G; };
+    // lanes per row: 2G ("wide") when its ops do not fit G lanes, or when its operands from
+    // global memory would need more than one slot per lane
+    std::vector<uint8_t> wide(n, 0);
+    for (int64_t r = 0; r < n; r++) wide[r] = P.nops(r) > (int64_t)G * THIN_SLOTS;
+    auto lanes_of = [&](int64_t row) -> int { return wide[row] ? 2 * G : G; };
     const int64_t nl = c.header[5];
     // codelets of each level, in plan order
     std::vector<std::vector<int64_t>> by_level(nl);
     for (int64_t i = 0; i < c.header[7]; i++) by_level[c.codelets[i * NCOD + C_PART]].push_back(i);
-    // rows of each level in plan order, wide rows first (so they start on 2G-lane boundaries);
-    // a row's position in its level is its first lane / G
-    std::vector<int32_t> lev(n, -1), pos(n, -1);
+    std::vector<int32_t> lev(n, -1);
     std::vector<std::vector<int64_t>> rows_of(nl);
+    // solve order of a row: its index in plan order (levels in turn, wide rows first in each);
+    // lvl_end: one past a level's last solve-order index; R: widest level in G-lane groups
+    std::vector<int64_t> plan_pos(n, -1), lvl_end(nl, 0);
+    std::vector<int32_t> nwide(nl, 0);
     int64_t R = 1;
-    for (int64_t l = 0; l < nl; l++) {
-        std::vector<int64_t> narrow;
-        for (int64_t ci : by_level[l]) {
-            const int64_t *r = &c.codelets[ci * NCOD];
-            const int32_t fl = (int32_t)r[C_FLAGS];
-            for (int64_t a = 0; a < r[C_M]; a++) {
-                const int64_t row = (fl & FS0) ? r[C_ROW0] + a * r[C_ROWSTEP] : c.aux[r[C_AUXOFF] + a];
-                (lanes_of(row) > G ? rows_of[l] : narrow).push_back(row);
-            }
-        }
-        rows_of[l].insert(rows_of[l].end(), narrow.begin(), narrow.end());
-        int64_t q = 0;
-        for (int64_t row : rows_of[l]) {
-            lev[row] = (int32_t)l;
-            pos[row] = (int32_t)q;
-            q += lanes_of(row) / G;
-        }
-        R = std::max(R, q);
-    }
-    if (R * G > THIN_THREADS) return;
-    int RW = 1;
-    while ((int64_t)RW * 2 * R * THIN_KT_MAX * 8 <= THIN_RING_BYTES && RW < 16) RW *= 2;
-    if (RW < 4) return;
-    // plan position of a row: index of its first record / G (levels start on 64-record
-    // boundaries, padded with placeholder records)
-    std::vector<int64_t> plan_pos(n, -1);
-    {
+    auto layout = [&]() {
+        // rows of each level in plan order, wide rows first (so they start on 2G-lane boundaries)
+        R = 1;
         int64_t q = 0;
         for (int64_t l = 0; l < nl; l++) {
-            for (int64_t row : rows_of[l]) {
-                plan_pos[row] = q;
-                q += lanes_of(row) / G;
+            std::vector<int64_t> narrow;
+            rows_of[l].clear();
+            for (int64_t ci : by_level[l]) {
+                const int64_t *r = &c.codelets[ci * NCOD];
+                const int32_t fl = (int32_t)r[C_FLAGS];
+                for (int64_t a = 0; a < r[C_M]; a++) {
+                    const int64_t row = (fl & FS0) ? r[C_ROW0] + a * r[C_ROWSTEP] : c.aux[r[C_AUXOFF] + a];
+                    (wide[row] ? rows_of[l] : narrow).push_back(row);
+                }
             }
-            q = (q * G + 63) / 64 * 64 / G;
+            nwide[l] = (int32_t)rows_of[l].size();
+            rows_of[l].insert(rows_of[l].end(), narrow.begin(), narrow.end());
+            int64_t groups = 0;
+            for (int64_t row : rows_of[l]) {
+                lev[row] = (int32_t)l;
+                plan_pos[row] = q++;
+                groups += lanes_of(row) / G;
+            }
+            lvl_end[l] = q;
+            R = std::max(R, groups);
         }
-    }
+    };
+    // an operand is read from the LDS ring unless a position written up to the reading level
+    // has overwritten its slot
+    auto is_global = [&](int64_t col, int64_t l) { return plan_pos[col] < lvl_end[l] - ring; };
+    layout();
+    bool changed = false;
+    for (int64_t l = 0; l < nl; l++)
+        for (int64_t row : rows_of[l]) {
+            if (wide[row]) continue;
+            const int64_t op = P.opstart(row), no = P.nops(row);
+            int64_t ng = 0;
+            for (int64_t i = 0; i < no; i++) ng += is_global(P.ci[op + i], l);
+            if (ng > G && 2 * G * THIN_SLOTS >= no) {
+                wide[row] = 1;
+                changed = true;
+            }
+        }
+    if (changed) layout();
+    if (R * G > THIN_THREADS) return;
     auto vidx = [&](int64_t e) -> int32_t { return perm ? (*perm)[e] : (int32_t)e; };
     int ngs = 0;
     std::vector<int32_t> slot_vi, slot_col, slot_code;
@@ -445,12 +461,17 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
                 for (int64_t i = 0; i < no; i++) {
                     const int32_t col = P.ci[op + i];
                     const int64_t m = lev[col];
-                    const bool global = m <= l - RW;
+                    const bool global = is_global(col, l);
+                    if (global && m > l - THIN_HORIZON) { // ring too small for this matrix
+                        D.thin_rec.clear();
+                        D.thin_lvl.clear();
+                        return;
+                    }
                     if (global != (pass == 0)) continue;
                     slot_vi[next] = vidx(op + i);
                     slot_col[next] = col;
                     slot_code[next] = global ? (int32_t)plan_pos[col]
-                                             : -(1 + (int32_t)((m & (RW - 1)) * R + pos[col]));
+                                             : -(1 + (int32_t)(plan_pos[col] & (ring - 1)));
                     if (global) ngs = std::max(ngs, next / NL + 1);
                     next++;
                 }
@@ -482,6 +503,8 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
         }
         D.thin_lvl.push_back((int32_t)first);
         D.thin_lvl.push_back((int32_t)lanes);
+        D.thin_lvl.push_back((int32_t)(lvl_end[l] - (int64_t)rows_of[l].size()));
+        D.thin_lvl.push_back(nwide[l]);
         D.thin_block = std::max<int32_t>(D.thin_block, (int32_t)((lanes + 63) / 64 * 64));
     }
     // empty levels up to a multiple of four, and four more for the kernel's fetches ahead
@@ -489,11 +512,15 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
     for (int64_t l = nl; l < pad + 4; l++) {
         D.thin_lvl.push_back(0);
         D.thin_lvl.push_back(0);
+        D.thin_lvl.push_back((int32_t)n);
+        D.thin_lvl.push_back(0);
     }
+    // row of each solve-order index
+    D.thin_rows.assign(n, 0);
+    for (int64_t r = 0; r < n; r++) D.thin_rows[plan_pos[r]] = (int32_t)r;
     D.thin_ngs = ngs == 4 ? THIN_SLOTS : ngs;
     D.thin_lg = lg;
-    D.thin_R = (int32_t)R;
-    D.thin_RW = RW;
+    D.thin_ring = ring;
     D.thin_nlev_pad = (int32_t)pad;
 }
 
@@ -597,11 +624,11 @@ ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
     if (!D.thin_rec.empty()) {
         if (ddf_status s = upload(p, &D.d_thin_rec, D.thin_rec.data(), D.thin_rec.size())) return s;
         if (ddf_status s = upload(p, &D.d_thin_lvl, D.thin_lvl.data(), D.thin_lvl.size())) return s;
+        if (ddf_status s = upload(p, &D.d_thin_rows, D.thin_rows.data(), D.thin_rows.size())) return s;
         if (ddf_status s = dalloc(p, (void **)&D.d_thin_stream,
                                   (D.thin_rec.size() / THIN_REC + 64) * THIN_SW * sizeof(double)))
             return s;
-        const int64_t slots = (int64_t)D.thin_rec.size() / THIN_REC >> D.thin_lg; // plan positions
-        if (ddf_status s = dalloc(p, (void **)&D.d_thin_xs, slots * THIN_KT_MAX * sizeof(double))) return s;
+        if (ddf_status s = dalloc(p, (void **)&D.d_thin_xs, D.thin_rows.size() * sizeof(double))) return s;
     }
     return upload(p, &D.d_aux, D.aux.data(), D.aux.size());
 }
@@ -612,19 +639,18 @@ bool use_thin(const DevTables &D, const SchedParams &sp, int32_t k) {
 }
 
 ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, int nlev, const double *vals,
-                       const double *b, double *x, int32_t k, hipStream_t s, const double *xf = nullptr,
-                       double *gv = nullptr) {
+                       const double *b, double *x, int32_t k, hipStream_t s) {
     ThinArgs t{};
     t.rec = D.d_thin_rec;
-    t.lvl = reinterpret_cast<const int2 *>(D.d_thin_lvl);
+    t.lvl = reinterpret_cast<const int4 *>(D.d_thin_lvl);
+    t.rows = D.d_thin_rows;
     t.nlev = nlev;
     t.nlev_pad = D.thin_nlev_pad;
-    t.ring_rows = D.thin_R;
-    t.ring_levels = D.thin_RW;
     t.lg = D.thin_lg;
     t.k = k;
-    t.kt = k <= 1 ? 1 : 2;
-    t.n = (int32_t)((int64_t)D.thin_rec.size() / THIN_REC >> D.thin_lg); // plan positions
+    t.kt = 1;
+    t.ring = D.thin_ring;
+    t.n = (int32_t)D.thin_rows.size();
     t.block = D.thin_block;
     t.xs = D.d_thin_xs;
     t.helpers = std::max(0, std::min(sp.helpers, 8));
@@ -633,8 +659,6 @@ ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, 
     t.vals = vals;
     t.b = b;
     t.x = x;
-    t.xf = xf;
-    t.gv = gv;
     t.stream = D.d_thin_stream;
     t.progress = p->d_ctr + CTR_STRIDE + 16; // second counter line: error flag, then these
     t.sink = p->d_ctr + CTR_STRIDE + 17;
@@ -666,6 +690,8 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     if (batch && kind != DDF_SPTRSV_LOWER) return fail(DDF_E_KIND, "batches are lower-triangular solves");
     ddf_opts o;
     apply_opts(o, opts);
+    if (o.thin_ring != 0 && (o.thin_ring < 256 || o.thin_ring > THIN_RING_MAX || (o.thin_ring & (o.thin_ring - 1))))
+        return fail(DDF_E_ARG, "thin_ring must be 0 or a power of two in 256..16384");
     if (o.window < 1 || o.window > 1024) return fail(DDF_E_ARG, "window must be in 1..1024");
     for (int b = 0; b < nmat; b++) {
         if (ddf_status s = validate(kind, mats[b])) return s;
@@ -734,11 +760,12 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         }
     }
     if (kind == DDF_SPTRSV_LOWER && !batch) {
+        const int32_t ring = o.thin_ring > 0 ? o.thin_ring : THIN_RING_MAX;
         Pattern P{kind, mats[0].n_rows, mats[0].n_cols, mats[0].row_ptr, mats[0].col_idx};
-        build_thin(p->fwd[0], P, nullptr, p->F);
+        build_thin(p->fwd[0], P, nullptr, ring, p->F);
         if (p->has_adj) {
             Pattern PT{2, mats[0].n_cols, mats[0].n_rows, rpT[0].data(), ciT[0].data()};
-            build_thin(p->adj[0], PT, &perm[0], p->T);
+            build_thin(p->adj[0], PT, &perm[0], ring, p->T);
         }
     }
     p->sp_f.path = p->sp_a.path = o.solve_path;
@@ -1027,9 +1054,26 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
         return fail(DDF_E_ARG, "gvals overlaps another buffer");
     if (p->n_rows == 0) return DDF_OK;
     if (use_thin(p->T, p->sp_a, nrhs)) {
-        // single-block transposed solve with the value gradient fused
-        return thin_launch(p, p->T, p->sp_a, (int)p->adj[0].header[5], d_vals, d_gx, d_gb, nrhs, (hipStream_t)stream,
-                           d_x, d_gvals);
+        // single-block transposed solve, then the value gradient row by row over the forward
+        // plan's codelets (sequential in the value array)
+        hipStream_t s = (hipStream_t)stream;
+        if (ddf_status st = thin_launch(p, p->T, p->sp_a, (int)p->adj[0].header[5], d_vals, d_gx, d_gb, nrhs, s))
+            return st;
+        if (!d_gvals) return DDF_OK;
+        SpmvArgs a{};
+        a.tasks = p->T.d_tasks + p->n_solve_tasks_adj;
+        a.ntasks = (int32_t)((int64_t)p->T.tasks.size() - p->n_solve_tasks_adj);
+        a.k = nrhs;
+        a.remap = p->sp_a.remap;
+        a.cods2 = p->F.d_cods;
+        a.aux2 = p->F.d_aux;
+        a.g = d_gb;
+        a.x2 = d_x;
+        a.gv = d_gvals;
+        a.gv_sign = -1.0;
+        a.gv_diag = 1;
+        HIPCHK(launch_spmv(a, false, s));
+        return DDF_OK;
     }
     int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
     return solve_launch(p, p->T, 0, nt, p->T.n_counters, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
@@ -1316,10 +1360,10 @@ ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables
     o->thin_rec = D->thin_rec.data();
     o->thin_lvl = D->thin_lvl.data();
     o->n_thin_rec = (int64_t)D->thin_rec.size() / THIN_REC;
-    o->n_thin_lvl = (int64_t)D->thin_lvl.size() / 2;
+    o->n_thin_lvl = (int64_t)D->thin_lvl.size() / 4;
+    o->thin_rows = D->thin_rows.data();
     o->thin_lg = D->thin_lg;
-    o->thin_ring_rows = D->thin_R;
-    o->thin_ring_levels = D->thin_RW;
+    o->thin_ring_size = D->thin_ring;
     o->thin_ngs = D->thin_ngs;
     o->thin_block = D->thin_block;
     return DDF_OK;
@@ -1360,7 +1404,8 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         break;
     case DDF_OP_SPTRSV_ADJ:
         if (p->has_adj && !p->batch && use_thin(p->T, p->sp_a, nrhs))
-            ba = 16 * nnz + p->T.thin_bytes() + 24 * vk;
+            ba = 16 * nnz + p->T.thin_bytes() + Fca +
+                 (int64_t)(p->T.tasks.size() - p->n_solve_tasks_adj) * (int64_t)sizeof(Task) + 24 * vk;
         else
             ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 32 * vk;
         bc = 20 * nnz + 4 * (n + 1) + 24 * vk;

@@ -45,7 +45,7 @@ class ddf_opts(C.Structure):
                 ("threads", C.c_int32), ("ops_per_lane", C.c_int32), ("rows_passes", C.c_int32),
                 ("xcd_remap", C.c_int32), ("solve_blocks", C.c_int32),
                 ("solve_path", C.c_int32), ("thin_helpers", C.c_int32), ("thin_ahead", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("thin_ring", C.c_int32)]
 
 
 class ddf_csr_host(C.Structure):
@@ -64,9 +64,10 @@ class ddf_device_tables_t(C.Structure):
     _fields_ = [("cods", C.POINTER(C.c_int32)), ("aux", C.POINTER(C.c_int32)), ("tasks", C.POINTER(C.c_int32)),
                 ("sync", C.POINTER(C.c_int32)), ("tasksN", C.POINTER(C.c_int32)), ("n_cods", C.c_int64),
                 ("aux_len", C.c_int64), ("n_tasks", C.c_int64), ("n_counters", C.c_int64), ("n_tasksN", C.c_int64),
-                ("thin_rec", C.POINTER(C.c_int32)), ("thin_lvl", C.POINTER(C.c_int32)), ("n_thin_rec", C.c_int64),
-                ("n_thin_lvl", C.c_int64), ("thin_lg", C.c_int32), ("thin_ring_rows", C.c_int32),
-                ("thin_ring_levels", C.c_int32), ("thin_ngs", C.c_int32), ("thin_block", C.c_int32),
+                ("thin_rec", C.POINTER(C.c_int32)), ("thin_lvl", C.POINTER(C.c_int32)),
+                ("thin_rows", C.POINTER(C.c_int32)), ("n_thin_rec", C.c_int64),
+                ("n_thin_lvl", C.c_int64), ("thin_lg", C.c_int32), ("thin_ring_size", C.c_int32),
+                ("thin_reserved", C.c_int32), ("thin_ngs", C.c_int32), ("thin_block", C.c_int32),
                 ("reserved", C.c_int32)]
 
 
@@ -367,9 +368,9 @@ def ddf_plan_device_tables(plan, which=0) -> dict:
     sync = grab(t.sync, t.n_tasks, 4) if t.sync else np.zeros((0, 4), np.int32)
     return {"cods": grab(t.cods, t.n_cods, 16), "aux": grab(t.aux, t.aux_len), "tasks": grab(t.tasks, t.n_tasks, 4),
             "sync": sync, "n_counters": int(t.n_counters), "tasksN": grab(t.tasksN, t.n_tasksN, 4),
-            "thin_rec": grab(t.thin_rec, t.n_thin_rec, 20), "thin_lvl": grab(t.thin_lvl, t.n_thin_lvl, 2),
-            "thin_lg": int(t.thin_lg), "thin_ring_rows": int(t.thin_ring_rows),
-            "thin_ring_levels": int(t.thin_ring_levels), "thin_ngs": int(t.thin_ngs),
+            "thin_rec": grab(t.thin_rec, t.n_thin_rec, 20), "thin_lvl": grab(t.thin_lvl, t.n_thin_lvl, 4),
+            "thin_rows": grab(t.thin_rows, t.n_thin_lvl and ddf_plan_info(plan)["n_rows"], 1).ravel(),
+            "thin_lg": int(t.thin_lg), "thin_ring_size": int(t.thin_ring_size), "thin_ngs": int(t.thin_ngs),
             "thin_block": int(t.thin_block)}
 
 

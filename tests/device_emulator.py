@@ -231,47 +231,55 @@ THIN_UNUSED = -(1 << 31)
 
 
 def thin_solve(tabs, L, B, vals=None, Xf=None):
-    """Replays the single-block solve: level by level, G lanes per row, operands by their
-    codes.  Checks that every ring operand finds its row in the LDS ring (written by one of the
-    last ring_levels levels, not overwritten), that every global operand sits in one of the
-    first thin_ngs slots of its lane, names the plan position of its column and was solved at
-    least THIN_HORIZON levels before (so the gather two levels ahead sees it final), that
-    empty slots carry no op, and that every row is solved once.  With Xf (transposed solve),
-    also returns the value gradient of the follow-up pass: -<x[col], Xf[row]> at each op's
-    value index and -<x[row], Xf[row]> at the diagonal."""
+    """Replays the single-block solve: level by level, G lanes per row (2G for wide rows),
+    operands by their codes.  Checks that every ring operand finds its row in the LDS ring (its
+    slot, solve-order index mod ring size, not overwritten by a row solved up to and including
+    the reading level), that every global operand sits in one of the first thin_ngs slots of
+    its lane, names the solve-order index of its column and was solved at least
+    THIN_HORIZON levels before (so the gather two levels ahead sees it final), that empty slots
+    carry no op, and that every row is solved once.  With Xf (transposed solve), also returns
+    the value gradient of the follow-up pass: -<x[col], Xf[row]> at each op's value index and
+    -<x[row], Xf[row]> at the diagonal."""
     rec, lvl, lg = tabs["thin_rec"], tabs["thin_lvl"], tabs["thin_lg"]
-    R, RW, ngs = tabs["thin_ring_rows"], tabs["thin_ring_levels"], tabs["thin_ngs"]
+    M, ngs, rows_of = tabs["thin_ring_size"], tabs["thin_ngs"], tabs["thin_rows"]
     S = 5  # op slots per lane
-    assert RW >= 4 and RW & (RW - 1) == 0 and ngs in (0, 1, 2, 3, 5)
-    assert lvl.shape[0] % 4 == 0 and (lvl[-4:, 1] == 0).all()
+    assert M > 0 and M & (M - 1) == 0 and ngs in (0, 1, 2, 3, 5)
+    assert lvl.shape[0] % 4 == 0 and lvl.shape[1] == 4 and (lvl[-4:, 1] == 0).all()
     assert rec.shape[0] % 64 == 0 and tabs["thin_block"] >= lvl[:, 1].max()
+    assert B.shape[1] == 1 and sorted(rows_of.tolist()) == list(range(B.shape[0]))
     v = L.values if vals is None else vals
     n, k = B.shape
     G = 1 << lg
-    plan_rows = rec[::G, 0]
     X = np.full((n, k), np.nan)
     gv = np.full(v.shape[0], np.nan) if Xf is not None else None
     level_of = np.full(n, -1)
     ring = {}
-    for l, (first, lanes) in enumerate(lvl):
+    so_next = 0
+    for l, (first, lanes, so0, nw) in enumerate(lvl):
         if lanes == 0:
             continue
-        assert 0 < lanes <= 1024 and lanes % G == 0 and first % 64 == 0 and lanes // G <= R
+        assert 0 < lanes <= 1024 and lanes % G == 0 and first % 64 == 0 and so0 == so_next
         nxt = first + (lanes + 63) // 64 * 64
         assert (rec[first:first + lanes, 3] == 0).all() and (rec[first + lanes:nxt, 3] == 1).all()
         assert (rec[first + lanes:nxt, 4 + 2 * S:4 + 3 * S] == THIN_UNUSED).all()
         acc, diag, dpos, slot = {}, {}, {}, {}
+        reads = {}
+        rank = 0
         for s in range(lanes):
             r = rec[first + s]
             row, dp, cnt, wide = int(r[0]), int(r[1]), int(r[2]), int(r[19])
             assert wide in (0, 1, 2)
             if s % G == 0 and wide != 2:
-                # head of a row of G lanes (wide = 0) or of 2G lanes (wide = 1, 2G-aligned)
+                # head of a row of G lanes (wide = 0) or of 2G lanes (wide = 1, 2G-aligned; all
+                # wide rows of a level come first)
                 assert row not in acc and (wide == 0 or s % (2 * G) == 0)
+                assert (wide == 1) == (rank < nw)
+                so = so0 + rank
+                assert rows_of[so] == row
+                rank += 1
                 acc[row] = np.zeros(k)
                 diag[row], dpos[row] = v[dp], dp
-                slot[row] = (l % RW) * R + s // G
-                assert plan_rows[(first + s) // G] == row
+                slot[row] = so % M
             else:
                 assert row in acc
                 prev = rec[first + s - (s % G if wide != 2 or s % G else G)]
@@ -284,18 +292,22 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
                 m = level_of[col]
                 assert 0 <= m < l, f"row {row} reads x[{col}] not solved in an earlier level"
                 if code >= 0:
-                    assert j < ngs and plan_rows[code] == col and m <= l - 3
+                    assert j < ngs and rows_of[code] == col and m <= l - 3
                 else:
-                    assert ring.get(-code - 1) == (col, m) and m > l - RW
+                    assert ring.get(-code - 1) == col
+                    reads[-code - 1] = col
                 acc[row] += v[vi] * X[col]
                 if gv is not None:
                     assert np.isnan(gv[vi])
                     gv[vi] = -np.dot(X[col], Xf[row])
+        so_next = so0 + rank
+        # waves of one level may write before others read: no slot read here is written here
+        assert not (set(slot.values()) & set(reads)), "a ring slot is read and overwritten in one level"
         for row, a in acc.items():
             assert level_of[row] == -1
             X[row] = (B[row] - a) / diag[row]
             level_of[row] = l
-            ring[slot[row]] = (row, l)
+            ring[slot[row]] = row
             if gv is not None:
                 gv[dpos[row]] = -np.dot(X[row], Xf[row])
     assert (level_of >= 0).all()

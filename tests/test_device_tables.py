@@ -44,8 +44,9 @@ def replay_solve(L, k=2, seed=0, **kw):
     T = ddf.ddf_plan_device_tables(p, 1)
     U, perm = O.transpose(L)
     if F["thin_rec"].shape[0]:
-        check_solve(L, B, E.thin_solve(F, L, B), ref)
+        check_solve(L, B[:, :1], E.thin_solve(F, L, B[:, :1]), ref[:, :1])
     if T["thin_rec"].shape[0]:
+        G, ref = G[:, :1], ref[:, :1]
         lam_t, gv_t = E.thin_solve(T, U, G, vals=L.values, Xf=ref)
         GBt, GVt = O.sptrsv_adj(L, ref, G)
         check_solve(L, G, lam_t, GBt, transposed=True)
@@ -144,3 +145,18 @@ def test_thin_records_workloads():
     # a level wider than one pass is not eligible
     L = I.tril(I.laplacian(1200, 1200, 1, I.OFFS_5PT, 4.0))
     assert ddf.ddf_plan_device_tables(hplan(1, L, build_adjoint=0), 0)["thin_rec"].shape[0] == 0
+
+
+def test_thin_small_ring_global_operands():
+    # a 256-row ring forces most operands through the global gather path
+    w = I.c2_stencil27_offband(nx=16)
+    p = hplan(1, w.L, thin_ring=256)
+    F, T = ddf.ddf_plan_device_tables(p, 0), ddf.ddf_plan_device_tables(p, 1)
+    for D in (F, T):
+        assert D["thin_ring_size"] == 256 and D["thin_rec"].shape[0]
+        codes = D["thin_rec"][:, 14:19]
+        assert (codes >= 0).any() and (codes[codes != E.THIN_UNUSED] < 0).any() and D["thin_ngs"] >= 1
+    replay_solve(w.L, k=1, thin_ring=256)
+    with pytest.raises(ddf.DDFError):
+        hplan(1, w.L, thin_ring=300)
+

@@ -179,6 +179,8 @@ def test_c2_scaled():
     w = I.c2_stencil27_offband(nx=30)
     spmv_case(w.A, 1)
     sptrsv_case(w.L, 1)
+    # small LDS ring: most operands of the single-block solve come through the global gathers
+    sptrsv_case(w.L, 1, opts=ddf.ddf_opts_default(thin_ring=256))
 
 
 def test_c3_scaled():
