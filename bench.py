@@ -229,8 +229,9 @@ def main():
     info_A = ddf.ddf_plan_info(pA)
     kernel_of = {"spmv": "k_spmv1" if k == 1 else "k_spmvN", "spmv_adj": "k_spmv1" if k == 1 else "k_spmvN"}
     if pL is not None:
-        kernel_of["sptrsv"] = "k_solve_thin" if info_L["solve_path"] == 2 else "k_solve"
-        kernel_of["sptrsv_adj"] = "k_solve_thin" if info_L["solve_path_adj"] == 2 else "k_solve"
+        names = {1: "k_solve", 2: "k_solve_thin", 3: "k_solve_range"}
+        kernel_of["sptrsv"] = names[info_L["solve_path"]]
+        kernel_of["sptrsv_adj"] = names[info_L["solve_path_adj"]]
     dom = max(per_op, key=lambda n: per_op[n]["ms"])
     kname = kernel_of[dom]
     ach = traffic[dom][0] / (per_op[dom]["ms"] / 1e3) / 1e9

@@ -73,7 +73,7 @@ typedef struct {
                               0 = every block the device keeps resident                     */
     int32_t solve_path;    /* solve kernel: 0 auto (single-block when every level fits one
                               1024-lane pass, else multi-block), 1 multi-block, 2 single-block
-                              when possible                                                */
+                              when possible, 3 one launch per level of the multi-block tasks */
     int32_t thin_helpers;  /* single-block solve: helper blocks that pull the next levels'
                               tables into the solver's L2; -1 default (2), 0 none, max 8  */
     int32_t thin_ahead;    /* single-block solve: levels the helpers run ahead; 0 default
@@ -130,7 +130,8 @@ typedef struct {
     double inspect_seconds;     /* wall time of the host inspector                   */
     uint64_t hash;              /* FNV-1a over the canonical tables                  */
     int32_t ops_per_lane, rows_passes, xcd_remap;
-    int32_t solve_path;         /* kernel the solve uses: 1 multi-block, 2 single-block  */
+    int32_t solve_path;         /* kernel the solve uses: 1 multi-block, 2 single-block,
+                                   3 one launch per level                                */
     int32_t solve_path_adj;     /* same for the adjoint solve (0 for SpMV plans)          */
     int32_t reserved;
 } ddf_plan_info_t;

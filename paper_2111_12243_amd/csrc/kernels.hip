@@ -203,7 +203,8 @@ __device__ __forceinline__ void spmv_stream_body(const SpmvArgs &a, const DCod &
             col[j] = c.col0 + i0 * c.sigma0 + a.aux[c.xt_off + i1];
         else
             col[j] = a.aux[c.xt_off + a0 * nn + e];
-        v[j] = val_at<VPERM>(a, ebase + e);
+        // a wave reads whole lines of values exactly once: non-temporal loads leave the L2 to x
+        v[j] = VPERM ? val_at<VPERM>(a, ebase + e) : __builtin_nontemporal_load(a.vals + ebase + e);
     }
     double xv[SJ];
 #pragma unroll
@@ -314,6 +315,62 @@ __device__ __forceinline__ void spmvN_rect(const SpmvArgs &a, const DCod &c, con
     }
 }
 
+// Rectangular codelet, RV consecutive right-hand sides per lane (vector loads of x and y),
+// KR lanes per row.
+template <int KR, int RV, int MODE, bool VPERM>
+__device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, const Task &tk, int lane) {
+    static_assert(RV == 2 || RV == 4, "vector width");
+    constexpr int P = WAVE / KR;
+    const int slot = lane / KR, r = (lane % KR) * RV;
+    const int k = a.k, nn = c.nn;
+    for (int base = tk.i0b; base < tk.i0e; base += P) {
+        const int i0 = min(base + slot, tk.i0e - 1);
+        const bool active = base + slot < tk.i0e;
+        const int row = row_of(c, a.aux, i0);
+        const int opst = c.op0 + i0 * c.op_step;
+        const int cbase = (MODE == XM_FULL) ? c.xt_off + i0 * nn : c.col0 + i0 * c.sigma0;
+        double acc[RV];
+#pragma unroll
+        for (int q = 0; q < RV; q++) acc[q] = 0.0;
+        for (int i1 = 0; i1 < nn; i1 += RU) {
+            int col[RU];
+            double v[RU];
+            double2 xv[RU][RV / 2];
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                const int j = min(i1 + u, nn - 1);
+                if constexpr (MODE == XM_STRIDED)
+                    col[u] = cbase + j * c.sigma1;
+                else if constexpr (MODE == XM_SHARED)
+                    col[u] = cbase + a.aux[c.xt_off + j];
+                else
+                    col[u] = a.aux[cbase + j];
+                v[u] = val_at<VPERM>(a, opst + j);
+            }
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                const double2 *xp = reinterpret_cast<const double2 *>(a.x + (int64_t)col[u] * k + r);
+#pragma unroll
+                for (int h = 0; h < RV / 2; h++) xv[u][h] = xp[h];
+            }
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+                if (i1 + u < nn) {
+#pragma unroll
+                    for (int h = 0; h < RV / 2; h++) {
+                        acc[2 * h] += v[u] * xv[u][h].x;
+                        acc[2 * h + 1] += v[u] * xv[u][h].y;
+                    }
+                }
+        }
+        if (active) {
+            double2 *yp = reinterpret_cast<double2 *>(a.y + (int64_t)row * k + r);
+#pragma unroll
+            for (int h = 0; h < RV / 2; h++) yp[h] = make_double2(acc[2 * h], acc[2 * h + 1]);
+        }
+    }
+}
+
 template <int KR, bool VPERM>
 __device__ __forceinline__ void spmvN_walk(const SpmvArgs &a, const DCod &c, const Task &tk, int lane) {
     constexpr int P = WAVE / KR;
@@ -335,7 +392,9 @@ __device__ __forceinline__ void spmvN_walk(const SpmvArgs &a, const DCod &c, con
     }
 }
 
-template <int KR, bool VPERM>
+// KR lanes per row; RV > 1: rectangular codelets take RV right-hand sides per lane (k is
+// KR * RV), others one per lane over KW lanes per row
+template <int KR, int RV, int KW, bool VPERM>
 __global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
@@ -348,14 +407,25 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
     const DCod c = load_cod(a.cods + tk.cod);
     const int mode = xmode(c.flags);
     const bool rect = (c.flags & FRECT) && !(c.flags & DOPS) && c.nn > 0;
-    if (rect && mode == XM_STRIDED)
-        spmvN_rect<KR, XM_STRIDED, VPERM>(a, c, tk, lane);
-    else if (rect && mode == XM_SHARED)
-        spmvN_rect<KR, XM_SHARED, VPERM>(a, c, tk, lane);
-    else if (rect && mode == XM_FULL)
-        spmvN_rect<KR, XM_FULL, VPERM>(a, c, tk, lane);
-    else
-        spmvN_walk<KR, VPERM>(a, c, tk, lane);
+    if constexpr (RV > 1) {
+        if (rect && mode == XM_STRIDED)
+            spmvN_rect_v<KR, RV, XM_STRIDED, VPERM>(a, c, tk, lane);
+        else if (rect && mode == XM_SHARED)
+            spmvN_rect_v<KR, RV, XM_SHARED, VPERM>(a, c, tk, lane);
+        else if (rect && mode == XM_FULL)
+            spmvN_rect_v<KR, RV, XM_FULL, VPERM>(a, c, tk, lane);
+        else
+            spmvN_walk<KW, VPERM>(a, c, tk, lane);
+    } else {
+        if (rect && mode == XM_STRIDED)
+            spmvN_rect<KR, XM_STRIDED, VPERM>(a, c, tk, lane);
+        else if (rect && mode == XM_SHARED)
+            spmvN_rect<KR, XM_SHARED, VPERM>(a, c, tk, lane);
+        else if (rect && mode == XM_FULL)
+            spmvN_rect<KR, XM_FULL, VPERM>(a, c, tk, lane);
+        else
+            spmvN_walk<KR, VPERM>(a, c, tk, lane);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1045,9 +1115,23 @@ hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s) {
         else hipLaunchKernelGGL(k_spmv1<false>, grid, block, 0, s, a);
         return hipGetLastError();
     }
+    // vector right-hand sides when k allows and x, y are 16-byte aligned
+    const bool al = ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.y)) & 15) == 0;
+#define DDF_SPMVNV(KR, RV, KW)                                                                      \
+    {                                                                                               \
+        if (vperm) hipLaunchKernelGGL((k_spmvN<KR, RV, KW, true>), grid, block, 0, s, a);         \
+        else hipLaunchKernelGGL((k_spmvN<KR, RV, KW, false>), grid, block, 0, s, a);               \
+        return hipGetLastError();                                                                   \
+    }
+    if (al && a.k == 2) DDF_SPMVNV(1, 2, 2)
+    if (al && a.k == 4) DDF_SPMVNV(1, 4, 4)
+    if (al && a.k == 8) DDF_SPMVNV(2, 4, 8)
+    if (al && a.k == 16) DDF_SPMVNV(4, 4, 16)
+    if (al && a.k == 32) DDF_SPMVNV(8, 4, 32)
+#undef DDF_SPMVNV
 #define DDF_SPMVN(KR)                                                                               \
-    if (vperm) hipLaunchKernelGGL((k_spmvN<KR, true>), grid, block, 0, s, a);                      \
-    else hipLaunchKernelGGL((k_spmvN<KR, false>), grid, block, 0, s, a);                            \
+    if (vperm) hipLaunchKernelGGL((k_spmvN<KR, 1, KR, true>), grid, block, 0, s, a);             \
+    else hipLaunchKernelGGL((k_spmvN<KR, 1, KR, false>), grid, block, 0, s, a);                   \
     break;
     switch (kr_for(a.k)) {
     case 2: DDF_SPMVN(2)
@@ -1115,6 +1199,32 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
 }
 
 int num_cu() { return g_num_cu > 0 ? g_num_cu : 256; }
+
+// One level's tasks per launch (the launch boundaries order the levels): plain loads and
+// stores, no tickets, no waits.
+template <int KT, bool ADJ>
+__global__ __launch_bounds__(WAVE *WPB) void k_solve_range(SolveArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    const int t = xcd_block(blockIdx.x, gridDim.x, 1) * WPB + threadIdx.x / WAVE;
+    if (t >= a.ntasks) return;
+    solve_task<KT, ADJ, false>(a, t, lane);
+}
+
+hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t s) {
+    if (a.ntasks == 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.ntasks + WPB - 1) / WPB)), block(WAVE * WPB);
+    switch (kt * 2 + (adj ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_solve_range<1, false>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_solve_range<1, true>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_solve_range<2, false>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_solve_range<2, true>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_solve_range<4, false>), grid, block, 0, s, a); break;
+    case 9: hipLaunchKernelGGL((k_solve_range<4, true>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_solve_range<8, false>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_solve_range<8, true>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s) {
     if (a.ntasks == 0) return hipSuccess;

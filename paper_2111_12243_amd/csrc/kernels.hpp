@@ -125,6 +125,7 @@ hipError_t init_device_info();
 hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s);
 int kr_for(int k);
 hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s);
+hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t s);
 int num_cu();
 hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s);

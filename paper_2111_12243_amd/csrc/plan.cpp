@@ -635,7 +635,7 @@ ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
 
 // the single-block kernel takes up to THIN_KT_MAX right-hand sides
 bool use_thin(const DevTables &D, const SchedParams &sp, int32_t k) {
-    return !D.thin_rec.empty() && sp.path != 1 && k <= THIN_KT_MAX;
+    return !D.thin_rec.empty() && (sp.path == 0 || sp.path == 2) && k <= THIN_KT_MAX;
 }
 
 ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, int nlev, const double *vals,
@@ -870,6 +870,23 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.ctr = p->d_ctr;
     a.spin_limit = p->spin_limit;
     a.k_override = k_override;
+    if (sp.path == 3) {
+        // one launch per level (task ranges of equal signal counter; the GV tasks last)
+        const Task *tk = a.tasks;
+        const int4 *sy = a.sync;
+        int64_t i = 0;
+        while (i < ntasks) {
+            const int32_t ctr = D.sync[(t0 + i) * 4 + 2];
+            int64_t j = i + 1;
+            while (j < ntasks && D.sync[(t0 + j) * 4 + 2] == ctr) j++;
+            a.tasks = tk + i;
+            a.sync = sy + i;
+            a.ntasks = (int32_t)(j - i);
+            HIPCHK(launch_solve_range(a, adj, kt, s));
+            i = j;
+        }
+        return DDF_OK;
+    }
     HIPCHK(launch_reset(p->d_ctr, (2 + ncounters) * CTR_STRIDE, s));
     HIPCHK(launch_solve(a, adj, kt, sp.blocks, s));
     return DDF_OK;
@@ -1319,8 +1336,8 @@ ddf_status ddf_plan_info(ddf_plan_t p, ddf_plan_info_t *o) {
     o->rows_passes = p->sp_f.passes;
     o->xcd_remap = p->sp_f.remap;
     if (p->kind != 0) {
-        o->solve_path = use_thin(p->F, p->sp_f, 1) ? 2 : 1;
-        o->solve_path_adj = p->has_adj ? (use_thin(p->T, p->sp_a, 1) ? 2 : 1) : 0;
+        o->solve_path = use_thin(p->F, p->sp_f, 1) ? 2 : p->sp_f.path == 3 ? 3 : 1;
+        o->solve_path_adj = p->has_adj ? (use_thin(p->T, p->sp_a, 1) ? 2 : p->sp_a.path == 3 ? 3 : 1) : 0;
     }
     return DDF_OK;
 }
@@ -1568,6 +1585,9 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
         if (!D.thin_rec.empty() && nrhs <= THIN_KT_MAX)
             for (int hp : {2, 0, 4, 1})
                 for (int ah : {32, 96}) cands.push_back({target.ops_per_lane, target.passes, target.remap, 0, 2, hp, ah});
+        if (!p->batch)
+            for (int opl : {4, 8})
+                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, 0, 3, target.helpers, target.ahead});
         const int full = 4 * num_cu(); // up to four 256-thread blocks per CU
         for (int blocks : {full, full / 4, full / 16})
             for (int opl : {4, 2, 8})

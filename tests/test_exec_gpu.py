@@ -66,7 +66,7 @@ def spmv_case(A, k, seed=0, opts=None, plain=True):
 
 
 def sptrsv_case(L, k, seed=0, opts=None, plain=True, inplace=False):
-    for path in (1, 2):  # multi-block persistent kernel; single-block kernel where eligible
+    for path in (1, 2, 3):  # multi-block persistent; single-block where eligible; a launch per level
         o = opts if opts is not None else ddf.ddf_opts_default()
         o.solve_path = path
         sptrsv_case_path(L, k, seed, o, plain and path == 1, inplace)
