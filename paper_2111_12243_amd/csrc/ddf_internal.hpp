@@ -86,6 +86,10 @@ struct DevTables {
     std::vector<Task> tasksN;          // SpMV with several right-hand sides
     std::vector<int32_t> sync;         // solve: 4 int32 per task (wait counter, count, signal counter)
     int64_t n_counters = 0;            // solve: level counters the schedule uses
+    int64_t csr_rows = 0, csr_nnz = 0; // SpMV, one right-hand side: rows run from the CSR pattern
+    int64_t table_bytes1 = 0;          // plan bytes a one-RHS SpMV launch reads
+    std::vector<int32_t> cod_aux;      // aux words of each codelet
+    std::vector<uint8_t> csr_cod;      // SpMV, one right-hand side: codelet run from the CSR pattern
     std::vector<int32_t> thin_rec;     // single-block solve records (empty if not eligible)
     std::vector<int32_t> thin_lvl;     // per level: first record, lanes, first solve index, wide rows
     std::vector<int32_t> thin_rows;    // row of each solve-order index

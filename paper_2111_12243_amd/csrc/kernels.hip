@@ -257,6 +257,68 @@ __device__ void spmv_group_task(const SpmvArgs &a, const Task &tk, int lane) {
     }
 }
 
+// Rows [r0, r1) of the CSR pattern, one right-hand side: elements streamed like a stream task
+// (products into LDS, then one lane per row sums), or one long row in chunks with a wave sum.
+template <bool VPERM>
+__device__ void spmv_csr_task(const SpmvArgs &a, const Task &tk, int lane, double *__restrict__ lds) {
+    const int r0 = tk.i0b, r1 = tk.i0e;
+    const int e0 = a.rp[r0], e1 = a.rp[r1];
+    if (tk.meta & TASK_LONG) {
+        double acc = 0.0;
+        for (int base = e0; base < e1; base += WAVE * SJ) {
+            int col[SJ];
+            double v[SJ];
+#pragma unroll
+            for (int j = 0; j < SJ; j++) {
+                const int e = min(base + lane + WAVE * j, e1 - 1);
+                col[j] = a.ci[e];
+                v[j] = VPERM ? a.vals[a.perm[e]] : __builtin_nontemporal_load(a.vals + e);
+            }
+            double xv[SJ];
+#pragma unroll
+            for (int j = 0; j < SJ; j++) xv[j] = a.x[col[j]];
+#pragma unroll
+            for (int j = 0; j < SJ; j++)
+                if (base + lane + WAVE * j < e1) acc += v[j] * xv[j];
+        }
+        double t[1] = {acc};
+        group_sum<1>(t, WAVE);
+        if (lane == 0) a.y[r0] = t[0];
+        return;
+    }
+    const int E = e1 - e0, nrow = r1 - r0;
+    if (E == 0) {
+        if (lane < nrow) a.y[r0 + lane] = 0.0;
+        return;
+    }
+    int col[SJ];
+    double v[SJ];
+#pragma unroll
+    for (int j = 0; j < SJ; j++) {
+        const int e = e0 + min(lane + WAVE * j, E - 1);
+        col[j] = a.ci[e];
+        v[j] = VPERM ? a.vals[a.perm[e]] : __builtin_nontemporal_load(a.vals + e);
+    }
+    double xv[SJ];
+#pragma unroll
+    for (int j = 0; j < SJ; j++) xv[j] = a.x[col[j]];
+#pragma unroll
+    for (int j = 0; j < SJ; j++)
+        if (lane + WAVE * j < E) lds[lane + WAVE * j] = v[j] * xv[j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < nrow) {
+        const int b0 = a.rp[r0 + lane] - e0, b1 = a.rp[r0 + lane + 1] - e0;
+        double sum = 0.0;
+        for (int q = b0; q < b1; q++) sum += lds[q];
+        a.y[r0 + lane] = sum;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // one right-hand side: stream and lanes-per-row tasks (and phase-1 GV tasks)
 template <bool VPERM>
 __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
@@ -267,6 +329,8 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
     const Task tk = a.tasks[t];
     if ((tk.meta >> 8) & 1)
         spmv_gv_task(a, tk, lane);
+    else if (tk.meta & TASK_CSR)
+        spmv_csr_task<VPERM>(a, tk, lane, lds_all[wave]);
     else if (tk.meta & TASK_STREAM)
         spmv_stream_task<VPERM>(a, tk, lane, lds_all[wave]);
     else

@@ -16,6 +16,7 @@ struct SpmvArgs {
     int32_t remap; // XCD-contiguous block order
     const double *vals;
     const int32_t *perm; // values through perm (transposed plan)
+    const int32_t *rp, *ci; // CSR pattern of the pass (TASK_CSR tasks)
     const double *x;
     double *y;
     // phase-1 tasks of a fused adjoint launch: gv[e] = sum_r g[row, r] x2[col, r]
@@ -80,7 +81,9 @@ struct ThinArgs {
 constexpr int LOOKAHEAD = 4;   // elements per lane a solve task loads before its wait
 constexpr int CTR_STRIDE = 32; // uint32 per counter line (128 bytes)
 enum : int32_t { TASK_FAST = 1 << 9,     // solve: thin-range task whose rows fit the look-ahead registers
-                 TASK_STREAM = 1 << 10 }; // SpMV: one-RHS task streamed element by element
+                 TASK_STREAM = 1 << 10,   // SpMV: one-RHS task streamed element by element
+                 TASK_CSR = 1 << 11,      // SpMV, one RHS: rows [i0b, i0e) of the CSR pattern
+                 TASK_LONG = 1 << 12 };   // with TASK_CSR: one row longer than a stream task
 constexpr int STREAM_ELEMS = 64 * 8;     // elements of a stream task (64 lanes x 8)
 
 struct SolveArgs {

@@ -37,6 +37,7 @@ struct ddf_plan_s {
     std::vector<Canon> fwd, adj;
     std::vector<MatInfo> mats;
     std::vector<int32_t> hrp, hci; // single-matrix host pattern (plain comparators)
+    std::vector<int32_t> hrpT;     // row pointers of the transposed pattern (single matrix)
     int64_t n_rows = 0, n_cols = 0, nnz = 0, vec_total = 0;
     SchedParams sp_f, sp_a;
     DevTables F, T, Fpm;
@@ -120,10 +121,12 @@ void pack(const Canon &c, const Pattern &P, int mat, DevTables &D) {
     const size_t first = D.cods.size();
     D.cods.resize(first + ncod);
     std::vector<int64_t> rows, opst, nops;
+    D.cod_aux.resize(first + ncod);
     for (int64_t i = 0; i < ncod; i++) {
         const int64_t *r = &c.codelets[i * NCOD];
         const int32_t fl = (int32_t)r[C_FLAGS];
         const int32_t m = (int32_t)r[C_M];
+        const size_t aux0 = D.aux.size();
         DCod d;
         d.m = m;
         d.nn = (int32_t)r[C_NN];
@@ -221,6 +224,7 @@ void pack(const Canon &c, const Pattern &P, int mat, DevTables &D) {
         }
         d.flags = dfl;
         D.cods[first + i] = d;
+        D.cod_aux[first + i] = (int32_t)(D.aux.size() - aux0);
     }
 }
 
@@ -275,6 +279,92 @@ void spmv1_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_ind
     }
     const int32_t rows = STREAM_ELEMS / d.nn;
     for (int32_t a = 0; a < d.m; a += rows) out.push_back({cod_index, a, std::min(d.m, a + rows), TASK_STREAM});
+}
+
+// Ops of a device codelet.
+int64_t cod_ops(const DCod &d, const std::vector<int32_t> &aux) {
+    if (d.flags & FRECT) return (int64_t)d.m * d.nn;
+    int64_t s = 0;
+    for (int32_t a = 0; a < d.m; a++) s += aux[d.cnt_off + a];
+    return s;
+}
+
+// Rows of a device codelet.
+void cod_rows(const DCod &d, const std::vector<int32_t> &aux, std::vector<int32_t> &out) {
+    for (int32_t a = 0; a < d.m; a++) out.push_back((d.flags & FS0) ? d.row0 + a * d.row_step : aux[d.rows_off + a]);
+}
+
+// Codelets with fewer ops than this run as packed row ranges of the CSR pattern (one wave per
+// up to STREAM_ELEMS elements or 64 rows; a longer row gets a wave of its own).
+constexpr int64_t TINY_OPS = 128;
+
+// Splits a plan pass between codelet tasks and CSR row ranges: a codelet with fewer than
+// TINY_OPS ops runs from the CSR pattern when all its rows lie in runs of at least CSR_RUN
+// consecutive such rows (scattered small codelets keep their own tasks).
+constexpr int64_t CSR_RUN = 16;
+
+void split_tiny(const DevTables &D, int64_t n_rows, std::vector<uint8_t> &csr_cod, std::vector<int32_t> &rows) {
+    std::vector<uint8_t> tiny_row(n_rows, 0);
+    std::vector<int32_t> tmp;
+    csr_cod.assign(D.cods.size(), 0);
+    for (size_t c = 0; c < D.cods.size(); c++)
+        if (cod_ops(D.cods[c], D.aux) < TINY_OPS) {
+            tmp.clear();
+            cod_rows(D.cods[c], D.aux, tmp);
+            for (int32_t r : tmp) tiny_row[r] = 1;
+        }
+    // length of the run of tiny rows through each row
+    std::vector<int32_t> run(n_rows, 0);
+    for (int64_t r = 0; r < n_rows;) {
+        if (!tiny_row[r]) {
+            r++;
+            continue;
+        }
+        int64_t e = r;
+        while (e < n_rows && tiny_row[e]) e++;
+        for (int64_t q = r; q < e; q++) run[q] = (int32_t)std::min<int64_t>(e - r, INT32_MAX);
+        r = e;
+    }
+    rows.clear();
+    for (size_t c = 0; c < D.cods.size(); c++) {
+        if (cod_ops(D.cods[c], D.aux) >= TINY_OPS) continue;
+        tmp.clear();
+        cod_rows(D.cods[c], D.aux, tmp);
+        bool ok = true;
+        for (int32_t r : tmp) ok = ok && run[r] >= CSR_RUN;
+        if (!ok) continue;
+        csr_cod[c] = 1;
+        rows.insert(rows.end(), tmp.begin(), tmp.end());
+    }
+}
+
+void csr_tasks(std::vector<int32_t> &rows, const std::vector<int32_t> &rp, std::vector<Task> &out) {
+    std::sort(rows.begin(), rows.end());
+    size_t i = 0;
+    while (i < rows.size()) {
+        const int32_t r0 = rows[i];
+        const int64_t len0 = rp[r0 + 1] - rp[r0];
+        if (len0 > STREAM_ELEMS) {
+            out.push_back({-1, r0, r0 + 1, TASK_CSR | TASK_LONG});
+            i++;
+            continue;
+        }
+        size_t j = i + 1;
+        while (j < rows.size() && rows[j] == rows[j - 1] + 1 && j - i < 64 &&
+               (int64_t)rp[rows[j] + 1] - rp[r0] <= STREAM_ELEMS)
+            j++;
+        out.push_back({-1, r0, rows[j - 1] + 1, TASK_CSR});
+        i = j;
+    }
+}
+
+// Plan bytes a one-RHS SpMV launch reads: records and aux of the codelets it runs as codelets,
+// its task list, and the CSR columns and row pointers of the rows it runs from the pattern.
+int64_t spmv1_table_bytes(const DevTables &D) {
+    int64_t b = (int64_t)D.tasks.size() * sizeof(Task) + 4 * D.csr_nnz + 8 * D.csr_rows;
+    for (size_t c = 0; c < D.cods.size(); c++)
+        if (!D.csr_cod[c]) b += (int64_t)sizeof(DCod) + 4 * (int64_t)D.cod_aux[c];
+    return b;
 }
 
 // SpMV tasks for several right-hand sides: fixed row blocks (right-hand sides across lanes).
@@ -551,19 +641,37 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
         if (fwd) {
             p->F.tasks.clear();
             p->F.tasksN.clear();
+            std::vector<int32_t> tiny;
+            std::vector<uint8_t> csr_cod;
+            split_tiny(p->F, p->n_rows, csr_cod, tiny);
             for (size_t c = 0; c < p->F.cods.size(); c++) {
-                spmv1_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_f, p->F.tasks);
+                if (!csr_cod[c]) spmv1_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_f, p->F.tasks);
                 spmvN_tasks(p->F.cods[c], (int32_t)c, p->sp_f, p->F.tasksN);
             }
+            p->F.csr_cod = csr_cod;
+            p->F.csr_rows = (int64_t)tiny.size();
+            p->F.csr_nnz = 0;
+            for (int32_t r : tiny) p->F.csr_nnz += p->hrp[r + 1] - p->hrp[r];
+            csr_tasks(tiny, p->hrp, p->F.tasks);
+            p->F.table_bytes1 = spmv1_table_bytes(p->F);
             if (ddf_status s = upload_tasks(p, p->F)) return s;
         }
         if (adjp && p->has_adj) {
             p->T.tasks.clear();
             p->T.tasksN.clear();
+            std::vector<int32_t> tiny;
+            std::vector<uint8_t> csr_cod;
+            split_tiny(p->T, p->n_cols, csr_cod, tiny);
             for (size_t c = 0; c < p->T.cods.size(); c++) {
-                spmv1_tasks(p->T.cods[c], p->T.aux, (int32_t)c, p->sp_a, p->T.tasks);
+                if (!csr_cod[c]) spmv1_tasks(p->T.cods[c], p->T.aux, (int32_t)c, p->sp_a, p->T.tasks);
                 spmvN_tasks(p->T.cods[c], (int32_t)c, p->sp_a, p->T.tasksN);
             }
+            p->T.csr_cod = csr_cod;
+            p->T.csr_rows = (int64_t)tiny.size();
+            p->T.csr_nnz = 0;
+            for (int32_t r : tiny) p->T.csr_nnz += p->hrpT[r + 1] - p->hrpT[r];
+            csr_tasks(tiny, p->hrpT, p->T.tasks);
+            p->T.table_bytes1 = spmv1_table_bytes(p->T);
             p->n_gx_tasks = (int64_t)p->T.tasks.size();
             p->n_gx_tasksN = (int64_t)p->T.tasksN.size();
             std::vector<Task> gvt;
@@ -743,6 +851,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     if (!batch) {
         p->hrp.assign(mats[0].row_ptr, mats[0].row_ptr + mats[0].n_rows + 1);
         p->hci.assign(mats[0].col_idx, mats[0].col_idx + p->nnz);
+        if (p->has_adj) p->hrpT = rpT[0];
     }
     // device tables (built on the host for every plan; uploaded unless host_only)
     if (!p->host_only) {
@@ -815,14 +924,16 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         // CSR copies for the plain comparators
         if ((s = upload(p, &p->d_rp, p->hrp.data(), p->hrp.size()))) return fin(s);
         if ((s = upload(p, &p->d_ci, p->hci.data(), p->hci.size()))) return fin(s);
+        if (p->has_adj) {
+            if ((s = upload(p, &p->d_rpT, rpT[0].data(), rpT[0].size()))) return fin(s);
+            if ((s = upload(p, &p->d_ciT, ciT[0].data(), ciT[0].size()))) return fin(s);
+        }
         if (kind == DDF_SPTRSV_LOWER) {
             std::vector<int32_t> rows(p->fwd[0].part_rows.begin(), p->fwd[0].part_rows.end());
             if ((s = upload(p, &p->d_rows, rows.data(), rows.size()))) return fin(s);
             if (p->has_adj) {
                 std::vector<int32_t> rr(p->adj[0].part_rows.begin(), p->adj[0].part_rows.end());
                 if ((s = upload(p, &p->d_rrows, rr.data(), rr.size()))) return fin(s);
-                if ((s = upload(p, &p->d_rpT, rpT[0].data(), rpT[0].size()))) return fin(s);
-                if ((s = upload(p, &p->d_ciT, ciT[0].data(), ciT[0].size()))) return fin(s);
             }
         }
     }
@@ -972,6 +1083,8 @@ ddf_status ddf_spmv_v(ddf_plan_t p, const double *d_vals, const double *d_x, dou
     SpmvArgs a{};
     a.cods = p->F.d_cods;
     a.aux = p->F.d_aux;
+    a.rp = p->d_rp;
+    a.ci = p->d_ci;
     const bool many = nrhs > 1;
     a.tasks = many ? p->F.d_tasksN : p->F.d_tasks;
     a.ntasks = (int32_t)(many ? p->F.tasksN.size() : p->F.tasks.size());
@@ -1037,6 +1150,8 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
     SpmvArgs a{};
     a.cods = p->T.d_cods;
     a.aux = p->T.d_aux;
+    a.rp = p->d_rpT;
+    a.ci = p->d_ciT;
     a.tasks = (many ? p->T.d_tasksN : p->T.d_tasks) + t0;
     a.ntasks = (int32_t)(t1 - t0);
     a.k = nrhs;
@@ -1398,12 +1513,12 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
     int64_t ba = 0, bc = 0, fl = 0;
     switch (op) {
     case DDF_OP_SPMV:
-        ba = 8 * nnz + p->F.launch_bytes(many) + 8 * ck + 8 * vk;
+        ba = 8 * nnz + (many ? p->F.launch_bytes(true) : p->F.table_bytes1) + 8 * ck + 8 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 8 * ck + 8 * vk;
         fl = 2 * nnz * nrhs;
         break;
     case DDF_OP_SPMV_ADJ:
-        ba = 20 * nnz + (p->has_adj ? p->T.launch_bytes(many) : 0) + Fca + 16 * vk + 16 * ck;
+        ba = 20 * nnz + (p->has_adj ? (many ? p->T.launch_bytes(true) : p->T.table_bytes1) : 0) + Fca + 16 * vk + 16 * ck;
         bc = 20 * nnz + 4 * (n + 1) + 8 * vk + 16 * ck;
         fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
         break;

@@ -12,6 +12,9 @@ FS0, FS1, FS2, FSEP, FRECT, FRUNS = 1, 2, 4, 8, 16, 32
 DOPS, DCONTIG, DXPTR, DRPTR = 64, 128, 256, 512
 TASK_FAST = 1 << 9
 TASK_STREAM = 1 << 10
+TASK_CSR = 1 << 11
+TASK_LONG = 1 << 12
+STREAM_ELEMS = 512
 STREAM_ELEMS = 512
 LOOKAHEAD = 4
 F = {n: i for i, n in enumerate(["flags", "m", "nn", "row0", "row_step", "op0", "op_step", "col0", "sigma0",
@@ -125,9 +128,23 @@ def spmv(tabs, A, X, vals=None, perm=None, tasks=None, many=False):
     Y = np.full((A.n_rows, k), np.nan)
     seen = np.zeros(A.n_rows, int)
     for t in (range(T.tasks.shape[0]) if tasks is None else tasks):
-        c, meta, rows = T.task_rows(t)
+        meta = int(T.tasks[t][3])
         if (meta >> 8) & 1:
             continue
+        if meta & TASK_CSR:
+            # rows [i0b, i0e) straight from the CSR pattern (at most 64 rows and STREAM_ELEMS
+            # elements, or one longer row)
+            r0, r1 = int(T.tasks[t][1]), int(T.tasks[t][2])
+            assert int(T.tasks[t][0]) == -1 and 0 <= r0 < r1 <= A.n_rows
+            ne = int(A.row_ptr[r1]) - int(A.row_ptr[r0])
+            if meta & TASK_LONG:
+                assert r1 == r0 + 1 and ne > STREAM_ELEMS
+            else:
+                assert r1 - r0 <= 64 and ne <= STREAM_ELEMS
+            rows = [(r, int(A.row_ptr[r]), int(A.row_ptr[r + 1] - A.row_ptr[r]),
+                     A.col_idx[A.row_ptr[r]:A.row_ptr[r + 1]]) for r in range(r0, r1)]
+        else:
+            c, meta, rows = T.task_rows(t)
         for row, opst, nops, cols in rows:
             assert 0 <= row < A.n_rows
             seen[row] += 1

@@ -115,4 +115,23 @@ def test_traffic_formulas():
     assert fl == 2 * nnz
     info = ddf.ddf_plan_info(p)
     assert info["dev_plan_bytes"] > 0
-    assert ba == 8 * nnz + 16 * n + info["dev_plan_bytes"]  # values + vectors + the tables read
+    # values + vectors + the tables one launch reads: records and aux of the codelets it runs as
+    # codelets, its tasks, and columns and row pointers of the rows it runs from the CSR pattern
+    D = ddf.ddf_plan_device_tables(p, 0)
+    cods, aux, tasks = D["cods"], D["aux"], D["tasks"]
+    offs = cods[:, 10:15]
+    starts = [min([o for o in r if o >= 0], default=None) for r in offs]
+    ends, nxt = [0] * len(starts), aux.size
+    for c in range(len(starts) - 1, -1, -1):
+        ends[c] = nxt
+        if starts[c] is not None:
+            nxt = starts[c]
+    tables, csr_rows, csr_nnz = tasks.shape[0] * 16, 0, 0
+    run_as_codelet = set(int(t[0]) for t in tasks if not t[3] & (1 << 11))
+    for c in run_as_codelet:
+        tables += 64 + 4 * (ends[c] - starts[c] if starts[c] is not None else 0)
+    for t in tasks:
+        if t[3] & (1 << 11):
+            csr_rows += t[2] - t[1]
+            csr_nnz += int(w.A.row_ptr[t[2]] - w.A.row_ptr[t[1]])
+    assert ba == 8 * nnz + 16 * n + tables + 4 * csr_nnz + 8 * csr_rows
