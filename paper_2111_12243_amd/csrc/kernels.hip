@@ -993,7 +993,13 @@ __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
         *reinterpret_cast<int4 *>(w + 512) = make_int4(0, 0, THIN_UNUSED, 0);
         return;
     }
-    const int32_t *r = a.rec + p * THIN_REC;
+    // the record as five 16-byte loads: header, value indices 0-3, index 4 and columns 0-2,
+    // columns 3-4 and codes 0-1, codes 2-4 and the wide flag
+    const int4 *q = reinterpret_cast<const int4 *>(a.rec + p * THIN_REC);
+    const int4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
+    static_assert(THIN_REC == 20 && THIN_SLOTS == 5, "record layout");
+    const int32_t r[THIN_REC] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y,
+                                 q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z, q4.w};
     const int row = r[0], dpos = r[1];
     const int32_t *vi = r + 4, *co = r + 4 + 2 * THIN_SLOTS;
     const int64_t rb = (int64_t)row * a.k;

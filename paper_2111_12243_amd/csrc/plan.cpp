@@ -1701,7 +1701,7 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
             for (int hp : {2, 0, 4, 1})
                 for (int ah : {32, 96}) cands.push_back({target.ops_per_lane, target.passes, target.remap, 0, 2, hp, ah});
         if (!p->batch)
-            for (int opl : {4, 8})
+            for (int opl : {2, 1, 4})
                 for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, 0, 3, target.helpers, target.ahead});
         const int full = 4 * num_cu(); // up to four 256-thread blocks per CU
         for (int blocks : {full, full / 4, full / 16})
