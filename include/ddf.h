@@ -80,6 +80,12 @@ typedef struct {
                               (32), at least 8                                              */
     int32_t thin_ring;     /* single-block solve: LDS ring of recent solutions, in rows; a
                               power of two in 256..16384; 0 default (16384)                */
+    int32_t thin_lanes;    /* single-block solve: most lanes a level may use; a level with
+                              more is cut into consecutive sub-levels (its rows are
+                              independent, so any cut keeps the order); a multiple of 64 in
+                              64..1024; 0 default: chosen by a cost model (each level costs a
+                              fixed latency plus a share per wave of the block), and a level
+                              wider than 1024 lanes rules the single-block solve out        */
 } ddf_opts;
 
 typedef struct {
@@ -265,8 +271,10 @@ typedef struct {
                                 index of the diagonal, ops, placeholder flag (levels start on
                                 64-record boundaries), value indices[5], columns[5],
                                 operand codes[5]: INT32_MIN empty; >= 0 solve-order index of
-                                a row read from global memory; else -(1 + ring slot); then
-                                0, or 1 / 2 for the first / second half of a row of 2G lanes */
+                                a row read from global memory; -(1 + thin_ring_size) the
+                                row's right-hand-side term (value index -1, column the row);
+                                else -(1 + ring slot); then 0, or 1 / 2 for the first /
+                                second half of a row of 2G lanes                            */
     const int32_t *thin_lvl; /* [n][4] first record, lane slots in use, first solve-order
                                 index, rows of 2G lanes, per level, then empty levels up to a
                                 multiple of 4 plus 4 (absent: n = 0)                        */

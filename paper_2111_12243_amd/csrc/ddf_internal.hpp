@@ -95,7 +95,8 @@ struct DevTables {
     std::vector<int32_t> thin_rows;    // row of each solve-order index
     int32_t thin_lg = 0;
     int32_t thin_ring = 0;             // LDS ring size in plan positions
-    int32_t thin_nlev_pad = 0;         // levels rounded up to a multiple of 3
+    int32_t thin_nlev = 0;             // levels of the single-block solve (sub-levels included)
+    int32_t thin_nlev_pad = 0;         // levels rounded up to a multiple of 4
     int32_t thin_ngs = 0;              // op slots per lane that may hold a global operand
     int32_t thin_block = 64;           // threads of the solving block (widest level, rounded to 64)
     double *d_thin_xs = nullptr;       // solutions in solve order

@@ -809,37 +809,30 @@ __device__ __forceinline__ int4 thin_lvl(const ThinArgs &a, int l) {
                      (int)(e1 >> 32));
 }
 
-// whether the wave holding lane s has a lane in use at a level (uniform over the wave)
-__device__ __forceinline__ bool thin_wave_on(int4 lv, int s) { return (s & ~(WAVE - 1)) < lv.y; }
-
 template <int KT> struct ThinA {
     int code[THIN_SLOTS];
-    int wide; // 0: row of G lanes; 1, 2: first, second half of a row of 2G lanes
-    double v[THIN_SLOTS], d, b[KT];
+    double v[THIN_SLOTS]; // values over the diagonal
 };
 template <int KT, int NGS> struct ThinB {
     double gx[NGS > 0 ? NGS : 1][KT]; // operands gathered from global memory
 };
 
-// Fetches are issued by every wave, also one with no lane in use at the level (it reads the
-// stream's chunk of empty records): a fetch on one path only would make the compiler's wait
-// counts cover it on both.
+// Fetches are issued by every lane, also one with no record at the level (it reads the
+// stream's chunk of empty records, which stays in the L1 cache): a fetch on one path only
+// would make the compiler's wait counts cover it on both.
 template <int KT>
 __device__ __forceinline__ void thin_fetch_a(const ThinArgs &a, int l, int s, ThinA<KT> &t) {
     const int4 lv = thin_lvl(a, l);
-    const int64_t p = thin_wave_on(lv, s) ? (int64_t)lv.x + s : a.n_rec + (s & (WAVE - 1));
+    const int64_t p = s < lv.y ? (int64_t)lv.x + s : a.n_rec + (s & (WAVE - 1));
     const double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
     const int4 c = *reinterpret_cast<const int4 *>(w);
     const double2 v01 = *reinterpret_cast<const double2 *>(w + 128);
     const double2 v23 = *reinterpret_cast<const double2 *>(w + 256);
-    const double2 v4d = *reinterpret_cast<const double2 *>(w + 384);
-    const int4 bc = *reinterpret_cast<const int4 *>(w + 512);
+    const int4 v4c = *reinterpret_cast<const int4 *>(w + 384);
     t.code[0] = c.x; t.code[1] = c.y; t.code[2] = c.z; t.code[3] = c.w;
-    t.code[4] = bc.z;
-    t.wide = bc.w;
-    t.v[0] = v01.x; t.v[1] = v01.y; t.v[2] = v23.x; t.v[3] = v23.y; t.v[4] = v4d.x;
-    t.d = v4d.y;
-    t.b[0] = __hiloint2double(bc.y, bc.x);
+    t.code[4] = v4c.z;
+    t.v[0] = v01.x; t.v[1] = v01.y; t.v[2] = v23.x; t.v[3] = v23.y;
+    t.v[4] = __hiloint2double(v4c.y, v4c.x);
     static_assert(KT == 1, "one right-hand side");
 }
 
@@ -881,23 +874,24 @@ __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, co
         }
     }
     group_sum_c<LG, KT>(acc);
-    if (__any(t.wide != 0)) {
+    // lanes below ww hold the level's rows of 2G lanes (the level table counts them)
+    const int ww = lv.w << (LG + 1);
+    if (lv.w > 0) {
         // rows of 2G lanes: add the other half
 #pragma unroll
         for (int rr = 0; rr < KT; rr++) {
             const double o = lane_xor<G>(acc[rr]);
-            if (t.wide) acc[rr] += o;
+            if (s < ww) acc[rr] += o;
         }
     }
-    if (s < lv.y && t.wide != 2) {
+    if (s < lv.y && (s >= ww || !(s & G))) {
         // solve-order index: the level's first, plus the row's rank (wide rows of 2G lanes first)
-        const int ww = lv.w << (LG + 1);
         const int64_t rp = lv.z + (s < ww ? s >> (LG + 1) : lv.w + ((s - ww) >> LG));
         const int slot = (int)(rp & (a.ring - 1));
 #pragma unroll
         for (int rr = 0; rr < KT; rr++)
             if ((rr & (G - 1)) == g && rr < a.k) {
-                const double xn = (t.b[rr] - acc[rr]) * t.d; // t.d holds 1 / diagonal
+                const double xn = -acc[rr]; // the slots sum to -(b - sum of ops) / diagonal
                 a.xs[rp * KT + rr] = xn;
                 ring[slot * KT + rr] = xn;
             }
@@ -956,6 +950,8 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
     }
     extern __shared__ double ring[];
     const int s = threadIdx.x;
+    if (s == 0) ring[a.ring] = -1.0; // operand of the right-hand-side terms
+    __syncthreads();
     ThinA<KT> A0, A1, A2, A3;
     ThinB<KT, NGS> B0, B1;
     // same issue order as the loop's steady state (gathers for l + 1, then stream l + 3), so
@@ -989,8 +985,7 @@ __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
         *reinterpret_cast<int4 *>(w) = make_int4(THIN_UNUSED, THIN_UNUSED, THIN_UNUSED, THIN_UNUSED);
         *reinterpret_cast<double2 *>(w + 128) = make_double2(0.0, 0.0);
         *reinterpret_cast<double2 *>(w + 256) = make_double2(0.0, 0.0);
-        *reinterpret_cast<double2 *>(w + 384) = make_double2(0.0, 1.0);
-        *reinterpret_cast<int4 *>(w + 512) = make_int4(0, 0, THIN_UNUSED, 0);
+        *reinterpret_cast<int4 *>(w + 384) = make_int4(0, 0, THIN_UNUSED, 0);
         return;
     }
     // the record as five 16-byte loads: header, value indices 0-3, index 4 and columns 0-2,
@@ -1003,15 +998,16 @@ __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
     const int row = r[0], dpos = r[1];
     const int32_t *vi = r + 4, *co = r + 4 + 2 * THIN_SLOTS;
     const int64_t rb = (int64_t)row * a.k;
+    // every slot over the diagonal: the right-hand-side term's value is b
+    const double d = a.vals[dpos];
     double v[THIN_SLOTS];
 #pragma unroll
-    for (int j = 0; j < THIN_SLOTS; j++) v[j] = co[j] != THIN_UNUSED ? a.vals[vi[j]] : 0.0;
-    const double bv = a.b[rb];
+    for (int j = 0; j < THIN_SLOTS; j++)
+        v[j] = co[j] == THIN_UNUSED ? 0.0 : (vi[j] == THIN_VIDX_B ? a.b[rb] : a.vals[vi[j]]) / d;
     *reinterpret_cast<int4 *>(w) = make_int4(co[0], co[1], co[2], co[3]);
     *reinterpret_cast<double2 *>(w + 128) = make_double2(v[0], v[1]);
     *reinterpret_cast<double2 *>(w + 256) = make_double2(v[2], v[3]);
-    *reinterpret_cast<double2 *>(w + 384) = make_double2(v[4], 1.0 / a.vals[dpos]);
-    *reinterpret_cast<int4 *>(w + 512) = make_int4(__double2loint(bv), __double2hiint(bv), co[4], r[THIN_REC - 1]);
+    *reinterpret_cast<int4 *>(w + 384) = make_int4(__double2loint(v[4]), __double2hiint(v[4]), co[4], 0);
 }
 
 // Solutions from solve order into row order.
@@ -1227,7 +1223,7 @@ static void launch_thin(const ThinArgs &a, dim3 grid, dim3 block, size_t lds, hi
     static bool attr = false; // more dynamic LDS than the default 64 KiB
     if (!attr) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_thin<1, NGS, LG>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, THIN_RING_MAX * 8);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (THIN_RING_MAX + 1) * 8);
         attr = true;
     }
     hipLaunchKernelGGL((k_solve_thin<1, NGS, LG>), grid, block, lds, s, a);
@@ -1250,7 +1246,7 @@ hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     const dim3 sgrid((unsigned)((a.n_rec + 64 + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
     hipLaunchKernelGGL(k_thin_stream, sgrid, pblock, 0, s, a);
     const dim3 grid(1 + 8 * (unsigned)a.helpers), block((unsigned)a.block);
-    const size_t lds = (size_t)a.ring * sizeof(double);
+    const size_t lds = (size_t)(a.ring + 1) * sizeof(double);
     if (ngs == 0) launch_thin_lg<0>(a, grid, block, lds, s);
     else if (ngs == 1) launch_thin_lg<1>(a, grid, block, lds, s);
     else if (ngs == 2) launch_thin_lg<2>(a, grid, block, lds, s);

@@ -36,21 +36,27 @@ struct SpmvArgs {
 //   [14..18] its operand code: THIN_UNUSED for an empty slot; >= 0 the solve-order index of a
 //   row solved at least THIN_HORIZON levels before, read from global memory (only in the first
 //   `ngs` slots); otherwise -(1 + ring slot) of the LDS ring that keeps the solutions of the
-//   last `ring` rows solved, ring slot = solve-order index mod ring;
+//   last `ring` rows solved, ring slot = solve-order index mod ring; -(1 + ring) is the row's
+//   right-hand-side term (value index THIN_VIDX_B, column the row): its operand, the entry one
+//   past the ring, holds -1;
 //   [19] 0 for a row of G lanes; a "wide" row takes 2G lanes (its first G flagged 1, the
 //   others 2) and comes before the other rows of its level.
 // Every level's records start on a 64-record boundary; placeholder records (flag 1, no ops)
 // fill the gap.  The solve order numbers rows level by level, wide rows first.  Per call, a
-// stream is gathered in record order, structure-of-arrays per 64 records: five 16-byte fields
-// (codes 0..3, v0 v1, v2 v3, v4 and 1/diagonal, b code 4 wide flag) of 64 records each, then one
-// chunk of empty records that waves with no lane in use at a level read.  The solve writes
-// solutions in solve order, and a scatter puts them in row order.  One right-hand side.
+// stream is gathered in record order, structure-of-arrays per 64 records: four 16-byte fields
+// (codes 0..3; v0 v1; v2 v3; v4 and code 4) of 64 records each, each value divided by the row's
+// diagonal (the right-hand-side term's value is b / diagonal), so that a row's solution is
+// minus the sum of its slots; then one chunk of empty records, read by lanes with no record at
+// a level.  The solve writes solutions in solve order, and a scatter puts them in row order.
+// One right-hand side.
 constexpr int THIN_SLOTS = 5;
 constexpr int THIN_REC = 20;
-constexpr int THIN_SW = 10;                 // stream doubles per record
+constexpr int THIN_SW = 8;                  // stream doubles per record
+constexpr int32_t THIN_VIDX_B = -1;         // value index of the right-hand-side term
 constexpr int THIN_THREADS = 1024;
 constexpr int THIN_KT_MAX = 1;              // right-hand sides the single-block kernel takes
 constexpr int THIN_RING_MAX = 16384;       // LDS ring of solutions, plan positions (128 KiB)
+constexpr double THIN_WAVES_FIXED = 3.4;  // per-level fixed cost over the cost each wave adds
 constexpr int THIN_HORIZON = 3;           // a global operand's row was solved this many levels before
 constexpr int32_t THIN_UNUSED = (int32_t)0x80000000;
 struct ThinArgs {
@@ -63,7 +69,7 @@ struct ThinArgs {
     int32_t lg;       // log2 lanes per row
     int32_t k;        // right-hand sides (at most the kernel's KT)
     int32_t kt;       // the kernel's KT (stride of xs)
-    int32_t ring;     // LDS ring size in plan positions (a power of two)
+    int32_t ring;     // LDS ring size in plan positions (a power of two); one more entry holds -1
     int32_t helpers;  // blocks that pull upcoming levels into the solver's L2
     int32_t ahead;    // levels the helpers may run ahead of the solver
     int32_t n;        // rows

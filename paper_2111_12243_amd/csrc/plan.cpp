@@ -446,72 +446,128 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
 }
 
 // Records of the single-block solve, built from a matrix's codelets level by level (rows in
-// plan order).  Eligible when every row has at most 64 * THIN_SLOTS ops and every level fits
-// one 1024-lane pass; value indices go through perm for the transposed solve.
-void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *perm, int32_t ring, DevTables &D) {
+// plan order).  Every row takes its ops plus one right-hand-side term; eligible when that fits 64 * THIN_SLOTS slots per row and (without a lane cap)
+// every level fits one 1024-lane pass; value indices go through perm for the transposed solve.
+void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *perm, int32_t ring, int32_t lane_cap,
+                DevTables &D) {
     D.thin_rec.clear();
     D.thin_lvl.clear();
     D.thin_rows.clear();
     D.thin_block = 64;
     const int64_t n = P.n_rows;
-    // G lanes per row cover all but about 1% of rows; the rest ("wide" rows) take 2G lanes
+    // rows of G lanes, and "wide" rows of 2G lanes
     std::vector<int64_t> hist;
     int64_t maxn = 0;
     for (int64_t r = 0; r < n; r++) {
-        const int64_t no = P.nops(r);
+        const int64_t no = P.nops(r) + 1; // ops and the right-hand-side term
         maxn = std::max(maxn, no);
         if ((int64_t)hist.size() <= no) hist.resize(no + 1, 0);
         hist[no]++;
     }
-    int64_t p99 = 0;
-    for (int64_t acc = 0; p99 < (int64_t)hist.size(); p99++)
-        if ((acc += hist[p99]) * 100 >= n * 99) break;
-    int lg = 0;
-    while (((int64_t(THIN_SLOTS) << lg) < p99 || (int64_t(THIN_SLOTS) << (lg + 1)) < maxn) && lg < 5) lg++;
-    if ((int64_t(THIN_SLOTS) << (lg + 1)) < maxn) return;
+    // G: the fewest lanes over all rows, a row taking G lanes when its slots fit, else 2G
+    // (counted as 3G: the extra combining step makes wide rows worth it only where they are few)
+    int lg = -1;
+    int64_t best = 0;
+    for (int t = 0; t <= 5; t++) {
+        const int64_t cap1 = int64_t(THIN_SLOTS) << t;
+        if (2 * cap1 < maxn) continue;
+        int64_t lanes = 0;
+        for (int64_t no = 0; no < (int64_t)hist.size(); no++) lanes += hist[no] * (no <= cap1 ? 1 : 3) << t;
+        if (lg < 0 || lanes < best) {
+            best = lanes;
+            lg = t;
+        }
+    }
+    if (lg < 0) return;
     const int G = 1 << lg;
     // lanes per row: 2G ("wide") when its ops do not fit G lanes, or when its operands from
     // global memory would need more than one slot per lane
     std::vector<uint8_t> wide(n, 0);
-    for (int64_t r = 0; r < n; r++) wide[r] = P.nops(r) > (int64_t)G * THIN_SLOTS;
+    for (int64_t r = 0; r < n; r++) wide[r] = P.nops(r) + 1 > (int64_t)G * THIN_SLOTS;
     auto lanes_of = [&](int64_t row) -> int { return wide[row] ? 2 * G : G; };
-    const int64_t nl = c.header[5];
+    const int64_t ncl = c.header[5];
     // codelets of each level, in plan order
-    std::vector<std::vector<int64_t>> by_level(nl);
+    std::vector<std::vector<int64_t>> by_level(ncl);
     for (int64_t i = 0; i < c.header[7]; i++) by_level[c.codelets[i * NCOD + C_PART]].push_back(i);
     std::vector<int32_t> lev(n, -1);
-    std::vector<std::vector<int64_t>> rows_of(nl);
+    // the solve's levels: each level's rows in plan order, wide rows first (so they start on
+    // 2G-lane boundaries), cut into consecutive sub-levels of at most `lane_cap` lanes (rows of
+    // one level are independent, so any cut keeps the dependences)
+    std::vector<std::vector<int64_t>> rows_of;
+    std::vector<int32_t> nwide;
     // solve order of a row: its index in plan order (levels in turn, wide rows first in each);
     // lvl_end: one past a level's last solve-order index; R: widest level in G-lane groups
-    std::vector<int64_t> plan_pos(n, -1), lvl_end(nl, 0);
-    std::vector<int32_t> nwide(nl, 0);
-    int64_t R = 1;
+    std::vector<int64_t> plan_pos(n, -1), lvl_end;
+    int64_t R = 1, nl = 0;
+    // lane cap: given, or the one that minimises a cost model of the solve: every level costs a
+    // fixed latency plus a share per wave of the block (every wave streams its records, idle
+    // waves an empty chunk); THIN_WAVES_FIXED is the fixed part in units of that share
+    int64_t cap = lane_cap;
+    if (cap <= 0) {
+        std::vector<int64_t> lanes(ncl, 0);
+        int64_t maxl = 0;
+        for (int64_t l0 = 0; l0 < ncl; l0++) {
+            for (int64_t ci : by_level[l0]) {
+                const int64_t *r = &c.codelets[ci * NCOD];
+                const int32_t fl = (int32_t)r[C_FLAGS];
+                for (int64_t a = 0; a < r[C_M]; a++)
+                    lanes[l0] += lanes_of((fl & FS0) ? r[C_ROW0] + a * r[C_ROWSTEP] : c.aux[r[C_AUXOFF] + a]);
+            }
+            maxl = std::max(maxl, lanes[l0]);
+        }
+        if (maxl > THIN_THREADS) return;
+        double best = 0;
+        for (int64_t cc = 64; cc <= THIN_THREADS; cc += 64) {
+            int64_t subs = 0;
+            for (int64_t v : lanes) subs += (v + cc - 1) / cc;
+            const double cost = (double)subs * (THIN_WAVES_FIXED + (double)((std::min(cc, maxl) + 63) / 64));
+            if (cap <= 0 || cost < best) {
+                best = cost;
+                cap = cc;
+            }
+        }
+    }
     auto layout = [&]() {
-        // rows of each level in plan order, wide rows first (so they start on 2G-lane boundaries)
         R = 1;
         int64_t q = 0;
-        for (int64_t l = 0; l < nl; l++) {
-            std::vector<int64_t> narrow;
-            rows_of[l].clear();
-            for (int64_t ci : by_level[l]) {
+        rows_of.clear();
+        nwide.clear();
+        lvl_end.clear();
+        for (int64_t l0 = 0; l0 < ncl; l0++) {
+            std::vector<int64_t> wrows, narrow;
+            for (int64_t ci : by_level[l0]) {
                 const int64_t *r = &c.codelets[ci * NCOD];
                 const int32_t fl = (int32_t)r[C_FLAGS];
                 for (int64_t a = 0; a < r[C_M]; a++) {
                     const int64_t row = (fl & FS0) ? r[C_ROW0] + a * r[C_ROWSTEP] : c.aux[r[C_AUXOFF] + a];
-                    (wide[row] ? rows_of[l] : narrow).push_back(row);
+                    (wide[row] ? wrows : narrow).push_back(row);
                 }
             }
-            nwide[l] = (int32_t)rows_of[l].size();
-            rows_of[l].insert(rows_of[l].end(), narrow.begin(), narrow.end());
-            int64_t groups = 0;
-            for (int64_t row : rows_of[l]) {
-                lev[row] = (int32_t)l;
-                plan_pos[row] = q++;
-                groups += lanes_of(row) / G;
+            wrows.insert(wrows.end(), narrow.begin(), narrow.end());
+            size_t i = 0;
+            while (i < wrows.size()) {
+                std::vector<int64_t> sub;
+                int64_t lanes = 0;
+                int32_t nw = 0;
+                while (i < wrows.size() && (sub.empty() || lanes + lanes_of(wrows[i]) <= cap)) {
+                    lanes += lanes_of(wrows[i]);
+                    nw += wide[wrows[i]];
+                    sub.push_back(wrows[i++]);
+                }
+                const int64_t l = (int64_t)rows_of.size();
+                int64_t groups = 0;
+                for (int64_t row : sub) {
+                    lev[row] = (int32_t)l;
+                    plan_pos[row] = q++;
+                    groups += lanes_of(row) / G;
+                }
+                lvl_end.push_back(q);
+                nwide.push_back(nw);
+                rows_of.push_back(std::move(sub));
+                R = std::max(R, groups);
             }
-            lvl_end[l] = q;
-            R = std::max(R, groups);
         }
+        nl = (int64_t)rows_of.size();
     };
     // an operand is read from the LDS ring unless a position written up to the reading level
     // has overwritten its slot
@@ -524,7 +580,7 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
             const int64_t op = P.opstart(row), no = P.nops(row);
             int64_t ng = 0;
             for (int64_t i = 0; i < no; i++) ng += is_global(P.ci[op + i], l);
-            if (ng > G && 2 * G * THIN_SLOTS >= no) {
+            if (ng > G && 2 * G * THIN_SLOTS >= no + 1) {
                 wide[row] = 1;
                 changed = true;
             }
@@ -565,6 +621,11 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
                     if (global) ngs = std::max(ngs, next / NL + 1);
                     next++;
                 }
+            // the right-hand-side term: operand -1 read from the slot one past the ring, value
+            // b[row] (scaled by 1 / diagonal with the ops when the stream is gathered)
+            slot_vi[next] = THIN_VIDX_B;
+            slot_col[next] = (int32_t)row;
+            slot_code[next] = -(1 + ring);
             for (int g = 0; g < NL; g++) {
                 int32_t rec[THIN_REC] = {(int32_t)row, vidx(dpos), 0, 0};
                 rec[THIN_REC - 1] = NL == G ? 0 : g < G ? 1 : 2;
@@ -611,6 +672,7 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
     D.thin_ngs = ngs == 4 ? THIN_SLOTS : ngs;
     D.thin_lg = lg;
     D.thin_ring = ring;
+    D.thin_nlev = (int32_t)nl;
     D.thin_nlev_pad = (int32_t)pad;
 }
 
@@ -800,6 +862,8 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     apply_opts(o, opts);
     if (o.thin_ring != 0 && (o.thin_ring < 256 || o.thin_ring > THIN_RING_MAX || (o.thin_ring & (o.thin_ring - 1))))
         return fail(DDF_E_ARG, "thin_ring must be 0 or a power of two in 256..16384");
+    if (o.thin_lanes != 0 && (o.thin_lanes < 64 || o.thin_lanes > THIN_THREADS || o.thin_lanes % 64))
+        return fail(DDF_E_ARG, "thin_lanes must be 0 or a multiple of 64 in 64..1024");
     if (o.window < 1 || o.window > 1024) return fail(DDF_E_ARG, "window must be in 1..1024");
     for (int b = 0; b < nmat; b++) {
         if (ddf_status s = validate(kind, mats[b])) return s;
@@ -871,10 +935,10 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     if (kind == DDF_SPTRSV_LOWER && !batch) {
         const int32_t ring = o.thin_ring > 0 ? o.thin_ring : THIN_RING_MAX;
         Pattern P{kind, mats[0].n_rows, mats[0].n_cols, mats[0].row_ptr, mats[0].col_idx};
-        build_thin(p->fwd[0], P, nullptr, ring, p->F);
+        build_thin(p->fwd[0], P, nullptr, ring, o.thin_lanes, p->F);
         if (p->has_adj) {
             Pattern PT{2, mats[0].n_cols, mats[0].n_rows, rpT[0].data(), ciT[0].data()};
-            build_thin(p->adj[0], PT, &perm[0], ring, p->T);
+            build_thin(p->adj[0], PT, &perm[0], ring, o.thin_lanes, p->T);
         }
     }
     p->sp_f.path = p->sp_a.path = o.solve_path;
@@ -1113,7 +1177,7 @@ ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, d
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
     if (p->n_rows == 0) return DDF_OK;
     if (use_thin(p->F, p->sp_f, nrhs))
-        return thin_launch(p, p->F, p->sp_f, (int)p->fwd[0].header[5], d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
+        return thin_launch(p, p->F, p->sp_f, p->F.thin_nlev, d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
     // the single matrix's right-hand-side count is a per-call argument (k_override)
     return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), p->F.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
                         kt_for(nrhs), (hipStream_t)stream);
@@ -1189,7 +1253,7 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
         // single-block transposed solve, then the value gradient row by row over the forward
         // plan's codelets (sequential in the value array)
         hipStream_t s = (hipStream_t)stream;
-        if (ddf_status st = thin_launch(p, p->T, p->sp_a, (int)p->adj[0].header[5], d_vals, d_gx, d_gb, nrhs, s))
+        if (ddf_status st = thin_launch(p, p->T, p->sp_a, p->T.thin_nlev, d_vals, d_gx, d_gb, nrhs, s))
             return st;
         if (!d_gvals) return DDF_OK;
         SpmvArgs a{};

@@ -406,6 +406,20 @@ def random_lower(n: int, seed: int, density: float = 0.2, runs: bool = False) ->
     return _lower_from_pattern(t.row_ptr.astype(np.int64), t.col_idx, rng)
 
 
+def mixed_lower(n: int, seed: int, long_every: int = 150, long_ops: int = 8, short_max: int = 3) -> CSR:
+    """Lower-triangular matrix of short rows (0..short_max random earlier columns) with every
+    long_every-th row holding long_ops; diagonal = 1 + row abs-sum (last in each row)."""
+    rng = generator(seed)
+    rows, cols = [np.arange(n)], [np.arange(n)]
+    for i in range(1, n):
+        k = min(i, long_ops if i % long_every == 0 else int(rng.integers(0, short_max + 1)))
+        c = np.sort(rng.choice(i, size=k, replace=False)) if k else np.zeros(0, np.int64)
+        rows.append(np.full(c.size, i))
+        cols.append(c)
+    t = csr_from_pairs(n, n, np.concatenate(rows), np.concatenate(cols))
+    return _lower_from_pattern(t.row_ptr.astype(np.int64), t.col_idx, rng)
+
+
 def cached(name: str, builder, *args, **kw):
     """Build a workload once per process (and optionally on disk when DDF_INPUT_CACHE is set)."""
     key = (name, args, tuple(sorted(kw.items())))

@@ -15,7 +15,6 @@ TASK_STREAM = 1 << 10
 TASK_CSR = 1 << 11
 TASK_LONG = 1 << 12
 STREAM_ELEMS = 512
-STREAM_ELEMS = 512
 LOOKAHEAD = 4
 F = {n: i for i, n in enumerate(["flags", "m", "nn", "row0", "row_step", "op0", "op_step", "col0", "sigma0",
                                  "sigma1", "rows_off", "ops_off", "cnt_off", "xt_off", "xp_off", "mat"])}
@@ -245,6 +244,7 @@ def _rows_from(TF, task):
 
 
 THIN_UNUSED = -(1 << 31)
+THIN_VIDX_B = -1  # value index of a row's right-hand-side term
 
 
 def thin_solve(tabs, L, B, vals=None, Xf=None):
@@ -280,7 +280,7 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
         assert (rec[first:first + lanes, 3] == 0).all() and (rec[first + lanes:nxt, 3] == 1).all()
         assert (rec[first + lanes:nxt, 4 + 2 * S:4 + 3 * S] == THIN_UNUSED).all()
         acc, diag, dpos, slot = {}, {}, {}, {}
-        reads = {}
+        reads, bterm = {}, set()
         rank = 0
         for s in range(lanes):
             r = rec[first + s]
@@ -306,6 +306,11 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
                 vi, col, code = int(r[4 + j]), int(r[4 + S + j]), int(r[4 + 2 * S + j])
                 if code == THIN_UNUSED:
                     continue
+                if code == -(1 + M):
+                    # the row's right-hand-side term (its operand is the entry past the ring)
+                    assert vi == THIN_VIDX_B and col == row and row not in bterm
+                    bterm.add(row)
+                    continue
                 m = level_of[col]
                 assert 0 <= m < l, f"row {row} reads x[{col}] not solved in an earlier level"
                 if code >= 0:
@@ -320,6 +325,7 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
         so_next = so0 + rank
         # waves of one level may write before others read: no slot read here is written here
         assert not (set(slot.values()) & set(reads)), "a ring slot is read and overwritten in one level"
+        assert bterm == set(acc), "every row has one right-hand-side term"
         for row, a in acc.items():
             assert level_of[row] == -1
             X[row] = (B[row] - a) / diag[row]

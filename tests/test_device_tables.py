@@ -140,8 +140,11 @@ def test_thin_records_workloads():
     p = hplan(1, w.L)
     F, T = ddf.ddf_plan_device_tables(p, 0), ddf.ddf_plan_device_tables(p, 1)
     assert F["thin_rec"].shape[0] and T["thin_rec"].shape[0]
-    assert (T["thin_rec"][:, 19] == 1).any()  # the transposed factor has rows of 2G lanes
     replay_solve(w.L, k=1)
+    # about 1% of rows longer than G lanes hold: they take 2G lanes
+    L = I.mixed_lower(3000, 5)
+    F = replay_solve(L, k=1)
+    assert (F["thin_rec"][:, 19] == 1).any() and F["thin_lg"] == 0
     # a level wider than one pass is not eligible
     L = I.tril(I.laplacian(1200, 1200, 1, I.OFFS_5PT, 4.0))
     assert ddf.ddf_plan_device_tables(hplan(1, L, build_adjoint=0), 0)["thin_rec"].shape[0] == 0
@@ -160,3 +163,21 @@ def test_thin_small_ring_global_operands():
     with pytest.raises(ddf.DDFError):
         hplan(1, w.L, thin_ring=300)
 
+
+
+def test_thin_lane_cap_sub_levels():
+    # a lane cap cuts wide levels into consecutive sub-levels; the solve order stays valid
+    L = I.tril(I.laplacian(150, 150, 1, I.OFFS_5PT, 4.0))
+    full = ddf.ddf_plan_device_tables(hplan(1, L, thin_lanes=1024), 0)
+    F = replay_solve(L, k=1, thin_lanes=64)
+    used, used_full = F["thin_lvl"][:, 1], full["thin_lvl"][:, 1]
+    assert used_full.max() > 128 and used.max() <= 64 and (used > 0).sum() > (used_full > 0).sum()
+    assert used.sum() == used_full.sum() and F["thin_block"] == 64
+    # a level wider than 1024 lanes becomes eligible once cut
+    offs7 = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    L = I.tril(I.laplacian(40, 40, 40, offs7, 6.0))
+    assert ddf.ddf_plan_device_tables(hplan(1, L, build_adjoint=0), 0)["thin_rec"].shape[0] == 0
+    F = replay_solve(L, k=1, thin_lanes=1024)
+    assert F["thin_rec"].shape[0] and F["thin_lvl"][:, 1].max() <= 1024
+    with pytest.raises(ddf.DDFError):
+        hplan(1, L, thin_lanes=100)

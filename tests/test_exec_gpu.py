@@ -181,6 +181,18 @@ def test_c2_scaled():
     sptrsv_case(w.L, 1)
     # small LDS ring: most operands of the single-block solve come through the global gathers
     sptrsv_case(w.L, 1, opts=ddf.ddf_opts_default(thin_ring=256))
+    # levels cut into sub-levels of at most 128 lanes
+    sptrsv_case(w.L, 1, opts=ddf.ddf_opts_default(thin_lanes=128))
+
+
+def test_thin_sub_levels_wide():
+    # a 3D 7-point factor whose middle levels are wider than 1024 lanes: single-block only once cut
+    offs7 = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    L = I.tril(I.laplacian(48, 48, 48, offs7, 6.0))
+    o = ddf.ddf_opts_default(thin_lanes=1024, solve_path=2)
+    p = ddf.ddf_inspect(1, L, o)
+    assert ddf.ddf_plan_info(p)["solve_path"] == 2
+    sptrsv_case_path(L, 1, 0, o, False, False)
 
 
 def test_c3_scaled():
