@@ -84,8 +84,9 @@ typedef struct {
                               more is cut into consecutive sub-levels (its rows are
                               independent, so any cut keeps the order); a multiple of 64 in
                               64..1024; 0 default: chosen by a cost model (each level costs a
-                              fixed latency plus a share per wave of the block), and a level
-                              wider than 1024 lanes rules the single-block solve out        */
+                              fixed latency plus the issue time of the waves sharing a SIMD),
+                              and a level wider than 1024 lanes rules the single-block solve
+                              out                                                           */
 } ddf_opts;
 
 typedef struct {

@@ -771,13 +771,15 @@ __global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
 
 // Lane exchange within 16-lane rows through DPP (no LDS round trip): the value of lane
 // i ^ d for d in {1, 2, 4, 8}; other distances go through the LDS crossbar.
+// DPP moves with every source lane valid where the result is used (bound_ctrl set, so that no
+// old value has to be kept in the destination)
 template <int D> __device__ __forceinline__ int dpp_xor_i(int v) {
-    if constexpr (D == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);      // quad_perm 1,0,3,2
-    else if constexpr (D == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); // quad_perm 2,3,0,1
-    else if constexpr (D == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); // row_ror 8
+    if constexpr (D == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);      // quad_perm 1,0,3,2
+    else if constexpr (D == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true); // quad_perm 2,3,0,1
+    else if constexpr (D == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true); // row_ror 8
     else {
-        const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0xF, false); // row_shl 4: lane i + 4
-        const int dn = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false); // row_shr 4: lane i - 4
+        const int up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0xF, true); // row_shl 4: lane i + 4
+        const int dn = __builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, true); // row_shr 4: lane i - 4
         return (__lane_id() & 4) ? dn : up;
     }
 }
@@ -817,14 +819,17 @@ template <int KT, int NGS> struct ThinB {
     double gx[NGS > 0 ? NGS : 1][KT]; // operands gathered from global memory
 };
 
-// Fetches are issued by every lane, also one with no record at the level (it reads the
+// Fetches are issued by every wave, also one with no record at the level (it reads the
 // stream's chunk of empty records, which stays in the L1 cache): a fetch on one path only
 // would make the compiler's wait counts cover it on both.
 template <int KT>
 __device__ __forceinline__ void thin_fetch_a(const ThinArgs &a, int l, int s, ThinA<KT> &t) {
     const int4 lv = thin_lvl(a, l);
-    const int64_t p = s < lv.y ? (int64_t)lv.x + s : a.n_rec + (s & (WAVE - 1));
-    const double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
+    // the wave's chunk of 64 records (a level's records start on a chunk), or the empty chunk
+    // for a wave with no record at the level; lanes past the level's records read placeholders
+    const int wv = __builtin_amdgcn_readfirstlane(s / WAVE);
+    const int64_t chunk = wv * WAVE < lv.y ? (int64_t)(lv.x / WAVE) + wv : a.n_rec / WAVE;
+    const double *w = a.stream + chunk * (64 * THIN_SW) + (s & (WAVE - 1)) * 2;
     const int4 c = *reinterpret_cast<const int4 *>(w);
     const double2 v01 = *reinterpret_cast<const double2 *>(w + 128);
     const double2 v23 = *reinterpret_cast<const double2 *>(w + 256);
@@ -838,17 +843,13 @@ __device__ __forceinline__ void thin_fetch_a(const ThinArgs &a, int l, int s, Th
 
 template <int KT, int NGS>
 __device__ __forceinline__ void thin_fetch_b(const ThinArgs &a, const ThinA<KT> &t, ThinB<KT, NGS> &u) {
+    static_assert(KT == 1, "one right-hand side");
 #pragma unroll
     for (int j = 0; j < NGS; j++) {
-        // ring codes and empty slots read position 0 (in bounds; not used)
-        const int64_t c = max(t.code[j], 0);
-        if (KT == 1) {
-            u.gx[j][0] = a.xs[c];
-        } else {
-            const double2 q = *reinterpret_cast<const double2 *>(a.xs + c * KT);
-            u.gx[j][0] = q.x;
-            u.gx[j][KT - 1] = q.y;
-        }
+        // a global operand -(1 + solve-order index); any other code reads the zero past the
+        // solutions
+        const int c = t.code[j];
+        u.gx[j][0] = a.xs[c < 0 ? ~c : a.n];
     }
 }
 
@@ -861,17 +862,16 @@ __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, co
     double acc[KT];
 #pragma unroll
     for (int rr = 0; rr < KT; rr++) acc[rr] = 0.0;
+    const char *lds = reinterpret_cast<const char *>(ring);
 #pragma unroll
     for (int j = 0; j < THIN_SLOTS; j++) {
+        // the code is the operand's byte offset in LDS; in the first NGS slots a negative code
+        // is a global operand (gathered, while the LDS read takes the zero entry)
         const int c = t.code[j];
-        const bool used = c != THIN_UNUSED;
-        const int idx = (c < 0 && used) ? -(c + 1) : 0;
-#pragma unroll
-        for (int rr = 0; rr < KT; rr++) {
-            double xo = ring[idx * KT + rr];
-            if (j < NGS) xo = c >= 0 ? u.gx[j < NGS ? j : 0][rr] : xo;
-            acc[rr] = fma(t.v[j], used ? xo : 0.0, acc[rr]);
-        }
+        const int off = (j < NGS && c < 0) ? (a.ring + 1) * 8 : c;
+        double xo = *reinterpret_cast<const double *>(lds + off);
+        if (j < NGS) xo += u.gx[j < NGS ? j : 0][0];
+        acc[0] = fma(t.v[j], xo, acc[0]);
     }
     group_sum_c<LG, KT>(acc);
     // lanes below ww hold the level's rows of 2G lanes (the level table counts them)
@@ -890,7 +890,7 @@ __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, co
         const int slot = (int)(rp & (a.ring - 1));
 #pragma unroll
         for (int rr = 0; rr < KT; rr++)
-            if ((rr & (G - 1)) == g && rr < a.k) {
+            if ((rr & (G - 1)) == g) { // one right-hand side per call
                 const double xn = -acc[rr]; // the slots sum to -(b - sum of ops) / diagonal
                 a.xs[rp * KT + rr] = xn;
                 ring[slot * KT + rr] = xn;
@@ -914,7 +914,8 @@ __device__ __forceinline__ void thin_step(const ThinArgs &a, int l, int s, ThinA
 }
 
 // Helper blocks: each wave takes every nw-th level and touches each 128-byte line of its
-// stream entries, staying at most `ahead` levels in front of the solver.  A helper that waits
+// stream entries and of its global operands, staying at most `ahead` levels in front of the
+// solver.  A helper that waits
 // past its poll limit just stops (the solver never waits for it).
 __device__ void thin_helper(const ThinArgs &a) {
     const int h = (int)blockIdx.x / 8 - 1;
@@ -936,6 +937,21 @@ __device__ void thin_helper(const ThinArgs &a) {
 #pragma unroll 4
         for (uintptr_t o = (s0 & ~uintptr_t(127)) + lane * 128; o < s1; o += WAVE * 128)
             sink ^= *reinterpret_cast<const unsigned *>(o);
+        // and the lines of the solutions its global operands read (rows solved long before,
+        // mostly out of the L2 cache by now); a line touched before its row is solved is
+        // only brought in early
+        for (int r = lane; r < lv.y; r += WAVE) {
+            const int64_t p = (int64_t)lv.x + r;
+            const double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
+            // global operands sit in the first ngs slots, coded -(1 + solve-order index)
+            const int4 c = *reinterpret_cast<const int4 *>(w);
+            const int c4 = reinterpret_cast<const int *>(w + 384)[2];
+            if (c.x < 0 && a.ngs > 0) sink ^= *reinterpret_cast<const unsigned *>(a.xs + ~c.x);
+            if (c.y < 0 && a.ngs > 1) sink ^= *reinterpret_cast<const unsigned *>(a.xs + ~c.y);
+            if (c.z < 0 && a.ngs > 2) sink ^= *reinterpret_cast<const unsigned *>(a.xs + ~c.z);
+            if (c.w < 0 && a.ngs > 3) sink ^= *reinterpret_cast<const unsigned *>(a.xs + ~c.w);
+            if (c4 < 0 && a.ngs > 4) sink ^= *reinterpret_cast<const unsigned *>(a.xs + ~c4);
+        }
     }
     if (sink == 0x9e3779b9u) *a.sink = sink; // keeps the loads
 }
@@ -948,9 +964,14 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
         if (blockIdx.x % 8 == 0) thin_helper(a);
         return;
     }
-    extern __shared__ double ring[];
+    // the ring at a fixed LDS address (no base to add to each operand's offset), sized for the
+    // largest ring, then the -1 and 0 entries
+    __shared__ double ring[THIN_RING_MAX + 2];
     const int s = threadIdx.x;
-    if (s == 0) ring[a.ring] = -1.0; // operand of the right-hand-side terms
+    if (s == 0) {
+        ring[a.ring] = -1.0;    // operand of the right-hand-side terms
+        ring[a.ring + 1] = 0.0; // operand of empty slots
+    }
     __syncthreads();
     ThinA<KT> A0, A1, A2, A3;
     ThinB<KT, NGS> B0, B1;
@@ -977,15 +998,19 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
 // the reciprocal of the diagonal and b.  Also clears the solver's progress word before the solve starts.
 __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p == 0) *a.progress = 0u;
+    if (p == 0) {
+        *a.progress = 0u;
+        a.xs[a.n] = 0.0; // read by gathers of slots without a global operand
+    }
     if (p >= a.n_rec + 64) return;
     double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
+    const int zero = (a.ring + 1) * 8; // LDS byte offset of the zero entry
     if (p >= a.n_rec) {
         // the chunk of empty records
-        *reinterpret_cast<int4 *>(w) = make_int4(THIN_UNUSED, THIN_UNUSED, THIN_UNUSED, THIN_UNUSED);
+        *reinterpret_cast<int4 *>(w) = make_int4(zero, zero, zero, zero);
         *reinterpret_cast<double2 *>(w + 128) = make_double2(0.0, 0.0);
         *reinterpret_cast<double2 *>(w + 256) = make_double2(0.0, 0.0);
-        *reinterpret_cast<int4 *>(w + 384) = make_int4(0, 0, THIN_UNUSED, 0);
+        *reinterpret_cast<int4 *>(w + 384) = make_int4(0, 0, zero, 0);
         return;
     }
     // the record as five 16-byte loads: header, value indices 0-3, index 4 and columns 0-2,
@@ -1001,13 +1026,18 @@ __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
     // every slot over the diagonal: the right-hand-side term's value is b
     const double d = a.vals[dpos];
     double v[THIN_SLOTS];
+    int code[THIN_SLOTS];
 #pragma unroll
-    for (int j = 0; j < THIN_SLOTS; j++)
-        v[j] = co[j] == THIN_UNUSED ? 0.0 : (vi[j] == THIN_VIDX_B ? a.b[rb] : a.vals[vi[j]]) / d;
-    *reinterpret_cast<int4 *>(w) = make_int4(co[0], co[1], co[2], co[3]);
+    for (int j = 0; j < THIN_SLOTS; j++) {
+        const int c = co[j];
+        v[j] = c == THIN_UNUSED ? 0.0 : (vi[j] == THIN_VIDX_B ? a.b[rb] : a.vals[vi[j]]) / d;
+        // table codes: >= 0 global solve-order index, THIN_UNUSED empty, else -(1 + LDS entry)
+        code[j] = c >= 0 ? ~c : c == THIN_UNUSED ? zero : ~c * 8;
+    }
+    *reinterpret_cast<int4 *>(w) = make_int4(code[0], code[1], code[2], code[3]);
     *reinterpret_cast<double2 *>(w + 128) = make_double2(v[0], v[1]);
     *reinterpret_cast<double2 *>(w + 256) = make_double2(v[2], v[3]);
-    *reinterpret_cast<int4 *>(w + 384) = make_int4(__double2loint(v[4]), __double2hiint(v[4]), co[4], 0);
+    *reinterpret_cast<int4 *>(w + 384) = make_int4(__double2loint(v[4]), __double2hiint(v[4]), code[4], 0);
 }
 
 // Solutions from solve order into row order.
@@ -1218,26 +1248,18 @@ hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NGS, int LG>
-static void launch_thin(const ThinArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-    static bool attr = false; // more dynamic LDS than the default 64 KiB
-    if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_thin<1, NGS, LG>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (THIN_RING_MAX + 1) * 8);
-        attr = true;
-    }
-    hipLaunchKernelGGL((k_solve_thin<1, NGS, LG>), grid, block, lds, s, a);
+template <int NGS, int LG> static void launch_thin(const ThinArgs &a, dim3 grid, dim3 block, hipStream_t s) {
+    hipLaunchKernelGGL((k_solve_thin<1, NGS, LG>), grid, block, 0, s, a);
 }
 
-template <int NGS>
-static void launch_thin_lg(const ThinArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+template <int NGS> static void launch_thin_lg(const ThinArgs &a, dim3 grid, dim3 block, hipStream_t s) {
     switch (a.lg) {
-    case 0: launch_thin<NGS, 0>(a, grid, block, lds, s); break;
-    case 1: launch_thin<NGS, 1>(a, grid, block, lds, s); break;
-    case 2: launch_thin<NGS, 2>(a, grid, block, lds, s); break;
-    case 3: launch_thin<NGS, 3>(a, grid, block, lds, s); break;
-    case 4: launch_thin<NGS, 4>(a, grid, block, lds, s); break;
-    default: launch_thin<NGS, 5>(a, grid, block, lds, s); break;
+    case 0: launch_thin<NGS, 0>(a, grid, block, s); break;
+    case 1: launch_thin<NGS, 1>(a, grid, block, s); break;
+    case 2: launch_thin<NGS, 2>(a, grid, block, s); break;
+    case 3: launch_thin<NGS, 3>(a, grid, block, s); break;
+    case 4: launch_thin<NGS, 4>(a, grid, block, s); break;
+    default: launch_thin<NGS, 5>(a, grid, block, s); break;
     }
 }
 
@@ -1246,12 +1268,11 @@ hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     const dim3 sgrid((unsigned)((a.n_rec + 64 + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
     hipLaunchKernelGGL(k_thin_stream, sgrid, pblock, 0, s, a);
     const dim3 grid(1 + 8 * (unsigned)a.helpers), block((unsigned)a.block);
-    const size_t lds = (size_t)(a.ring + 1) * sizeof(double);
-    if (ngs == 0) launch_thin_lg<0>(a, grid, block, lds, s);
-    else if (ngs == 1) launch_thin_lg<1>(a, grid, block, lds, s);
-    else if (ngs == 2) launch_thin_lg<2>(a, grid, block, lds, s);
-    else if (ngs == 3) launch_thin_lg<3>(a, grid, block, lds, s);
-    else launch_thin_lg<THIN_SLOTS>(a, grid, block, lds, s);
+    if (ngs == 0) launch_thin_lg<0>(a, grid, block, s);
+    else if (ngs == 1) launch_thin_lg<1>(a, grid, block, s);
+    else if (ngs == 2) launch_thin_lg<2>(a, grid, block, s);
+    else if (ngs == 3) launch_thin_lg<3>(a, grid, block, s);
+    else launch_thin_lg<THIN_SLOTS>(a, grid, block, s);
     hipLaunchKernelGGL(k_thin_scatter, rgrid, pblock, 0, s, a);
     return hipGetLastError();
 }

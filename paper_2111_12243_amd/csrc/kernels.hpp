@@ -47,8 +47,11 @@ struct SpmvArgs {
 // (codes 0..3; v0 v1; v2 v3; v4 and code 4) of 64 records each, each value divided by the row's
 // diagonal (the right-hand-side term's value is b / diagonal), so that a row's solution is
 // minus the sum of its slots; then one chunk of empty records, read by lanes with no record at
-// a level.  The solve writes solutions in solve order, and a scatter puts them in row order.
-// One right-hand side.
+// a level.  A stream code is the byte offset in LDS of the slot's operand: a ring slot, the
+// entry past the ring (-1, right-hand-side terms) or the one after it (0, empty slots); in the
+// first `ngs` slots a global operand is coded -(1 + its solve-order index) instead, and the
+// other codes there also gather the zero kept past the solutions.  The solve writes solutions
+// in solve order, and a scatter puts them in row order.  One right-hand side.
 constexpr int THIN_SLOTS = 5;
 constexpr int THIN_REC = 20;
 constexpr int THIN_SW = 8;                  // stream doubles per record
@@ -56,7 +59,7 @@ constexpr int32_t THIN_VIDX_B = -1;         // value index of the right-hand-sid
 constexpr int THIN_THREADS = 1024;
 constexpr int THIN_KT_MAX = 1;              // right-hand sides the single-block kernel takes
 constexpr int THIN_RING_MAX = 16384;       // LDS ring of solutions, plan positions (128 KiB)
-constexpr double THIN_WAVES_FIXED = 3.4;  // per-level fixed cost over the cost each wave adds
+constexpr double THIN_SIMD_FIXED = 3.5;   // per-level fixed cost over one wave's issue time
 constexpr int THIN_HORIZON = 3;           // a global operand's row was solved this many levels before
 constexpr int32_t THIN_UNUSED = (int32_t)0x80000000;
 struct ThinArgs {
@@ -69,7 +72,8 @@ struct ThinArgs {
     int32_t lg;       // log2 lanes per row
     int32_t k;        // right-hand sides (at most the kernel's KT)
     int32_t kt;       // the kernel's KT (stride of xs)
-    int32_t ring;     // LDS ring size in plan positions (a power of two); one more entry holds -1
+    int32_t ring;     // LDS ring size in plan positions (a power of two); two more entries hold -1, 0
+    int32_t ngs;      // op slots per lane that may hold a global operand
     int32_t helpers;  // blocks that pull upcoming levels into the solver's L2
     int32_t ahead;    // levels the helpers may run ahead of the solver
     int32_t n;        // rows
@@ -79,7 +83,7 @@ struct ThinArgs {
     const double *b;
     double *x;
     double *stream;     // THIN_SW doubles per record, gathered before the solve
-    double *xs;         // solutions in solve order, kt per row
+    double *xs;         // solutions in solve order, kt per row, then one zero
     unsigned *progress; // levels the solver has finished (read by the helpers)
     unsigned *sink;     // helpers' discard word (never read)
 };

@@ -500,8 +500,9 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
     std::vector<int64_t> plan_pos(n, -1), lvl_end;
     int64_t R = 1, nl = 0;
     // lane cap: given, or the one that minimises a cost model of the solve: every level costs a
-    // fixed latency plus a share per wave of the block (every wave streams its records, idle
-    // waves an empty chunk); THIN_WAVES_FIXED is the fixed part in units of that share
+    // fixed latency plus the instruction issue of the waves that share a SIMD (four SIMDs per
+    // compute unit; idle waves issue as much as busy ones); THIN_SIMD_FIXED is the fixed part
+    // in units of one wave's issue
     int64_t cap = lane_cap;
     if (cap <= 0) {
         std::vector<int64_t> lanes(ncl, 0);
@@ -520,7 +521,8 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
         for (int64_t cc = 64; cc <= THIN_THREADS; cc += 64) {
             int64_t subs = 0;
             for (int64_t v : lanes) subs += (v + cc - 1) / cc;
-            const double cost = (double)subs * (THIN_WAVES_FIXED + (double)((std::min(cc, maxl) + 63) / 64));
+            const int64_t waves = (std::min(cc, maxl) + 63) / 64;
+            const double cost = (double)subs * (THIN_SIMD_FIXED + (double)((waves + 3) / 4));
             if (cap <= 0 || cost < best) {
                 best = cost;
                 cap = cc;
@@ -798,7 +800,8 @@ ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
         if (ddf_status s = dalloc(p, (void **)&D.d_thin_stream,
                                   (D.thin_rec.size() / THIN_REC + 64) * THIN_SW * sizeof(double)))
             return s;
-        if (ddf_status s = dalloc(p, (void **)&D.d_thin_xs, D.thin_rows.size() * sizeof(double))) return s;
+        // solutions in solve order, and one zero that gathers of slots without a global operand read
+        if (ddf_status s = dalloc(p, (void **)&D.d_thin_xs, (D.thin_rows.size() + 1) * sizeof(double))) return s;
     }
     return upload(p, &D.d_aux, D.aux.data(), D.aux.size());
 }
@@ -820,6 +823,7 @@ ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, 
     t.k = k;
     t.kt = 1;
     t.ring = D.thin_ring;
+    t.ngs = D.thin_ngs;
     t.n = (int32_t)D.thin_rows.size();
     t.block = D.thin_block;
     t.xs = D.d_thin_xs;
