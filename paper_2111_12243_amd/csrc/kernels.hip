@@ -1174,6 +1174,56 @@ __global__ __launch_bounds__(WAVE *WPB) void k_csr_gv(PlainArgs a) {
     }
 }
 
+// Value gradient of an adjoint (GvArgs): G lanes per row, each lane one entry at a time; the
+// row of g in registers; x rows read whole (16-byte loads when VEC).  KT = 0: any k.
+template <int KT, bool VEC> __global__ __launch_bounds__(WAVE *WPB) void k_gv_csr(GvArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
+    const int64_t row = ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
+    const int g = lane & (G - 1);
+    if (row >= a.n) return;
+    const int k = KT > 0 ? KT : a.k;
+    const double *__restrict__ gr = a.g + row * k;
+    const int e1 = a.rp[row + 1];
+    if constexpr (KT > 0) {
+        double gw[KT];
+        if constexpr (VEC) {
+#pragma unroll
+            for (int r = 0; r < KT; r += 2) {
+                const double2 q = *reinterpret_cast<const double2 *>(gr + r);
+                gw[r] = q.x;
+                gw[r + 1] = q.y;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < KT; r++) gw[r] = gr[r];
+        }
+        for (int e = a.rp[row] + g; e < e1; e += G) {
+            const double *__restrict__ xr = a.x + (int64_t)a.ci[e] * KT;
+            double s = 0.0;
+            if constexpr (VEC) {
+#pragma unroll
+                for (int r = 0; r < KT; r += 2) {
+                    const double2 q = *reinterpret_cast<const double2 *>(xr + r);
+                    s = fma(gw[r], q.x, s);
+                    s = fma(gw[r + 1], q.y, s);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < KT; r++) s = fma(gw[r], xr[r], s);
+            }
+            a.gv[e] = a.sign * s;
+        }
+    } else {
+        for (int e = a.rp[row] + g; e < e1; e += G) {
+            const double *__restrict__ xr = a.x + (int64_t)a.ci[e] * k;
+            double s = 0.0;
+            for (int r = 0; r < k; r++) s = fma(gr[r], xr[r], s);
+            a.gv[e] = a.sign * s;
+        }
+    }
+}
+
 int g_solve_blocks = 0; // resident blocks of the persistent kernel on the whole device
 int g_num_cu = 0;
 
@@ -1338,6 +1388,32 @@ static int lg_for(double avg, int ops_per_lane) {
     int lg = 0;
     while (lg < 6 && (double)(1 << lg) * ops_per_lane < avg) lg++;
     return lg;
+}
+
+hipError_t launch_gv(GvArgs a, double avg_row, hipStream_t s) {
+    a.lg = lg_for(avg_row, 1);
+    if (a.lg > 5) a.lg = 5;
+    const int R = WAVE >> a.lg;
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + (int64_t)R * WPB - 1) / ((int64_t)R * WPB))), block(WAVE * WPB);
+    const bool al = ((reinterpret_cast<uintptr_t>(a.g) | reinterpret_cast<uintptr_t>(a.x)) & 15) == 0;
+    switch (a.k) {
+    case 1: hipLaunchKernelGGL((k_gv_csr<1, false>), grid, block, 0, s, a); break;
+    case 2:
+        if (al) hipLaunchKernelGGL((k_gv_csr<2, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_gv_csr<2, false>), grid, block, 0, s, a);
+        break;
+    case 4:
+        if (al) hipLaunchKernelGGL((k_gv_csr<4, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_gv_csr<4, false>), grid, block, 0, s, a);
+        break;
+    case 8:
+        if (al) hipLaunchKernelGGL((k_gv_csr<8, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_gv_csr<8, false>), grid, block, 0, s, a);
+        break;
+    default: hipLaunchKernelGGL((k_gv_csr<0, false>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s) {

@@ -133,6 +133,20 @@ struct PlainArgs {
 
 enum PlainKind { PLAIN_SPMV, PLAIN_LEVEL, PLAIN_SPMV_ADJ, PLAIN_GV };
 
+// Value gradient over a CSR pattern: gv[e] = sign * sum_r g[row, r] x[col, r] for every stored
+// entry e = (row, col), rows of k values (row-major, stride k).
+struct GvArgs {
+    const int32_t *rp;
+    const int32_t *ci;
+    const double *g;
+    const double *x;
+    double *gv;
+    double sign;
+    int64_t n; // rows
+    int32_t k;
+    int32_t lg; // log2 lanes per row
+};
+
 int kt_for(int k);
 hipError_t init_device_info();
 hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s);
@@ -144,5 +158,6 @@ hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
+hipError_t launch_gv(GvArgs a, double avg_row, hipStream_t s);
 
 } // namespace ddf

@@ -1071,6 +1071,22 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     return DDF_OK;
 }
 
+// Value gradient over the plan's CSR pattern (the forward matrix, diagonal included for a
+// triangular plan): gv[e] = sign * <g[row], x[col]>.
+hipError_t launch_gv_pass(ddf_plan_t p, const double *g, const double *x, double *gv, double sign, int32_t k,
+                          hipStream_t s) {
+    GvArgs a{};
+    a.rp = p->d_rp;
+    a.ci = p->d_ci;
+    a.g = g;
+    a.x = x;
+    a.gv = gv;
+    a.sign = sign;
+    a.n = p->n_rows;
+    a.k = k;
+    return launch_gv(a, p->n_rows ? (double)p->nnz / (double)p->n_rows : 1.0, s);
+}
+
 } // namespace
 
 // =================================================================================================
@@ -1211,29 +1227,21 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
     hipStream_t s = (hipStream_t)stream;
     const bool many = nrhs > 1;
     const int64_t ngx = many ? p->n_gx_tasksN : p->n_gx_tasks;
-    const int64_t nall = (int64_t)(many ? p->T.tasksN.size() : p->T.tasks.size());
-    int64_t t0 = d_gx ? 0 : ngx;
-    int64_t t1 = d_gvals ? nall : ngx;
-    if (t1 <= t0) return DDF_OK;
+    if (d_gvals) HIPCHK(launch_gv_pass(p, d_gy, d_x, d_gvals, 1.0, nrhs, s));
+    if (!d_gx || ngx == 0) return DDF_OK;
     SpmvArgs a{};
     a.cods = p->T.d_cods;
     a.aux = p->T.d_aux;
     a.rp = p->d_rpT;
     a.ci = p->d_ciT;
-    a.tasks = (many ? p->T.d_tasksN : p->T.d_tasks) + t0;
-    a.ntasks = (int32_t)(t1 - t0);
+    a.tasks = many ? p->T.d_tasksN : p->T.d_tasks;
+    a.ntasks = (int32_t)ngx;
     a.k = nrhs;
     a.remap = p->sp_a.remap;
     a.vals = d_vals;
     a.perm = p->d_perm;
     a.x = d_gy;
     a.y = d_gx;
-    a.cods2 = p->F.d_cods;
-    a.aux2 = p->F.d_aux;
-    a.g = d_gy;
-    a.x2 = d_x;
-    a.gv = d_gvals;
-    a.gv_sign = 1.0;
     HIPCHK(launch_spmv(a, true, s));
     return DDF_OK;
 }
@@ -1253,31 +1261,17 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
     if (d_gvals && (overlap(d_gvals, p->nnz * 8, d_gb, nb) || overlap(d_gvals, p->nnz * 8, d_x, nb)))
         return fail(DDF_E_ARG, "gvals overlaps another buffer");
     if (p->n_rows == 0) return DDF_OK;
+    // the transposed solve for lambda, then the value gradient -lambda[row] x[col] of every entry
+    // of L (diagonal included), in value order
+    hipStream_t s = (hipStream_t)stream;
     if (use_thin(p->T, p->sp_a, nrhs)) {
-        // single-block transposed solve, then the value gradient row by row over the forward
-        // plan's codelets (sequential in the value array)
-        hipStream_t s = (hipStream_t)stream;
-        if (ddf_status st = thin_launch(p, p->T, p->sp_a, p->T.thin_nlev, d_vals, d_gx, d_gb, nrhs, s))
-            return st;
-        if (!d_gvals) return DDF_OK;
-        SpmvArgs a{};
-        a.tasks = p->T.d_tasks + p->n_solve_tasks_adj;
-        a.ntasks = (int32_t)((int64_t)p->T.tasks.size() - p->n_solve_tasks_adj);
-        a.k = nrhs;
-        a.remap = p->sp_a.remap;
-        a.cods2 = p->F.d_cods;
-        a.aux2 = p->F.d_aux;
-        a.g = d_gb;
-        a.x2 = d_x;
-        a.gv = d_gvals;
-        a.gv_sign = -1.0;
-        a.gv_diag = 1;
-        HIPCHK(launch_spmv(a, false, s));
-        return DDF_OK;
+        if (ddf_status st = thin_launch(p, p->T, p->sp_a, p->T.thin_nlev, d_vals, d_gx, d_gb, nrhs, s)) return st;
+    } else if (ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, p->T.n_counters, true, d_vals, d_gx,
+                                            d_gb, d_x, nullptr, nrhs, kt_for(nrhs), s)) {
+        return st;
     }
-    int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
-    return solve_launch(p, p->T, 0, nt, p->T.n_counters, true, d_vals, d_gx, d_gb, d_x, d_gvals, nrhs, kt_for(nrhs),
-                        (hipStream_t)stream);
+    if (d_gvals) HIPCHK(launch_gv_pass(p, d_gb, d_x, d_gvals, -1.0, nrhs, s));
+    return DDF_OK;
 }
 
 static int batch_kt(ddf_plan_t p) {
@@ -1586,7 +1580,9 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         fl = 2 * nnz * nrhs;
         break;
     case DDF_OP_SPMV_ADJ:
-        ba = 20 * nnz + (p->has_adj ? (many ? p->T.launch_bytes(true) : p->T.table_bytes1) : 0) + Fca + 16 * vk + 16 * ck;
+        // transposed product: values through perm; value gradient over the CSR pattern
+        ba = 24 * nnz + (p->has_adj ? (many ? p->T.launch_bytes(true) : p->T.table_bytes1) : 0) + 4 * (n + 1) +
+             16 * vk + 16 * ck;
         bc = 20 * nnz + 4 * (n + 1) + 8 * vk + 16 * ck;
         fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
         break;
@@ -1603,11 +1599,13 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         }
         break;
     case DDF_OP_SPTRSV_ADJ:
+        // transposed solve, then the value gradient over the CSR pattern (columns and row pointers)
         if (p->has_adj && !p->batch && use_thin(p->T, p->sp_a, nrhs))
-            ba = 16 * nnz + p->T.thin_bytes() + Fca +
-                 (int64_t)(p->T.tasks.size() - p->n_solve_tasks_adj) * (int64_t)sizeof(Task) + 24 * vk;
-        else
+            ba = 20 * nnz + p->T.thin_bytes() + 4 * (n + 1) + 24 * vk;
+        else if (p->batch)
             ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 32 * vk;
+        else
+            ba = 24 * nnz + (p->has_adj ? p->T.bytes() : 0) + 4 * (n + 1) + 32 * vk;
         bc = 20 * nnz + 4 * (n + 1) + 24 * vk;
         if (p->batch) {
             for (size_t b = 0; b < p->mats.size(); b++) {
