@@ -288,6 +288,10 @@ typedef struct {
     int32_t thin_ngs;         /* op slots per lane (the lowest) that may read global memory   */
     int32_t thin_block;       /* threads of the solving block                                  */
     int32_t reserved;
+    const int32_t *rowlist;   /* SpMV, one RHS: rows of the row-list tasks (tasks with bit 13:
+                                 list entries [i0b, i0e), one lane per row, run from the CSR
+                                 pattern)                                                      */
+    int64_t n_rowlist;
 } ddf_device_tables_t;
 ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
 

@@ -90,6 +90,9 @@ struct DevTables {
     int64_t table_bytes1 = 0;          // plan bytes a one-RHS SpMV launch reads
     std::vector<int32_t> cod_aux;      // aux words of each codelet
     std::vector<uint8_t> csr_cod;      // SpMV, one right-hand side: codelet run from the CSR pattern
+                                       // (1: in row ranges, 2: in the row list)
+    std::vector<int32_t> rowlist;      // SpMV, one right-hand side: rows of TASK_ROWS tasks
+    int32_t *d_rowlist = nullptr;
     std::vector<int32_t> thin_rec;     // single-block solve records (empty if not eligible)
     std::vector<int32_t> thin_lvl;     // per level: first record, lanes, first solve index, wide rows
     std::vector<int32_t> thin_rows;    // row of each solve-order index

@@ -319,6 +319,30 @@ __device__ void spmv_csr_task(const SpmvArgs &a, const Task &tk, int lane, doubl
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Scattered short rows from the CSR pattern, one lane per row of list[i0b, i0e): packs the
+// rows of small codelets that no run of consecutive rows covers, 64 to a wave.
+template <bool VPERM> __device__ void spmv_rows_task(const SpmvArgs &a, const Task &tk, int lane) {
+    const int i = tk.i0b + lane;
+    if (i >= tk.i0e) return;
+    const int row = a.rows[i];
+    const int e0 = a.rp[row], e1 = a.rp[row + 1];
+    double acc = 0.0;
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        int c[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            c[u] = a.ci[e + u];
+            v[u] = val_at<VPERM>(a, e + u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) acc = fma(v[u], a.x[c[u]], acc);
+    }
+    for (; e < e1; e++) acc = fma(val_at<VPERM>(a, e), a.x[a.ci[e]], acc);
+    a.y[row] = acc;
+}
+
 // one right-hand side: stream and lanes-per-row tasks (and phase-1 GV tasks)
 template <bool VPERM>
 __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
@@ -331,6 +355,8 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
         spmv_gv_task(a, tk, lane);
     else if (tk.meta & TASK_CSR)
         spmv_csr_task<VPERM>(a, tk, lane, lds_all[wave]);
+    else if (tk.meta & TASK_ROWS)
+        spmv_rows_task<VPERM>(a, tk, lane);
     else if (tk.meta & TASK_STREAM)
         spmv_stream_task<VPERM>(a, tk, lane, lds_all[wave]);
     else

@@ -16,7 +16,8 @@ struct SpmvArgs {
     int32_t remap; // XCD-contiguous block order
     const double *vals;
     const int32_t *perm; // values through perm (transposed plan)
-    const int32_t *rp, *ci; // CSR pattern of the pass (TASK_CSR tasks)
+    const int32_t *rp, *ci; // CSR pattern of the pass (TASK_CSR and TASK_ROWS tasks)
+    const int32_t *rows;    // row list of TASK_ROWS tasks
     const double *x;
     double *y;
     // phase-1 tasks of a fused adjoint launch: gv[e] = sum_r g[row, r] x2[col, r]
@@ -93,7 +94,9 @@ constexpr int CTR_STRIDE = 32; // uint32 per counter line (128 bytes)
 enum : int32_t { TASK_FAST = 1 << 9,     // solve: thin-range task whose rows fit the look-ahead registers
                  TASK_STREAM = 1 << 10,   // SpMV: one-RHS task streamed element by element
                  TASK_CSR = 1 << 11,      // SpMV, one RHS: rows [i0b, i0e) of the CSR pattern
-                 TASK_LONG = 1 << 12 };   // with TASK_CSR: one row longer than a stream task
+                 TASK_LONG = 1 << 12,     // with TASK_CSR: one row longer than a stream task
+                 TASK_ROWS = 1 << 13 };   // SpMV, one RHS: rows list[i0b, i0e) (<= 64), a lane each
+constexpr int ROWS_MAX_LEN = 8;          // longest row a TASK_ROWS lane takes
 constexpr int STREAM_ELEMS = 64 * 8;     // elements of a stream task (64 lanes x 8)
 
 struct SolveArgs {

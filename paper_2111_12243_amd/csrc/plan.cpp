@@ -268,11 +268,16 @@ void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_i
 // SpMV tasks of one codelet for one right-hand side: rectangular codelets whose values
 // (and full column table) are contiguous are streamed element by element, STREAM_ELEMS per
 // task; others get lanes-per-row tasks.
+// A rectangular codelet whose rows fit one stream task runs element-streamed.
+bool stream_cod(const DCod &d) {
+    const int mode = xmode_host(d.flags);
+    return (d.flags & FRECT) && d.nn >= 1 && d.nn <= STREAM_ELEMS && (mode == 0 || mode == 1 || mode == 3) &&
+           !(d.flags & DOPS) && (d.m == 1 || d.op_step == d.nn);
+}
+
 void spmv1_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_index, const SchedParams &sp,
                  std::vector<Task> &out) {
-    const int mode = xmode_host(d.flags);
-    const bool stream = (d.flags & FRECT) && d.nn >= 1 && d.nn <= STREAM_ELEMS && (mode == 0 || mode == 1 || mode == 3) &&
-                        !(d.flags & DOPS) && (d.m == 1 || d.op_step == d.nn);
+    const bool stream = stream_cod(d);
     if (!stream) {
         codelet_tasks(d, aux, cod_index, sp, 0, out);
         return;
@@ -298,12 +303,17 @@ void cod_rows(const DCod &d, const std::vector<int32_t> &aux, std::vector<int32_
 // up to STREAM_ELEMS elements or 64 rows; a longer row gets a wave of its own).
 constexpr int64_t TINY_OPS = 128;
 
-// Splits a plan pass between codelet tasks and CSR row ranges: a codelet with fewer than
-// TINY_OPS ops runs from the CSR pattern when all its rows lie in runs of at least CSR_RUN
-// consecutive such rows (scattered small codelets keep their own tasks).
+// Splits a plan pass between codelet tasks and rows run from the CSR pattern: a codelet with
+// fewer than TINY_OPS ops runs as row ranges when all its rows lie in runs of at least CSR_RUN
+// consecutive such rows, else in the row list (one lane per row, 64 rows to a wave) when none
+// of its rows is longer than ROWS_MAX_LEN; a codelet that does not stream and whose rows all
+// hold more than LONG_ROW entries runs as row ranges too (a wave per row beyond STREAM_ELEMS,
+// in chunks with every lane's loads in flight); the others keep their own tasks.
 constexpr int64_t CSR_RUN = 16;
+constexpr int64_t LONG_ROW = 256;
 
-void split_tiny(const DevTables &D, int64_t n_rows, std::vector<uint8_t> &csr_cod, std::vector<int32_t> &rows) {
+void split_tiny(const DevTables &D, int64_t n_rows, const std::vector<int32_t> &rp, std::vector<uint8_t> &csr_cod,
+                std::vector<int32_t> &rows, std::vector<int32_t> &listrows) {
     std::vector<uint8_t> tiny_row(n_rows, 0);
     std::vector<int32_t> tmp;
     csr_cod.assign(D.cods.size(), 0);
@@ -326,16 +336,46 @@ void split_tiny(const DevTables &D, int64_t n_rows, std::vector<uint8_t> &csr_co
         r = e;
     }
     rows.clear();
+    listrows.clear();
     for (size_t c = 0; c < D.cods.size(); c++) {
+        if (!stream_cod(D.cods[c])) {
+            tmp.clear();
+            cod_rows(D.cods[c], D.aux, tmp);
+            bool longrows = !tmp.empty();
+            for (int32_t r : tmp) longrows = longrows && rp[r + 1] - rp[r] > LONG_ROW;
+            if (longrows) {
+                csr_cod[c] = 1;
+                rows.insert(rows.end(), tmp.begin(), tmp.end());
+                continue;
+            }
+        }
         if (cod_ops(D.cods[c], D.aux) >= TINY_OPS) continue;
         tmp.clear();
         cod_rows(D.cods[c], D.aux, tmp);
-        bool ok = true;
-        for (int32_t r : tmp) ok = ok && run[r] >= CSR_RUN;
-        if (!ok) continue;
-        csr_cod[c] = 1;
-        rows.insert(rows.end(), tmp.begin(), tmp.end());
+        bool ok = true, fits = true;
+        for (int32_t r : tmp) {
+            ok = ok && run[r] >= CSR_RUN;
+            fits = fits && rp[r + 1] - rp[r] <= ROWS_MAX_LEN;
+        }
+        if (ok) {
+            csr_cod[c] = 1;
+            rows.insert(rows.end(), tmp.begin(), tmp.end());
+        } else if (fits) {
+            csr_cod[c] = 2;
+            listrows.insert(listrows.end(), tmp.begin(), tmp.end());
+        }
     }
+}
+
+// Row-list tasks: rows sorted by length (lanes of a wave then loop about equally long), 64 to
+// a task.  The sorted list is kept for the device.
+void rows_tasks(std::vector<int32_t> &listrows, const std::vector<int32_t> &rp, std::vector<Task> &out) {
+    std::sort(listrows.begin(), listrows.end(), [&](int32_t a, int32_t b) {
+        const int32_t la = rp[a + 1] - rp[a], lb = rp[b + 1] - rp[b];
+        return la != lb ? la < lb : a < b;
+    });
+    for (size_t i = 0; i < listrows.size(); i += 64)
+        out.push_back({-1, (int32_t)i, (int32_t)std::min(listrows.size(), i + 64), TASK_ROWS});
 }
 
 void csr_tasks(std::vector<int32_t> &rows, const std::vector<int32_t> &rp, std::vector<Task> &out) {
@@ -361,7 +401,7 @@ void csr_tasks(std::vector<int32_t> &rows, const std::vector<int32_t> &rp, std::
 // Plan bytes a one-RHS SpMV launch reads: records and aux of the codelets it runs as codelets,
 // its task list, and the CSR columns and row pointers of the rows it runs from the pattern.
 int64_t spmv1_table_bytes(const DevTables &D) {
-    int64_t b = (int64_t)D.tasks.size() * sizeof(Task) + 4 * D.csr_nnz + 8 * D.csr_rows;
+    int64_t b = (int64_t)D.tasks.size() * sizeof(Task) + 4 * D.csr_nnz + 8 * D.csr_rows + 4 * (int64_t)D.rowlist.size();
     for (size_t c = 0; c < D.cods.size(); c++)
         if (!D.csr_cod[c]) b += (int64_t)sizeof(DCod) + 4 * (int64_t)D.cod_aux[c];
     return b;
@@ -436,10 +476,13 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     drop_alloc(p, D.d_tasks);
     drop_alloc(p, D.d_tasksN);
     drop_alloc(p, D.d_sync);
+    drop_alloc(p, D.d_rowlist);
     D.d_tasks = nullptr;
     D.d_tasksN = nullptr;
     D.d_sync = nullptr;
+    D.d_rowlist = nullptr;
     ddf_status s = upload(p, &D.d_tasks, D.tasks.data(), D.tasks.size());
+    if (!s && !D.rowlist.empty()) s = upload(p, &D.d_rowlist, D.rowlist.data(), D.rowlist.size());
     if (!s && !D.tasksN.empty()) s = upload(p, &D.d_tasksN, D.tasksN.data(), D.tasksN.size());
     if (!s && !D.sync.empty()) s = upload(p, &D.d_sync, D.sync.data(), D.sync.size());
     return s;
@@ -705,43 +748,46 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
         if (fwd) {
             p->F.tasks.clear();
             p->F.tasksN.clear();
-            std::vector<int32_t> tiny;
+            std::vector<int32_t> tiny, listrows;
             std::vector<uint8_t> csr_cod;
-            split_tiny(p->F, p->n_rows, csr_cod, tiny);
+            split_tiny(p->F, p->n_rows, p->hrp, csr_cod, tiny, listrows);
             for (size_t c = 0; c < p->F.cods.size(); c++) {
                 if (!csr_cod[c]) spmv1_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_f, p->F.tasks);
                 spmvN_tasks(p->F.cods[c], (int32_t)c, p->sp_f, p->F.tasksN);
             }
             p->F.csr_cod = csr_cod;
-            p->F.csr_rows = (int64_t)tiny.size();
+            p->F.csr_rows = (int64_t)(tiny.size() + listrows.size());
             p->F.csr_nnz = 0;
             for (int32_t r : tiny) p->F.csr_nnz += p->hrp[r + 1] - p->hrp[r];
+            for (int32_t r : listrows) p->F.csr_nnz += p->hrp[r + 1] - p->hrp[r];
             csr_tasks(tiny, p->hrp, p->F.tasks);
+            rows_tasks(listrows, p->hrp, p->F.tasks);
+            p->F.rowlist = listrows;
             p->F.table_bytes1 = spmv1_table_bytes(p->F);
             if (ddf_status s = upload_tasks(p, p->F)) return s;
         }
         if (adjp && p->has_adj) {
             p->T.tasks.clear();
             p->T.tasksN.clear();
-            std::vector<int32_t> tiny;
+            std::vector<int32_t> tiny, listrows;
             std::vector<uint8_t> csr_cod;
-            split_tiny(p->T, p->n_cols, csr_cod, tiny);
+            split_tiny(p->T, p->n_cols, p->hrpT, csr_cod, tiny, listrows);
             for (size_t c = 0; c < p->T.cods.size(); c++) {
                 if (!csr_cod[c]) spmv1_tasks(p->T.cods[c], p->T.aux, (int32_t)c, p->sp_a, p->T.tasks);
                 spmvN_tasks(p->T.cods[c], (int32_t)c, p->sp_a, p->T.tasksN);
             }
             p->T.csr_cod = csr_cod;
-            p->T.csr_rows = (int64_t)tiny.size();
+            p->T.csr_rows = (int64_t)(tiny.size() + listrows.size());
             p->T.csr_nnz = 0;
             for (int32_t r : tiny) p->T.csr_nnz += p->hrpT[r + 1] - p->hrpT[r];
+            for (int32_t r : listrows) p->T.csr_nnz += p->hrpT[r + 1] - p->hrpT[r];
             csr_tasks(tiny, p->hrpT, p->T.tasks);
+            rows_tasks(listrows, p->hrpT, p->T.tasks);
+            p->T.rowlist = listrows;
             p->T.table_bytes1 = spmv1_table_bytes(p->T);
+            // the value gradient runs over the CSR pattern, apart from these tasks
             p->n_gx_tasks = (int64_t)p->T.tasks.size();
             p->n_gx_tasksN = (int64_t)p->T.tasksN.size();
-            std::vector<Task> gvt;
-            for (size_t c = 0; c < p->F.cods.size(); c++) codelet_tasks(p->F.cods[c], p->F.aux, (int32_t)c, p->sp_a, 1, gvt);
-            p->T.tasks.insert(p->T.tasks.end(), gvt.begin(), gvt.end());
-            p->T.tasksN.insert(p->T.tasksN.end(), gvt.begin(), gvt.end());
             if (ddf_status s = upload_tasks(p, p->T)) return s;
         }
         return DDF_OK;
@@ -1169,6 +1215,7 @@ ddf_status ddf_spmv_v(ddf_plan_t p, const double *d_vals, const double *d_x, dou
     a.aux = p->F.d_aux;
     a.rp = p->d_rp;
     a.ci = p->d_ci;
+    a.rows = p->F.d_rowlist;
     const bool many = nrhs > 1;
     a.tasks = many ? p->F.d_tasksN : p->F.d_tasks;
     a.ntasks = (int32_t)(many ? p->F.tasksN.size() : p->F.tasks.size());
@@ -1234,6 +1281,7 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
     a.aux = p->T.d_aux;
     a.rp = p->d_rpT;
     a.ci = p->d_ciT;
+    a.rows = p->T.d_rowlist;
     a.tasks = many ? p->T.d_tasksN : p->T.d_tasks;
     a.ntasks = (int32_t)ngx;
     a.k = nrhs;
@@ -1560,6 +1608,8 @@ ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables
     o->thin_ring_size = D->thin_ring;
     o->thin_ngs = D->thin_ngs;
     o->thin_block = D->thin_block;
+    o->rowlist = D->rowlist.data();
+    o->n_rowlist = (int64_t)D->rowlist.size();
     return DDF_OK;
 }
 

@@ -68,7 +68,7 @@ class ddf_device_tables_t(C.Structure):
                 ("thin_rows", C.POINTER(C.c_int32)), ("n_thin_rec", C.c_int64),
                 ("n_thin_lvl", C.c_int64), ("thin_lg", C.c_int32), ("thin_ring_size", C.c_int32),
                 ("thin_reserved", C.c_int32), ("thin_ngs", C.c_int32), ("thin_block", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("rowlist", C.POINTER(C.c_int32)), ("n_rowlist", C.c_int64)]
 
 
 class ddf_plan_info_t(C.Structure):
@@ -371,7 +371,7 @@ def ddf_plan_device_tables(plan, which=0) -> dict:
             "thin_rec": grab(t.thin_rec, t.n_thin_rec, 20), "thin_lvl": grab(t.thin_lvl, t.n_thin_lvl, 4),
             "thin_rows": grab(t.thin_rows, t.n_thin_lvl and ddf_plan_info(plan)["n_rows"], 1).ravel(),
             "thin_lg": int(t.thin_lg), "thin_ring_size": int(t.thin_ring_size), "thin_ngs": int(t.thin_ngs),
-            "thin_block": int(t.thin_block)}
+            "thin_block": int(t.thin_block), "rowlist": grab(t.rowlist, t.n_rowlist)}
 
 
 def ddf_plan_traffic(plan, op, nrhs) -> tuple:

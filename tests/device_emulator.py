@@ -14,6 +14,8 @@ TASK_FAST = 1 << 9
 TASK_STREAM = 1 << 10
 TASK_CSR = 1 << 11
 TASK_LONG = 1 << 12
+TASK_ROWS = 1 << 13
+ROWS_MAX_LEN = 8
 STREAM_ELEMS = 512
 LOOKAHEAD = 4
 F = {n: i for i, n in enumerate(["flags", "m", "nn", "row0", "row_step", "op0", "op_step", "col0", "sigma0",
@@ -142,6 +144,17 @@ def spmv(tabs, A, X, vals=None, perm=None, tasks=None, many=False):
                 assert r1 - r0 <= 64 and ne <= STREAM_ELEMS
             rows = [(r, int(A.row_ptr[r]), int(A.row_ptr[r + 1] - A.row_ptr[r]),
                      A.col_idx[A.row_ptr[r]:A.row_ptr[r + 1]]) for r in range(r0, r1)]
+        elif meta & TASK_ROWS:
+            # rows list[i0b, i0e) of the row list, one lane each, from the CSR pattern
+            i0b, i0e = int(T.tasks[t][1]), int(T.tasks[t][2])
+            lst = tabs["rowlist"]
+            assert int(T.tasks[t][0]) == -1 and 0 <= i0b < i0e <= lst.size and i0e - i0b <= 64
+            rows = []
+            for r in lst[i0b:i0e]:
+                r = int(r)
+                assert 0 <= r < A.n_rows and A.row_ptr[r + 1] - A.row_ptr[r] <= ROWS_MAX_LEN
+                rows.append((r, int(A.row_ptr[r]), int(A.row_ptr[r + 1] - A.row_ptr[r]),
+                             A.col_idx[A.row_ptr[r]:A.row_ptr[r + 1]]))
         else:
             c, meta, rows = T.task_rows(t)
         for row, opst, nops, cols in rows:

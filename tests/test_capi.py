@@ -127,11 +127,28 @@ def test_traffic_formulas():
         if starts[c] is not None:
             nxt = starts[c]
     tables, csr_rows, csr_nnz = tasks.shape[0] * 16, 0, 0
-    run_as_codelet = set(int(t[0]) for t in tasks if not t[3] & (1 << 11))
+    from_csr = (1 << 11) | (1 << 13)
+    run_as_codelet = set(int(t[0]) for t in tasks if not t[3] & from_csr)
     for c in run_as_codelet:
         tables += 64 + 4 * (ends[c] - starts[c] if starts[c] is not None else 0)
-    for t in tasks:
-        if t[3] & (1 << 11):
-            csr_rows += t[2] - t[1]
-            csr_nnz += int(w.A.row_ptr[t[2]] - w.A.row_ptr[t[1]])
+    rows = [r for t in tasks if t[3] & (1 << 11) for r in range(t[1], t[2])]
+    rows += [int(r) for t in tasks if t[3] & (1 << 13) for r in D["rowlist"][t[1]:t[2]]]
+    tables += 4 * D["rowlist"].size
+    csr_rows = len(rows)
+    csr_nnz = sum(int(w.A.row_ptr[r + 1] - w.A.row_ptr[r]) for r in rows)
     assert ba == 8 * nnz + 16 * n + tables + 4 * csr_nnz + 8 * csr_rows
+
+
+def test_row_list_tasks():
+    # scattered short rows of small codelets run from the CSR pattern, 64 rows to a wave
+    from paper_2111_12243_amd import inputs as I2
+    A = I2.c3_chung_lu(n=20000).A
+    p = ddf.ddf_inspect(0, A, hopts())
+    D = ddf.ddf_plan_device_tables(p, 0)
+    rl = D["rowlist"]
+    tasks = D["tasks"]
+    rt = tasks[(tasks[:, 3] & (1 << 13)) != 0]
+    assert rl.size > 0 and rt.shape[0] == (rl.size + 63) // 64
+    lens = np.diff(A.row_ptr)[rl]
+    assert (lens <= 8).all() and (np.diff(lens) >= 0).all()  # sorted by length
+    assert np.array_equal(np.sort(np.concatenate([np.arange(t[1], t[2]) for t in rt])), np.arange(rl.size))

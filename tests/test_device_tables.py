@@ -26,11 +26,11 @@ def replay_spmv(A, k=2, seed=0, **kw):
     for many in (False, True):
         check_product(A, X, E.spmv(F, A, X, many=many), O.spmv(A, X))
         lst = T["tasksN"] if many else T["tasks"]
-        n_gx = int(np.sum(((lst[:, 3] >> 8) & 1) == 0))
-        gx = E.spmv(T, AT, G, vals=A.values, perm=perm, tasks=range(n_gx), many=many)
+        # the value gradient runs over the CSR pattern: the transposed plan holds product tasks only
+        assert not ((lst[:, 3] >> 8) & 1).any()
+        gx = E.spmv(T, AT, G, vals=A.values, perm=perm, many=many)
         check_product(AT, G, gx, GXr)
-        check_gv(A, X, G, E.gv(T, F, A, G, X, n_gx, many=many), GVr)
-    assert (F["tasks"][:, 3] & E.TASK_STREAM).any() or A.nnz == 0 or True
+    return F
 
 
 def replay_solve(L, k=2, seed=0, **kw):
