@@ -1211,6 +1211,7 @@ template <int KT, bool VEC> __global__ __launch_bounds__(WAVE *WPB) void k_gv_cs
     const int k = KT > 0 ? KT : a.k;
     const double *__restrict__ gr = a.g + row * k;
     const int e1 = a.rp[row + 1];
+    if (e1 - a.rp[row] > GV_LONG_ROW) return; // in the chunk pass
     if constexpr (KT > 0) {
         double gw[KT];
         if constexpr (VEC) {
@@ -1247,6 +1248,24 @@ template <int KT, bool VEC> __global__ __launch_bounds__(WAVE *WPB) void k_gv_cs
             for (int r = 0; r < k; r++) s = fma(gr[r], xr[r], s);
             a.gv[e] = a.sign * s;
         }
+    }
+}
+
+// The chunks of long rows: a wave per GV_CHUNK entries of one row, 8 entries a lane.
+template <int KT> __global__ __launch_bounds__(WAVE *WPB) void k_gv_chunks(GvArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * WPB + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (c >= a.n_chunks) return;
+    const int2 ch = a.chunks[c];
+    const int64_t row = ch.x;
+    const int k = KT > 0 ? KT : a.k;
+    const double *__restrict__ gr = a.g + row * k;
+    const int e1 = min(a.rp[row + 1], ch.y + GV_CHUNK);
+    for (int e = ch.y + lane; e < e1; e += WAVE) {
+        const double *__restrict__ xr = a.x + (int64_t)a.ci[e] * k;
+        double s = 0.0;
+        for (int r = 0; r < k; r++) s = fma(gr[r], xr[r], s);
+        a.gv[e] = a.sign * s;
     }
 }
 
@@ -1416,9 +1435,14 @@ static int lg_for(double avg, int ops_per_lane) {
     return lg;
 }
 
-hipError_t launch_gv(GvArgs a, double avg_row, hipStream_t s) {
-    a.lg = lg_for(avg_row, 1);
+hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s) {
+    a.lg = lg_for(avg_short_row, 1);
     if (a.lg > 5) a.lg = 5;
+    if (a.n_chunks > 0) {
+        const dim3 cg((unsigned)((a.n_chunks + WPB - 1) / WPB)), cb(WAVE * WPB);
+        if (a.k == 1) hipLaunchKernelGGL((k_gv_chunks<1>), cg, cb, 0, s, a);
+        else hipLaunchKernelGGL((k_gv_chunks<0>), cg, cb, 0, s, a);
+    }
     const int R = WAVE >> a.lg;
     if (a.n <= 0) return hipSuccess;
     const dim3 grid((unsigned)((a.n + (int64_t)R * WPB - 1) / ((int64_t)R * WPB))), block(WAVE * WPB);

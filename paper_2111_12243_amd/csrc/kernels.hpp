@@ -148,7 +148,11 @@ struct GvArgs {
     int64_t n; // rows
     int32_t k;
     int32_t lg; // log2 lanes per row
+    const int2 *chunks; // (row, first entry) of the chunks of rows longer than GV_LONG_ROW
+    int64_t n_chunks;
 };
+constexpr int GV_LONG_ROW = 256;  // rows longer than this run in chunks of GV_CHUNK entries
+constexpr int GV_CHUNK = 512;
 
 int kt_for(int k);
 hipError_t init_device_info();
@@ -161,6 +165,6 @@ hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
-hipError_t launch_gv(GvArgs a, double avg_row, hipStream_t s);
+hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s);
 
 } // namespace ddf

@@ -46,6 +46,9 @@ struct ddf_plan_s {
     int64_t ctr_words = 0;            // allocated counter words
     int64_t n_gx_tasks = 0;           // SpMV adjoint: tasks before the GV pass (one RHS)
     int64_t n_gx_tasksN = 0;          // same, several right-hand sides
+    std::vector<int32_t> gv_chunks;   // value gradient: (row, first entry) per chunk of a long row
+    int32_t *d_gv_chunks = nullptr;
+    double gv_avg_short = 1.0;        // mean length of the other rows
     double *d_vals = nullptr;
     int32_t *d_perm = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_rpT = nullptr, *d_ciT = nullptr;
     int32_t *d_rows = nullptr, *d_rrows = nullptr;
@@ -1035,10 +1038,27 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         if ((s = upload(p, &p->d_perm, pall.data(), pall.size()))) return fin(s);
     }
     if (!batch) {
-        // CSR copies for the plain comparators
+        // CSR copies for the plain comparators and the adjoints' value gradient
         if ((s = upload(p, &p->d_rp, p->hrp.data(), p->hrp.size()))) return fin(s);
         if ((s = upload(p, &p->d_ci, p->hci.data(), p->hci.size()))) return fin(s);
         if (p->has_adj) {
+            // value gradient: rows longer than GV_LONG_ROW go in chunks of GV_CHUNK entries
+            int64_t short_rows = 0, short_nnz = 0;
+            for (int64_t r = 0; r < p->n_rows; r++) {
+                const int32_t b0 = p->hrp[r], len = p->hrp[r + 1] - b0;
+                if (len > GV_LONG_ROW) {
+                    for (int32_t e = b0; e < b0 + len; e += GV_CHUNK) {
+                        p->gv_chunks.push_back((int32_t)r);
+                        p->gv_chunks.push_back(e);
+                    }
+                } else {
+                    short_rows++;
+                    short_nnz += len;
+                }
+            }
+            p->gv_avg_short = short_rows ? std::max(1.0, (double)short_nnz / (double)short_rows) : 1.0;
+            if (!p->gv_chunks.empty() && (s = upload(p, &p->d_gv_chunks, p->gv_chunks.data(), p->gv_chunks.size())))
+                return fin(s);
             if ((s = upload(p, &p->d_rpT, rpT[0].data(), rpT[0].size()))) return fin(s);
             if ((s = upload(p, &p->d_ciT, ciT[0].data(), ciT[0].size()))) return fin(s);
         }
@@ -1130,7 +1150,9 @@ hipError_t launch_gv_pass(ddf_plan_t p, const double *g, const double *x, double
     a.sign = sign;
     a.n = p->n_rows;
     a.k = k;
-    return launch_gv(a, p->n_rows ? (double)p->nnz / (double)p->n_rows : 1.0, s);
+    a.chunks = reinterpret_cast<const int2 *>(p->d_gv_chunks);
+    a.n_chunks = (int64_t)p->gv_chunks.size() / 2;
+    return launch_gv(a, p->gv_avg_short, s);
 }
 
 } // namespace
