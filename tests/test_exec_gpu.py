@@ -204,3 +204,52 @@ def test_c5_scaled():
     w = I.c5_laplace27(nx=32, k=8)
     spmv_case(w.A, 8)
     sptrsv_case(w.L, 8)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("path", [2, 3])
+def test_graph_capture_step(path):
+    # one step (SpMV, its adjoint, the solve, its adjoint) captured in a graph and replayed
+    # several times, with eager work and synchronisation between replays; every replay must
+    # match the eager results bit for bit
+    print(f"graph capture of one step, solve path {path}", flush=True)
+    w = I.c2_stencil27_offband(nx=18)
+    A, L = w.A, w.L
+    pA = ddf.ddf_inspect(0, A)
+    pL = ddf.ddf_inspect(1, L, ddf.ddf_opts_default(solve_path=path))
+    assert ddf.ddf_plan_info(pL)["solve_path"] == path
+    vA, vL = dev(A.values), dev(L.values)
+    x, gy = dev(rnd((A.n_cols, 1), 3)), dev(rnd((A.n_rows, 1), 4))
+    b, gx = dev(rnd((L.n_rows, 1), 5)), dev(rnd((L.n_rows, 1), 6))
+    y, gxa, gva = torch.empty_like(gy), torch.empty_like(x), torch.empty(A.nnz, dtype=torch.float64, device=DEV)
+    xs, gb, gvl = torch.empty_like(b), torch.empty_like(b), torch.empty(L.nnz, dtype=torch.float64, device=DEV)
+    outs = (y, gxa, gva, xs, gb, gvl)
+
+    def step():
+        ddf.ddf_spmv_v(pA, vA, x, y, 1)
+        ddf.ddf_spmv_adjoint(pA, vA, x, gy, gxa, gva, 1)
+        ddf.ddf_sptrsv_v(pL, vL, b, xs, 1)
+        ddf.ddf_sptrsv_adjoint(pL, vL, xs, gx, gb, gvl, 1)
+
+    step()
+    torch.cuda.synchronize()
+    ref = [host(t).copy() for t in outs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(3):
+        for t in outs:
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for got, want in zip(outs, ref):
+            assert np.array_equal(host(got), want), f"replay {rep}"
+        step()  # eager work between replays
+        torch.cuda.synchronize()
