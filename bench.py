@@ -7,7 +7,10 @@ tables, vectors read once and written once; see ddf_plan_traffic) divided by the
 The plain GPU comparators (CSR-vector SpMV, FP64-atomic adjoint, one launch per level) are
 timed the same way, and the CPU oracle on a bounded sample of the same step.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c5|c1|c3]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c5|c1|c3|c4]
+
+With --workload c4 (256 triangular matrices with 1..32 right-hand sides each) a step is the
+batched solve and its adjoint, one launch each; the comparator is one launch per matrix.
 """
 import argparse
 import hashlib
@@ -76,6 +79,8 @@ def main():
         from paper_2111_12243_amd import build as B
         B.build()
     dev = torch.device("cuda:0")
+    if args.workload == "c4":
+        return bench_batch(args, np, torch, ddf, I, dev)
     t0 = time.time()
     w = I.workload(args.workload)
     log(f"[bench] workload {w.name} generated in {time.time() - t0:.1f}s")
@@ -275,6 +280,140 @@ def main():
         "plain": {"ms_per_step": round(ms_plain, 4), "value": round(value_plain, 2),
                   "speedup_vs_plain": round(ms_plain / ms, 3)},
         "per_op": per_op, "bytes_alg_per_step": bytes_step, "parity": parity,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, np, torch, ddf, I, dev):
+    """The batched solve and its adjoint on C4, one persistent launch each."""
+    import oracle as O
+    t0 = time.time()
+    w = I.workload("c4")
+    mats = [m["L"] for m in w.batch]
+    ks = [m["k"] for m in w.batch]
+    log(f"[bench] workload {w.name} generated in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    p = ddf.ddf_inspect_batch(ddf.DDF_SPTRSV_LOWER, mats, ks)
+    t_insp = time.time() - t0
+    log(f"[bench] inspect {t_insp:.2f}s")
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    vals = d(np.concatenate([m.values for m in mats]))
+    B = d(np.concatenate([m["B"].ravel() for m in w.batch]))
+    G = d(np.concatenate([m["G"].ravel() for m in w.batch]))
+    X, GB, GV = torch.empty_like(B), torch.empty_like(B), torch.empty_like(vals)
+    ops = {"sptrsv_batch": lambda: ddf.ddf_sptrsv_batch(p, vals, B, X),
+           "sptrsv_batch_adj": lambda: ddf.ddf_sptrsv_batch_adjoint(p, vals, X, G, GB, GV)}
+    if args.profile_op:
+        for name in args.profile_op.split(","):
+            for _ in range(args.steps):
+                ops[name]()
+            torch.cuda.synchronize()
+            log(f"[bench] ran {name} x{args.steps}")
+        return
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    for _ in range(args.warmup):
+        for f in ops.values():
+            f()
+    torch.cuda.synchronize()
+    marks = {n: [] for n in ops}
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(args.steps):
+        for n, f in ops.items():
+            a, b = ev(), ev()
+            a.record()
+            f()
+            b.record()
+            marks[n].append((a, b))
+    e1.record()
+    torch.cuda.synchronize()
+    ddf.ddf_plan_sync_status(p)
+    ms = e0.elapsed_time(e1) / args.steps
+    op_ms = {n: sum(a.elapsed_time(b) for a, b in m) / len(m) for n, m in marks.items()}
+    log(f"[bench] batch step {ms:.3f} ms {op_ms}")
+    # comparator: the same solve, one launch per matrix
+    ddf.ddf_sptrsv_batch_per_matrix(p, vals, B, X)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    for _ in range(2):
+        ddf.ddf_sptrsv_batch_per_matrix(p, vals, B, X)
+    b.record()
+    torch.cuda.synchronize()
+    per_matrix_ms = a.elapsed_time(b) / 2
+    # graph replay of the forward launch
+    g = ddf.ddf_graph_create_batch(p, 0, vals, B, None, X, None)
+    ddf.ddf_graph_launch(g)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    for _ in range(3):
+        ddf.ddf_graph_launch(g)
+    b.record()
+    torch.cuda.synchronize()
+    graph_ms = a.elapsed_time(b) / 3
+    ddf.ddf_graph_destroy(g)
+
+    traffic = {"sptrsv_batch": ddf.ddf_plan_traffic(p, ddf.DDF_OP_SPTRSV, 1),
+               "sptrsv_batch_adj": ddf.ddf_plan_traffic(p, ddf.DDF_OP_SPTRSV_ADJ, 1)}
+    bytes_step = sum(t[0] for t in traffic.values())
+    value = bytes_step / (ms / 1e3) / 1e9
+    per_op = {n: {"ms": round(op_ms[n], 4), "gbps_alg": round(traffic[n][0] / op_ms[n] / 1e6, 1),
+                  "pct_peak": round(100 * traffic[n][0] / op_ms[n] / 1e6 / PEAK_GBPS, 2)} for n in ops}
+    per_op["sptrsv_batch"]["plain_ms"] = round(per_matrix_ms, 4)
+    per_op["sptrsv_batch"]["speedup_vs_plain"] = round(per_matrix_ms / op_ms["sptrsv_batch"], 3)
+    per_op["sptrsv_batch"]["graph_replay_ms"] = round(graph_ms, 4)
+
+    # parity spot check: a few matrices against the oracle
+    ddf.ddf_sptrsv_batch(p, vals, B, X)
+    torch.cuda.synchronize()
+    xh = X.cpu().numpy()
+    rel, off = 0.0, 0
+    for m in w.batch:
+        n, k = m["L"].n_rows, m["k"]
+        if len(mats) < 8 or m is w.batch[0] or m is w.batch[-1]:
+            ref = O.sptrsv(m["L"], m["B"])
+            got = xh[off:off + n * k].reshape(n, k)
+            rel = max(rel, float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)))
+        off += n * k
+    dom = max(per_op, key=lambda n: per_op[n]["ms"])
+    ach = traffic[dom][0] / (op_ms[dom] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBPS, "unit": "GB/s",
+                "frac": round(ach / PEAK_GBPS, 4), "traffic": None, "kernel": f"k_solve ({dom})",
+                "bytes_alg_per_launch": traffic[dom][0]}
+    cpu = None
+    if not args.no_cpu:
+        t0 = time.time()
+        done = 0
+        for m in w.batch:
+            xr = O.sptrsv(m["L"], m["B"])
+            O.sptrsv_adj(m["L"], xr, m["G"])
+            done += 1
+            if time.time() - t0 > args.cpu_seconds:
+                break
+        cpu_s = time.time() - t0
+        frac_rows = sum(m["L"].n_rows for m in w.batch[:done]) / sum(m.n_rows for m in mats)
+        cpu_step = cpu_s / frac_rows
+        cpu = {"value": round(bytes_step / cpu_step / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {done} of {len(mats)} matrices (solve and adjoint), {cpu_s:.1f} s, "
+                         f"scaled by their share of the rows to {cpu_step * 1e3:.0f} ms per step"}
+    out = {
+        "metric": "SpMV/SpTRSV fwd+adjoint effective HBM GB/s and % of peak vs plain, FP64",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "matrices": len(mats), "rows": sum(m.n_rows for m in mats),
+                   "nnz_L": sum(m.nnz for m in mats), "nrhs_range": [min(ks), max(ks)],
+                   "max_levels": ddf.ddf_plan_info(p)["max_levels"], "inspect_s": round(t_insp, 3)},
+        "pct_of_peak": round(100 * value / PEAK_GBPS, 2),
+        "per_op": per_op, "bytes_alg_per_step": bytes_step, "parity": {"sptrsv_rel_err": rel},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
