@@ -784,15 +784,15 @@ __global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
 // Single-block solve for matrices whose every level fits one pass of the block: one lane slot
 // per (row, lane-of-row), levels separated by block barriers.
 //
-// One CU runs the whole solve, so its vector memory pipeline is the limit: a level costs
-// roughly the vector memory instructions its waves issue.  Only waves with lanes in use at a
-// level fetch or compute for it, and a lane fetches one stream entry (operand codes, values,
-// diagonal, b) plus only the operands that must come from global memory.  Operands solved in
-// the last ring_levels levels come from an LDS ring.  A wave's vector memory operations
-// complete in issue order, so nothing on a level's critical path reads global memory: the
-// stream entry is fetched four levels ahead and the global operands (rows final by then) two
-// levels ahead.  Helper blocks dispatched to the solver's XCD pull the stream of the levels
-// just ahead into the shared L2.
+// One CU runs the whole solve, so a level costs a fixed latency (barrier, LDS round trips),
+// the vector memory instructions its waves issue and the VALU issue of the waves that share a
+// SIMD.  A lane fetches one stream entry per level (operand codes as LDS offsets, values over
+// the diagonal) plus only the operands that must come from global memory; the others come
+// from an LDS ring of the most recent solutions.  A wave's vector memory operations complete
+// in issue order, so nothing on a level's critical path reads global memory: the stream entry
+// is fetched four levels ahead and the global operands (rows final by then) two levels ahead.
+// Helper blocks dispatched to the solver's XCD pull the stream and the global operands of the
+// levels just ahead into the shared L2.
 // ------------------------------------------------------------------------------------------
 
 // Lane exchange within 16-lane rows through DPP (no LDS round trip): the value of lane
