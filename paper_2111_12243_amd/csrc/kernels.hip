@@ -364,7 +364,8 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
 }
 
 // several right-hand sides: KR lanes per row, lane r owns right-hand sides r, r + KR, ...
-constexpr int RU = 4; // ops per unrolled chunk of a rectangular row
+constexpr int RU = 4;  // ops per unrolled chunk of a rectangular row (one RHS per lane)
+constexpr int RUV = 8; // the same with RV right-hand sides per lane (16-byte loads)
 
 template <int KR, int MODE, bool VPERM>
 __device__ __forceinline__ void spmvN_rect(const SpmvArgs &a, const DCod &c, const Task &tk, int lane) {
@@ -422,12 +423,12 @@ __device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, c
         double acc[RV];
 #pragma unroll
         for (int q = 0; q < RV; q++) acc[q] = 0.0;
-        for (int i1 = 0; i1 < nn; i1 += RU) {
-            int col[RU];
-            double v[RU];
-            double2 xv[RU][RV / 2];
+        for (int i1 = 0; i1 < nn; i1 += RUV) {
+            int col[RUV];
+            double v[RUV];
+            double2 xv[RUV][RV / 2];
 #pragma unroll
-            for (int u = 0; u < RU; u++) {
+            for (int u = 0; u < RUV; u++) {
                 const int j = min(i1 + u, nn - 1);
                 if constexpr (MODE == XM_STRIDED)
                     col[u] = cbase + j * c.sigma1;
@@ -438,13 +439,13 @@ __device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, c
                 v[u] = val_at<VPERM>(a, opst + j);
             }
 #pragma unroll
-            for (int u = 0; u < RU; u++) {
+            for (int u = 0; u < RUV; u++) {
                 const double2 *xp = reinterpret_cast<const double2 *>(a.x + (int64_t)col[u] * k + r);
 #pragma unroll
                 for (int h = 0; h < RV / 2; h++) xv[u][h] = xp[h];
             }
 #pragma unroll
-            for (int u = 0; u < RU; u++)
+            for (int u = 0; u < RUV; u++)
                 if (i1 + u < nn) {
 #pragma unroll
                     for (int h = 0; h < RV / 2; h++) {
