@@ -72,8 +72,10 @@ typedef struct {
     int32_t solve_blocks;  /* schedule (solve): 256-thread blocks of the persistent kernel;
                               0 = every block the device keeps resident                     */
     int32_t solve_path;    /* solve kernel: 0 auto (single-block when every level fits one
-                              1024-lane pass, else multi-block), 1 multi-block, 2 single-block
-                              when possible, 3 one launch per level of the multi-block tasks */
+                              1024-lane pass, else multi-block; batches: one launch per level
+                              over all matrices, one op per lane, one row pass), 1 multi-block
+                              (batches: one persistent launch), 2 single-block when
+                              possible, 3 one launch per level of the multi-block tasks     */
     int32_t thin_helpers;  /* single-block solve: helper blocks that pull the next levels'
                               tables into the solver's L2; -1 default (2), 0 none, max 8  */
     int32_t thin_ahead;    /* single-block solve: levels the helpers run ahead; 0 default
@@ -263,7 +265,8 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
  *                        look-ahead eligible << 9 | streamed << 10); for SpMV the list used
  *                        with one right-hand side; for the solve in ticket order
  *   sync   [n_tasks][4]  solve: level counter to wait on (-1: none), task count it must
- *                        reach, level counter to signal (-1: none), 0
+ *                        reach, level counter to signal (-1: none), level (-1 for
+ *                        the value-gradient tasks of a batch adjoint)
  *   tasksN [n_tasksN][4] SpMV: the list used with several right-hand sides */
 typedef struct {
     const int32_t *cods, *aux, *tasks, *sync, *tasksN;

@@ -444,7 +444,7 @@ std::vector<std::pair<int64_t, int64_t>> build_solve(const DevTables &D, const s
             for (const Task &t : per[b][l]) {
                 tasks.push_back(t);
                 const int32_t sy[4] = {l > 0 ? (int32_t)(base[b] + l - 1) : -1,
-                                       l > 0 ? (int32_t)per[b][l - 1].size() : 0, (int32_t)(base[b] + l), 0};
+                                       l > 0 ? (int32_t)per[b][l - 1].size() : 0, (int32_t)(base[b] + l), l};
                 sync.insert(sync.end(), sy, sy + 4);
             }
         }
@@ -461,7 +461,7 @@ void append_gv(const DevTables &F, int64_t c0, int64_t c1, std::pair<int64_t, in
     for (int64_t c = c0; c < c1; c++) codelet_tasks(F.cods[c], F.aux, (int32_t)c, sp, 1, tk);
     for (const Task &t : tk) {
         tasks.push_back(t);
-        const int32_t sy[4] = {(int32_t)last.first, (int32_t)last.second, -1, 0};
+        const int32_t sy[4] = {(int32_t)last.first, (int32_t)last.second, -1, -1};
         sync.insert(sync.end(), sy, sy + 4);
     }
 }
@@ -995,6 +995,13 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         }
     }
     p->sp_f.path = p->sp_a.path = o.solve_path;
+    if (batch && o.solve_path == 0) {
+        // batches: one launch per level over all matrices, one op per lane and one row pass
+        // (the one-launch persistent kernel is solve_path 1)
+        p->sp_f.path = p->sp_a.path = 3;
+        p->sp_f.ops_per_lane = p->sp_a.ops_per_lane = 1;
+        p->sp_f.passes = p->sp_a.passes = 1;
+    }
     p->sp_f.helpers = p->sp_a.helpers = o.thin_helpers < 0 ? 2 : std::min(o.thin_helpers, 8);
     p->sp_f.ahead = p->sp_a.ahead = o.thin_ahead <= 0 ? 32 : std::max(o.thin_ahead, 8);
     if (p->host_only) {
@@ -1116,14 +1123,15 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.spin_limit = p->spin_limit;
     a.k_override = k_override;
     if (sp.path == 3) {
-        // one launch per level (task ranges of equal signal counter; the GV tasks last)
+        // one launch per level (task ranges of equal level, over all matrices of a batch; the
+        // GV tasks last)
         const Task *tk = a.tasks;
         const int4 *sy = a.sync;
         int64_t i = 0;
         while (i < ntasks) {
-            const int32_t ctr = D.sync[(t0 + i) * 4 + 2];
+            const int32_t lev = D.sync[(t0 + i) * 4 + 3];
             int64_t j = i + 1;
-            while (j < ntasks && D.sync[(t0 + j) * 4 + 2] == ctr) j++;
+            while (j < ntasks && D.sync[(t0 + j) * 4 + 3] == lev) j++;
             a.tasks = tk + i;
             a.sync = sy + i;
             a.ntasks = (int32_t)(j - i);

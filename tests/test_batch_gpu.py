@@ -15,9 +15,10 @@ from paper_2111_12243_amd import ddf  # noqa: E402
 DEV = "cuda:0"
 
 
-def make_batch(nmat, n_lo, n_hi):
+def make_batch(nmat, n_lo, n_hi, path=0):
     mats = [I.batch_matrix(b, n_lo=n_lo, n_hi=n_hi) for b in range(nmat)]
-    plan = ddf.ddf_inspect_batch(1, [m["L"] for m in mats], [m["k"] for m in mats])
+    plan = ddf.ddf_inspect_batch(1, [m["L"] for m in mats], [m["k"] for m in mats],
+                                 ddf.ddf_opts_default(solve_path=path))
     vals = np.concatenate([m["L"].values for m in mats])
     B = np.concatenate([m["B"].ravel() for m in mats])
     G = np.concatenate([m["G"].ravel() for m in mats])
@@ -41,10 +42,11 @@ def split_vals(vec, mats):
     return out
 
 
+@pytest.mark.parametrize("path", [0, 1])  # per-level launches (default), one persistent launch
 @pytest.mark.parametrize("nmat,n_lo,n_hi", [(6, 300, 3000), (24, 1000, 20000)])
-def test_batch_forward_adjoint(nmat, n_lo, n_hi):
-    print(f"batch nmat={nmat}", flush=True)
-    mats, plan, vals, B, G = make_batch(nmat, n_lo, n_hi)
+def test_batch_forward_adjoint(nmat, n_lo, n_hi, path):
+    print(f"batch nmat={nmat} path={path}", flush=True)
+    mats, plan, vals, B, G = make_batch(nmat, n_lo, n_hi, path)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
     dv, db, dg = d(vals), d(B), d(G)
     dx = torch.full_like(db, np.nan)
@@ -73,8 +75,10 @@ def test_batch_forward_adjoint(nmat, n_lo, n_hi):
         check_gv_solve(m["L"], ref, gb, GB, gv, GV)
 
 
-def test_graph_replays():
-    mats, plan, vals, B, G = make_batch(8, 500, 5000)
+@pytest.mark.parametrize("path", [0, 1])
+def test_graph_replays(path):
+    print(f"graph replays path={path}", flush=True)
+    mats, plan, vals, B, G = make_batch(8, 500, 5000, path)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
     dv, db = d(vals), d(B)
     direct = torch.empty_like(db)
