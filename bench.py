@@ -1,7 +1,10 @@
 """Benchmark of the DDF hot path on one MI355X.
 
 One step = SpMV forward, SpMV adjoint (A^T g and dA), SpTRSV forward and SpTRSV adjoint
-(L^T lambda = g and dL) on one synthetic workload, FP64, inputs resident in HBM.  The value is
+(L^T lambda = g and dL) on one synthetic workload, FP64, inputs resident in HBM.  The
+adjoint's transposed solve does not need the forward solution, so it runs on a second stream
+beside the other calls; its value gradient waits for the forward solve.  The serial step time
+is reported too.  The value is
 whole-step effective HBM bandwidth: the algorithmic bytes of the four calls (values, plan
 tables, vectors read once and written once; see ddf_plan_traffic) divided by the step time.
 The plain GPU comparators (CSR-vector SpMV, FP64-atomic adjoint, one launch per level) are
@@ -45,19 +48,25 @@ def log(*a):
 
 
 def kernels_sha():
-    p = os.path.join(ROOT, "paper_2111_12243_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:12]
+    """Digest of the library's sources (kernels and the schedules that drive them)."""
+    d = os.path.join(ROOT, "paper_2111_12243_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:12]
 
 
-def traffic_from_profiles(kernel, workload):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, when it was taken on the
-    current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+def traffic_from_profiles(op, workload):
+    """HBM bytes per call (every kernel the call launches) from a committed rocprofv3 counter
+    summary, when it was taken on the current library sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{op}_{workload}.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m_sha = re.search(r"kernels_hip_sha:\s*(\w+)", txt)
-    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_sha = re.search(r"sources_sha:\s*(\w+)", txt)
+    m_b = re.search(r"hbm_bytes_per_call:\s*([0-9.eE+]+)", txt)
     if not m_sha or not m_b or m_sha.group(1) != kernels_sha():
         return None
     return float(m_b.group(1))
@@ -140,8 +149,10 @@ def main():
 
     if args.profile_op:
         # a leg per name, each run --steps times (rocprofv3 counter and trace runs); "copy" is
-        # an elementwise copy of 64 Mi doubles (512 MiB read, 512 MiB written) to scale counters
-        for name in args.profile_op.split(","):
+        # an elementwise copy of 64 Mi doubles (512 MiB read, 512 MiB written) to scale counters.
+        # A one-element fill ends each leg, so that a trace splits into legs at its fill kernels.
+        mark = torch.zeros(1, dtype=torch.float64, device=dev)
+        for leg, name in enumerate(args.profile_op.split(",")):
             if name == "copy":
                 src = torch.rand(1 << 26, dtype=torch.float64, device=dev)
                 dst = torch.empty_like(src)
@@ -150,6 +161,7 @@ def main():
                 fn = ops[name]
             for _ in range(args.steps):
                 fn()
+            mark.fill_(float(leg))
             torch.cuda.synchronize()
             log(f"[bench] ran {name} x{args.steps}")
         return
@@ -196,9 +208,43 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    # timed region: K whole steps, each call bracketed by events
+    # Each call's own duration: serial steps, each call bracketed by HIP events on the stream
+    # it launches on (overlapped calls would share the GPU and read slower one by one).
     op_ms = {}
-    ms = time_steps(ops, args.steps, args.warmup, op_ms)
+    ms_serial = time_steps(ops, args.steps, args.warmup, op_ms)
+    if pL is not None:
+        # timed region: K whole steps with the adjoint's transposed solve on a second stream
+        s_adj = torch.cuda.Stream()
+        ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+        def ddf_step():
+            s0 = torch.cuda.current_stream()
+            s_adj.wait_stream(s0)
+            with torch.cuda.stream(s_adj):
+                ddf.ddf_sptrsv_adjoint(pL, vL, None, Gx, GB, None, k)
+            ops["spmv"]()
+            ops["spmv_adj"]()
+            ops["sptrsv"]()
+            fwd = torch.cuda.Event()
+            fwd.record(s0)
+            s_adj.wait_event(fwd)
+            with torch.cuda.stream(s_adj):
+                ddf.ddf_sptrsv_value_grad(pL, Xs, GB, GVL, k)
+            s0.wait_stream(s_adj)
+
+        for _ in range(args.warmup):
+            ddf_step()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(args.steps):
+            ddf_step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        log(f"[bench] DDF step {ms:.3f} ms with the adjoint's solve on a second stream, {ms_serial:.3f} ms serial")
+    else:
+        ms = ms_serial
     if pL is not None:
         ddf.ddf_plan_sync_status(pL)
     log(f"[bench] DDF step {ms:.3f} ms")
@@ -240,10 +286,10 @@ def main():
     dom = max(per_op, key=lambda n: per_op[n]["ms"])
     kname = kernel_of[dom]
     ach = traffic[dom][0] / (per_op[dom]["ms"] / 1e3) / 1e9
-    hbm = traffic_from_profiles(f"{kname}_{dom}", args.workload)
+    hbm = traffic_from_profiles(dom, args.workload)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach / PEAK_GBPS, 4),
-                "traffic": hbm, "kernel": f"{kname} ({dom})", "bytes_alg_per_launch": traffic[dom][0]}
+                "traffic": hbm, "kernel": f"{dom} call (main kernel {kname})", "bytes_alg_per_call": traffic[dom][0]}
 
     cpu = None
     if not args.no_cpu:
@@ -269,7 +315,7 @@ def main():
         "metric": "SpMV/SpTRSV fwd+adjoint effective HBM GB/s and % of peak vs plain, FP64",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64", "data": "synthetic", "ms_per_step_serial": round(ms_serial, 4),
         "config": {"workload": w.name, "n": A.n_rows, "nnz_A": A.nnz, "nnz_L": L.nnz if L is not None else 0,
                    "levels": info_L.get("n_parts", 0), "nrhs": k,
                    "solve_kernel": {"fwd": kernel_of.get("sptrsv"), "adj": kernel_of.get("sptrsv_adj")},
@@ -385,9 +431,13 @@ def bench_batch(args, np, torch, ddf, I, dev):
         off += n * k
     dom = max(per_op, key=lambda n: per_op[n]["ms"])
     ach = traffic[dom][0] / (op_ms[dom] / 1e3) / 1e9
+    binfo = ddf.ddf_plan_info(p)
+    bkey = "solve_path_adj" if dom.endswith("adj") else "solve_path"
+    bnames = {1: "k_solve", 2: "k_solve_thin", 3: "k_solve_range"}
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBPS, "unit": "GB/s",
-                "frac": round(ach / PEAK_GBPS, 4), "traffic": None, "kernel": f"k_solve ({dom})",
-                "bytes_alg_per_launch": traffic[dom][0]}
+                "frac": round(ach / PEAK_GBPS, 4), "traffic": None,
+                "kernel": f"{dom} call (main kernel {bnames.get(binfo.get(bkey), 'k_solve')})",
+                "bytes_alg_per_call": traffic[dom][0]}
     cpu = None
     if not args.no_cpu:
         t0 = time.time()

@@ -18,8 +18,9 @@
  *  - Outputs are overwritten (y = A x, never y += A x).
  *  - Execution calls are asynchronous on `stream` (a hipStream_t, NULL = default stream),
  *    allocate nothing, and copy nothing synchronously, so they may be captured in a graph.
- *    One execution per plan may be in flight at a time: the plan's scratch (level
- *    counters) is shared by its calls.
+ *    Per plan, one forward call (SpMV, solve) and one adjoint call (ddf_spmv_adjoint,
+ *    ddf_sptrsv_adjoint, ddf_sptrsv_value_grad) may be in flight at a time, on any
+ *    streams: the solves' scratch (level counters, per-call streams) is per direction.
  *  - Arguments are validated before any launch.  On an error no kernel is launched,
  *    outputs are untouched, and ddf_last_error() holds a message (thread-local).
  *  - A zero diagonal is not an error: it gives inf/nan by IEEE rules.
@@ -192,7 +193,8 @@ ddf_status ddf_sptrsv_v(ddf_plan_t plan, const double *d_vals, const double *d_b
 /* SpMV adjoint for upstream d_gy = dLoss/dY (n_rows, nrhs):
  *   d_gx    (n_cols, nrhs) = A^T G   (transposed plan, deterministic, no atomics)
  *   d_gvals [nnz]          = sum_r G[i,r] X[col,r]  (dLoss/dA_ij = g_i x_j)
- * Either output may be NULL.  Both passes run in one launch.  Needs build_adjoint. */
+ * Either output may be NULL.  Two launches: the value gradient over the CSR pattern, then the
+ * transposed product.  Needs build_adjoint. */
 ddf_status ddf_spmv_adjoint(ddf_plan_t plan, const double *d_vals, const double *d_x,
                             const double *d_gy, double *d_gx, double *d_gvals, int32_t nrhs,
                             ddf_stream_t stream);
@@ -200,10 +202,20 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t plan, const double *d_vals, const double 
 /* SpTRSV adjoint for upstream d_gx = dLoss/dX, given the forward solution d_x:
  *   d_gb    (n, nrhs) = Lam with L^T Lam = G   (reverse-level plan of L^T)
  *   d_gvals [nnz]     = -sum_r Lam[i,r] X[col,r] for every stored entry incl. the diagonal
- * d_gvals may be NULL.  One persistent launch.  Needs build_adjoint. */
+ * d_gvals may be NULL (then d_x is not read).  The transposed solve, then the value gradient
+ * over the CSR pattern of L.  Needs build_adjoint. */
 ddf_status ddf_sptrsv_adjoint(ddf_plan_t plan, const double *d_vals, const double *d_x,
                               const double *d_gx, double *d_gb, double *d_gvals, int32_t nrhs,
                               ddf_stream_t stream);
+
+/* The value gradient of the SpTRSV adjoint alone (the second half of ddf_sptrsv_adjoint),
+ * from d_gb = Lam (n, nrhs) and the forward solution d_x (n, nrhs):
+ *   d_gvals [nnz] = -sum_r Lam[i,r] X[col,r] for every stored entry of L incl. the diagonal.
+ * With ddf_sptrsv_adjoint(..., d_gvals = NULL) before it, the adjoint's transposed solve no
+ * longer depends on the forward solve, so the two can run on different streams.  Single
+ * plans (not batches) built with build_adjoint; d_gvals must not overlap d_gb or d_x. */
+ddf_status ddf_sptrsv_value_grad(ddf_plan_t plan, const double *d_x, const double *d_gb, double *d_gvals,
+                                 int32_t nrhs, ddf_stream_t stream);
 
 /* Batched forms (plan from ddf_inspect_batch; nrhs per matrix fixed at inspect time).
  * d_vals_packed may be NULL to use the values captured at inspect time. */

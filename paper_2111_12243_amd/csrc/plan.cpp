@@ -43,7 +43,8 @@ struct ddf_plan_s {
     DevTables F, T, Fpm;
     std::vector<int64_t> pm_task_ptr; // per-matrix ranges of Fpm.tasks
     int64_t n_solve_tasks_adj = 0;    // adjoint: tasks before the GV pass
-    int64_t ctr_words = 0;            // allocated counter words
+    int64_t ctr_words_f = 0;          // counter words of the forward solves
+    int64_t ctr_words_a = 0;          // and of the adjoint's (after them, in the same allocation)
     int64_t n_gx_tasks = 0;           // SpMV adjoint: tasks before the GV pass (one RHS)
     int64_t n_gx_tasksN = 0;          // same, several right-hand sides
     std::vector<int32_t> gv_chunks;   // value gradient: (row, first entry) per chunk of a long row
@@ -53,7 +54,8 @@ struct ddf_plan_s {
     int32_t *d_perm = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_rpT = nullptr, *d_ciT = nullptr;
     int32_t *d_rows = nullptr, *d_rrows = nullptr;
     MatInfo *d_mats = nullptr;
-    unsigned *d_ctr = nullptr;
+    unsigned *d_ctr = nullptr;        // forward solves' counters, progress words and error flag
+    unsigned *d_ctr_adj = nullptr;    // the adjoint's own (a forward and an adjoint may overlap)
     int64_t spin_limit = int64_t(1) << 26;
     double inspect_seconds = 0;
     uint64_t hash = 0;
@@ -728,14 +730,17 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
 // schedule.  Grown (never shrunk) when a schedule needs more.
 ddf_status ensure_counters(ddf_plan_t p) {
     if (p->host_only || p->kind == DDF_SPMV) return DDF_OK;
-    const int64_t need = (2 + std::max({p->F.n_counters, p->T.n_counters, p->Fpm.n_counters})) * CTR_STRIDE;
-    if (need <= p->ctr_words) return DDF_OK;
+    const int64_t nf = std::max(p->ctr_words_f, (2 + std::max(p->F.n_counters, p->Fpm.n_counters)) * CTR_STRIDE);
+    const int64_t na = std::max(p->ctr_words_a, (2 + p->T.n_counters) * CTR_STRIDE);
+    if (p->d_ctr && nf <= p->ctr_words_f && na <= p->ctr_words_a) return DDF_OK;
     drop_alloc(p, p->d_ctr);
-    p->d_ctr = nullptr;
-    if (ddf_status s = dalloc(p, (void **)&p->d_ctr, need * sizeof(unsigned))) return s;
-    if (hipError_t e = hipMemset(p->d_ctr, 0, need * sizeof(unsigned)))
+    p->d_ctr = p->d_ctr_adj = nullptr;
+    if (ddf_status s = dalloc(p, (void **)&p->d_ctr, (nf + na) * sizeof(unsigned))) return s;
+    if (hipError_t e = hipMemset(p->d_ctr, 0, (nf + na) * sizeof(unsigned)))
         return fail(DDF_E_HIP, std::string("hipMemset: ") + hipGetErrorString(e));
-    p->ctr_words = need;
+    p->d_ctr_adj = p->d_ctr + nf;
+    p->ctr_words_f = nf;
+    p->ctr_words_a = na;
     return DDF_OK;
 }
 
@@ -883,8 +888,9 @@ ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, 
     t.b = b;
     t.x = x;
     t.stream = D.d_thin_stream;
-    t.progress = p->d_ctr + CTR_STRIDE + 16; // second counter line: error flag, then these
-    t.sink = p->d_ctr + CTR_STRIDE + 17;
+    unsigned *ctr = &D == &p->T ? p->d_ctr_adj : p->d_ctr;
+    t.progress = ctr + CTR_STRIDE + 16; // second counter line: error flag, then these
+    t.sink = ctr + CTR_STRIDE + 17;
     HIPCHK(launch_solve_thin(t, D.thin_ngs, s));
     return DDF_OK;
 }
@@ -1119,7 +1125,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.x = x;
     a.xf = xf;
     a.gv = gv;
-    a.ctr = p->d_ctr;
+    a.ctr = adj ? p->d_ctr_adj : p->d_ctr;
     a.spin_limit = p->spin_limit;
     a.k_override = k_override;
     if (sp.path == 3) {
@@ -1140,7 +1146,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
         }
         return DDF_OK;
     }
-    HIPCHK(launch_reset(p->d_ctr, (2 + ncounters) * CTR_STRIDE, s));
+    HIPCHK(launch_reset(a.ctr, (2 + ncounters) * CTR_STRIDE, s));
     HIPCHK(launch_solve(a, adj, kt, sp.blocks, s));
     return DDF_OK;
 }
@@ -1349,6 +1355,21 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
         return st;
     }
     if (d_gvals) HIPCHK(launch_gv_pass(p, d_gb, d_x, d_gvals, -1.0, nrhs, s));
+    return DDF_OK;
+}
+
+ddf_status ddf_sptrsv_value_grad(ddf_plan_t p, const double *d_x, const double *d_gb, double *d_gvals,
+                                 int32_t nrhs, ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPTRSV_LOWER || p->batch) return fail(DDF_E_KIND, "plan is not a single-matrix SpTRSV plan");
+    if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    const int64_t nb = p->n_rows * nrhs * 8;
+    if ((!d_x || !d_gb || !d_gvals) && p->n_rows) return fail(DDF_E_ARG, "NULL buffer");
+    if (overlap(d_gvals, p->nnz * 8, d_gb, nb) || overlap(d_gvals, p->nnz * 8, d_x, nb))
+        return fail(DDF_E_ARG, "gvals overlaps another buffer");
+    if (p->n_rows == 0) return DDF_OK;
+    HIPCHK(launch_gv_pass(p, d_gb, d_x, d_gvals, -1.0, nrhs, (hipStream_t)stream));
     return DDF_OK;
 }
 
@@ -1717,14 +1738,18 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
 ddf_status ddf_plan_sync_status(ddf_plan_t p, ddf_stream_t stream) {
     if (ddf_status s = need_device(p)) return s;
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
-    unsigned flag = 0;
     if (!p->d_ctr) return DDF_OK;
-    HIPCHK(hipMemcpy(&flag, p->d_ctr + CTR_STRIDE, sizeof(unsigned), hipMemcpyDeviceToHost));
-    if (flag) {
-        unsigned z = 0;
-        HIPCHK(hipMemcpy(p->d_ctr + CTR_STRIDE, &z, sizeof(unsigned), hipMemcpyHostToDevice));
-        return fail(DDF_E_DEVICE, "a level wait exceeded its spin limit");
+    bool tripped = false;
+    for (unsigned *c : {p->d_ctr, p->d_ctr_adj}) {
+        unsigned flag = 0;
+        HIPCHK(hipMemcpy(&flag, c + CTR_STRIDE, sizeof(unsigned), hipMemcpyDeviceToHost));
+        if (flag) {
+            unsigned z = 0;
+            HIPCHK(hipMemcpy(c + CTR_STRIDE, &z, sizeof(unsigned), hipMemcpyHostToDevice));
+            tripped = true;
+        }
     }
+    if (tripped) return fail(DDF_E_DEVICE, "a level wait exceeded its spin limit");
     return DDF_OK;
 }
 

@@ -25,7 +25,7 @@ STATUS = ["DDF_OK", "DDF_E_ARG", "DDF_E_CSR", "DDF_E_NOT_LOWER", "DDF_E_NO_DIAG"
 
 EXPORTED = [
     "ddf_opts_default", "ddf_inspect", "ddf_inspect_batch", "ddf_plan_destroy", "ddf_spmv",
-    "ddf_spmv_v", "ddf_sptrsv", "ddf_sptrsv_v", "ddf_spmv_adjoint", "ddf_sptrsv_adjoint",
+    "ddf_spmv_v", "ddf_sptrsv", "ddf_sptrsv_v", "ddf_spmv_adjoint", "ddf_sptrsv_adjoint", "ddf_sptrsv_value_grad",
     "ddf_sptrsv_batch", "ddf_sptrsv_batch_adjoint", "ddf_graph_create_batch", "ddf_graph_launch",
     "ddf_graph_destroy", "ddf_plain_spmv", "ddf_plain_sptrsv", "ddf_plain_spmv_adjoint",
     "ddf_plain_sptrsv_adjoint", "ddf_sptrsv_batch_per_matrix", "ddf_autotune", "ddf_plan_info",
@@ -105,6 +105,7 @@ def lib():
             "ddf_sptrsv_v": (I32, [P, P, P, P, I32, P]),
             "ddf_spmv_adjoint": (I32, [P, P, P, P, P, P, I32, P]),
             "ddf_sptrsv_adjoint": (I32, [P, P, P, P, P, P, I32, P]),
+            "ddf_sptrsv_value_grad": (I32, [P, P, P, P, I32, P]),
             "ddf_sptrsv_batch": (I32, [P, P, P, P, P]),
             "ddf_sptrsv_batch_adjoint": (I32, [P, P, P, P, P, P, P]),
             "ddf_graph_create_batch": (I32, [P, I32, P, P, P, P, P, C.POINTER(P)]),
@@ -252,6 +253,10 @@ def ddf_spmv_adjoint(plan, vals, x, gy, gx, gvals, nrhs, stream=None):
 def ddf_sptrsv_adjoint(plan, vals, x, gx, gb, gvals, nrhs, stream=None):
     _check(lib().ddf_sptrsv_adjoint(plan.handle, _ptr(vals), _ptr(x), _ptr(gx), _ptr(gb), _ptr(gvals),
                                     nrhs, _stream(stream)))
+
+
+def ddf_sptrsv_value_grad(plan, x, gb, gvals, nrhs, stream=None):
+    _check(lib().ddf_sptrsv_value_grad(plan.handle, _ptr(x), _ptr(gb), _ptr(gvals), nrhs, _stream(stream)))
 
 
 def ddf_sptrsv_batch(plan, vals, b, x, stream=None):

@@ -90,6 +90,7 @@ def test_host_only_plan_refuses_execution():
     p = ddf.ddf_inspect(1, I.random_lower(10, 2), hopts())
     expect(ddf.DDF_E_UNSUPPORTED, lambda: ddf.ddf_sptrsv_v(p, 0, 0, 0, 1, 0))
     expect(ddf.DDF_E_UNSUPPORTED, lambda: ddf.ddf_spmv_v(p, 0, 0, 0, 1, 0))
+    expect(ddf.DDF_E_UNSUPPORTED, lambda: ddf.ddf_sptrsv_value_grad(p, 0, 0, 0, 1, 0))
     q = ddf.ddf_inspect(0, I.random_csr(8, 8, 1), ddf.ddf_opts_default(host_only=1, build_adjoint=0))
     expect(ddf.DDF_E_UNSUPPORTED, lambda: ddf.ddf_plan_export(q, 1))
     info = ddf.ddf_plan_info(p)

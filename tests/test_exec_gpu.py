@@ -253,3 +253,37 @@ def test_graph_capture_step(path):
             assert np.array_equal(host(got), want), f"replay {rep}"
         step()  # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("path", [1, 2, 3])
+def test_forward_and_adjoint_on_two_streams(path):
+    # the adjoint's transposed solve runs on a second stream while the forward solve runs;
+    # its value gradient waits for the forward solution.  Same bits as the serial calls.
+    print(f"two-stream forward and adjoint, solve path {path}", flush=True)
+    w = I.c2_stencil27_offband(nx=24)
+    L = w.L
+    plan = ddf.ddf_inspect(1, L, ddf.ddf_opts_default(solve_path=path))
+    vals, b, g = dev(L.values), dev(rnd((L.n_rows, 1), 7)), dev(rnd((L.n_rows, 1), 8))
+    x, gb = torch.empty_like(b), torch.empty_like(b)
+    gv = torch.empty(L.nnz, dtype=torch.float64, device=DEV)
+    ddf.ddf_sptrsv_v(plan, vals, b, x, 1)
+    ddf.ddf_sptrsv_adjoint(plan, vals, x, g, gb, gv, 1)
+    ref = (host(x).copy(), host(gb).copy(), host(gv).copy())
+    for rep in range(2):
+        x2, gb2 = torch.full_like(b, np.nan), torch.full_like(b, np.nan)
+        gv2 = torch.full_like(gv, np.nan)
+        torch.cuda.synchronize()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        with torch.cuda.stream(s1):
+            ddf.ddf_sptrsv_v(plan, vals, b, x2, 1)
+            done = torch.cuda.Event()
+            done.record(s1)
+        with torch.cuda.stream(s2):
+            ddf.ddf_sptrsv_adjoint(plan, vals, None, g, gb2, None, 1)
+            s2.wait_event(done)
+            ddf.ddf_sptrsv_value_grad(plan, x2, gb2, gv2, 1)
+        torch.cuda.synchronize()
+        ddf.ddf_plan_sync_status(plan)
+        for got, want in zip((x2, gb2, gv2), ref):
+            assert np.array_equal(host(got), want), f"rep {rep}"
