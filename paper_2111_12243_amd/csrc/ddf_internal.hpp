@@ -103,7 +103,7 @@ struct DevTables {
     int32_t thin_ngs = 0;              // op slots per lane that may hold a global operand
     int32_t thin_block = 64;           // threads of the solving block (widest level, rounded to 64)
     double *d_thin_xs = nullptr;       // solutions in solve order
-    int32_t *d_thin_rec = nullptr;
+    int32_t *d_thin_gidx = nullptr;    // per-call gather index (the records stay on the host)
     int32_t *d_thin_lvl = nullptr;
     int32_t *d_thin_rows = nullptr;
     double *d_thin_stream = nullptr;   // per-call stream, THIN_SW doubles per record
@@ -116,7 +116,11 @@ struct DevTables {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
                (int64_t)tasks.size() * sizeof(Task) + (int64_t)sync.size() * 4;
     }
-    int64_t thin_bytes() const { return (int64_t)(thin_rec.size() + thin_lvl.size() + thin_rows.size()) * 4; }
+    // plan bytes a single-block solve reads per call: gather index (6 int32 per record of 20),
+    // level table, rows
+    int64_t thin_bytes() const {
+        return ((int64_t)thin_rec.size() / 20 * 6 + (int64_t)thin_lvl.size() + (int64_t)thin_rows.size()) * 4;
+    }
     // bytes a launch reads: records and aux (upper bound) plus its own task list
     int64_t launch_bytes(bool many_rhs) const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +

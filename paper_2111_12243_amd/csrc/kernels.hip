@@ -1021,14 +1021,10 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
     }
 }
 
-// Per-call gather, in record order, of each slot's operand codes, values (0 for empty slots),
-// the reciprocal of the diagonal and b.  Also clears the solver's progress word before the solve starts.
-__global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
+// Once per upload: each slot's stream code (an LDS byte offset, or a global operand), and the
+// chunk of empty records, codes and values.
+__global__ __launch_bounds__(256) void k_thin_codes(ThinArgs a) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p == 0) {
-        *a.progress = 0u;
-        a.xs[a.n] = 0.0; // read by gathers of slots without a global operand
-    }
     if (p >= a.n_rec + 64) return;
     double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
     const int zero = (a.ring + 1) * 8; // LDS byte offset of the zero entry
@@ -1040,31 +1036,43 @@ __global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
         *reinterpret_cast<int4 *>(w + 384) = make_int4(0, 0, zero, 0);
         return;
     }
-    // the record as five 16-byte loads: header, value indices 0-3, index 4 and columns 0-2,
-    // columns 3-4 and codes 0-1, codes 2-4 and the wide flag
-    const int4 *q = reinterpret_cast<const int4 *>(a.rec + p * THIN_REC);
-    const int4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
     static_assert(THIN_REC == 20 && THIN_SLOTS == 5, "record layout");
-    const int32_t r[THIN_REC] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y,
-                                 q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z, q4.w};
-    const int row = r[0], dpos = r[1];
-    const int32_t *vi = r + 4, *co = r + 4 + 2 * THIN_SLOTS;
-    const int64_t rb = (int64_t)row * a.k;
-    // every slot over the diagonal: the right-hand-side term's value is b
-    const double d = a.vals[dpos];
-    double v[THIN_SLOTS];
+    const int32_t *co = a.rec + p * THIN_REC + 4 + 2 * THIN_SLOTS;
     int code[THIN_SLOTS];
 #pragma unroll
     for (int j = 0; j < THIN_SLOTS; j++) {
-        const int c = co[j];
-        v[j] = c == THIN_UNUSED ? 0.0 : (vi[j] == THIN_VIDX_B ? a.b[rb] : a.vals[vi[j]]) / d;
         // table codes: >= 0 global solve-order index, THIN_UNUSED empty, else -(1 + LDS entry)
+        const int c = co[j];
         code[j] = c >= 0 ? ~c : c == THIN_UNUSED ? zero : ~c * 8;
     }
     *reinterpret_cast<int4 *>(w) = make_int4(code[0], code[1], code[2], code[3]);
+    *reinterpret_cast<int2 *>(w + 385) = make_int2(code[4], 0);
+}
+
+// Per call, in record order: each slot's value over the row's diagonal (0 for empty slots, b
+// for the right-hand-side term); the codes stay.  Also clears the solver's progress word.
+__global__ __launch_bounds__(256) void k_thin_stream(ThinArgs a) {
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x, a.remap) * 256 + threadIdx.x;
+    if (p == 0) {
+        *a.progress = 0u;
+        a.xs[a.n] = 0.0; // read by gathers of slots without a global operand
+    }
+    if (p >= a.n_rec) return;
+    const int32_t *g = a.gidx + (p >> 6) * (64 * THIN_GIDX);
+    const int4 g4 = reinterpret_cast<const int4 *>(g)[p & 63];
+    const int2 g2 = reinterpret_cast<const int2 *>(g + 64 * 4)[p & 63];
+    const int32_t vi[THIN_SLOTS] = {g4.x, g4.y, g4.z, g4.w, g2.x};
+    const double d = a.vals[g2.y];
+    double v[THIN_SLOTS];
+#pragma unroll
+    for (int j = 0; j < THIN_SLOTS; j++) {
+        const int32_t i = vi[j];
+        v[j] = i == THIN_UNUSED ? 0.0 : (i < 0 ? a.b[(int64_t)(-2 - i) * a.k] : a.vals[i]) / d;
+    }
+    double *w = a.stream + (p >> 6) * (64 * THIN_SW) + (p & 63) * 2;
     *reinterpret_cast<double2 *>(w + 128) = make_double2(v[0], v[1]);
     *reinterpret_cast<double2 *>(w + 256) = make_double2(v[2], v[3]);
-    *reinterpret_cast<int4 *>(w + 384) = make_int4(__double2loint(v[4]), __double2hiint(v[4]), code[4], 0);
+    w[384] = v[4];
 }
 
 // Solutions from solve order into row order.
@@ -1361,7 +1369,7 @@ template <int NGS> static void launch_thin_lg(const ThinArgs &a, dim3 grid, dim3
 
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     if (a.nlev == 0) return hipSuccess;
-    const dim3 sgrid((unsigned)((a.n_rec + 64 + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
+    const dim3 sgrid((unsigned)((a.n_rec + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
     hipLaunchKernelGGL(k_thin_stream, sgrid, pblock, 0, s, a);
     const dim3 grid(1 + 8 * (unsigned)a.helpers), block((unsigned)a.block);
     if (ngs == 0) launch_thin_lg<0>(a, grid, block, s);
@@ -1370,6 +1378,11 @@ hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     else if (ngs == 3) launch_thin_lg<3>(a, grid, block, s);
     else launch_thin_lg<THIN_SLOTS>(a, grid, block, s);
     hipLaunchKernelGGL(k_thin_scatter, rgrid, pblock, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_thin_codes(const ThinArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_thin_codes, dim3((unsigned)((a.n_rec + 64 + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

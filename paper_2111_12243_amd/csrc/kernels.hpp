@@ -51,11 +51,18 @@ struct SpmvArgs {
 // a level.  A stream code is the byte offset in LDS of the slot's operand: a ring slot, the
 // entry past the ring (-1, right-hand-side terms) or the one after it (0, empty slots); in the
 // first `ngs` slots a global operand is coded -(1 + its solve-order index) instead, and the
-// other codes there also gather the zero kept past the solutions.  The solve writes solutions
-// in solve order, and a scatter puts them in row order.  One right-hand side.
+// other codes there also gather the zero kept past the solutions.  The codes and the empty
+// chunk do not change between calls: they are written once, when the tables are uploaded, from
+// the records, which are then released.  Per call only the values are gathered, driven by a
+// compact index table of THIN_GIDX int32 per record, per 64-record chunk the value indices of
+// slots 0-3 (an int4 per record), then slot 4's and the diagonal's (an int2 per record); a slot
+// index is the value index, THIN_UNUSED for an empty slot, or -(2 + row) for the
+// right-hand-side term.  The solve writes solutions in solve order, and a scatter puts them in
+// row order.  One right-hand side.
 constexpr int THIN_SLOTS = 5;
 constexpr int THIN_REC = 20;
 constexpr int THIN_SW = 8;                  // stream doubles per record
+constexpr int THIN_GIDX = 6;                // gather-index int32 per record
 constexpr int32_t THIN_VIDX_B = -1;         // value index of the right-hand-side term
 constexpr int THIN_THREADS = 1024;
 constexpr int THIN_KT_MAX = 1;              // right-hand sides the single-block kernel takes
@@ -64,7 +71,9 @@ constexpr double THIN_SIMD_FIXED = 3.5;   // per-level fixed cost over one wave'
 constexpr int THIN_HORIZON = 3;           // a global operand's row was solved this many levels before
 constexpr int32_t THIN_UNUSED = (int32_t)0x80000000;
 struct ThinArgs {
-    const int32_t *rec;
+    const int32_t *rec;  // records (only while the codes are written at upload)
+    const int32_t *gidx; // gather index table, THIN_GIDX int32 per record
+    int32_t remap;       // XCD-contiguous record ranges in the gather
     const int4 *lvl; // per level: first record, lanes in use, first solve index, wide rows
                      // (padded with empty levels)
     const int32_t *rows; // row of each solve-order index
@@ -163,6 +172,7 @@ hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t 
 int num_cu();
 hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s);
+hipError_t launch_thin_codes(const ThinArgs &a, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
 hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s);

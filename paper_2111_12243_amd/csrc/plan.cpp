@@ -848,14 +848,41 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
 ddf_status upload_tables(ddf_plan_t p, DevTables &D) {
     if (ddf_status s = upload(p, &D.d_cods, D.cods.data(), D.cods.size())) return s;
     if (!D.thin_rec.empty()) {
-        if (ddf_status s = upload(p, &D.d_thin_rec, D.thin_rec.data(), D.thin_rec.size())) return s;
+        const int64_t n_rec = (int64_t)D.thin_rec.size() / THIN_REC; // a multiple of 64
+        // gather index: per 64-record chunk, slots 0-3 (int4 per record), then slot 4 and the
+        // diagonal (int2 per record); a slot holds its value index, THIN_UNUSED, or -(2 + row)
+        // for the right-hand-side term
+        std::vector<int32_t> gidx((size_t)n_rec * THIN_GIDX);
+        for (int64_t q = 0; q < n_rec; q++) {
+            const int32_t *r = &D.thin_rec[(size_t)q * THIN_REC];
+            int32_t *g = &gidx[(size_t)(q / 64) * 64 * THIN_GIDX];
+            const int l = (int)(q % 64);
+            for (int j = 0; j < THIN_SLOTS; j++) {
+                const int32_t code = r[4 + 2 * THIN_SLOTS + j], vi = r[4 + j];
+                const int32_t e = code == THIN_UNUSED ? THIN_UNUSED : vi == THIN_VIDX_B ? -2 - r[0] : vi;
+                if (j < 4) g[l * 4 + j] = e;
+                else g[64 * 4 + l * 2] = e;
+            }
+            g[64 * 4 + l * 2 + 1] = r[1];
+        }
+        if (ddf_status s = upload(p, &D.d_thin_gidx, gidx.data(), gidx.size())) return s;
         if (ddf_status s = upload(p, &D.d_thin_lvl, D.thin_lvl.data(), D.thin_lvl.size())) return s;
         if (ddf_status s = upload(p, &D.d_thin_rows, D.thin_rows.data(), D.thin_rows.size())) return s;
-        if (ddf_status s = dalloc(p, (void **)&D.d_thin_stream,
-                                  (D.thin_rec.size() / THIN_REC + 64) * THIN_SW * sizeof(double)))
-            return s;
+        if (ddf_status s = dalloc(p, (void **)&D.d_thin_stream, (n_rec + 64) * THIN_SW * sizeof(double))) return s;
         // solutions in solve order, and one zero that gathers of slots without a global operand read
         if (ddf_status s = dalloc(p, (void **)&D.d_thin_xs, (D.thin_rows.size() + 1) * sizeof(double))) return s;
+        // the stream's codes, written once from the records (on the null stream, then released)
+        int32_t *d_rec = nullptr;
+        if (ddf_status s = upload(p, &d_rec, D.thin_rec.data(), D.thin_rec.size())) return s;
+        ThinArgs t{};
+        t.rec = d_rec;
+        t.n_rec = n_rec;
+        t.ring = D.thin_ring;
+        t.stream = D.d_thin_stream;
+        hipError_t e = launch_thin_codes(t, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        drop_alloc(p, d_rec);
+        HIPCHK(e);
     }
     return upload(p, &D.d_aux, D.aux.data(), D.aux.size());
 }
@@ -868,7 +895,8 @@ bool use_thin(const DevTables &D, const SchedParams &sp, int32_t k) {
 ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, int nlev, const double *vals,
                        const double *b, double *x, int32_t k, hipStream_t s) {
     ThinArgs t{};
-    t.rec = D.d_thin_rec;
+    t.gidx = D.d_thin_gidx;
+    t.remap = &D == &p->T ? 1 : 0; // the transposed plan's value gathers reuse lines across nearby records
     t.lvl = reinterpret_cast<const int4 *>(D.d_thin_lvl);
     t.rows = D.d_thin_rows;
     t.nlev = nlev;
