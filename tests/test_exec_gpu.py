@@ -173,6 +173,16 @@ def test_random_sptrsv(seed):
     sptrsv_case(L, k, seed, opts, inplace=bool(seed % 3 == 0))
 
 
+@pytest.mark.parametrize("k", [4, 8])
+def test_value_gradient_vector_rhs(k):
+    # k = 4 and 8 take the value gradient's 16-byte loads over right-hand sides: rows of ~15
+    # entries, then rows past the chunked-row bound (256 entries), then a solve
+    for j, dens in enumerate((0.01, 0.25)):
+        A = I.random_csr(500, 1500, 70 + j, density=dens, empty_frac=0.1)
+        spmv_case(A, k, 70 + j, plain=False)
+    sptrsv_case(I.random_lower(700, 80 + k, density=0.05, runs=True), k, 80 + k, plain=False)
+
+
 # ---------------------------------------------------------------- scaled workloads
 
 def test_c2_scaled():
