@@ -133,7 +133,7 @@ typedef struct {
     int64_t codelets_by_type[3];                     /* BLAS, PSC I, PSC II */
     int64_t ops_by_type[3];
     int64_t n_tasks, n_tasks_adjoint;
-    int64_t dev_plan_bytes;     /* forward device tables: records + aux + tasks      */
+    int64_t dev_plan_bytes;     /* forward device tables: records + aux + tasks (solve schedules: + one 64-byte codelet copy per task) */
     int64_t dev_plan_bytes_adj; /* adjoint-pass device tables (0 if none)            */
     int32_t has_adjoint;
     int32_t max_levels;

@@ -110,11 +110,18 @@ struct DevTables {
     DCod *d_cods = nullptr;
     int32_t *d_aux = nullptr;
     Task *d_tasks = nullptr;
+    DCod *d_tcods = nullptr;           // solve: the codelet record of each task, in task order
     Task *d_tasksN = nullptr;
     int32_t *d_sync = nullptr;
+    // device bytes of the tables (solve schedules add the per-task codelet copy)
     int64_t bytes() const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
-               (int64_t)tasks.size() * sizeof(Task) + (int64_t)sync.size() * 4;
+               (int64_t)tasks.size() * (sizeof(Task) + (sync.empty() ? 0 : sizeof(DCod))) + (int64_t)sync.size() * 4;
+    }
+    // plan bytes a multi-block solve reads: each task, its codelet copy and its sync entry, and aux
+    int64_t solve_read_bytes() const {
+        return (int64_t)aux.size() * 4 + (int64_t)tasks.size() * (sizeof(Task) + sizeof(DCod)) +
+               (int64_t)sync.size() * 4;
     }
     // plan bytes a single-block solve reads per call: gather index (6 int32 per record of 20),
     // level table, rows

@@ -533,6 +533,12 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
 // ------------------------------------------------------------------------------------------
 constexpr int PE = LOOKAHEAD;
 
+// A single-matrix call's bases are zero: no load on the task's dependent chain for them.
+__device__ __forceinline__ MatInfo mat_info(const SolveArgs &a, const DCod &c) {
+    if (a.k_override > 0) return MatInfo{0, 0, 0, a.k_override, 0};
+    return a.mats[c.mat];
+}
+
 template <bool COH>
 __device__ __forceinline__ double xload(const double *p) {
     if constexpr (COH) return cload(p);
@@ -549,8 +555,8 @@ template <int KT, bool ADJ, bool COH>
 __device__ void solve_task(const SolveArgs &a, int t, int lane) {
     const Task tk = a.tasks[t];
     const int phase = (tk.meta >> 8) & 1;
-    const DCod c = load_cod((phase ? a.cods2 : a.cods) + tk.cod);
-    const MatInfo mi = a.mats[c.mat];
+    const DCod c = a.tcods ? a.tcods[t] : load_cod((phase ? a.cods2 : a.cods) + tk.cod);
+    const MatInfo mi = mat_info(a, c);
     const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
     const int slot = lane >> lg, g = lane & (G - 1);
     const int k = a.k_override > 0 ? a.k_override : mi.k;
@@ -661,8 +667,8 @@ __device__ __forceinline__ void pre_load(const SolveArgs &a, int t, int lane, Pr
     const Task tk = a.tasks[t];
     p.fast = (tk.meta >> 9) & 1;
     if (!p.fast) return;
-    const DCod c = load_cod(a.cods + tk.cod);
-    const MatInfo mi = a.mats[c.mat];
+    const DCod c = a.tcods ? a.tcods[t] : load_cod(a.cods + tk.cod);
+    const MatInfo mi = mat_info(a, c);
     p.lg = tk.meta & 7;
     p.k = a.k_override > 0 ? a.k_override : mi.k;
     p.vec_base = mi.vec_base;

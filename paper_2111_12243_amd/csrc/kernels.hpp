@@ -114,6 +114,7 @@ struct SolveArgs {
     const DCod *cods2; // phase 1 (adjoint): L's forward plan for the GV pass
     const int32_t *aux2;
     const Task *tasks;
+    const DCod *tcods; // the codelet of each task, in task order (loaded beside the task), or null
     const int4 *sync; // per task: counter to wait on (-1 none), count to wait for, counter to signal
     int32_t ntasks;
     int32_t backoff_max;

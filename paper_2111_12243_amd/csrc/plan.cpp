@@ -482,11 +482,25 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     drop_alloc(p, D.d_tasksN);
     drop_alloc(p, D.d_sync);
     drop_alloc(p, D.d_rowlist);
+    drop_alloc(p, D.d_tcods);
     D.d_tasks = nullptr;
     D.d_tasksN = nullptr;
     D.d_sync = nullptr;
     D.d_rowlist = nullptr;
+    D.d_tcods = nullptr;
     ddf_status s = upload(p, &D.d_tasks, D.tasks.data(), D.tasks.size());
+    if (!s && !D.sync.empty() && !D.tasks.empty()) {
+        // solve schedules: each task's codelet record in task order, so that a wave loads its
+        // task and its codelet side by side (phase-1 tasks of an adjoint are over L's forward
+        // plan)
+        std::vector<DCod> tc(D.tasks.size());
+        for (size_t i = 0; i < D.tasks.size(); i++) {
+            const Task &t = D.tasks[i];
+            const bool fwd_plan = &D == &p->T && ((t.meta >> 8) & 1);
+            tc[i] = (fwd_plan ? p->F.cods : (&D == &p->T ? p->T.cods : p->F.cods))[t.cod];
+        }
+        s = upload(p, &D.d_tcods, tc.data(), tc.size());
+    }
     if (!s && !D.rowlist.empty()) s = upload(p, &D.d_rowlist, D.rowlist.data(), D.rowlist.size());
     if (!s && !D.tasksN.empty()) s = upload(p, &D.d_tasksN, D.tasksN.data(), D.tasksN.size());
     if (!s && !D.sync.empty()) s = upload(p, &D.d_sync, D.sync.data(), D.sync.size());
@@ -1143,6 +1157,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.cods2 = p->F.d_cods;
     a.aux2 = p->F.d_aux;
     a.tasks = D.d_tasks + t0;
+    a.tcods = D.d_tcods ? D.d_tcods + t0 : nullptr;
     a.sync = reinterpret_cast<const int4 *>(D.d_sync) + t0;
     a.ntasks = (int32_t)ntasks;
     a.backoff_max = sp.backoff > 0 ? sp.backoff : 16;
@@ -1160,6 +1175,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
         // one launch per level (task ranges of equal level, over all matrices of a batch; the
         // GV tasks last)
         const Task *tk = a.tasks;
+        const DCod *tc = a.tcods;
         const int4 *sy = a.sync;
         int64_t i = 0;
         while (i < ntasks) {
@@ -1167,6 +1183,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
             int64_t j = i + 1;
             while (j < ntasks && D.sync[(t0 + j) * 4 + 3] == lev) j++;
             a.tasks = tk + i;
+            a.tcods = tc ? tc + i : nullptr;
             a.sync = sy + i;
             a.ntasks = (int32_t)(j - i);
             HIPCHK(launch_solve_range(a, adj, kt, s));
@@ -1699,7 +1716,7 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
     int64_t vk = p->batch ? p->vec_total : n * nrhs;      // sum of n_b k_b
     int64_t ck = p->batch ? p->vec_total : nc * nrhs;
     int64_t kf = p->batch ? 0 : nrhs;
-    int64_t Fca = (int64_t)p->F.cods.size() * sizeof(DCod) + (int64_t)p->F.aux.size() * 4;
+    int64_t Fca = (int64_t)p->F.aux.size() * 4; // the batch adjoint's GV tasks read L's forward aux
     const bool many = !p->batch && nrhs > 1;
     int64_t ba = 0, bc = 0, fl = 0;
     switch (op) {
@@ -1716,7 +1733,8 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
         break;
     case DDF_OP_SPTRSV:
-        ba = 8 * nnz + (!p->batch && use_thin(p->F, p->sp_f, nrhs) ? p->F.thin_bytes() : p->F.bytes()) + 16 * vk;
+        ba = 8 * nnz + (!p->batch && use_thin(p->F, p->sp_f, nrhs) ? p->F.thin_bytes() : p->F.solve_read_bytes()) +
+             16 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
         if (p->batch) {
             for (size_t b = 0; b < p->mats.size(); b++) {
@@ -1732,9 +1750,9 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         if (p->has_adj && !p->batch && use_thin(p->T, p->sp_a, nrhs))
             ba = 20 * nnz + p->T.thin_bytes() + 4 * (n + 1) + 24 * vk;
         else if (p->batch)
-            ba = 20 * nnz + (p->has_adj ? p->T.bytes() : 0) + Fca + 32 * vk;
+            ba = 20 * nnz + (p->has_adj ? p->T.solve_read_bytes() : 0) + Fca + 32 * vk;
         else
-            ba = 24 * nnz + (p->has_adj ? p->T.bytes() : 0) + 4 * (n + 1) + 32 * vk;
+            ba = 24 * nnz + (p->has_adj ? p->T.solve_read_bytes() : 0) + 4 * (n + 1) + 32 * vk;
         bc = 20 * nnz + 4 * (n + 1) + 24 * vk;
         if (p->batch) {
             for (size_t b = 0; b < p->mats.size(); b++) {
@@ -1750,8 +1768,8 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         if (!p->batch && use_thin(p->T, p->sp_a, nrhs))
             ba = 8 * nnz + p->T.thin_bytes() + 16 * vk;
         else
-            ba = 8 * nnz + (int64_t)p->T.cods.size() * sizeof(DCod) + (int64_t)p->T.aux.size() * 4 +
-                 p->n_solve_tasks_adj * (int64_t)(sizeof(Task) + 16) + 16 * vk;
+            ba = 8 * nnz + (int64_t)p->T.aux.size() * 4 +
+                 p->n_solve_tasks_adj * (int64_t)(sizeof(Task) + sizeof(DCod) + 16) + 16 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
         fl = p->batch ? 0 : kf * (2 * (nnz - n) + n);
         break;
