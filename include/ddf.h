@@ -283,14 +283,18 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
 typedef struct {
     const int32_t *cods, *aux, *tasks, *sync, *tasksN;
     int64_t n_cods, aux_len, n_tasks, n_counters, n_tasksN;
-    const int32_t *thin_rec; /* single-block solve: [n_thin_rec][20] per lane slot: row, value
+    const int32_t *thin_rec; /* single-block solve: [n_thin_rec][21] per lane slot: row, value
                                 index of the diagonal, ops, placeholder flag (levels start on
                                 64-record boundaries), value indices[5], columns[5],
                                 operand codes[5]: INT32_MIN empty; >= 0 solve-order index of
                                 a row read from global memory; -(1 + thin_ring_size) the
                                 row's right-hand-side term (value index -1, column the row);
+                                -(1 + e) with e >= thin_ring_size + 2 a pinned LDS entry e
+                                (a global operand past the lane's first two global slots);
                                 else -(1 + ring slot); then 0, or 1 / 2 for the first /
-                                second half of a row of 2G lanes                            */
+                                second half of a row of 2G lanes; then, in a row's first
+                                lane, the second LDS entry its solution is written to (its
+                                ring slot, or its pinned entry), -1 in other lanes          */
     const int32_t *thin_lvl; /* [n][4] first record, lane slots in use, first solve-order
                                 index, rows of 2G lanes, per level, then empty levels up to a
                                 multiple of 4 plus 4 (absent: n = 0)                        */

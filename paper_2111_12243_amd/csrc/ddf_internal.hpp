@@ -45,6 +45,10 @@ struct Canon {
     int64_t n_codelets() const { return header[7]; }
 };
 
+// Single-block solve: int32 per lane-slot record, and per record of the gather index.
+constexpr int THIN_REC = 21;
+constexpr int THIN_GIDX = 6;
+
 // Device codelet record: 16 x int32 = 64 bytes.
 struct DCod {
     int32_t flags, m, nn, row0, row_step, op0, op_step, col0;
@@ -101,6 +105,7 @@ struct DevTables {
     int32_t thin_nlev = 0;             // levels of the single-block solve (sub-levels included)
     int32_t thin_nlev_pad = 0;         // levels rounded up to a multiple of 4
     int32_t thin_ngs = 0;              // op slots per lane that may hold a global operand
+    int32_t thin_pins = 0;             // pinned LDS entries in use
     int32_t thin_block = 64;           // threads of the solving block (widest level, rounded to 64)
     double *d_thin_xs = nullptr;       // solutions in solve order
     int32_t *d_thin_gidx = nullptr;    // per-call gather index (the records stay on the host)
@@ -123,10 +128,10 @@ struct DevTables {
         return (int64_t)aux.size() * 4 + (int64_t)tasks.size() * (sizeof(Task) + sizeof(DCod)) +
                (int64_t)sync.size() * 4;
     }
-    // plan bytes a single-block solve reads per call: gather index (6 int32 per record of 20),
-    // level table, rows
+    // plan bytes a single-block solve reads per call: gather index, level table, rows
     int64_t thin_bytes() const {
-        return ((int64_t)thin_rec.size() / 20 * 6 + (int64_t)thin_lvl.size() + (int64_t)thin_rows.size()) * 4;
+        return ((int64_t)thin_rec.size() / THIN_REC * THIN_GIDX + (int64_t)thin_lvl.size() +
+                (int64_t)thin_rows.size()) * 4;
     }
     // bytes a launch reads: records and aux (upper bound) plus its own task list
     int64_t launch_bytes(bool many_rhs) const {

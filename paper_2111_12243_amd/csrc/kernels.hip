@@ -847,6 +847,7 @@ __device__ __forceinline__ int4 thin_lvl(const ThinArgs &a, int l) {
 template <int KT> struct ThinA {
     int code[THIN_SLOTS];
     double v[THIN_SLOTS]; // values over the diagonal
+    int pin;              // the writer's second LDS entry (byte offset)
 };
 template <int KT, int NGS> struct ThinB {
     double gx[NGS > 0 ? NGS : 1][KT]; // operands gathered from global memory
@@ -869,6 +870,7 @@ __device__ __forceinline__ void thin_fetch_a(const ThinArgs &a, int l, int s, Th
     const int4 v4c = *reinterpret_cast<const int4 *>(w + 384);
     t.code[0] = c.x; t.code[1] = c.y; t.code[2] = c.z; t.code[3] = c.w;
     t.code[4] = v4c.z;
+    t.pin = v4c.w;
     t.v[0] = v01.x; t.v[1] = v01.y; t.v[2] = v23.x; t.v[3] = v23.y;
     t.v[4] = __hiloint2double(v4c.y, v4c.x);
     static_assert(KT == 1, "one right-hand side");
@@ -886,7 +888,7 @@ __device__ __forceinline__ void thin_fetch_b(const ThinArgs &a, const ThinA<KT> 
     }
 }
 
-template <int KT, int NGS, int LG>
+template <int KT, int NGS, int LG, bool PIN>
 __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, const ThinA<KT> &t,
                                              const ThinB<KT, NGS> &u, double *ring) {
     constexpr int G = 1 << LG;
@@ -927,16 +929,17 @@ __device__ __forceinline__ void thin_compute(const ThinArgs &a, int l, int s, co
                 const double xn = -acc[rr]; // the slots sum to -(b - sum of ops) / diagonal
                 a.xs[rp * KT + rr] = xn;
                 ring[slot * KT + rr] = xn;
+                if constexpr (PIN) *reinterpret_cast<double *>(reinterpret_cast<char *>(ring) + t.pin) = xn;
             }
     }
 }
 
 // One level: solve it, then gather the global operands of the level two ahead and fetch the
 // stream entry of the level four ahead (into the slot this level used).
-template <int KT, int NGS, int LG>
+template <int KT, int NGS, int LG, bool PIN>
 __device__ __forceinline__ void thin_step(const ThinArgs &a, int l, int s, ThinA<KT> &a0, ThinB<KT, NGS> &b0,
                                           const ThinA<KT> &a2, double *ring) {
-    thin_compute<KT, NGS, LG>(a, l, s, a0, b0, ring);
+    thin_compute<KT, NGS, LG, PIN>(a, l, s, a0, b0, ring);
     __builtin_amdgcn_sched_barrier(0);
     thin_fetch_b<KT, NGS>(a, a2, b0);
     thin_fetch_a<KT>(a, l + 4, s, a0);
@@ -989,7 +992,7 @@ __device__ void thin_helper(const ThinArgs &a) {
     if (sink == 0x9e3779b9u) *a.sink = sink; // keeps the loads
 }
 
-template <int KT, int NGS, int LG>
+template <int KT, int NGS, int LG, bool PIN>
 __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
     static_assert(THIN_SLOTS == 5, "stream layout");
     if (blockIdx.x != 0) {
@@ -998,8 +1001,8 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
         return;
     }
     // the ring at a fixed LDS address (no base to add to each operand's offset), sized for the
-    // largest ring, then the -1 and 0 entries
-    __shared__ double ring[THIN_RING_MAX + 2];
+    // largest ring, then the -1 and 0 entries and the pinned entries (after the plan's ring)
+    __shared__ double ring[THIN_RING_MAX + 2 + THIN_PIN];
     const int s = threadIdx.x;
     if (s == 0) {
         ring[a.ring] = -1.0;    // operand of the right-hand-side terms
@@ -1020,10 +1023,10 @@ __global__ __launch_bounds__(THIN_THREADS) void k_solve_thin(ThinArgs a) {
     thin_fetch_a<KT>(a, 3, s, A3);
     __builtin_amdgcn_sched_barrier(0);
     for (int l = 0; l < a.nlev_pad; l += 4) {
-        thin_step<KT, NGS, LG>(a, l, s, A0, B0, A2, ring);
-        thin_step<KT, NGS, LG>(a, l + 1, s, A1, B1, A3, ring);
-        thin_step<KT, NGS, LG>(a, l + 2, s, A2, B0, A0, ring);
-        thin_step<KT, NGS, LG>(a, l + 3, s, A3, B1, A1, ring);
+        thin_step<KT, NGS, LG, PIN>(a, l, s, A0, B0, A2, ring);
+        thin_step<KT, NGS, LG, PIN>(a, l + 1, s, A1, B1, A3, ring);
+        thin_step<KT, NGS, LG, PIN>(a, l + 2, s, A2, B0, A0, ring);
+        thin_step<KT, NGS, LG, PIN>(a, l + 3, s, A3, B1, A1, ring);
     }
 }
 
@@ -1042,8 +1045,9 @@ __global__ __launch_bounds__(256) void k_thin_codes(ThinArgs a) {
         *reinterpret_cast<int4 *>(w + 384) = make_int4(0, 0, zero, 0);
         return;
     }
-    static_assert(THIN_REC == 20 && THIN_SLOTS == 5, "record layout");
+    static_assert(THIN_REC == 21 && THIN_SLOTS == 5, "record layout");
     const int32_t *co = a.rec + p * THIN_REC + 4 + 2 * THIN_SLOTS;
+    const int pin = a.rec[p * THIN_REC + THIN_REC - 1]; // the writer's second LDS entry
     int code[THIN_SLOTS];
 #pragma unroll
     for (int j = 0; j < THIN_SLOTS; j++) {
@@ -1052,7 +1056,7 @@ __global__ __launch_bounds__(256) void k_thin_codes(ThinArgs a) {
         code[j] = c >= 0 ? ~c : c == THIN_UNUSED ? zero : ~c * 8;
     }
     *reinterpret_cast<int4 *>(w) = make_int4(code[0], code[1], code[2], code[3]);
-    *reinterpret_cast<int2 *>(w + 385) = make_int2(code[4], 0);
+    *reinterpret_cast<int2 *>(w + 385) = make_int2(code[4], pin < 0 ? 0 : pin * 8);
 }
 
 // Per call, in record order: each slot's value over the row's diagonal (0 for empty slots, b
@@ -1358,18 +1362,18 @@ hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NGS, int LG> static void launch_thin(const ThinArgs &a, dim3 grid, dim3 block, hipStream_t s) {
-    hipLaunchKernelGGL((k_solve_thin<1, NGS, LG>), grid, block, 0, s, a);
+template <int NGS, int LG, bool PIN> static void launch_thin(const ThinArgs &a, dim3 grid, dim3 block, hipStream_t s) {
+    hipLaunchKernelGGL((k_solve_thin<1, NGS, LG, PIN>), grid, block, 0, s, a);
 }
 
-template <int NGS> static void launch_thin_lg(const ThinArgs &a, dim3 grid, dim3 block, hipStream_t s) {
+template <int NGS, bool PIN = false> static void launch_thin_lg(const ThinArgs &a, dim3 grid, dim3 block, hipStream_t s) {
     switch (a.lg) {
-    case 0: launch_thin<NGS, 0>(a, grid, block, s); break;
-    case 1: launch_thin<NGS, 1>(a, grid, block, s); break;
-    case 2: launch_thin<NGS, 2>(a, grid, block, s); break;
-    case 3: launch_thin<NGS, 3>(a, grid, block, s); break;
-    case 4: launch_thin<NGS, 4>(a, grid, block, s); break;
-    default: launch_thin<NGS, 5>(a, grid, block, s); break;
+    case 0: launch_thin<NGS, 0, PIN>(a, grid, block, s); break;
+    case 1: launch_thin<NGS, 1, PIN>(a, grid, block, s); break;
+    case 2: launch_thin<NGS, 2, PIN>(a, grid, block, s); break;
+    case 3: launch_thin<NGS, 3, PIN>(a, grid, block, s); break;
+    case 4: launch_thin<NGS, 4, PIN>(a, grid, block, s); break;
+    default: launch_thin<NGS, 5, PIN>(a, grid, block, s); break;
     }
 }
 
@@ -1378,7 +1382,10 @@ hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     const dim3 sgrid((unsigned)((a.n_rec + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
     hipLaunchKernelGGL(k_thin_stream, sgrid, pblock, 0, s, a);
     const dim3 grid(1 + 8 * (unsigned)a.helpers), block((unsigned)a.block);
-    if (ngs == 0) launch_thin_lg<0>(a, grid, block, s);
+    // a plan with pinned entries has at most two global slots per lane; the two-slot kernel
+    // runs it (a slot without a global operand gathers the zero past the solutions)
+    if (a.pins) launch_thin_lg<2, true>(a, grid, block, s);
+    else if (ngs == 0) launch_thin_lg<0>(a, grid, block, s);
     else if (ngs == 1) launch_thin_lg<1>(a, grid, block, s);
     else if (ngs == 2) launch_thin_lg<2>(a, grid, block, s);
     else if (ngs == 3) launch_thin_lg<3>(a, grid, block, s);

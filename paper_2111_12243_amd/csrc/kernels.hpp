@@ -41,7 +41,11 @@ struct SpmvArgs {
 //   right-hand-side term (value index THIN_VIDX_B, column the row): its operand, the entry one
 //   past the ring, holds -1;
 //   [19] 0 for a row of G lanes; a "wide" row takes 2G lanes (its first G flagged 1, the
-//   others 2) and comes before the other rows of its level.
+//   others 2) and comes before the other rows of its level;
+//   [20] in the row's first lane (its writer), the LDS entry that receives its solution besides
+//   the ring slot: the ring slot itself, or a pinned entry past the ring's two constants that
+//   keeps the solution to the end of the solve, for readers too far ahead for the ring whose
+//   lanes already use THIN_PIN_SLOTS global slots (-1 in the other lanes).
 // Every level's records start on a 64-record boundary; placeholder records (flag 1, no ops)
 // fill the gap.  The solve order numbers rows level by level, wide rows first.  Per call, a
 // stream is gathered in record order, structure-of-arrays per 64 records: four 16-byte fields
@@ -51,7 +55,9 @@ struct SpmvArgs {
 // a level.  A stream code is the byte offset in LDS of the slot's operand: a ring slot, the
 // entry past the ring (-1, right-hand-side terms) or the one after it (0, empty slots); in the
 // first `ngs` slots a global operand is coded -(1 + its solve-order index) instead, and the
-// other codes there also gather the zero kept past the solutions.  The codes and the empty
+// other codes there also gather the zero kept past the solutions; a pinned operand's code is
+// its pinned entry's offset.  The fourth word of the last field holds the writer lane's second
+// LDS entry (its byte offset).  The codes and the empty
 // chunk do not change between calls: they are written once, when the tables are uploaded, from
 // the records, which are then released.  Per call only the values are gathered, driven by a
 // compact index table of THIN_GIDX int32 per record, per 64-record chunk the value indices of
@@ -60,13 +66,14 @@ struct SpmvArgs {
 // right-hand-side term.  The solve writes solutions in solve order, and a scatter puts them in
 // row order.  One right-hand side.
 constexpr int THIN_SLOTS = 5;
-constexpr int THIN_REC = 20;
 constexpr int THIN_SW = 8;                  // stream doubles per record
-constexpr int THIN_GIDX = 6;                // gather-index int32 per record
+constexpr int THIN_PIN = 2048;              // pinned LDS entries
+constexpr int THIN_PIN_SLOTS = 2;           // global slots a lane may use when pins are available
 constexpr int32_t THIN_VIDX_B = -1;         // value index of the right-hand-side term
 constexpr int THIN_THREADS = 1024;
 constexpr int THIN_KT_MAX = 1;              // right-hand sides the single-block kernel takes
-constexpr int THIN_RING_MAX = 16384;       // LDS ring of solutions, plan positions (128 KiB)
+constexpr int THIN_RING_MAX = 16384;       // LDS ring of solutions, plan positions (128 KiB); then
+                                           // -1, 0 and the pinned entries
 constexpr double THIN_SIMD_FIXED = 3.5;   // per-level fixed cost over one wave's issue time
 constexpr int THIN_HORIZON = 3;           // a global operand's row was solved this many levels before
 constexpr int32_t THIN_UNUSED = (int32_t)0x80000000;
@@ -84,6 +91,7 @@ struct ThinArgs {
     int32_t kt;       // the kernel's KT (stride of xs)
     int32_t ring;     // LDS ring size in plan positions (a power of two); two more entries hold -1, 0
     int32_t ngs;      // op slots per lane that may hold a global operand
+    int32_t pins;     // the plan uses pinned LDS entries (writers store their solution twice)
     int32_t helpers;  // blocks that pull upcoming levels into the solver's L2
     int32_t ahead;    // levels the helpers may run ahead of the solver
     int32_t n;        // rows

@@ -652,76 +652,115 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
     if (changed) layout();
     if (R * G > THIN_THREADS) return;
     auto vidx = [&](int64_t e) -> int32_t { return perm ? (*perm)[e] : (int32_t)e; };
+    // Records, level by level.  With pins, a global operand past the first THIN_PIN_SLOTS
+    // slots of its lane is read from a pinned LDS entry instead (past the ring's two constants),
+    // written by its row when that row is solved; a lane then needs at most THIN_PIN_SLOTS
+    // global slots.  Returns false when the matrix needs more than THIN_PIN entries.
     int ngs = 0;
     std::vector<int32_t> slot_vi, slot_col, slot_code;
-    for (int64_t l = 0; l < nl; l++) {
-        const int64_t first = (int64_t)D.thin_rec.size() / THIN_REC;
-        for (int64_t row : rows_of[l]) {
-            const int64_t op = P.opstart(row), no = P.nops(row);
-            const int64_t dpos = P.kind == 2 ? op - 1 : op + no;
-            // slot s = j * NL + g (op slot j of lane g of the row's NL lanes): operands from
-            // global memory first, so that they sit in the lowest slot indices of every lane
-            const int NL = lanes_of(row);
-            const int S = NL * THIN_SLOTS;
-            slot_vi.assign(S, vidx(dpos));
-            slot_col.assign(S, (int32_t)row);
-            slot_code.assign(S, THIN_UNUSED);
-            int next = 0;
-            for (int pass = 0; pass < 2; pass++)
-                for (int64_t i = 0; i < no; i++) {
-                    const int32_t col = P.ci[op + i];
-                    const int64_t m = lev[col];
-                    const bool global = is_global(col, l);
-                    if (global && m > l - THIN_HORIZON) { // ring too small for this matrix
-                        D.thin_rec.clear();
-                        D.thin_lvl.clear();
-                        return;
+    std::vector<int64_t> head(n, -1);  // record of each row's writer lane
+    std::vector<int32_t> pin_of(n, -1); // pinned LDS entry of a row
+    std::vector<char> pinned_op;
+    auto emit = [&](bool pins) -> bool {
+        ngs = 0;
+        D.thin_rec.clear();
+        D.thin_lvl.clear();
+        D.thin_block = 64;
+        std::fill(head.begin(), head.end(), -1);
+        std::fill(pin_of.begin(), pin_of.end(), -1);
+        int32_t npin = 0;
+        for (int64_t l = 0; l < nl; l++) {
+            const int64_t first = (int64_t)D.thin_rec.size() / THIN_REC;
+            for (int64_t row : rows_of[l]) {
+                const int64_t op = P.opstart(row), no = P.nops(row);
+                const int64_t dpos = P.kind == 2 ? op - 1 : op + no;
+                // slot s = j * NL + g (op slot j of lane g of the row's NL lanes): operands from
+                // global memory first, so that they sit in the lowest slot indices of every lane
+                const int NL = lanes_of(row);
+                const int S = NL * THIN_SLOTS;
+                slot_vi.assign(S, vidx(dpos));
+                slot_col.assign(S, (int32_t)row);
+                slot_code.assign(S, THIN_UNUSED);
+                // globals in op order: the ones past the lanes' pinned-slot bound go to LDS
+                // entries of their own
+                pinned_op.assign(no, 0);
+                for (int64_t i = 0, ng = 0; i < no; i++)
+                    if (is_global(P.ci[op + i], l)) pinned_op[i] = pins && ng++ >= THIN_PIN_SLOTS * NL;
+                int next = 0;
+                for (int pass = 0; pass < 2; pass++)
+                    for (int64_t i = 0; i < no; i++) {
+                        const int32_t col = P.ci[op + i];
+                        const int64_t m = lev[col];
+                        const bool pinned = pinned_op[i] != 0;
+                        const bool global = is_global(col, l) && !pinned;
+                        if (global && m > l - THIN_HORIZON) { // ring too small for this matrix
+                            D.thin_rec.clear();
+                            D.thin_lvl.clear();
+                            return true;
+                        }
+                        if (global != (pass == 0)) continue;
+                        slot_vi[next] = vidx(op + i);
+                        slot_col[next] = col;
+                        if (pinned) {
+                            if (pin_of[col] < 0) {
+                                if (npin == THIN_PIN) return false;
+                                pin_of[col] = npin++;
+                                D.thin_rec[(size_t)head[col] * THIN_REC + THIN_REC - 1] = ring + 2 + pin_of[col];
+                            }
+                            slot_code[next] = -(1 + ring + 2 + pin_of[col]);
+                        } else {
+                            slot_code[next] = global ? (int32_t)plan_pos[col]
+                                                     : -(1 + (int32_t)(plan_pos[col] & (ring - 1)));
+                        }
+                        if (global) ngs = std::max(ngs, next / NL + 1);
+                        next++;
                     }
-                    if (global != (pass == 0)) continue;
-                    slot_vi[next] = vidx(op + i);
-                    slot_col[next] = col;
-                    slot_code[next] = global ? (int32_t)plan_pos[col]
-                                             : -(1 + (int32_t)(plan_pos[col] & (ring - 1)));
-                    if (global) ngs = std::max(ngs, next / NL + 1);
-                    next++;
+                // the right-hand-side term: operand -1 read from the slot one past the ring, value
+                // b[row] (scaled by 1 / diagonal with the ops when the stream is gathered)
+                slot_vi[next] = THIN_VIDX_B;
+                slot_col[next] = (int32_t)row;
+                slot_code[next] = -(1 + ring);
+                head[row] = (int64_t)D.thin_rec.size() / THIN_REC;
+                for (int g = 0; g < NL; g++) {
+                    int32_t rec[THIN_REC] = {(int32_t)row, vidx(dpos), 0, 0};
+                    rec[THIN_REC - 2] = NL == G ? 0 : g < G ? 1 : 2;
+                    // the writer lane's second LDS entry: its own ring slot until a pin is given
+                    rec[THIN_REC - 1] = g == 0 ? (int32_t)(plan_pos[row] & (ring - 1)) : -1;
+                    int cnt = 0;
+                    for (int j = 0; j < THIN_SLOTS; j++) {
+                        const int sl = j * NL + g;
+                        rec[4 + j] = slot_vi[sl];
+                        rec[4 + THIN_SLOTS + j] = slot_col[sl];
+                        rec[4 + 2 * THIN_SLOTS + j] = slot_code[sl];
+                        cnt += slot_code[sl] != THIN_UNUSED;
+                    }
+                    rec[2] = cnt;
+                    D.thin_rec.insert(D.thin_rec.end(), rec, rec + THIN_REC);
                 }
-            // the right-hand-side term: operand -1 read from the slot one past the ring, value
-            // b[row] (scaled by 1 / diagonal with the ops when the stream is gathered)
-            slot_vi[next] = THIN_VIDX_B;
-            slot_col[next] = (int32_t)row;
-            slot_code[next] = -(1 + ring);
-            for (int g = 0; g < NL; g++) {
-                int32_t rec[THIN_REC] = {(int32_t)row, vidx(dpos), 0, 0};
-                rec[THIN_REC - 1] = NL == G ? 0 : g < G ? 1 : 2;
-                int cnt = 0;
-                for (int j = 0; j < THIN_SLOTS; j++) {
-                    const int sl = j * NL + g;
-                    rec[4 + j] = slot_vi[sl];
-                    rec[4 + THIN_SLOTS + j] = slot_col[sl];
-                    rec[4 + 2 * THIN_SLOTS + j] = slot_code[sl];
-                    cnt += slot_code[sl] != THIN_UNUSED;
-                }
-                rec[2] = cnt;
+            }
+            const int64_t lanes = (int64_t)D.thin_rec.size() / THIN_REC - first;
+            // placeholders up to the next 64-record boundary: the level's first row, flag 1, no ops
+            while (((int64_t)D.thin_rec.size() / THIN_REC) % 64) {
+                int32_t rec[THIN_REC];
+                std::copy(&D.thin_rec[first * THIN_REC], &D.thin_rec[first * THIN_REC] + THIN_REC, rec);
+                rec[2] = 0;
+                rec[3] = 1;
+                rec[THIN_REC - 2] = 0;
+                rec[THIN_REC - 1] = -1;
+                for (int j = 0; j < THIN_SLOTS; j++) rec[4 + 2 * THIN_SLOTS + j] = THIN_UNUSED;
                 D.thin_rec.insert(D.thin_rec.end(), rec, rec + THIN_REC);
             }
+            D.thin_lvl.push_back((int32_t)first);
+            D.thin_lvl.push_back((int32_t)lanes);
+            D.thin_lvl.push_back((int32_t)(lvl_end[l] - (int64_t)rows_of[l].size()));
+            D.thin_lvl.push_back(nwide[l]);
+            D.thin_block = std::max<int32_t>(D.thin_block, (int32_t)((lanes + 63) / 64 * 64));
         }
-        const int64_t lanes = (int64_t)D.thin_rec.size() / THIN_REC - first;
-        // placeholders up to the next 64-record boundary: the level's first row, flag 1, no ops
-        while (((int64_t)D.thin_rec.size() / THIN_REC) % 64) {
-            int32_t rec[THIN_REC];
-            std::copy(&D.thin_rec[first * THIN_REC], &D.thin_rec[first * THIN_REC] + THIN_REC, rec);
-            rec[2] = 0;
-            rec[3] = 1;
-            rec[THIN_REC - 1] = 0;
-            for (int j = 0; j < THIN_SLOTS; j++) rec[4 + 2 * THIN_SLOTS + j] = THIN_UNUSED;
-            D.thin_rec.insert(D.thin_rec.end(), rec, rec + THIN_REC);
-        }
-        D.thin_lvl.push_back((int32_t)first);
-        D.thin_lvl.push_back((int32_t)lanes);
-        D.thin_lvl.push_back((int32_t)(lvl_end[l] - (int64_t)rows_of[l].size()));
-        D.thin_lvl.push_back(nwide[l]);
-        D.thin_block = std::max<int32_t>(D.thin_block, (int32_t)((lanes + 63) / 64 * 64));
-    }
+        D.thin_pins = npin;
+        return true;
+    };
+    if (!emit(true)) emit(false);
+    if (D.thin_rec.empty()) return;
     // empty levels up to a multiple of four, and four more for the kernel's fetches ahead
     const int64_t pad = (nl + 3) / 4 * 4;
     for (int64_t l = nl; l < pad + 4; l++) {
@@ -920,6 +959,7 @@ ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, 
     t.kt = 1;
     t.ring = D.thin_ring;
     t.ngs = D.thin_ngs;
+    t.pins = D.thin_pins > 0 ? 1 : 0;
     t.n = (int32_t)D.thin_rows.size();
     t.block = D.thin_block;
     t.xs = D.d_thin_xs;

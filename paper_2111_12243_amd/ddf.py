@@ -373,7 +373,7 @@ def ddf_plan_device_tables(plan, which=0) -> dict:
     sync = grab(t.sync, t.n_tasks, 4) if t.sync else np.zeros((0, 4), np.int32)
     return {"cods": grab(t.cods, t.n_cods, 16), "aux": grab(t.aux, t.aux_len), "tasks": grab(t.tasks, t.n_tasks, 4),
             "sync": sync, "n_counters": int(t.n_counters), "tasksN": grab(t.tasksN, t.n_tasksN, 4),
-            "thin_rec": grab(t.thin_rec, t.n_thin_rec, 20), "thin_lvl": grab(t.thin_lvl, t.n_thin_lvl, 4),
+            "thin_rec": grab(t.thin_rec, t.n_thin_rec, 21), "thin_lvl": grab(t.thin_lvl, t.n_thin_lvl, 4),
             "thin_rows": grab(t.thin_rows, t.n_thin_lvl and ddf_plan_info(plan)["n_rows"], 1).ravel(),
             "thin_lg": int(t.thin_lg), "thin_ring_size": int(t.thin_ring_size), "thin_ngs": int(t.thin_ngs),
             "thin_block": int(t.thin_block), "rowlist": grab(t.rowlist, t.n_rowlist)}

@@ -420,6 +420,27 @@ def mixed_lower(n: int, seed: int, long_every: int = 150, long_ops: int = 8, sho
     return _lower_from_pattern(t.row_ptr.astype(np.int64), t.col_idx, rng)
 
 
+def hub_lower(n: int, seed: int, hub_every: int = 97, hub_ops: int = 30, near: int = 50, far: int = 300) -> CSR:
+    """Lower-triangular chain (row i reads row i-1, plus up to two random columns among the
+    `near` rows before it) with every hub_every-th row also reading hub_ops random columns at
+    least `far` rows back; diagonal = 1 + row abs-sum (last in each row)."""
+    rng = generator(seed)
+    rows, cols = [np.arange(n)], [np.arange(n)]
+    for i in range(1, n):
+        c = {i - 1}
+        lo = max(0, i - near)
+        for _ in range(int(rng.integers(0, 3))):
+            if i - 1 > lo:
+                c.add(int(rng.integers(lo, i - 1)))
+        if i % hub_every == 0 and i > far + hub_ops:
+            c.update(int(x) for x in rng.choice(i - far, size=hub_ops, replace=False))
+        c = np.array(sorted(c), dtype=np.int64)
+        rows.append(np.full(c.size, i))
+        cols.append(c)
+    t = csr_from_pairs(n, n, np.concatenate(rows), np.concatenate(cols))
+    return _lower_from_pattern(t.row_ptr.astype(np.int64), t.col_idx, rng)
+
+
 def cached(name: str, builder, *args, **kw):
     """Build a workload once per process (and optionally on disk when DDF_INPUT_CACHE is set)."""
     key = (name, args, tuple(sorted(kw.items())))

@@ -258,6 +258,7 @@ def _rows_from(TF, task):
 
 THIN_UNUSED = -(1 << 31)
 THIN_VIDX_B = -1  # value index of a row's right-hand-side term
+THIN_PIN = 2048  # pinned LDS entries past the ring's two constants
 
 
 def thin_solve(tabs, L, B, vals=None, Xf=None):
@@ -266,14 +267,15 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
     slot, solve-order index mod ring size, not overwritten by a row solved up to and including
     the reading level), that every global operand sits in one of the first thin_ngs slots of
     its lane, names the solve-order index of its column and was solved at least
-    THIN_HORIZON levels before (so the gather two levels ahead sees it final), that empty slots
-    carry no op, and that every row is solved once.  With Xf (transposed solve), also returns
+    THIN_HORIZON levels before (so the gather two levels ahead sees it final), that a pinned
+    operand's entry (past the ring's two constants) was written by its row, by that row alone,
+    that empty slots carry no op, and that every row is solved once.  With Xf (transposed solve), also returns
     the value gradient of the follow-up pass: -<x[col], Xf[row]> at each op's value index and
     -<x[row], Xf[row]> at the diagonal."""
     rec, lvl, lg = tabs["thin_rec"], tabs["thin_lvl"], tabs["thin_lg"]
     M, ngs, rows_of = tabs["thin_ring_size"], tabs["thin_ngs"], tabs["thin_rows"]
     S = 5  # op slots per lane
-    assert M > 0 and M & (M - 1) == 0 and ngs in (0, 1, 2, 3, 5)
+    assert M > 0 and M & (M - 1) == 0 and ngs in (0, 1, 2, 3, 5) and rec.shape[1] == 21
     assert lvl.shape[0] % 4 == 0 and lvl.shape[1] == 4 and (lvl[-4:, 1] == 0).all()
     assert rec.shape[0] % 64 == 0 and tabs["thin_block"] >= lvl[:, 1].max()
     assert B.shape[1] == 1 and sorted(rows_of.tolist()) == list(range(B.shape[0]))
@@ -283,7 +285,7 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
     X = np.full((n, k), np.nan)
     gv = np.full(v.shape[0], np.nan) if Xf is not None else None
     level_of = np.full(n, -1)
-    ring = {}
+    ring, pinned, pin_w = {}, {}, {}
     so_next = 0
     for l, (first, lanes, so0, nw) in enumerate(lvl):
         if lanes == 0:
@@ -310,8 +312,11 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
                 acc[row] = np.zeros(k)
                 diag[row], dpos[row] = v[dp], dp
                 slot[row] = so % M
+                # the writer's second LDS entry: its ring slot, or a pinned entry
+                pin_w[row] = int(r[20])
+                assert pin_w[row] == so % M or M + 2 <= pin_w[row] < M + 2 + THIN_PIN
             else:
-                assert row in acc
+                assert row in acc and int(r[20]) == -1
                 prev = rec[first + s - (s % G if wide != 2 or s % G else G)]
                 assert int(prev[0]) == row and (wide == int(prev[19]) or (wide == 2 and int(prev[19]) == 1))
             assert cnt == sum(int(c) != THIN_UNUSED for c in r[4 + 2 * S:4 + 3 * S])
@@ -328,6 +333,8 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
                 assert 0 <= m < l, f"row {row} reads x[{col}] not solved in an earlier level"
                 if code >= 0:
                     assert j < ngs and rows_of[code] == col and m <= l - 3
+                elif -code - 1 >= M + 2:
+                    assert pinned.get(-code - 1) == col, f"row {row} reads pinned entry {-code - 1}"
                 else:
                     assert ring.get(-code - 1) == col
                     reads[-code - 1] = col
@@ -344,6 +351,9 @@ def thin_solve(tabs, L, B, vals=None, Xf=None):
             X[row] = (B[row] - a) / diag[row]
             level_of[row] = l
             ring[slot[row]] = row
+            if pin_w[row] >= M + 2:
+                assert pin_w[row] not in pinned, "a pinned entry is written twice"
+                pinned[pin_w[row]] = row
             if gv is not None:
                 gv[dpos[row]] = -np.dot(X[row], Xf[row])
     assert (level_of >= 0).all()

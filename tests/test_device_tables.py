@@ -165,6 +165,19 @@ def test_thin_small_ring_global_operands():
 
 
 
+def test_thin_pinned_operands():
+    # hub rows read ~30 rows far behind a 256-row ring: past two global slots per lane their
+    # operands come from pinned LDS entries, written once by the rows that own them
+    L = I.hub_lower(3000, 5)
+    F = replay_solve(L, k=1, thin_ring=256)
+    M = F["thin_ring_size"]
+    codes = F["thin_rec"][:, 14:19]
+    pinned = (codes <= -(M + 3)) & (codes != E.THIN_UNUSED)
+    assert pinned.sum() > 50 and F["thin_ngs"] <= 2
+    writers = F["thin_rec"][:, 20]
+    assert (writers >= M + 2).sum() == len(set((-codes[pinned] - 1).tolist()))
+
+
 def test_thin_lane_cap_sub_levels():
     # a lane cap cuts wide levels into consecutive sub-levels; the solve order stays valid
     L = I.tril(I.laplacian(150, 150, 1, I.OFFS_5PT, 4.0))

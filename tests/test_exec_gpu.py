@@ -195,6 +195,13 @@ def test_c2_scaled():
     sptrsv_case(w.L, 1, opts=ddf.ddf_opts_default(thin_lanes=128))
 
 
+def test_thin_pinned_operands():
+    # hub rows read ~30 rows far behind a 256-row ring: operands past two global slots per
+    # lane come from pinned LDS entries
+    opts = ddf.ddf_opts_default(thin_ring=256)
+    sptrsv_case(I.hub_lower(3000, 5), 1, 7, opts)
+
+
 def test_thin_sub_levels_wide():
     # a 3D 7-point factor whose middle levels are wider than 1024 lanes: single-block only once cut
     offs7 = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
