@@ -637,19 +637,26 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
     // has overwritten its slot
     auto is_global = [&](int64_t col, int64_t l) { return plan_pos[col] < lvl_end[l] - ring; };
     layout();
-    bool changed = false;
-    for (int64_t l = 0; l < nl; l++)
-        for (int64_t row : rows_of[l]) {
-            if (wide[row]) continue;
-            const int64_t op = P.opstart(row), no = P.nops(row);
-            int64_t ng = 0;
-            for (int64_t i = 0; i < no; i++) ng += is_global(P.ci[op + i], l);
-            if (ng > G && 2 * G * THIN_SLOTS >= no + 1) {
-                wide[row] = 1;
-                changed = true;
+    const std::vector<uint8_t> wide_ops = wide;
+    // rows whose operands from global memory would need more than `per_lane` slots per lane
+    // (and whose slots fit 2G lanes) take 2G lanes
+    auto mark = [&](int per_lane) {
+        bool changed = false;
+        for (int64_t l = 0; l < nl; l++)
+            for (int64_t row : rows_of[l]) {
+                if (wide_ops[row]) continue;
+                const int64_t op = P.opstart(row), no = P.nops(row);
+                int64_t ng = 0;
+                for (int64_t i = 0; i < no; i++) ng += is_global(P.ci[op + i], l);
+                const uint8_t w = ng > (int64_t)per_lane * G && 2 * G * THIN_SLOTS >= no + 1;
+                if (w != wide[row]) {
+                    wide[row] = w;
+                    changed = true;
+                }
             }
-        }
-    if (changed) layout();
+        if (changed) layout();
+    };
+    mark(1);
     if (R * G > THIN_THREADS) return;
     auto vidx = [&](int64_t e) -> int32_t { return perm ? (*perm)[e] : (int32_t)e; };
     // Records, level by level.  With pins, a global operand past the first THIN_PIN_SLOTS
@@ -760,6 +767,26 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
         return true;
     };
     if (!emit(true)) emit(false);
+    if (!D.thin_rec.empty() && ngs == THIN_PIN_SLOTS) {
+        // every lane gathers two slots anyway: rows with up to two global operands per lane
+        // stay at G lanes (fewer lanes per level), unless that needs more global slots
+        const int ngs1 = ngs;
+        mark(THIN_PIN_SLOTS);
+        bool ok = R * G <= THIN_THREADS;
+        if (ok) {
+            if (!emit(true)) emit(false);
+            ok = !D.thin_rec.empty() && ngs <= ngs1;
+        }
+        if (!ok) {
+            mark(1);
+            if (R * G > THIN_THREADS) {
+                D.thin_rec.clear();
+                D.thin_lvl.clear();
+                return;
+            }
+            if (!emit(true)) emit(false);
+        }
+    }
     if (D.thin_rec.empty()) return;
     // empty levels up to a multiple of four, and four more for the kernel's fetches ahead
     const int64_t pad = (nl + 3) / 4 * 4;
