@@ -78,9 +78,9 @@ typedef struct {
                               (batches: one persistent launch), 2 single-block when
                               possible, 3 one launch per level of the multi-block tasks     */
     int32_t thin_helpers;  /* single-block solve: helper blocks that pull the next levels'
-                              tables into the solver's L2; -1 default (2), 0 none, max 8  */
+                              tables into the solver's L2; -1 default (4), 0 none, max 8  */
     int32_t thin_ahead;    /* single-block solve: levels the helpers run ahead; 0 default
-                              (32), at least 8                                              */
+                              (24), at least 8                                              */
     int32_t thin_ring;     /* single-block solve: LDS ring of recent solutions, in rows; a
                               power of two in 256..16384; 0 default (16384)                */
     int32_t thin_lanes;    /* single-block solve: most lanes a level may use; a level with

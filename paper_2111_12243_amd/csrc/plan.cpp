@@ -1117,8 +1117,8 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         p->sp_f.ops_per_lane = p->sp_a.ops_per_lane = 1;
         p->sp_f.passes = p->sp_a.passes = 1;
     }
-    p->sp_f.helpers = p->sp_a.helpers = o.thin_helpers < 0 ? 2 : std::min(o.thin_helpers, 8);
-    p->sp_f.ahead = p->sp_a.ahead = o.thin_ahead <= 0 ? 32 : std::max(o.thin_ahead, 8);
+    p->sp_f.helpers = p->sp_a.helpers = o.thin_helpers < 0 ? 4 : std::min(o.thin_helpers, 8);
+    p->sp_f.ahead = p->sp_a.ahead = o.thin_ahead <= 0 ? 24 : std::max(o.thin_ahead, 8);
     if (p->host_only) {
         ddf_status st = build_schedule(p, true, true);
         if (st) {
@@ -1982,8 +1982,8 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
     } else {
         const DevTables &D = adjop ? p->T : p->F;
         if (!D.thin_rec.empty() && nrhs <= THIN_KT_MAX)
-            for (int hp : {2, 0, 4, 1})
-                for (int ah : {32, 96}) cands.push_back({target.ops_per_lane, target.passes, target.remap, 0, 2, hp, ah});
+            for (int hp : {4, 2, 0})
+                for (int ah : {24, 32, 64}) cands.push_back({target.ops_per_lane, target.passes, target.remap, 0, 2, hp, ah});
         if (!p->batch)
             for (int opl : {2, 1, 4})
                 for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, 0, 3, target.helpers, target.ahead});
