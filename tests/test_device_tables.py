@@ -178,6 +178,18 @@ def test_thin_pinned_operands():
     assert (writers >= M + 2).sum() == len(set((-codes[pinned] - 1).tolist()))
 
 
+def test_thin_pinned_entries_overflow():
+    # hubs every third row need more than the 2048 pinned entries: the plan falls back to more
+    # global slots per lane and pins nothing
+    L = I.hub_lower(12000, 9, hub_every=3, hub_ops=30)
+    F = replay_solve(L, k=1, thin_ring=256)
+    M = F["thin_ring_size"]
+    codes = F["thin_rec"][:, 14:19]
+    assert F["thin_rec"].shape[0] and F["thin_ngs"] > 2
+    assert not ((codes <= -(M + 3)) & (codes != E.THIN_UNUSED)).any()
+    assert (F["thin_rec"][:, 20] < M).all()
+
+
 def test_thin_lane_cap_sub_levels():
     # a lane cap cuts wide levels into consecutive sub-levels; the solve order stays valid
     L = I.tril(I.laplacian(150, 150, 1, I.OFFS_5PT, 4.0))
