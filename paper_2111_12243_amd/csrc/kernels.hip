@@ -565,7 +565,9 @@ __device__ __forceinline__ void xstore(double *p, double v) {
 }
 
 // every row of one task, all passes, all right-hand-side tiles
-template <int KT, bool ADJ, bool COH, bool U4 = false>
+// SINGLE (the per-level kernel of a single-matrix call): ops' column reads run four ahead, and
+// the adjoint's values come in U's order (gathered before the solve), not through perm.
+template <int KT, bool ADJ, bool COH, bool SINGLE = false>
 __device__ void solve_task(const SolveArgs &a, int t, int lane) {
     const Task tk = a.tasks[t];
     const int phase = (tk.meta >> 8) & 1;
@@ -612,7 +614,8 @@ __device__ void solve_task(const SolveArgs &a, int t, int lane) {
         }
         return;
     }
-    const int32_t *__restrict__ perm = ADJ ? a.perm + mi.val_base : nullptr;
+    constexpr bool VP = ADJ && !SINGLE; // values through perm
+    const int32_t *__restrict__ perm = VP ? a.perm + mi.val_base : nullptr;
     const double *__restrict__ b = a.b + mi.vec_base;
     double *x = a.x + mi.vec_base;
     for (int base = tk.i0b; base < tk.i0e; base += R) {
@@ -623,7 +626,7 @@ __device__ void solve_task(const SolveArgs &a, int t, int lane) {
         if (active) {
             ri = row_info(c, a.aux, i0);
             const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
-            diag = ADJ ? vals[perm[dpos]] : vals[dpos];
+            diag = VP ? vals[perm[dpos]] : vals[dpos];
         }
         const int64_t rb = (int64_t)ri.row * k;
         for (int r0 = 0; r0 < k; r0 += KT) {
@@ -631,8 +634,8 @@ __device__ void solve_task(const SolveArgs &a, int t, int lane) {
 #pragma unroll
             for (int r = 0; r < KT; r++) acc[r] = 0.0;
             if (active)
-                walk_any<U4>(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
-                    const double v = ADJ ? vals[perm[e]] : vals[e];
+                walk_any<SINGLE>(mode, c, a.aux, i0, ri, g, G, [&](int e, int col) {
+                    const double v = VP ? vals[perm[e]] : vals[e];
                     const double *xr = x + (int64_t)col * k + r0;
 #pragma unroll
                     for (int r = 0; r < KT; r++)
@@ -1424,26 +1427,40 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
 int num_cu() { return g_num_cu > 0 ? g_num_cu : 256; }
 
 // One level's tasks per launch (the launch boundaries order the levels): plain loads and
-// stores, no tickets, no waits.  U4 (single-matrix calls): four ops' column reads ahead of
-// their loads (C5: 3% faster; batches of small matrices: 5% slower).
-template <int KT, bool ADJ, bool U4>
+// stores, no tickets, no waits.  SINGLE (single-matrix calls): four ops' column reads ahead
+// of their loads (C5: 3% faster; batches of small matrices: 5% slower), and the adjoint's
+// values already in U's order.
+template <int KT, bool ADJ, bool SINGLE>
 __global__ __launch_bounds__(WAVE *WPB) void k_solve_range(SolveArgs a) {
     const int lane = threadIdx.x % WAVE;
     const int t = xcd_block(blockIdx.x, gridDim.x, 1) * WPB + threadIdx.x / WAVE;
     if (t >= a.ntasks) return;
-    solve_task<KT, ADJ, false, U4>(a, t, lane);
+    solve_task<KT, ADJ, false, SINGLE>(a, t, lane);
 }
 
-template <bool U4> static void launch_range(const SolveArgs &a, bool adj, int kt, dim3 grid, dim3 block, hipStream_t s) {
+// dst[i] = src[idx[i]], XCD-contiguous ranges (nearby i often share source lines)
+__global__ __launch_bounds__(256) void k_gather(double *__restrict__ dst, const double *__restrict__ src,
+                                                const int32_t *__restrict__ idx, int64_t n) {
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+hipError_t launch_gather(double *dst, const double *src, const int32_t *idx, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, src, idx, n);
+    return hipGetLastError();
+}
+
+template <bool SINGLE> static void launch_range(const SolveArgs &a, bool adj, int kt, dim3 grid, dim3 block, hipStream_t s) {
     switch (kt * 2 + (adj ? 1 : 0)) {
-    case 2: hipLaunchKernelGGL((k_solve_range<1, false, U4>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_solve_range<1, true, U4>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_solve_range<2, false, U4>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_solve_range<2, true, U4>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_solve_range<4, false, U4>), grid, block, 0, s, a); break;
-    case 9: hipLaunchKernelGGL((k_solve_range<4, true, U4>), grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_solve_range<8, false, U4>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_solve_range<8, true, U4>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_solve_range<1, false, SINGLE>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_solve_range<1, true, SINGLE>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_solve_range<2, false, SINGLE>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_solve_range<2, true, SINGLE>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_solve_range<4, false, SINGLE>), grid, block, 0, s, a); break;
+    case 9: hipLaunchKernelGGL((k_solve_range<4, true, SINGLE>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_solve_range<8, false, SINGLE>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_solve_range<8, true, SINGLE>), grid, block, 0, s, a); break;
     }
 }
 

@@ -128,7 +128,8 @@ struct SolveArgs {
     int32_t backoff_max;
     const MatInfo *mats;
     const double *vals;
-    const int32_t *perm; // adjoint: U's entries -> L's values (per matrix, local)
+    const int32_t *perm; // adjoint: U's entries -> L's values (per matrix, local); the per-level
+                         // kernel of a single-matrix call reads vals in U's order instead
     const double *b;     // right-hand side (adjoint: upstream gradient)
     double *x;           // solution (adjoint: lambda)
     const double *xf;    // adjoint: forward solution (for GV)
@@ -183,6 +184,7 @@ hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s);
 hipError_t launch_thin_codes(const ThinArgs &a, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_gather(double *dst, const double *src, const int32_t *idx, int64_t n, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
 hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s);
 

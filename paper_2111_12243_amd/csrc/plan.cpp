@@ -51,6 +51,7 @@ struct ddf_plan_s {
     int32_t *d_gv_chunks = nullptr;
     double gv_avg_short = 1.0;        // mean length of the other rows
     double *d_vals = nullptr;
+    double *d_valsT = nullptr; // single-matrix SpTRSV adjoint: values in transposed order, per call
     int32_t *d_perm = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_rpT = nullptr, *d_ciT = nullptr;
     int32_t *d_rows = nullptr, *d_rrows = nullptr;
     MatInfo *d_mats = nullptr;
@@ -1158,6 +1159,10 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         std::vector<int32_t> pall;
         for (int b = 0; b < nmat; b++) pall.insert(pall.end(), perm[b].begin(), perm[b].end());
         if ((s = upload(p, &p->d_perm, pall.data(), pall.size()))) return fin(s);
+        // the per-level transposed solve of one matrix reads its values gathered in transposed
+        // order (one pass per call) instead of through perm in every level
+        if (!batch && kind == DDF_SPTRSV_LOWER && (s = dalloc(p, (void **)&p->d_valsT, (size_t)p->nnz * 8)))
+            return fin(s);
     }
     if (!batch) {
         // CSR copies for the plain comparators and the adjoints' value gradient
@@ -1240,7 +1245,12 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.k_override = k_override;
     if (sp.path == 3) {
         // one launch per level (task ranges of equal level, over all matrices of a batch; the
-        // GV tasks last)
+        // GV tasks last).  The transposed solve of one matrix first gathers its values in
+        // transposed order, so that no level reads them through perm.
+        if (adj && k_override > 0 && p->d_valsT && p->nnz) {
+            HIPCHK(launch_gather(p->d_valsT, vals, p->d_perm, p->nnz, s));
+            a.vals = p->d_valsT;
+        }
         const Task *tk = a.tasks;
         const DCod *tc = a.tcods;
         const int4 *sy = a.sync;
@@ -1819,7 +1829,8 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         else if (p->batch)
             ba = 20 * nnz + (p->has_adj ? p->T.solve_read_bytes() : 0) + Fca + 32 * vk;
         else
-            ba = 24 * nnz + (p->has_adj ? p->T.solve_read_bytes() : 0) + 4 * (n + 1) + 32 * vk;
+            ba = 24 * nnz + (p->has_adj ? p->T.solve_read_bytes() : 0) + 4 * (n + 1) + 32 * vk +
+                 (p->sp_a.path == 3 ? 16 * nnz : 0); // the values' transposed copy: written, read back
         bc = 20 * nnz + 4 * (n + 1) + 24 * vk;
         if (p->batch) {
             for (size_t b = 0; b < p->mats.size(); b++) {
@@ -1836,7 +1847,8 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
             ba = 8 * nnz + p->T.thin_bytes() + 16 * vk;
         else
             ba = 8 * nnz + (int64_t)p->T.aux.size() * 4 +
-                 p->n_solve_tasks_adj * (int64_t)(sizeof(Task) + sizeof(DCod) + 16) + 16 * vk;
+                 p->n_solve_tasks_adj * (int64_t)(sizeof(Task) + sizeof(DCod) + 16) + 16 * vk +
+                 (!p->batch && p->sp_a.path == 3 ? 16 * nnz : 0);
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
         fl = p->batch ? 0 : kf * (2 * (nnz - n) + n);
         break;
