@@ -9,7 +9,9 @@
  * and chosen per window by the cost model of Eq. (1)), grouped into partitions of
  * independent rows (dependence levels for the solve); an executor (Sec. IV-B) runs the
  * codelets partition by partition.  Here the executor is a set of HIP kernels; the solve
- * runs every level inside one persistent kernel.
+ * runs its levels in one single-block kernel when every level fits one block (one
+ * right-hand side), else in one launch per level or in one persistent kernel with level
+ * counters, as set by the options or the autotuner.
  *
  * Conventions for every call below:
  *  - Host arrays are read during the call only; nothing keeps a pointer to them.
@@ -20,7 +22,8 @@
  *    allocate nothing, and copy nothing synchronously, so they may be captured in a graph.
  *    Per plan, one forward call (SpMV, solve) and one adjoint call (ddf_spmv_adjoint,
  *    ddf_sptrsv_adjoint, ddf_sptrsv_value_grad) may be in flight at a time, on any
- *    streams: the solves' scratch (level counters, per-call streams) is per direction.
+ *    streams: the solves' scratch (level counters, per-call streams, the values in
+ *    transposed order) is per direction.
  *  - Arguments are validated before any launch.  On an error no kernel is launched,
  *    outputs are untouched, and ddf_last_error() holds a message (thread-local).
  *  - A zero diagonal is not an error: it gives inf/nan by IEEE rules.
