@@ -304,3 +304,34 @@ def test_forward_and_adjoint_on_two_streams(path):
         ddf.ddf_plan_sync_status(plan)
         for got, want in zip((x2, gb2, gv2), ref):
             assert np.array_equal(host(got), want), f"rep {rep}"
+
+
+@pytest.mark.gpu
+def test_value_grad_argument_checks():
+    # ddf_sptrsv_value_grad validates before any launch and leaves its output untouched
+    print("value-gradient argument checks", flush=True)
+    L = I.random_lower(200, 3, density=0.05)
+    plan = ddf.ddf_inspect(1, L)
+    x, gb = dev(rnd((L.n_rows, 2), 1)), dev(rnd((L.n_rows, 2), 2))
+    gv = torch.full((L.nnz,), 7.0, dtype=torch.float64, device=DEV)
+    for args, status in (((None, gb, gv, 2), ddf.DDF_E_ARG),   # no x
+                         ((x, gb, None, 2), ddf.DDF_E_ARG),    # no output
+                         ((x, gb, gb, 2), ddf.DDF_E_ARG),      # output overlaps an input
+                         ((x, gb, gv, 0), ddf.DDF_E_ARG)):     # bad right-hand-side count
+        with pytest.raises(ddf.DDFError) as e:
+            ddf.ddf_sptrsv_value_grad(plan, *args)
+        assert e.value.status == status
+    assert (host(gv) == 7.0).all()
+    spmv_plan = ddf.ddf_inspect(0, L)
+    with pytest.raises(ddf.DDFError) as e:
+        ddf.ddf_sptrsv_value_grad(spmv_plan, x, gb, gv, 2)
+    assert e.value.status == ddf.DDF_E_KIND
+    no_adj = ddf.ddf_inspect(1, L, ddf.ddf_opts_default(build_adjoint=0))
+    with pytest.raises(ddf.DDFError) as e:
+        ddf.ddf_sptrsv_value_grad(no_adj, x, gb, gv, 2)
+    assert e.value.status == ddf.DDF_E_UNSUPPORTED
+    # a valid call: gv[e] = -<gb[row], x[col]> for every stored entry, the diagonal included
+    ddf.ddf_sptrsv_value_grad(plan, x, gb, gv, 2)
+    rows = np.repeat(np.arange(L.n_rows), np.diff(L.row_ptr))
+    want = -(host(gb)[rows] * host(x)[L.col_idx]).sum(1)
+    assert np.allclose(host(gv), want, rtol=1e-13, atol=1e-14)
