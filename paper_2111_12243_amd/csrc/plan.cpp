@@ -288,7 +288,8 @@ void spmv1_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_ind
         codelet_tasks(d, aux, cod_index, sp, 0, out);
         return;
     }
-    const int32_t rows = STREAM_ELEMS / d.nn;
+    // the kernel sums one row per lane: at most 64 rows, and at most STREAM_ELEMS elements
+    const int32_t rows = std::min<int32_t>(STREAM_ELEMS / d.nn, 64);
     for (int32_t a = 0; a < d.m; a += rows) out.push_back({cod_index, a, std::min(d.m, a + rows), TASK_STREAM});
 }
 

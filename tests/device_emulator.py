@@ -98,6 +98,7 @@ class Tables:
             # full table contiguous columns from xt_off + i0b*nn
             fl, nn = int(c[F["flags"]]), int(c[F["nn"]])
             assert fl & FRECT and 1 <= nn and (i0e - i0b) * nn <= STREAM_ELEMS and not fl & DOPS
+            assert i0e - i0b <= 64  # one row per lane sums the products
             assert c[F["m"]] == 1 or c[F["op_step"]] == nn
             mode = xmode(fl)
             assert mode in (0, 1, 3)

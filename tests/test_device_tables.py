@@ -131,6 +131,20 @@ def test_stream_tasks_single_entry_rows():
     replay_spmv(eye, k=1)
 
 
+@pytest.mark.parametrize("window", [128, 1024])
+def test_stream_tasks_wide_windows(window):
+    # rectangular codelets of one to three entries per row over windows wider than a wave:
+    # every stream task must stay within the 64 rows one wave sums
+    n = 2000
+    eye = I.csr_from_pairs(n, n, np.arange(n), np.arange(n), np.arange(1.0, n + 1))
+    F = replay_spmv(eye, k=1, window=window)
+    T = I.laplacian(n, 1, 1, [(-1, 0, 0), (0, 0, 0), (1, 0, 0)], 2.0)  # tridiagonal
+    F2 = replay_spmv(T, k=1, window=window)
+    for tabs in (F, F2):
+        st = tabs["tasks"][(tabs["tasks"][:, 3] & E.TASK_STREAM) != 0]
+        assert len(st) and (st[:, 2] - st[:, 1]).max() <= 64
+
+
 def test_thin_records_workloads():
     w = I.c1_laplace2d()
     F = ddf.ddf_plan_device_tables(hplan(1, w.L), 0)

@@ -137,6 +137,17 @@ def test_crafted_spmv():
     spmv_case(A, 5)
 
 
+@pytest.mark.parametrize("window", [128, 1024])
+def test_wide_window_stream_tasks(window):
+    # diagonal and tridiagonal matrices under windows wider than a wave: rectangular
+    # codelets of one or three entries per row run as stream tasks of at most 64 rows
+    n = 2000
+    opts = ddf.ddf_opts_default(window=window)
+    spmv_case(I.csr_from_pairs(n, n, np.arange(n), np.arange(n), np.arange(1.0, n + 1)), 1, 11, opts, plain=False)
+    tri = I.laplacian(n, 1, 1, [(-1, 0, 0), (0, 0, 0), (1, 0, 0)], 2.0)
+    spmv_case(tri, 1, 12, opts, plain=False)
+
+
 def test_crafted_sptrsv():
     n = 200
     sptrsv_case(I.csr_from_pairs(n, n, np.arange(n), np.arange(n), np.arange(1.0, n + 1)), 1)

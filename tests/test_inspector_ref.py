@@ -101,6 +101,93 @@ def test_c1_sptrsv_plan():
     assert int(cod[:, C["cost"]].sum()) == 8817
 
 
+def test_c1_spmv_region_costs():
+    # Each window is one grid line of 64 points (Eq. 1, c = |p| + 3 + |s0| + |s1| + |s2|).
+    # BLAS_first = PSCI_first: no single row is BLAS (its columns are not one stride), so both
+    # take the longest PSC I runs: the edge point, the 62 interior points, the other edge point.
+    #   boundary line j = 0 or 63: rows of 3, 4 x 62, 3 entries -> (3+3+3) + (248+3+4) + (3+3+3)
+    #     = 273; the shared pattern {0, 1, 2, 65} of the middle codelet has 2 runs, and 2*2 = 4
+    #     ties its 4 plain offsets, so it stays PLAIN (ties go to the plain table)
+    #   interior line: rows of 4, 5 x 62, 4 -> (4+3+4) + (310+3+5) + (4+3+4) = 340
+    # PSCII_first takes the whole ragged line as one PSC II codelet (only the rows are strided):
+    # |p| + 3 + 64 op starts + |p| plain columns (runs would cost 2 * 3 per row, more than |p|):
+    #   boundary: 254 + 3 + 64 + 254 = 575;  interior: 318 + 3 + 64 + 318 = 703
+    p = O.inspect(0, I.c1_laplace2d().A, 64)
+    reg = p["regions"]
+    assert reg.shape[0] == 64
+    for j in range(64):
+        want = [273, 273, 575] if j in (0, 63) else [340, 340, 703]
+        assert reg[j, 5:8].tolist() == want, j
+        assert reg[j, 4] == 0  # the tie goes to BLAS_first
+    assert not np.any(p["codelets"][:, C["flags"]] & F_RUNS)
+
+
+def _rows_csr(cols_per_row, n_cols):
+    rows = np.concatenate([np.full(len(c), i) for i, c in enumerate(cols_per_row)])
+    cols = np.concatenate([np.asarray(c) for c in cols_per_row])
+    return I.csr_from_pairs(len(cols_per_row), n_cols, rows, cols, np.ones(rows.size))
+
+
+def test_runs_table_strictly_smaller():
+    # Row q holds {q..q+3} and {q+10..q+13}: rectangular, rows and value offsets strided,
+    # separable (sigma0 = 1), columns not strided -> one PSC I codelet over the 4 rows.  Its
+    # shared pattern {0,1,2,3,10,11,12,13} has R = 2 runs: 2R = 4 < 8 plain offsets, so the
+    # table is runs (0, 4), (10, 4) and the cost is 32 + 3 + 4 = 39 for every strategy.
+    A = _rows_csr([np.r_[q:q + 4, q + 10:q + 14] for q in range(4)], 20)
+    p = O.inspect(0, A, 64)
+    assert p["codelets"].shape[0] == 1
+    c = dict(zip(O.COD_FIELDS, p["codelets"][0]))
+    assert c["flags"] == F_S0 | F_S1 | F_SEP | F_RECT | F_RUNS and c["type"] == 1
+    assert c["sigma0"] == 1 and c["col0"] == 0
+    assert p["aux"].tolist() == [0, 4, 10, 4]
+    assert c["cost"] == 39 and p["regions"][0, 4:8].tolist() == [0, 39, 39, 39]
+
+
+def test_runs_table_tie_stays_plain():
+    # Row q holds {q, q+1, q+5, q+6}: the shared pattern {0, 1, 5, 6} has R = 2 runs, and
+    # 2R = 4 equals its 4 plain offsets: the tie keeps the plain table.  Cost 16 + 3 + 4 = 23.
+    A = _rows_csr([[q, q + 1, q + 5, q + 6] for q in range(4)], 12)
+    p = O.inspect(0, A, 64)
+    c = dict(zip(O.COD_FIELDS, p["codelets"][0]))
+    assert c["flags"] == F_S0 | F_S1 | F_SEP | F_RECT
+    assert p["aux"].tolist() == [0, 1, 5, 6] and c["cost"] == 23
+
+
+def test_runs_full_table():
+    # Two rows {0..3, 10..13} and {1..4, 15..18}: rectangular (8 each), not separable (the
+    # column difference between the rows is 1 for the first run and 5 for the second).  PSC I
+    # with a full column table: 16 plain columns against R = 4 runs -> 2R = 8 < 16, runs
+    # (start, len) per row.  Cost 16 + 3 + 8 = 27; two single-row codelets would cost 2 * 15.
+    A = _rows_csr([np.r_[0:4, 10:14], np.r_[1:5, 15:19]], 20)
+    p = O.inspect(0, A, 64)
+    assert p["codelets"].shape[0] == 1
+    c = dict(zip(O.COD_FIELDS, p["codelets"][0]))
+    assert c["flags"] == F_S0 | F_S1 | F_RECT | F_RUNS and c["type"] == 1
+    assert p["aux"].tolist() == [0, 4, 10, 4, 1, 4, 15, 4] and c["cost"] == 27
+
+
+def test_pscii_first_strictly_cheapest():
+    # Rows of 5, 6, 5, 6 entries, each two runs: {q, q+1} and 3 or 4 columns from q+10.
+    # A single row is PSC I (its columns have strides 1, 9, 1 ...) and any two neighbours are
+    # ragged (only the rows stay strided), so BLAS_first and PSCI_first both cut one codelet
+    # per row, each with a shared pattern of R = 2 runs (2R = 4 < 5 or 6 offsets):
+    #   (5+3+4) + (6+3+4) + (5+3+4) + (6+3+4) = 50.
+    # PSCII_first keeps the 4 rows together (rows strided): |p| = 22, + 3, + 4 op starts, and
+    # full runs, 2 per row: 2 * 8 = 16 < 22 plain columns -> 22 + 3 + 4 + 16 = 45 (row counts
+    # are loop bounds, not costed).  PSCII_first is strictly cheapest and is chosen.
+    rows = [np.r_[q:q + 2, q + 10:q + 13 + (q % 2)] for q in range(4)]
+    A = _rows_csr(rows, 20)
+    p = O.inspect(0, A, 64)
+    reg = p["regions"][0]
+    assert reg[4:8].tolist() == [2, 50, 50, 45]
+    assert p["codelets"].shape[0] == 1
+    c = dict(zip(O.COD_FIELDS, p["codelets"][0]))
+    assert c["type"] == 2 and c["flags"] == F_S0 | F_RUNS and c["nn"] == -1 and c["cost"] == 45
+    # OPSTART, COUNTS, then the runs of each row (start, len)
+    assert p["aux"].tolist() == [0, 5, 11, 16, 5, 6, 5, 6,
+                                 0, 2, 10, 3, 1, 2, 11, 4, 2, 2, 12, 3, 3, 2, 13, 4]
+
+
 # ---------------------------------------------------------------- brute force + invariants
 
 def brute_flags(kind, A, rows):
@@ -129,6 +216,29 @@ def brute_flags(kind, A, rows):
             | (F_SEP if sep else 0) | F_RECT)
 
 
+def brute_runs(kind, A, q, fl):
+    """The column table is stored as runs when 2 x (maximal runs of consecutive columns) is
+    below its plain size: the shared pattern's nn offsets (SEP) or every column."""
+    if fl & F_S2:
+        return False
+    rp = A.row_ptr.astype(np.int64)
+    off = 1 if kind == 2 else 0
+    cut = 0 if kind == 0 else 1
+
+    def cols(r):
+        b = rp[r] + off
+        return A.col_idx[b:b + (rp[r + 1] - rp[r] - cut)].astype(np.int64)
+
+    def runs(c):
+        return 0 if c.size == 0 else 1 + int(np.count_nonzero(np.diff(c) != 1))
+
+    if fl & F_SEP:
+        c = cols(q[0])
+        return 2 * runs(c) < c.size
+    cs = [cols(r) for r in q]
+    return 2 * sum(runs(c) for c in cs) < sum(c.size for c in cs)
+
+
 def check_plan(kind, A, p, t=64):
     cod, reg = p["codelets"], p["regions"]
     # exact cover: decoding the plan reproduces the operations of the CSR
@@ -147,6 +257,7 @@ def check_plan(kind, A, p, t=64):
         q = pr[pp[r[0]] + r[1] + u: pp[r[0]] + r[1] + u + m]
         fl = brute_flags(kind, A, q)
         assert (rec[C["flags"]] & ~F_RUNS) == fl
+        assert bool(rec[C["flags"]] & F_RUNS) == brute_runs(kind, A, q, fl)
         k = ((fl & F_S0) != 0) + ((fl & F_S1) != 0) + ((fl & F_S2) != 0)
         assert rec[C["type"]] == 3 - k
     # the chosen strategy is the cheapest, ties to the first; its codelets add up to it
