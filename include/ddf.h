@@ -314,6 +314,12 @@ typedef struct {
                                  list entries [i0b, i0e), one lane per row, run from the CSR
                                  pattern)                                                      */
     int64_t n_rowlist;
+    const int32_t *df_tasks;  /* solve, persistent dataflow kernel: [n_df_tasks][4] codelet, first
+                                 row, end row (at most 8 rows), 0; in level order over all
+                                 matrices (which = 2: matrix after matrix)                     */
+    int64_t n_df_tasks;
+    const int64_t *df_ptr;    /* [n_df_ptr] task ranges: 0, n_df_tasks (which = 2: per matrix) */
+    int64_t n_df_ptr;
 } ddf_device_tables_t;
 ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
 

@@ -88,7 +88,9 @@ struct DevTables {
     std::vector<int32_t> aux;          // canonical aux followed by device supplements
     std::vector<Task> tasks;           // solve; SpMV with one right-hand side
     std::vector<Task> tasksN;          // SpMV with several right-hand sides
-    std::vector<int32_t> sync;         // solve: 4 int32 per task (wait counter, count, signal counter)
+    std::vector<int32_t> sync;         // solve: 4 int32 per task (wait counter, count, signal counter, level)
+    std::vector<Task> df_tasks;        // dataflow solve: up to DF_RG rows of one codelet, in level order
+    std::vector<int64_t> df_ptr;       // per-matrix ranges of df_tasks (per-matrix schedules only)
     int64_t n_counters = 0;            // solve: level counters the schedule uses
     int64_t csr_rows = 0, csr_nnz = 0; // SpMV, one right-hand side: rows run from the CSR pattern
     int64_t table_bytes1 = 0;          // plan bytes a one-RHS SpMV launch reads
@@ -116,17 +118,25 @@ struct DevTables {
     int32_t *d_aux = nullptr;
     Task *d_tasks = nullptr;
     DCod *d_tcods = nullptr;           // solve: the codelet record of each task, in task order
+    Task *d_df_tasks = nullptr;
+    DCod *d_df_tcods = nullptr;        // the codelet record of each dataflow task
     Task *d_tasksN = nullptr;
     int32_t *d_sync = nullptr;
     // device bytes of the tables (solve schedules add the per-task codelet copy)
     int64_t bytes() const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
-               (int64_t)tasks.size() * (sizeof(Task) + (sync.empty() ? 0 : sizeof(DCod))) + (int64_t)sync.size() * 4;
+               (int64_t)tasks.size() * (sizeof(Task) + (sync.empty() ? 0 : sizeof(DCod))) + (int64_t)sync.size() * 4 +
+               (int64_t)df_tasks.size() * (sizeof(Task) + sizeof(DCod));
     }
-    // plan bytes a multi-block solve reads: each task, its codelet copy and its sync entry, and aux
+    // plan bytes a one-launch-per-level solve reads: each task, its codelet copy and its sync
+    // entry, and aux
     int64_t solve_read_bytes() const {
         return (int64_t)aux.size() * 4 + (int64_t)tasks.size() * (sizeof(Task) + sizeof(DCod)) +
                (int64_t)sync.size() * 4;
+    }
+    // plan bytes the dataflow solve reads: each task and its codelet copy, and aux
+    int64_t df_read_bytes() const {
+        return (int64_t)aux.size() * 4 + (int64_t)df_tasks.size() * (sizeof(Task) + sizeof(DCod));
     }
     // plan bytes a single-block solve reads per call: gather index, level table, rows
     int64_t thin_bytes() const {

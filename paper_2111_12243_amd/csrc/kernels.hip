@@ -534,19 +534,9 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Persistent level-ordered solve (forward L x = b, or the adjoint U lam = g with U = L^T
-// read through perm, followed by the GV pass).
-//
-// Blocks take groups in ticket order.  A WIDE group is a slice of one level's tasks: its
-// waves exchange solution values with the rest of the device through device-scope (sc1)
-// loads and stores.  A THIN group is a run of consecutive small levels of one matrix, all
-// run by this block: levels are separated by block barriers, solution values stay in the
-// XCD's caches (one agent-scope acquire on entry, one release on exit), and each wave
-// loads the next level's rows, values and columns (none of which depend on the solution)
-// while it computes the current level.
+// Solve task body shared by the per-level kernel (k_solve_range): every row of one task, all
+// passes, all right-hand-side tiles (forward L x = b, or the adjoint U lam = g with U = L^T).
 // ------------------------------------------------------------------------------------------
-constexpr int PE = LOOKAHEAD;
-
 // A single-matrix call's bases are zero: no load on the task's dependent chain for them.
 __device__ __forceinline__ MatInfo mat_info(const SolveArgs &a, const DCod &c) {
     if (a.k_override > 0) return MatInfo{0, 0, 0, a.k_override, 0};
@@ -651,157 +641,187 @@ __device__ void solve_task(const SolveArgs &a, int t, int lane) {
     }
 }
 
-// What a wave loaded ahead for its task of the next thin level.
-struct Pre {
-    double v[PE];
-    int col[PE];
-    double diag;
-    int64_t vec_base;
-    int task, row, nops, lg, k;
-    bool active, fast;
+// ------------------------------------------------------------------------------------------
+// Dataflow solve: the whole solve (or transposed solve) in one persistent launch, with no
+// level barriers.  Each solution value is its own ready flag: before the launch the output
+// is filled with DF_SENT, a signalling NaN that no arithmetic result has (results are
+// quiet NaNs), and a task loads the solution values its rows need with device-coherent
+// loads (agent-scope relaxed atomics, which bypass the per-XCD caches), re-reading with
+// backoff those that still hold the sentinel; it stores its own results the same way.  An
+// 8-byte store is seen whole, so a value that is not the sentinel is final: no counters,
+// fences or flags are needed.
+//
+// A task is up to DF_RG rows of one codelet; tasks are in level order, a topological order of
+// the dependences.  KR lanes per row each own right-hand sides r, r + KR, ...; a pass of a
+// wave covers 64 / KR rows, that is 64 / (KR DF_RG) consecutive tasks.  The blocks first
+// check in: when all of them are resident at once, wave w runs passes w, w + V, w + 2V, ... of
+// the V waves (no atomics at all); when some are not (another kernel holds part of the
+// device), the first block to give up waiting switches every wave to passes taken in order
+// from an atomic ticket.  Either way the earliest unfinished task is held by a running wave
+// whose dependences are all complete, so the solve always progresses.  A wait longer than
+// the plan's spin limit raises the plan's error flag and stops waiting (the results are then
+// reported invalid by ddf_plan_sync_status); once the flag is up every wave stops waiting.
+// ------------------------------------------------------------------------------------------
+constexpr unsigned long long DF_SENT_BITS = 0x7FF4DDF0DDF0DDF0ull; // signalling NaN
+constexpr int DF_ARRIVE_POLLS = 400;                                 // check-in wait (~0.3 ms)
+
+__device__ __forceinline__ bool df_missing(double v) {
+    return (unsigned long long)__double_as_longlong(v) == DF_SENT_BITS;
+}
+
+// Columns of one row's ops in ascending order, for every column-table mode.
+struct ColIter {
+    int mode, base, j, cum, ln, st;
+    const int32_t *__restrict__ s;
+    __device__ __forceinline__ void init(const DCod &c, const int32_t *__restrict__ aux, int i0, const RowInfo &ri) {
+        mode = xmode(c.flags);
+        j = -1;
+        cum = ln = st = 0;
+        base = 0;
+        s = aux;
+        if (mode == XM_STRIDED || mode == XM_SHARED || mode == XM_SHARED_RUNS) base = c.col0 + i0 * c.sigma0;
+        if (mode == XM_SHARED || mode == XM_SHARED_RUNS) s = aux + c.xt_off;
+        else if (mode == XM_FULL) {
+            const int off = (c.flags & FRECT) ? i0 * c.nn : (c.flags & DCONTIG) ? ri.opst - c.op0 : aux[c.xp_off + i0];
+            s = aux + c.xt_off + off;
+        } else if (mode == XM_FULL_RUNS)
+            s = aux + c.xt_off + 2 * aux[c.xp_off + i0];
+    }
+    // column of op i1; in the run modes i1 must grow by one from call to call
+    __device__ __forceinline__ int col(const DCod &c, int i1) {
+        if (mode == XM_STRIDED) return base + i1 * c.sigma1;
+        if (mode == XM_SHARED || mode == XM_FULL) return base + s[i1];
+        while (i1 >= cum + ln) {
+            cum += ln;
+            ++j;
+            st = s[2 * j];
+            ln = s[2 * j + 1];
+        }
+        return base + st + (i1 - cum);
+    }
 };
 
-__device__ __forceinline__ int col_at(int mode, const DCod &c, const int32_t *__restrict__ aux, int i0,
-                                      const RowInfo &ri, int i1) {
-    if (mode == XM_STRIDED) return c.col0 + i0 * c.sigma0 + i1 * c.sigma1;
-    if (mode == XM_SHARED) return c.col0 + i0 * c.sigma0 + aux[c.xt_off + i1];
-    int off;
-    if (c.flags & FRECT)
-        off = i0 * c.nn;
-    else if (c.flags & DCONTIG)
-        off = ri.opst - c.op0;
-    else
-        off = aux[c.xp_off + i0];
-    return aux[c.xt_off + off + i1];
-}
-
-template <bool ADJ>
-__device__ __forceinline__ void pre_load(const SolveArgs &a, int t, int lane, Pre &p) {
-    p.task = t;
-    p.active = false;
-    p.fast = false;
-    if (t < 0) return;
-    const Task tk = a.tasks[t];
-    p.fast = (tk.meta >> 9) & 1;
-    if (!p.fast) return;
-    const DCod c = a.tcods ? a.tcods[t] : load_cod(a.cods + tk.cod);
+// One pass of a wave: rows of W consecutive tasks, KR lanes per row.  SINGLE: one matrix (the
+// adjoint's values already in U's order); else batch members, values through perm for the
+// adjoint.
+template <int KR, bool ADJ, bool SINGLE>
+__device__ __forceinline__ void df_pass(const SolveArgs &a, int p, int lane) {
+    constexpr int P = WAVE / KR, W = P / DF_RG;
+    const int slot = lane / KR, r = lane % KR;
+    const int t = p * W + slot / DF_RG, i = slot % DF_RG;
+    const int tc = min(t, a.ntasks - 1);
+    const Task tk = a.tasks[tc];
+    const DCod c = a.tcods[tc];
     const MatInfo mi = mat_info(a, c);
-    p.lg = tk.meta & 7;
-    p.k = a.k_override > 0 ? a.k_override : mi.k;
-    p.vec_base = mi.vec_base;
-    const int G = 1 << p.lg, g = lane & (G - 1);
-    const int i0 = tk.i0b + (lane >> p.lg);
-    p.active = i0 < tk.i0e;
-    if (!p.active) return;
+    const int k = mi.k;
+    const int i0 = tk.i0b + i;
+    const bool active = t < a.ntasks && i0 < tk.i0e;
     const double *__restrict__ vals = a.vals + mi.val_base;
-    const int32_t *__restrict__ perm = ADJ ? a.perm + mi.val_base : nullptr;
-    const RowInfo ri = row_info(c, a.aux, i0);
-    const int mode = xmode(c.flags);
-    p.row = ri.row;
-    p.nops = ri.nops;
-    const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
-    p.diag = ADJ ? vals[perm[dpos]] : vals[dpos];
-#pragma unroll
-    for (int j = 0; j < PE; j++) {
-        const int i1 = g + j * G;
-        p.v[j] = 0.0;
-        p.col[j] = 0;
-        if (i1 < ri.nops) {
-            const int e = ri.opst + i1;
-            p.v[j] = ADJ ? vals[perm[e]] : vals[e];
-            p.col[j] = col_at(mode, c, a.aux, i0, ri, i1);
-        }
+    const int32_t *__restrict__ perm = (ADJ && !SINGLE) ? a.perm + mi.val_base : nullptr;
+    const double *__restrict__ b = a.b + mi.vec_base;
+    double *x = a.x + mi.vec_base;
+    RowInfo ri{0, 0, 0};
+    double diag = 1.0;
+    if (active) {
+        ri = row_info(c, a.aux, i0);
+        const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
+        diag = (ADJ && !SINGLE) ? vals[perm[dpos]] : vals[dpos];
     }
-}
-
-template <int KT, bool ADJ, bool COH>
-__device__ __forceinline__ void pre_compute(const SolveArgs &a, const Pre &p, int lane) {
-    if (p.task < 0) return;
-    if (!p.fast) {
-        solve_task<KT, ADJ, COH>(a, p.task, lane);
-        return;
-    }
-    const int G = 1 << p.lg, g = lane & (G - 1);
-    const int k = p.k;
-    const double *__restrict__ b = a.b + p.vec_base;
-    double *x = a.x + p.vec_base;
-    const int64_t rb = (int64_t)p.row * k;
-    for (int r0 = 0; r0 < k; r0 += KT) {
-        double acc[KT];
+    unsigned *err = a.ctr + CTR_STRIDE;
+    for (int r0 = 0; r0 < k; r0 += KR) { // more right-hand sides than lanes: KR = 8 only
+        const int rr = r0 + r;
+        const int nops = (active && rr < k) ? ri.nops : 0;
+        ColIter it;
+        it.mode = XM_STRIDED; // lanes without a row read no table
+        it.base = 0;
+        if (active) it.init(c, a.aux, i0, ri);
+        double acc = 0.0;
+        for (int i1 = 0; __ballot(i1 < nops); i1 += DF_U) {
+            double v[DF_U], xv[DF_U];
+            int col[DF_U];
 #pragma unroll
-        for (int r = 0; r < KT; r++) acc[r] = 0.0;
-        if (p.active) {
-#pragma unroll
-            for (int j = 0; j < PE; j++) {
-                if (g + j * G < p.nops) {
-                    const double *xr = x + (int64_t)p.col[j] * k + r0;
-#pragma unroll
-                    for (int r = 0; r < KT; r++)
-                        if (r0 + r < k) acc[r] += p.v[j] * xload<COH>(xr + r);
-                }
+            for (int u = 0; u < DF_U; u++) {
+                const bool ok = i1 + u < nops;
+                col[u] = ok ? it.col(c, i1 + u) : 0;
+                const int e = ri.opst + i1 + u;
+                v[u] = ok ? ((ADJ && !SINGLE) ? vals[perm[e]] : vals[e]) : 0.0;
             }
-        }
-        group_sum<KT>(acc, G);
-        if (p.active) {
 #pragma unroll
-            for (int r = 0; r < KT; r++)
-                if ((r & (G - 1)) == g && r0 + r < k) xstore<COH>(x + rb + r0 + r, (b[rb + r0 + r] - acc[r]) / p.diag);
-        }
-    }
-}
-
-// Each wave takes tasks in ticket order.  A task of level l signals its level's counter
-// when done and waits, before computing, until level l-1's counter holds all of that
-// level's tasks; since a level only starts once the previous one is complete, that implies
-// every earlier level is complete.  Tickets follow the level order, so every task a wave
-// waits on is held by a running wave.  Counters live on separate 128-byte lines so the
-// waits on different levels do not contend; what a task reads that does not depend on the
-// solution is loaded before it waits.
-template <int KT, bool ADJ>
-__global__ __launch_bounds__(WAVE *WPB) void k_solve(SolveArgs a) {
-    const int lane = threadIdx.x % WAVE;
-    // lane 0 carries the increments; every lane issues the atomics so that no branch
-    // depends on the lane id (results are broadcast with readfirstlane)
-    const unsigned one = lane == 0 ? 1u : 0u;
-    unsigned *__restrict__ cnt = a.ctr + 2 * CTR_STRIDE;
-    for (;;) {
-        const int t = __builtin_amdgcn_readfirstlane(
-            (int)__hip_atomic_fetch_add(a.ctr, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        if (t >= a.ntasks) break;
-        const int4 sy = a.sync[t];
-        Pre pre;
-        pre.task = -1;
-        if (((a.tasks[t].meta >> 8) & 1) == 0) pre_load<ADJ>(a, t, lane, pre);
-        if (sy.x >= 0) {
-            // bounded wait with backoff; past the spin limit, or once another wave has
-            // tripped the error flag, stop waiting (the results are then reported invalid)
+            for (int u = 0; u < DF_U; u++) xv[u] = i1 + u < nops ? cload(x + (int64_t)col[u] * k + rr) : 0.0;
+            // wait for the values still missing: re-read them with backoff
             int64_t spins = 0;
             int back = 1;
             for (;;) {
-                const int d = __builtin_amdgcn_readfirstlane((int)cload_u(cnt + (int64_t)sy.x * CTR_STRIDE));
-                if (d >= sy.y) break;
+                bool miss = false;
+#pragma unroll
+                for (int u = 0; u < DF_U; u++) miss = miss || df_missing(xv[u]);
+                if (!__ballot(miss)) break;
                 for (int z = 0; z < back; z++) __builtin_amdgcn_s_sleep(1);
                 if (back < a.backoff_max) back <<= 1;
                 spins += back;
                 bool trip = spins > a.spin_limit;
-                if ((spins & 1023) < back)
-                    trip = trip || __builtin_amdgcn_readfirstlane((int)cload_u(a.ctr + CTR_STRIDE)) != 0;
-                if (trip) {
-                    __hip_atomic_store(a.ctr + CTR_STRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((spins & 1023) < back) trip = trip || cload_u(err) != 0u;
+                if (__ballot(trip)) {
+                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
+#pragma unroll
+                for (int u = 0; u < DF_U; u++)
+                    if (df_missing(xv[u])) xv[u] = cload(x + (int64_t)col[u] * k + rr);
             }
+#pragma unroll
+            for (int u = 0; u < DF_U; u++) acc = fma(v[u], xv[u], acc);
         }
-        asm volatile("" ::: "memory");
-        if (pre.task >= 0)
-            pre_compute<KT, ADJ, true>(a, pre, lane);
-        else
-            solve_task<KT, ADJ, true>(a, t, lane);
-        // this wave's device-scope stores are complete before its level's counter moves
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        if (sy.z >= 0)
-            __hip_atomic_fetch_add(cnt + (int64_t)sy.z * CTR_STRIDE, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (active && rr < k) {
+            const int64_t o = (int64_t)ri.row * k + rr;
+            double res = (b[o] - acc) / diag;
+            if (df_missing(res)) res = __longlong_as_double(0x7FF8000000000000ll); // never: quiet results
+            cstore(x + o, res);
+        }
     }
+}
+
+// ctr lines: 0 ticket, 1 error flag, 2 check-in count, 3 mode (0 undecided, 1 static, 2 ticket)
+template <int KR, bool ADJ, bool SINGLE>
+__global__ __launch_bounds__(WAVE *WPB) void k_solve_df(SolveArgs a) {
+    __shared__ int s_mode;
+    unsigned *ticket = a.ctr, *arrive = a.ctr + 2 * CTR_STRIDE, *mode_w = a.ctr + 3 * CTR_STRIDE;
+    if (threadIdx.x == 0) {
+        const unsigned n = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        unsigned want = 0u;
+        if (n == gridDim.x) __hip_atomic_compare_exchange_strong(mode_w, &want, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+        unsigned m = cload_u(mode_w);
+        for (int polls = 0; m == 0u; polls++) {
+            if (polls >= DF_ARRIVE_POLLS) {
+                want = 0u;
+                __hip_atomic_compare_exchange_strong(mode_w, &want, 2u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __builtin_amdgcn_s_sleep(8);
+            m = cload_u(mode_w);
+        }
+        s_mode = (int)m;
+    }
+    __syncthreads();
+    const int mode = s_mode;
+    const int lane = threadIdx.x % WAVE;
+    const unsigned one = lane == 0 ? 1u : 0u;
+    const int nw = (int)gridDim.x * WPB;
+    int p = mode == 1 ? (int)blockIdx.x * WPB + (int)threadIdx.x / WAVE
+                      : __builtin_amdgcn_readfirstlane(
+                            (int)__hip_atomic_fetch_add(ticket, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    while (p < a.npass) {
+        df_pass<KR, ADJ, SINGLE>(a, p, lane);
+        p = mode == 1 ? p + nw
+                      : __builtin_amdgcn_readfirstlane(
+                            (int)__hip_atomic_fetch_add(ticket, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < n; i += (int64_t)blockDim.x * gridDim.x)
+        p[i] = v;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1324,7 +1344,8 @@ hipError_t init_device_info() {
     int dev = 0, ncu = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<8, true>, WAVE * WPB, 0);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve_df<8, true, false>, WAVE * WPB, 0);
     if (e != hipSuccess) return e;
     g_num_cu = ncu > 0 ? ncu : 1;
     g_solve_blocks = (nb > 0 ? nb : 1) * g_num_cu;
@@ -1425,6 +1446,7 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
 }
 
 int num_cu() { return g_num_cu > 0 ? g_num_cu : 256; }
+int resident_solve_blocks() { return g_solve_blocks > 0 ? g_solve_blocks : 1024; }
 
 // One level's tasks per launch (the launch boundaries order the levels): plain loads and
 // stores, no tickets, no waits.  SINGLE (single-matrix calls): four ops' column reads ahead
@@ -1472,24 +1494,53 @@ hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s) {
-    if (a.ntasks == 0) return hipSuccess;
-    int nb;
-#define DDF_SOLVE_CASE(K, A)                                                                        \
-    nb = solve_grid(a.ntasks, blocks);                                                              \
-    hipLaunchKernelGGL((k_solve<K, A>), dim3(nb), dim3(WAVE * WPB), 0, s, a);                       \
-    break;
-    switch (kt * 2 + (adj ? 1 : 0)) {
-    case 2: DDF_SOLVE_CASE(1, false)
-    case 3: DDF_SOLVE_CASE(1, true)
-    case 4: DDF_SOLVE_CASE(2, false)
-    case 5: DDF_SOLVE_CASE(2, true)
-    case 8: DDF_SOLVE_CASE(4, false)
-    case 9: DDF_SOLVE_CASE(4, true)
-    case 16: DDF_SOLVE_CASE(8, false)
-    default: DDF_SOLVE_CASE(8, true)
+int df_lanes(int k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; }
+
+hipError_t launch_fill_u64(void *p, int64_t n, unsigned long long v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)nb), dim3(256), 0, s, (unsigned long long *)p, n, v);
+    return hipGetLastError();
+}
+
+// Clears the dataflow solve's ticket, check-in count and mode (not the error flag, which
+// ddf_plan_sync_status reads and clears).
+__global__ void k_df_reset(unsigned *ctr) {
+    const int i = threadIdx.x;
+    if (i < CTR_STRIDE) ctr[i] = 0u;
+    else if (i < 3 * CTR_STRIDE) ctr[CTR_STRIDE + i] = 0u;
+}
+
+hipError_t launch_df_reset(unsigned *ctr, hipStream_t s) {
+    hipLaunchKernelGGL(k_df_reset, dim3(1), dim3(3 * CTR_STRIDE), 0, s, ctr);
+    return hipGetLastError();
+}
+
+// The output block [fill, fill + nfill) marked unsolved, then one persistent launch: a.npass
+// passes of kr lanes per row, `blocks` 256-thread blocks (0: every block the device keeps
+// resident at once).
+hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool single, int kr, int blocks, double *fill, int64_t nfill,
+                           hipStream_t s) {
+    if (a.npass <= 0) return hipSuccess;
+    hipError_t e = launch_fill_u64(fill, nfill, DF_SENT_BITS, s);
+    if (e != hipSuccess) return e;
+    const int nb = solve_grid(a.npass, blocks);
+#define DDF_DF(KR, A, S) hipLaunchKernelGGL((k_solve_df<KR, A, S>), dim3(nb), dim3(WAVE * WPB), 0, s, a)
+#define DDF_DF_KR(A, S)                                                                             \
+    switch (kr) {                                                                                   \
+    case 1: DDF_DF(1, A, S); break;                                                                 \
+    case 2: DDF_DF(2, A, S); break;                                                                 \
+    case 4: DDF_DF(4, A, S); break;                                                                 \
+    default: DDF_DF(8, A, S); break;                                                                \
     }
-#undef DDF_SOLVE_CASE
+    if (single) {
+        if (adj) DDF_DF_KR(true, true) else DDF_DF_KR(false, true)
+    } else {
+        if (adj) DDF_DF_KR(true, false) else DDF_DF_KR(false, false)
+    }
+#undef DDF_DF_KR
+#undef DDF_DF
     return hipGetLastError();
 }
 

@@ -106,10 +106,8 @@ struct ThinArgs {
     unsigned *sink;     // helpers' discard word (never read)
 };
 
-constexpr int LOOKAHEAD = 4;   // elements per lane a solve task loads before its wait
 constexpr int CTR_STRIDE = 32; // uint32 per counter line (128 bytes)
-enum : int32_t { TASK_FAST = 1 << 9,     // solve: thin-range task whose rows fit the look-ahead registers
-                 TASK_STREAM = 1 << 10,   // SpMV: one-RHS task streamed element by element
+enum : int32_t { TASK_STREAM = 1 << 10,   // SpMV: one-RHS task streamed element by element
                  TASK_CSR = 1 << 11,      // SpMV, one RHS: rows [i0b, i0e) of the CSR pattern
                  TASK_LONG = 1 << 12,     // with TASK_CSR: one row longer than a stream task
                  TASK_ROWS = 1 << 13 };   // SpMV, one RHS: rows list[i0b, i0e) (<= 64), a lane each
@@ -137,7 +135,12 @@ struct SolveArgs {
     unsigned *ctr;       // lines of CTR_STRIDE: ticket, error flag, then one counter per level
     int64_t spin_limit;
     int32_t k_override; // > 0: right-hand sides of a single-matrix call
+    int32_t npass;      // dataflow solve: wave passes (each 64 / KR rows, DF_RG rows per task)
 };
+constexpr int WAVE_LANES = 64;
+constexpr int DF_RG = 8;  // dataflow solve: rows per task (one codelet's)
+constexpr int DF_PASS_MAX = 8; // dataflow solve: most tasks one wave pass takes (one right-hand side)
+constexpr int DF_U = 16;  // dataflow solve: ops per lane loaded before a wait
 
 struct PlainArgs {
     const int32_t *rp;
@@ -177,9 +180,13 @@ int kt_for(int k);
 hipError_t init_device_info();
 hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s);
 int kr_for(int k);
-hipError_t launch_solve(const SolveArgs &a, bool adj, int kt, int blocks, hipStream_t s);
+int df_lanes(int k); // lanes per row of the dataflow solve for k right-hand sides
+hipError_t launch_df_reset(unsigned *ctr, hipStream_t s);
+hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool single, int kr, int blocks, double *fill, int64_t nfill,
+                           hipStream_t s);
 hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t s);
 int num_cu();
+int resident_solve_blocks(); // 256-thread blocks of the dataflow solve the device keeps resident
 hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s);
 hipError_t launch_thin_codes(const ThinArgs &a, hipStream_t s);

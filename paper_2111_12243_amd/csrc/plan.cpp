@@ -41,7 +41,6 @@ struct ddf_plan_s {
     int64_t n_rows = 0, n_cols = 0, nnz = 0, vec_total = 0;
     SchedParams sp_f, sp_a;
     DevTables F, T, Fpm;
-    std::vector<int64_t> pm_task_ptr; // per-matrix ranges of Fpm.tasks
     int64_t n_solve_tasks_adj = 0;    // adjoint: tasks before the GV pass
     int64_t ctr_words_f = 0;          // counter words of the forward solves
     int64_t ctr_words_a = 0;          // and of the adjoint's (after them, in the same allocation)
@@ -240,18 +239,14 @@ int lg_of(int64_t n, int opl) {
     return lg;
 }
 
-// Tasks of one codelet: rows grouped so that a task's lanes-per-row fits its rows.  A task
-// that a single pass covers, on a plain column table, with every row within the look-ahead
-// registers is marked TASK_FAST.
+// Tasks of one codelet: rows grouped so that a task's lanes-per-row fits its rows.
 void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_index, const SchedParams &sp,
                    int phase, std::vector<Task> &out) {
     const int32_t m = d.m;
     auto nops_of = [&](int32_t a) -> int64_t { return (d.flags & FRECT) ? d.nn : aux[d.cnt_off + a]; };
-    const int mode = xmode_host(d.flags);
     int32_t a = 0;
     while (a < m) {
         int lg = lg_of(nops_of(a), sp.ops_per_lane);
-        int64_t mx = nops_of(a);
         int32_t b = a + 1;
         while (b < m) {
             int lgb = lg_of(nops_of(b), sp.ops_per_lane);
@@ -259,14 +254,9 @@ void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_i
             if (lgb + 2 < lg || lgb > lg + 1) break;
             if ((b - a + 1) > (64 >> lgn) * sp.passes) break;
             lg = lgn;
-            mx = std::max(mx, nops_of(b));
             b++;
         }
-        int meta = lg | (phase << 8);
-        if (phase == 0 && (b - a) <= (64 >> lg) && (mode == 0 || mode == 1 || mode == 3) &&
-            mx <= ((int64_t)LOOKAHEAD << lg))
-            meta |= TASK_FAST;
-        out.push_back({cod_index, a, b, meta});
+        out.push_back({cod_index, a, b, lg | (phase << 8)});
         a = b;
     }
 }
@@ -470,6 +460,54 @@ void append_gv(const DevTables &F, int64_t c0, int64_t c1, std::pair<int64_t, in
     }
 }
 
+// Dataflow-solve tasks: level by level over all matrices (a topological order of every
+// matrix's dependences), each codelet's rows in groups of up to DF_RG.  A wave pass takes 1, 2,
+// 4 or 8 consecutive tasks (by the right-hand-side count) starting at a multiple of that
+// count, and its rows must not depend on each other: every level's list is padded with empty
+// tasks (no rows) to a multiple of 8.  by_matrix: matrix after matrix instead (per-matrix
+// launches), with each matrix's range in ptr.
+void build_df(const DevTables &D, const std::vector<int64_t> &cod_begin, const std::vector<std::vector<int32_t>> &levels,
+              bool by_matrix, std::vector<Task> &out, std::vector<int64_t> &ptr) {
+    const int nm = (int)cod_begin.size() - 1;
+    out.clear();
+    ptr.assign(1, 0);
+    auto emit = [&](int64_t c) {
+        const int32_t m = D.cods[c].m;
+        for (int32_t a = 0; a < m; a += DF_RG) out.push_back({(int32_t)c, a, std::min(m, a + DF_RG), 0});
+    };
+    auto pad = [&]() {
+        while (out.size() % DF_PASS_MAX) out.push_back({out.back().cod, 0, 0, 0});
+    };
+    // codelets of a matrix come in level order: per matrix, the first codelet of each level
+    std::vector<std::vector<int64_t>> lvl_begin(nm);
+    int32_t maxl = 0;
+    for (int b = 0; b < nm; b++) {
+        int32_t nl = 0;
+        for (int32_t l : levels[b]) nl = std::max(nl, l + 1);
+        maxl = std::max(maxl, nl);
+        lvl_begin[b].assign(nl + 1, cod_begin[b + 1]);
+        for (int64_t c = cod_begin[b + 1] - 1; c >= cod_begin[b]; c--) lvl_begin[b][levels[b][c - cod_begin[b]]] = c;
+        for (int32_t l = nl - 1; l >= 0; l--) lvl_begin[b][l] = std::min(lvl_begin[b][l], lvl_begin[b][l + 1]);
+    }
+    if (by_matrix) {
+        for (int b = 0; b < nm; b++) {
+            for (int32_t l = 0; l + 1 < (int32_t)lvl_begin[b].size(); l++) {
+                for (int64_t c = lvl_begin[b][l]; c < lvl_begin[b][l + 1]; c++) emit(c);
+                if (!out.empty()) pad();
+            }
+            ptr.push_back((int64_t)out.size());
+        }
+        return;
+    }
+    for (int32_t l = 0; l < maxl; l++) {
+        for (int b = 0; b < nm; b++)
+            if (l + 1 < (int32_t)lvl_begin[b].size())
+                for (int64_t c = lvl_begin[b][l]; c < lvl_begin[b][l + 1]; c++) emit(c);
+        if (!out.empty()) pad();
+    }
+    ptr.push_back((int64_t)out.size());
+}
+
 void drop_alloc(ddf_plan_t p, void *ptr) {
     if (!ptr) return;
     auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
@@ -485,6 +523,10 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     drop_alloc(p, D.d_sync);
     drop_alloc(p, D.d_rowlist);
     drop_alloc(p, D.d_tcods);
+    drop_alloc(p, D.d_df_tasks);
+    drop_alloc(p, D.d_df_tcods);
+    D.d_df_tasks = nullptr;
+    D.d_df_tcods = nullptr;
     D.d_tasks = nullptr;
     D.d_tasksN = nullptr;
     D.d_sync = nullptr;
@@ -502,6 +544,13 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
             tc[i] = (fwd_plan ? p->F.cods : (&D == &p->T ? p->T.cods : p->F.cods))[t.cod];
         }
         s = upload(p, &D.d_tcods, tc.data(), tc.size());
+    }
+    if (!s && !D.df_tasks.empty()) {
+        const std::vector<DCod> &cods = &D == &p->T ? p->T.cods : p->F.cods;
+        std::vector<DCod> tc(D.df_tasks.size());
+        for (size_t i = 0; i < D.df_tasks.size(); i++) tc[i] = cods[D.df_tasks[i].cod];
+        s = upload(p, &D.d_df_tasks, D.df_tasks.data(), D.df_tasks.size());
+        if (!s) s = upload(p, &D.d_df_tcods, tc.data(), tc.size());
     }
     if (!s && !D.rowlist.empty()) s = upload(p, &D.d_rowlist, D.rowlist.data(), D.rowlist.size());
     if (!s && !D.tasksN.empty()) s = upload(p, &D.d_tasksN, D.tasksN.data(), D.tasksN.size());
@@ -812,8 +861,8 @@ void build_thin(const Canon &c, const Pattern &P, const std::vector<int32_t> *pe
 // schedule.  Grown (never shrunk) when a schedule needs more.
 ddf_status ensure_counters(ddf_plan_t p) {
     if (p->host_only || p->kind == DDF_SPMV) return DDF_OK;
-    const int64_t nf = std::max(p->ctr_words_f, (2 + std::max(p->F.n_counters, p->Fpm.n_counters)) * CTR_STRIDE);
-    const int64_t na = std::max(p->ctr_words_a, (2 + p->T.n_counters) * CTR_STRIDE);
+    const int64_t nf = std::max<int64_t>(p->ctr_words_f, 4 * CTR_STRIDE);
+    const int64_t na = std::max<int64_t>(p->ctr_words_a, 4 * CTR_STRIDE);
     if (p->d_ctr && nf <= p->ctr_words_f && na <= p->ctr_words_a) return DDF_OK;
     drop_alloc(p, p->d_ctr);
     p->d_ctr = p->d_ctr_adj = nullptr;
@@ -891,21 +940,11 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
         p->F.sync.clear();
         p->F.n_counters = 0;
         build_solve(p->F, cb, lv, p->sp_f, p->F.tasks, p->F.sync, p->F.n_counters);
+        build_df(p->F, cb, lv, false, p->F.df_tasks, p->F.df_ptr);
         if (ddf_status s = upload_tasks(p, p->F)) return s;
         if (p->batch) {
-            // per-matrix schedules for the one-launch-per-matrix comparator
-            p->Fpm.tasks.clear();
-            p->Fpm.sync.clear();
-            p->Fpm.n_counters = 0;
-            p->pm_task_ptr.assign(1, 0);
-            for (int b = 0; b < p->nmat; b++) {
-                std::vector<int64_t> one = {cb[b], cb[b + 1]};
-                std::vector<std::vector<int32_t>> l1 = {lv[b]};
-                int64_t nc = 0; // every per-matrix launch resets and reuses counters from 0
-                build_solve(p->F, one, l1, p->sp_f, p->Fpm.tasks, p->Fpm.sync, nc);
-                p->Fpm.n_counters = std::max(p->Fpm.n_counters, nc);
-                p->pm_task_ptr.push_back((int64_t)p->Fpm.tasks.size());
-            }
+            // per-matrix dataflow schedules for the one-launch-per-matrix comparator
+            build_df(p->F, cb, lv, true, p->Fpm.df_tasks, p->Fpm.df_ptr);
             if (ddf_status s = upload_tasks(p, p->Fpm)) return s;
         }
     }
@@ -920,6 +959,7 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
         p->T.sync.clear();
         p->T.n_counters = 0;
         auto last = build_solve(p->T, cba, lva, p->sp_a, p->T.tasks, p->T.sync, p->T.n_counters);
+        build_df(p->T, cba, lva, false, p->T.df_tasks, p->T.df_ptr);
         p->n_solve_tasks_adj = (int64_t)p->T.tasks.size();
         for (int b = 0; b < p->nmat; b++) append_gv(p->F, cb[b], cb[b + 1], last[b], p->sp_a, p->T.tasks, p->T.sync);
         if (ddf_status s = upload_tasks(p, p->T)) return s;
@@ -1220,9 +1260,14 @@ ddf_status check_nrhs(int32_t k) {
 
 const double *vals_or_own(ddf_plan_t p, const double *v) { return v ? v : p->d_vals; }
 
-ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t ntasks, int64_t ncounters, bool adj,
-                        const double *vals, const double *b, double *x, const double *xf, double *gv,
-                        int32_t k_override, int kt, hipStream_t s) {
+// One solve (adj: the transposed solve) over a schedule: tasks [t0, t0 + ntasks) of the
+// one-launch-per-level lists (the batch adjoint's value-gradient tasks come last, level -1).
+// Path 1 runs the dataflow tasks of D instead (matrix `mat` of a per-matrix schedule, or all),
+// then any value-gradient tasks in one more launch.  An in-place call (b == x) takes one launch
+// per level: the dataflow solve marks the output as not yet solved before it starts.
+ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t ntasks, bool adj, const double *vals,
+                        const double *b, double *x, const double *xf, double *gv, int32_t k_override, int kt,
+                        hipStream_t s, int mat = -1) {
     const SchedParams &sp = adj ? p->sp_a : p->sp_f;
     SolveArgs a{};
     a.cods = adj ? p->T.d_cods : p->F.d_cods;
@@ -1231,7 +1276,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.aux2 = p->F.d_aux;
     a.tasks = D.d_tasks + t0;
     a.tcods = D.d_tcods ? D.d_tcods + t0 : nullptr;
-    a.sync = reinterpret_cast<const int4 *>(D.d_sync) + t0;
+    a.sync = D.d_sync ? reinterpret_cast<const int4 *>(D.d_sync) + t0 : nullptr;
     a.ntasks = (int32_t)ntasks;
     a.backoff_max = sp.backoff > 0 ? sp.backoff : 16;
     a.mats = p->d_mats;
@@ -1244,33 +1289,61 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.ctr = adj ? p->d_ctr_adj : p->d_ctr;
     a.spin_limit = p->spin_limit;
     a.k_override = k_override;
-    if (sp.path == 3) {
-        // one launch per level (task ranges of equal level, over all matrices of a batch; the
-        // GV tasks last).  The transposed solve of one matrix first gathers its values in
-        // transposed order, so that no level reads them through perm.
-        if (adj && k_override > 0 && p->d_valsT && p->nnz) {
-            HIPCHK(launch_gather(p->d_valsT, vals, p->d_perm, p->nnz, s));
-            a.vals = p->d_valsT;
+    const bool single = k_override > 0;
+    // the transposed solve of one matrix gathers its values in transposed order first, so that
+    // no task reads them through perm
+    if (adj && single && p->d_valsT && p->nnz) {
+        HIPCHK(launch_gather(p->d_valsT, vals, p->d_perm, p->nnz, s));
+        a.vals = p->d_valsT;
+    }
+    if (sp.path == 1 && b != x && !D.df_tasks.empty()) {
+        const int64_t d0 = mat >= 0 ? D.df_ptr[mat] : 0;
+        const int64_t d1 = mat >= 0 ? D.df_ptr[mat + 1] : (int64_t)D.df_tasks.size();
+        SolveArgs df = a;
+        df.tasks = D.d_df_tasks + d0;
+        df.tcods = D.d_df_tcods + d0;
+        df.ntasks = (int32_t)(d1 - d0);
+        const int kr = single ? df_lanes(k_override) : 8;
+        const int per_pass = WAVE_LANES / kr / DF_RG;
+        df.npass = (int32_t)((df.ntasks + per_pass - 1) / per_pass);
+        // the output block the tasks write: marked not yet solved before the launch
+        double *fill = x;
+        int64_t nfill = single ? p->n_rows * (int64_t)k_override : p->vec_total;
+        if (mat >= 0) {
+            fill = x + p->mats[mat].vec_base;
+            nfill = (int64_t)p->mats[mat].n * p->mats[mat].k;
         }
-        const Task *tk = a.tasks;
-        const DCod *tc = a.tcods;
-        const int4 *sy = a.sync;
-        int64_t i = 0;
-        while (i < ntasks) {
-            const int32_t lev = D.sync[(t0 + i) * 4 + 3];
-            int64_t j = i + 1;
-            while (j < ntasks && D.sync[(t0 + j) * 4 + 3] == lev) j++;
-            a.tasks = tk + i;
-            a.tcods = tc ? tc + i : nullptr;
-            a.sync = sy + i;
-            a.ntasks = (int32_t)(j - i);
+        if (df.ntasks > 0) {
+            HIPCHK(launch_df_reset(df.ctr, s));
+            HIPCHK(launch_solve_df(df, adj, single, kr, sp.blocks, fill, nfill, s));
+        }
+        const int64_t ngv = adj ? ntasks - p->n_solve_tasks_adj : 0;
+        if (ngv > 0) { // the batch adjoint's value gradient, after the solve
+            a.tasks += p->n_solve_tasks_adj;
+            if (a.tcods) a.tcods += p->n_solve_tasks_adj;
+            a.sync += p->n_solve_tasks_adj;
+            a.ntasks = (int32_t)ngv;
             HIPCHK(launch_solve_range(a, adj, kt, s));
-            i = j;
         }
         return DDF_OK;
     }
-    HIPCHK(launch_reset(a.ctr, (2 + ncounters) * CTR_STRIDE, s));
-    HIPCHK(launch_solve(a, adj, kt, sp.blocks, s));
+    // one launch per level (task ranges of equal level, over all matrices of a batch; the GV
+    // tasks last)
+    const Task *tk = a.tasks;
+    const DCod *tc = a.tcods;
+    const int4 *sy = a.sync;
+    int64_t i = 0;
+    while (i < ntasks) {
+        const int32_t lev = D.sync[(t0 + i) * 4 + 3];
+        int64_t j = i + 1;
+        while (j < ntasks && D.sync[(t0 + j) * 4 + 3] == lev) j++;
+        a.tasks = tk + i;
+        a.tcods = tc ? tc + i : nullptr;
+        a.sync = sy + i;
+        a.ntasks = (int32_t)(j - i);
+        HIPCHK(launch_solve_range(a, adj, kt, s));
+        i = j;
+    }
     return DDF_OK;
 }
 
@@ -1405,7 +1478,7 @@ ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, d
     if (use_thin(p->F, p->sp_f, nrhs))
         return thin_launch(p, p->F, p->sp_f, p->F.thin_nlev, d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
     // the single matrix's right-hand-side count is a per-call argument (k_override)
-    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), p->F.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
+    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
                         kt_for(nrhs), (hipStream_t)stream);
 }
 
@@ -1473,8 +1546,8 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
     hipStream_t s = (hipStream_t)stream;
     if (use_thin(p->T, p->sp_a, nrhs)) {
         if (ddf_status st = thin_launch(p, p->T, p->sp_a, p->T.thin_nlev, d_vals, d_gx, d_gb, nrhs, s)) return st;
-    } else if (ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, p->T.n_counters, true, d_vals, d_gx,
-                                            d_gb, d_x, nullptr, nrhs, kt_for(nrhs), s)) {
+    } else if (ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, true, d_vals, d_gx, d_gb, d_x, nullptr,
+                                            nrhs, kt_for(nrhs), s)) {
         return st;
     }
     if (d_gvals) HIPCHK(launch_gv_pass(p, d_gb, d_x, d_gvals, -1.0, nrhs, s));
@@ -1510,7 +1583,7 @@ ddf_status ddf_sptrsv_batch(ddf_plan_t p, const double *d_vals, const double *d_
     int64_t nb = p->vec_total * 8;
     if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
-    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), p->F.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
+    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nullptr, nullptr, 0,
                         batch_kt(p), (hipStream_t)stream);
 }
 
@@ -1525,8 +1598,7 @@ ddf_status ddf_sptrsv_batch_adjoint(ddf_plan_t p, const double *d_vals, const do
     if (d_gb != d_gx && overlap(d_gb, nb, d_gx, nb)) return fail(DDF_E_ARG, "gb and gx partially overlap");
     if (overlap(d_gb, nb, d_x, nb)) return fail(DDF_E_ARG, "gb overlaps x");
     int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
-    return solve_launch(p, p->T, 0, nt, p->T.n_counters, true, d_vals, d_gx, d_gb, d_x, d_gvals, 0, batch_kt(p),
-                        (hipStream_t)stream);
+    return solve_launch(p, p->T, 0, nt, true, d_vals, d_gx, d_gb, d_x, d_gvals, 0, batch_kt(p), (hipStream_t)stream);
 }
 
 ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t p, const double *d_vals, const double *d_b, double *d_x,
@@ -1535,12 +1607,16 @@ ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t p, const double *d_vals, const
     if (!p->batch) return fail(DDF_E_KIND, "plan is not a batch plan");
     d_vals = vals_or_own(p, d_vals);
     if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
-    for (int b = 0; b < p->nmat; b++) {
-        int64_t t0 = p->pm_task_ptr[b], t1 = p->pm_task_ptr[b + 1];
-        if (ddf_status s = solve_launch(p, p->Fpm, t0, t1 - t0, p->Fpm.n_counters, false, d_vals, d_b, d_x, nullptr, nullptr, 0,
-                                        kt_for(p->mats[b].k), (hipStream_t)stream))
-            return s;
-    }
+    if (d_b == d_x) return fail(DDF_E_ARG, "the per-matrix comparator does not run in place");
+    // matrix after matrix: one dataflow launch each (the batch schedule's per-matrix lists)
+    const int path = p->sp_f.path;
+    p->sp_f.path = 1;
+    ddf_status st = DDF_OK;
+    for (int b = 0; b < p->nmat && !st; b++)
+        st = solve_launch(p, p->Fpm, 0, 0, false, d_vals, d_b, d_x, nullptr, nullptr, 0, kt_for(p->mats[b].k),
+                          (hipStream_t)stream, b);
+    p->sp_f.path = path;
+    return st;
     return DDF_OK;
 }
 
@@ -1784,6 +1860,10 @@ ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables
     o->thin_block = D->thin_block;
     o->rowlist = D->rowlist.data();
     o->n_rowlist = (int64_t)D->rowlist.size();
+    o->df_tasks = reinterpret_cast<const int32_t *>(D->df_tasks.data());
+    o->n_df_tasks = (int64_t)D->df_tasks.size();
+    o->df_ptr = D->df_ptr.data();
+    o->n_df_ptr = (int64_t)D->df_ptr.size();
     return DDF_OK;
 }
 
@@ -1811,7 +1891,10 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
         break;
     case DDF_OP_SPTRSV:
-        ba = 8 * nnz + (!p->batch && use_thin(p->F, p->sp_f, nrhs) ? p->F.thin_bytes() : p->F.solve_read_bytes()) +
+        ba = 8 * nnz +
+             (!p->batch && use_thin(p->F, p->sp_f, nrhs) ? p->F.thin_bytes()
+              : p->sp_f.path == 1                        ? p->F.df_read_bytes()
+                                                         : p->F.solve_read_bytes()) +
              16 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
         if (p->batch) {
@@ -1825,13 +1908,16 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         break;
     case DDF_OP_SPTRSV_ADJ:
         // transposed solve, then the value gradient over the CSR pattern (columns and row pointers)
+        // (batches: the value-gradient tasks read L's forward plan; one matrix: the values are
+        // first copied in transposed order, written and read back)
         if (p->has_adj && !p->batch && use_thin(p->T, p->sp_a, nrhs))
             ba = 20 * nnz + p->T.thin_bytes() + 4 * (n + 1) + 24 * vk;
         else if (p->batch)
-            ba = 20 * nnz + (p->has_adj ? p->T.solve_read_bytes() : 0) + Fca + 32 * vk;
+            ba = 20 * nnz + (p->has_adj ? (p->sp_a.path == 1 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
+                 Fca + 32 * vk;
         else
-            ba = 24 * nnz + (p->has_adj ? p->T.solve_read_bytes() : 0) + 4 * (n + 1) + 32 * vk +
-                 (p->sp_a.path == 3 ? 16 * nnz : 0); // the values' transposed copy: written, read back
+            ba = 24 * nnz + (p->has_adj ? (p->sp_a.path == 1 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
+                 4 * (n + 1) + 32 * vk + 16 * nnz;
         bc = 20 * nnz + 4 * (n + 1) + 24 * vk;
         if (p->batch) {
             for (size_t b = 0; b < p->mats.size(); b++) {
@@ -1847,9 +1933,11 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         if (!p->batch && use_thin(p->T, p->sp_a, nrhs))
             ba = 8 * nnz + p->T.thin_bytes() + 16 * vk;
         else
-            ba = 8 * nnz + (int64_t)p->T.aux.size() * 4 +
-                 p->n_solve_tasks_adj * (int64_t)(sizeof(Task) + sizeof(DCod) + 16) + 16 * vk +
-                 (!p->batch && p->sp_a.path == 3 ? 16 * nnz : 0);
+            ba = 8 * nnz +
+                 (p->sp_a.path == 1 ? p->T.df_read_bytes()
+                                    : (int64_t)p->T.aux.size() * 4 +
+                                          p->n_solve_tasks_adj * (int64_t)(sizeof(Task) + sizeof(DCod) + 16)) +
+                 16 * vk + (!p->batch ? 16 * nnz : 0);
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
         fl = p->batch ? 0 : kf * (2 * (nnz - n) + n);
         break;
@@ -2000,10 +2088,10 @@ extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_st
         if (!p->batch)
             for (int opl : {2, 1, 4})
                 for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, 0, 3, target.helpers, target.ahead});
-        const int full = 4 * num_cu(); // up to four 256-thread blocks per CU
-        for (int blocks : {full, full / 4, full / 16})
-            for (int opl : {4, 2, 8})
-                for (int ps : {1, 2}) cands.push_back({opl, ps, target.remap, blocks, 1, target.helpers, target.ahead});
+        // the dataflow solve: every resident block, or fewer waves polling ahead of the frontier
+        const int full = resident_solve_blocks();
+        for (int blocks : {0, full / 2, full / 4})
+            cands.push_back({target.ops_per_lane, target.passes, target.remap, blocks, 1, target.helpers, target.ahead});
     }
     for (const Cand &cd : cands) {
         if (st || (budget_ms > 0 && spent > budget_ms)) break;

@@ -10,14 +10,12 @@ import numpy as np
 
 FS0, FS1, FS2, FSEP, FRECT, FRUNS = 1, 2, 4, 8, 16, 32
 DOPS, DCONTIG, DXPTR, DRPTR = 64, 128, 256, 512
-TASK_FAST = 1 << 9
 TASK_STREAM = 1 << 10
 TASK_CSR = 1 << 11
 TASK_LONG = 1 << 12
 TASK_ROWS = 1 << 13
 ROWS_MAX_LEN = 8
 STREAM_ELEMS = 512
-LOOKAHEAD = 4
 F = {n: i for i, n in enumerate(["flags", "m", "nn", "row0", "row_step", "op0", "op_step", "col0", "sigma0",
                                  "sigma1", "rows_off", "ops_off", "cnt_off", "xt_off", "xp_off", "mat"])}
 
@@ -84,14 +82,9 @@ class Tables:
         c = self.cods[cod]
         lg = meta & 7
         assert 0 <= i0b < i0e <= c[F["m"]]
-        if meta & TASK_FAST:
-            assert i0e - i0b <= (64 >> lg)
-            assert xmode(int(c[F["flags"]])) in (0, 1, 3)
         out = []
         for i0 in range(i0b, i0e):
             row, opst, nops = self.row_info(c, i0)
-            if meta & TASK_FAST:
-                assert nops <= (LOOKAHEAD << lg)
             out.append((row, opst, nops, self.cols(c, i0, opst, nops)))
         if meta & TASK_STREAM:
             # the stream kernel's own indexing: contiguous values from op0 + i0b*nn, and for a
@@ -245,6 +238,51 @@ def solve(tabs, L, B, kind=1, vals=None, perm=None, fwd_tabs=None, Xf=None, with
             done[sig] += 1
     assert (writer >= 0).all()
     return X, gvout
+
+
+DF_RG = 8
+DF_PASS_MAX = 8
+
+
+def df_solve(tabs, L, B, kind=1, vals=None, perm=None, only_mat=None):
+    """Replays the dataflow solve's tasks in list order (kind 1: L X = B; kind 2: U Lam = B
+    with U = L^T, values through perm).  Checks that a task holds at most DF_RG rows of one
+    codelet, that every solution entry a row reads was written by an earlier task (so the list
+    is a topological order, and the earliest unfinished task never waits), and exact cover."""
+    T = Tables(dict(tabs, tasks=tabs["df_tasks"]))
+    v = L.values if vals is None else vals
+    n, k = B.shape
+    X = np.full((n, k), np.nan)
+    written = np.full(n, -1)  # task that wrote each row
+    ptr = tabs["df_ptr"]
+    per_matrix = only_mat is not None and ptr.size > 2  # matrix after matrix, ranges in ptr
+    lo, hi = (int(ptr[only_mat]), int(ptr[only_mat + 1])) if per_matrix else (0, T.tasks.shape[0])
+    assert lo % DF_PASS_MAX == 0 and hi % DF_PASS_MAX == 0
+    for t in range(lo, hi):
+        cod, i0b, i0e, meta = (int(x) for x in T.tasks[t])
+        assert meta == 0 and 0 <= i0e - i0b <= DF_RG and 0 <= cod < T.cods.shape[0]
+        if i0e == i0b:
+            continue  # padding: a wave pass never spans two levels
+        if only_mat is not None and int(T.cods[cod][F["mat"]]) != only_mat:
+            assert not per_matrix
+            continue
+        c, _, rows = T.task_rows(t)
+        for row, opst, nops, cols in rows:
+            acc = np.zeros(k)
+            for i1, col in enumerate(cols):
+                e = opst + i1
+                # written by a task of an earlier group of DF_PASS_MAX (a wave pass takes up to
+                # that many consecutive tasks, all at once)
+                assert 0 <= written[col] and written[col] // DF_PASS_MAX < t // DF_PASS_MAX, \
+                    f"row {row} reads x[{col}] before an earlier pass wrote it"
+                acc += (v[perm[e]] if kind == 2 else v[e]) * X[col]
+            d = opst - 1 if kind == 2 else opst + nops
+            diag = v[perm[d]] if kind == 2 else v[d]
+            assert written[row] == -1
+            X[row] = (B[row] - acc) / diag
+            written[row] = t
+    assert (written >= 0).all()
+    return X
 
 
 def _rows_from(TF, task):

@@ -43,6 +43,10 @@ def replay_solve(L, k=2, seed=0, **kw):
     check_solve(L, B, X, ref)
     T = ddf.ddf_plan_device_tables(p, 1)
     U, perm = O.transpose(L)
+    # the dataflow lists: forward and transposed solves in dependence order
+    check_solve(L, B, E.df_solve(F, L, B), ref)
+    check_solve(L, G, E.df_solve(T, U, G, kind=2, vals=L.values, perm=perm), O.sptrsv_adj(L, ref, G)[0],
+                transposed=True)
     if F["thin_rec"].shape[0]:
         check_solve(L, B[:, :1], E.thin_solve(F, L, B[:, :1]), ref[:, :1])
     if T["thin_rec"].shape[0]:
@@ -112,13 +116,17 @@ def test_batch_schedule_per_matrix():
         X, _ = E.solve(F, L, B, only_mat=b)
         ref = O.sptrsv(L, B)
         check_solve(L, B, X, ref)
-        X2, _ = E.solve(PM, L, B, only_mat=b)
-        assert np.array_equal(X, X2)
+        # the dataflow lists, batch (all matrices level by level) and per matrix, each in
+        # dependence order
+        check_solve(L, B, E.df_solve(F, L, B, only_mat=b), ref)
+        check_solve(L, B, E.df_solve(PM, L, B, only_mat=b), ref)
         U, perm = O.transpose(L)
         lam, gv = E.solve(T, U, m["G"], kind=2, vals=L.values, perm=perm, fwd_tabs=F, Xf=ref, with_gv=True,
                           only_mat=b)
         GBr, GVr = O.sptrsv_adj(L, ref, m["G"])
         check_solve(L, m["G"], lam, GBr, transposed=True)
+        check_solve(L, m["G"], E.df_solve(T, U, m["G"], kind=2, vals=L.values, perm=perm, only_mat=b), GBr,
+                    transposed=True)
 
 
 def test_stream_tasks_single_entry_rows():

@@ -88,7 +88,17 @@ def sptrsv_case_path(L, k, seed, opts, plain, inplace):
         b = dev(B)
     x2 = torch.empty_like(b)
     ddf.ddf_sptrsv(plan, b, x2, k)
-    assert np.array_equal(host(x2), got)
+    ddf.ddf_plan_sync_status(plan)
+    got2 = host(x2)
+    if inplace:
+        # an in-place call of the dataflow path runs one launch per level: other rounding order
+        check_solve(L, B, got2, ref)
+    else:
+        assert np.array_equal(got2, got)
+    # determinism: the same call again gives the same bits
+    x3 = torch.empty_like(b)
+    ddf.ddf_sptrsv(plan, b, x3, k)
+    assert np.array_equal(host(x3), got2)
     # adjoint
     GB, GV = O.sptrsv_adj(L, ref, G)
     xs, g = dev(ref), dev(G)
