@@ -76,7 +76,7 @@ struct SchedParams {
     int32_t passes = 2;
     int32_t remap = 1;
     int32_t blocks = 0;   // solve: persistent grid in 256-thread blocks (0 = all resident)
-    int32_t backoff = 16; // solve: longest sleep between polls (units of 64 cycles)
+    int32_t backoff = 4;  // dataflow solve: longest sleep between polls (units of 64 cycles)
     int32_t path = 0;     // solve: 0 auto, 1 multi-block, 2 single-block
     int32_t helpers = 4;  // single-block solve: L2 prefetch blocks on the solver's XCD
     int32_t ahead = 24;   // single-block solve: levels the prefetch runs ahead (>= 8)

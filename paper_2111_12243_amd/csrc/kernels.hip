@@ -669,8 +669,10 @@ __device__ __forceinline__ bool df_missing(double v) {
     return (unsigned long long)__double_as_longlong(v) == DF_SENT_BITS;
 }
 
-// Columns of one row's ops in ascending order, for every column-table mode.
-struct ColIter {
+// Columns of one row's ops, for every column-table mode, in ascending op order, or descending
+// (DESC).  In the run mode the op index must move by one from call to call (up, or down from
+// the last op); the other modes take any order.
+template <bool DESC> struct ColIter {
     int mode, base, j, cum, ln, st;
     const int32_t *__restrict__ s;
     __device__ __forceinline__ void init(const DCod &c, const int32_t *__restrict__ aux, int i0, const RowInfo &ri) {
@@ -684,27 +686,67 @@ struct ColIter {
         else if (mode == XM_FULL) {
             const int off = (c.flags & FRECT) ? i0 * c.nn : (c.flags & DCONTIG) ? ri.opst - c.op0 : aux[c.xp_off + i0];
             s = aux + c.xt_off + off;
-        } else if (mode == XM_FULL_RUNS)
+        } else if (mode == XM_FULL_RUNS) {
             s = aux + c.xt_off + 2 * aux[c.xp_off + i0];
+            if (DESC) { // start past the row's last run (the run index table has one more entry)
+                j = aux[c.xp_off + i0 + 1] - aux[c.xp_off + i0];
+                cum = ri.nops;
+            }
+        }
     }
-    // column of op i1; in the run modes i1 must grow by one from call to call
     __device__ __forceinline__ int col(const DCod &c, int i1) {
         if (mode == XM_STRIDED) return base + i1 * c.sigma1;
         if (mode == XM_SHARED || mode == XM_FULL) return base + s[i1];
-        while (i1 >= cum + ln) {
-            cum += ln;
-            ++j;
-            st = s[2 * j];
-            ln = s[2 * j + 1];
+        if (DESC) {
+            while (i1 < cum) {
+                --j;
+                st = s[2 * j];
+                ln = s[2 * j + 1];
+                cum -= ln;
+            }
+        } else {
+            while (i1 >= cum + ln) {
+                cum += ln;
+                ++j;
+                st = s[2 * j];
+                ln = s[2 * j + 1];
+            }
         }
         return base + st + (i1 - cum);
     }
 };
 
-// One pass of a wave: rows of W consecutive tasks, KR lanes per row.  SINGLE: one matrix (the
-// adjoint's values already in U's order); else batch members, values through perm for the
-// adjoint.
-template <int KR, bool ADJ, bool SINGLE>
+// Re-reads the values that still hold the sentinel, with backoff; returns false once the
+// wait has tripped the watchdog (the spin limit, or the error flag raised by another wave).
+template <int U>
+__device__ __forceinline__ bool df_backoff(const SolveArgs &a, int64_t &spins, int &back, unsigned *err) {
+    for (int z = 0; z < back; z++) __builtin_amdgcn_s_sleep(1);
+    if (back < a.backoff_max) back <<= 1;
+    spins += back;
+    bool trip = spins > a.spin_limit;
+    if ((spins & 1023) < back) trip = trip || cload_u(err) != 0u;
+    if (__ballot(trip)) {
+        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+    }
+    return true;
+}
+
+// A row's result from its values and the solution values it reads: stored for the readers.
+template <int U>
+__device__ __forceinline__ void df_finish(const double (&v)[U], const double (&xv)[U], double acc, double bo,
+                                          double diag, double *dst) {
+#pragma unroll
+    for (int u = 0; u < U; u++) acc = fma(v[u], xv[u], acc);
+    double res = (bo - acc) / diag;
+    if (df_missing(res)) res = __longlong_as_double(0x7FF8000000000000ll); // never: results are quiet
+    cstore(dst, res);
+}
+
+// One pass of a wave: rows of W consecutive tasks, KR lanes per row, lane r owning right-hand
+// sides r, r + KR, ...  VPERM: the values through perm (the transposed solve reads L's values
+// in U's order).
+template <int KR, bool ADJ, bool VPERM>
 __device__ __forceinline__ void df_pass(const SolveArgs &a, int p, int lane) {
     constexpr int P = WAVE / KR, W = P / DF_RG;
     const int slot = lane / KR, r = lane % KR;
@@ -717,7 +759,7 @@ __device__ __forceinline__ void df_pass(const SolveArgs &a, int p, int lane) {
     const int i0 = tk.i0b + i;
     const bool active = t < a.ntasks && i0 < tk.i0e;
     const double *__restrict__ vals = a.vals + mi.val_base;
-    const int32_t *__restrict__ perm = (ADJ && !SINGLE) ? a.perm + mi.val_base : nullptr;
+    const int32_t *__restrict__ perm = VPERM ? a.perm + mi.val_base : nullptr;
     const double *__restrict__ b = a.b + mi.vec_base;
     double *x = a.x + mi.vec_base;
     RowInfo ri{0, 0, 0};
@@ -725,64 +767,80 @@ __device__ __forceinline__ void df_pass(const SolveArgs &a, int p, int lane) {
     if (active) {
         ri = row_info(c, a.aux, i0);
         const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
-        diag = (ADJ && !SINGLE) ? vals[perm[dpos]] : vals[dpos];
+        diag = VPERM ? vals[perm[dpos]] : vals[dpos];
     }
     unsigned *err = a.ctr + CTR_STRIDE;
     for (int r0 = 0; r0 < k; r0 += KR) { // more right-hand sides than lanes: KR = 8 only
         const int rr = r0 + r;
-        const int nops = (active && rr < k) ? ri.nops : 0;
-        ColIter it;
+        const bool mine = active && rr < k; // this lane computes x[row, rr]
+        const int nops = mine ? ri.nops : 0;
+        const int64_t o = (int64_t)ri.row * k + rr;
+        // ops in the order that leaves the latest dependences to the last chunk: ascending
+        // columns for L, descending for U = L^T (its rows' first columns were solved last)
+        ColIter<ADJ> it;
         it.mode = XM_STRIDED; // lanes without a row read no table
         it.base = 0;
         if (active) it.init(c, a.aux, i0, ri);
+        const bool one_chunk = !__ballot(nops > DF_U);
         double acc = 0.0;
+        bool pend = mine; // one chunk: the row's result is not stored yet
         for (int i1 = 0; __ballot(i1 < nops); i1 += DF_U) {
             double v[DF_U], xv[DF_U];
             int col[DF_U];
 #pragma unroll
             for (int u = 0; u < DF_U; u++) {
                 const bool ok = i1 + u < nops;
-                col[u] = ok ? it.col(c, i1 + u) : 0;
-                const int e = ri.opst + i1 + u;
-                v[u] = ok ? ((ADJ && !SINGLE) ? vals[perm[e]] : vals[e]) : 0.0;
+                const int op = ADJ ? nops - 1 - (i1 + u) : i1 + u;
+                col[u] = ok ? it.col(c, op) : 0;
+                const int e = ri.opst + op;
+                v[u] = ok ? (VPERM ? vals[perm[e]] : vals[e]) : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < DF_U; u++) xv[u] = i1 + u < nops ? cload(x + (int64_t)col[u] * k + rr) : 0.0;
-            // wait for the values still missing: re-read them with backoff
+            const double bo = (one_chunk && mine) ? b[o] : 0.0;
             int64_t spins = 0;
             int back = 1;
             for (;;) {
                 bool miss = false;
 #pragma unroll
                 for (int u = 0; u < DF_U; u++) miss = miss || df_missing(xv[u]);
-                if (!__ballot(miss)) break;
-                for (int z = 0; z < back; z++) __builtin_amdgcn_s_sleep(1);
-                if (back < a.backoff_max) back <<= 1;
-                spins += back;
-                bool trip = spins > a.spin_limit;
-                if ((spins & 1023) < back) trip = trip || cload_u(err) != 0u;
-                if (__ballot(trip)) {
-                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (one_chunk) {
+                    // a row whose values have all arrived is solved and stored at once, while
+                    // the wave keeps waiting for its other rows
+                    if (pend && !miss) {
+                        df_finish<DF_U>(v, xv, acc, bo, diag, x + o);
+                        pend = false;
+                    }
+                    if (!__ballot(pend)) break;
+                } else if (!__ballot(miss)) {
+                    break;
+                }
+                if (!df_backoff<DF_U>(a, spins, back, err)) {
+                    // past the watchdog: the results are reported invalid, but every row is stored
+                    if (one_chunk && pend) df_finish<DF_U>(v, xv, acc, bo, diag, x + o);
+                    pend = false;
                     break;
                 }
 #pragma unroll
                 for (int u = 0; u < DF_U; u++)
                     if (df_missing(xv[u])) xv[u] = cload(x + (int64_t)col[u] * k + rr);
             }
+            if (!one_chunk) {
 #pragma unroll
-            for (int u = 0; u < DF_U; u++) acc = fma(v[u], xv[u], acc);
+                for (int u = 0; u < DF_U; u++) acc = fma(v[u], xv[u], acc);
+            }
         }
-        if (active && rr < k) {
-            const int64_t o = (int64_t)ri.row * k + rr;
+        // chunked rows, and rows of a pass whose rows have no ops at all (the chunk loop did not run)
+        if (mine && (!one_chunk || pend)) {
             double res = (b[o] - acc) / diag;
-            if (df_missing(res)) res = __longlong_as_double(0x7FF8000000000000ll); // never: quiet results
+            if (df_missing(res)) res = __longlong_as_double(0x7FF8000000000000ll); // never: results are quiet
             cstore(x + o, res);
         }
     }
 }
 
 // ctr lines: 0 ticket, 1 error flag, 2 check-in count, 3 mode (0 undecided, 1 static, 2 ticket)
-template <int KR, bool ADJ, bool SINGLE>
+template <int KR, bool ADJ, bool VPERM>
 __global__ __launch_bounds__(WAVE *WPB) void k_solve_df(SolveArgs a) {
     __shared__ int s_mode;
     unsigned *ticket = a.ctr, *arrive = a.ctr + 2 * CTR_STRIDE, *mode_w = a.ctr + 3 * CTR_STRIDE;
@@ -812,7 +870,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_solve_df(SolveArgs a) {
                       : __builtin_amdgcn_readfirstlane(
                             (int)__hip_atomic_fetch_add(ticket, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     while (p < a.npass) {
-        df_pass<KR, ADJ, SINGLE>(a, p, lane);
+        df_pass<KR, ADJ, VPERM>(a, p, lane);
         p = mode == 1 ? p + nw
                       : __builtin_amdgcn_readfirstlane(
                             (int)__hip_atomic_fetch_add(ticket, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -1494,6 +1552,9 @@ hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t 
     return hipGetLastError();
 }
 
+// Lanes per row of the dataflow solve for k right-hand sides (a lane per right-hand side, at
+// most 8: a pass covers 64, 32, 16 or 8 rows; more right-hand sides loop 8 at a time).  One row
+// group per pass for k = 8: rows that wait for different dependences do not share a pass.
 int df_lanes(int k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; }
 
 hipError_t launch_fill_u64(void *p, int64_t n, unsigned long long v, hipStream_t s) {
@@ -1519,8 +1580,8 @@ hipError_t launch_df_reset(unsigned *ctr, hipStream_t s) {
 
 // The output block [fill, fill + nfill) marked unsolved, then one persistent launch: a.npass
 // passes of kr lanes per row, `blocks` 256-thread blocks (0: every block the device keeps
-// resident at once).
-hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool single, int kr, int blocks, double *fill, int64_t nfill,
+// resident at once).  vperm: the values through perm.
+hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool vperm, int kr, int blocks, double *fill, int64_t nfill,
                            hipStream_t s) {
     if (a.npass <= 0) return hipSuccess;
     hipError_t e = launch_fill_u64(fill, nfill, DF_SENT_BITS, s);
@@ -1534,11 +1595,7 @@ hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool single, int kr, in
     case 4: DDF_DF(4, A, S); break;                                                                 \
     default: DDF_DF(8, A, S); break;                                                                \
     }
-    if (single) {
-        if (adj) DDF_DF_KR(true, true) else DDF_DF_KR(false, true)
-    } else {
-        if (adj) DDF_DF_KR(true, false) else DDF_DF_KR(false, false)
-    }
+    if (adj && vperm) DDF_DF_KR(true, true) else if (adj) DDF_DF_KR(true, false) else DDF_DF_KR(false, false)
 #undef DDF_DF_KR
 #undef DDF_DF
     return hipGetLastError();

@@ -182,7 +182,7 @@ hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s);
 int kr_for(int k);
 int df_lanes(int k); // lanes per row of the dataflow solve for k right-hand sides
 hipError_t launch_df_reset(unsigned *ctr, hipStream_t s);
-hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool single, int kr, int blocks, double *fill, int64_t nfill,
+hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool vperm, int kr, int blocks, double *fill, int64_t nfill,
                            hipStream_t s);
 hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t s);
 int num_cu();
