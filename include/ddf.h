@@ -323,6 +323,17 @@ typedef struct {
 } ddf_device_tables_t;
 ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
 
+/* Kernel timing for measurement.  With enable = 1, every later execution call on the plan
+ * (up to 256 calls) records a pair of HIP events on its stream around its main kernel: the
+ * solve kernel of a solve or transposed solve (one launch per level: from the first level's
+ * launch to the last's), the product kernel of ddf_spmv or ddf_spmv_adjoint; enable = 0 stops
+ * it.  Either call forgets the calls timed so far.  Events are created on the first enable
+ * (the only allocation); execution calls still allocate nothing.
+ * ddf_plan_kernel_time synchronises those events and returns the total time of the timed
+ * kernels in ms, the number of timed calls and the number of kernel launches they made. */
+ddf_status ddf_plan_time_kernels(ddf_plan_t plan, int32_t enable);
+ddf_status ddf_plan_kernel_time(ddf_plan_t plan, double *ms, int64_t *calls, int64_t *launches);
+
 /* Synchronises `stream`, then reads and clears the plan's device error flag. */
 ddf_status ddf_plan_sync_status(ddf_plan_t plan, ddf_stream_t stream);
 /* Test hook: spin limit of the persistent kernels' level waits (0 = default). */

@@ -126,7 +126,8 @@ def sptrsv_adj(L, X, G):
 
 
 def levels(L):
-    rp, ci, _ = _csr(L)
+    rp = np.ascontiguousarray(L.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(L.col_idx, dtype=np.int32)
     lev = np.zeros(max(L.n_rows, 1), dtype=np.int64)
     n = lib().orc_levels(L.n_rows, _p(rp), _p(ci), _p(lev))
     return lev[:L.n_rows], int(n)
@@ -195,6 +196,106 @@ def classify(kind, A, q):
     nn = np.zeros(1, dtype=np.int64)
     f = lib().orc_classify(kind, _p(rp), _p(ci), _p(q), q.size, _p(nn))
     return int(f), int(nn[0])
+
+
+_LIB_OMP = None
+
+
+def lib_omp():
+    """The many-core loops (ddf_oracle_omp.c)."""
+    global _LIB_OMP
+    if _LIB_OMP is None:
+        path = os.path.join(_HERE, "liboracle_omp.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(path)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        L.omp_spmv.argtypes = [I32, P, P, P, I32, P, P]
+        L.omp_spmv_adj.argtypes = [I32, I32, P, P, P, P, P, P, I32, P, P, P, P]
+        L.omp_sptrsv.argtypes = [I32, P, P, P, I32, P, P, I64, P, P]
+        L.omp_sptrsv_adj.argtypes = [I32, P, P, P, P, P, P, I32, P, P, I64, P, P, P, P]
+        _LIB_OMP = L
+    return _LIB_OMP
+
+
+def _reverse_cols(rpT, ciT, n):
+    """Columns of the rows of a CSR pattern taken from the last row to the first, each column
+    c renumbered n - 1 - c."""
+    lens = np.diff(rpT)
+    row_of = np.repeat(np.arange(n), lens)
+    order = np.lexsort((np.arange(ciT.size), -row_of))
+    return (n - 1 - ciT[order]).astype(np.int32)
+
+
+def level_sets(lev, nlev):
+    """(ptr[nlev + 1], rows) of the level sets, rows ascending within a level."""
+    order = np.argsort(lev, kind="stable").astype(np.int64)
+    ptr = np.zeros(nlev + 1, dtype=np.int64)
+    np.cumsum(np.bincount(lev, minlength=nlev), out=ptr[1:])
+    return ptr, order
+
+
+class ManyCore:
+    """The serial oracle's value loops over host cores (OpenMP), for one matrix: the transposed
+    pattern and the level sets are built once here (outside any timing)."""
+
+    def __init__(self, A, triangular=False):
+        self.A = A
+        self.rp, self.ci, self.v = _csr(A)
+        self.AT, perm = transpose(A)
+        self.rpT = np.ascontiguousarray(self.AT.row_ptr, dtype=np.int32)
+        self.ciT = np.ascontiguousarray(self.AT.col_idx, dtype=np.int32)
+        self.perm = np.ascontiguousarray(perm, dtype=np.int64)
+        if triangular:
+            lev, nl = levels(A)
+            self.lptr, self.lrows = level_sets(lev, nl)
+            # reverse levels of U = L^T (0 for rows of U without off-diagonals, else one more
+            # than the deepest of the later rows they read): the forward levels of U with its
+            # rows and columns numbered from the end
+            n = A.n_rows
+            lens = np.diff(self.rpT)[::-1]
+            rpR = np.zeros(n + 1, dtype=np.int32)
+            np.cumsum(lens, out=rpR[1:])
+            ciR = np.concatenate([n - 1 - self.ciT[self.rpT[i]:self.rpT[i + 1]] for i in range(n - 1, -1, -1)]) \
+                if n < 4096 else _reverse_cols(self.rpT, self.ciT, n)
+            from types import SimpleNamespace
+            rl, nl = levels(SimpleNamespace(n_rows=n, row_ptr=rpR, col_idx=ciR.astype(np.int32), values=None))
+            self.ulptr, self.ulrows = level_sets(rl[::-1].copy(), nl)
+
+    def spmv(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        k = X.shape[1]
+        Y = np.empty((self.A.n_rows, k))
+        lib_omp().omp_spmv(self.A.n_rows, _p(self.rp), _p(self.ci), _p(self.v), k, _p(X), _p(Y))
+        return Y
+
+    def spmv_adj(self, X, G):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        G = np.ascontiguousarray(G, dtype=np.float64)
+        k = G.shape[1]
+        GX, GV = np.empty((self.A.n_cols, k)), np.empty(self.v.size)
+        lib_omp().omp_spmv_adj(self.A.n_rows, self.A.n_cols, _p(self.rp), _p(self.ci), _p(self.v), _p(self.rpT),
+                               _p(self.ciT), _p(self.perm), k, _p(X), _p(G), _p(GX), _p(GV))
+        return GX, GV
+
+    def sptrsv(self, B):
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        k = B.shape[1]
+        X = np.empty((self.A.n_rows, k))
+        lib_omp().omp_sptrsv(self.A.n_rows, _p(self.rp), _p(self.ci), _p(self.v), k, _p(self.lptr),
+                             _p(self.lrows), self.lptr.size - 1, _p(B), _p(X))
+        return X
+
+    def sptrsv_adj(self, X, G):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        G = np.ascontiguousarray(G, dtype=np.float64)
+        k = G.shape[1]
+        GB, GV = np.empty((self.A.n_rows, k)), np.empty(self.v.size)
+        lib_omp().omp_sptrsv_adj(self.A.n_rows, _p(self.rp), _p(self.ci), _p(self.v), _p(self.rpT), _p(self.ciT),
+                                 _p(self.perm), k, _p(self.ulptr), _p(self.ulrows), self.ulptr.size - 1, _p(X),
+                                 _p(G), _p(GB), _p(GV))
+        return GB, GV
 
 
 def flags_count(flags):

@@ -1473,11 +1473,12 @@ template <int NGS, bool PIN = false> static void launch_thin_lg(const ThinArgs &
     }
 }
 
-hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
+hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (a.nlev == 0) return hipSuccess;
     const dim3 sgrid((unsigned)((a.n_rec + 255) / 256)), rgrid((unsigned)((a.n + 255) / 256)), pblock(256);
     hipLaunchKernelGGL(k_thin_stream, sgrid, pblock, 0, s, a);
     const dim3 grid(1 + 8 * (unsigned)a.helpers), block((unsigned)a.block);
+    if (ev0) (void)hipEventRecord(ev0, s);
     // a plan with pinned entries has at most two global slots per lane; the two-slot kernel
     // runs it (a slot without a global operand gathers the zero past the solutions)
     if (a.pins) launch_thin_lg<2, true>(a, grid, block, s);
@@ -1486,6 +1487,7 @@ hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s) {
     else if (ngs == 2) launch_thin_lg<2>(a, grid, block, s);
     else if (ngs == 3) launch_thin_lg<3>(a, grid, block, s);
     else launch_thin_lg<THIN_SLOTS>(a, grid, block, s);
+    if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL(k_thin_scatter, rgrid, pblock, 0, s, a);
     return hipGetLastError();
 }
@@ -1582,11 +1584,12 @@ hipError_t launch_df_reset(unsigned *ctr, hipStream_t s) {
 // passes of kr lanes per row, `blocks` 256-thread blocks (0: every block the device keeps
 // resident at once).  vperm: the values through perm.
 hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool vperm, int kr, int blocks, double *fill, int64_t nfill,
-                           hipStream_t s) {
+                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (a.npass <= 0) return hipSuccess;
     hipError_t e = launch_fill_u64(fill, nfill, DF_SENT_BITS, s);
     if (e != hipSuccess) return e;
     const int nb = solve_grid(a.npass, blocks);
+    if (ev0) (void)hipEventRecord(ev0, s);
 #define DDF_DF(KR, A, S) hipLaunchKernelGGL((k_solve_df<KR, A, S>), dim3(nb), dim3(WAVE * WPB), 0, s, a)
 #define DDF_DF_KR(A, S)                                                                             \
     switch (kr) {                                                                                   \
@@ -1598,7 +1601,9 @@ hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool vperm, int kr, int
     if (adj && vperm) DDF_DF_KR(true, true) else if (adj) DDF_DF_KR(true, false) else DDF_DF_KR(false, false)
 #undef DDF_DF_KR
 #undef DDF_DF
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (ev1) (void)hipEventRecord(ev1, s);
+    return e;
 }
 
 static int lg_for(double avg, int ops_per_lane) {

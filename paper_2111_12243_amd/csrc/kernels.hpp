@@ -183,12 +183,14 @@ int kr_for(int k);
 int df_lanes(int k); // lanes per row of the dataflow solve for k right-hand sides
 hipError_t launch_df_reset(unsigned *ctr, hipStream_t s);
 hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool vperm, int kr, int blocks, double *fill, int64_t nfill,
-                           hipStream_t s);
+                           hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t s);
 int num_cu();
 int resident_solve_blocks(); // 256-thread blocks of the dataflow solve the device keeps resident
 hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
-hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s);
+// ev0 / ev1 (nullable): events recorded on the stream around the solve kernel itself
+hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
 hipError_t launch_thin_codes(const ThinArgs &a, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_gather(double *dst, const double *src, const int32_t *idx, int64_t n, hipStream_t s);

@@ -61,7 +61,23 @@ struct ddf_plan_s {
     uint64_t hash = 0;
     int max_levels = 0;
     std::vector<void *> allocs;
+    // kernel timing (ddf_plan_time_kernels): event pairs around the main kernel of each call
+    std::vector<hipEvent_t> tev;
+    int32_t tev_used = 0;
+    int64_t tev_launches = 0;
+    bool timing = false;
 };
+
+namespace {
+constexpr int TIMED_CALLS = 256;
+// The next event pair for a timed call (null when timing is off or the pairs are used up).
+std::pair<hipEvent_t, hipEvent_t> next_timer(ddf_plan_t p, int64_t launches) {
+    if (!p->timing || p->tev_used >= TIMED_CALLS) return {nullptr, nullptr};
+    const int i = p->tev_used++;
+    p->tev_launches += launches;
+    return {p->tev[2 * i], p->tev[2 * i + 1]};
+}
+} // namespace
 
 struct ddf_graph_s {
     hipGraph_t g = nullptr;
@@ -1044,12 +1060,14 @@ ddf_status thin_launch(ddf_plan_t p, const DevTables &D, const SchedParams &sp, 
     unsigned *ctr = &D == &p->T ? p->d_ctr_adj : p->d_ctr;
     t.progress = ctr + CTR_STRIDE + 16; // second counter line: error flag, then these
     t.sink = ctr + CTR_STRIDE + 17;
-    HIPCHK(launch_solve_thin(t, D.thin_ngs, s));
+    const auto tm = next_timer(p, 1);
+    HIPCHK(launch_solve_thin(t, D.thin_ngs, s, tm.first, tm.second));
     return DDF_OK;
 }
 
 void free_plan(ddf_plan_t p) {
     if (!p) return;
+    for (hipEvent_t e : p->tev) (void)hipEventDestroy(e);
     for (void *ptr : p->allocs) (void)hipFree(ptr);
     delete p;
 }
@@ -1318,7 +1336,8 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
         }
         if (df.ntasks > 0) {
             HIPCHK(launch_df_reset(df.ctr, s));
-            HIPCHK(launch_solve_df(df, adj, adj && !single, kr, sp.blocks, fill, nfill, s));
+            const auto tm = next_timer(p, 1);
+            HIPCHK(launch_solve_df(df, adj, adj && !single, kr, sp.blocks, fill, nfill, s, tm.first, tm.second));
         }
         const int64_t ngv = adj ? ntasks - p->n_solve_tasks_adj : 0;
         if (ngv > 0) { // the batch adjoint's value gradient, after the solve
@@ -1335,6 +1354,11 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     const Task *tk = a.tasks;
     const DCod *tc = a.tcods;
     const int4 *sy = a.sync;
+    int64_t nlaunch = 0;
+    for (int64_t i = 0; i < ntasks; i++)
+        if (i == 0 || D.sync[(t0 + i) * 4 + 3] != D.sync[(t0 + i - 1) * 4 + 3]) nlaunch++;
+    const auto tm = next_timer(p, nlaunch);
+    if (tm.first) (void)hipEventRecord(tm.first, s);
     int64_t i = 0;
     while (i < ntasks) {
         const int32_t lev = D.sync[(t0 + i) * 4 + 3];
@@ -1347,6 +1371,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
         HIPCHK(launch_solve_range(a, adj, kt, s));
         i = j;
     }
+    if (tm.second) (void)hipEventRecord(tm.second, s);
     return DDF_OK;
 }
 
@@ -1459,7 +1484,10 @@ ddf_status ddf_spmv_v(ddf_plan_t p, const double *d_vals, const double *d_x, dou
     a.vals = d_vals;
     a.x = d_x;
     a.y = d_y;
+    const auto tm = next_timer(p, 1);
+    if (tm.first) (void)hipEventRecord(tm.first, s);
     HIPCHK(launch_spmv(a, false, s));
+    if (tm.second) (void)hipEventRecord(tm.second, s);
     return DDF_OK;
 }
 
@@ -1525,7 +1553,10 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
     a.perm = p->d_perm;
     a.x = d_gy;
     a.y = d_gx;
+    const auto tm = next_timer(p, 1);
+    if (tm.first) (void)hipEventRecord(tm.first, s);
     HIPCHK(launch_spmv(a, true, s));
+    if (tm.second) (void)hipEventRecord(tm.second, s);
     return DDF_OK;
 }
 
@@ -1967,6 +1998,34 @@ ddf_status ddf_plan_sync_status(ddf_plan_t p, ddf_stream_t stream) {
         }
     }
     if (tripped) return fail(DDF_E_DEVICE, "a level wait exceeded its spin limit");
+    return DDF_OK;
+}
+
+ddf_status ddf_plan_time_kernels(ddf_plan_t p, int32_t enable) {
+    if (ddf_status s = need_device(p)) return s;
+    if (enable && p->tev.empty()) {
+        p->tev.resize(2 * TIMED_CALLS, nullptr);
+        for (hipEvent_t &e : p->tev) HIPCHK(hipEventCreate(&e));
+    }
+    p->timing = enable != 0;
+    p->tev_used = 0;
+    p->tev_launches = 0;
+    return DDF_OK;
+}
+
+ddf_status ddf_plan_kernel_time(ddf_plan_t p, double *ms, int64_t *calls, int64_t *launches) {
+    if (ddf_status s = need_device(p)) return s;
+    if (!ms || !calls || !launches) return fail(DDF_E_ARG, "NULL argument");
+    double total = 0;
+    for (int i = 0; i < p->tev_used; i++) {
+        HIPCHK(hipEventSynchronize(p->tev[2 * i + 1]));
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, p->tev[2 * i], p->tev[2 * i + 1]));
+        total += t;
+    }
+    *ms = total;
+    *calls = p->tev_used;
+    *launches = p->tev_launches;
     return DDF_OK;
 }
 

@@ -24,6 +24,7 @@ STATUS = ["DDF_OK", "DDF_E_ARG", "DDF_E_CSR", "DDF_E_NOT_LOWER", "DDF_E_NO_DIAG"
  DDF_E_DEVICE, DDF_E_UNSUPPORTED) = range(10)
 
 EXPORTED = [
+    "ddf_plan_time_kernels", "ddf_plan_kernel_time",
     "ddf_opts_default", "ddf_inspect", "ddf_inspect_batch", "ddf_plan_destroy", "ddf_spmv",
     "ddf_spmv_v", "ddf_sptrsv", "ddf_sptrsv_v", "ddf_spmv_adjoint", "ddf_sptrsv_adjoint", "ddf_sptrsv_value_grad",
     "ddf_sptrsv_batch", "ddf_sptrsv_batch_adjoint", "ddf_graph_create_batch", "ddf_graph_launch",
@@ -125,6 +126,8 @@ def lib():
             "ddf_plan_traffic": (I32, [P, I32, I32, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
             "ddf_plan_sync_status": (I32, [P, P]),
             "ddf_plan_set_spin_limit": (I32, [P, I64]),
+            "ddf_plan_time_kernels": (I32, [P, I32]),
+            "ddf_plan_kernel_time": (I32, [P, C.POINTER(D), C.POINTER(I64), C.POINTER(I64)]),
             "ddf_status_string": (C.c_char_p, [I32]),
             "ddf_last_error": (C.c_char_p, []),
             "ddf_version": (C.c_char_p, []),
@@ -382,6 +385,18 @@ def ddf_plan_device_tables(plan, which=0) -> dict:
             "df_tasks": grab(t.df_tasks, t.n_df_tasks, 4),
             "df_ptr": (np.ctypeslib.as_array(t.df_ptr, shape=(t.n_df_ptr,)).copy() if t.n_df_ptr
                        else np.zeros(0, np.int64))}
+
+
+def ddf_plan_time_kernels(plan, enable=1) -> None:
+    """Start (1) or stop (0) timing the main kernel of each execution call on the plan."""
+    _check(lib().ddf_plan_time_kernels(plan.handle, int(enable)))
+
+
+def ddf_plan_kernel_time(plan) -> tuple:
+    """(total ms, timed calls, kernel launches) of the calls timed since ddf_plan_time_kernels."""
+    ms, calls, launches = C.c_double(), C.c_int64(), C.c_int64()
+    _check(lib().ddf_plan_kernel_time(plan.handle, C.byref(ms), C.byref(calls), C.byref(launches)))
+    return ms.value, calls.value, launches.value
 
 
 def ddf_plan_traffic(plan, op, nrhs) -> tuple:
