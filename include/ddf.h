@@ -155,6 +155,10 @@ typedef enum {
     DDF_OP_SPTRSV = 2,
     DDF_OP_SPTRSV_ADJ = 3,
     DDF_OP_SPTRSV_T = 4, /* the transposed solve alone (ddf_sptrsv_adjoint with d_gvals = NULL) */
+    /* ddf_plan_traffic only: the bytes of a call's main kernel (the one ddf_plan_time_kernels
+     * times): the product kernel of ddf_spmv_adjoint, the solve kernel of a transposed solve */
+    DDF_OP_SPMV_ADJ_KERNEL = 5,
+    DDF_OP_SPTRSV_ADJ_KERNEL = 6,
 } ddf_op;
 
 /* Defaults for ddf_opts (window 64, adjoint plan on). */

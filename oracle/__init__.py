@@ -215,6 +215,7 @@ def lib_omp():
         L.omp_spmv_adj.argtypes = [I32, I32, P, P, P, P, P, P, I32, P, P, P, P]
         L.omp_sptrsv.argtypes = [I32, P, P, P, I32, P, P, I64, P, P]
         L.omp_sptrsv_adj.argtypes = [I32, P, P, P, P, P, P, I32, P, P, I64, P, P, P, P]
+        L.omp_threads.restype = I32
         _LIB_OMP = L
     return _LIB_OMP
 
@@ -234,6 +235,11 @@ def level_sets(lev, nlev):
     ptr = np.zeros(nlev + 1, dtype=np.int64)
     np.cumsum(np.bincount(lev, minlength=nlev), out=ptr[1:])
     return ptr, order
+
+
+def omp_threads():
+    """Threads the many-core loops run on."""
+    return int(lib_omp().omp_threads())
 
 
 class ManyCore:

@@ -96,3 +96,7 @@ void omp_sptrsv_adj(int32_t n, const int32_t *rp, const int32_t *ci, const doubl
         }
     }
 }
+
+/* Threads the parallel loops above use. */
+#include <omp.h>
+int omp_threads(void) { return omp_get_max_threads(); }

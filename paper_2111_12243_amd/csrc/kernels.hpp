@@ -132,7 +132,7 @@ struct SolveArgs {
     double *x;           // solution (adjoint: lambda)
     const double *xf;    // adjoint: forward solution (for GV)
     double *gv;          // adjoint: value gradient
-    unsigned *ctr;       // lines of CTR_STRIDE: ticket, error flag, then one counter per level
+    unsigned *ctr;       // dataflow solve: lines of CTR_STRIDE: ticket, error flag, check-in count, mode
     int64_t spin_limit;
     int32_t k_override; // > 0: right-hand sides of a single-matrix call
     int32_t npass;      // dataflow solve: wave passes (each 64 / KR rows, DF_RG rows per task)

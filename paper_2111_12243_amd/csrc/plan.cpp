@@ -1282,8 +1282,8 @@ const double *vals_or_own(ddf_plan_t p, const double *v) { return v ? v : p->d_v
 
 // One solve (adj: the transposed solve) over a schedule: tasks [t0, t0 + ntasks) of the
 // one-launch-per-level lists (the batch adjoint's value-gradient tasks come last, level -1).
-// Path 1 runs the dataflow tasks of D instead (matrix `mat` of a per-matrix schedule, or all),
-// then any value-gradient tasks in one more launch.  An in-place call (b == x) takes one launch
+// Every path but 3 runs the dataflow tasks of D instead (matrix `mat` of a per-matrix schedule,
+// or all), then any value-gradient tasks in one more launch.  An in-place call (b == x) takes one launch
 // per level: the dataflow solve marks the output as not yet solved before it starts.
 ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t ntasks, bool adj, const double *vals,
                         const double *b, double *x, const double *xf, double *gv, int32_t k_override, int kt,
@@ -1317,7 +1317,7 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
         HIPCHK(launch_gather(p->d_valsT, vals, p->d_perm, p->nnz, s));
         a.vals = p->d_valsT;
     }
-    if (sp.path == 1 && b != x && !D.df_tasks.empty()) {
+    if (sp.path != 3 && b != x && !D.df_tasks.empty()) {
         const int64_t d0 = mat >= 0 ? D.df_ptr[mat] : 0;
         const int64_t d1 = mat >= 0 ? D.df_ptr[mat + 1] : (int64_t)D.df_tasks.size();
         SolveArgs df = a;
@@ -1927,7 +1927,7 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
     case DDF_OP_SPTRSV:
         ba = 8 * nnz +
              (!p->batch && use_thin(p->F, p->sp_f, nrhs) ? p->F.thin_bytes()
-              : p->sp_f.path == 1                        ? p->F.df_read_bytes()
+              : p->sp_f.path != 3                        ? p->F.df_read_bytes()
                                                          : p->F.solve_read_bytes()) +
              16 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
@@ -1947,10 +1947,10 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         if (p->has_adj && !p->batch && use_thin(p->T, p->sp_a, nrhs))
             ba = 20 * nnz + p->T.thin_bytes() + 4 * (n + 1) + 24 * vk;
         else if (p->batch)
-            ba = 20 * nnz + (p->has_adj ? (p->sp_a.path == 1 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
+            ba = 20 * nnz + (p->has_adj ? (p->sp_a.path != 3 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
                  Fca + 32 * vk;
         else
-            ba = 24 * nnz + (p->has_adj ? (p->sp_a.path == 1 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
+            ba = 24 * nnz + (p->has_adj ? (p->sp_a.path != 3 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
                  4 * (n + 1) + 32 * vk + 16 * nnz;
         bc = 20 * nnz + 4 * (n + 1) + 24 * vk;
         if (p->batch) {
@@ -1968,10 +1968,30 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
             ba = 8 * nnz + p->T.thin_bytes() + 16 * vk;
         else
             ba = 8 * nnz +
-                 (p->sp_a.path == 1 ? p->T.df_read_bytes()
+                 (p->sp_a.path != 3 ? p->T.df_read_bytes()
                                     : (int64_t)p->T.aux.size() * 4 +
                                           p->n_solve_tasks_adj * (int64_t)(sizeof(Task) + sizeof(DCod) + 16)) +
                  16 * vk + (!p->batch ? 16 * nnz : 0);
+        bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
+        fl = p->batch ? 0 : kf * (2 * (nnz - n) + n);
+        break;
+    case DDF_OP_SPMV_ADJ_KERNEL:
+        // the transposed product alone: values through perm, the transposed plan's tables, g
+        // read, gx written
+        if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+        ba = 12 * nnz + (many ? p->T.launch_bytes(true) : p->T.table_bytes1) + 8 * vk + 8 * ck;
+        bc = 12 * nnz + 4 * (nc + 1) + 8 * vk + 8 * ck;
+        fl = 2 * nnz * nrhs;
+        break;
+    case DDF_OP_SPTRSV_ADJ_KERNEL:
+        // the transposed solve kernel alone: values (already in U's order for one matrix,
+        // through perm for a batch), tables, g read, lambda written
+        if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+        if (!p->batch && use_thin(p->T, p->sp_a, nrhs))
+            ba = 8 * nnz + p->T.thin_bytes() + 16 * vk;
+        else
+            ba = (p->batch ? 12 : 8) * nnz + (p->sp_a.path != 3 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) +
+                 16 * vk;
         bc = 12 * nnz + 4 * (n + 1) + 16 * vk;
         fl = p->batch ? 0 : kf * (2 * (nnz - n) + n);
         break;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libddf.so")
 
 DDF_SPMV, DDF_SPTRSV_LOWER = 0, 1
 DDF_OP_SPMV, DDF_OP_SPMV_ADJ, DDF_OP_SPTRSV, DDF_OP_SPTRSV_ADJ, DDF_OP_SPTRSV_T = 0, 1, 2, 3, 4
+DDF_OP_SPMV_ADJ_KERNEL, DDF_OP_SPTRSV_ADJ_KERNEL = 5, 6
 STATUS = ["DDF_OK", "DDF_E_ARG", "DDF_E_CSR", "DDF_E_NOT_LOWER", "DDF_E_NO_DIAG", "DDF_E_KIND",
           "DDF_E_NOMEM", "DDF_E_HIP", "DDF_E_DEVICE", "DDF_E_UNSUPPORTED"]
 (DDF_OK, DDF_E_ARG, DDF_E_CSR, DDF_E_NOT_LOWER, DDF_E_NO_DIAG, DDF_E_KIND, DDF_E_NOMEM, DDF_E_HIP,
