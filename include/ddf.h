@@ -224,6 +224,21 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t plan, const double *d_vals, const doubl
 ddf_status ddf_sptrsv_value_grad(ddf_plan_t plan, const double *d_x, const double *d_gb, double *d_gvals,
                                  int32_t nrhs, ddf_stream_t stream);
 
+/* ddf_sptrsv_adjoint for callers that cannot allocate device memory, with the same arguments,
+ * outputs and errors.  Its scratch (the values of L in the order of L^T, and the dataflow
+ * solve's four counter lines) lives in one static device array of the library, 32 MiB + 512 B
+ * per GPU, held until the process ends, instead of in the plan's own allocations: the call
+ * makes no allocation and no library routine it calls does.  The transposed solve always runs
+ * the dataflow kernel (in place, gb == gx: one launch per level).  Limits: at most 4194304
+ * stored values in L (larger plans get DDF_E_ARG before any launch).  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (on different streams, or two
+ * plans at once) race and give wrong results; run them one after another.  The counters start
+ * from zero at each call (cleared by a kernel, not a memset); a watchdog trip is reported by
+ * ddf_plan_sync_status on the plan. */
+ddf_status ddf_sptrsv_adjoint_noalloc(ddf_plan_t plan, const double *d_vals, const double *d_x,
+                                      const double *d_gx, double *d_gb, double *d_gvals, int32_t nrhs,
+                                      ddf_stream_t stream);
+
 /* Batched forms (plan from ddf_inspect_batch; nrhs per matrix fixed at inspect time).
  * d_vals_packed may be NULL to use the values captured at inspect time. */
 ddf_status ddf_sptrsv_batch(ddf_plan_t plan, const double *d_vals_packed,

@@ -20,6 +20,8 @@
 // its stores to complete (s_waitcnt vmcnt(0)) before bumping the counter.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ddf_internal.hpp"
 #include "kernels.hpp"
 
@@ -769,7 +771,7 @@ __device__ __forceinline__ void df_pass(const SolveArgs &a, int p, int lane) {
         const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
         diag = VPERM ? vals[perm[dpos]] : vals[dpos];
     }
-    unsigned *err = a.ctr + CTR_STRIDE;
+    unsigned *err = a.err ? a.err : a.ctr + CTR_STRIDE;
     for (int r0 = 0; r0 < k; r0 += KR) { // more right-hand sides than lanes: KR = 8 only
         const int rr = r0 + r;
         const bool mine = active && rr < k; // this lane computes x[row, rr]
@@ -1503,6 +1505,30 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
+}
+
+// Scratch of the no-allocation entry point: a file-scope device array, one copy per GPU, held
+// until the process ends.  Host code uses the address hipGetSymbolAddress gives for the
+// current device, never the array's name.
+static __device__ __align__(256) double scratch[NOALLOC_CTR_WORDS / 2 + NOALLOC_VALUES];
+
+hipError_t noalloc_scratch(double **ptr) {
+    constexpr int MAXDEV = 64;
+    static double *addr[MAXDEV] = {nullptr};
+    static std::mutex mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 int num_cu() { return g_num_cu > 0 ? g_num_cu : 256; }

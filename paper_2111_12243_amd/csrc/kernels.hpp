@@ -133,6 +133,7 @@ struct SolveArgs {
     const double *xf;    // adjoint: forward solution (for GV)
     double *gv;          // adjoint: value gradient
     unsigned *ctr;       // dataflow solve: lines of CTR_STRIDE: ticket, error flag, check-in count, mode
+    unsigned *err;       // the error flag the dataflow solve raises (null: ctr's second line)
     int64_t spin_limit;
     int32_t k_override; // > 0: right-hand sides of a single-matrix call
     int32_t npass;      // dataflow solve: wave passes (each 64 / KR rows, DF_RG rows per task)
@@ -187,6 +188,12 @@ hipError_t launch_solve_df(const SolveArgs &a, bool adj, bool vperm, int kr, int
 hipError_t launch_solve_range(const SolveArgs &a, bool adj, int kt, hipStream_t s);
 int num_cu();
 int resident_solve_blocks(); // 256-thread blocks of the dataflow solve the device keeps resident
+// The static scratch of the no-allocation entry point on the current device: its address
+// (taken once per device) and its size in doubles; the first NOALLOC_CTR_WORDS / 2 doubles
+// hold the dataflow solve's counter lines, the rest the gathered values.
+constexpr int64_t NOALLOC_VALUES = int64_t(1) << 22; // values the scratch holds (32 MiB)
+constexpr int64_t NOALLOC_CTR_WORDS = 4 * CTR_STRIDE; // uint32 words of the counter lines
+hipError_t noalloc_scratch(double **ptr);
 hipError_t launch_reset(unsigned *ctr, int64_t n, hipStream_t s);
 // ev0 / ev1 (nullable): events recorded on the stream around the solve kernel itself
 hipError_t launch_solve_thin(const ThinArgs &a, int ngs, hipStream_t s, hipEvent_t ev0 = nullptr,

@@ -1285,9 +1285,17 @@ const double *vals_or_own(ddf_plan_t p, const double *v) { return v ? v : p->d_v
 // Every path but 3 runs the dataflow tasks of D instead (matrix `mat` of a per-matrix schedule,
 // or all), then any value-gradient tasks in one more launch.  An in-place call (b == x) takes one launch
 // per level: the dataflow solve marks the output as not yet solved before it starts.
+// Where a solve call keeps its scratch: the values in transposed order and the dataflow
+// solve's counter lines (null: the plan's own), and the error flag it raises.
+struct SolveScratch {
+    double *valsT = nullptr;
+    unsigned *ctr = nullptr;
+    unsigned *err = nullptr;
+};
+
 ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t ntasks, bool adj, const double *vals,
                         const double *b, double *x, const double *xf, double *gv, int32_t k_override, int kt,
-                        hipStream_t s, int mat = -1) {
+                        hipStream_t s, int mat = -1, const SolveScratch &scr = SolveScratch()) {
     const SchedParams &sp = adj ? p->sp_a : p->sp_f;
     SolveArgs a{};
     a.cods = adj ? p->T.d_cods : p->F.d_cods;
@@ -1306,16 +1314,18 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.x = x;
     a.xf = xf;
     a.gv = gv;
-    a.ctr = adj ? p->d_ctr_adj : p->d_ctr;
+    a.ctr = scr.ctr ? scr.ctr : adj ? p->d_ctr_adj : p->d_ctr;
+    a.err = scr.err;
     a.spin_limit = p->spin_limit;
     a.k_override = k_override;
     const bool single = k_override > 0;
     // the transposed solve of one matrix gathers its values in transposed order first, so that
     // no task reads them through perm (one matrix: 0.37 ms of gather against 0.56 ms more in
     // the dataflow solve on the 170^3 stencil)
-    if (adj && single && p->d_valsT && p->nnz) {
-        HIPCHK(launch_gather(p->d_valsT, vals, p->d_perm, p->nnz, s));
-        a.vals = p->d_valsT;
+    double *valsT = scr.valsT ? scr.valsT : p->d_valsT;
+    if (adj && single && valsT && p->nnz) {
+        HIPCHK(launch_gather(valsT, vals, p->d_perm, p->nnz, s));
+        a.vals = valsT;
     }
     if (sp.path != 3 && b != x && !D.df_tasks.empty()) {
         const int64_t d0 = mat >= 0 ? D.df_ptr[mat] : 0;
@@ -1600,6 +1610,43 @@ ddf_status ddf_sptrsv_value_grad(ddf_plan_t p, const double *d_x, const double *
         return fail(DDF_E_ARG, "gvals overlaps another buffer");
     if (p->n_rows == 0) return DDF_OK;
     HIPCHK(launch_gv_pass(p, d_gb, d_x, d_gvals, -1.0, nrhs, (hipStream_t)stream));
+    return DDF_OK;
+}
+
+ddf_status ddf_sptrsv_adjoint_noalloc(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gx,
+                                      double *d_gb, double *d_gvals, int32_t nrhs, ddf_stream_t stream) {
+    if (ddf_status s = need_device(p)) return s;
+    if (p->kind != DDF_SPTRSV_LOWER || p->batch) return fail(DDF_E_KIND, "plan is not a single-matrix SpTRSV plan");
+    if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
+    if (ddf_status s = check_nrhs(nrhs)) return s;
+    d_vals = vals_or_own(p, d_vals);
+    int64_t nb = p->n_rows * nrhs * 8;
+    if ((!d_vals && p->nnz) || (!d_gx && p->n_rows) || (!d_gb && p->n_rows) || (d_gvals && !d_x))
+        return fail(DDF_E_ARG, "NULL buffer");
+    if (d_gb != d_gx && overlap(d_gb, nb, d_gx, nb)) return fail(DDF_E_ARG, "gb and gx partially overlap");
+    if (overlap(d_gb, nb, d_x, nb)) return fail(DDF_E_ARG, "gb overlaps x");
+    if (d_gvals && (overlap(d_gvals, p->nnz * 8, d_gb, nb) || overlap(d_gvals, p->nnz * 8, d_x, nb)))
+        return fail(DDF_E_ARG, "gvals overlaps another buffer");
+    if (p->nnz > NOALLOC_VALUES)
+        return fail(DDF_E_ARG, "ddf_sptrsv_adjoint_noalloc: " + std::to_string(p->nnz) +
+                                   " values exceed its static scratch of " + std::to_string(NOALLOC_VALUES));
+    if (p->n_rows == 0) return DDF_OK;
+    double *scr = nullptr;
+    HIPCHK(noalloc_scratch(&scr));
+    SolveScratch ss;
+    ss.ctr = reinterpret_cast<unsigned *>(scr);
+    ss.valsT = scr + NOALLOC_CTR_WORDS / 2;
+    ss.err = p->d_ctr_adj + CTR_STRIDE; // reported by ddf_plan_sync_status like the other calls
+    hipStream_t s = (hipStream_t)stream;
+    // the dataflow transposed solve (in place: one launch per level), whatever path the plan
+    // takes otherwise, then the value gradient
+    const int32_t path = p->sp_a.path;
+    p->sp_a.path = d_gb == d_gx ? 3 : 1;
+    ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, true, d_vals, d_gx, d_gb, d_x, nullptr, nrhs,
+                                 kt_for(nrhs), s, -1, ss);
+    p->sp_a.path = path;
+    if (st) return st;
+    if (d_gvals) HIPCHK(launch_gv_pass(p, d_gb, d_x, d_gvals, -1.0, nrhs, s));
     return DDF_OK;
 }
 

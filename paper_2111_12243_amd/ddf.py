@@ -25,6 +25,7 @@ STATUS = ["DDF_OK", "DDF_E_ARG", "DDF_E_CSR", "DDF_E_NOT_LOWER", "DDF_E_NO_DIAG"
  DDF_E_DEVICE, DDF_E_UNSUPPORTED) = range(10)
 
 EXPORTED = [
+    "ddf_sptrsv_adjoint_noalloc",
     "ddf_plan_time_kernels", "ddf_plan_kernel_time",
     "ddf_opts_default", "ddf_inspect", "ddf_inspect_batch", "ddf_plan_destroy", "ddf_spmv",
     "ddf_spmv_v", "ddf_sptrsv", "ddf_sptrsv_v", "ddf_spmv_adjoint", "ddf_sptrsv_adjoint", "ddf_sptrsv_value_grad",
@@ -110,6 +111,7 @@ def lib():
             "ddf_spmv_adjoint": (I32, [P, P, P, P, P, P, I32, P]),
             "ddf_sptrsv_adjoint": (I32, [P, P, P, P, P, P, I32, P]),
             "ddf_sptrsv_value_grad": (I32, [P, P, P, P, I32, P]),
+            "ddf_sptrsv_adjoint_noalloc": (I32, [P, P, P, P, P, P, I32, P]),
             "ddf_sptrsv_batch": (I32, [P, P, P, P, P]),
             "ddf_sptrsv_batch_adjoint": (I32, [P, P, P, P, P, P, P]),
             "ddf_graph_create_batch": (I32, [P, I32, P, P, P, P, P, C.POINTER(P)]),
@@ -259,6 +261,12 @@ def ddf_spmv_adjoint(plan, vals, x, gy, gx, gvals, nrhs, stream=None):
 def ddf_sptrsv_adjoint(plan, vals, x, gx, gb, gvals, nrhs, stream=None):
     _check(lib().ddf_sptrsv_adjoint(plan.handle, _ptr(vals), _ptr(x), _ptr(gx), _ptr(gb), _ptr(gvals),
                                     nrhs, _stream(stream)))
+
+
+def ddf_sptrsv_adjoint_noalloc(plan, vals, x, gx, gb, gvals, nrhs, stream=None):
+    """ddf_sptrsv_adjoint with its scratch in the library's static device array (no allocation)."""
+    _check(lib().ddf_sptrsv_adjoint_noalloc(plan.handle, _ptr(vals), _ptr(x), _ptr(gx), _ptr(gb), _ptr(gvals),
+                                            nrhs, _stream(stream)))
 
 
 def ddf_sptrsv_value_grad(plan, x, gb, gvals, nrhs, stream=None):
