@@ -26,7 +26,11 @@
  *    transposed order) is per direction.
  *  - Arguments are validated before any launch.  On an error no kernel is launched,
  *    outputs are untouched, and ddf_last_error() holds a message (thread-local).
- *  - A zero diagonal is not an error: it gives inf/nan by IEEE rules.
+ *  - A zero diagonal is not an error: it gives inf/nan by IEEE rules.  The dataflow and
+ *    one-launch-per-level solves compute (b_i - sum) / L_ii as forward substitution does, so
+ *    every entry has the substitution's IEEE class (+inf, -inf, nan); the single-block solve
+ *    divides each value of a row by L_ii before summing, so the same entries are non-finite
+ *    but some that substitution makes +-inf come out nan.
  */
 #ifndef DDF_H
 #define DDF_H

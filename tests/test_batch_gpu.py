@@ -100,3 +100,63 @@ def test_graph_replays(path):
         assert np.array_equal(out.cpu().numpy(), ref), f"replay {rep}"
     ddf.ddf_plan_sync_status(plan)
     g.close()
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_adjoint_graph_replays(path):
+    # the batched adjoint (transposed solve and value gradient) captured once and replayed, with
+    # eager work between the replays: every replay equals the direct call, which the oracle checks
+    print(f"adjoint graph replays path={path}", flush=True)
+    mats, plan, vals, B, G = make_batch(8, 500, 5000, path)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    refs = [O.sptrsv(m["L"], m["B"]) for m in mats]
+    dv, dg, dxf = d(vals), d(G), d(np.concatenate([r.ravel() for r in refs]))
+    gb, gv = torch.empty_like(dg), torch.empty_like(dv)
+    ddf.ddf_sptrsv_batch_adjoint(plan, dv, dxf, dg, gb, gv)
+    ddf.ddf_plan_sync_status(plan)
+    want_gb, want_gv = gb.cpu().numpy().copy(), gv.cpu().numpy().copy()
+    for m, lam, gvm, ref in zip(mats, split(want_gb, mats), split_vals(want_gv, mats), refs):
+        GBr, GVr = O.sptrsv_adj(m["L"], ref, m["G"])
+        check_solve(m["L"], m["G"], lam, GBr, transposed=True)
+        check_gv_solve(m["L"], ref, lam, GBr, gvm, GVr)
+    out_gb, out_gv = torch.full_like(dg, np.nan), torch.full_like(dv, np.nan)
+    g = ddf.ddf_graph_create_batch(plan, 1, dv, dg, dxf, out_gb, out_gv)
+    for rep in range(3):
+        out_gb.fill_(np.nan)
+        out_gv.fill_(np.nan)
+        torch.cuda.synchronize()
+        ddf.ddf_graph_launch(g)
+        torch.cuda.synchronize()
+        assert np.array_equal(out_gb.cpu().numpy(), want_gb), f"replay {rep}"
+        assert np.array_equal(out_gv.cpu().numpy(), want_gv), f"replay {rep}"
+        ddf.ddf_sptrsv_batch_adjoint(plan, dv, dxf, dg, gb, gv)  # eager work between replays
+        torch.cuda.synchronize()
+    ddf.ddf_plan_sync_status(plan)
+    g.close()
+
+
+def test_full_batch_workload():
+    # all 256 matrices of the batch workload (n log-uniform in [1e3, 2e5], 1..32 right-hand
+    # sides), forward and adjoint, every member against the oracle
+    print("full batch workload", flush=True)
+    w = I.workload("c4")
+    mats = w.batch
+    Ls = [m["L"] for m in mats]
+    plan = ddf.ddf_inspect_batch(1, Ls, [m["k"] for m in mats])
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    dv = d(np.concatenate([L.values for L in Ls]))
+    db = d(np.concatenate([m["B"].ravel() for m in mats]))
+    dg = d(np.concatenate([m["G"].ravel() for m in mats]))
+    dx = torch.full_like(db, np.nan)
+    ddf.ddf_sptrsv_batch(plan, dv, db, dx)
+    ddf.ddf_plan_sync_status(plan)
+    refs = [O.sptrsv(m["L"], m["B"]) for m in mats]
+    for m, x, ref in zip(mats, split(dx.cpu().numpy(), mats), refs):
+        check_solve(m["L"], m["B"], x, ref)
+    gb, gv = torch.full_like(db, np.nan), torch.full_like(dv, np.nan)
+    ddf.ddf_sptrsv_batch_adjoint(plan, dv, d(np.concatenate([r.ravel() for r in refs])), dg, gb, gv)
+    ddf.ddf_plan_sync_status(plan)
+    for m, lam, gvm, ref in zip(mats, split(gb.cpu().numpy(), mats), split_vals(gv.cpu().numpy(), mats), refs):
+        GBr, GVr = O.sptrsv_adj(m["L"], ref, m["G"])
+        check_solve(m["L"], m["G"], lam, GBr, transposed=True)
+        check_gv_solve(m["L"], ref, lam, GBr, gvm, GVr)

@@ -356,3 +356,49 @@ def test_value_grad_argument_checks():
     rows = np.repeat(np.arange(L.n_rows), np.diff(L.row_ptr))
     want = -(host(gb)[rows] * host(x)[L.col_idx]).sum(1)
     assert np.allclose(host(gv), want, rtol=1e-13, atol=1e-14)
+
+
+# ---------------------------------------------------------------- zero diagonals
+
+def same_nonfinite(got, ref, exact_classes):
+    """The oracle's non-finite entries (a zero diagonal and every row that depends on it) are
+    non-finite on the device too, and the finite ones agree within the solve tolerance.
+    exact_classes: also the same inf signs and nans, entry by entry."""
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(got), fin)
+    if fin.any():
+        err = np.max(np.abs(got[fin] - ref[fin]))
+        assert err <= 1e-12 * max(np.max(np.abs(ref[fin])), 1e-300)
+    if exact_classes:
+        assert np.array_equal(got[~fin], ref[~fin], equal_nan=True)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_zero_diagonal_ieee(k):
+    # rows with a zero diagonal: forward substitution gives (b - sum) / 0 = +-inf there (the
+    # oracle's IEEE rule) and inf or nan in every row that reads them.  The dataflow and
+    # per-level kernels divide as the oracle does (same classes); the single-block kernel
+    # divides the values first, so the same entries are non-finite, some as nan
+    base = I.random_lower(600, 31, density=0.01)
+    vals = base.values.copy()
+    diag = base.row_ptr[1:] - 1
+    vals[diag[[100, 350]]] = 0.0
+    L = I.CSR(base.n_rows, base.n_cols, base.row_ptr, base.col_idx, vals)
+    rng = np.random.default_rng(4)
+    B, G = rng.uniform(-1, 1, (L.n_rows, k)), rng.uniform(-1, 1, (L.n_rows, k))
+    with np.errstate(all="ignore"):
+        ref = O.sptrsv(L, B)
+        lam_ref, _ = O.sptrsv_adj(L, np.nan_to_num(ref), G)
+    assert (~np.isfinite(ref)).sum() > 2 and (~np.isfinite(lam_ref)).sum() > 2
+    for path in (1, 2, 3):
+        print(f"zero diagonal k={k} path={path}", flush=True)
+        plan = ddf.ddf_inspect(1, L, ddf.ddf_opts_default(solve_path=path))
+        info = ddf.ddf_plan_info(plan)
+        b, x = dev(B), torch.empty((L.n_rows, k), dtype=torch.float64, device=DEV)
+        ddf.ddf_sptrsv(plan, b, x, k)
+        ddf.ddf_plan_sync_status(plan)
+        same_nonfinite(host(x), ref, info["solve_path"] != 2)
+        gb = torch.empty_like(x)
+        ddf.ddf_sptrsv_adjoint(plan, dev(L.values), None, dev(G), gb, None, k)
+        ddf.ddf_plan_sync_status(plan)
+        same_nonfinite(host(gb), lam_ref, info["solve_path_adj"] != 2)
