@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--profile-op", default="", help="run only these ops K times each (for rocprofv3)")
     ap.add_argument("--tsync", action="store_true", help="dependent-hop latency of the solve kernels")
+    ap.add_argument("--cost-model", action="store_true",
+                    help="Eq. (1) plan cost against measured SpMV kernel time over a family of patterns")
     return ap.parse_args()
 
 
@@ -143,6 +145,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.tsync:
         return bench_tsync(args, np, torch, ddf, I, dev)
+    if args.cost_model:
+        return bench_cost_model(args, np, torch, ddf, I, dev)
     if args.workload == "c4":
         return bench_batch(args, np, torch, ddf, I, dev)
     t0 = time.time()
@@ -285,6 +289,13 @@ def main():
             roofline["two_term_floor_ms"] = round(floor_ms, 4)
             roofline["frac_of_two_term_floor"] = round(floor_ms / kernel_ms, 4)
 
+    # inspector cost and its amortisation (Sec. V-C): NER = inspector time over the time one
+    # executor run saves against the plain kernel; the inspector time includes the device
+    # tables' upload (ddf_inspect's wall time, both plans of a pattern for the forward and
+    # adjoint calls)
+    t_insp = {"spmv": tA, "spmv_adj": tA, "sptrsv": tL, "sptrsv_adj": tL}
+    ner = {n: (round(t_insp[n] * 1e3 / (plain_ops[n] - op_ms[n]), 1) if plain_ops[n] > op_ms[n] else None)
+           for n in ops}
     bytes_step = sum(t[0] for t in traffic.values())
     value = bytes_step / (ms / 1e3) / 1e9
     cpu = None
@@ -303,7 +314,7 @@ def main():
                    "solve_kernel": {"fwd": kernel_of.get("sptrsv"), "adj": kernel_of.get("sptrsv_adj")},
                    "codelets_A_by_type": info_A["codelets_by_type"], "ops_A_by_type": info_A["ops_by_type"],
                    "codelets_L_by_type": info_L.get("codelets_by_type"), "ops_L_by_type": info_L.get("ops_by_type"),
-                   "inspect_s": {"A": round(tA, 3), "L": round(tL, 3)},
+                   "inspect_s": {"A": round(tA, 3), "L": round(tL, 3)}, "ner": ner,
                    "timing": "median of K steps, 1 GiB written between steps, one stream"},
         "pct_of_peak": round(100 * value / PEAK_GBPS, 2),
         "plain": {"ms_per_step": round(ms_plain, 4), "value": round(bytes_step / (ms_plain / 1e3) / 1e9, 2),
@@ -419,6 +430,90 @@ def bench_tsync(args, np, torch, ddf, I, dev):
     print(json.dumps(out), flush=True)
 
 
+def cost_model_patterns(np, I):
+    """A family of seeded sparse patterns of about 2-8M stored entries: stencils of several
+    shapes, banded matrices with gaps, random rows of column runs, power-law rows, and random
+    scattered columns (the plan's codelet mix goes from all-BLAS to all-PSC II)."""
+    pats = []
+    for nx in (160, 224):
+        pats.append((f"5pt_{nx}^2", I.laplacian(nx * 4, nx, 1, I.OFFS_5PT, 4.0)))
+    for nx in (60, 80):
+        pats.append((f"27pt_{nx}^3", I.laplacian(nx, nx, nx, I.OFFS_27PT, 26.0)))
+    offs7 = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    pats.append(("7pt_100^3", I.laplacian(100, 100, 100, offs7, 6.0)))
+    for b, n in ((1, 1 << 20), (4, 1 << 19), (16, 1 << 18)):
+        # band of 2b + 1 diagonals
+        rows = np.repeat(np.arange(n), 2 * b + 1)
+        cols = rows + np.tile(np.arange(-b, b + 1), n)
+        ok = (cols >= 0) & (cols < n)
+        pats.append((f"band{2 * b + 1}_{n}", I.csr_from_pairs(n, n, rows[ok], cols[ok], np.ones(int(ok.sum())))))
+    for gap, n in ((3, 1 << 19), (7, 1 << 19)):
+        # strided rows: columns i, i + gap, i + 2 gap, ... (PSC I with a shared table)
+        rows = np.repeat(np.arange(n), 6)
+        cols = (rows + np.tile(np.arange(6) * gap * np.arange(1, 7), n)) % n
+        pats.append((f"gap{gap}_{n}", I.csr_from_pairs(n, n, rows, cols, np.ones(rows.size))))
+    def unique_pairs(n, rows, cols):
+        key = np.unique(rows.astype(np.int64) * n + cols)
+        return I.csr_from_pairs(n, n, key // n, key % n, np.ones(key.size))
+
+    for seed, n, d in ((1, 400000, 4), (2, 300000, 12)):
+        # d random columns per row
+        rng = np.random.default_rng(900 + seed)
+        rows = np.repeat(np.arange(n), d)
+        pats.append((f"random{d}_{n}", unique_pairs(n, rows, rng.integers(0, n, rows.size))))
+    for seed, n, ln in ((3, 300000, 4), (4, 300000, 12)):
+        # two runs of ln consecutive columns per row, at random places
+        rng = np.random.default_rng(900 + seed)
+        starts = rng.integers(0, n - ln, (n, 2))
+        rows = np.repeat(np.arange(n), 2 * ln)
+        cols = (starts[:, :, None] + np.arange(ln)[None, None, :]).reshape(-1)
+        pats.append((f"runs{ln}_{n}", unique_pairs(n, rows, cols)))
+    for n in (300000, 600000):
+        pats.append((f"chunglu_{n}", I.c3_chung_lu(n=n).A))
+    return pats
+
+
+def bench_cost_model(args, np, torch, ddf, I, dev):
+    """The cost model of Eq. (1) against the GPU (the analogue of the paper's Fig. 5, which
+    fits measured codelet time against the model): per pattern the summed Eq. (1) cost of the
+    SpMV plan and the measured time of its SpMV kernel (one right-hand side, median of K with
+    a 1 GiB flush before each), then a least-squares line time = a cost + b and its r^2, beside
+    the same fit against the stored-entry count."""
+    timer = Timer(torch, dev)
+    pts = []
+    for name, A in cost_model_patterns(np, I):
+        p = ddf.ddf_inspect(ddf.DDF_SPMV, A, ddf.ddf_opts_default(build_adjoint=0))
+        cod = ddf.ddf_plan_export(p, 0)["codelets"]
+        cost = int(cod[:, 17].sum())
+        x = torch.from_numpy(np.random.default_rng(5).uniform(-1, 1, (A.n_cols, 1))).to(dev)
+        y = torch.empty((A.n_rows, 1), dtype=torch.float64, device=dev)
+        ker = []
+        for _ in range(args.steps):
+            timer.flush()
+            ddf.ddf_plan_time_kernels(p, 1)
+            ddf.ddf_spmv(p, x, y, 1)
+            kms, calls, _ = ddf.ddf_plan_kernel_time(p)
+            ker.append(kms / max(calls, 1))
+        t = median(ker) * 1e3
+        share = [int(v) for v in np.bincount(cod[:, 0], weights=cod[:, 7], minlength=3)]
+        pts.append({"pattern": name, "nnz": A.nnz, "eq1_cost": cost, "us": round(t, 2), "ops_by_type": share})
+        log(f"[bench] {name}: nnz {A.nnz} cost {cost} {t:.1f} us ops by type {share}")
+        del p
+
+    def fit(xs, ys):
+        xs, ys = np.asarray(xs, float), np.asarray(ys, float)
+        a, b = np.polyfit(xs, ys, 1)
+        r = ys - (a * xs + b)
+        return a, b, 1.0 - float(r @ r) / float(((ys - ys.mean()) ** 2).sum())
+
+    us = [q["us"] for q in pts]
+    a, b, r2 = fit([q["eq1_cost"] for q in pts], us)
+    a2, b2, r2n = fit([q["nnz"] for q in pts], us)
+    print(json.dumps({"points": pts, "fit_eq1": {"us_per_cost_unit": a, "us0": b, "r2": round(r2, 4)},
+                      "fit_nnz": {"us_per_entry": a2, "us0": b2, "r2": round(r2n, 4)},
+                      "sources_sha": kernels_sha()}), flush=True)
+
+
 def bench_batch(args, np, torch, ddf, I, dev):
     """The batched solve and its adjoint on C4 (256 matrices, 1..32 right-hand sides)."""
     t0 = time.time()
@@ -529,6 +624,8 @@ def bench_batch(args, np, torch, ddf, I, dev):
         "config": {"workload": w.name, "matrices": len(mats), "rows": sum(m.n_rows for m in mats),
                    "nnz_L": sum(m.nnz for m in mats), "nrhs_range": [min(ks), max(ks)],
                    "max_levels": binfo["max_levels"], "inspect_s": round(t_insp, 3),
+                   "ner": {"sptrsv_batch": round(t_insp * 1e3 / (per_matrix_ms - op_ms["sptrsv_batch"]), 1)
+                           if per_matrix_ms > op_ms["sptrsv_batch"] else None},
                    "solve_kernel": {"fwd": bnames.get(binfo["solve_path"]), "adj": bnames.get(binfo["solve_path_adj"])}},
         "pct_of_peak": round(100 * value / PEAK_GBPS, 2),
         "per_op": per_op, "bytes_alg_per_step": bytes_step,

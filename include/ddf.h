@@ -9,9 +9,9 @@
  * and chosen per window by the cost model of Eq. (1)), grouped into partitions of
  * independent rows (dependence levels for the solve); an executor (Sec. IV-B) runs the
  * codelets partition by partition.  Here the executor is a set of HIP kernels; the solve
- * runs its levels in one single-block kernel when every level fits one block (one
- * right-hand side), else in one launch per level or in one persistent kernel with level
- * counters, as set by the options or the autotuner.
+ * runs in one persistent dataflow kernel (a row waits only for the solution values it reads;
+ * no level barriers), in one single-block kernel when every level fits one block (one
+ * right-hand side), or in one launch per level, as set by the options or the autotuner.
  *
  * Conventions for every call below:
  *  - Host arrays are read during the call only; nothing keeps a pointer to them.
@@ -22,8 +22,8 @@
  *    allocate nothing, and copy nothing synchronously, so they may be captured in a graph.
  *    Per plan, one forward call (SpMV, solve) and one adjoint call (ddf_spmv_adjoint,
  *    ddf_sptrsv_adjoint, ddf_sptrsv_value_grad) may be in flight at a time, on any
- *    streams: the solves' scratch (level counters, per-call streams, the values in
- *    transposed order) is per direction.
+ *    streams: the solves' scratch (the dataflow kernel's counters, per-call streams, the
+ *    values in transposed order) is per direction.
  *  - Arguments are validated before any launch.  On an error no kernel is launched,
  *    outputs are untouched, and ddf_last_error() holds a message (thread-local).
  *  - A zero diagonal is not an error: it gives inf/nan by IEEE rules.  The dataflow and
@@ -77,13 +77,13 @@ typedef struct {
                               next power of two of row length / this); 0 = default 4       */
     int32_t rows_passes;   /* schedule: row passes per wavefront task; 0 = default 2       */
     int32_t xcd_remap;     /* schedule: give each XCD a contiguous block range; -1 default */
-    int32_t solve_blocks;  /* schedule (solve): 256-thread blocks of the persistent kernel;
-                              0 = every block the device keeps resident                     */
+    int32_t solve_blocks;  /* schedule (solve): 256-thread blocks of the persistent dataflow
+                              kernel; 0 = every block the device keeps resident at once     */
     int32_t solve_path;    /* solve kernel: 0 auto (single-block when every level fits one
-                              1024-lane pass, else multi-block; batches: one launch per level
-                              over all matrices, one op per lane, one row pass), 1 multi-block
-                              (batches: one persistent launch), 2 single-block when
-                              possible, 3 one launch per level of the multi-block tasks     */
+                              1024-lane pass, else the dataflow kernel; batches: one launch
+                              per level over all matrices, one op per lane, one row pass),
+                              1 the dataflow kernel (one persistent launch, batches too),
+                              2 single-block when possible, 3 one launch per level        */
     int32_t thin_helpers;  /* single-block solve: helper blocks that pull the next levels'
                               tables into the solver's L2; -1 default (4), 0 none, max 8  */
     int32_t thin_ahead;    /* single-block solve: levels the helpers run ahead; 0 default
@@ -193,9 +193,12 @@ ddf_status ddf_spmv(ddf_plan_t plan, const double *d_x, double *d_y, int32_t nrh
 ddf_status ddf_spmv_v(ddf_plan_t plan, const double *d_vals, const double *d_x, double *d_y,
                       int32_t nrhs, ddf_stream_t stream);
 
-/* SpTRSV executor: L X = B, every level inside one persistent kernel with device-side
- * level waits.  d_b and d_x are (n, nrhs); d_b == d_x (in place) is allowed; partial
- * overlap is not. */
+/* SpTRSV executor: L X = B on the plan's solve path: by default the single-block kernel when
+ * eligible (one right-hand side, every level within one block), else the persistent dataflow
+ * kernel (one launch: the output is first marked unsolved, then each row is solved once the
+ * solution values it reads are there); solve_path 3: one launch per level.  d_b and d_x are
+ * (n, nrhs); d_b == d_x (in place) is allowed (the dataflow path then takes one launch per
+ * level); partial overlap is not. */
 ddf_status ddf_sptrsv(ddf_plan_t plan, const double *d_b, double *d_x, int32_t nrhs,
                       ddf_stream_t stream);
 ddf_status ddf_sptrsv_v(ddf_plan_t plan, const double *d_vals, const double *d_b, double *d_x,
@@ -253,7 +256,10 @@ ddf_status ddf_sptrsv_batch_adjoint(ddf_plan_t plan, const double *d_vals_packed
                                     ddf_stream_t stream);
 
 /* hipGraph of one batched solve (forward, or adjoint when adjoint = 1) on fixed buffers:
- * captured once, replayed by ddf_graph_launch on any stream. */
+ * captured once, replayed by ddf_graph_launch on any stream.  ddf_autotune replaces the
+ * plan's schedule buffers: a graph captured before it (this one, or any capture of the
+ * execution calls) would read freed memory, so ddf_graph_launch refuses it with DDF_E_ARG;
+ * capture again after tuning.  Destroy a plan's graphs before the plan. */
 ddf_status ddf_graph_create_batch(ddf_plan_t plan, int32_t adjoint, const double *d_vals_packed,
                                   const double *d_in_packed, const double *d_x_packed,
                                   double *d_out_packed, double *d_gvals_packed,
@@ -279,10 +285,13 @@ ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t plan, const double *d_vals_pac
                                        const double *d_b_packed, double *d_x_packed,
                                        ddf_stream_t stream);
 
-/* Autotuner: times schedule candidates (ops per lane, row passes, XCD remap) for `op` with
- * nrhs right-hand sides on scratch buffers, keeps the fastest in the plan.  Results are
- * cached by plan hash (in memory, and in the JSON file named by DDF_TUNE_CACHE if set).
- * Synchronises `stream`.  budget_ms bounds the total timing time (<= 0: no bound). */
+/* Autotuner: times schedule candidates (SpMV: ops per lane, row passes, XCD remap; solves:
+ * single-block helper settings, one launch per level, dataflow grid sizes) for `op` with nrhs
+ * right-hand sides on scratch buffers, keeps the fastest in the plan.  Results are cached by
+ * plan hash (in memory, and in the JSON file named by DDF_TUNE_CACHE if set).  Synchronises
+ * `stream`; allocates its scratch and frees it.  It replaces the plan's schedule buffers, so
+ * graphs captured earlier on the plan must be captured again (see ddf_graph_create_batch).
+ * budget_ms bounds the total timing time (<= 0: no bound). */
 ddf_status ddf_autotune(ddf_plan_t plan, ddf_op op, int32_t nrhs, ddf_stream_t stream,
                         double budget_ms);
 
@@ -300,11 +309,13 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
  *   cods   [n_cods][16]  flags, m, nn, row0, row_step, op0, op_step, col0, sigma0, sigma1,
  *                        rows_off, ops_off, cnt_off, xt_off, xp_off, mat
  *   tasks  [n_tasks][4]  codelet, first row, end row, meta (log2 lanes per row | phase << 8 |
- *                        look-ahead eligible << 9 | streamed << 10); for SpMV the list used
- *                        with one right-hand side; for the solve in ticket order
- *   sync   [n_tasks][4]  solve: level counter to wait on (-1: none), task count it must
- *                        reach, level counter to signal (-1: none), level (-1 for
- *                        the value-gradient tasks of a batch adjoint)
+ *                        streamed << 10 | row ranges << 11 | long row << 12 | row list << 13);
+ *                        for SpMV the list used with one right-hand side; for the solve the
+ *                        one-launch-per-level schedule, in level order
+ *   sync   [n_tasks][4]  solve: the level order of that schedule as a counter protocol (the
+ *                        counter of the level before, its task count, the task's own level
+ *                        counter; checked by the CPU replay), then the level the launch
+ *                        groups by (-1 for the value-gradient tasks of a batch adjoint)
  *   tasksN [n_tasksN][4] SpMV: the list used with several right-hand sides */
 typedef struct {
     const int32_t *cods, *aux, *tasks, *sync, *tasksN;
@@ -359,7 +370,8 @@ ddf_status ddf_plan_kernel_time(ddf_plan_t plan, double *ms, int64_t *calls, int
 
 /* Synchronises `stream`, then reads and clears the plan's device error flag. */
 ddf_status ddf_plan_sync_status(ddf_plan_t plan, ddf_stream_t stream);
-/* Test hook: spin limit of the persistent kernels' level waits (0 = default). */
+/* Test hook: spin limit of the dataflow solve's waits (0 = default): a wait that exceeds it
+ * raises the plan's error flag (DDF_E_DEVICE from ddf_plan_sync_status) and stops. */
 ddf_status ddf_plan_set_spin_limit(ddf_plan_t plan, int64_t limit);
 
 const char *ddf_status_string(ddf_status s);

@@ -57,6 +57,8 @@ def lib():
         L.orc_transpose.argtypes = [I32, I32, P, P, P, P, P, P, P]
         L.orc_inspect.argtypes = [I32, I32, I32, P, P, I32, I32]
         L.orc_inspect.restype = C.POINTER(_Plan)
+        L.orc_inspect_ex.argtypes = [I32, I32, I32, P, P, I32, I32, I32]
+        L.orc_inspect_ex.restype = C.POINTER(_Plan)
         L.orc_plan_free.argtypes = [C.POINTER(_Plan)]
         L.orc_classify.argtypes = [I32, P, P, P, I64, P]
         L.orc_classify.restype = I32
@@ -153,12 +155,13 @@ def transpose(A):
     return AT, perm
 
 
-def inspect(kind, A, t=64, sample=1):
+def inspect(kind, A, t=64, sample=1, only_blas=False):
     """Canonical plan tables of Algorithm 1 for kind 0 (SpMV), 1 (lower solve, diagonal last)
-    or 2 (transposed solve: upper, diagonal first, levels from the last row)."""
+    or 2 (transposed solve: upper, diagonal first, levels from the last row).  only_blas: the
+    ablation's BLAS-only column-slice cover of every window."""
     rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
-    pp = lib().orc_inspect(kind, A.n_rows, A.n_cols, _p(rp), _p(ci), t, sample)
+    pp = lib().orc_inspect_ex(kind, A.n_rows, A.n_cols, _p(rp), _p(ci), t, sample, int(only_blas))
     try:
         p = pp.contents
         h = np.array(p.header[:], dtype=np.int64)
@@ -181,11 +184,11 @@ def inspect(kind, A, t=64, sample=1):
         lib().orc_plan_free(pp)
 
 
-def inspect_adjoint(kind, A, t=64, sample=1):
+def inspect_adjoint(kind, A, t=64, sample=1, only_blas=False):
     """Plan of the adjoint pass: for SpMV, A^T inspected as SpMV; for the lower solve,
     U = L^T (diagonal first) inspected as kind 2 on reverse levels.  Returns (plan, perm)."""
     AT, perm = transpose(A)
-    return inspect(0 if kind == 0 else 2, AT, t, sample), perm
+    return inspect(0 if kind == 0 else 2, AT, t, sample, only_blas), perm
 
 
 def classify(kind, A, q):

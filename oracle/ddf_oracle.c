@@ -428,11 +428,109 @@ static void emit(const kernel_t *K, const int64_t *q, int64_t m, int64_t part, i
     }
 }
 
+/* ----------------------------------------------------------------------------------------
+ * The BLAS-only cover of a window: the ablation of Sec. V-A and V-B, where every codelet is
+ * a BLAS codelet (all three access functions strided, Sec. III-B).  Rows whose columns do
+ * not keep one stride cannot be whole BLAS codelets, so codelets become column slices
+ * (Sec. III-C, the three-BLAS cover of the worked example): a codelet covers ops
+ * [a, a + w) of m consecutive rows of the window.
+ *   1. Each row's ops are cut into slices from left to right; a slice starts at the first op
+ *      not yet cut and takes the following ops while the column difference stays the one
+ *      between its first two ops (a slice of one op has stride 0).
+ *   2. Slices are taken row by row (window order), left to right; an unused slice starts a
+ *      codelet, which grows down to the next row of the window while that row has an unused
+ *      slice at the same op offset with the same width and column stride, and the row
+ *      number, value index and first column still move by the steps of the first two rows.
+ * Rows without ops get no codelet.  Each codelet costs |p| + 3 by Eq. (1) (no tables).
+ * -------------------------------------------------------------------------------------- */
+typedef struct {
+    int64_t a, w, s1;
+    int used;
+} slice_t;
+
+static void emit_slice(const kernel_t *K, const int64_t *q, int64_t m, int64_t a, int64_t w, int64_t s1,
+                       int64_t part, int64_t region, int64_t u, vec64 *cod) {
+    int64_t op0 = opstart(K, q[0]) + a;
+    push64(cod, 0); /* BLAS */
+    push64(cod, F_S0 | F_S1 | F_S2 | F_SEP | F_RECT);
+    push64(cod, part);
+    push64(cod, region);
+    push64(cod, u);
+    push64(cod, m);
+    push64(cod, w);
+    push64(cod, m * w);
+    push64(cod, q[0]);
+    push64(cod, m >= 2 ? q[1] - q[0] : 0);
+    push64(cod, op0);
+    push64(cod, m >= 2 ? opstart(K, q[1]) - opstart(K, q[0]) : 0);
+    push64(cod, K->ci[op0]);
+    push64(cod, m >= 2 ? f2(K, q[1], a) - f2(K, q[0], a) : 0);
+    push64(cod, w >= 2 ? s1 : 0);
+    push64(cod, 0); /* aux_off: no tables */
+    push64(cod, 0);
+    push64(cod, m * w + 3);
+}
+
+/* Emits the window's BLAS-only codelets; returns their total Eq. (1) cost. */
+static int64_t blas_only_window(const kernel_t *K, const int64_t *q, int64_t T, int64_t part, int64_t region,
+                                vec64 *cod) {
+    slice_t **sl = (slice_t **)calloc(T, sizeof(slice_t *));
+    int64_t *ns = (int64_t *)calloc(T, sizeof(int64_t));
+    for (int64_t u = 0; u < T; u++) {
+        int64_t n = nops(K, q[u]);
+        sl[u] = (slice_t *)calloc(n > 0 ? n : 1, sizeof(slice_t));
+        int64_t a = 0;
+        while (a < n) {
+            int64_t w = 1, s1 = 0;
+            if (a + 1 < n) {
+                s1 = f2(K, q[u], a + 1) - f2(K, q[u], a);
+                w = 2;
+                while (a + w < n && f2(K, q[u], a + w) - f2(K, q[u], a + w - 1) == s1) w++;
+            }
+            slice_t s = {a, w, s1, 0};
+            sl[u][ns[u]++] = s;
+            a += w;
+        }
+    }
+    int64_t total = 0;
+    for (int64_t u = 0; u < T; u++) {
+        for (int64_t j = 0; j < ns[u]; j++) {
+            slice_t *s = &sl[u][j];
+            if (s->used) continue;
+            s->used = 1;
+            int64_t m = 1;
+            while (u + m < T) {
+                /* the next row's slice at the same op offset, unused, of the same shape */
+                slice_t *nx = NULL;
+                for (int64_t jj = 0; jj < ns[u + m]; jj++)
+                    if (sl[u + m][jj].a == s->a) nx = &sl[u + m][jj];
+                if (!nx || nx->used || nx->w != s->w || nx->s1 != s->s1) break;
+                /* the steps of the first two rows hold for rows, value starts and first columns */
+                if (m >= 2) {
+                    const int64_t *r = q + u;
+                    if (r[m] - r[m - 1] != r[1] - r[0]) break;
+                    if (opstart(K, r[m]) - opstart(K, r[m - 1]) != opstart(K, r[1]) - opstart(K, r[0])) break;
+                    if (f2(K, r[m], s->a) - f2(K, r[m - 1], s->a) != f2(K, r[1], s->a) - f2(K, r[0], s->a)) break;
+                }
+                nx->used = 1;
+                m++;
+            }
+            emit_slice(K, q + u, m, s->a, s->w, s->s1, part, region, u, cod);
+            total += m * s->w + 3;
+        }
+    }
+    for (int64_t u = 0; u < T; u++) free(sl[u]);
+    free(sl);
+    free(ns);
+    return total;
+}
+
 /* Inspector.  kind: 0 SpMV, 1 lower solve (diagonal last), 2 transposed solve (upper,
  * diagonal first; levels run from the last row).  t: window.  sample: mine only windows
- * w with w % sample == 0 or w the last one (1 = all); unmined windows get chosen = -1. */
-orc_plan *orc_inspect(int32_t kind, int32_t n_rows, int32_t n_cols, const int32_t *rp,
-                      const int32_t *ci, int32_t t, int32_t sample) {
+ * w with w % sample == 0 or w the last one (1 = all); unmined windows get chosen = -1.
+ * only_blas: every window takes its BLAS-only cover (chosen = 3, costs [total, 0, 0]). */
+orc_plan *orc_inspect_ex(int32_t kind, int32_t n_rows, int32_t n_cols, const int32_t *rp,
+                         const int32_t *ci, int32_t t, int32_t sample, int32_t only_blas) {
     kernel_t K = {kind, rp, ci};
     orc_plan *p = (orc_plan *)calloc(1, sizeof(orc_plan));
     int64_t n = n_rows;
@@ -483,6 +581,15 @@ orc_plan *orc_inspect(int32_t kind, int32_t n_rows, int32_t n_cols, const int32_
                 nreg++;
                 continue;
             }
+            if (only_blas) {
+                push64(&reg, cod.n / NCOD);
+                push64(&reg, 3);
+                int64_t at = reg.n;
+                for (int s = 0; s < 3; s++) push64(&reg, 0);
+                reg.v[at] = blas_only_window(&K, q, T, l, nreg, &cod);
+                nreg++;
+                continue;
+            }
             int64_t cost[3];
             for (int s = 0; s < 3; s++) cost[s] = strategy(&K, q, T, s, NULL, NULL, NULL);
             int best = 0;
@@ -512,6 +619,11 @@ orc_plan *orc_inspect(int32_t kind, int32_t n_rows, int32_t n_cols, const int32_
     p->header[7] = cod.n / NCOD;
     p->header[8] = aux.n;
     return p;
+}
+
+orc_plan *orc_inspect(int32_t kind, int32_t n_rows, int32_t n_cols, const int32_t *rp,
+                      const int32_t *ci, int32_t t, int32_t sample) {
+    return orc_inspect_ex(kind, n_rows, n_cols, rp, ci, t, sample, 0);
 }
 
 /* Debug view used by the tests: the strided-function count k(u, m) of rows q[0..m-1] of a

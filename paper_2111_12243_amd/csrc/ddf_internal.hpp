@@ -91,7 +91,7 @@ struct DevTables {
     std::vector<int32_t> sync;         // solve: 4 int32 per task (wait counter, count, signal counter, level)
     std::vector<Task> df_tasks;        // dataflow solve: up to DF_RG rows of one codelet, in level order
     std::vector<int64_t> df_ptr;       // per-matrix ranges of df_tasks (per-matrix schedules only)
-    int64_t n_counters = 0;            // solve: level counters the schedule uses
+    int64_t n_counters = 0;            // solve: level counters of the sync protocol (CPU replay)
     int64_t csr_rows = 0, csr_nnz = 0; // SpMV, one right-hand side: rows run from the CSR pattern
     int64_t table_bytes1 = 0;          // plan bytes a one-RHS SpMV launch reads
     std::vector<int32_t> cod_aux;      // aux words of each codelet

@@ -12,12 +12,13 @@
 // row group.  G lanes cooperate on one row (G = 2^lg chosen per task by the scheduler),
 // 64/G rows per pass; partial sums are combined with cross-lane shuffles.
 //
-// The solve runs every level inside one persistent kernel.  Waves take tasks in ticket
-// order; a task of level l waits until its matrix has completed every task of levels < l
-// (per-matrix done counters).  Since tickets are handed out in order, every task a wave
-// waits on is held by a running wave, so no co-residency assumption is needed.  Solution
-// values cross XCDs through device-scope (sc1) stores and loads; a finished task waits for
-// its stores to complete (s_waitcnt vmcnt(0)) before bumping the counter.
+// The solve (Sec. IV-B: partitions in order, codelets of a partition in parallel) runs in one
+// of three kernels:
+//  - k_solve_df, the dataflow solve: one persistent launch with no level barriers; a row
+//    waits only for the solution values it reads, each of which is its own ready flag;
+//  - k_solve_thin, the single-block solve: one block runs every level, levels separated by
+//    block barriers, recent solutions in an LDS ring (one right-hand side, narrow levels);
+//  - k_solve_range, one launch per level (the launch boundary orders the levels).
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -1385,7 +1386,7 @@ template <int KT> __global__ __launch_bounds__(WAVE *WPB) void k_gv_chunks(GvArg
     }
 }
 
-int g_solve_blocks = 0; // resident blocks of the persistent kernel on the whole device
+int g_solve_blocks = 0; // blocks of the dataflow solve the whole device keeps resident at once
 int g_num_cu = 0;
 
 int solve_grid(int ntasks, int want) {

@@ -61,6 +61,7 @@ struct ddf_plan_s {
     uint64_t hash = 0;
     int max_levels = 0;
     std::vector<void *> allocs;
+    uint64_t generation = 0; // bumped whenever the schedule's device buffers are replaced
     // kernel timing (ddf_plan_time_kernels): event pairs around the main kernel of each call
     std::vector<hipEvent_t> tev;
     int32_t tev_used = 0;
@@ -82,6 +83,8 @@ std::pair<hipEvent_t, hipEvent_t> next_timer(ddf_plan_t p, int64_t launches) {
 struct ddf_graph_s {
     hipGraph_t g = nullptr;
     hipGraphExec_t e = nullptr;
+    ddf_plan_t plan = nullptr;
+    uint64_t generation = 0; // the plan's schedule generation the graph captured
 };
 
 namespace {
@@ -535,6 +538,7 @@ void drop_alloc(ddf_plan_t p, void *ptr) {
 
 ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     if (p->host_only) return DDF_OK;
+    p->generation++; // graphs captured before now read the buffers freed below
     // schedule buffers are replaced when the schedule changes (autotune)
     drop_alloc(p, D.d_tasks);
     drop_alloc(p, D.d_tasksN);
@@ -1174,7 +1178,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     p->sp_f.path = p->sp_a.path = o.solve_path;
     if (batch && o.solve_path == 0) {
         // batches: one launch per level over all matrices, one op per lane and one row pass
-        // (the one-launch persistent kernel is solve_path 1)
+        // (the one-launch dataflow kernel is solve_path 1)
         p->sp_f.path = p->sp_a.path = 3;
         p->sp_f.ops_per_lane = p->sp_a.ops_per_lane = 1;
         p->sp_f.passes = p->sp_a.passes = 1;
@@ -1719,6 +1723,8 @@ ddf_status ddf_graph_create_batch(ddf_plan_t p, int32_t adjoint, const double *d
         if (e == hipSuccess) e = e2;
     }
     if (e == hipSuccess && st == DDF_OK) e = hipGraphInstantiate(&g->e, g->g, nullptr, nullptr, 0);
+    g->plan = p;
+    g->generation = p->generation;
     (void)hipStreamDestroy(s);
     if (st != DDF_OK || e != hipSuccess) {
         if (g->e) (void)hipGraphExecDestroy(g->e);
@@ -1733,6 +1739,9 @@ ddf_status ddf_graph_create_batch(ddf_plan_t p, int32_t adjoint, const double *d
 
 ddf_status ddf_graph_launch(ddf_graph_t g, ddf_stream_t stream) {
     if (!g || !g->e) return fail(DDF_E_ARG, "graph is NULL");
+    if (g->plan->generation != g->generation)
+        return fail(DDF_E_ARG, "the plan's schedule changed (ddf_autotune) after this graph was captured: "
+                               "capture it again");
     HIPCHK(hipGraphLaunch(g->e, (hipStream_t)stream));
     return DDF_OK;
 }

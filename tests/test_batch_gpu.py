@@ -160,3 +160,27 @@ def test_full_batch_workload():
         GBr, GVr = O.sptrsv_adj(m["L"], ref, m["G"])
         check_solve(m["L"], m["G"], lam, GBr, transposed=True)
         check_gv_solve(m["L"], ref, lam, GBr, gvm, GVr)
+
+
+def test_graph_refused_after_autotune():
+    # tuning replaces the schedule buffers a captured graph reads: its replay is refused
+    print("graph after autotune", flush=True)
+    mats, plan, vals, B, G = make_batch(4, 300, 2000, 1)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    dv, db = d(vals), d(B)
+    out = torch.empty_like(db)
+    g = ddf.ddf_graph_create_batch(plan, 0, dv, db, None, out, None)
+    ddf.ddf_graph_launch(g)
+    torch.cuda.synchronize()
+    ddf.ddf_autotune(plan, ddf.DDF_OP_SPTRSV, 1, budget_ms=100)
+    with pytest.raises(ddf.DDFError) as e:
+        ddf.ddf_graph_launch(g)
+    assert e.value.status == ddf.DDF_E_ARG
+    g.close()
+    g2 = ddf.ddf_graph_create_batch(plan, 0, dv, db, None, out, None)
+    ddf.ddf_graph_launch(g2)
+    torch.cuda.synchronize()
+    ddf.ddf_plan_sync_status(plan)
+    for m, x in zip(mats, split(out.cpu().numpy(), mats)):
+        check_solve(m["L"], m["B"], x, O.sptrsv(m["L"], m["B"]))
+    g2.close()
