@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--profile-op", default="", help="run only these ops K times each (for rocprofv3)")
     ap.add_argument("--tsync", action="store_true", help="dependent-hop latency of the solve kernels")
+    ap.add_argument("--ablation", action="store_true",
+                    help="BLAS-only ablation: full plans against column-slice plans on the workload")
     ap.add_argument("--cost-model", action="store_true",
                     help="Eq. (1) plan cost against measured SpMV kernel time over a family of patterns")
     return ap.parse_args()
@@ -147,6 +149,8 @@ def main():
         return bench_tsync(args, np, torch, ddf, I, dev)
     if args.cost_model:
         return bench_cost_model(args, np, torch, ddf, I, dev)
+    if args.ablation:
+        return bench_ablation(args, np, torch, ddf, I, dev)
     if args.workload == "c4":
         return bench_batch(args, np, torch, ddf, I, dev)
     t0 = time.time()
@@ -471,6 +475,65 @@ def cost_model_patterns(np, I):
     for n in (300000, 600000):
         pats.append((f"chunglu_{n}", I.c3_chung_lu(n=n).A))
     return pats
+
+
+def bench_ablation(args, np, torch, ddf, I, dev):
+    """The BLAS-only ablation (Sec. V-A for SpMV, V-B for SpTRSV): the workload's forward SpMV
+    and forward solve with the full inspector's plan against the plan whose windows are covered
+    by BLAS codelets only (column slices of rows, partial sums combined with FP64 atomics).  The
+    solve's slices run one launch per level, so the full plan's one-launch-per-level solve is
+    timed too: that ratio holds the executor fixed and isolates the codelet types.  Same timing
+    protocol as the main bench (flush, HIP events, medians)."""
+    w = I.workload(args.workload)
+    k, A, L = w.k, w.A, w.L
+    log(f"[ablation] workload {w.name}, k={k}")
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    plans, tinsp = {}, {}
+    for name, kind, M, ob, path in (("spmv_ddf", 0, A, 0, 0), ("spmv_blas_only", 0, A, 1, 0),
+                                    ("sptrsv_ddf", 1, L, 0, 0), ("sptrsv_ddf_level", 1, L, 0, 3),
+                                    ("sptrsv_blas_only", 1, L, 1, 0)):
+        t0 = time.time()
+        plans[name] = ddf.ddf_inspect(kind, M, ddf.ddf_opts_default(only_blas=ob, build_adjoint=0, solve_path=path))
+        tinsp[name] = round(time.time() - t0, 3)
+        log(f"[ablation] {name}: inspect {tinsp[name]}s")
+    vA, X, vL, B = d(A.values), d(w.X), d(L.values), d(w.B)
+    out = {n: torch.empty((A.n_rows if n.startswith("spmv") else L.n_rows, k), dtype=torch.float64, device=dev)
+           for n in plans}
+    ops = {n: (lambda n=n: ddf.ddf_spmv_v(plans[n], vA, X, out[n], k)) if n.startswith("spmv")
+           else (lambda n=n: ddf.ddf_sptrsv_v(plans[n], vL, B, out[n], k)) for n in plans}
+    timer = Timer(torch, dev)
+    _, op_all = timer.run(ops, args.steps, args.warmup)
+    ms = {n: median(v) for n, v in op_all.items()}
+    for n in ms:
+        log(f"[ablation] {n}: {ms[n]:.4f} ms")
+
+    def rel(a, b):
+        a, b = out[a].cpu().numpy(), out[b].cpu().numpy()
+        return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+    def cods(n):
+        i = ddf.ddf_plan_info(plans[n])
+        return {"codelets": int(i["n_codelets"]), "by_type": [int(v) for v in i["codelets_by_type"]],
+                "plan_bytes": int(i["dev_plan_bytes"]), "inspect_s": tinsp[n]}
+
+    res = {
+        "metric": "blas_only_ablation", "workload": w.name, "nrhs": k, "steps": args.steps,
+        "spmv": {"ddf_ms": round(ms["spmv_ddf"], 4), "blas_only_ms": round(ms["spmv_blas_only"], 4),
+                 "ratio": round(ms["spmv_blas_only"] / ms["spmv_ddf"], 3), "paper_ratio": 10.0,
+                 "max_rel_diff": rel("spmv_blas_only", "spmv_ddf"),
+                 "ddf": cods("spmv_ddf"), "blas_only": cods("spmv_blas_only")},
+        "sptrsv": {"ddf_ms": round(ms["sptrsv_ddf"], 4), "ddf_level_ms": round(ms["sptrsv_ddf_level"], 4),
+                   "blas_only_ms": round(ms["sptrsv_blas_only"], 4),
+                   "ratio": round(ms["sptrsv_blas_only"] / ms["sptrsv_ddf"], 3),
+                   "ratio_same_executor": round(ms["sptrsv_blas_only"] / ms["sptrsv_ddf_level"], 3),
+                   "paper_ratio": 3.9, "max_rel_diff": rel("sptrsv_blas_only", "sptrsv_ddf"),
+                   "ddf": cods("sptrsv_ddf"), "blas_only": cods("sptrsv_blas_only")},
+        "timing": "median of K steps, 1 GiB written between steps, one stream",
+    }
+    print(json.dumps(res), flush=True)
 
 
 def bench_cost_model(args, np, torch, ddf, I, dev):

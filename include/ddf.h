@@ -97,6 +97,15 @@ typedef struct {
                               fixed latency plus the issue time of the waves sharing a SIMD),
                               and a level wider than 1024 lanes rules the single-block solve
                               out                                                           */
+    int32_t only_blas;     /* 1: the BLAS-only ablation (Sec. V-A, V-B): every window covered by
+                              BLAS codelets only, as column slices of rows (a codelet is ops
+                              [a, a + w) of m rows, all three access functions strided);
+                              rows are then shared by several codelets, whose partial sums
+                              the executor combines with FP64 atomic adds (results are not
+                              bitwise reproducible run to run).  Such a plan runs ddf_spmv(_v)
+                              and ddf_sptrsv(_v) (one launch per level) and exports its
+                              tables; the adjoint calls and ddf_autotune return
+                              DDF_E_UNSUPPORTED, and so does a batch.  Default 0          */
 } ddf_opts;
 
 typedef struct {

@@ -41,6 +41,7 @@ struct Canon {
     std::vector<int64_t> part_ptr, part_rows, regions, codelets;
     std::vector<int32_t> aux;
     std::vector<int32_t> perm; // adjoint plan: transposed entry -> forward value index
+    bool sliced = false;       // BLAS-only cover: codelets are column slices, rows shared
     int64_t n_parts() const { return header[5]; }
     int64_t n_codelets() const { return header[7]; }
 };
@@ -155,7 +156,7 @@ ddf_status fail(ddf_status s, const std::string &msg);
 
 // inspector.cpp
 ddf_status validate(int kind, const ddf_csr_host &A);
-void inspect(const Pattern &P, int32_t t, int threads, Canon &out);
+void inspect(const Pattern &P, int32_t t, int threads, Canon &out, bool only_blas = false);
 void transpose(int32_t n_rows, int32_t n_cols, const int32_t *rp, const int32_t *ci,
                std::vector<int32_t> &rpT, std::vector<int32_t> &ciT, std::vector<int32_t> &perm);
 uint64_t hash_canon(const Canon &c, uint64_t h);

@@ -282,6 +282,85 @@ void emit(const Window &W, const Scan &S, int32_t u, int32_t m, int64_t part, in
     }
 }
 
+// The BLAS-only cover of a window (the ablation of Sec. V-A/V-B, every codelet BLAS): each
+// row's ops cut greedily into column slices of one stride, then slices of consecutive rows
+// with the same op offset, width and stride stacked while the row number, value start and
+// first column keep the steps of the first two rows.  A codelet is ops [a, a + w) of m rows;
+// rows without ops get none.  Region record: chosen strategy 3, costs (total, 0, 0).
+struct Cut {
+    int32_t a, w;
+    int64_t s1;
+};
+
+void cover_blas_only(const Pattern &P, const int64_t *q, int32_t T, int64_t part, int64_t pos0, int64_t region,
+                     Window &W, BlockOut &out) {
+    W.load(P, q, T);
+    std::vector<std::vector<Cut>> cuts(T);
+    std::vector<std::vector<uint8_t>> taken(T);
+    for (int32_t u = 0; u < T; u++) {
+        const int64_t n = W.nops[u];
+        for (int64_t a = 0; a < n;) {
+            int64_t w = 1, s1 = 0;
+            if (a + 1 < n) {
+                s1 = W.col(u, a + 1) - W.col(u, a);
+                for (w = 2; a + w < n && W.col(u, a + w) - W.col(u, a + w - 1) == s1; w++) {
+                }
+            }
+            cuts[u].push_back({(int32_t)a, (int32_t)w, s1});
+            a += w;
+        }
+        taken[u].assign(cuts[u].size(), 0);
+    }
+    // index of row u's cut that starts at op a, or -1
+    auto find = [&](int32_t u, int32_t a) -> int64_t {
+        auto it = std::lower_bound(cuts[u].begin(), cuts[u].end(), a,
+                                   [](const Cut &c, int32_t v) { return c.a < v; });
+        return (it != cuts[u].end() && it->a == a) ? it - cuts[u].begin() : -1;
+    };
+    const int64_t first = (int64_t)(out.cod.size() / NCOD);
+    int64_t total = 0;
+    for (int32_t u = 0; u < T; u++) {
+        for (size_t j = 0; j < cuts[u].size(); j++) {
+            if (taken[u][j]) continue;
+            taken[u][j] = 1;
+            const Cut c = cuts[u][j];
+            int32_t m = 1;
+            for (; u + m < T; m++) {
+                const int64_t jj = find(u + m, c.a);
+                if (jj < 0 || taken[u + m][jj] || cuts[u + m][jj].w != c.w || cuts[u + m][jj].s1 != c.s1) break;
+                if (m >= 2 && (q[u + m] - q[u + m - 1] != q[u + 1] - q[u] ||
+                               W.opst[u + m] - W.opst[u + m - 1] != W.opst[u + 1] - W.opst[u] ||
+                               W.col(u + m, c.a) - W.col(u + m - 1, c.a) != W.col(u + 1, c.a) - W.col(u, c.a)))
+                    break;
+                taken[u + m][jj] = 1;
+            }
+            int64_t rec[NCOD];
+            rec[C_TYPE] = 0;
+            rec[C_FLAGS] = FS0 | FS1 | FS2 | FSEP | FRECT;
+            rec[C_PART] = part;
+            rec[C_REGION] = region;
+            rec[C_U] = u;
+            rec[C_M] = m;
+            rec[C_NN] = c.w;
+            rec[C_P] = (int64_t)m * c.w;
+            rec[C_ROW0] = q[u];
+            rec[C_ROWSTEP] = m >= 2 ? q[u + 1] - q[u] : 0;
+            rec[C_OP0] = W.opst[u] + c.a;
+            rec[C_OPSTEP] = m >= 2 ? W.opst[u + 1] - W.opst[u] : 0;
+            rec[C_COL0] = W.col(u, c.a);
+            rec[C_SIG0] = m >= 2 ? W.col(u + 1, c.a) - W.col(u, c.a) : 0;
+            rec[C_SIG1] = c.w >= 2 ? c.s1 : 0;
+            rec[C_AUXOFF] = 0; // no tables
+            rec[C_AUXLEN] = 0;
+            rec[C_COST] = (int64_t)m * c.w + 3;
+            total += rec[C_COST];
+            out.cod.insert(out.cod.end(), rec, rec + NCOD);
+        }
+    }
+    const int64_t reg[NREG] = {part, pos0, T, first, 3, total, 0, 0};
+    out.reg.insert(out.reg.end(), reg, reg + NREG);
+}
+
 // Mines one window; appends its region record and chosen codelets.
 void mine_window(const Pattern &P, const int64_t *q, int32_t T, int64_t part, int64_t pos0,
                  int64_t region, Window &W, std::vector<Scan> &scans, BlockOut &out) {
@@ -329,8 +408,9 @@ void mine_window(const Pattern &P, const int64_t *q, int32_t T, int64_t part, in
 
 } // namespace
 
-void inspect(const Pattern &P, int32_t t, int threads, Canon &C) {
+void inspect(const Pattern &P, int32_t t, int threads, Canon &C, bool only_blas) {
     const int64_t n = P.n_rows;
+    C.sliced = only_blas;
     // 1) grouping independent rows
     std::vector<int32_t> grp((size_t)std::max<int64_t>(n, 1), 0);
     int64_t nparts = 0;
@@ -384,7 +464,10 @@ void inspect(const Pattern &P, int32_t t, int threads, Canon &C) {
             for (int64_t w = b * BLK; w < std::min(nw, (b + 1) * BLK); w++) {
                 const Win &wi = wins[w];
                 const int64_t *q = C.part_rows.data() + C.part_ptr[wi.part] + wi.pos0;
-                mine_window(P, q, wi.T, wi.part, wi.pos0, w, W, scans, out);
+                if (only_blas)
+                    cover_blas_only(P, q, wi.T, wi.part, wi.pos0, w, W, out);
+                else
+                    mine_window(P, q, wi.T, wi.part, wi.pos0, w, W, scans, out);
             }
         }
     };
@@ -417,7 +500,7 @@ void inspect(const Pattern &P, int32_t t, int threads, Canon &C) {
         for (int64_t c = 0; c < nc; c++) {
             int64_t *dst = &C.codelets[(cbase + c) * NCOD];
             std::memcpy(dst, &b.cod[c * NCOD], NCOD * 8);
-            dst[C_AUXOFF] += abase;
+            if (!only_blas) dst[C_AUXOFF] += abase;
         }
         std::memcpy(C.aux.data() + abase, b.aux.data(), b.aux.size() * 4);
         cbase += nc;

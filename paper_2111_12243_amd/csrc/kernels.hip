@@ -1386,6 +1386,81 @@ template <int KT> __global__ __launch_bounds__(WAVE *WPB) void k_gv_chunks(GvArg
     }
 }
 
+// Column-slice (BLAS-only) plans.  Every codelet is ops [a, a + nn) of m rows with all three
+// access functions strided, so a row's ops may lie in several codelets: each task's rows add
+// their slice's partial sums into the row (SpMV: into y; solve: into the row's accumulator), one
+// FP64 atomic add per row and right-hand side.  KR == 1 (one right-hand side): G lanes to a row
+// (G from the task) with a shuffle reduction; KR > 1: KR lanes to a row, lane r owning
+// right-hand sides r, r + KR, ...  In the solve every contributing lane then counts itself into
+// the row's tally after a device-scope fence, and the lane whose count completes the tally
+// (slices x contributing lanes per slice) reads the sums back from L2 and writes the solution.
+template <bool SOLVE, int KR> __global__ __launch_bounds__(WAVE *WPB) void k_slices(SliceArgs a) {
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int t = blockIdx.x * WPB + wave;
+    if (t >= a.ntasks) return;
+    const Task tk = a.tasks[t];
+    const DCod c = load_cod(a.cods + tk.cod);
+    const int k = a.k;
+    const int lg = KR == 1 ? (tk.meta & 0xff) : 0;
+    const int G = 1 << lg, P = KR == 1 ? WAVE >> lg : WAVE / KR;
+    const int slot = KR == 1 ? lane >> lg : lane / KR, g = KR == 1 ? lane & (G - 1) : 0;
+    const int rl = KR == 1 ? 0 : lane % KR;
+    const int lanes_per_slice = KR == 1 ? 1 : min(KR, k); // tally count of one slice
+    for (int base = tk.i0b; base < tk.i0e; base += P) {
+        const int i0 = min(base + slot, tk.i0e - 1);
+        const bool active = base + slot < tk.i0e;
+        const int64_t row = c.row0 + (int64_t)i0 * c.row_step;
+        const int64_t op = c.op0 + (int64_t)i0 * c.op_step;
+        const int64_t col = c.col0 + (int64_t)i0 * c.sigma0;
+        bool counted = false;
+        if constexpr (KR == 1) {
+            for (int r = 0; r < k; r++) {
+                double acc = 0.0;
+                for (int i1 = g; i1 < c.nn; i1 += G)
+                    acc += a.vals[op + i1] * a.x[(col + (int64_t)i1 * c.sigma1) * k + r];
+                for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+                if (active && g == 0) unsafeAtomicAdd(a.y + row * k + r, acc);
+            }
+            counted = active && g == 0;
+        } else {
+            for (int r = rl; r < k; r += KR) {
+                double acc = 0.0;
+                for (int i1 = 0; i1 < c.nn; i1++) acc += a.vals[op + i1] * a.x[(col + (int64_t)i1 * c.sigma1) * k + r];
+                if (active) unsafeAtomicAdd(a.y + row * k + r, acc);
+            }
+            counted = active && rl < k;
+        }
+        if constexpr (SOLVE) {
+            if (counted) {
+                __threadfence();
+                const unsigned prev = atomicAdd(a.cnt + row, 1u);
+                if (prev + 1 == (unsigned)(a.need[row] * lanes_per_slice)) {
+                    __threadfence();
+                    const double d = a.vals[a.rp[row + 1] - 1];
+                    for (int r = 0; r < k; r++)
+                        a.xs[row * k + r] = (a.b[row * k + r] - cload(a.y + row * k + r)) / d;
+                }
+            }
+        }
+    }
+}
+
+// Before the slices: SpMV zeroes y; the solve zeroes the accumulators and tallies and solves
+// the rows that have no ops (x = b / diagonal).
+template <bool SOLVE> __global__ __launch_bounds__(256) void k_slices_init(SliceArgs a) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= a.n) return;
+    const int k = a.k;
+    for (int r = 0; r < k; r++) a.y[row * k + r] = 0.0;
+    if constexpr (SOLVE) {
+        a.cnt[row] = 0;
+        if (a.need[row] == 0) {
+            const double d = a.vals[a.rp[row + 1] - 1];
+            for (int r = 0; r < k; r++) a.xs[row * k + r] = a.b[row * k + r] / d;
+        }
+    }
+}
+
 int g_solve_blocks = 0; // blocks of the dataflow solve the whole device keeps resident at once
 int g_num_cu = 0;
 
@@ -1505,6 +1580,29 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
     int64_t nb = (n + 255) / 256;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_slices_init(const SliceArgs &a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    if (a.need) hipLaunchKernelGGL(k_slices_init<true>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_slices_init<false>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int KR> static void launch_slices_kr(const SliceArgs &a, dim3 grid, dim3 block, hipStream_t s) {
+    if (a.need) hipLaunchKernelGGL((k_slices<true, KR>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_slices<false, KR>), grid, block, 0, s, a);
+}
+
+hipError_t launch_slices(const SliceArgs &a, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.ntasks + WPB - 1) / WPB)), block(WAVE * WPB);
+    if (a.k <= 1) launch_slices_kr<1>(a, grid, block, s);
+    else if (a.k == 2) launch_slices_kr<2>(a, grid, block, s);
+    else if (a.k <= 4) launch_slices_kr<4>(a, grid, block, s);
+    else launch_slices_kr<8>(a, grid, block, s);
     return hipGetLastError();
 }
 

@@ -177,6 +177,27 @@ struct GvArgs {
 constexpr int GV_LONG_ROW = 256;  // rows longer than this run in chunks of GV_CHUNK entries
 constexpr int GV_CHUNK = 512;
 
+// Column-slice (BLAS-only) plans: SpMV adds each slice's partial sums into y (zeroed by the
+// init kernel); the solve adds them into per-row accumulators and tallies, and the contributor
+// completing a row's tally writes its solution (init: zeroes both, solves rows without ops).
+struct SliceArgs {
+    const DCod *cods;
+    const Task *tasks; // rows [i0b, i0e) of a codelet, meta = log2 lanes per row
+    int32_t ntasks;
+    int32_t k;            // right-hand sides (row stride of x, y, b, xs)
+    const double *vals;
+    const double *x;      // operand vector (solve: the solution being built, = xs)
+    double *y;            // SpMV: the output; solve: per-row accumulators
+    const double *b;      // solve: right-hand side
+    double *xs;           // solve: solution
+    unsigned *cnt;        // solve: slices added per row
+    const int32_t *need;  // solve: slices per row (null for SpMV)
+    const int32_t *rp;    // solve: row pointers of L (diagonal last)
+    int64_t n;            // rows
+};
+hipError_t launch_slices_init(const SliceArgs &a, hipStream_t s);
+hipError_t launch_slices(const SliceArgs &a, hipStream_t s);
+
 int kt_for(int k);
 hipError_t init_device_info();
 hipError_t launch_spmv(const SpmvArgs &a, bool vperm, hipStream_t s);

@@ -62,6 +62,14 @@ struct ddf_plan_s {
     int max_levels = 0;
     std::vector<void *> allocs;
     uint64_t generation = 0; // bumped whenever the schedule's device buffers are replaced
+    // BLAS-only (column-slice) plans: slice tasks level by level (solve: task range of each
+    // level in sl_lvl), slices per row, and per-call accumulators and tallies
+    bool sliced = false;
+    std::vector<int64_t> sl_lvl;
+    int32_t *d_need = nullptr;
+    double *d_acc = nullptr;
+    int64_t acc_words = 0;
+    unsigned *d_tally = nullptr;
     // kernel timing (ddf_plan_time_kernels): event pairs around the main kernel of each call
     std::vector<hipEvent_t> tev;
     int32_t tev_used = 0;
@@ -172,8 +180,10 @@ void pack(const Canon &c, const Pattern &P, int mat, DevTables &D) {
         for (int32_t a = 0; a < m; a++)
             rows[a] = (fl & FS0) ? (int64_t)d.row0 + (int64_t)a * d.row_step : c.aux[ap + a];
         for (int32_t a = 0; a < m; a++) {
-            opst[a] = P.opstart(rows[a]);
-            nops[a] = P.nops(rows[a]);
+            // a column slice covers ops [op0 - opstart, + nn) of each row; a whole-row
+            // codelet all of them
+            opst[a] = c.sliced ? (int64_t)d.op0 + (int64_t)a * d.op_step : P.opstart(rows[a]);
+            nops[a] = c.sliced ? (int64_t)d.nn : P.nops(rows[a]);
         }
         if (!(fl & FS0)) {
             d.rows_off = (int32_t)D.aux.size();
@@ -903,8 +913,36 @@ std::vector<int32_t> codelet_levels(const Canon &c) {
     return lv;
 }
 
+// Schedule of a column-slice plan (forward only): the slice tasks of every codelet, in codelet
+// order, which is level order; for the solve, the task range of each level and the slices
+// per row.
+ddf_status build_slices(ddf_plan_t p) {
+    DevTables &D = p->F;
+    D.tasks.clear();
+    p->sl_lvl.assign(1, 0);
+    const Canon &c = p->fwd[0];
+    std::vector<int32_t> need(p->n_rows, 0), rows;
+    for (size_t i = 0; i < D.cods.size(); i++) {
+        const int64_t lev = c.codelets[i * NCOD + C_PART];
+        while ((int64_t)p->sl_lvl.size() <= lev) p->sl_lvl.push_back((int64_t)D.tasks.size());
+        codelet_tasks(D.cods[i], D.aux, (int32_t)i, p->sp_f, 0, D.tasks);
+        rows.clear();
+        cod_rows(D.cods[i], D.aux, rows);
+        for (int32_t r : rows) need[r]++;
+    }
+    p->sl_lvl.push_back((int64_t)D.tasks.size());
+    if (p->host_only) return DDF_OK;
+    if (ddf_status s = upload_tasks(p, D)) return s;
+    if (p->kind == DDF_SPTRSV_LOWER && !p->d_need) {
+        if (ddf_status s = upload(p, &p->d_need, need.data(), need.size())) return s;
+        if (ddf_status s = dalloc(p, (void **)&p->d_tally, (size_t)p->n_rows * sizeof(unsigned))) return s;
+    }
+    return DDF_OK;
+}
+
 // (Re)build every task list of the plan from its schedule parameters.
 ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
+    if (p->sliced) return fwd ? build_slices(p) : DDF_OK;
     if (p->kind == DDF_SPMV) {
         if (fwd) {
             p->F.tasks.clear();
@@ -1099,6 +1137,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     if (o.thin_lanes != 0 && (o.thin_lanes < 64 || o.thin_lanes > THIN_THREADS || o.thin_lanes % 64))
         return fail(DDF_E_ARG, "thin_lanes must be 0 or a multiple of 64 in 64..1024");
     if (o.window < 1 || o.window > 1024) return fail(DDF_E_ARG, "window must be in 1..1024");
+    if (o.only_blas && batch) return fail(DDF_E_UNSUPPORTED, "BLAS-only plans are single-matrix plans");
     for (int b = 0; b < nmat; b++) {
         if (ddf_status s = validate(kind, mats[b])) return s;
         if (batch && (!nrhs || nrhs[b] < 1 || nrhs[b] > 32)) return fail(DDF_E_ARG, "nrhs must be in 1..32");
@@ -1112,6 +1151,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     p->opts = o;
     p->host_only = o.host_only != 0;
     p->has_adj = o.build_adjoint != 0;
+    p->sliced = o.only_blas != 0;
     p->sp_f.ops_per_lane = p->sp_a.ops_per_lane = o.ops_per_lane;
     p->sp_f.passes = p->sp_a.passes = o.rows_passes;
     p->sp_f.remap = p->sp_a.remap = o.xcd_remap < 0 ? 1 : o.xcd_remap;
@@ -1123,11 +1163,11 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     for (int b = 0; b < nmat; b++) {
         const ddf_csr_host &A = mats[b];
         Pattern P{kind, A.n_rows, A.n_cols, A.row_ptr, A.col_idx};
-        inspect(P, o.window, o.threads, p->fwd[b]);
+        inspect(P, o.window, o.threads, p->fwd[b], o.only_blas != 0);
         if (p->has_adj) {
             transpose(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, rpT[b], ciT[b], perm[b]);
             Pattern PT{kind == DDF_SPMV ? 0 : 2, A.n_cols, A.n_rows, rpT[b].data(), ciT[b].data()};
-            inspect(PT, o.window, o.threads, p->adj[b]);
+            inspect(PT, o.window, o.threads, p->adj[b], o.only_blas != 0);
             p->adj[b].perm = perm[b];
         }
         MatInfo &mi = p->mats[b];
@@ -1166,7 +1206,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
             pack(p->adj[b], PT, b, p->T);
         }
     }
-    if (kind == DDF_SPTRSV_LOWER && !batch) {
+    if (kind == DDF_SPTRSV_LOWER && !batch && !p->sliced) {
         const int32_t ring = o.thin_ring > 0 ? o.thin_ring : THIN_RING_MAX;
         Pattern P{kind, mats[0].n_rows, mats[0].n_cols, mats[0].row_ptr, mats[0].col_idx};
         build_thin(p->fwd[0], P, nullptr, ring, o.thin_lanes, p->F);
@@ -1407,6 +1447,67 @@ hipError_t launch_gv_pass(ddf_plan_t p, const double *g, const double *x, double
     return launch_gv(a, p->gv_avg_short, s);
 }
 
+// Column-slice plans: SpMV is one init launch (y = 0) and one launch of every slice task; the
+// solve is one init launch (accumulators and tallies zeroed, rows without ops solved) and one
+// launch per level that holds slices (the launch boundary orders the levels).
+ddf_status sliced_run(ddf_plan_t p, const double *vals, const double *x_or_b, double *out, int32_t k,
+                      hipStream_t s) {
+    const bool solve = p->kind == DDF_SPTRSV_LOWER;
+    SliceArgs a{};
+    a.cods = p->F.d_cods;
+    a.tasks = p->F.d_tasks;
+    a.k = k;
+    a.vals = vals;
+    a.n = p->n_rows;
+    if (solve) {
+        const int64_t words = p->n_rows * (int64_t)k;
+        if (words > p->acc_words) {
+            drop_alloc(p, p->d_acc);
+            p->d_acc = nullptr;
+            p->acc_words = 0;
+            if (ddf_status st = dalloc(p, (void **)&p->d_acc, (size_t)words * 8)) return st;
+            p->acc_words = words;
+        }
+        a.x = out;
+        a.y = p->d_acc;
+        a.b = x_or_b;
+        a.xs = out;
+        a.cnt = p->d_tally;
+        a.need = p->d_need;
+        a.rp = p->d_rp;
+    } else {
+        a.x = x_or_b;
+        a.y = out;
+    }
+    int64_t nlaunch = 1;
+    if (solve) {
+        for (size_t l = 0; l + 1 < p->sl_lvl.size(); l++) nlaunch += p->sl_lvl[l + 1] > p->sl_lvl[l];
+    } else {
+        nlaunch += !p->F.tasks.empty();
+    }
+    const auto tm = next_timer(p, nlaunch);
+    if (tm.first) (void)hipEventRecord(tm.first, s);
+    HIPCHK(launch_slices_init(a, s));
+    if (solve) {
+        for (size_t l = 0; l + 1 < p->sl_lvl.size(); l++) {
+            if (p->sl_lvl[l + 1] == p->sl_lvl[l]) continue;
+            a.tasks = p->F.d_tasks + p->sl_lvl[l];
+            a.ntasks = (int32_t)(p->sl_lvl[l + 1] - p->sl_lvl[l]);
+            HIPCHK(launch_slices(a, s));
+        }
+    } else {
+        a.ntasks = (int32_t)p->F.tasks.size();
+        HIPCHK(launch_slices(a, s));
+    }
+    if (tm.second) (void)hipEventRecord(tm.second, s);
+    return DDF_OK;
+}
+
+ddf_status refuse_sliced(ddf_plan_t p) {
+    if (p && p->sliced) return fail(DDF_E_UNSUPPORTED, "BLAS-only plans run the forward SpMV and solve only");
+    return DDF_OK;
+}
+
 } // namespace
 
 // =================================================================================================
@@ -1484,6 +1585,7 @@ ddf_status ddf_spmv_v(ddf_plan_t p, const double *d_vals, const double *d_x, dou
     if (overlap(d_x, p->n_cols * nrhs * 8, d_y, p->n_rows * nrhs * 8)) return fail(DDF_E_ARG, "x and y overlap");
     hipStream_t s = (hipStream_t)stream;
     if (p->n_rows == 0) return DDF_OK;
+    if (p->sliced) return sliced_run(p, d_vals, d_x, d_y, nrhs, s);
     SpmvArgs a{};
     a.cods = p->F.d_cods;
     a.aux = p->F.d_aux;
@@ -1520,6 +1622,7 @@ ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, d
     if ((!d_vals && p->nnz) || (!d_b && p->n_rows) || (!d_x && p->n_rows)) return fail(DDF_E_ARG, "NULL buffer");
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
     if (p->n_rows == 0) return DDF_OK;
+    if (p->sliced) return sliced_run(p, d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
     if (use_thin(p->F, p->sp_f, nrhs))
         return thin_launch(p, p->F, p->sp_f, p->F.thin_nlev, d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
     // the single matrix's right-hand-side count is a per-call argument (k_override)
@@ -1535,6 +1638,7 @@ ddf_status ddf_sptrsv(ddf_plan_t p, const double *d_b, double *d_x, int32_t nrhs
 ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gy,
                             double *d_gx, double *d_gvals, int32_t nrhs, ddf_stream_t stream) {
     if (ddf_status s = need_device(p)) return s;
+    if (ddf_status s = refuse_sliced(p)) return s;
     if (p->kind != DDF_SPMV) return fail(DDF_E_KIND, "plan is not an SpMV plan");
     if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
     if (ddf_status s = check_nrhs(nrhs)) return s;
@@ -1577,6 +1681,7 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
 ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gx,
                               double *d_gb, double *d_gvals, int32_t nrhs, ddf_stream_t stream) {
     if (ddf_status s = need_device(p)) return s;
+    if (ddf_status s = refuse_sliced(p)) return s;
     if (p->kind != DDF_SPTRSV_LOWER || p->batch) return fail(DDF_E_KIND, "plan is not a single-matrix SpTRSV plan");
     if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
     if (ddf_status s = check_nrhs(nrhs)) return s;
@@ -1620,6 +1725,7 @@ ddf_status ddf_sptrsv_value_grad(ddf_plan_t p, const double *d_x, const double *
 ddf_status ddf_sptrsv_adjoint_noalloc(ddf_plan_t p, const double *d_vals, const double *d_x, const double *d_gx,
                                       double *d_gb, double *d_gvals, int32_t nrhs, ddf_stream_t stream) {
     if (ddf_status s = need_device(p)) return s;
+    if (ddf_status s = refuse_sliced(p)) return s;
     if (p->kind != DDF_SPTRSV_LOWER || p->batch) return fail(DDF_E_KIND, "plan is not a single-matrix SpTRSV plan");
     if (!p->has_adj) return fail(DDF_E_UNSUPPORTED, "plan was built without its adjoint plan");
     if (ddf_status s = check_nrhs(nrhs)) return s;
@@ -2160,6 +2266,7 @@ void save_tune_file() {
 
 extern "C" ddf_status ddf_autotune(ddf_plan_t p, ddf_op op, int32_t nrhs, ddf_stream_t stream, double budget_ms) {
     if (ddf_status s = need_device(p)) return s;
+    if (ddf_status s = refuse_sliced(p)) return s;
     if (p->batch) nrhs = 1;
     else if (ddf_status s = check_nrhs(nrhs)) return s;
     if (op < DDF_OP_SPMV || op > DDF_OP_SPTRSV_ADJ) return fail(DDF_E_ARG, "autotune takes the four executor ops");

@@ -48,7 +48,7 @@ class ddf_opts(C.Structure):
                 ("threads", C.c_int32), ("ops_per_lane", C.c_int32), ("rows_passes", C.c_int32),
                 ("xcd_remap", C.c_int32), ("solve_blocks", C.c_int32),
                 ("solve_path", C.c_int32), ("thin_helpers", C.c_int32), ("thin_ahead", C.c_int32),
-                ("thin_ring", C.c_int32), ("thin_lanes", C.c_int32)]
+                ("thin_ring", C.c_int32), ("thin_lanes", C.c_int32), ("only_blas", C.c_int32)]
 
 
 class ddf_csr_host(C.Structure):

@@ -134,3 +134,71 @@ def test_stencils_blas_only():
     check_blas_only(1, w.L, O.inspect(1, w.L, only_blas=True))
     w = I.c5_laplace27(nx=8, k=1)
     check_blas_only(0, w.A, O.inspect(0, w.A, only_blas=True))
+
+
+# ---- the library's column-slice schedule, replayed on the CPU ----
+# Device record fields (16 int32) and the slice executor's rules: a task is rows [i0b, i0e) of
+# one codelet; every (row, op) is added exactly once; in the solve a row is complete when all
+# of its slices are in, and a slice may only read rows completed in earlier levels (tasks come
+# in level order; a row with no ops is solved before the first level).
+DF = {n: i for i, n in enumerate(["flags", "m", "nn", "row0", "row_step", "op0", "op_step", "col0", "sigma0",
+                                  "sigma1", "rows_off", "ops_off", "cnt_off", "xt_off", "xp_off", "mat"])}
+
+
+def replay_slices(kind, A, t):
+    from paper_2111_12243_amd import ddf
+    p = ddf.ddf_inspect(kind, A, ddf.ddf_opts_default(host_only=1, only_blas=1, window=t, build_adjoint=0))
+    tabs = ddf.ddf_plan_device_tables(p, 0)
+    canon = ddf.ddf_plan_export(p, 0)
+    cods, tasks = tabs["cods"], tabs["tasks"]
+    assert tabs["aux"].size == 0
+    rp, ci = A.row_ptr.astype(np.int64), A.col_idx.astype(np.int64)
+    x = np.random.default_rng(t).uniform(-1, 1, A.n_cols)
+    y = np.zeros(A.n_rows)
+    seen = np.zeros(A.nnz, np.int64)
+    level = canon["codelets"][:, C["part"]]
+    done_level = np.full(A.n_rows, -1)  # solve: level in which a row completed
+    for tk in tasks:
+        c = cods[tk[0]]
+        assert c[DF["flags"]] & BLAS_FLAGS == BLAS_FLAGS and c[DF["rows_off"]] == -1
+        assert 0 <= tk[1] < tk[2] <= c[DF["m"]]
+        for i0 in range(tk[1], tk[2]):
+            row = c[DF["row0"]] + i0 * c[DF["row_step"]]
+            op = c[DF["op0"]] + i0 * c[DF["op_step"]]
+            assert 0 <= row < A.n_rows
+            for i1 in range(c[DF["nn"]]):
+                e, col = op + i1, c[DF["col0"]] + i0 * c[DF["sigma0"]] + i1 * c[DF["sigma1"]]
+                assert rp[row] <= e < rp[row + 1] and ci[e] == col
+                if kind == 1:
+                    assert e != rp[row + 1] - 1  # the diagonal is not an op
+                    assert 0 <= done_level[col] < level[tk[0]] or rp[col + 1] - rp[col] == 1
+                seen[e] += 1
+                y[row] += A.values[e] * x[col]
+        if kind == 1:
+            # rows whose slices are all in by the end of this task's level
+            for i0 in range(tk[1], tk[2]):
+                row = c[DF["row0"]] + i0 * c[DF["row_step"]]
+                diag = rp[row + 1] - 1
+                if seen[rp[row]:diag].all():
+                    done_level[row] = level[tk[0]]
+    keep = np.ones(A.nnz, bool)
+    if kind == 1:
+        keep[rp[1:] - 1] = False
+    assert (seen[keep] == 1).all() and (seen[~keep] == 0).all()
+    if kind == 0:
+        assert np.allclose(y, O.spmv(A, x[:, None])[:, 0], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_library_slice_schedule(seed):
+    rng = np.random.default_rng(700 + seed)
+    A = I.random_csr(int(rng.integers(1, 150)), int(rng.integers(1, 150)), seed, density=0.06, runs=bool(seed % 2))
+    replay_slices(0, A, int(rng.choice([1, 8, 64])))
+    L = I.random_lower(int(rng.integers(1, 150)), seed, density=0.05, runs=bool(seed % 2))
+    replay_slices(1, L, int(rng.choice([1, 8, 64])))
+
+
+def test_library_slice_schedule_workload():
+    w = I.c5_laplace27(nx=8, k=1)
+    replay_slices(0, w.A, 64)
+    replay_slices(1, w.L, 64)

@@ -10,9 +10,9 @@ from paper_2111_12243_amd import inputs as I
 KEYS = ["header", "part_ptr", "part_rows", "regions", "codelets", "aux"]
 
 
-def host_plan(kind, A, t=64, threads=0, adjoint=1):
+def host_plan(kind, A, t=64, threads=0, adjoint=1, only_blas=0):
     return ddf.ddf_inspect(kind, A, ddf.ddf_opts_default(host_only=1, window=t, threads=threads,
-                                                         build_adjoint=adjoint))
+                                                         build_adjoint=adjoint, only_blas=only_blas))
 
 
 def assert_same(lib_tabs, ref_tabs):
@@ -21,10 +21,10 @@ def assert_same(lib_tabs, ref_tabs):
         assert np.array_equal(lib_tabs[k], ref_tabs[k]), k
 
 
-def check(kind, A, t=64, threads=0):
-    p = host_plan(kind, A, t, threads)
-    assert_same(ddf.ddf_plan_export(p, 0), O.inspect(kind, A, t))
-    ref, perm = O.inspect_adjoint(kind, A, t)
+def check(kind, A, t=64, threads=0, only_blas=False):
+    p = host_plan(kind, A, t, threads, only_blas=int(only_blas))
+    assert_same(ddf.ddf_plan_export(p, 0), O.inspect(kind, A, t, only_blas=only_blas))
+    ref, perm = O.inspect_adjoint(kind, A, t, only_blas=only_blas)
     got = ddf.ddf_plan_export(p, 1)
     assert_same(got, ref)
     assert np.array_equal(got["perm"], perm)
@@ -95,3 +95,25 @@ def test_c5_scaled():
     w = I.c5_laplace27(nx=30, k=1)
     check(0, w.A)
     check(1, w.L)
+
+
+# BLAS-only ablation (every window covered by column slices): same bar, forward and adjoint.
+@pytest.mark.parametrize("seed", range(12))
+def test_blas_only_random(seed):
+    rng = np.random.default_rng(300 + seed)
+    A = I.random_csr(int(rng.integers(0, 200)), int(rng.integers(1, 200)), seed,
+                     density=float(rng.uniform(0.002, 0.1)), empty_frac=float(rng.uniform(0, 0.4)),
+                     runs=bool(seed % 2))
+    check(0, A, t=int(rng.choice([1, 4, 64])), only_blas=True)
+    L = I.random_lower(int(rng.integers(1, 200)), seed, density=float(rng.uniform(0.0, 0.08)),
+                       runs=bool(seed % 2))
+    check(1, L, t=int(rng.choice([1, 8, 64])), only_blas=True)
+
+
+def test_blas_only_workloads():
+    w = I.c1_laplace2d()
+    check(0, w.A, only_blas=True)
+    check(1, w.L, only_blas=True)
+    w = I.c5_laplace27(nx=14, k=1)
+    check(0, w.A, threads=4, only_blas=True)
+    check(1, w.L, threads=4, only_blas=True)
