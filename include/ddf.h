@@ -358,11 +358,25 @@ typedef struct {
                                  pattern)                                                      */
     int64_t n_rowlist;
     const int32_t *df_tasks;  /* solve, persistent dataflow kernel: [n_df_tasks][4] codelet, first
-                                 row, end row (at most 8 rows), 0; in level order over all
-                                 matrices (which = 2: matrix after matrix)                     */
+                                 row, end row (at most 8 rows of at most 16 ops), 0; in level
+                                 order over all matrices (which = 2: matrix after matrix).
+                                 Rows of more than 16 ops go in wide-row tasks, first in their
+                                 level: codelet, first row, offset of the rows' columns in
+                                 df_lcols, (1 << 14) | (rows << 16), 1 to 8 consecutive rows  */
     int64_t n_df_tasks;
     const int64_t *df_ptr;    /* [n_df_ptr] task ranges: 0, n_df_tasks (which = 2: per matrix) */
     int64_t n_df_ptr;
+    const int32_t *df_lcols;  /* [n_df_lcols] columns of the wide-row tasks' ops: row after row,
+                                 each in op order                                              */
+    int64_t n_df_lcols;
+    int32_t df_group;         /* 8: every level and every wide-row task starts a group of 8
+                                 tasks (empty tasks fill the gaps); 1: no padding, and a
+                                 level's rows of at most 16 ops go 8 to a mixed task (codelet
+                                 of its first row, first slot, end slot, 1 << 15) whatever
+                                 their codelets (batches)                                      */
+    int32_t df_reserved;
+    const int32_t *df_slots;  /* [n_df_slots][2] (codelet, row within it) of each mixed-task row */
+    int64_t n_df_slots;
 } ddf_device_tables_t;
 ddf_status ddf_plan_device_tables(ddf_plan_t plan, int32_t which, ddf_device_tables_t *out);
 

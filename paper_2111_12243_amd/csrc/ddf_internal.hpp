@@ -92,6 +92,10 @@ struct DevTables {
     std::vector<int32_t> sync;         // solve: 4 int32 per task (wait counter, count, signal counter, level)
     std::vector<Task> df_tasks;        // dataflow solve: up to DF_RG rows of one codelet, in level order
     std::vector<int64_t> df_ptr;       // per-matrix ranges of df_tasks (per-matrix schedules only)
+    std::vector<int32_t> df_lcols;     // columns of the dataflow solve's wide-row tasks
+    int32_t *d_df_lcols = nullptr;
+    std::vector<int32_t> df_slots;     // (codelet, row) of the dataflow solve's mixed-task row slots
+    int32_t *d_df_slots = nullptr;
     int64_t n_counters = 0;            // solve: level counters of the sync protocol (CPU replay)
     int64_t csr_rows = 0, csr_nnz = 0; // SpMV, one right-hand side: rows run from the CSR pattern
     int64_t table_bytes1 = 0;          // plan bytes a one-RHS SpMV launch reads
@@ -127,7 +131,8 @@ struct DevTables {
     int64_t bytes() const {
         return (int64_t)cods.size() * sizeof(DCod) + (int64_t)aux.size() * 4 +
                (int64_t)tasks.size() * (sizeof(Task) + (sync.empty() ? 0 : sizeof(DCod))) + (int64_t)sync.size() * 4 +
-               (int64_t)df_tasks.size() * (sizeof(Task) + sizeof(DCod));
+               (int64_t)df_tasks.size() * (sizeof(Task) + sizeof(DCod)) +
+               (int64_t)(df_lcols.size() + df_slots.size()) * 4;
     }
     // plan bytes a one-launch-per-level solve reads: each task, its codelet copy and its sync
     // entry, and aux
@@ -137,7 +142,8 @@ struct DevTables {
     }
     // plan bytes the dataflow solve reads: each task and its codelet copy, and aux
     int64_t df_read_bytes() const {
-        return (int64_t)aux.size() * 4 + (int64_t)df_tasks.size() * (sizeof(Task) + sizeof(DCod));
+        return (int64_t)aux.size() * 4 + (int64_t)df_tasks.size() * (sizeof(Task) + sizeof(DCod)) +
+               (int64_t)(df_lcols.size() + df_slots.size()) * 4;
     }
     // plan bytes a single-block solve reads per call: gather index, level table, rows
     int64_t thin_bytes() const {

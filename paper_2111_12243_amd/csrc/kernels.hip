@@ -648,11 +648,13 @@ __device__ void solve_task(const SolveArgs &a, int t, int lane) {
 // Dataflow solve: the whole solve (or transposed solve) in one persistent launch, with no
 // level barriers.  Each solution value is its own ready flag: before the launch the output
 // is filled with DF_SENT, a signalling NaN that no arithmetic result has (results are
-// quiet NaNs), and a task loads the solution values its rows need with device-coherent
-// loads (agent-scope relaxed atomics, which bypass the per-XCD caches), re-reading with
-// backoff those that still hold the sentinel; it stores its own results the same way.  An
-// 8-byte store is seen whole, so a value that is not the sentinel is final: no counters,
-// fences or flags are needed.
+// quiet NaNs), and a task loads the solution values its rows need first through the caches
+// (wload), then re-reads those that still hold the sentinel with device-coherent loads
+// (agent-scope relaxed atomics, which bypass the per-XCD caches), with backoff; it stores its
+// own results with device-coherent stores.  Every location is written once, after the fill,
+// and the launch starts with caches that hold nothing older than the fill, so a cached copy
+// is the sentinel or the final value; an 8-byte store is seen whole, so a value that is not
+// the sentinel is final: no counters, fences or flags are needed.
 //
 // A task is up to DF_RG rows of one codelet; tasks are in level order, a topological order of
 // the dependences.  KR lanes per row each own right-hand sides r, r + KR, ...; a pass of a
@@ -667,6 +669,14 @@ __device__ void solve_task(const SolveArgs &a, int t, int lane) {
 // ------------------------------------------------------------------------------------------
 constexpr unsigned long long DF_SENT_BITS = 0x7FF4DDF0DDF0DDF0ull; // signalling NaN
 constexpr int DF_ARRIVE_POLLS = 400;                                 // check-in wait (~0.3 ms)
+
+// First read of a solution value: a relaxed load at workgroup scope, which the per-CU and
+// per-XCD caches may serve.  A location holds only the sentinel (written before the launch)
+// or its final value (written once), so a cached copy is either final or the sentinel; the
+// sentinel is then re-read from the device-coherent level (cload) until it is final.
+__device__ __forceinline__ double wload(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 __device__ __forceinline__ bool df_missing(double v) {
     return (unsigned long long)__double_as_longlong(v) == DF_SENT_BITS;
@@ -746,21 +756,123 @@ __device__ __forceinline__ void df_finish(const double (&v)[U], const double (&x
     cstore(dst, res);
 }
 
+// A wide-row task (DF_LONG) with the whole wave: its R rows (R up to 8) take 64 / R' lanes each
+// (R' = R rounded up to a power of two); of a row's lanes, KL = min(k rounded up to a power of
+// two, lanes) own right-hand sides r, r + KL, ..., and the GR = lanes / KL groups of them split
+// the row's ops (in each chunk of GR x DF_U ops, group j takes ops j, j + GR, ...).  The
+// groups' sums are combined with cross-lane shuffles and the first group stores the row.  The
+// task's rows keep their columns one after the other in lcols (ascending op order; the
+// transposed solve walks the ops from the last, as the other rows do).
+template <bool ADJ, bool VPERM>
+__device__ __forceinline__ void df_long(const SolveArgs &a, const Task &tk, const DCod &c, int lane) {
+    const int nrow = (tk.meta >> DF_LONG_ROWS_SHIFT) & 15;
+    const int lgr = nrow <= 1 ? 0 : nrow <= 2 ? 1 : nrow <= 4 ? 2 : 3;
+    const int lanes = WAVE >> lgr;
+    const MatInfo mi = mat_info(a, c);
+    const int k = mi.k;
+    int kl = 1;
+    while (kl < k && kl < lanes) kl <<= 1;
+    const int gr = lanes / kl;
+    const int ri_idx = lane / lanes, sub = lane % lanes;
+    const int r = sub % kl, gq = sub / kl;
+    const bool row_on = ri_idx < nrow;
+    const double *__restrict__ vals = a.vals + mi.val_base;
+    const int32_t *__restrict__ perm = VPERM ? a.perm + mi.val_base : nullptr;
+    const double *__restrict__ b = a.b + mi.vec_base;
+    double *x = a.x + mi.vec_base;
+    RowInfo ri{0, 0, 0};
+    int coff = tk.i0e; // this row's columns: after those of the task's earlier rows
+    double diag = 1.0;
+    if (row_on) {
+        for (int j = 0; j < ri_idx; j++) coff += row_info(c, a.aux, tk.i0b + j).nops;
+        ri = row_info(c, a.aux, tk.i0b + ri_idx);
+        const int dpos = ADJ ? ri.opst - 1 : ri.opst + ri.nops;
+        diag = VPERM ? vals[perm[dpos]] : vals[dpos];
+    }
+    const int32_t *__restrict__ cols = a.lcols + coff;
+    unsigned *err = a.err ? a.err : a.ctr + CTR_STRIDE;
+    bool live = true; // false once the watchdog has tripped
+    for (int r0 = 0; r0 < k; r0 += kl) {
+        const int rr = r0 + r;
+        const bool mine = row_on && rr < k;
+        const int nops = mine ? ri.nops : 0;
+        double acc = 0.0;
+        for (int i1 = 0; __ballot(i1 < nops); i1 += gr * DF_U) {
+            double v[DF_U], xv[DF_U];
+            int col[DF_U];
+#pragma unroll
+            for (int u = 0; u < DF_U; u++) {
+                const int q = i1 + u * gr + gq;
+                const bool ok = q < nops;
+                const int op = ADJ ? nops - 1 - q : q;
+                col[u] = ok ? cols[op] : 0;
+                const int e = ri.opst + op;
+                v[u] = ok ? (VPERM ? vals[perm[e]] : vals[e]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < DF_U; u++)
+                xv[u] = i1 + u * gr + gq < nops ? wload(x + (int64_t)col[u] * k + rr) : 0.0;
+            int64_t spins = 0;
+            int back = 1;
+            for (;;) {
+                bool miss = false;
+#pragma unroll
+                for (int u = 0; u < DF_U; u++) miss = miss || df_missing(xv[u]);
+                if (!__ballot(miss) || !live) break;
+                if (!df_backoff<DF_U>(a, spins, back, err)) {
+                    live = false; // past the watchdog: the results are reported invalid
+                    break;
+                }
+#pragma unroll
+                for (int u = 0; u < DF_U; u++)
+                    if (df_missing(xv[u])) xv[u] = cload(x + (int64_t)col[u] * k + rr);
+            }
+#pragma unroll
+            for (int u = 0; u < DF_U; u++) acc = fma(v[u], xv[u], acc);
+        }
+        for (int o = kl; o < lanes; o <<= 1) acc += __shfl_xor(acc, o, WAVE);
+        if (gq == 0 && mine) {
+            double res = (b[(int64_t)ri.row * k + rr] - acc) / diag;
+            if (df_missing(res)) res = __longlong_as_double(0x7FF8000000000000ll); // never: results are quiet
+            cstore(x + (int64_t)ri.row * k + rr, res);
+        }
+    }
+}
+
 // One pass of a wave: rows of W consecutive tasks, KR lanes per row, lane r owning right-hand
 // sides r, r + KR, ...  VPERM: the values through perm (the transposed solve reads L's values
-// in U's order).
+// in U's order).  A pass whose first task is a wide-row task runs that task alone.
 template <int KR, bool ADJ, bool VPERM>
 __device__ __forceinline__ void df_pass(const SolveArgs &a, int p, int lane) {
     constexpr int P = WAVE / KR, W = P / DF_RG;
+    // a wide-row task runs alone; a pass that starts with an empty task is all empty (empty
+    // tasks fill a group of DF_PASS_MAX up to its end)
+    const Task head = a.tasks[p * W];
+    if (head.meta & DF_LONG) {
+        df_long<ADJ, VPERM>(a, head, a.tcods[p * W], lane);
+        return;
+    }
+    if (head.i0e == head.i0b) return;
     const int slot = lane / KR, r = lane % KR;
-    const int t = p * W + slot / DF_RG, i = slot % DF_RG;
-    const int tc = min(t, a.ntasks - 1);
-    const Task tk = a.tasks[tc];
-    const DCod c = a.tcods[tc];
+    DCod c;
+    int i0;
+    bool active;
+    if (KR == DF_RG && (head.meta & DF_MIXED)) {
+        // a mixed task (one task per pass): row slot s is (codelet, row) slots[i0b + s]
+        active = slot < head.i0e - head.i0b;
+        const int2 sl = a.slots[head.i0b + (active ? slot : 0)];
+        c = a.cods[sl.x];
+        i0 = sl.y;
+    } else {
+        const int t = p * W + slot / DF_RG, i = slot % DF_RG;
+        const int tc = min(t, a.ntasks - 1);
+        const Task tk = a.tasks[tc];
+        c = a.tcods[tc];
+        i0 = tk.i0b + i;
+        active = t < a.ntasks && i0 < tk.i0e;
+    }
     const MatInfo mi = mat_info(a, c);
     const int k = mi.k;
-    const int i0 = tk.i0b + i;
-    const bool active = t < a.ntasks && i0 < tk.i0e;
     const double *__restrict__ vals = a.vals + mi.val_base;
     const int32_t *__restrict__ perm = VPERM ? a.perm + mi.val_base : nullptr;
     const double *__restrict__ b = a.b + mi.vec_base;
@@ -799,7 +911,7 @@ __device__ __forceinline__ void df_pass(const SolveArgs &a, int p, int lane) {
                 v[u] = ok ? (VPERM ? vals[perm[e]] : vals[e]) : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < DF_U; u++) xv[u] = i1 + u < nops ? cload(x + (int64_t)col[u] * k + rr) : 0.0;
+            for (int u = 0; u < DF_U; u++) xv[u] = i1 + u < nops ? wload(x + (int64_t)col[u] * k + rr) : 0.0;
             const double bo = (one_chunk && mine) ? b[o] : 0.0;
             int64_t spins = 0;
             int back = 1;

@@ -137,11 +137,24 @@ struct SolveArgs {
     int64_t spin_limit;
     int32_t k_override; // > 0: right-hand sides of a single-matrix call
     int32_t npass;      // dataflow solve: wave passes (each 64 / KR rows, DF_RG rows per task)
+    const int32_t *lcols; // dataflow solve: columns of the wide-row tasks (offset in the task's i0e)
+    const int2 *slots;    // dataflow solve: (codelet, row) of the mixed tasks' row slots
 };
 constexpr int WAVE_LANES = 64;
 constexpr int DF_RG = 8;  // dataflow solve: rows per task (one codelet's)
 constexpr int DF_PASS_MAX = 8; // dataflow solve: most tasks one wave pass takes (one right-hand side)
 constexpr int DF_U = 16;  // dataflow solve: ops per lane loaded before a wait
+// Dataflow solve: rows of more than DF_U ops (more than one chunk of a lane) run as wide-row
+// tasks (meta DF_LONG | rows << 16): up to 8 consecutive rows of one codelet, from row i0b,
+// their columns one after the other at lcols[i0e...].  Such a task has a wave pass to itself:
+// its rows split the 64 lanes, and each row's lanes split its ops as well as its right-hand
+// sides.  In a list for several right-hand-side counts a task of this kind sits at a multiple
+// of DF_PASS_MAX, followed by empty tasks up to the next multiple.
+constexpr int32_t DF_LONG = 1 << 14;
+constexpr int DF_LONG_ROWS_SHIFT = 16;
+// Dataflow solve of a batch (8 lanes per row, one task per pass): a mixed task (meta DF_MIXED)
+// holds up to DF_RG rows of any codelets of one level, row slots[s] for s in [i0b, i0e).
+constexpr int32_t DF_MIXED = 1 << 15;
 
 struct PlainArgs {
     const int32_t *rp;

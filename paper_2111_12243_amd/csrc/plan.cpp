@@ -491,23 +491,140 @@ void append_gv(const DevTables &F, int64_t c0, int64_t c1, std::pair<int64_t, in
     }
 }
 
+// A device codelet's row i0 (row, first value index, ops) and its ops' columns, decoded on the
+// host the way the kernels read the records.
+struct HostRow {
+    int64_t row, opst, nops;
+};
+
+HostRow host_row(const DCod &d, const std::vector<int32_t> &aux, int32_t i0) {
+    HostRow r;
+    r.row = (d.flags & FS0) ? (int64_t)d.row0 + (int64_t)i0 * d.row_step : aux[d.rows_off + i0];
+    r.opst = (d.flags & DOPS) ? aux[d.ops_off + i0] : (int64_t)d.op0 + (int64_t)i0 * d.op_step;
+    r.nops = (d.flags & FRECT) ? d.nn : aux[d.cnt_off + i0];
+    return r;
+}
+
+void host_cols(const DCod &d, const std::vector<int32_t> &aux, int32_t i0, const HostRow &r,
+               std::vector<int32_t> &out) {
+    const int mode = xmode_host(d.flags);
+    const int64_t base = (int64_t)d.col0 + (int64_t)i0 * d.sigma0;
+    if (mode == 0) {
+        for (int64_t b = 0; b < r.nops; b++) out.push_back((int32_t)(base + b * d.sigma1));
+    } else if (mode == 1) {
+        for (int64_t b = 0; b < r.nops; b++) out.push_back((int32_t)(base + aux[d.xt_off + b]));
+    } else if (mode == 3) {
+        const int64_t off = (d.flags & FRECT) ? (int64_t)i0 * d.nn
+                            : (d.flags & DCONTIG) ? r.opst - d.op0
+                                                  : aux[d.xp_off + i0];
+        for (int64_t b = 0; b < r.nops; b++) out.push_back(aux[d.xt_off + off + b]);
+    } else {
+        // runs: (start, length) pairs; shared (mode 2) from the table's head, full (mode 4)
+        // from the row's first run
+        int64_t j = mode == 2 ? 0 : aux[d.xp_off + i0];
+        const int64_t b0 = mode == 2 ? base : 0;
+        int64_t got = 0;
+        while (got < r.nops) {
+            const int64_t st = aux[d.xt_off + 2 * j], ln = aux[d.xt_off + 2 * j + 1];
+            for (int64_t q = 0; q < ln && got < r.nops; q++, got++) out.push_back((int32_t)(b0 + st + q));
+            j++;
+        }
+    }
+}
+
+// Rows a wide-row task of the dataflow solve may hold: the most R of 8, 4, 2 whose lanes per
+// row (64 / R) still split, after the right-hand-side lanes, into enough groups for the longest
+// row's ops to take one chunk of DF_U per group; else 1.
+int wide_rows_for(int64_t nops, int32_t k) {
+    int kr = 1;
+    while (kr < k && kr < WAVE_LANES) kr <<= 1;
+    for (int R = DF_RG; R > 1; R >>= 1) {
+        const int lanes = WAVE_LANES / R, kl = std::min(kr, lanes);
+        if ((int64_t)(lanes / kl) * DF_U >= nops) return R;
+    }
+    return 1;
+}
+
 // Dataflow-solve tasks: level by level over all matrices (a topological order of every
-// matrix's dependences), each codelet's rows in groups of up to DF_RG.  A wave pass takes 1, 2,
-// 4 or 8 consecutive tasks (by the right-hand-side count) starting at a multiple of that
-// count, and its rows must not depend on each other: every level's list is padded with empty
-// tasks (no rows) to a multiple of 8.  by_matrix: matrix after matrix instead (per-matrix
-// launches), with each matrix's range in ptr.
+// matrix's dependences).  Rows of at most DF_U ops go in groups of up to DF_RG consecutive rows
+// of one codelet; longer rows go in wide-row tasks of consecutive long rows (as many as
+// wide_rows_for allows for the task's longest row and the matrix's right-hand-side count, 8
+// where that count is a per-call argument), first in their level, with their columns appended
+// to lcols.  A wave pass takes 1, 2, 4 or 8 consecutive tasks, starting at a multiple of that
+// count, and its rows must not depend on each other; with group = DF_PASS_MAX (lists for any
+// right-hand-side count) every level is padded with empty tasks to a multiple of 8 and every
+// wide-row task starts a group of 8 that it fills with empty tasks.  With group = 1 (batches,
+// whose passes take one task of up to 8 rows) nothing is padded, and the short rows of a level
+// go 8 to a mixed task whatever their codelets (small codelets would otherwise leave most of a
+// pass idle), each row slot a (codelet, row) pair in slots.  by_matrix: matrix after matrix
+// instead (per-matrix launches), with each matrix's range in ptr.
 void build_df(const DevTables &D, const std::vector<int64_t> &cod_begin, const std::vector<std::vector<int32_t>> &levels,
-              bool by_matrix, std::vector<Task> &out, std::vector<int64_t> &ptr) {
+              bool by_matrix, int group, const std::vector<MatInfo> *mats, std::vector<Task> &out,
+              std::vector<int64_t> &ptr, std::vector<int32_t> &lcols, std::vector<int32_t> &slots) {
     const int nm = (int)cod_begin.size() - 1;
     out.clear();
+    lcols.clear();
+    slots.clear();
     ptr.assign(1, 0);
-    auto emit = [&](int64_t c) {
-        const int32_t m = D.cods[c].m;
-        for (int32_t a = 0; a < m; a += DF_RG) out.push_back({(int32_t)c, a, std::min(m, a + DF_RG), 0});
+    std::vector<Task> shortt, widet;
+    std::vector<int64_t> nops;
+    auto split = [&](int64_t c) {
+        const DCod &d = D.cods[c];
+        const int32_t k = mats ? (*mats)[d.mat].k : 8;
+        nops.resize(d.m);
+        for (int32_t a = 0; a < d.m; a++) nops[a] = host_row(d, D.aux, a).nops;
+        int32_t a = 0;
+        while (a < d.m) {
+            int32_t e = a;
+            if (nops[a] <= DF_U) {
+                while (e < d.m && nops[e] <= DF_U && e - a < DF_RG) e++;
+                shortt.push_back({(int32_t)c, a, e, 0});
+            } else {
+                int R = wide_rows_for(nops[a], k);
+                e = a + 1;
+                while (e < d.m && nops[e] > DF_U && e - a < std::min(R, wide_rows_for(nops[e], k))) {
+                    R = std::min(R, wide_rows_for(nops[e], k));
+                    e++;
+                }
+                widet.push_back({(int32_t)c, a, e, DF_LONG});
+            }
+            a = e;
+        }
     };
     auto pad = [&]() {
-        while (out.size() % DF_PASS_MAX) out.push_back({out.back().cod, 0, 0, 0});
+        while (out.size() % group) out.push_back({out.back().cod, 0, 0, 0});
+    };
+    // wide-row tasks first (they take longest), then the others
+    auto flush = [&]() {
+        for (const Task &t : widet) {
+            const DCod &d = D.cods[t.cod];
+            out.push_back({t.cod, t.i0b, (int32_t)lcols.size(), DF_LONG | ((t.i0e - t.i0b) << DF_LONG_ROWS_SHIFT)});
+            for (int32_t a = t.i0b; a < t.i0e; a++) host_cols(d, D.aux, a, host_row(d, D.aux, a), lcols);
+            pad();
+        }
+        if (group == 1) {
+            int32_t n = 0, first = 0;
+            for (const Task &t : shortt)
+                for (int32_t a = t.i0b; a < t.i0e; a++) {
+                    if (n == 0) first = t.cod;
+                    slots.push_back(t.cod);
+                    slots.push_back(a);
+                    if (++n == DF_RG) {
+                        const int32_t e = (int32_t)(slots.size() / 2);
+                        out.push_back({first, e - n, e, DF_MIXED});
+                        n = 0;
+                    }
+                }
+            if (n) {
+                const int32_t e = (int32_t)(slots.size() / 2);
+                out.push_back({first, e - n, e, DF_MIXED});
+            }
+        } else {
+            out.insert(out.end(), shortt.begin(), shortt.end());
+        }
+        if (!out.empty()) pad();
+        shortt.clear();
+        widet.clear();
     };
     // codelets of a matrix come in level order: per matrix, the first codelet of each level
     std::vector<std::vector<int64_t>> lvl_begin(nm);
@@ -523,8 +640,8 @@ void build_df(const DevTables &D, const std::vector<int64_t> &cod_begin, const s
     if (by_matrix) {
         for (int b = 0; b < nm; b++) {
             for (int32_t l = 0; l + 1 < (int32_t)lvl_begin[b].size(); l++) {
-                for (int64_t c = lvl_begin[b][l]; c < lvl_begin[b][l + 1]; c++) emit(c);
-                if (!out.empty()) pad();
+                for (int64_t c = lvl_begin[b][l]; c < lvl_begin[b][l + 1]; c++) split(c);
+                flush();
             }
             ptr.push_back((int64_t)out.size());
         }
@@ -533,8 +650,8 @@ void build_df(const DevTables &D, const std::vector<int64_t> &cod_begin, const s
     for (int32_t l = 0; l < maxl; l++) {
         for (int b = 0; b < nm; b++)
             if (l + 1 < (int32_t)lvl_begin[b].size())
-                for (int64_t c = lvl_begin[b][l]; c < lvl_begin[b][l + 1]; c++) emit(c);
-        if (!out.empty()) pad();
+                for (int64_t c = lvl_begin[b][l]; c < lvl_begin[b][l + 1]; c++) split(c);
+        flush();
     }
     ptr.push_back((int64_t)out.size());
 }
@@ -557,8 +674,12 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     drop_alloc(p, D.d_tcods);
     drop_alloc(p, D.d_df_tasks);
     drop_alloc(p, D.d_df_tcods);
+    drop_alloc(p, D.d_df_lcols);
+    drop_alloc(p, D.d_df_slots);
     D.d_df_tasks = nullptr;
     D.d_df_tcods = nullptr;
+    D.d_df_lcols = nullptr;
+    D.d_df_slots = nullptr;
     D.d_tasks = nullptr;
     D.d_tasksN = nullptr;
     D.d_sync = nullptr;
@@ -583,6 +704,8 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
         for (size_t i = 0; i < D.df_tasks.size(); i++) tc[i] = cods[D.df_tasks[i].cod];
         s = upload(p, &D.d_df_tasks, D.df_tasks.data(), D.df_tasks.size());
         if (!s) s = upload(p, &D.d_df_tcods, tc.data(), tc.size());
+        if (!s && !D.df_lcols.empty()) s = upload(p, &D.d_df_lcols, D.df_lcols.data(), D.df_lcols.size());
+        if (!s && !D.df_slots.empty()) s = upload(p, &D.d_df_slots, D.df_slots.data(), D.df_slots.size());
     }
     if (!s && !D.rowlist.empty()) s = upload(p, &D.d_rowlist, D.rowlist.data(), D.rowlist.size());
     if (!s && !D.tasksN.empty()) s = upload(p, &D.d_tasksN, D.tasksN.data(), D.tasksN.size());
@@ -995,16 +1118,21 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
     for (int b = 0; b < p->nmat; b++) cb[b + 1] = cb[b] + p->fwd[b].header[7];
     std::vector<std::vector<int32_t>> lv(p->nmat);
     for (int b = 0; b < p->nmat; b++) lv[b] = codelet_levels(p->fwd[b]);
+    // a batch's dataflow passes take one task each (8 lanes per row), and its matrices' right-
+    // hand-side counts are known; a single matrix's count is a per-call argument
+    const int df_group = p->batch ? 1 : DF_PASS_MAX;
+    const std::vector<MatInfo> *df_mats = p->batch ? &p->mats : nullptr;
     if (fwd) {
         p->F.tasks.clear();
         p->F.sync.clear();
         p->F.n_counters = 0;
         build_solve(p->F, cb, lv, p->sp_f, p->F.tasks, p->F.sync, p->F.n_counters);
-        build_df(p->F, cb, lv, false, p->F.df_tasks, p->F.df_ptr);
+        build_df(p->F, cb, lv, false, df_group, df_mats, p->F.df_tasks, p->F.df_ptr, p->F.df_lcols, p->F.df_slots);
         if (ddf_status s = upload_tasks(p, p->F)) return s;
         if (p->batch) {
             // per-matrix dataflow schedules for the one-launch-per-matrix comparator
-            build_df(p->F, cb, lv, true, p->Fpm.df_tasks, p->Fpm.df_ptr);
+            build_df(p->F, cb, lv, true, df_group, df_mats, p->Fpm.df_tasks, p->Fpm.df_ptr, p->Fpm.df_lcols,
+                     p->Fpm.df_slots);
             if (ddf_status s = upload_tasks(p, p->Fpm)) return s;
         }
     }
@@ -1019,7 +1147,8 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
         p->T.sync.clear();
         p->T.n_counters = 0;
         auto last = build_solve(p->T, cba, lva, p->sp_a, p->T.tasks, p->T.sync, p->T.n_counters);
-        build_df(p->T, cba, lva, false, p->T.df_tasks, p->T.df_ptr);
+        build_df(p->T, cba, lva, false, df_group, df_mats, p->T.df_tasks, p->T.df_ptr, p->T.df_lcols,
+                 p->T.df_slots);
         p->n_solve_tasks_adj = (int64_t)p->T.tasks.size();
         for (int b = 0; b < p->nmat; b++) append_gv(p->F, cb[b], cb[b + 1], last[b], p->sp_a, p->T.tasks, p->T.sync);
         if (ddf_status s = upload_tasks(p, p->T)) return s;
@@ -1377,6 +1506,8 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
         SolveArgs df = a;
         df.tasks = D.d_df_tasks + d0;
         df.tcods = D.d_df_tcods + d0;
+        df.lcols = D.d_df_lcols;
+        df.slots = reinterpret_cast<const int2 *>(D.d_df_slots);
         df.ntasks = (int32_t)(d1 - d0);
         const int kr = single ? df_lanes(k_override) : 8;
         const int per_pass = WAVE_LANES / kr / DF_RG;
@@ -2060,6 +2191,12 @@ ddf_status ddf_plan_device_tables(ddf_plan_t p, int32_t which, ddf_device_tables
     o->n_df_tasks = (int64_t)D->df_tasks.size();
     o->df_ptr = D->df_ptr.data();
     o->n_df_ptr = (int64_t)D->df_ptr.size();
+    o->df_lcols = D->df_lcols.data();
+    o->n_df_lcols = (int64_t)D->df_lcols.size();
+    o->df_group = p->batch ? 1 : DF_PASS_MAX;
+    o->df_slots = D->df_slots.data();
+    o->n_df_slots = (int64_t)D->df_slots.size() / 2;
+    o->df_reserved = 0;
     return DDF_OK;
 }
 

@@ -73,7 +73,9 @@ class ddf_device_tables_t(C.Structure):
                 ("thin_reserved", C.c_int32), ("thin_ngs", C.c_int32), ("thin_block", C.c_int32),
                 ("reserved", C.c_int32), ("rowlist", C.POINTER(C.c_int32)), ("n_rowlist", C.c_int64),
                 ("df_tasks", C.POINTER(C.c_int32)), ("n_df_tasks", C.c_int64), ("df_ptr", C.POINTER(C.c_int64)),
-                ("n_df_ptr", C.c_int64)]
+                ("n_df_ptr", C.c_int64), ("df_lcols", C.POINTER(C.c_int32)), ("n_df_lcols", C.c_int64),
+                ("df_group", C.c_int32), ("df_reserved", C.c_int32), ("df_slots", C.POINTER(C.c_int32)),
+                ("n_df_slots", C.c_int64)]
 
 
 class ddf_plan_info_t(C.Structure):
@@ -391,7 +393,7 @@ def ddf_plan_device_tables(plan, which=0) -> dict:
             "thin_rows": grab(t.thin_rows, t.n_thin_lvl and ddf_plan_info(plan)["n_rows"], 1).ravel(),
             "thin_lg": int(t.thin_lg), "thin_ring_size": int(t.thin_ring_size), "thin_ngs": int(t.thin_ngs),
             "thin_block": int(t.thin_block), "rowlist": grab(t.rowlist, t.n_rowlist),
-            "df_tasks": grab(t.df_tasks, t.n_df_tasks, 4),
+            "df_tasks": grab(t.df_tasks, t.n_df_tasks, 4), "df_lcols": grab(t.df_lcols, t.n_df_lcols), "df_group": int(t.df_group), "df_slots": grab(t.df_slots, t.n_df_slots, 2),
             "df_ptr": (np.ctypeslib.as_array(t.df_ptr, shape=(t.n_df_ptr,)).copy() if t.n_df_ptr
                        else np.zeros(0, np.int64))}
 

@@ -387,6 +387,34 @@ def random_csr(n_rows: int, n_cols: int, seed: int, density: float = 0.1,
     return a
 
 
+def long_rows_lower(n: int = 600, seed: int = 5) -> CSR:
+    """Sparse random lower-triangular matrix plus a few rows of hundreds of entries: a full
+    prefix (one run), a strided row, two scattered rows, and a dense first column (a long row
+    of the transpose).  Off-diagonals U[-0.01, 0.01], diagonal 1 + U[0, 1]."""
+    rng = generator(seed)
+    base = random_lower(n, seed, density=0.004)
+    r, c = [], []
+    for i in range(n):
+        cols = base.col_idx[base.row_ptr[i]:base.row_ptr[i + 1]]
+        r.append(np.full(cols.size, i))
+        c.append(cols)
+    h, s = n // 2, (5 * n) // 6
+    extra = {h: np.arange(h), h + 1: rng.choice(h + 1, (5 * n) // 12, replace=False), s: np.arange(0, s, 3),
+             n - 1: rng.choice(n - 1, (2 * n) // 3, replace=False)}
+    for i, cols in extra.items():
+        r.append(np.full(cols.size, i))
+        c.append(cols)
+    r.append(np.arange(1, n))
+    c.append(np.zeros(n - 1, np.int64))
+    rows, cols = np.concatenate(r), np.concatenate(c)
+    pairs = np.unique(np.stack([rows, cols], 1), axis=0)
+    rows, cols = pairs[:, 0], pairs[:, 1]
+    off = cols < rows
+    vals = rng.uniform(-1, 1, rows.size) * 0.01
+    vals[~off] = 1.0 + rng.uniform(0, 1, (~off).sum())
+    return csr_from_pairs(n, n, rows, cols, vals)
+
+
 def random_lower(n: int, seed: int, density: float = 0.2, runs: bool = False) -> CSR:
     """Random lower-triangular matrix, diagonal = 1 + row abs-sum (last in each row)."""
     rng = generator(seed)

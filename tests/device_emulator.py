@@ -242,14 +242,22 @@ def solve(tabs, L, B, kind=1, vals=None, perm=None, fwd_tabs=None, Xf=None, with
 
 DF_RG = 8
 DF_PASS_MAX = 8
+DF_U = 16  # ops of a lane's chunk: longer rows go in wide-row tasks
+DF_LONG = 1 << 14  # a wide-row task: rows i0b, i0b + 1, ... (count in bits 16+), columns at df_lcols[i0e:]
+DF_MIXED = 1 << 15  # a mixed task (batches): rows df_slots[i0b:i0e], each (codelet, row)
 
 
 def df_solve(tabs, L, B, kind=1, vals=None, perm=None, only_mat=None):
     """Replays the dataflow solve's tasks in list order (kind 1: L X = B; kind 2: U Lam = B
     with U = L^T, values through perm).  Checks that a task holds at most DF_RG rows of one
-    codelet, that every solution entry a row reads was written by an earlier task (so the list
-    is a topological order, and the earliest unfinished task never waits), and exact cover."""
+    codelet, of at most DF_U ops each, or is a wide-row task of 1..8 consecutive rows of more
+    than DF_U ops whose column list matches the codelet's columns, alone in its group of
+    df_group tasks; that every solution entry a row reads was written by a task of an earlier
+    group (so the list is a topological order, and the earliest unfinished task never waits);
+    and exact cover."""
     T = Tables(dict(tabs, tasks=tabs["df_tasks"]))
+    grp = tabs.get("df_group", DF_PASS_MAX)
+    assert grp in (1, DF_PASS_MAX)
     v = L.values if vals is None else vals
     n, k = B.shape
     X = np.full((n, k), np.nan)
@@ -257,23 +265,57 @@ def df_solve(tabs, L, B, kind=1, vals=None, perm=None, only_mat=None):
     ptr = tabs["df_ptr"]
     per_matrix = only_mat is not None and ptr.size > 2  # matrix after matrix, ranges in ptr
     lo, hi = (int(ptr[only_mat]), int(ptr[only_mat + 1])) if per_matrix else (0, T.tasks.shape[0])
-    assert lo % DF_PASS_MAX == 0 and hi % DF_PASS_MAX == 0
+    assert lo % grp == 0 and hi % grp == 0
+    lcols = tabs.get("df_lcols", np.zeros(0, np.int32))
+    slots = tabs.get("df_slots", np.zeros((0, 2), np.int32))
+    wide_group = -1  # the group a wide-row task holds alone
     for t in range(lo, hi):
         cod, i0b, i0e, meta = (int(x) for x in T.tasks[t])
-        assert meta == 0 and 0 <= i0e - i0b <= DF_RG and 0 <= cod < T.cods.shape[0]
-        if i0e == i0b:
-            continue  # padding: a wave pass never spans two levels
-        if only_mat is not None and int(T.cods[cod][F["mat"]]) != only_mat:
+        assert 0 <= cod < T.cods.shape[0]
+        c = T.cods[cod]
+        if meta & DF_LONG:
+            assert meta & 0xFFFF == DF_LONG and t % grp == 0
+            nrow = meta >> 16
+            assert 1 <= nrow <= DF_RG and i0b + nrow <= c[F["m"]]
+            rows, off = [], i0e
+            for i0 in range(i0b, i0b + nrow):
+                row, opst, nops = T.row_info(c, i0)
+                assert nops > DF_U and 0 <= off and off + nops <= lcols.size
+                cols = [int(q) for q in lcols[off:off + nops]]
+                assert cols == [int(q) for q in T.cols(c, i0, opst, nops)]
+                rows.append((row, opst, nops, cols))
+                off += nops
+            wide_group = t // grp
+        elif meta == DF_MIXED:
+            # a batch's mixed task: up to DF_RG rows of any codelets (of one matrix here or not)
+            assert grp == 1 and 1 <= i0e - i0b <= DF_RG and i0e <= slots.shape[0]
+            rows = []
+            for sc, si in slots[i0b:i0e]:
+                sc, si = int(sc), int(si)
+                assert 0 <= sc < T.cods.shape[0] and 0 <= si < T.cods[sc][F["m"]]
+                row, opst, nops = T.row_info(T.cods[sc], si)
+                assert nops <= DF_U
+                if only_mat is None or int(T.cods[sc][F["mat"]]) == only_mat:
+                    rows.append((row, opst, nops, T.cols(T.cods[sc], si, opst, nops)))
+                else:
+                    assert not per_matrix
+        else:
+            assert meta == 0 and 0 <= i0e - i0b <= DF_RG
+            if i0e == i0b:
+                continue  # padding: a wave pass never spans two levels
+            assert t // grp != wide_group, "a wide-row task shares its group"
+            _, _, rows = T.task_rows(t)
+            assert all(nops <= DF_U for _, _, nops, _ in rows)
+        if meta != DF_MIXED and only_mat is not None and int(c[F["mat"]]) != only_mat:
             assert not per_matrix
             continue
-        c, _, rows = T.task_rows(t)
         for row, opst, nops, cols in rows:
             acc = np.zeros(k)
             for i1, col in enumerate(cols):
                 e = opst + i1
-                # written by a task of an earlier group of DF_PASS_MAX (a wave pass takes up to
-                # that many consecutive tasks, all at once)
-                assert 0 <= written[col] and written[col] // DF_PASS_MAX < t // DF_PASS_MAX, \
+                # written by a task of an earlier group (a wave pass takes up to a group's
+                # consecutive tasks, all at once)
+                assert 0 <= written[col] and written[col] // grp < t // grp, \
                     f"row {row} reads x[{col}] before an earlier pass wrote it"
                 acc += (v[perm[e]] if kind == 2 else v[e]) * X[col]
             d = opst - 1 if kind == 2 else opst + nops

@@ -184,3 +184,16 @@ def test_graph_refused_after_autotune():
     for m, x in zip(mats, split(out.cpu().numpy(), mats)):
         check_solve(m["L"], m["B"], x, O.sptrsv(m["L"], m["B"]))
     g2.close()
+
+
+def test_dataflow_batch_reuses_output_buffer():
+    # consecutive dataflow solves with different right-hand sides into one output buffer
+    mats, plan, vals, B, G = make_batch(5, 2000, 9000, path=1)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    dv, dx = d(vals), torch.full((B.size,), np.nan, dtype=torch.float64, device=DEV)
+    for rep in range(3):
+        Bs = B * (rep + 1) - rep
+        ddf.ddf_sptrsv_batch(plan, dv, d(Bs), dx)
+        ddf.ddf_plan_sync_status(plan)
+        for m, x, b in zip(mats, split(dx.cpu().numpy(), mats), split(Bs, mats)):
+            check_solve(m["L"], b, x, O.sptrsv(m["L"], b))

@@ -228,3 +228,41 @@ def test_thin_lane_cap_sub_levels():
     assert F["thin_rec"].shape[0] and F["thin_lvl"][:, 1].max() <= 1024
     with pytest.raises(ddf.DDFError):
         hplan(1, L, thin_lanes=100)
+
+
+@pytest.mark.parametrize("window", [4, 64])
+def test_long_row_tasks(window):
+    L = I.long_rows_lower()
+    F = replay_solve(L, k=3, window=window)
+    p = hplan(1, L, window=window)
+    T = ddf.ddf_plan_device_tables(p, 1)
+    for tabs in (F, T):
+        lng = (tabs["df_tasks"][:, 3] & E.DF_LONG) != 0
+        assert lng.sum() >= 1 and tabs["df_lcols"].size > 0 and tabs["df_group"] == E.DF_PASS_MAX
+        assert (np.flatnonzero(lng) % E.DF_PASS_MAX == 0).all()
+
+
+def test_long_row_tasks_batch():
+    mats = [I.batch_matrix(b, n_lo=4000, n_hi=8000) for b in (2, 5, 0)]
+    Ls = [m["L"] for m in mats]
+    p = ddf.ddf_inspect_batch(1, Ls, [m["k"] for m in mats], ddf.ddf_opts_default(host_only=1))
+    F, T, PM = (ddf.ddf_plan_device_tables(p, w) for w in (0, 1, 2))
+    assert ((F["df_tasks"][:, 3] & E.DF_LONG) != 0).any() and F["df_group"] == 1
+    assert (F["df_tasks"][:, 3] == E.DF_MIXED).any() and F["df_slots"].shape[1] == 2
+    for b, m in enumerate(mats):
+        L, B = m["L"], m["B"]
+        ref = O.sptrsv(L, B)
+        check_solve(L, B, E.df_solve(F, L, B, only_mat=b), ref)
+        check_solve(L, B, E.df_solve(PM, L, B, only_mat=b), ref)
+        U, perm = O.transpose(L)
+        check_solve(L, m["G"], E.df_solve(T, U, m["G"], kind=2, vals=L.values, perm=perm, only_mat=b),
+                    O.sptrsv_adj(L, ref, m["G"])[0], transposed=True)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_wide_row_tasks_dense_rows(seed):
+    # rows of 17..100 ops: wide-row tasks of several rows (rows that fit 64 / R lanes)
+    L = I.random_lower(160, 40 + seed, density=0.25 + 0.1 * seed)
+    F = replay_solve(L, k=1 + seed, seed=seed, window=int([4, 64][seed % 2]))
+    nrows = F["df_tasks"][(F["df_tasks"][:, 3] & E.DF_LONG) != 0, 3] >> 16
+    assert nrows.size and nrows.max() >= 2

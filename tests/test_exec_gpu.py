@@ -402,3 +402,39 @@ def test_zero_diagonal_ieee(k):
         ddf.ddf_sptrsv_adjoint(plan, dev(L.values), None, dev(G), gb, None, k)
         ddf.ddf_plan_sync_status(plan)
         same_nonfinite(host(gb), lam_ref, info["solve_path_adj"] != 2)
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_long_rows(k):
+    # rows of hundreds of ops run as long-row tasks of the dataflow solve (a wave each), in the
+    # forward and the transposed solve
+    sptrsv_case(I.long_rows_lower(), k, seed=k)
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_wide_rows(k):
+    # rows of 17..100 ops: wide-row tasks of several rows each
+    sptrsv_case(I.random_lower(300, 44 + k, density=0.2), k, seed=k)
+
+
+@pytest.mark.parametrize("k", [1, 8])
+def test_dataflow_reuses_output_buffer(k):
+    # the dataflow solve reads solution values through the caches first: consecutive solves
+    # with different right-hand sides into one output buffer must each see only their own
+    # values (every launch refills the output with the not-yet-solved mark first)
+    L = I.c5_laplace27(nx=24, k=k).L
+    o = ddf.ddf_opts_default(solve_path=1, build_adjoint=1)
+    plan = ddf.ddf_inspect(1, L, o)
+    U, _ = O.transpose(L)
+    x = torch.full((L.n_rows, k), np.nan, dtype=torch.float64, device=DEV)
+    lam = torch.full_like(x, np.nan)
+    vals = dev(L.values)
+    for rep in range(4):
+        B = rnd((L.n_rows, k), 100 + rep) * (rep + 1)
+        ddf.ddf_sptrsv(plan, dev(B), x, k)
+        ref = O.sptrsv(L, B)
+        check_solve(L, B, host(x), ref)
+        G = rnd((L.n_rows, k), 200 + rep)
+        ddf.ddf_sptrsv_adjoint(plan, vals, x, dev(G), lam, None, k)
+        check_solve(L, G, host(lam), O.sptrsv_adj(L, ref, G)[0], transposed=True)
+    ddf.ddf_plan_sync_status(plan)
