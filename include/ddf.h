@@ -80,10 +80,11 @@ typedef struct {
     int32_t solve_blocks;  /* schedule (solve): 256-thread blocks of the persistent dataflow
                               kernel; 0 = every block the device keeps resident at once     */
     int32_t solve_path;    /* solve kernel: 0 auto (single-block when every level fits one
-                              1024-lane pass, else the dataflow kernel; batches: one launch
-                              per level over all matrices, one op per lane, one row pass),
-                              1 the dataflow kernel (one persistent launch, batches too),
-                              2 single-block when possible, 3 one launch per level        */
+                              1024-lane pass, else the dataflow kernel; batches: the
+                              dataflow kernel), 1 the dataflow kernel (one persistent
+                              launch, batches too), 2 single-block when possible, 3 one
+                              launch per level (batches: over all matrices, one op per
+                              lane, one row pass)                                          */
     int32_t thin_helpers;  /* single-block solve: helper blocks that pull the next levels'
                               tables into the solver's L2; -1 default (4), 0 none, max 8  */
     int32_t thin_ahead;    /* single-block solve: levels the helpers run ahead; 0 default

@@ -172,31 +172,6 @@ __device__ __forceinline__ int row_of(const DCod &c, const int32_t *__restrict__
     return (c.flags & FS0) ? c.row0 + i0 * c.row_step : aux[c.rows_off + i0];
 }
 
-// GV over the forward plan for phase-1 tasks: one output per op (lanes split the ops)
-__device__ void spmv_gv_task(const SpmvArgs &a, const Task &tk, int lane) {
-    const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
-    const int slot = lane >> lg, g = lane & (G - 1);
-    const int k = a.k;
-    const DCod c = load_cod(a.cods2 + tk.cod);
-    const int mode = xmode(c.flags);
-    for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
-        const RowInfo ri = row_info(c, a.aux2, i0);
-        const double *__restrict__ grow = a.g + (int64_t)ri.row * k;
-        walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
-            const double *__restrict__ xr = a.x2 + (int64_t)col * k;
-            double s = 0.0;
-            for (int r = 0; r < k; r++) s += grow[r] * xr[r];
-            a.gv[e] = a.gv_sign * s;
-        });
-        if (a.gv_diag && g == 0) {
-            const double *__restrict__ xr = a.x2 + (int64_t)ri.row * k;
-            double s = 0.0;
-            for (int r = 0; r < k; r++) s += grow[r] * xr[r];
-            a.gv[ri.opst + ri.nops] = a.gv_sign * s;
-        }
-    }
-}
-
 template <int MODE, bool VPERM>
 __device__ __forceinline__ void spmv_stream_body(const SpmvArgs &a, const DCod &c, int a0, int nrow, int lane,
                                                  double *__restrict__ lds) {
@@ -360,7 +335,7 @@ template <bool VPERM> __device__ void spmv_rows_task(const SpmvArgs &a, const Ta
     a.y[row] = acc;
 }
 
-// one right-hand side: stream and lanes-per-row tasks (and phase-1 GV tasks)
+// one right-hand side: stream and lanes-per-row tasks
 template <bool VPERM>
 __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
     __shared__ double lds_all[WPB][WAVE * SJ];
@@ -368,9 +343,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
     const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
     if (t >= a.ntasks) return;
     const Task tk = a.tasks[t];
-    if ((tk.meta >> 8) & 1)
-        spmv_gv_task(a, tk, lane);
-    else if (tk.meta & TASK_CSR)
+    if (tk.meta & TASK_CSR)
         spmv_csr_task<VPERM>(a, tk, lane, lds_all[wave]);
     else if (tk.meta & TASK_ROWS)
         spmv_rows_task<VPERM>(a, tk, lane);
@@ -508,10 +481,6 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
     const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
     if (t >= a.ntasks) return;
     const Task tk = a.tasks[t];
-    if ((tk.meta >> 8) & 1) {
-        spmv_gv_task(a, tk, lane);
-        return;
-    }
     const DCod c = load_cod(a.cods + tk.cod);
     const int mode = xmode(c.flags);
     const bool rect = (c.flags & FRECT) && !(c.flags & DOPS) && c.nn > 0;
@@ -563,50 +532,13 @@ __device__ __forceinline__ void xstore(double *p, double v) {
 template <int KT, bool ADJ, bool COH, bool SINGLE = false>
 __device__ void solve_task(const SolveArgs &a, int t, int lane) {
     const Task tk = a.tasks[t];
-    const int phase = (tk.meta >> 8) & 1;
-    const DCod c = a.tcods ? a.tcods[t] : load_cod((phase ? a.cods2 : a.cods) + tk.cod);
+    const DCod c = a.tcods ? a.tcods[t] : load_cod(a.cods + tk.cod);
     const MatInfo mi = mat_info(a, c);
     const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
     const int slot = lane >> lg, g = lane & (G - 1);
     const int k = a.k_override > 0 ? a.k_override : mi.k;
     const double *__restrict__ vals = a.vals + mi.val_base;
     const int mode = xmode(c.flags);
-    if (ADJ && phase) {
-        // GV over L's forward plan: gv[e] = -sum_r lam[row, r] x[col, r], diagonal included
-        const double *lam = a.x + mi.vec_base;
-        const double *__restrict__ xf = a.xf + mi.vec_base;
-        double *__restrict__ gv = a.gv + mi.val_base;
-        for (int i0 = tk.i0b + slot; i0 < tk.i0e; i0 += R) {
-            const RowInfo ri = row_info(c, a.aux2, i0);
-            const int64_t rb = (int64_t)ri.row * k;
-            if (k <= KT) {
-                double lr[KT];
-#pragma unroll
-                for (int r = 0; r < KT; r++) lr[r] = r < k ? xload<COH>(lam + rb + r) : 0.0;
-                walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
-                    const double *__restrict__ xr = xf + (int64_t)col * k;
-                    double s = 0.0;
-#pragma unroll
-                    for (int r = 0; r < KT; r++)
-                        if (r < k) s += lr[r] * xr[r];
-                    gv[e] = -s;
-                });
-            } else {
-                walk_any(mode, c, a.aux2, i0, ri, g, G, [&](int e, int col) {
-                    const double *__restrict__ xr = xf + (int64_t)col * k;
-                    double s = 0.0;
-                    for (int r = 0; r < k; r++) s += xload<COH>(lam + rb + r) * xr[r];
-                    gv[e] = -s;
-                });
-            }
-            if (g == 0) {
-                double s = 0.0;
-                for (int r = 0; r < k; r++) s += xload<COH>(lam + rb + r) * xf[rb + r];
-                gv[ri.opst + ri.nops] = -s;
-            }
-        }
-        return;
-    }
     constexpr bool VP = ADJ && !SINGLE; // values through perm
     const int32_t *__restrict__ perm = VP ? a.perm + mi.val_base : nullptr;
     const double *__restrict__ b = a.b + mi.vec_base;
@@ -1430,72 +1362,122 @@ __global__ __launch_bounds__(WAVE *WPB) void k_csr_gv(PlainArgs a) {
 }
 
 // Value gradient of an adjoint (GvArgs): G lanes per row, each lane one entry at a time; the
-// row of g in registers; x rows read whole (16-byte loads when VEC).  KT = 0: any k.
-template <int KT, bool VEC> __global__ __launch_bounds__(WAVE *WPB) void k_gv_csr(GvArgs a) {
+// row of g in registers; x rows read whole (16-byte loads when VEC: k even, 16-byte aligned
+// vectors).  Any k up to KT (a power of two): slots past k are predicated off (EXACT: k = KT,
+// no predicates).
+template <int KT, bool EXACT>
+__device__ __forceinline__ void gv_row_load(const double *__restrict__ gr, int k, double (&gw)[KT]) {
+#pragma unroll
+    for (int r = 0; r < KT; r++) gw[r] = (EXACT || r < k) ? gr[r] : 0.0;
+}
+
+template <int KT, bool VEC, bool EXACT>
+__device__ __forceinline__ double gv_dot(const double (&gw)[KT], const double *__restrict__ xr, int k) {
+    double s = 0.0;
+    if constexpr (VEC) {
+#pragma unroll
+        for (int r = 0; r < KT; r += 2)
+            if (EXACT || r < k) {
+                const double2 q = *reinterpret_cast<const double2 *>(xr + r);
+                s = fma(gw[r], q.x, s);
+                s = fma(gw[r + 1], q.y, s);
+            }
+    } else {
+#pragma unroll
+        for (int r = 0; r < KT; r++)
+            if (EXACT || r < k) s = fma(gw[r], xr[r], s);
+    }
+    return s;
+}
+
+template <int KT, bool VEC, bool EXACT> __global__ __launch_bounds__(WAVE *WPB) void k_gv_csr(GvArgs a) {
     const int lane = threadIdx.x % WAVE;
     const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
     const int64_t row = ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
     const int g = lane & (G - 1);
     if (row >= a.n) return;
-    const int k = KT > 0 ? KT : a.k;
-    const double *__restrict__ gr = a.g + row * k;
+    const int k = a.k;
     const int e1 = a.rp[row + 1];
     if (e1 - a.rp[row] > GV_LONG_ROW) return; // in the chunk pass
-    if constexpr (KT > 0) {
-        double gw[KT];
-        if constexpr (VEC) {
-#pragma unroll
-            for (int r = 0; r < KT; r += 2) {
-                const double2 q = *reinterpret_cast<const double2 *>(gr + r);
-                gw[r] = q.x;
-                gw[r + 1] = q.y;
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < KT; r++) gw[r] = gr[r];
-        }
-        for (int e = a.rp[row] + g; e < e1; e += G) {
-            const double *__restrict__ xr = a.x + (int64_t)a.ci[e] * KT;
-            double s = 0.0;
-            if constexpr (VEC) {
-#pragma unroll
-                for (int r = 0; r < KT; r += 2) {
-                    const double2 q = *reinterpret_cast<const double2 *>(xr + r);
-                    s = fma(gw[r], q.x, s);
-                    s = fma(gw[r + 1], q.y, s);
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < KT; r++) s = fma(gw[r], xr[r], s);
-            }
-            a.gv[e] = a.sign * s;
-        }
-    } else {
-        for (int e = a.rp[row] + g; e < e1; e += G) {
-            const double *__restrict__ xr = a.x + (int64_t)a.ci[e] * k;
-            double s = 0.0;
-            for (int r = 0; r < k; r++) s = fma(gr[r], xr[r], s);
-            a.gv[e] = a.sign * s;
-        }
-    }
+    double gw[KT];
+    gv_row_load<KT, EXACT>(a.g + row * k, k, gw);
+    for (int e = a.rp[row] + g; e < e1; e += G) a.gv[e] = a.sign * gv_dot<KT, VEC, EXACT>(gw, a.x + (int64_t)a.ci[e] * k, k);
 }
 
 // The chunks of long rows: a wave per GV_CHUNK entries of one row, 8 entries a lane.
-template <int KT> __global__ __launch_bounds__(WAVE *WPB) void k_gv_chunks(GvArgs a) {
+template <int KT, bool VEC, bool EXACT> __global__ __launch_bounds__(WAVE *WPB) void k_gv_chunks(GvArgs a) {
     const int64_t c = (int64_t)blockIdx.x * WPB + threadIdx.x / WAVE;
     const int lane = threadIdx.x % WAVE;
     if (c >= a.n_chunks) return;
     const int2 ch = a.chunks[c];
     const int64_t row = ch.x;
-    const int k = KT > 0 ? KT : a.k;
-    const double *__restrict__ gr = a.g + row * k;
+    const int k = a.k;
+    double gw[KT];
+    gv_row_load<KT, EXACT>(a.g + row * k, k, gw);
     const int e1 = min(a.rp[row + 1], ch.y + GV_CHUNK);
-    for (int e = ch.y + lane; e < e1; e += WAVE) {
-        const double *__restrict__ xr = a.x + (int64_t)a.ci[e] * k;
-        double s = 0.0;
-        for (int r = 0; r < k; r++) s = fma(gr[r], xr[r], s);
-        a.gv[e] = a.sign * s;
+    for (int e = ch.y + lane; e < e1; e += WAVE) a.gv[e] = a.sign * gv_dot<KT, VEC, EXACT>(gw, a.x + (int64_t)a.ci[e] * k, k);
+}
+
+// One entry's value gradient in a batch: k of the matrix (at most KT) decides the predicates
+// and the vector loads at run time (matrices of one class differ).
+template <int KT>
+__device__ __forceinline__ double gv_dot_any(const double (&gw)[KT], const double *__restrict__ xr, int k, bool vec) {
+    if constexpr (KT == 1) {
+        return gv_dot<1, false, true>(gw, xr, k);
+    } else {
+        if (k == KT) return vec ? gv_dot<KT, true, true>(gw, xr, k) : gv_dot<KT, false, true>(gw, xr, k);
+        return vec ? gv_dot<KT, true, false>(gw, xr, k) : gv_dot<KT, false, false>(gw, xr, k);
     }
+}
+
+// Matrix of row q of a class (binary search over the class's row starts).
+__device__ __forceinline__ int gv_class_mat(const GvBatchArgs &a, int64_t q) {
+    int lo = 0, hi = a.nm - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.mstart[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int KT> __global__ __launch_bounds__(WAVE *WPB) void k_gv_batch(GvBatchArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    const int lg = a.lg, G = 1 << lg, R = WAVE >> lg;
+    const int64_t q = ((int64_t)blockIdx.x * WPB + threadIdx.x / WAVE) * R + (lane >> lg);
+    const int g = lane & (G - 1);
+    if (q >= a.n) return;
+    const int j = gv_class_mat(a, q);
+    const MatInfo mi = a.mats[a.mids[j]];
+    const int64_t row = q - a.mstart[j];
+    const int k = mi.k;
+    const int32_t *__restrict__ rp = a.rp + mi.row_base;
+    const int e1 = rp[row + 1];
+    if (e1 - rp[row] > GV_LONG_ROW) return; // in the chunk pass
+    const bool vec = a.aligned && k % 2 == 0 && mi.vec_base % 2 == 0;
+    double gw[KT];
+    if (k == KT) gv_row_load<KT, true>(a.g + mi.vec_base + row * k, k, gw);
+    else gv_row_load<KT, false>(a.g + mi.vec_base + row * k, k, gw);
+    const double *__restrict__ x = a.x + mi.vec_base;
+    for (int e = rp[row] + g; e < e1; e += G) a.gv[e] = -gv_dot_any<KT>(gw, x + (int64_t)a.ci[e] * k, k, vec);
+}
+
+// The chunks of a class's long rows: a wave per GV_CHUNK entries of one row.
+template <int KT> __global__ __launch_bounds__(WAVE *WPB) void k_gv_batch_chunks(GvBatchArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * WPB + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (c >= a.n_chunks) return;
+    const int4 ch = a.chunks[c];
+    const MatInfo mi = a.mats[ch.x];
+    const int64_t row = ch.y;
+    const int k = mi.k;
+    const bool vec = a.aligned && k % 2 == 0 && mi.vec_base % 2 == 0;
+    double gw[KT];
+    if (k == KT) gv_row_load<KT, true>(a.g + mi.vec_base + row * k, k, gw);
+    else gv_row_load<KT, false>(a.g + mi.vec_base + row * k, k, gw);
+    const double *__restrict__ x = a.x + mi.vec_base;
+    const int e1 = min(a.rp[mi.row_base + row + 1], ch.z + GV_CHUNK);
+    for (int e = ch.z + lane; e < e1; e += WAVE) a.gv[e] = -gv_dot_any<KT>(gw, x + (int64_t)a.ci[e] * k, k, vec);
 }
 
 // Column-slice (BLAS-only) plans.  Every codelet is ops [a, a + nn) of m rows with all three
@@ -1849,35 +1831,65 @@ static int lg_for(double avg, int ops_per_lane) {
     return lg;
 }
 
+template <int KT, bool VEC, bool EXACT> static void launch_gv_kt(const GvArgs &a, hipStream_t s) {
+    if (a.n_chunks > 0) {
+        const dim3 cg((unsigned)((a.n_chunks + WPB - 1) / WPB)), cb(WAVE * WPB);
+        hipLaunchKernelGGL((k_gv_chunks<KT, VEC, EXACT>), cg, cb, 0, s, a);
+    }
+    const int R = WAVE >> a.lg;
+    if (a.n <= 0) return;
+    const dim3 grid((unsigned)((a.n + (int64_t)R * WPB - 1) / ((int64_t)R * WPB))), block(WAVE * WPB);
+    hipLaunchKernelGGL((k_gv_csr<KT, VEC, EXACT>), grid, block, 0, s, a);
+}
+
+template <int KT> static void launch_gv_vec(const GvArgs &a, bool vec, hipStream_t s) {
+    if (a.k == KT) {
+        if (vec) launch_gv_kt<KT, true, true>(a, s);
+        else launch_gv_kt<KT, false, true>(a, s);
+    } else {
+        if (vec) launch_gv_kt<KT, true, false>(a, s);
+        else launch_gv_kt<KT, false, false>(a, s);
+    }
+}
+
 hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s) {
     // about two entries a lane: each lane loads its row of g once for both (one entry a lane:
     // C5 2.59 ms for the SpMV adjoint instead of 2.43)
     a.lg = lg_for(avg_short_row, 2);
     if (a.lg > 5) a.lg = 5;
+    // 16-byte loads of x rows when every row starts 16-byte aligned
+    const bool vec = a.k % 2 == 0 && ((reinterpret_cast<uintptr_t>(a.g) | reinterpret_cast<uintptr_t>(a.x)) & 15) == 0;
+    if (a.k <= 1) launch_gv_kt<1, false, true>(a, s);
+    else if (a.k <= 2) launch_gv_vec<2>(a, vec, s);
+    else if (a.k <= 4) launch_gv_vec<4>(a, vec, s);
+    else if (a.k <= 8) launch_gv_vec<8>(a, vec, s);
+    else if (a.k <= 16) launch_gv_vec<16>(a, vec, s);
+    else launch_gv_vec<32>(a, vec, s);
+    return hipGetLastError();
+}
+
+template <int KT> static void launch_gv_batch_kt(const GvBatchArgs &a, hipStream_t s) {
     if (a.n_chunks > 0) {
         const dim3 cg((unsigned)((a.n_chunks + WPB - 1) / WPB)), cb(WAVE * WPB);
-        if (a.k == 1) hipLaunchKernelGGL((k_gv_chunks<1>), cg, cb, 0, s, a);
-        else hipLaunchKernelGGL((k_gv_chunks<0>), cg, cb, 0, s, a);
+        hipLaunchKernelGGL((k_gv_batch_chunks<KT>), cg, cb, 0, s, a);
     }
     const int R = WAVE >> a.lg;
-    if (a.n <= 0) return hipSuccess;
+    if (a.n <= 0) return;
     const dim3 grid((unsigned)((a.n + (int64_t)R * WPB - 1) / ((int64_t)R * WPB))), block(WAVE * WPB);
-    const bool al = ((reinterpret_cast<uintptr_t>(a.g) | reinterpret_cast<uintptr_t>(a.x)) & 15) == 0;
-    switch (a.k) {
-    case 1: hipLaunchKernelGGL((k_gv_csr<1, false>), grid, block, 0, s, a); break;
-    case 2:
-        if (al) hipLaunchKernelGGL((k_gv_csr<2, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_gv_csr<2, false>), grid, block, 0, s, a);
-        break;
-    case 4:
-        if (al) hipLaunchKernelGGL((k_gv_csr<4, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_gv_csr<4, false>), grid, block, 0, s, a);
-        break;
-    case 8:
-        if (al) hipLaunchKernelGGL((k_gv_csr<8, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_gv_csr<8, false>), grid, block, 0, s, a);
-        break;
-    default: hipLaunchKernelGGL((k_gv_csr<0, false>), grid, block, 0, s, a); break;
+    hipLaunchKernelGGL((k_gv_batch<KT>), grid, block, 0, s, a);
+}
+
+hipError_t launch_gv_batch_class(GvBatchArgs a, int kt, double avg_short_row, hipStream_t s) {
+    a.lg = lg_for(avg_short_row, 2);
+    if (a.lg > 5) a.lg = 5;
+    a.aligned = ((reinterpret_cast<uintptr_t>(a.g) | reinterpret_cast<uintptr_t>(a.x)) & 15) == 0;
+    switch (kt) {
+    case 1: launch_gv_batch_kt<1>(a, s); break;
+    case 2: launch_gv_batch_kt<2>(a, s); break;
+    case 4: launch_gv_batch_kt<4>(a, s); break;
+    case 8: launch_gv_batch_kt<8>(a, s); break;
+    case 16: launch_gv_batch_kt<16>(a, s); break;
+    default: launch_gv_batch_kt<32>(a, s); break;
     }
     return hipGetLastError();
 }

@@ -12,7 +12,7 @@ struct SpmvArgs {
     const int32_t *aux;
     const Task *tasks;
     int32_t ntasks;
-    int32_t k;     // right-hand sides (row stride of x, y, g)
+    int32_t k;     // right-hand sides (row stride of x, y)
     int32_t remap; // XCD-contiguous block order
     const double *vals;
     const int32_t *perm; // values through perm (transposed plan)
@@ -20,14 +20,6 @@ struct SpmvArgs {
     const int32_t *rows;    // row list of TASK_ROWS tasks
     const double *x;
     double *y;
-    // phase-1 tasks of a fused adjoint launch: gv[e] = sum_r g[row, r] x2[col, r]
-    const DCod *cods2;
-    const int32_t *aux2;
-    const double *g;
-    const double *x2;
-    double *gv;
-    double gv_sign;  // GV scale (+1 for SpMV, -1 for the solve adjoint)
-    int32_t gv_diag; // also write the diagonal entry (triangular forward plans)
 };
 
 // Single-block solve of a matrix whose every level fits one 1024-thread pass; G lanes per row,
@@ -115,10 +107,8 @@ constexpr int ROWS_MAX_LEN = 8;          // longest row a TASK_ROWS lane takes
 constexpr int STREAM_ELEMS = 64 * 8;     // elements of a stream task (64 lanes x 8)
 
 struct SolveArgs {
-    const DCod *cods;  // phase 0: the solve's plan
+    const DCod *cods;  // the solve's plan
     const int32_t *aux;
-    const DCod *cods2; // phase 1 (adjoint): L's forward plan for the GV pass
-    const int32_t *aux2;
     const Task *tasks;
     const DCod *tcods; // the codelet of each task, in task order (loaded beside the task), or null
     const int4 *sync; // per task: counter to wait on (-1 none), count to wait for, counter to signal
@@ -130,8 +120,6 @@ struct SolveArgs {
                          // kernel of a single-matrix call reads vals in U's order instead
     const double *b;     // right-hand side (adjoint: upstream gradient)
     double *x;           // solution (adjoint: lambda)
-    const double *xf;    // adjoint: forward solution (for GV)
-    double *gv;          // adjoint: value gradient
     unsigned *ctr;       // dataflow solve: lines of CTR_STRIDE: ticket, error flag, check-in count, mode
     unsigned *err;       // the error flag the dataflow solve raises (null: ctr's second line)
     int64_t spin_limit;
@@ -187,6 +175,26 @@ struct GvArgs {
     const int2 *chunks; // (row, first entry) of the chunks of rows longer than GV_LONG_ROW
     int64_t n_chunks;
 };
+// Value gradient of a batch adjoint, one launch per class of right-hand-side counts (k up to
+// KT, a power of two): the class's rows are its matrices' rows, matrix after matrix; row q of
+// the class is row q - mstart[j] of matrix mids[j] (mstart ascending, one more entry at the
+// end).  Rows longer than GV_LONG_ROW run as chunks {matrix, row, first entry, 0}.
+struct GvBatchArgs {
+    const int32_t *rp;   // packed row pointers (batch-wide entry indices)
+    const int32_t *ci;   // packed columns (local to each matrix)
+    const double *g;     // lambda, packed vectors (n_b, k_b) per matrix
+    const double *x;     // forward solution, packed the same way
+    double *gv;          // value gradient, packed values
+    const MatInfo *mats;
+    const int32_t *mids;
+    const int32_t *mstart;
+    int32_t nm;          // matrices of the class
+    int64_t n;           // rows of the class
+    int32_t lg;          // log2 lanes per row
+    const int4 *chunks;
+    int64_t n_chunks;
+    int32_t aligned;     // g and x 16-byte aligned
+};
 constexpr int GV_LONG_ROW = 256;  // rows longer than this run in chunks of GV_CHUNK entries
 constexpr int GV_CHUNK = 512;
 
@@ -237,5 +245,6 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_gather(double *dst, const double *src, const int32_t *idx, int64_t n, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
 hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s);
+hipError_t launch_gv_batch_class(GvBatchArgs a, int kt, double avg_short_row, hipStream_t s);
 
 } // namespace ddf

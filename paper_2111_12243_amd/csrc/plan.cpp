@@ -41,7 +41,7 @@ struct ddf_plan_s {
     int64_t n_rows = 0, n_cols = 0, nnz = 0, vec_total = 0;
     SchedParams sp_f, sp_a;
     DevTables F, T, Fpm;
-    int64_t n_solve_tasks_adj = 0;    // adjoint: tasks before the GV pass
+    int64_t n_solve_tasks_adj = 0;    // adjoint: tasks of the one-launch-per-level transposed solve
     int64_t ctr_words_f = 0;          // counter words of the forward solves
     int64_t ctr_words_a = 0;          // and of the adjoint's (after them, in the same allocation)
     int64_t n_gx_tasks = 0;           // SpMV adjoint: tasks before the GV pass (one RHS)
@@ -49,6 +49,17 @@ struct ddf_plan_s {
     std::vector<int32_t> gv_chunks;   // value gradient: (row, first entry) per chunk of a long row
     int32_t *d_gv_chunks = nullptr;
     double gv_avg_short = 1.0;        // mean length of the other rows
+    // batch adjoint's value gradient, per class of right-hand-side counts (k up to 1, 2, 4, ..., 32):
+    // its matrices (offset in gvb_mids), its rows, its long-row chunks (offset in gvb_chunks, int4
+    // each) and the mean length of its other rows
+    struct GvClass {
+        int32_t kt, nm;
+        int64_t mid_off, nrows, chunk_off, nchunks;
+        double avg;
+    };
+    std::vector<GvClass> gvb;
+    int32_t *d_gvb_mids = nullptr;   // per class: matrix ids, then row starts (nm + 1)
+    int32_t *d_gvb_chunks = nullptr;
     double *d_vals = nullptr;
     double *d_valsT = nullptr; // single-matrix SpTRSV adjoint: values in transposed order, per call
     int32_t *d_perm = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_rpT = nullptr, *d_ciT = nullptr;
@@ -479,18 +490,6 @@ std::vector<std::pair<int64_t, int64_t>> build_solve(const DevTables &D, const s
     return last;
 }
 
-// GV tasks (phase 1) of matrix b's forward codelets, run once its last level is complete.
-void append_gv(const DevTables &F, int64_t c0, int64_t c1, std::pair<int64_t, int64_t> last, const SchedParams &sp,
-               std::vector<Task> &tasks, std::vector<int32_t> &sync) {
-    std::vector<Task> tk;
-    for (int64_t c = c0; c < c1; c++) codelet_tasks(F.cods[c], F.aux, (int32_t)c, sp, 1, tk);
-    for (const Task &t : tk) {
-        tasks.push_back(t);
-        const int32_t sy[4] = {(int32_t)last.first, (int32_t)last.second, -1, -1};
-        sync.insert(sync.end(), sy, sy + 4);
-    }
-}
-
 // A device codelet's row i0 (row, first value index, ops) and its ops' columns, decoded on the
 // host the way the kernels read the records.
 struct HostRow {
@@ -688,14 +687,10 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     ddf_status s = upload(p, &D.d_tasks, D.tasks.data(), D.tasks.size());
     if (!s && !D.sync.empty() && !D.tasks.empty()) {
         // solve schedules: each task's codelet record in task order, so that a wave loads its
-        // task and its codelet side by side (phase-1 tasks of an adjoint are over L's forward
-        // plan)
+        // task and its codelet side by side
+        const std::vector<DCod> &cods = &D == &p->T ? p->T.cods : p->F.cods;
         std::vector<DCod> tc(D.tasks.size());
-        for (size_t i = 0; i < D.tasks.size(); i++) {
-            const Task &t = D.tasks[i];
-            const bool fwd_plan = &D == &p->T && ((t.meta >> 8) & 1);
-            tc[i] = (fwd_plan ? p->F.cods : (&D == &p->T ? p->T.cods : p->F.cods))[t.cod];
-        }
+        for (size_t i = 0; i < D.tasks.size(); i++) tc[i] = cods[D.tasks[i].cod];
         s = upload(p, &D.d_tcods, tc.data(), tc.size());
     }
     if (!s && !D.df_tasks.empty()) {
@@ -1146,11 +1141,10 @@ ddf_status build_schedule(ddf_plan_t p, bool fwd, bool adjp) {
         p->T.tasks.clear();
         p->T.sync.clear();
         p->T.n_counters = 0;
-        auto last = build_solve(p->T, cba, lva, p->sp_a, p->T.tasks, p->T.sync, p->T.n_counters);
+        build_solve(p->T, cba, lva, p->sp_a, p->T.tasks, p->T.sync, p->T.n_counters);
         build_df(p->T, cba, lva, false, df_group, df_mats, p->T.df_tasks, p->T.df_ptr, p->T.df_lcols,
                  p->T.df_slots);
         p->n_solve_tasks_adj = (int64_t)p->T.tasks.size();
-        for (int b = 0; b < p->nmat; b++) append_gv(p->F, cb[b], cb[b + 1], last[b], p->sp_a, p->T.tasks, p->T.sync);
         if (ddf_status s = upload_tasks(p, p->T)) return s;
     }
     return ensure_counters(p);
@@ -1345,10 +1339,10 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         }
     }
     p->sp_f.path = p->sp_a.path = o.solve_path;
-    if (batch && o.solve_path == 0) {
-        // batches: one launch per level over all matrices, one op per lane and one row pass
-        // (the one-launch dataflow kernel is solve_path 1)
-        p->sp_f.path = p->sp_a.path = 3;
+    if (batch) {
+        // batches: the dataflow kernel by default; the one-launch-per-level tasks (solve_path 3,
+        // and the adjoint's value-gradient pass) take one op per lane and one row pass
+        if (o.solve_path == 0) p->sp_f.path = p->sp_a.path = 1;
         p->sp_f.ops_per_lane = p->sp_a.ops_per_lane = 1;
         p->sp_f.passes = p->sp_a.passes = 1;
     }
@@ -1397,6 +1391,59 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         // order (one pass per call) instead of through perm in every level
         if (!batch && kind == DDF_SPTRSV_LOWER && (s = dalloc(p, (void **)&p->d_valsT, (size_t)p->nnz * 8)))
             return fin(s);
+    }
+    if (batch && p->has_adj) {
+        // the batch adjoint's value gradient: every matrix's CSR pattern, packed, with row
+        // pointers that hold batch-wide entry indices; matrices grouped by right-hand-side
+        // count class, one launch per class; rows longer than GV_LONG_ROW go in chunks
+        if (p->nnz > INT32_MAX || p->n_rows > INT32_MAX)
+            return fin(fail(DDF_E_ARG, "a batch with an adjoint holds at most 2^31 - 1 entries"));
+        std::vector<int32_t> rp(p->n_rows + 1), ci((size_t)p->nnz), mids, chunks;
+        for (int b = 0; b < nmat; b++) {
+            const ddf_csr_host &A = mats[b];
+            const MatInfo &mi = p->mats[b];
+            for (int32_t r = 0; r < A.n_rows; r++) rp[mi.row_base + r] = (int32_t)(mi.val_base + A.row_ptr[r]);
+            std::copy(A.col_idx, A.col_idx + A.row_ptr[A.n_rows], ci.begin() + mi.val_base);
+        }
+        rp[p->n_rows] = (int32_t)p->nnz;
+        for (int kt = 1; kt <= 32; kt <<= 1) {
+            ddf_plan_s::GvClass c{kt, 0, (int64_t)mids.size(), 0, (int64_t)chunks.size() / 4, 0, 1.0};
+            std::vector<int32_t> starts;
+            int64_t short_rows = 0, short_nnz = 0;
+            for (int b = 0; b < nmat; b++) {
+                const int32_t k = p->mats[b].k;
+                if (k > kt || (kt > 1 && k <= kt / 2)) continue;
+                const ddf_csr_host &A = mats[b];
+                mids.push_back(b);
+                starts.push_back((int32_t)c.nrows);
+                c.nrows += A.n_rows;
+                for (int32_t r = 0; r < A.n_rows; r++) {
+                    const int32_t b0 = A.row_ptr[r], len = A.row_ptr[r + 1] - b0;
+                    if (len > GV_LONG_ROW) {
+                        for (int32_t e = b0; e < b0 + len; e += GV_CHUNK) {
+                            const int32_t q[4] = {b, r, (int32_t)(p->mats[b].val_base + e), 0};
+                            chunks.insert(chunks.end(), q, q + 4);
+                        }
+                    } else {
+                        short_rows++;
+                        short_nnz += len;
+                    }
+                }
+            }
+            c.nm = (int32_t)starts.size();
+            if (c.nm == 0) {
+                continue;
+            }
+            starts.push_back((int32_t)c.nrows);
+            mids.insert(mids.end(), starts.begin(), starts.end());
+            c.nchunks = (int64_t)chunks.size() / 4 - c.chunk_off;
+            c.avg = short_rows ? std::max(1.0, (double)short_nnz / (double)short_rows) : 1.0;
+            p->gvb.push_back(c);
+        }
+        if ((s = upload(p, &p->d_rp, rp.data(), rp.size()))) return fin(s);
+        if ((s = upload(p, &p->d_ci, ci.data(), ci.size()))) return fin(s);
+        if ((s = upload(p, &p->d_gvb_mids, mids.data(), mids.size()))) return fin(s);
+        if (!chunks.empty() && (s = upload(p, &p->d_gvb_chunks, chunks.data(), chunks.size()))) return fin(s);
     }
     if (!batch) {
         // CSR copies for the plain comparators and the adjoints' value gradient
@@ -1454,10 +1501,9 @@ ddf_status check_nrhs(int32_t k) {
 const double *vals_or_own(ddf_plan_t p, const double *v) { return v ? v : p->d_vals; }
 
 // One solve (adj: the transposed solve) over a schedule: tasks [t0, t0 + ntasks) of the
-// one-launch-per-level lists (the batch adjoint's value-gradient tasks come last, level -1).
-// Every path but 3 runs the dataflow tasks of D instead (matrix `mat` of a per-matrix schedule,
-// or all), then any value-gradient tasks in one more launch.  An in-place call (b == x) takes one launch
-// per level: the dataflow solve marks the output as not yet solved before it starts.
+// one-launch-per-level lists.  Every path but 3 runs the dataflow tasks of D instead (matrix
+// `mat` of a per-matrix schedule, or all).  An in-place call (b == x) takes one launch per
+// level: the dataflow solve marks the output as not yet solved before it starts.
 // Where a solve call keeps its scratch: the values in transposed order and the dataflow
 // solve's counter lines (null: the plan's own), and the error flag it raises.
 struct SolveScratch {
@@ -1467,14 +1513,12 @@ struct SolveScratch {
 };
 
 ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t ntasks, bool adj, const double *vals,
-                        const double *b, double *x, const double *xf, double *gv, int32_t k_override, int kt,
+                        const double *b, double *x, int32_t k_override, int kt,
                         hipStream_t s, int mat = -1, const SolveScratch &scr = SolveScratch()) {
     const SchedParams &sp = adj ? p->sp_a : p->sp_f;
     SolveArgs a{};
     a.cods = adj ? p->T.d_cods : p->F.d_cods;
     a.aux = adj ? p->T.d_aux : p->F.d_aux;
-    a.cods2 = p->F.d_cods;
-    a.aux2 = p->F.d_aux;
     a.tasks = D.d_tasks + t0;
     a.tcods = D.d_tcods ? D.d_tcods + t0 : nullptr;
     a.sync = D.d_sync ? reinterpret_cast<const int4 *>(D.d_sync) + t0 : nullptr;
@@ -1485,8 +1529,6 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
     a.perm = p->d_perm;
     a.b = b;
     a.x = x;
-    a.xf = xf;
-    a.gv = gv;
     a.ctr = scr.ctr ? scr.ctr : adj ? p->d_ctr_adj : p->d_ctr;
     a.err = scr.err;
     a.spin_limit = p->spin_limit;
@@ -1524,18 +1566,9 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
             const auto tm = next_timer(p, 1);
             HIPCHK(launch_solve_df(df, adj, adj && !single, kr, sp.blocks, fill, nfill, s, tm.first, tm.second));
         }
-        const int64_t ngv = adj ? ntasks - p->n_solve_tasks_adj : 0;
-        if (ngv > 0) { // the batch adjoint's value gradient, after the solve
-            a.tasks += p->n_solve_tasks_adj;
-            if (a.tcods) a.tcods += p->n_solve_tasks_adj;
-            a.sync += p->n_solve_tasks_adj;
-            a.ntasks = (int32_t)ngv;
-            HIPCHK(launch_solve_range(a, adj, kt, s));
-        }
         return DDF_OK;
     }
-    // one launch per level (task ranges of equal level, over all matrices of a batch; the GV
-    // tasks last)
+    // one launch per level (task ranges of equal level, over all matrices of a batch)
     const Task *tk = a.tasks;
     const DCod *tc = a.tcods;
     const int4 *sy = a.sync;
@@ -1576,6 +1609,29 @@ hipError_t launch_gv_pass(ddf_plan_t p, const double *g, const double *x, double
     a.chunks = reinterpret_cast<const int2 *>(p->d_gv_chunks);
     a.n_chunks = (int64_t)p->gv_chunks.size() / 2;
     return launch_gv(a, p->gv_avg_short, s);
+}
+
+// The batch adjoint's value gradient, gv[e] = -<lambda[row], x[col]> over every entry of every
+// L_b (diagonal included): one pass over the packed CSR patterns per class of right-hand-side
+// counts.
+hipError_t launch_gv_batch(ddf_plan_t p, const double *lam, const double *x, double *gv, hipStream_t s) {
+    for (const auto &c : p->gvb) {
+        GvBatchArgs a{};
+        a.rp = p->d_rp;
+        a.ci = p->d_ci;
+        a.g = lam;
+        a.x = x;
+        a.gv = gv;
+        a.mats = p->d_mats;
+        a.mids = p->d_gvb_mids + c.mid_off;
+        a.mstart = a.mids + c.nm;
+        a.nm = c.nm;
+        a.n = c.nrows;
+        a.chunks = reinterpret_cast<const int4 *>(p->d_gvb_chunks) + c.chunk_off;
+        a.n_chunks = c.nchunks;
+        if (hipError_t e = launch_gv_batch_class(a, c.kt, c.avg, s)) return e;
+    }
+    return hipSuccess;
 }
 
 // Column-slice plans: SpMV is one init launch (y = 0) and one launch of every slice task; the
@@ -1757,7 +1813,7 @@ ddf_status ddf_sptrsv_v(ddf_plan_t p, const double *d_vals, const double *d_b, d
     if (use_thin(p->F, p->sp_f, nrhs))
         return thin_launch(p, p->F, p->sp_f, p->F.thin_nlev, d_vals, d_b, d_x, nrhs, (hipStream_t)stream);
     // the single matrix's right-hand-side count is a per-call argument (k_override)
-    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nullptr, nullptr, nrhs,
+    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nrhs,
                         kt_for(nrhs), (hipStream_t)stream);
 }
 
@@ -1830,7 +1886,7 @@ ddf_status ddf_sptrsv_adjoint(ddf_plan_t p, const double *d_vals, const double *
     hipStream_t s = (hipStream_t)stream;
     if (use_thin(p->T, p->sp_a, nrhs)) {
         if (ddf_status st = thin_launch(p, p->T, p->sp_a, p->T.thin_nlev, d_vals, d_gx, d_gb, nrhs, s)) return st;
-    } else if (ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, true, d_vals, d_gx, d_gb, d_x, nullptr,
+    } else if (ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, true, d_vals, d_gx, d_gb,
                                             nrhs, kt_for(nrhs), s)) {
         return st;
     }
@@ -1883,7 +1939,7 @@ ddf_status ddf_sptrsv_adjoint_noalloc(ddf_plan_t p, const double *d_vals, const 
     // takes otherwise, then the value gradient
     const int32_t path = p->sp_a.path;
     p->sp_a.path = d_gb == d_gx ? 3 : 1;
-    ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, true, d_vals, d_gx, d_gb, d_x, nullptr, nrhs,
+    ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, true, d_vals, d_gx, d_gb, nrhs,
                                  kt_for(nrhs), s, -1, ss);
     p->sp_a.path = path;
     if (st) return st;
@@ -1905,7 +1961,7 @@ ddf_status ddf_sptrsv_batch(ddf_plan_t p, const double *d_vals, const double *d_
     int64_t nb = p->vec_total * 8;
     if ((!d_vals && p->nnz) || !d_b || !d_x) return fail(DDF_E_ARG, "NULL buffer");
     if (d_b != d_x && overlap(d_b, nb, d_x, nb)) return fail(DDF_E_ARG, "b and x partially overlap");
-    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, nullptr, nullptr, 0,
+    return solve_launch(p, p->F, 0, (int64_t)p->F.tasks.size(), false, d_vals, d_b, d_x, 0,
                         batch_kt(p), (hipStream_t)stream);
 }
 
@@ -1919,8 +1975,11 @@ ddf_status ddf_sptrsv_batch_adjoint(ddf_plan_t p, const double *d_vals, const do
     if ((!d_vals && p->nnz) || !d_gx || !d_gb || (d_gvals && !d_x)) return fail(DDF_E_ARG, "NULL buffer");
     if (d_gb != d_gx && overlap(d_gb, nb, d_gx, nb)) return fail(DDF_E_ARG, "gb and gx partially overlap");
     if (overlap(d_gb, nb, d_x, nb)) return fail(DDF_E_ARG, "gb overlaps x");
-    int64_t nt = d_gvals ? (int64_t)p->T.tasks.size() : p->n_solve_tasks_adj;
-    return solve_launch(p, p->T, 0, nt, true, d_vals, d_gx, d_gb, d_x, d_gvals, 0, batch_kt(p), (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    if (ddf_status st = solve_launch(p, p->T, 0, p->n_solve_tasks_adj, true, d_vals, d_gx, d_gb, 0, batch_kt(p), s))
+        return st;
+    if (d_gvals) HIPCHK(launch_gv_batch(p, d_gb, d_x, d_gvals, s));
+    return DDF_OK;
 }
 
 ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t p, const double *d_vals, const double *d_b, double *d_x,
@@ -1935,7 +1994,7 @@ ddf_status ddf_sptrsv_batch_per_matrix(ddf_plan_t p, const double *d_vals, const
     p->sp_f.path = 1;
     ddf_status st = DDF_OK;
     for (int b = 0; b < p->nmat && !st; b++)
-        st = solve_launch(p, p->Fpm, 0, 0, false, d_vals, d_b, d_x, nullptr, nullptr, 0, kt_for(p->mats[b].k),
+        st = solve_launch(p, p->Fpm, 0, 0, false, d_vals, d_b, d_x, 0, kt_for(p->mats[b].k),
                           (hipStream_t)stream, b);
     p->sp_f.path = path;
     return st;
@@ -2207,7 +2266,6 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
     int64_t vk = p->batch ? p->vec_total : n * nrhs;      // sum of n_b k_b
     int64_t ck = p->batch ? p->vec_total : nc * nrhs;
     int64_t kf = p->batch ? 0 : nrhs;
-    int64_t Fca = (int64_t)p->F.aux.size() * 4; // the batch adjoint's GV tasks read L's forward aux
     const bool many = !p->batch && nrhs > 1;
     int64_t ba = 0, bc = 0, fl = 0;
     switch (op) {
@@ -2241,13 +2299,13 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         break;
     case DDF_OP_SPTRSV_ADJ:
         // transposed solve, then the value gradient over the CSR pattern (columns and row pointers)
-        // (batches: the value-gradient tasks read L's forward plan; one matrix: the values are
-        // first copied in transposed order, written and read back)
+        // (batches: the solve reads the values through perm; one matrix: the values are first
+        // copied in transposed order, written and read back)
         if (p->has_adj && !p->batch && use_thin(p->T, p->sp_a, nrhs))
             ba = 20 * nnz + p->T.thin_bytes() + 4 * (n + 1) + 24 * vk;
         else if (p->batch)
-            ba = 20 * nnz + (p->has_adj ? (p->sp_a.path != 3 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
-                 Fca + 32 * vk;
+            ba = 24 * nnz + (p->has_adj ? (p->sp_a.path != 3 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
+                 4 * (n + 1) + 32 * vk;
         else
             ba = 24 * nnz + (p->has_adj ? (p->sp_a.path != 3 ? p->T.df_read_bytes() : p->T.solve_read_bytes()) : 0) +
                  4 * (n + 1) + 32 * vk + 16 * nnz;

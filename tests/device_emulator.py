@@ -124,8 +124,7 @@ def spmv(tabs, A, X, vals=None, perm=None, tasks=None, many=False):
     seen = np.zeros(A.n_rows, int)
     for t in (range(T.tasks.shape[0]) if tasks is None else tasks):
         meta = int(T.tasks[t][3])
-        if (meta >> 8) & 1:
-            continue
+        assert (meta >> 8) & 1 == 0  # every task computes rows
         if meta & TASK_CSR:
             # rows [i0b, i0e) straight from the CSR pattern (at most 64 rows and STREAM_ELEMS
             # elements, or one longer row)
@@ -164,23 +163,7 @@ def spmv(tabs, A, X, vals=None, perm=None, tasks=None, many=False):
     return Y
 
 
-def gv(tabs, fwd_tabs, A, G, X, t0, many=False):
-    """GV[e] = sum_r G[row, r] X[col, r] over phase-1 tasks (tasks of `tabs`, records and
-    aux of the forward tables) from t0 on."""
-    T, TF = Tables(dict(tabs, tasks=tabs["tasksN"]) if many else tabs), Tables(fwd_tabs)
-    out = np.full(int(A.row_ptr[-1]), np.nan)
-    for t in range(t0, T.tasks.shape[0]):
-        c, meta, rows = _rows_from(TF, T.tasks[t])
-        assert (meta >> 8) & 1
-        for row, opst, nops, cols in rows:
-            for i1, col in enumerate(cols):
-                e = opst + i1
-                assert np.isnan(out[e])
-                out[e] = G[row] @ X[col]
-    return out
-
-
-def solve(tabs, L, B, kind=1, vals=None, perm=None, fwd_tabs=None, Xf=None, with_gv=False, only_mat=None):
+def solve(tabs, L, B, kind=1, vals=None, perm=None, only_mat=None):
     """Replays the persistent solve task by task in ticket order.  kind 1: L X = B on L's
     plan; kind 2: U Lam = B with U = L^T, values through perm.  Checks the counter protocol:
     each task's wait is already satisfied by earlier tickets, every count waited for equals
@@ -192,11 +175,9 @@ def solve(tabs, L, B, kind=1, vals=None, perm=None, fwd_tabs=None, Xf=None, with
     n, k = B.shape
     X = np.full((n, k), np.nan)
     writer = np.full(n, -2)  # signal counter of the task that wrote each row
-    gvout = np.full(int(L.row_ptr[-1]), np.nan) if with_gv else None
-    TF = Tables(fwd_tabs) if fwd_tabs is not None else None
+
     def mat_of(t):
-        cod = int(T.tasks[t][0])
-        return int((TF.cods if (int(T.tasks[t][3]) >> 8) & 1 else T.cods)[cod][F["mat"]])
+        return int(T.cods[int(T.tasks[t][0])][F["mat"]])
 
     # one launch covers the tasks of `only_mat` (per-matrix schedules reuse counter ids)
     mine = [t for t in range(T.tasks.shape[0]) if only_mat is None or mat_of(t) == only_mat]
@@ -208,36 +189,26 @@ def solve(tabs, L, B, kind=1, vals=None, perm=None, fwd_tabs=None, Xf=None, with
         if w >= 0:
             assert nsig[w] == cnt, "count waited for differs from the tasks signalling the counter"
             assert done[w] >= cnt, "wait not satisfied by earlier tickets"
-        meta = int(T.tasks[t][3])
-        if (meta >> 8) & 1:
-            assert with_gv and TF is not None
-            assert (writer >= 0).all() and (writer <= w).all(), "GV pass before the solve finished"
-            c, _, rows = _rows_from(TF, T.tasks[t])
-            for row, opst, nops, cols in rows:
-                for i1, col in enumerate(cols):
-                    gvout[opst + i1] = -(X[row] @ Xf[col])
-                gvout[opst + nops] = -(X[row] @ Xf[row])
-        else:
-            assert sig >= 0 and (w == -1 or w == sig - 1)
-            c, _, rows = T.task_rows(t)
-            pending = []
-            for row, opst, nops, cols in rows:
-                acc = np.zeros(k)
-                for i1, col in enumerate(cols):
-                    e = opst + i1
-                    assert writer[col] >= 0 and writer[col] <= w, f"row {row} reads x[{col}] not covered by its wait"
-                    acc += (v[perm[e]] if kind == 2 else v[e]) * X[col]
-                d = opst - 1 if kind == 2 else opst + nops
-                diag = v[perm[d]] if kind == 2 else v[d]
-                pending.append((row, (B[row] - acc) / diag))
-            for row, val in pending:
-                assert writer[row] == -2
-                X[row] = val
-                writer[row] = sig
-        if sig >= 0:
-            done[sig] += 1
+        assert (int(T.tasks[t][3]) >> 8) & 1 == 0  # every task solves rows
+        assert sig >= 0 and (w == -1 or w == sig - 1)
+        c, _, rows = T.task_rows(t)
+        pending = []
+        for row, opst, nops, cols in rows:
+            acc = np.zeros(k)
+            for i1, col in enumerate(cols):
+                e = opst + i1
+                assert writer[col] >= 0 and writer[col] <= w, f"row {row} reads x[{col}] not covered by its wait"
+                acc += (v[perm[e]] if kind == 2 else v[e]) * X[col]
+            d = opst - 1 if kind == 2 else opst + nops
+            diag = v[perm[d]] if kind == 2 else v[d]
+            pending.append((row, (B[row] - acc) / diag))
+        for row, val in pending:
+            assert writer[row] == -2
+            X[row] = val
+            writer[row] = sig
+        done[sig] += 1
     assert (writer >= 0).all()
-    return X, gvout
+    return X
 
 
 DF_RG = 8
@@ -325,16 +296,6 @@ def df_solve(tabs, L, B, kind=1, vals=None, perm=None, only_mat=None):
             written[row] = t
     assert (written >= 0).all()
     return X
-
-
-def _rows_from(TF, task):
-    cod, i0b, i0e, meta = (int(v) for v in task)
-    c = TF.cods[cod]
-    out = []
-    for i0 in range(i0b, i0e):
-        row, opst, nops = TF.row_info(c, i0)
-        out.append((row, opst, nops, TF.cols(c, i0, opst, nops)))
-    return c, meta, out
 
 
 THIN_UNUSED = -(1 << 31)
