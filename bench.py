@@ -578,7 +578,7 @@ def bench_cost_model(args, np, torch, ddf, I, dev):
 
 
 def bench_batch(args, np, torch, ddf, I, dev):
-    """The batched solve and its adjoint on C4 (256 matrices, 1..32 right-hand sides)."""
+    """The batched solve and its adjoint on the batch workload (256 matrices, 1..32 right-hand sides)."""
     t0 = time.time()
     w = I.workload("c4")
     mats = [m["L"] for m in w.batch]

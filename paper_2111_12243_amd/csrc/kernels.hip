@@ -677,6 +677,41 @@ __device__ __forceinline__ bool df_backoff(const SolveArgs &a, int64_t &spins, i
     return true;
 }
 
+// Re-reads a lane's missing solution values.  ALL: every one of them.  Otherwise only the last
+// missing one, which is normally the latest dependence since a lane's ops run in dependence
+// order, and once it has arrived the others still missing at once: a wait then costs one load
+// per lane and poll rather than one per missing value.  With one or two right-hand sides a pass
+// holds 32 or 64 rows, one or two lanes each, whose polls hit different lines: polling only
+// the last keeps the many waiting waves from crowding the memory system (27-point Laplacian
+// on 170^3, one right-hand side: 19.3 ms -> 4.8 ms).  With more right-hand sides the lanes of
+// a row poll one line together and the extra round trip after the last arrival costs more
+// than the polls (eight right-hand sides: 3.1 ms -> 4.3 ms).
+template <int U, bool ALL>
+__device__ __forceinline__ void df_poll(double (&xv)[U], const int (&col)[U], const double *x, int k, int rr) {
+    if constexpr (ALL) {
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (df_missing(xv[u])) xv[u] = cload(x + (int64_t)col[u] * k + rr);
+        return;
+    }
+    int last = -1;
+#pragma unroll
+    for (int u = 0; u < U; u++)
+        if (df_missing(xv[u])) last = u;
+    bool got = false;
+#pragma unroll
+    for (int u = 0; u < U; u++)
+        if (u == last) {
+            xv[u] = cload(x + (int64_t)col[u] * k + rr);
+            got = !df_missing(xv[u]);
+        }
+    if (got) {
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (u != last && df_missing(xv[u])) xv[u] = cload(x + (int64_t)col[u] * k + rr);
+    }
+}
+
 // A row's result from its values and the solution values it reads: stored for the readers.
 template <int U>
 __device__ __forceinline__ void df_finish(const double (&v)[U], const double (&xv)[U], double acc, double bo,
@@ -755,9 +790,7 @@ __device__ __forceinline__ void df_long(const SolveArgs &a, const Task &tk, cons
                     live = false; // past the watchdog: the results are reported invalid
                     break;
                 }
-#pragma unroll
-                for (int u = 0; u < DF_U; u++)
-                    if (df_missing(xv[u])) xv[u] = cload(x + (int64_t)col[u] * k + rr);
+                df_poll<DF_U, true>(xv, col, x, k, rr);
             }
 #pragma unroll
             for (int u = 0; u < DF_U; u++) acc = fma(v[u], xv[u], acc);
@@ -876,9 +909,7 @@ __device__ __forceinline__ int df_pass(const SolveArgs &a, int p, int pn, int la
                     pend = false;
                     break;
                 }
-#pragma unroll
-                for (int u = 0; u < DF_U; u++)
-                    if (df_missing(xv[u])) xv[u] = cload(x + (int64_t)col[u] * k + rr);
+                df_poll<DF_U, (KR > 2)>(xv, col, x, k, rr);
             }
             if (!one_chunk) {
 #pragma unroll
@@ -1741,8 +1772,8 @@ int resident_solve_blocks() { return g_solve_blocks > 0 ? g_solve_blocks : 1024;
 
 // One level's tasks per launch (the launch boundaries order the levels): plain loads and
 // stores, no tickets, no waits.  SINGLE (single-matrix calls): four ops' column reads ahead
-// of their loads (C5: 3% faster; batches of small matrices: 5% slower), and the adjoint's
-// values already in U's order.
+// of their loads (27-point Laplacian on 170^3: 3% faster; batches of small matrices: 5%
+// slower), and the adjoint's values already in U's order.
 template <int KT, bool ADJ, bool SINGLE>
 __global__ __launch_bounds__(WAVE *WPB) void k_solve_range(SolveArgs a) {
     const int lane = threadIdx.x % WAVE;
@@ -1866,7 +1897,7 @@ template <int KT> static void launch_gv_vec(const GvArgs &a, bool vec, hipStream
 
 hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s) {
     // about two entries a lane: each lane loads its row of g once for both (one entry a lane:
-    // C5 2.59 ms for the SpMV adjoint instead of 2.43)
+    // 2.59 ms for the SpMV adjoint of the 27-point Laplacian on 170^3 instead of 2.43)
     a.lg = lg_for(avg_short_row, 2);
     if (a.lg > 5) a.lg = 5;
     // 16-byte loads of x rows when every row starts 16-byte aligned

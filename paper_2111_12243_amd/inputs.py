@@ -212,7 +212,7 @@ class Workload:
     Gy: np.ndarray | None = None  # SpMV upstream gradient (n_rows, k)
     B: np.ndarray | None = None  # SpTRSV right-hand side (n, k)
     Gx: np.ndarray | None = None  # SpTRSV upstream gradient (n, k)
-    batch: list = field(default_factory=list)  # C4: list of dicts {L, k, B, G}
+    batch: list = field(default_factory=list)  # batch workloads: list of dicts {L, k, B, G}
     meta: dict = field(default_factory=dict)
 
 

@@ -438,3 +438,26 @@ def test_dataflow_reuses_output_buffer(k):
         ddf.ddf_sptrsv_adjoint(plan, vals, x, dev(G), lam, None, k)
         check_solve(L, G, host(lam), O.sptrsv_adj(L, ref, G)[0], transposed=True)
     ddf.ddf_plan_sync_status(plan)
+
+
+@pytest.mark.parametrize("k", [1, 8])
+def test_spin_limit_watchdog(k):
+    # a spin limit of one poll: the dataflow solve's first wait trips the watchdog, every wave
+    # stops waiting and the kernel ends; the call is then reported invalid, the flag cleared,
+    # and the next solve at the default limit is exact again (the wait is bounded by the
+    # limit, so this never hangs)
+    L = bidiag(20000)
+    plan = ddf.ddf_inspect(1, L, ddf.ddf_opts_default(solve_path=1))
+    B = rnd((L.n_rows, k), k)
+    b = dev(B)
+    x = torch.full_like(b, np.nan)
+    ddf.ddf_plan_set_spin_limit(plan, 1)
+    ddf.ddf_sptrsv(plan, b, x, k)
+    with pytest.raises(ddf.DDFError) as err:
+        ddf.ddf_plan_sync_status(plan)
+    assert err.value.status == ddf.DDF_E_DEVICE
+    ddf.ddf_plan_set_spin_limit(plan, 0)
+    x = torch.full_like(b, np.nan)
+    ddf.ddf_sptrsv(plan, b, x, k)
+    ddf.ddf_plan_sync_status(plan)
+    check_solve(L, B, host(x), O.sptrsv(L, B))
