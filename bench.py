@@ -492,14 +492,16 @@ def bench_ablation(args, np, torch, ddf, I, dev):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
 
     plans, tinsp = {}, {}
-    for name, kind, M, ob, path in (("spmv_ddf", 0, A, 0, 0), ("spmv_blas_only", 0, A, 1, 0),
-                                    ("sptrsv_ddf", 1, L, 0, 0), ("sptrsv_ddf_level", 1, L, 0, 3),
-                                    ("sptrsv_blas_only", 1, L, 1, 0)):
+    cases = [("spmv_ddf", 0, A, 0, 0), ("spmv_blas_only", 0, A, 1, 0)]
+    if L is not None:
+        cases += [("sptrsv_ddf", 1, L, 0, 0), ("sptrsv_ddf_level", 1, L, 0, 3), ("sptrsv_blas_only", 1, L, 1, 0)]
+    for name, kind, M, ob, path in cases:
         t0 = time.time()
         plans[name] = ddf.ddf_inspect(kind, M, ddf.ddf_opts_default(only_blas=ob, build_adjoint=0, solve_path=path))
         tinsp[name] = round(time.time() - t0, 3)
         log(f"[ablation] {name}: inspect {tinsp[name]}s")
-    vA, X, vL, B = d(A.values), d(w.X), d(L.values), d(w.B)
+    vA, X = d(A.values), d(w.X)
+    vL, B = (d(L.values), d(w.B)) if L is not None else (None, None)
     out = {n: torch.empty((A.n_rows if n.startswith("spmv") else L.n_rows, k), dtype=torch.float64, device=dev)
            for n in plans}
     ops = {n: (lambda n=n: ddf.ddf_spmv_v(plans[n], vA, X, out[n], k)) if n.startswith("spmv")
@@ -525,12 +527,13 @@ def bench_ablation(args, np, torch, ddf, I, dev):
                  "ratio": round(ms["spmv_blas_only"] / ms["spmv_ddf"], 3), "paper_ratio": 10.0,
                  "max_rel_diff": rel("spmv_blas_only", "spmv_ddf"),
                  "ddf": cods("spmv_ddf"), "blas_only": cods("spmv_blas_only")},
-        "sptrsv": {"ddf_ms": round(ms["sptrsv_ddf"], 4), "ddf_level_ms": round(ms["sptrsv_ddf_level"], 4),
-                   "blas_only_ms": round(ms["sptrsv_blas_only"], 4),
-                   "ratio": round(ms["sptrsv_blas_only"] / ms["sptrsv_ddf"], 3),
-                   "ratio_same_executor": round(ms["sptrsv_blas_only"] / ms["sptrsv_ddf_level"], 3),
-                   "paper_ratio": 3.9, "max_rel_diff": rel("sptrsv_blas_only", "sptrsv_ddf"),
-                   "ddf": cods("sptrsv_ddf"), "blas_only": cods("sptrsv_blas_only")},
+        "sptrsv": None if L is None else {
+            "ddf_ms": round(ms["sptrsv_ddf"], 4), "ddf_level_ms": round(ms["sptrsv_ddf_level"], 4),
+            "blas_only_ms": round(ms["sptrsv_blas_only"], 4),
+            "ratio": round(ms["sptrsv_blas_only"] / ms["sptrsv_ddf"], 3),
+            "ratio_same_executor": round(ms["sptrsv_blas_only"] / ms["sptrsv_ddf_level"], 3),
+            "paper_ratio": 3.9, "max_rel_diff": rel("sptrsv_blas_only", "sptrsv_ddf"),
+            "ddf": cods("sptrsv_ddf"), "blas_only": cods("sptrsv_blas_only")},
         "timing": "median of K steps, 1 GiB written between steps, one stream",
     }
     print(json.dumps(res), flush=True)
