@@ -161,6 +161,11 @@ typedef struct {
                                    3 one launch per level                                */
     int32_t solve_path_adj;     /* same for the adjoint solve (0 for SpMV plans)          */
     int32_t reserved;
+    double phase_seconds[5];    /* wall time of ddf_inspect's phases: [0] Alg. 1 on the
+                                   forward pattern(s) (inspect_seconds minus [1]), [1] the
+                                   transposition and the adjoint plan's Alg. 1, [2] device
+                                   records and tables (packing), [3] single-block solve
+                                   records, [4] schedules, uploads and the rest            */
 } ddf_plan_info_t;
 
 typedef enum {

@@ -164,7 +164,7 @@ ddf_status fail(ddf_status s, const std::string &msg);
 ddf_status validate(int kind, const ddf_csr_host &A);
 void inspect(const Pattern &P, int32_t t, int threads, Canon &out, bool only_blas = false);
 void transpose(int32_t n_rows, int32_t n_cols, const int32_t *rp, const int32_t *ci,
-               std::vector<int32_t> &rpT, std::vector<int32_t> &ciT, std::vector<int32_t> &perm);
+               std::vector<int32_t> &rpT, std::vector<int32_t> &ciT, std::vector<int32_t> &perm, int threads = 0);
 uint64_t hash_canon(const Canon &c, uint64_t h);
 
 } // namespace ddf

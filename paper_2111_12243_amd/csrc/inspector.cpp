@@ -57,20 +57,54 @@ ddf_status validate(int kind, const ddf_csr_host &A) {
 }
 
 void transpose(int32_t n_rows, int32_t n_cols, const int32_t *rp, const int32_t *ci,
-               std::vector<int32_t> &rpT, std::vector<int32_t> &ciT, std::vector<int32_t> &perm) {
-    int64_t nnz = rp[n_rows];
+               std::vector<int32_t> &rpT, std::vector<int32_t> &ciT, std::vector<int32_t> &perm, int threads) {
+    const int64_t nnz = rp[n_rows];
     rpT.assign((size_t)n_cols + 1, 0);
     ciT.resize(nnz);
     perm.resize(nnz);
-    for (int64_t e = 0; e < nnz; e++) rpT[ci[e] + 1]++;
-    for (int64_t j = 0; j < n_cols; j++) rpT[j + 1] += rpT[j];
-    std::vector<int32_t> next(rpT.begin(), rpT.end() - 1);
-    for (int64_t i = 0; i < n_rows; i++)
-        for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
-            int32_t p = next[ci[e]]++;
-            ciT[p] = (int32_t)i;
-            perm[p] = (int32_t)e;
+    // row chunks on host threads: each counts its entries per column, the chunks' counts are
+    // laid out column by column in chunk order, then each chunk scatters its own entries, so
+    // a column's entries come in ascending row order as in the serial counting sort
+    int nt = threads > 0 ? threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = (int)std::min<int64_t>({nt, 16, std::max<int64_t>(1, nnz / (int64_t(1) << 20))});
+    std::vector<int64_t> rb(nt + 1);
+    for (int t = 0; t <= nt; t++) {
+        // chunk boundaries at rows that split the entries evenly
+        const int64_t target = nnz * t / nt;
+        rb[t] = std::lower_bound(rp, rp + n_rows + 1, (int32_t)target) - rp;
+    }
+    rb[nt] = n_rows;
+    std::vector<std::vector<int32_t>> cnt(nt, std::vector<int32_t>((size_t)n_cols, 0));
+    auto run = [&](auto &&f) {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nt; t++) pool.emplace_back(f, t);
+        f(0);
+        for (auto &th : pool) th.join();
+    };
+    run([&](int t) {
+        int32_t *c = cnt[t].data();
+        for (int64_t e = rp[rb[t]]; e < rp[rb[t + 1]]; e++) c[ci[e]]++;
+    });
+    // column starts, then each chunk's first slot in each column
+    int64_t acc = 0;
+    for (int64_t j = 0; j < n_cols; j++) {
+        rpT[j] = (int32_t)acc;
+        for (int t = 0; t < nt; t++) {
+            const int32_t v = cnt[t][j];
+            cnt[t][j] = (int32_t)acc;
+            acc += v;
         }
+    }
+    rpT[n_cols] = (int32_t)acc;
+    run([&](int t) {
+        int32_t *next = cnt[t].data();
+        for (int64_t i = rb[t]; i < rb[t + 1]; i++)
+            for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+                const int32_t q = next[ci[e]]++;
+                ciT[q] = (int32_t)i;
+                perm[q] = (int32_t)e;
+            }
+    });
 }
 
 uint64_t hash_canon(const Canon &c, uint64_t h) {

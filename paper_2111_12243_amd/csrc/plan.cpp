@@ -9,6 +9,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <sstream>
 #include <string>
 
@@ -69,6 +70,7 @@ struct ddf_plan_s {
     unsigned *d_ctr_adj = nullptr;    // the adjoint's own (a forward and an adjoint may overlap)
     int64_t spin_limit = int64_t(1) << 26;
     double inspect_seconds = 0;
+    double phase_seconds[5] = {0, 0, 0, 0, 0}; // ddf_inspect's phases (ddf_plan_info_t)
     uint64_t hash = 0;
     int max_levels = 0;
     std::vector<void *> allocs;
@@ -1247,6 +1249,10 @@ void apply_opts(ddf_opts &o, const ddf_opts *in) {
 }
 
 // Shared body of ddf_inspect / ddf_inspect_batch.
+double seconds_since(std::chrono::steady_clock::time_point t) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count();
+}
+
 ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, const int32_t *nrhs,
                      const ddf_opts *opts, bool batch, ddf_plan_t *out) {
     *out = nullptr;
@@ -1288,10 +1294,12 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         Pattern P{kind, A.n_rows, A.n_cols, A.row_ptr, A.col_idx};
         inspect(P, o.window, o.threads, p->fwd[b], o.only_blas != 0);
         if (p->has_adj) {
-            transpose(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, rpT[b], ciT[b], perm[b]);
+            const auto ta = std::chrono::steady_clock::now();
+            transpose(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, rpT[b], ciT[b], perm[b], o.threads);
             Pattern PT{kind == DDF_SPMV ? 0 : 2, A.n_cols, A.n_rows, rpT[b].data(), ciT[b].data()};
             inspect(PT, o.window, o.threads, p->adj[b], o.only_blas != 0);
-            p->adj[b].perm = perm[b];
+            p->adj[b].perm = std::move(perm[b]);
+            p->phase_seconds[1] += seconds_since(ta);
         }
         MatInfo &mi = p->mats[b];
         mi.row_base = p->n_rows;
@@ -1305,7 +1313,8 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
         p->vec_total += (int64_t)A.n_rows * (batch ? nrhs[b] : 1);
         p->max_levels = std::max<int>(p->max_levels, (int)p->fwd[b].header[5]);
     }
-    p->inspect_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    p->inspect_seconds = seconds_since(t0);
+    p->phase_seconds[0] = p->inspect_seconds - p->phase_seconds[1];
     uint64_t h = 1469598103934665603ull;
     for (auto &c : p->fwd) h = hash_canon(c, h);
     p->hash = h;
@@ -1321,6 +1330,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
             return fail(DDF_E_HIP, std::string("device query: ") + hipGetErrorString(e));
         }
     }
+    auto tph = std::chrono::steady_clock::now();
     for (int b = 0; b < nmat; b++) {
         Pattern P{kind, mats[b].n_rows, mats[b].n_cols, mats[b].row_ptr, mats[b].col_idx};
         pack(p->fwd[b], P, b, p->F);
@@ -1329,15 +1339,21 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
             pack(p->adj[b], PT, b, p->T);
         }
     }
+    p->phase_seconds[2] = seconds_since(tph);
+    tph = std::chrono::steady_clock::now();
     if (kind == DDF_SPTRSV_LOWER && !batch && !p->sliced) {
         const int32_t ring = o.thin_ring > 0 ? o.thin_ring : THIN_RING_MAX;
         Pattern P{kind, mats[0].n_rows, mats[0].n_cols, mats[0].row_ptr, mats[0].col_idx};
-        build_thin(p->fwd[0], P, nullptr, ring, o.thin_lanes, p->F);
+        // the transposed plan's records on a second host thread (the two are independent)
+        std::thread adj_thin;
         if (p->has_adj) {
             Pattern PT{2, mats[0].n_cols, mats[0].n_rows, rpT[0].data(), ciT[0].data()};
-            build_thin(p->adj[0], PT, &perm[0], ring, o.thin_lanes, p->T);
+            adj_thin = std::thread([&, PT]() { build_thin(p->adj[0], PT, &p->adj[0].perm, ring, o.thin_lanes, p->T); });
         }
+        build_thin(p->fwd[0], P, nullptr, ring, o.thin_lanes, p->F);
+        if (adj_thin.joinable()) adj_thin.join();
     }
+    p->phase_seconds[3] = seconds_since(tph);
     p->sp_f.path = p->sp_a.path = o.solve_path;
     if (batch) {
         // batches: the dataflow kernel by default; the one-launch-per-level tasks (solve_path 3,
@@ -1349,20 +1365,24 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     p->sp_f.helpers = p->sp_a.helpers = o.thin_helpers < 0 ? 4 : std::min(o.thin_helpers, 8);
     p->sp_f.ahead = p->sp_a.ahead = o.thin_ahead <= 0 ? 24 : std::max(o.thin_ahead, 8);
     if (p->host_only) {
+        tph = std::chrono::steady_clock::now();
         ddf_status st = build_schedule(p, true, true);
         if (st) {
             free_plan(p);
             return st;
         }
+        p->phase_seconds[4] = seconds_since(tph);
         *out = p;
         return DDF_OK;
     }
     ddf_status s = DDF_OK;
+    tph = std::chrono::steady_clock::now();
     auto fin = [&](ddf_status st) {
         if (st) {
             free_plan(p);
             return st;
         }
+        p->phase_seconds[4] = seconds_since(tph);
         *out = p;
         return DDF_OK;
     };
@@ -1385,7 +1405,7 @@ ddf_status make_plan(ddf_kind kind, int32_t nmat, const ddf_csr_host *mats, cons
     }
     if (p->has_adj) {
         std::vector<int32_t> pall;
-        for (int b = 0; b < nmat; b++) pall.insert(pall.end(), perm[b].begin(), perm[b].end());
+        for (int b = 0; b < nmat; b++) pall.insert(pall.end(), p->adj[b].perm.begin(), p->adj[b].perm.end());
         if ((s = upload(p, &p->d_perm, pall.data(), pall.size()))) return fin(s);
         // the per-level transposed solve of one matrix reads its values gathered in transposed
         // order (one pass per call) instead of through perm in every level
@@ -2192,6 +2212,7 @@ ddf_status ddf_plan_info(ddf_plan_t p, ddf_plan_info_t *o) {
     o->has_adjoint = p->has_adj;
     o->max_levels = p->max_levels;
     o->inspect_seconds = p->inspect_seconds;
+    for (int i = 0; i < 5; i++) o->phase_seconds[i] = p->phase_seconds[i];
     o->hash = p->hash;
     o->ops_per_lane = p->sp_f.ops_per_lane;
     o->rows_passes = p->sp_f.passes;

@@ -87,7 +87,7 @@ class ddf_plan_info_t(C.Structure):
                 ("has_adjoint", C.c_int32), ("max_levels", C.c_int32), ("inspect_seconds", C.c_double),
                 ("hash", C.c_uint64), ("ops_per_lane", C.c_int32), ("rows_passes", C.c_int32),
                 ("xcd_remap", C.c_int32), ("solve_path", C.c_int32), ("solve_path_adj", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("phase_seconds", C.c_double * 5)]
 
 
 _LIB = None
