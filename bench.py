@@ -58,6 +58,10 @@ def parse():
     return ap.parse_args()
 
 
+# ddf_inspect's phases (ddf_plan_info_t.phase_seconds)
+PHASES = ["alg1_forward", "adjoint_plan", "packing", "single_block_records", "schedules_uploads"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -319,6 +323,9 @@ def main():
                    "codelets_A_by_type": info_A["codelets_by_type"], "ops_A_by_type": info_A["ops_by_type"],
                    "codelets_L_by_type": info_L.get("codelets_by_type"), "ops_L_by_type": info_L.get("ops_by_type"),
                    "inspect_s": {"A": round(tA, 3), "L": round(tL, 3)}, "ner": ner,
+                   "inspect_phases_s": {"A": [round(v, 3) for v in info_A["phase_seconds"]],
+                                        "L": [round(v, 3) for v in info_L["phase_seconds"]] if info_L else None,
+                                        "phases": PHASES},
                    "timing": "median of K steps, 1 GiB written between steps, one stream"},
         "pct_of_peak": round(100 * value / PEAK_GBPS, 2),
         "plain": {"ms_per_step": round(ms_plain, 4), "value": round(bytes_step / (ms_plain / 1e3) / 1e9, 2),
@@ -605,9 +612,19 @@ def bench_batch(args, np, torch, ddf, I, dev):
     ops = {"sptrsv_batch": lambda: ddf.ddf_sptrsv_batch(p, vals, B, X),
            "sptrsv_batch_adj": lambda: ddf.ddf_sptrsv_batch_adjoint(p, vals, X, G, GB, GV)}
     if args.profile_op:
-        for name in args.profile_op.split(","):
+        # a leg per name, as in the single-matrix bench: "copy" calibrates the counters, and a
+        # one-element fill ends each leg
+        mark = torch.zeros(1, dtype=torch.float64, device=dev)
+        for leg, name in enumerate(args.profile_op.split(",")):
+            if name == "copy":
+                src = torch.rand(1 << 26, dtype=torch.float64, device=dev)
+                dst = torch.empty_like(src)
+                fn = lambda: torch.mul(src, 1.0, out=dst)  # noqa: E731
+            else:
+                fn = ops[name]
             for _ in range(args.steps):
-                ops[name]()
+                fn()
+            mark.fill_(float(leg))
             torch.cuda.synchronize()
             log(f"[bench] ran {name} x{args.steps}")
         return
@@ -690,6 +707,7 @@ def bench_batch(args, np, torch, ddf, I, dev):
         "config": {"workload": w.name, "matrices": len(mats), "rows": sum(m.n_rows for m in mats),
                    "nnz_L": sum(m.nnz for m in mats), "nrhs_range": [min(ks), max(ks)],
                    "max_levels": binfo["max_levels"], "inspect_s": round(t_insp, 3),
+                   "inspect_phases_s": [round(v, 3) for v in binfo["phase_seconds"]], "phases": PHASES,
                    "ner": {"sptrsv_batch": round(t_insp * 1e3 / (per_matrix_ms - op_ms["sptrsv_batch"]), 1)
                            if per_matrix_ms > op_ms["sptrsv_batch"] else None},
                    "solve_kernel": {"fwd": bnames.get(binfo["solve_path"]), "adj": bnames.get(binfo["solve_path_adj"])}},
