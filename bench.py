@@ -280,7 +280,9 @@ def main():
     ba_dom = ddf.ddf_plan_traffic(pdom, kop, k)[0]
     ach = ba_dom / (kernel_ms / 1e3) / 1e9
     wl = args.workload
-    fetch = profile_value(f"traffic_{dom}_{wl}.md", "hbm_bytes_per_call")
+    # HBM bytes per launch of the dominant kernel, from the committed counter summary of this
+    # call (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), when taken on these sources
+    fetch = profile_value(f"traffic_{dom}_{wl}.md", f"hbm_bytes_per_launch_{kernel_of[dom]}")
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach / PEAK_GBPS, 4), "traffic": fetch,
                 "kernel": kernel_of[dom], "call": dom, "kernel_ms": round(kernel_ms, 4),
@@ -669,9 +671,11 @@ def bench_batch(args, np, torch, ddf, I, dev):
     bnames = {1: "k_solve_df", 2: "k_solve_thin", 3: "k_solve_range"}
     ba_dom = ddf.ddf_plan_traffic(p, kop, 1)[0]
     ach = ba_dom / (kernel_ms / 1e3) / 1e9
+    kname = bnames.get(binfo.get(bkey))
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBPS, "unit": "GB/s",
-                "frac": round(ach / PEAK_GBPS, 4), "traffic": None, "kernel": bnames.get(binfo.get(bkey)),
-                "call": dom, "kernel_ms": round(kernel_ms, 4), "bytes_alg_per_launch": ba_dom}
+                "frac": round(ach / PEAK_GBPS, 4),
+                "traffic": profile_value(f"traffic_{dom}_c4.md", f"hbm_bytes_per_launch_{kname}"),
+                "kernel": kname, "call": dom, "kernel_ms": round(kernel_ms, 4), "bytes_alg_per_launch": ba_dom}
     cpu = None
     if not args.no_cpu:
         import oracle as O
