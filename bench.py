@@ -290,7 +290,7 @@ def main():
     if dom.startswith("sptrsv"):
         # two-term bound of a level-ordered solve: t >= max(bytes / peak, levels x t_sync), with
         # t_sync the measured latency of one dependent hop of this kernel (bench.py --tsync)
-        tsync = profile_value("tsync.md", f"{kernel_of[dom]}_us_per_hop")
+        tsync = profile_value("tsync.md", f"{kernel_of[dom]}_k{1 if k <= 2 else 8}_us_per_hop")
         nlev = int(info_L["n_parts"])
         roofline["levels"] = nlev
         roofline["t_sync_us"] = tsync
@@ -420,25 +420,26 @@ def bench_tsync(args, np, torch, ddf, I, dev):
     of one row each) solved by the dataflow kernel, the single-block kernel and one launch per
     level; microseconds per level (the t_sync of the two-term solve bound)."""
     out = {}
-    for name, path, n in (("k_solve_df", 1, 50000), ("k_solve_thin", 2, 50000), ("k_solve_range", 3, 5000)):
+    for name, path, n, k in (("k_solve_df", 1, 50000, 1), ("k_solve_df", 1, 50000, 8), ("k_solve_thin", 2, 50000, 1),
+                             ("k_solve_range", 3, 5000, 1), ("k_solve_range", 3, 5000, 8)):
         rows = np.concatenate([np.arange(1, n), np.arange(n)])
         cols = np.concatenate([np.arange(n - 1), np.arange(n)])
         L = I.csr_from_pairs(n, n, rows, cols, np.random.default_rng(1).uniform(1, 2, rows.size))
         p = ddf.ddf_inspect(1, L, ddf.ddf_opts_default(solve_path=path, build_adjoint=0))
         assert ddf.ddf_plan_info(p)["solve_path"] == path
-        b = torch.from_numpy(np.random.default_rng(2).uniform(-1, 1, (n, 1))).to(dev)
+        b = torch.from_numpy(np.random.default_rng(2).uniform(-1, 1, (n, k))).to(dev)
         x = torch.empty_like(b)
         ts = []
         for _ in range(args.warmup + 5):
             ddf.ddf_plan_time_kernels(p, 1)
-            ddf.ddf_sptrsv(p, b, x, 1)
+            ddf.ddf_sptrsv(p, b, x, k)
             kms, _, _ = ddf.ddf_plan_kernel_time(p)
             ts.append(kms)
         ddf.ddf_plan_time_kernels(p, 0)
         ddf.ddf_plan_sync_status(p)
         us = median(ts[args.warmup:]) * 1e3 / n
-        out[f"{name}_us_per_hop"] = round(us, 4)
-        log(f"[bench] {name}: {us:.3f} us per dependent level ({n} levels)")
+        out[f"{name}_k{k}_us_per_hop"] = round(us, 4)
+        log(f"[bench] {name}, {k} right-hand side(s): {us:.3f} us per dependent level ({n} levels)")
     out["sources_sha"] = kernels_sha()
     print(json.dumps(out), flush=True)
 
