@@ -323,7 +323,7 @@ ddf_status ddf_plan_traffic(ddf_plan_t plan, ddf_op op, int32_t nrhs, int64_t *b
  * schedule.  Valid until the next ddf_autotune or ddf_plan_destroy.
  *   cods   [n_cods][16]  flags, m, nn, row0, row_step, op0, op_step, col0, sigma0, sigma1,
  *                        rows_off, ops_off, cnt_off, xt_off, xp_off, mat
- *   tasks  [n_tasks][4]  codelet, first row, end row, meta (log2 lanes per row | phase << 8 |
+ *   tasks  [n_tasks][4]  codelet, first row, end row, meta (log2 lanes per row |
  *                        streamed << 10 | row ranges << 11 | long row << 12 | row list << 13);
  *                        for SpMV the list used with one right-hand side; for the solve the
  *                        one-launch-per-level schedule, in level order

@@ -57,8 +57,8 @@ struct DCod {
 };
 static_assert(sizeof(DCod) == 64, "DCod layout");
 
-// A wavefront's work item: rows [i0b, i0e) of one codelet; meta = log2(lanes per row) |
-// phase << 8 (phase 1 = second pass of a fused launch).
+// A wavefront's work item: rows [i0b, i0e) of one codelet; meta = log2(lanes per row) and
+// the task-kind bits of the schedule that holds it.
 struct Task {
     int32_t cod, i0b, i0e, meta;
 };

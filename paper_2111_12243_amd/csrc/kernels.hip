@@ -158,8 +158,7 @@ __device__ __forceinline__ DCod load_cod(const DCod *p) { return *p; }
 //    combine their partial sums;
 //  - rhs-lanes (several right-hand sides): KR lanes per row, lane r owns right-hand side r,
 //    so each x row is read as one contiguous 8*k-byte segment and no reduction is needed.
-// VPERM reads values through perm (the transposed plan of the adjoint pass).  Phase-1
-// tasks of a fused adjoint launch compute GV[e] = sum_r G[row, r] X[col, r] instead.
+// VPERM reads values through perm (the transposed plan of the adjoint pass).
 // ------------------------------------------------------------------------------------------
 constexpr int SJ = 8; // elements per lane of a stream task (64 * SJ per task)
 
@@ -397,11 +396,23 @@ __device__ __forceinline__ void spmvN_rect(const SpmvArgs &a, const DCod &c, con
 }
 
 // Rectangular codelet, RV consecutive right-hand sides per lane (vector loads of x and y),
-// KR lanes per row.
-template <int KR, int RV, int MODE, bool VPERM>
-__device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, const Task &tk, int lane) {
+// KR lanes per row.  STG: the codelet's ops are row-major and contiguous (op_step == nn) and
+// P rows of them fit the wave's LDS slice sv: the wave first copies the values of its P rows
+// there with coalesced loads (a row's nn values are nn * 8 bytes apart from the next row's, so
+// direct loads would touch a cache line per row), then reads them from LDS.
+constexpr int SV_CAP = 1024; // doubles of LDS per wave for staged values
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int KR, int RV, int MODE, bool VPERM, bool STG>
+__device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, const Task &tk, int lane, double *sv) {
     static_assert(RV == 2 || RV == 4, "vector width");
     constexpr int P = WAVE / KR;
+    constexpr int SU = SV_CAP / WAVE;
     const int slot = lane / KR, r = (lane % KR) * RV;
     const int k = a.k, nn = c.nn;
     for (int base = tk.i0b; base < tk.i0e; base += P) {
@@ -410,6 +421,21 @@ __device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, c
         const int row = row_of(c, a.aux, i0);
         const int opst = c.op0 + i0 * c.op_step;
         const int cbase = (MODE == XM_FULL) ? c.xt_off + i0 * nn : c.col0 + i0 * c.sigma0;
+        if constexpr (STG) {
+            const int e0 = c.op0 + base * nn, ne = min(P, tk.i0e - base) * nn;
+            double t[SU];
+#pragma unroll
+            for (int u = 0; u < SU; u++) {
+                const int q = lane + u * WAVE;
+                t[u] = q < ne ? val_at<VPERM>(a, e0 + q) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < SU; u++) {
+                const int q = lane + u * WAVE;
+                if (q < ne) sv[q] = t[u];
+            }
+            wave_sync();
+        }
         double acc[RV];
 #pragma unroll
         for (int q = 0; q < RV; q++) acc[q] = 0.0;
@@ -426,7 +452,10 @@ __device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, c
                     col[u] = cbase + a.aux[c.xt_off + j];
                 else
                     col[u] = a.aux[cbase + j];
-                v[u] = val_at<VPERM>(a, opst + j);
+                if constexpr (STG)
+                    v[u] = sv[(i0 - base) * nn + j];
+                else
+                    v[u] = val_at<VPERM>(a, opst + j);
             }
 #pragma unroll
             for (int u = 0; u < RUV; u++) {
@@ -449,6 +478,7 @@ __device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, c
 #pragma unroll
             for (int h = 0; h < RV / 2; h++) yp[h] = make_double2(acc[2 * h], acc[2 * h + 1]);
         }
+        if constexpr (STG) wave_sync();
     }
 }
 
@@ -476,7 +506,7 @@ __device__ __forceinline__ void spmvN_walk(const SpmvArgs &a, const DCod &c, con
 // KR lanes per row; RV > 1: rectangular codelets take RV right-hand sides per lane (k is
 // KR * RV), others one per lane over KW lanes per row
 template <int KR, int RV, int KW, bool VPERM>
-__global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
+__global__ __launch_bounds__(WAVE *WPB, 4) void k_spmvN(SpmvArgs a) {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
     if (t >= a.ntasks) return;
@@ -485,12 +515,21 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmvN(SpmvArgs a) {
     const int mode = xmode(c.flags);
     const bool rect = (c.flags & FRECT) && !(c.flags & DOPS) && c.nn > 0;
     if constexpr (RV > 1) {
-        if (rect && mode == XM_STRIDED)
-            spmvN_rect_v<KR, RV, XM_STRIDED, VPERM>(a, c, tk, lane);
+        __shared__ double sv_all[WPB][SV_CAP];
+        double *sv = sv_all[wave];
+        const bool stg = c.op_step == c.nn && (WAVE / KR) * c.nn <= SV_CAP;
+        if (rect && stg && mode == XM_SHARED)
+            spmvN_rect_v<KR, RV, XM_SHARED, VPERM, true>(a, c, tk, lane, sv);
+        else if (rect && stg && mode == XM_STRIDED)
+            spmvN_rect_v<KR, RV, XM_STRIDED, VPERM, true>(a, c, tk, lane, sv);
+        else if (rect && stg && mode == XM_FULL)
+            spmvN_rect_v<KR, RV, XM_FULL, VPERM, true>(a, c, tk, lane, sv);
+        else if (rect && mode == XM_STRIDED)
+            spmvN_rect_v<KR, RV, XM_STRIDED, VPERM, false>(a, c, tk, lane, sv);
         else if (rect && mode == XM_SHARED)
-            spmvN_rect_v<KR, RV, XM_SHARED, VPERM>(a, c, tk, lane);
+            spmvN_rect_v<KR, RV, XM_SHARED, VPERM, false>(a, c, tk, lane, sv);
         else if (rect && mode == XM_FULL)
-            spmvN_rect_v<KR, RV, XM_FULL, VPERM>(a, c, tk, lane);
+            spmvN_rect_v<KR, RV, XM_FULL, VPERM, false>(a, c, tk, lane, sv);
         else
             spmvN_walk<KW, VPERM>(a, c, tk, lane);
     } else {
@@ -1461,6 +1500,148 @@ template <int KT, bool VEC, bool EXACT> __global__ __launch_bounds__(WAVE *WPB) 
     for (int e = ch.y + lane; e < e1; e += WAVE) a.gv[e] = a.sign * gv_dot<KT, VEC, EXACT>(gw, a.x + (int64_t)a.ci[e] * k, k);
 }
 
+// The SpMV adjoint's value gradient through the forward plan's several-right-hand-side tasks:
+// GV[e] = sign * sum_r G[row, r] X[col, r] for every op e of every codelet (in the forward plan
+// an op's index is its value index).  The lane layout is k_spmvN's: KR lanes per row, RV
+// consecutive right-hand sides per lane, so the x rows of P consecutive rows are read as
+// contiguous 16-byte pieces across the wave, and the KR lanes of a row add their partial dots
+// by cross-lane exchange.  Rectangular codelets with row-major contiguous ops collect their P
+// rows' gradients in LDS and write them with coalesced stores; other codelets write each op's
+// gradient from the row's first lane.  Rows of a wave past the task's end repeat its last row
+// (same values, no stores), which keeps every lane of the exchange active.
+template <int KR> __device__ __forceinline__ double kr_sum(double s) {
+    if constexpr (KR >= 2) s += lane_xor<1>(s);
+    if constexpr (KR >= 4) s += lane_xor<2>(s);
+    if constexpr (KR >= 8) s += lane_xor<4>(s);
+    if constexpr (KR >= 16) s += lane_xor<8>(s);
+    return s;
+}
+
+template <int RV>
+__device__ __forceinline__ double rv_dot(const double (&gw)[RV], const double *__restrict__ xr) {
+    double s = 0.0;
+#pragma unroll
+    for (int h = 0; h < RV / 2; h++) {
+        const double2 q = reinterpret_cast<const double2 *>(xr)[h];
+        s = fma(gw[2 * h], q.x, s);
+        s = fma(gw[2 * h + 1], q.y, s);
+    }
+    return s;
+}
+
+template <int RV> __device__ __forceinline__ void rv_load(const double *__restrict__ gr, double (&gw)[RV]) {
+#pragma unroll
+    for (int h = 0; h < RV / 2; h++) {
+        const double2 q = reinterpret_cast<const double2 *>(gr)[h];
+        gw[2 * h] = q.x;
+        gw[2 * h + 1] = q.y;
+    }
+}
+
+template <int KR, int RV, int MODE, bool STG>
+__device__ __forceinline__ void gv_rect(const GvPlanArgs &a, const DCod &c, const Task &tk, int lane, double *sv) {
+    constexpr int P = WAVE / KR;
+    const int slot = lane / KR, r = (lane % KR) * RV;
+    const int k = a.k, nn = c.nn;
+    for (int base = tk.i0b; base < tk.i0e; base += P) {
+        const int i0 = min(base + slot, tk.i0e - 1);
+        const bool active = base + slot < tk.i0e;
+        const int row = row_of(c, a.aux, i0);
+        const int opst = c.op0 + i0 * c.op_step;
+        const int cbase = (MODE == XM_FULL) ? c.xt_off + i0 * nn : c.col0 + i0 * c.sigma0;
+        double gw[RV];
+        rv_load<RV>(a.g + (int64_t)row * k + r, gw);
+        for (int i1 = 0; i1 < nn; i1 += RUV) {
+            int col[RUV];
+            double2 xv[RUV][RV / 2];
+#pragma unroll
+            for (int u = 0; u < RUV; u++) {
+                const int j = min(i1 + u, nn - 1);
+                if constexpr (MODE == XM_STRIDED)
+                    col[u] = cbase + j * c.sigma1;
+                else if constexpr (MODE == XM_SHARED)
+                    col[u] = cbase + a.aux[c.xt_off + j];
+                else
+                    col[u] = a.aux[cbase + j];
+            }
+#pragma unroll
+            for (int u = 0; u < RUV; u++) {
+                const double2 *xp = reinterpret_cast<const double2 *>(a.x + (int64_t)col[u] * k + r);
+#pragma unroll
+                for (int h = 0; h < RV / 2; h++) xv[u][h] = xp[h];
+            }
+#pragma unroll
+            for (int u = 0; u < RUV; u++) {
+                double d = 0.0;
+#pragma unroll
+                for (int h = 0; h < RV / 2; h++) {
+                    d = fma(gw[2 * h], xv[u][h].x, d);
+                    d = fma(gw[2 * h + 1], xv[u][h].y, d);
+                }
+                d = a.sign * kr_sum<KR>(d);
+                if (i1 + u < nn && r == 0) {
+                    if constexpr (STG)
+                        sv[(i0 - base) * nn + i1 + u] = d;
+                    else if (active)
+                        a.gv[opst + i1 + u] = d;
+                }
+            }
+        }
+        if constexpr (STG) {
+            wave_sync();
+            const int e0 = c.op0 + base * nn, ne = min(P, tk.i0e - base) * nn;
+            for (int q = lane; q < ne; q += WAVE) a.gv[e0 + q] = sv[q];
+            wave_sync();
+        }
+    }
+}
+
+template <int KR, int RV>
+__device__ __forceinline__ void gv_walk(const GvPlanArgs &a, const DCod &c, const Task &tk, int lane) {
+    constexpr int P = WAVE / KR;
+    const int slot = lane / KR, r = (lane % KR) * RV;
+    const int k = a.k;
+    const int mode = xmode(c.flags);
+    for (int base = tk.i0b; base < tk.i0e; base += P) {
+        const int i0 = min(base + slot, tk.i0e - 1);
+        const bool active = base + slot < tk.i0e;
+        const RowInfo ri = row_info(c, a.aux, i0);
+        double gw[RV];
+        rv_load<RV>(a.g + (int64_t)ri.row * k + r, gw);
+        walk_any(mode, c, a.aux, i0, ri, 0, 1, [&](int e, int col) {
+            const double d = a.sign * kr_sum<KR>(rv_dot<RV>(gw, a.x + (int64_t)col * k + r));
+            if (active && r == 0) a.gv[e] = d;
+        });
+    }
+}
+
+template <int KR, int RV> __global__ __launch_bounds__(WAVE *WPB, 4) void k_gv_plan(GvPlanArgs a) {
+    __shared__ double sv_all[WPB][SV_CAP];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
+    if (t >= a.ntasks) return;
+    const Task tk = a.tasks[t];
+    const DCod c = load_cod(a.cods + tk.cod);
+    const int mode = xmode(c.flags);
+    const bool rect = (c.flags & FRECT) && !(c.flags & DOPS) && c.nn > 0;
+    const bool stg = c.op_step == c.nn && (WAVE / KR) * c.nn <= SV_CAP;
+    double *sv = sv_all[wave];
+    if (rect && stg && mode == XM_SHARED)
+        gv_rect<KR, RV, XM_SHARED, true>(a, c, tk, lane, sv);
+    else if (rect && stg && mode == XM_STRIDED)
+        gv_rect<KR, RV, XM_STRIDED, true>(a, c, tk, lane, sv);
+    else if (rect && stg && mode == XM_FULL)
+        gv_rect<KR, RV, XM_FULL, true>(a, c, tk, lane, sv);
+    else if (rect && mode == XM_SHARED)
+        gv_rect<KR, RV, XM_SHARED, false>(a, c, tk, lane, sv);
+    else if (rect && mode == XM_STRIDED)
+        gv_rect<KR, RV, XM_STRIDED, false>(a, c, tk, lane, sv);
+    else if (rect && mode == XM_FULL)
+        gv_rect<KR, RV, XM_FULL, false>(a, c, tk, lane, sv);
+    else
+        gv_walk<KR, RV>(a, c, tk, lane);
+}
+
 // One entry's value gradient in a batch: k of the matrix (at most KT) decides the predicates
 // and the vector loads at run time (matrices of one class differ).
 template <int KT>
@@ -1908,6 +2089,26 @@ hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s) {
     else if (a.k <= 8) launch_gv_vec<8>(a, vec, s);
     else if (a.k <= 16) launch_gv_vec<16>(a, vec, s);
     else launch_gv_vec<32>(a, vec, s);
+    return hipGetLastError();
+}
+
+bool gv_plan_fits(int32_t k, const double *g, const double *x) {
+    const bool al = ((reinterpret_cast<uintptr_t>(g) | reinterpret_cast<uintptr_t>(x)) & 15) == 0;
+    return al && (k == 2 || k == 4 || k == 8 || k == 16 || k == 32);
+}
+
+hipError_t launch_gv_plan(const GvPlanArgs &a, hipStream_t s) {
+    const int nb = (a.ntasks + WPB - 1) / WPB;
+    if (nb == 0) return hipSuccess;
+    const dim3 grid(nb), block(WAVE * WPB);
+    switch (a.k) {
+    case 2: hipLaunchKernelGGL((k_gv_plan<1, 2>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_gv_plan<1, 4>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_gv_plan<2, 4>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_gv_plan<4, 4>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_gv_plan<8, 4>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -175,6 +175,19 @@ struct GvArgs {
     const int2 *chunks; // (row, first entry) of the chunks of rows longer than GV_LONG_ROW
     int64_t n_chunks;
 };
+// Value gradient of the SpMV adjoint through the forward plan's several-right-hand-side tasks.
+struct GvPlanArgs {
+    const DCod *cods;
+    const int32_t *aux;
+    const Task *tasks;
+    int32_t ntasks;
+    int32_t k;
+    int32_t remap;
+    const double *g;
+    const double *x;
+    double *gv;
+    double sign;
+};
 // Value gradient of a batch adjoint, one launch per class of right-hand-side counts (k up to
 // KT, a power of two): the class's rows are its matrices' rows, matrix after matrix; row q of
 // the class is row q - mstart[j] of matrix mids[j] (mstart ascending, one more entry at the
@@ -245,6 +258,9 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_gather(double *dst, const double *src, const int32_t *idx, int64_t n, hipStream_t s);
 hipError_t launch_plain(PlainKind which, PlainArgs a, double avg_row, int kt, hipStream_t s);
 hipError_t launch_gv(GvArgs a, double avg_short_row, hipStream_t s);
+// k in {2, 4, 8, 16, 32} and g, x 16-byte aligned
+bool gv_plan_fits(int32_t k, const double *g, const double *x);
+hipError_t launch_gv_plan(const GvPlanArgs &a, hipStream_t s);
 hipError_t launch_gv_batch_class(GvBatchArgs a, int kt, double avg_short_row, hipStream_t s);
 
 } // namespace ddf

@@ -285,7 +285,7 @@ int lg_of(int64_t n, int opl) {
 
 // Tasks of one codelet: rows grouped so that a task's lanes-per-row fits its rows.
 void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_index, const SchedParams &sp,
-                   int phase, std::vector<Task> &out) {
+                   std::vector<Task> &out) {
     const int32_t m = d.m;
     auto nops_of = [&](int32_t a) -> int64_t { return (d.flags & FRECT) ? d.nn : aux[d.cnt_off + a]; };
     int32_t a = 0;
@@ -300,7 +300,7 @@ void codelet_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_i
             lg = lgn;
             b++;
         }
-        out.push_back({cod_index, a, b, lg | (phase << 8)});
+        out.push_back({cod_index, a, b, lg});
         a = b;
     }
 }
@@ -319,7 +319,7 @@ void spmv1_tasks(const DCod &d, const std::vector<int32_t> &aux, int32_t cod_ind
                  std::vector<Task> &out) {
     const bool stream = stream_cod(d);
     if (!stream) {
-        codelet_tasks(d, aux, cod_index, sp, 0, out);
+        codelet_tasks(d, aux, cod_index, sp, out);
         return;
     }
     // the kernel sums one row per lane: at most 64 rows, and at most STREAM_ELEMS elements
@@ -472,7 +472,7 @@ std::vector<std::pair<int64_t, int64_t>> build_solve(const DevTables &D, const s
         per[b].resize(nl);
         maxl = std::max(maxl, nl);
         for (int64_t c = cod_begin[b]; c < cod_begin[b + 1]; c++)
-            codelet_tasks(D.cods[c], D.aux, (int32_t)c, sp, 0, per[b][levels[b][c - cod_begin[b]]]);
+            codelet_tasks(D.cods[c], D.aux, (int32_t)c, sp, per[b][levels[b][c - cod_begin[b]]]);
         base[b] = counter_base;
         counter_base += nl;
     }
@@ -1045,7 +1045,7 @@ ddf_status build_slices(ddf_plan_t p) {
     for (size_t i = 0; i < D.cods.size(); i++) {
         const int64_t lev = c.codelets[i * NCOD + C_PART];
         while ((int64_t)p->sl_lvl.size() <= lev) p->sl_lvl.push_back((int64_t)D.tasks.size());
-        codelet_tasks(D.cods[i], D.aux, (int32_t)i, p->sp_f, 0, D.tasks);
+        codelet_tasks(D.cods[i], D.aux, (int32_t)i, p->sp_f, D.tasks);
         rows.clear();
         cod_rows(D.cods[i], D.aux, rows);
         for (int32_t r : rows) need[r]++;
@@ -1862,7 +1862,22 @@ ddf_status ddf_spmv_adjoint(ddf_plan_t p, const double *d_vals, const double *d_
     hipStream_t s = (hipStream_t)stream;
     const bool many = nrhs > 1;
     const int64_t ngx = many ? p->n_gx_tasksN : p->n_gx_tasks;
-    if (d_gvals) HIPCHK(launch_gv_pass(p, d_gy, d_x, d_gvals, 1.0, nrhs, s));
+    if (d_gvals && many && gv_plan_fits(nrhs, d_gy, d_x)) {
+        GvPlanArgs g{};
+        g.cods = p->F.d_cods;
+        g.aux = p->F.d_aux;
+        g.tasks = p->F.d_tasksN;
+        g.ntasks = (int32_t)p->F.tasksN.size();
+        g.k = nrhs;
+        g.remap = p->sp_f.remap;
+        g.g = d_gy;
+        g.x = d_x;
+        g.gv = d_gvals;
+        g.sign = 1.0;
+        HIPCHK(launch_gv_plan(g, s));
+    } else if (d_gvals) {
+        HIPCHK(launch_gv_pass(p, d_gy, d_x, d_gvals, 1.0, nrhs, s));
+    }
     if (!d_gx || ngx == 0) return DDF_OK;
     SpmvArgs a{};
     a.cods = p->T.d_cods;
