@@ -204,6 +204,15 @@ def test_value_gradient_vector_rhs(k):
     sptrsv_case(I.random_lower(700, 80 + k, density=0.05, runs=True), k, 80 + k, plain=False)
 
 
+@pytest.mark.parametrize("k", [2, 4, 16, 32])
+def test_stencil_rhs_counts(k):
+    # rectangular shared-offset codelets at every vector right-hand-side count: values staged
+    # in LDS where a wave's rows fit (k = 16, 32) and read directly where they do not (k = 2,
+    # 4: 64 rows of 27 ops), in the product and in the adjoint's value gradient
+    A = I.laplacian(21, 9, 7, I.OFFS_27PT, 26.0)
+    spmv_case(A, k, 90 + k, plain=False)
+
+
 # ---------------------------------------------------------------- scaled workloads
 
 def test_c2_scaled():
