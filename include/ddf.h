@@ -222,8 +222,10 @@ ddf_status ddf_sptrsv_v(ddf_plan_t plan, const double *d_vals, const double *d_b
 /* SpMV adjoint for upstream d_gy = dLoss/dY (n_rows, nrhs):
  *   d_gx    (n_cols, nrhs) = A^T G   (transposed plan, deterministic, no atomics)
  *   d_gvals [nnz]          = sum_r G[i,r] X[col,r]  (dLoss/dA_ij = g_i x_j)
- * Either output may be NULL.  Two launches: the value gradient over the CSR pattern, then the
- * transposed product.  Needs build_adjoint. */
+ * Either output may be NULL.  Two launches: the value gradient, then the transposed product.
+ * The value gradient runs over the forward plan's codelets (every op once, in the product's
+ * lane layout) when nrhs is 2, 4, 8, 16 or 32 and d_gy, d_x are 16-byte aligned, otherwise
+ * over the CSR pattern.  Needs build_adjoint. */
 ddf_status ddf_spmv_adjoint(ddf_plan_t plan, const double *d_vals, const double *d_x,
                             const double *d_gy, double *d_gx, double *d_gvals, int32_t nrhs,
                             ddf_stream_t stream);

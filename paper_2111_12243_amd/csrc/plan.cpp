@@ -2311,9 +2311,13 @@ ddf_status ddf_plan_traffic(ddf_plan_t p, ddf_op op, int32_t nrhs, int64_t *byte
         fl = 2 * nnz * nrhs;
         break;
     case DDF_OP_SPMV_ADJ:
-        // transposed product: values through perm; value gradient over the CSR pattern
-        ba = 24 * nnz + (p->has_adj ? (many ? p->T.launch_bytes(true) : p->T.table_bytes1) : 0) + 4 * (n + 1) +
-             16 * vk + 16 * ck;
+        // transposed product: values through perm; value gradient over the CSR pattern, or with
+        // 2, 4, 8, 16 or 32 right-hand sides over the forward plan's tasks
+        if (many && (nrhs & (nrhs - 1)) == 0 && nrhs <= 32)
+            ba = 20 * nnz + (p->has_adj ? p->T.launch_bytes(true) : 0) + p->F.launch_bytes(true) + 16 * vk + 16 * ck;
+        else
+            ba = 24 * nnz + (p->has_adj ? (many ? p->T.launch_bytes(true) : p->T.table_bytes1) : 0) + 4 * (n + 1) +
+                 16 * vk + 16 * ck;
         bc = 20 * nnz + 4 * (n + 1) + 8 * vk + 16 * ck;
         fl = 2 * nnz * nrhs + nnz * (2 * nrhs - 1);
         break;
