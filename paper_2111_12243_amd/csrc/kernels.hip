@@ -354,9 +354,9 @@ __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
 
 // several right-hand sides: KR lanes per row, lane r owns right-hand sides r, r + KR, ...
 constexpr int RU = 4;  // ops per unrolled chunk of a rectangular row (one RHS per lane)
-// the same with RV right-hand sides per lane (16-byte loads): 7 loads no operand in vain on
-// 7-point rows and one on 27-point rows (27-point Laplacian on 170^3, 8 right-hand sides:
-// 0.78 ms with 8, 0.74 with 6, 0.72 with 7)
+// the same with RV right-hand sides per lane (16-byte loads); a chunk past the row's end
+// repeats its last operand, so 7 wastes no load on 7-point rows and one on 27-point rows
+// (27-point Laplacian on 170^3, 8 right-hand sides: 0.78 ms with 8, 0.74 with 6, 0.72 with 7)
 constexpr int RUV = 7;
 
 template <int KR, int MODE, bool VPERM>
