@@ -846,6 +846,22 @@ __device__ __forceinline__ void df_long(const SolveArgs &a, const Task &tk, cons
     }
 }
 
+// Task list entries and codelet copies through the constant address space: scalar loads where
+// the index is wave-uniform (16-byte vectors, since structs cannot be copied out of that space).
+typedef int dfv4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) dfv4 *const_v4_ptr;
+
+__device__ __forceinline__ Task k_task(const Task *tasks, int i) {
+    const dfv4 v = ((const_v4_ptr)tasks)[i];
+    return Task{v.x, v.y, v.z, v.w};
+}
+
+__device__ __forceinline__ DCod k_cod(const DCod *cods, int i) {
+    const const_v4_ptr p = (const_v4_ptr)cods + 4 * (int64_t)i;
+    const dfv4 a = p[0], b = p[1], c = p[2], d = p[3];
+    return DCod{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+}
+
 // One pass of a wave: rows of W consecutive tasks, KR lanes per row, lane r owning right-hand
 // sides r, r + KR, ...  VPERM: the values through perm (the transposed solve reads L's values
 // in U's order).  A pass whose first task is a wide-row task runs that task alone.
@@ -857,15 +873,20 @@ __device__ __forceinline__ int df_pass(const SolveArgs &a, int p, int pn, int la
     // the first task tells which kind of pass this is); and the same lines of the wave's next
     // pass (pn, when known), touched so that they are in the caches when it starts: the sum
     // returned keeps those loads
-    const int t = p * W + slot / DF_RG, i = slot % DF_RG;
-    const int tc = min(t, a.ntasks - 1);
-    const Task head = a.tasks[p * W];
-    const Task tk = a.tasks[tc];
-    DCod c = a.tcods[tc];
+    // (pass indices are wave-uniform; with one task per pass, W = 1, so are the task's and the
+    // touched next task's indices, and both are read through the constant address space: scalar
+    // loads, served by the scalar cache)
+    const int pu = __builtin_amdgcn_readfirstlane(p);
+    const int t = pu * W + slot / DF_RG, i = slot % DF_RG;
+    const int tc = W == 1 ? min(pu, a.ntasks - 1) : min(t, a.ntasks - 1);
+    const Task head = k_task(a.tasks, pu * W);
+    const Task tk = k_task(a.tasks, tc);
+    DCod c = k_cod(a.tcods, tc);
     int touch = 0;
     if (pn >= 0 && pn < a.npass) {
-        const int tn = min(pn * W + slot / DF_RG, a.ntasks - 1);
-        touch = a.tasks[tn].meta + a.tcods[tn].flags;
+        const int pnu = __builtin_amdgcn_readfirstlane(pn);
+        const int tn = W == 1 ? min(pnu, a.ntasks - 1) : min(pnu * W + slot / DF_RG, a.ntasks - 1);
+        touch = k_task(a.tasks, tn).meta + k_cod(a.tcods, tn).flags;
     }
     // a wide-row task runs alone; a pass that starts with an empty task is all empty (empty
     // tasks fill a group of DF_PASS_MAX up to its end)

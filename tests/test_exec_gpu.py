@@ -213,6 +213,42 @@ def test_stencil_rhs_counts(k):
     spmv_case(A, k, 90 + k, plain=False)
 
 
+def off16(a):
+    """Device copy of a whose first element sits 8 bytes past a 16-byte boundary."""
+    buf = torch.empty(a.size + 1, dtype=torch.float64, device=DEV)
+    v = buf[1:]
+    v.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()))
+    assert v.data_ptr() % 16 == 8
+    return v.view(a.shape)
+
+
+@pytest.mark.parametrize("k", [2, 8])
+def test_unaligned_vectors(k):
+    # x, y, g and the outputs off 16-byte boundaries: the product takes one right-hand side per
+    # lane instead of 16-byte pieces, and the value gradient runs over the CSR pattern instead
+    # of the plan; the solve and its adjoint on unaligned vectors too
+    A = I.laplacian(13, 7, 5, I.OFFS_27PT, 26.0)
+    plan = ddf.ddf_inspect(0, A)
+    X, G = rnd((A.n_cols, k), 95), rnd((A.n_rows, k), 96)
+    x, g = off16(X), off16(G)
+    y = off16(np.full((A.n_rows, k), np.nan))
+    ddf.ddf_spmv(plan, x, y, k)
+    check_product(A, X, host(y), O.spmv(A, X))
+    GX, GV = O.spmv_adj(A, X, G)
+    gx = off16(np.full((A.n_cols, k), np.nan))
+    gv = off16(np.full(A.nnz, np.nan))
+    ddf.ddf_spmv_adjoint(plan, dev(A.values), x, g, gx, gv, k)
+    AT, _ = O.transpose(A)
+    check_product(AT, G, host(gx), GX)
+    check_gv(A, X, G, host(gv), GV)
+    L = I.tril(A)
+    lp = ddf.ddf_inspect(1, L)
+    B = rnd((L.n_rows, k), 97)
+    xs = off16(np.full((L.n_rows, k), np.nan))
+    ddf.ddf_sptrsv(lp, off16(B), xs, k)
+    check_solve(L, B, host(xs), O.sptrsv(L, B))
+
+
 # ---------------------------------------------------------------- scaled workloads
 
 def test_c2_scaled():
