@@ -850,6 +850,7 @@ __device__ __forceinline__ void df_long(const SolveArgs &a, const Task &tk, cons
 // the index is wave-uniform (16-byte vectors, since structs cannot be copied out of that space).
 typedef int dfv4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) dfv4 *const_v4_ptr;
+typedef const __attribute__((address_space(4))) int *const_i32k_ptr;
 
 __device__ __forceinline__ Task k_task(const Task *tasks, int i) {
     const dfv4 v = ((const_v4_ptr)tasks)[i];
@@ -862,42 +863,17 @@ __device__ __forceinline__ DCod k_cod(const DCod *cods, int i) {
     return DCod{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
 }
 
-// One pass of a wave: rows of W consecutive tasks, KR lanes per row, lane r owning right-hand
-// sides r, r + KR, ...  VPERM: the values through perm (the transposed solve reads L's values
-// in U's order).  A pass whose first task is a wide-row task runs that task alone.
-template <int KR, bool ADJ, bool VPERM>
-__device__ __forceinline__ int df_pass(const SolveArgs &a, int p, int pn, int lane) {
+// The rows of one pass (df_pass): MIX, a mixed task whose row slots name their own codelets;
+// otherwise the slots' tasks, whose codelet record, with one task per pass, is wave-uniform.
+template <int KR, bool ADJ, bool VPERM, bool MIX>
+__device__ __forceinline__ void df_rows(const SolveArgs &a, const Task &head, const Task &tk, DCod c, int t, int i,
+                                        int lane) {
     constexpr int P = WAVE / KR, W = P / DF_RG;
+    constexpr bool UNI = !MIX && W == 1;
     const int slot = lane / KR, r = lane % KR;
-    // the pass's first task, and each slot's task and codelet record, loaded together (before
-    // the first task tells which kind of pass this is); and the same lines of the wave's next
-    // pass (pn, when known), touched so that they are in the caches when it starts: the sum
-    // returned keeps those loads
-    // (pass indices are wave-uniform; with one task per pass, W = 1, so are the task's and the
-    // touched next task's indices, and both are read through the constant address space: scalar
-    // loads, served by the scalar cache)
-    const int pu = __builtin_amdgcn_readfirstlane(p);
-    const int t = pu * W + slot / DF_RG, i = slot % DF_RG;
-    const int tc = W == 1 ? min(pu, a.ntasks - 1) : min(t, a.ntasks - 1);
-    const Task head = k_task(a.tasks, pu * W);
-    const Task tk = k_task(a.tasks, tc);
-    DCod c = k_cod(a.tcods, tc);
-    int touch = 0;
-    if (pn >= 0 && pn < a.npass) {
-        const int pnu = __builtin_amdgcn_readfirstlane(pn);
-        const int tn = W == 1 ? min(pnu, a.ntasks - 1) : min(pnu * W + slot / DF_RG, a.ntasks - 1);
-        touch = k_task(a.tasks, tn).meta + k_cod(a.tcods, tn).flags;
-    }
-    // a wide-row task runs alone; a pass that starts with an empty task is all empty (empty
-    // tasks fill a group of DF_PASS_MAX up to its end)
-    if (head.meta & DF_LONG) {
-        df_long<ADJ, VPERM>(a, head, a.tcods[p * W], lane);
-        return touch;
-    }
-    if (head.i0e == head.i0b) return touch;
     int i0;
     bool active;
-    if (KR == DF_RG && (head.meta & DF_MIXED)) {
+    if constexpr (MIX) {
         // a mixed task (one task per pass): row slot s is (codelet, row) slots[i0b + s]
         active = slot < head.i0e - head.i0b;
         const int2 sl = a.slots[head.i0b + (active ? slot : 0)];
@@ -932,6 +908,11 @@ __device__ __forceinline__ int df_pass(const SolveArgs &a, int p, int pn, int la
         it.mode = XM_STRIDED; // lanes without a row read no table
         it.base = 0;
         if (active) it.init(c, a.aux, i0, ri);
+        // one task per pass and a rectangular codelet with a shared column table: every row has
+        // nn ops, so an op's offset in the table is the same in every lane with a row and is read
+        // with a scalar load
+        const bool kshared = UNI && (c.flags & FRECT) && !(c.flags & DOPS) && xmode(c.flags) == XM_SHARED;
+        const int cb = c.col0 + i0 * c.sigma0;
         const bool one_chunk = !__ballot(nops > DF_U);
         double acc = 0.0;
         bool pend = mine; // one chunk: the row's result is not stored yet
@@ -942,7 +923,13 @@ __device__ __forceinline__ int df_pass(const SolveArgs &a, int p, int pn, int la
             for (int u = 0; u < DF_U; u++) {
                 const bool ok = i1 + u < nops;
                 const int op = ADJ ? nops - 1 - (i1 + u) : i1 + u;
-                col[u] = ok ? it.col(c, op) : 0;
+                if (UNI && kshared) {
+                    const int opu = min(ADJ ? c.nn - 1 - (i1 + u) : i1 + u, c.nn - 1);
+                    const int xo = ((const_i32k_ptr)a.aux)[c.xt_off + max(opu, 0)];
+                    col[u] = ok ? cb + xo : 0;
+                } else {
+                    col[u] = ok ? it.col(c, op) : 0;
+                }
                 const int e = ri.opst + op;
                 v[u] = ok ? (VPERM ? vals[perm[e]] : vals[e]) : 0.0;
             }
@@ -986,6 +973,45 @@ __device__ __forceinline__ int df_pass(const SolveArgs &a, int p, int pn, int la
             cstore(x + o, res);
         }
     }
+}
+
+// One pass of a wave: rows of W consecutive tasks, KR lanes per row, lane r owning right-hand
+// sides r, r + KR, ...  VPERM: the values through perm (the transposed solve reads L's values
+// in U's order).  A pass whose first task is a wide-row task runs that task alone.
+template <int KR, bool ADJ, bool VPERM>
+__device__ __forceinline__ int df_pass(const SolveArgs &a, int p, int pn, int lane) {
+    constexpr int P = WAVE / KR, W = P / DF_RG;
+    const int slot = lane / KR, r = lane % KR;
+    // the pass's first task, and each slot's task and codelet record, loaded together (before
+    // the first task tells which kind of pass this is); and the same lines of the wave's next
+    // pass (pn, when known), touched so that they are in the caches when it starts: the sum
+    // returned keeps those loads
+    // (pass indices are wave-uniform; with one task per pass, W = 1, so are the task's and the
+    // touched next task's indices, and both are read through the constant address space: scalar
+    // loads, served by the scalar cache)
+    const int pu = __builtin_amdgcn_readfirstlane(p);
+    const int t = pu * W + slot / DF_RG, i = slot % DF_RG;
+    const int tc = W == 1 ? min(pu, a.ntasks - 1) : min(t, a.ntasks - 1);
+    const Task head = k_task(a.tasks, pu * W);
+    const Task tk = k_task(a.tasks, tc);
+    DCod c = k_cod(a.tcods, tc);
+    int touch = 0;
+    if (pn >= 0 && pn < a.npass) {
+        const int pnu = __builtin_amdgcn_readfirstlane(pn);
+        const int tn = W == 1 ? min(pnu, a.ntasks - 1) : min(pnu * W + slot / DF_RG, a.ntasks - 1);
+        touch = k_task(a.tasks, tn).meta + k_cod(a.tcods, tn).flags;
+    }
+    // a wide-row task runs alone; a pass that starts with an empty task is all empty (empty
+    // tasks fill a group of DF_PASS_MAX up to its end)
+    if (head.meta & DF_LONG) {
+        df_long<ADJ, VPERM>(a, head, a.tcods[p * W], lane);
+        return touch;
+    }
+    if (head.i0e == head.i0b) return touch;
+    if (KR == DF_RG && (head.meta & DF_MIXED))
+        df_rows<KR, ADJ, VPERM, true>(a, head, tk, c, t, i, lane);
+    else
+        df_rows<KR, ADJ, VPERM, false>(a, head, tk, c, t, i, lane);
     return touch;
 }
 
