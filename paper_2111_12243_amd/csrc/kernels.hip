@@ -149,6 +149,24 @@ __device__ __forceinline__ int xcd_block(int b, int nb, int remap) {
 
 __device__ __forceinline__ DCod load_cod(const DCod *p) { return *p; }
 
+// Task list entries and codelet copies through the constant address space: scalar loads where
+// the index is wave-uniform (16-byte vectors, since structs cannot be copied out of that space).
+typedef int dfv4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) dfv4 *const_v4_ptr;
+typedef const __attribute__((address_space(4))) int *const_i32k_ptr;
+
+__device__ __forceinline__ Task k_task(const Task *tasks, int i) {
+    const dfv4 v = ((const_v4_ptr)tasks)[i];
+    return Task{v.x, v.y, v.z, v.w};
+}
+
+__device__ __forceinline__ DCod k_cod(const DCod *cods, int i) {
+    const const_v4_ptr p = (const_v4_ptr)cods + 4 * (int64_t)i;
+    const dfv4 a = p[0], b = p[1], c = p[2], d = p[3];
+    return DCod{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+}
+
+
 // ------------------------------------------------------------------------------------------
 // SpMV executor.  Three task shapes, chosen per task by the scheduler:
 //  - stream (one right-hand side, rectangular codelet with contiguous values): the task's
@@ -382,7 +400,7 @@ __device__ __forceinline__ void spmvN_rect(const SpmvArgs &a, const DCod &c, con
                     if constexpr (MODE == XM_STRIDED)
                         col[u] = cbase + j * c.sigma1;
                     else if constexpr (MODE == XM_SHARED)
-                        col[u] = cbase + a.aux[c.xt_off + j];
+                        col[u] = cbase + ((const_i32k_ptr)a.aux)[c.xt_off + j];
                     else
                         col[u] = a.aux[cbase + j];
                     v[u] = val_at<VPERM>(a, opst + j);
@@ -452,7 +470,7 @@ __device__ __forceinline__ void spmvN_rect_v(const SpmvArgs &a, const DCod &c, c
                 if constexpr (MODE == XM_STRIDED)
                     col[u] = cbase + j * c.sigma1;
                 else if constexpr (MODE == XM_SHARED)
-                    col[u] = cbase + a.aux[c.xt_off + j];
+                    col[u] = cbase + ((const_i32k_ptr)a.aux)[c.xt_off + j];
                 else
                     col[u] = a.aux[cbase + j];
                 if constexpr (STG)
@@ -511,10 +529,12 @@ __device__ __forceinline__ void spmvN_walk(const SpmvArgs &a, const DCod &c, con
 template <int KR, int RV, int KW, bool VPERM>
 __global__ __launch_bounds__(WAVE *WPB, 4) void k_spmvN(SpmvArgs a) {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
+    // a task per wave: its index is wave-uniform, the task and its codelet record come with
+    // scalar loads, and so do the codelet's shared column offsets
+    const int t = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave);
     if (t >= a.ntasks) return;
-    const Task tk = a.tasks[t];
-    const DCod c = load_cod(a.cods + tk.cod);
+    const Task tk = k_task(a.tasks, t);
+    const DCod c = k_cod(a.cods, tk.cod);
     const int mode = xmode(c.flags);
     const bool rect = (c.flags & FRECT) && !(c.flags & DOPS) && c.nn > 0;
     if constexpr (RV > 1) {
@@ -844,23 +864,6 @@ __device__ __forceinline__ void df_long(const SolveArgs &a, const Task &tk, cons
             cstore(x + (int64_t)ri.row * k + rr, res);
         }
     }
-}
-
-// Task list entries and codelet copies through the constant address space: scalar loads where
-// the index is wave-uniform (16-byte vectors, since structs cannot be copied out of that space).
-typedef int dfv4 __attribute__((ext_vector_type(4)));
-typedef const __attribute__((address_space(4))) dfv4 *const_v4_ptr;
-typedef const __attribute__((address_space(4))) int *const_i32k_ptr;
-
-__device__ __forceinline__ Task k_task(const Task *tasks, int i) {
-    const dfv4 v = ((const_v4_ptr)tasks)[i];
-    return Task{v.x, v.y, v.z, v.w};
-}
-
-__device__ __forceinline__ DCod k_cod(const DCod *cods, int i) {
-    const const_v4_ptr p = (const_v4_ptr)cods + 4 * (int64_t)i;
-    const dfv4 a = p[0], b = p[1], c = p[2], d = p[3];
-    return DCod{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
 }
 
 // The rows of one pass (df_pass): MIX, a mixed task whose row slots name their own codelets;
@@ -1610,7 +1613,7 @@ __device__ __forceinline__ void gv_rect(const GvPlanArgs &a, const DCod &c, cons
                 if constexpr (MODE == XM_STRIDED)
                     col[u] = cbase + j * c.sigma1;
                 else if constexpr (MODE == XM_SHARED)
-                    col[u] = cbase + a.aux[c.xt_off + j];
+                    col[u] = cbase + ((const_i32k_ptr)a.aux)[c.xt_off + j];
                 else
                     col[u] = a.aux[cbase + j];
             }
@@ -1668,10 +1671,10 @@ __device__ __forceinline__ void gv_walk(const GvPlanArgs &a, const DCod &c, cons
 template <int KR, int RV> __global__ __launch_bounds__(WAVE *WPB, 4) void k_gv_plan(GvPlanArgs a) {
     __shared__ double sv_all[WPB][SV_CAP];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
+    const int t = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave);
     if (t >= a.ntasks) return;
-    const Task tk = a.tasks[t];
-    const DCod c = load_cod(a.cods + tk.cod);
+    const Task tk = k_task(a.tasks, t);
+    const DCod c = k_cod(a.cods, tk.cod);
     const int mode = xmode(c.flags);
     const bool rect = (c.flags & FRECT) && !(c.flags & DOPS) && c.nn > 0;
     const bool stg = c.op_step == c.nn && (WAVE / KR) * c.nn <= SV_CAP;
