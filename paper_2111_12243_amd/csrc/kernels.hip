@@ -237,8 +237,8 @@ __device__ __forceinline__ void spmv_stream_body(const SpmvArgs &a, const DCod &
 }
 
 template <bool VPERM>
-__device__ void spmv_stream_task(const SpmvArgs &a, const Task &tk, int lane, double *__restrict__ lds) {
-    const DCod c = load_cod(a.cods + tk.cod);
+__device__ __forceinline__ void spmv_stream_task(const SpmvArgs &a, const Task &tk, int lane, double *__restrict__ lds) {
+    const DCod c = k_cod(a.cods, tk.cod);
     const int mode = xmode(c.flags);
     if (mode == XM_STRIDED)
         spmv_stream_body<XM_STRIDED, VPERM>(a, c, tk.i0b, tk.i0e - tk.i0b, lane, lds);
@@ -249,8 +249,8 @@ __device__ void spmv_stream_task(const SpmvArgs &a, const Task &tk, int lane, do
 }
 
 template <bool VPERM>
-__device__ void spmv_group_task(const SpmvArgs &a, const Task &tk, int lane) {
-    const DCod c = load_cod(a.cods + tk.cod);
+__device__ __forceinline__ void spmv_group_task(const SpmvArgs &a, const Task &tk, int lane) {
+    const DCod c = k_cod(a.cods, tk.cod);
     const int lg = tk.meta & 7, G = 1 << lg, R = WAVE >> lg;
     const int slot = lane >> lg, g = lane & (G - 1);
     const int mode = xmode(c.flags);
@@ -357,9 +357,9 @@ template <bool VPERM>
 __global__ __launch_bounds__(WAVE *WPB) void k_spmv1(SpmvArgs a) {
     __shared__ double lds_all[WPB][WAVE * SJ];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int t = xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave;
+    const int t = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x, a.remap) * WPB + wave);
     if (t >= a.ntasks) return;
-    const Task tk = a.tasks[t];
+    const Task tk = k_task(a.tasks, t);
     if (tk.meta & TASK_CSR)
         spmv_csr_task<VPERM>(a, tk, lane, lds_all[wave]);
     else if (tk.meta & TASK_ROWS)
