@@ -213,6 +213,16 @@ def test_stencil_rhs_counts(k):
     spmv_case(A, k, 90 + k, plain=False)
 
 
+@pytest.mark.parametrize("k", [4, 8])
+def test_stencil_factor_uniform_passes(k):
+    # stencil factors whose rows are rectangular shared-offset codelets of 3 and 13 ops: with 8
+    # right-hand sides each pass holds one task and reads its codelet and column offsets with
+    # scalar loads (forward and transposed), with 4 a pass spans two tasks
+    offs7 = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    sptrsv_case(I.tril(I.laplacian(11, 9, 13, offs7, 6.0)), k, 110 + k, plain=False)
+    sptrsv_case(I.tril(I.laplacian(17, 6, 9, I.OFFS_27PT, 26.0)), k, 120 + k, plain=False)
+
+
 def off16(a):
     """Device copy of a whose first element sits 8 bytes past a 16-byte boundary."""
     buf = torch.empty(a.size + 1, dtype=torch.float64, device=DEV)
