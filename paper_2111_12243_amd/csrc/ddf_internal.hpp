@@ -96,6 +96,11 @@ struct DevTables {
     int32_t *d_df_lcols = nullptr;
     std::vector<int32_t> df_slots;     // (codelet, row) of the dataflow solve's mixed-task row slots
     int32_t *d_df_slots = nullptr;
+    // device-only form of a batch's mixed-task row slots: per slot four int32 (first value
+    // index | (k - 1) << 27, first element of the row in x, offset in df_mcols | ops << 27, the
+    // matrix's first value index) and the rows' operand elements (vector base + column * k)
+    std::vector<int32_t> df_mdesc, df_mcols;
+    int32_t *d_df_mdesc = nullptr, *d_df_mcols = nullptr;
     int64_t n_counters = 0;            // solve: level counters of the sync protocol (CPU replay)
     int64_t csr_rows = 0, csr_nnz = 0; // SpMV, one right-hand side: rows run from the CSR pattern
     int64_t table_bytes1 = 0;          // plan bytes a one-RHS SpMV launch reads
@@ -143,7 +148,7 @@ struct DevTables {
     // plan bytes the dataflow solve reads: each task and its codelet copy, and aux
     int64_t df_read_bytes() const {
         return (int64_t)aux.size() * 4 + (int64_t)df_tasks.size() * (sizeof(Task) + sizeof(DCod)) +
-               (int64_t)(df_lcols.size() + df_slots.size()) * 4;
+               (int64_t)(df_lcols.size() + (df_mdesc.empty() ? df_slots.size() : df_mdesc.size() + df_mcols.size())) * 4;
     }
     // plan bytes a single-block solve reads per call: gather index, level table, rows
     int64_t thin_bytes() const {

@@ -978,6 +978,68 @@ __device__ __forceinline__ void df_rows(const SolveArgs &a, const Task &head, co
     }
 }
 
+// A mixed task's rows (batches) from their slot descriptors: a row's first value index,
+// right-hand-side count, output element, ops and operand elements come from one 16-byte record
+// and a list of absolute operand elements, instead of from its codelet record, its matrix's
+// bases and the codelet's column tables, which shortens the pass's chain of dependent loads.
+// A mixed row has at most DF_U ops, so its ops are one chunk.
+constexpr int DF_MD_MASK = (1 << 27) - 1;
+
+template <int KR, bool ADJ, bool VPERM>
+__device__ __forceinline__ void df_mixed(const SolveArgs &a, const Task &head, int lane) {
+    const int slot = lane / KR, r = lane % KR;
+    const bool active = slot < head.i0e - head.i0b;
+    const int4 d = a.mdesc[head.i0b + (active ? slot : 0)];
+    const int e0 = d.x & DF_MD_MASK, k = (int)((unsigned)d.x >> 27) + 1;
+    const int coff = d.z & DF_MD_MASK, rn = active ? (int)((unsigned)d.z >> 27) : 0;
+    const int64_t rowel = d.y;
+    const double *__restrict__ vals = a.vals + (VPERM ? d.w : 0);
+    double diag = 1.0;
+    if (active) {
+        const int dpos = ADJ ? e0 - 1 : e0 + rn;
+        diag = VPERM ? vals[a.perm[dpos]] : vals[dpos];
+    }
+    unsigned *err = a.err ? a.err : a.ctr + CTR_STRIDE;
+    for (int r0 = 0; r0 < k; r0 += KR) { // a lane's own row sets k
+        const int rr = r0 + r;
+        const bool mine = active && rr < k;
+        const int nops = mine ? rn : 0;
+        const int64_t o = rowel + rr;
+        double v[DF_U], xv[DF_U];
+        int col[DF_U];
+#pragma unroll
+        for (int u = 0; u < DF_U; u++) {
+            const bool ok = u < nops;
+            const int op = ADJ ? nops - 1 - u : u;
+            col[u] = ok ? a.mcols[coff + op] : 0;
+            v[u] = ok ? (VPERM ? vals[a.perm[e0 + op]] : vals[e0 + op]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < DF_U; u++) xv[u] = u < nops ? wload(a.x + (int64_t)col[u] + rr) : 0.0;
+        const double bo = mine ? a.b[o] : 0.0;
+        int64_t spins = 0;
+        int back = 1;
+        bool pend = mine;
+        for (;;) {
+            bool miss = false;
+#pragma unroll
+            for (int u = 0; u < DF_U; u++) miss = miss || df_missing(xv[u]);
+            if (pend && !miss) {
+                df_finish<DF_U>(v, xv, 0.0, bo, diag, a.x + o);
+                pend = false;
+            }
+            if (!__ballot(pend)) break;
+            if (!df_backoff<DF_U>(a, spins, back, err)) {
+                // past the watchdog: the results are reported invalid, but every row is stored
+                if (pend) df_finish<DF_U>(v, xv, 0.0, bo, diag, a.x + o);
+                pend = false;
+                break;
+            }
+            df_poll<DF_U, (KR > 2)>(xv, col, a.x, 1, rr);
+        }
+    }
+}
+
 // One pass of a wave: rows of W consecutive tasks, KR lanes per row, lane r owning right-hand
 // sides r, r + KR, ...  VPERM: the values through perm (the transposed solve reads L's values
 // in U's order).  A pass whose first task is a wide-row task runs that task alone.
@@ -1011,7 +1073,9 @@ __device__ __forceinline__ int df_pass(const SolveArgs &a, int p, int pn, int la
         return touch;
     }
     if (head.i0e == head.i0b) return touch;
-    if (KR == DF_RG && (head.meta & DF_MIXED))
+    if (KR == DF_RG && (head.meta & DF_MIXED) && a.mdesc)
+        df_mixed<KR, ADJ, VPERM>(a, head, lane);
+    else if (KR == DF_RG && (head.meta & DF_MIXED))
         df_rows<KR, ADJ, VPERM, true>(a, head, tk, c, t, i, lane);
     else
         df_rows<KR, ADJ, VPERM, false>(a, head, tk, c, t, i, lane);

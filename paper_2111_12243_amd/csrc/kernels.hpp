@@ -127,6 +127,8 @@ struct SolveArgs {
     int32_t npass;      // dataflow solve: wave passes (each 64 / KR rows, DF_RG rows per task)
     const int32_t *lcols; // dataflow solve: columns of the wide-row tasks (offset in the task's i0e)
     const int2 *slots;    // dataflow solve: (codelet, row) of the mixed tasks' row slots
+    const int4 *mdesc;    // dataflow solve: the same slots' descriptors (NULL: read the codelets)
+    const int32_t *mcols; // dataflow solve: the mixed rows' operand elements
 };
 constexpr int WAVE_LANES = 64;
 constexpr int DF_RG = 8;  // dataflow solve: rows per task (one codelet's)

@@ -664,6 +664,47 @@ void drop_alloc(ddf_plan_t p, void *ptr) {
     (void)hipFree(ptr);
 }
 
+// The device-only descriptors of a batch's mixed-task row slots (DevTables::df_mdesc), so that
+// a mixed pass reads each row's value range, output position and operand list from one record
+// instead of its codelet record, the matrix's bases and the codelet's column tables.  Left
+// empty (the kernel then reads the codelets) when a field does not fit its bits.
+void mixed_desc(const std::vector<DCod> &cods, const std::vector<int32_t> &aux, const std::vector<int32_t> &slots,
+                const std::vector<MatInfo> &mats, std::vector<int32_t> &desc, std::vector<int32_t> &mcols) {
+    desc.clear();
+    mcols.clear();
+    constexpr int64_t M27 = int64_t(1) << 27;
+    std::vector<int32_t> cols;
+    for (size_t q = 0; q + 1 < slots.size(); q += 2) {
+        const DCod &d = cods[slots[q]];
+        const int32_t i0 = slots[q + 1];
+        const HostRow r = host_row(d, aux, i0);
+        const MatInfo &mi = mats[d.mat];
+        const int64_t e = mi.val_base + r.opst, coff = (int64_t)mcols.size();
+        const int64_t rowel = mi.vec_base + r.row * mi.k;
+        if (e >= M27 || coff + r.nops >= M27 || r.nops > DF_U || mi.k < 1 || mi.k > 32 || rowel >= (int64_t(1) << 31) ||
+            mi.val_base >= (int64_t(1) << 31)) {
+            desc.clear();
+            mcols.clear();
+            return;
+        }
+        cols.clear();
+        host_cols(d, aux, i0, r, cols);
+        for (int32_t c : cols) {
+            const int64_t el = mi.vec_base + (int64_t)c * mi.k;
+            if (el >= (int64_t(1) << 31)) {
+                desc.clear();
+                mcols.clear();
+                return;
+            }
+            mcols.push_back((int32_t)el);
+        }
+        desc.push_back((int32_t)(e | ((int64_t)(mi.k - 1) << 27)));
+        desc.push_back((int32_t)rowel);
+        desc.push_back((int32_t)(coff | (r.nops << 27)));
+        desc.push_back((int32_t)mi.val_base);
+    }
+}
+
 ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     if (p->host_only) return DDF_OK;
     p->generation++; // graphs captured before now read the buffers freed below
@@ -677,6 +718,10 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
     drop_alloc(p, D.d_df_tcods);
     drop_alloc(p, D.d_df_lcols);
     drop_alloc(p, D.d_df_slots);
+    drop_alloc(p, D.d_df_mdesc);
+    drop_alloc(p, D.d_df_mcols);
+    D.d_df_mdesc = nullptr;
+    D.d_df_mcols = nullptr;
     D.d_df_tasks = nullptr;
     D.d_df_tcods = nullptr;
     D.d_df_lcols = nullptr;
@@ -703,6 +748,12 @@ ddf_status upload_tasks(ddf_plan_t p, DevTables &D) {
         if (!s) s = upload(p, &D.d_df_tcods, tc.data(), tc.size());
         if (!s && !D.df_lcols.empty()) s = upload(p, &D.d_df_lcols, D.df_lcols.data(), D.df_lcols.size());
         if (!s && !D.df_slots.empty()) s = upload(p, &D.d_df_slots, D.df_slots.data(), D.df_slots.size());
+        D.df_mdesc.clear();
+        D.df_mcols.clear();
+        if (p->batch && !D.df_slots.empty())
+            mixed_desc(cods, &D == &p->T ? p->T.aux : p->F.aux, D.df_slots, p->mats, D.df_mdesc, D.df_mcols);
+        if (!s && !D.df_mdesc.empty()) s = upload(p, &D.d_df_mdesc, D.df_mdesc.data(), D.df_mdesc.size());
+        if (!s && !D.df_mcols.empty()) s = upload(p, &D.d_df_mcols, D.df_mcols.data(), D.df_mcols.size());
     }
     if (!s && !D.rowlist.empty()) s = upload(p, &D.d_rowlist, D.rowlist.data(), D.rowlist.size());
     if (!s && !D.tasksN.empty()) s = upload(p, &D.d_tasksN, D.tasksN.data(), D.tasksN.size());
@@ -1570,6 +1621,8 @@ ddf_status solve_launch(ddf_plan_t p, const DevTables &D, int64_t t0, int64_t nt
         df.tcods = D.d_df_tcods + d0;
         df.lcols = D.d_df_lcols;
         df.slots = reinterpret_cast<const int2 *>(D.d_df_slots);
+        df.mdesc = reinterpret_cast<const int4 *>(D.d_df_mdesc);
+        df.mcols = D.d_df_mcols;
         df.ntasks = (int32_t)(d1 - d0);
         const int kr = single ? df_lanes(k_override) : 8;
         const int per_pass = WAVE_LANES / kr / DF_RG;
